@@ -1,0 +1,358 @@
+"""Space-time Galerkin + Spline Upwind discretisation (paper Sections 2-3).
+Test infrastructure (see package doc).
+
+Layout: a space-time coefficient vector on the full basis has shape
+(n_t, n_d, ..., n_1) in C order, i.e. x_1 fastest and time slowest (the
+colexicographic order of Section 2).  Time layer 0 is the first B-spline in
+time, the only one that is non-zero at t = 0; the unknowns are layers
+1..n_t-1 (the space X_h with the initial condition, N_t = n_t - 1).
+
+Every quantity is an integral evaluated by (p+1)-point Gauss quadrature on
+each space-time element.  Two interchangeable evaluators are provided:
+``explicit`` builds the sparse matrix Phi of basis values at all tensor Gauss
+points (a Kronecker product of the 1D collocation matrices: a tensor-product
+B-spline is the product of its univariate factors) and assembles the explicit
+sparse space-time matrices Phi_i^T diag(omega * coef) Phi_j; ``tensor``
+evaluates the same sums with 1D contractions along each axis (for sizes where
+Phi would not fit).  Tests pin one against the other on small grids.
+
+Readings taken here (the paper is silent or ambiguous):
+* Initial datum (eq. (3.1) has u = 0 at t = 0 plus a source; the workloads
+  use an indicator initial datum and no source): the datum is lifted into time
+  layer 0 with coefficients u0(gamma_i) sampled at the spatial Greville points.
+* theta (eq. (3.4)): the L-infinity norms are maxima of |.| over the Gauss
+  points of the elements inside the window; the window of the full-basis
+  function j (0-based) in a direction is (xi_{j-p}, xi_{j+p+1}) in the paper's
+  1-based knot indexing (eq. (2.2)) with indices clamped to the knot vector;
+  time functions of X_t are full indices 1..n_t-1.  If the denominator is 0,
+  Theta = 1 where the numerator is positive, else 0.
+* theta is min(..., 1) on the Greville grid, then low-ranked; the low-rank
+  interpolant is not clipped again.  Interpolation in time uses the Greville
+  points of X_t; below the first of them it is extended by a constant.
+* The low rank (eq. (3.8)) is the truncated SVD with the smallest R such that
+  the Frobenius tail is <= eps times the norm (a deterministic stand-in for a
+  randomized sketch: the same tolerance, a unique answer).
+* Outer loop: defect correction u <- u + alpha*delta with
+  (A_lin + M[c~]) delta = -N(u), N the full residual with the exact ionic
+  current at the Gauss points.  Newton: c = dI_ion/du, alpha = 1.  Picard
+  (Section 3.1): c = C_r of eq. (3.6), alpha = 0.5.  c is sampled on the
+  Greville grid and low-ranked like theta.  w is lagged: w^k solves the
+  L-system of Section 3.1.1 with u^k.  theta is refreshed while
+  ||delta||_inf > theta_freeze and then kept fixed.
+* The FD preconditioner of Section 3.2 uses sigma-scaled stiffness matrices
+  (the paper's parametric version has unit diffusion).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, List, Optional
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .operators1d import eval_spline, tau_splines
+from .splines import bspline_all, breakpoints, greville, n_basis, quadrature
+
+
+def ionic_current(u, w, P):
+    """I_ion = c1 u (u-a)(u-1) + c2 u w (eq. (3.1))."""
+    return P.c1 * u * (u - P.a) * (u - 1.0) + P.c2 * u * w
+
+
+def ionic_du(u, w, P):
+    """dI_ion/du = c1 (3u^2 - 2(1+a)u + a) + c2 w."""
+    return P.c1 * (3.0 * u * u - 2.0 * (1.0 + P.a) * u + P.a) + P.c2 * w
+
+
+def reaction_coefficient(u, w, P):
+    """C_r = c1 (u-a)(u-1) + c2 w (eq. (3.6)), the fixed-point reaction coefficient."""
+    return P.c1 * (u - P.a) * (u - 1.0) + P.c2 * w
+
+
+def truncated_svd(A: np.ndarray, eps: float):
+    """Smallest-rank R with ||A - U S V^T||_F <= eps ||A||_F (eq. (3.8))."""
+    U, s, Vt = np.linalg.svd(A, full_matrices=False)
+    tot = float(np.sum(s * s))
+    if tot == 0.0:
+        return 0, U[:, :0], s[:0], Vt[:0].T
+    tail = np.concatenate([np.cumsum((s * s)[::-1])[::-1], [0.0]])  # tail[R] = sum_{k>=R} s_k^2
+    R = int(np.argmax(tail <= eps * eps * tot))
+    return R, U[:, :R], s[:R], Vt[:R].T
+
+
+def hat_matrix(nodes: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """H[q, g] = value at x_q of the piecewise-linear interpolant of e_g on nodes
+    (constant extension outside the node range)."""
+    return np.stack([np.interp(x, nodes, e) for e in np.eye(len(nodes))], axis=1)
+
+
+@dataclasses.dataclass
+class LowRank:
+    """c(x, t) ~ sum_r s_r phi_r(t) psi_r(x): U (N_t x R), s (R), V (N_s x R) on the Greville grid."""
+    U: np.ndarray
+    s: np.ndarray
+    V: np.ndarray
+
+    @property
+    def R(self):
+        return len(self.s)
+
+
+class SpaceTime:
+    """Discrete space-time problem of one workload (see module doc)."""
+
+    def __init__(self, prob, knots: Optional[List[np.ndarray]] = None, mode: str = "explicit",
+                 nq_extra: int = 0, su: bool = True, f: Optional[Callable] = None):
+        self.P = prob
+        d = prob.d
+        self.d = d
+        kn = knots if knots is not None else prob.uniform_knots()
+        self.kn = [np.asarray(k, dtype=np.float64) for k in kn[:d]] + [prob.T * np.asarray(kn[d], dtype=np.float64)]
+        self.p = [prob.p_s] * d + [prob.p_t]
+        self.n = [n_basis(k, p) for k, p in zip(self.kn, self.p)]
+        self.mode = mode
+        self.su = su
+        self.f = f
+        # axis a of an array (time first): a = 0 is time, a = 1 is x_d, ..., a = d is x_1
+        self.dirs = [d] + list(range(d - 1, -1, -1))      # direction index of each axis
+        self.quad = [quadrature(k, p + 1 + nq_extra) for k, p in zip(self.kn, self.p)]
+        maxder = [2] * d + [prob.p_t]
+        self.E = [[bspline_all(self.kn[l], self.p[l], self.quad[l][0], k) for k in range(maxder[l] + 1)]
+                  for l in range(d + 1)]
+        self.omega = self._outer([self.quad[l][1] for l in range(d + 1)])
+        self.taus = tau_splines(self.kn[d], prob.p_t, prob.p_t + 1 + nq_extra)
+        tq = self.quad[d][0]
+        self.tau_q = [eval_spline(kk, q, c, tq) for kk, q, c in self.taus]
+        self.grev_s = [greville(self.kn[l], self.p[l]) for l in range(d)]
+        self.grev_t = greville(self.kn[d], self.p[d])[1:]          # X_t Greville points
+        self.Ht = hat_matrix(self.grev_t, tq)
+        self.Hs = [hat_matrix(self.grev_s[l], self.quad[l][0]) for l in range(d)]
+        self.shape = tuple([self.n[d]] + [self.n[l] for l in range(d - 1, -1, -1)])
+        self.qshape = tuple([len(self.quad[d][0])] + [len(self.quad[l][0]) for l in range(d - 1, -1, -1)])
+        self._phi = {}
+
+    # ------------------------------------------------------------------ helpers
+    def _outer(self, vecs_by_dir):
+        """Tensor (outer) product arranged [time][x_d]...[x_1], flattened."""
+        out = np.array([1.0])
+        for a in range(self.d + 1):
+            out = np.multiply.outer(out, vecs_by_dir[self.dirs[a]])
+        return out.reshape(-1)
+
+    def _ders(self, spec):
+        """spec maps direction -> derivative order; returns per-direction matrices."""
+        return [self.E[l][spec.get(l, 0)] for l in range(self.d + 1)]
+
+    def phi(self, spec) -> sp.csr_matrix:
+        """Sparse matrix of the requested derivative of every space-time basis
+        function at every tensor Gauss point (Kronecker product of 1D ones)."""
+        key = tuple(sorted(spec.items()))
+        if key not in self._phi:
+            mats = self._ders(spec)
+            M = sp.csr_matrix(mats[self.dirs[0]])
+            for a in range(1, self.d + 1):
+                M = sp.kron(M, sp.csr_matrix(mats[self.dirs[a]]), format="csr")
+            M.eliminate_zeros()
+            self._phi[key] = M
+        return self._phi[key]
+
+    def ev(self, x_full: np.ndarray, spec) -> np.ndarray:
+        """Values at all tensor Gauss points of the spline with coefficients x_full."""
+        if self.mode == "explicit":
+            return self.phi(spec) @ x_full
+        X = x_full.reshape(self.shape)
+        mats = self._ders(spec)
+        for a in range(self.d + 1):
+            X = np.moveaxis(np.tensordot(mats[self.dirs[a]], X, axes=([1], [a])), 0, a)
+        return X.reshape(-1)
+
+    def evT(self, g: np.ndarray, spec) -> np.ndarray:
+        """Transpose of ev: sum over Gauss points of g times the basis derivative."""
+        if self.mode == "explicit":
+            return self.phi(spec).T @ g
+        G = g.reshape(self.qshape)
+        mats = self._ders(spec)
+        for a in range(self.d + 1):
+            G = np.moveaxis(np.tensordot(mats[self.dirs[a]].T, G, axes=([1], [a])), 0, a)
+        return G.reshape(-1)
+
+    def lowrank_at_quad(self, lr: LowRank) -> np.ndarray:
+        """sum_r s_r phi_r(t) psi_r(x) at all tensor Gauss points."""
+        out = np.zeros(int(np.prod(self.qshape)))
+        for r in range(lr.R):
+            tpart = self.Ht @ lr.U[:, r]
+            V = lr.V[:, r].reshape(self.shape[1:])
+            for a in range(1, self.d + 1):
+                V = np.moveaxis(np.tensordot(self.Hs[self.dirs[a]], V, axes=([1], [a - 1])), 0, a - 1)
+            out += lr.s[r] * np.multiply.outer(tpart, V).reshape(-1)
+        return out
+
+    def full(self, x_unk: np.ndarray, layer0: Optional[np.ndarray] = None) -> np.ndarray:
+        """Unknown vector (N_t*N_s) -> full vector with time layer 0 prepended."""
+        N_s = int(np.prod(self.n[: self.d]))
+        l0 = np.zeros(N_s) if layer0 is None else layer0
+        return np.concatenate([l0, x_unk])
+
+    def rows(self, y_full: np.ndarray) -> np.ndarray:
+        """Drop the test functions of time layer 0 (they are not in X_h)."""
+        N_s = int(np.prod(self.n[: self.d]))
+        return y_full[N_s:]
+
+    # --------------------------------------------------------- initial datum
+    def lift(self) -> np.ndarray:
+        """Coefficients of the lifted initial datum: u0 at the spatial Greville grid."""
+        grids = np.meshgrid(*[self.grev_s[l] for l in range(self.d - 1, -1, -1)], indexing="ij")
+        pts = np.stack([grids[self.d - 1 - l].reshape(-1) for l in range(self.d)], axis=1)
+        return self.P.u0(pts)
+
+    # ------------------------------------------------------- bilinear forms
+    def _lin_terms(self, x_full, theta_q):
+        """C_m int dt u v + int grad u . D grad v + SU term, tested against all full functions."""
+        P, d = self.P, self.d
+        om = self.omega
+        y = P.Cm * self.evT(om * self.ev(x_full, {d: 1}), {})
+        for l in range(d):
+            y += P.sigma[l] * self.evT(om * self.ev(x_full, {l: 1}), {l: 1})
+        if self.su and theta_q is not None:
+            for k in range(1, P.p_t + 1):
+                tk = np.repeat(self.tau_q[k - 1], int(np.prod(self.qshape[1:])))
+                y += P.Cm * self.evT(om * tk * theta_q * self.ev(x_full, {d: k}), {d: k})
+        return y
+
+    def apply_J(self, x_unk, coef_q, theta_q):
+        """Linearised operator applied to an unknown vector (Section 3.1.1 form)."""
+        xf = self.full(x_unk)
+        y = self._lin_terms(xf, theta_q) + self.evT(self.omega * coef_q * self.ev(xf, {}), {})
+        return self.rows(y)
+
+    def residual(self, u_full, w_full, theta_q):
+        """N(u) = A(u, w; v) + S(u; v) - F(v) for all v in X_h, exact I_ion at Gauss points."""
+        uq = self.ev(u_full, {})
+        wq = self.ev(w_full, {})
+        y = self._lin_terms(u_full, theta_q) + self.evT(self.omega * ionic_current(uq, wq, self.P), {})
+        if self.f is not None:
+            y -= self.evT(self.omega * self.f_at_quad(), {})
+        return self.rows(y)
+
+    def f_at_quad(self):
+        grids = np.meshgrid(*([self.quad[self.d][0]] + [self.quad[l][0] for l in range(self.d - 1, -1, -1)]),
+                            indexing="ij")
+        t = grids[0].reshape(-1)
+        xs = [grids[self.d - l].reshape(-1) for l in range(self.d)]
+        return self.f(xs, t)
+
+    def assemble_J(self, coef_q, theta_q):
+        """Explicit sparse matrix of apply_J (unknown rows x unknown columns)."""
+        P, d, om = self.P, self.d, self.omega
+        Dg = sp.diags
+        A = P.Cm * self.phi({}).T @ Dg(om) @ self.phi({d: 1})
+        for l in range(d):
+            A = A + P.sigma[l] * self.phi({l: 1}).T @ Dg(om) @ self.phi({l: 1})
+        A = A + self.phi({}).T @ Dg(om * coef_q) @ self.phi({})
+        if self.su and theta_q is not None:
+            for k in range(1, P.p_t + 1):
+                tk = np.repeat(self.tau_q[k - 1], int(np.prod(self.qshape[1:])))
+                A = A + P.Cm * self.phi({d: k}).T @ Dg(om * tk * theta_q) @ self.phi({d: k})
+        N_s = int(np.prod(self.n[:d]))
+        return sp.csr_matrix(A)[N_s:, N_s:]
+
+    def assemble_precond(self):
+        """Explicit A-hat of Section 3.2 (sigma-scaled stiffness, shift a*c1, no SU)."""
+        P, d, om = self.P, self.d, self.omega
+        Dg = sp.diags(om)
+        A = P.Cm * self.phi({}).T @ Dg @ self.phi({d: 1}) + P.a * P.c1 * self.phi({}).T @ Dg @ self.phi({})
+        for l in range(d):
+            A = A + P.sigma[l] * self.phi({l: 1}).T @ Dg @ self.phi({l: 1})
+        N_s = int(np.prod(self.n[:d]))
+        return sp.csr_matrix(A)[N_s:, N_s:]
+
+    # --------------------------------------------------------- w update
+    def w_update_explicit(self, u_full):
+        """Solve L w = g of Section 3.1.1 as one explicit sparse system.
+        L = int (dt w + b d_e w) z, g = int b u z over X_h; w has zero initial layer."""
+        P, d, om = self.P, self.d, self.omega
+        Dg = sp.diags(om)
+        Lf = self.phi({}).T @ Dg @ self.phi({d: 1}) + P.b * P.de * self.phi({}).T @ Dg @ self.phi({})
+        Gf = P.b * self.phi({}).T @ Dg @ self.phi({})
+        N_s = int(np.prod(self.n[:d]))
+        L = sp.csc_matrix(Lf)[N_s:, N_s:]
+        g = (sp.csr_matrix(Gf) @ u_full)[N_s:]
+        w = spla.splu(L).solve(g)
+        return self.full(w)
+
+    def w_update_kron(self, u_full):
+        """Same system through the Kronecker structure L = (W_t + b d_e M_t) (x) M_s and
+        g = b (M_t[X_t, :] (x) M_s) u: M_s cancels, leaving one N_t x N_t solve per
+        spatial index (Section 3.2, last part)."""
+        P, d = self.P, self.d
+        tq, tw, _ = self.quad[d]
+        B0, B1 = self.E[d][0], self.E[d][1]
+        Wt = B0.T @ (tw[:, None] * B1)
+        Mt = B0.T @ (tw[:, None] * B0)
+        Lt = (Wt + P.b * P.de * Mt)[1:, 1:]
+        G = P.b * Mt[1:, :]
+        U = u_full.reshape(self.n[d], -1)
+        w = np.linalg.solve(Lt, G @ U)
+        return self.full(w.reshape(-1))
+
+    # --------------------------------------------------------- theta (eq. 3.4)
+    def element_windows(self, l: int, first: int):
+        """For each full basis index j >= first in direction l, the element range
+        [e0, e1) inside (xi_{j-p}, xi_{j+p+1}) (1-based paper indices, clamped)."""
+        kn, p = self.kn[l], self.p[l]
+        z = breakpoints(kn)
+        out = []
+        for j in range(first, self.n[l]):
+            lo = kn[max(j - p, 0)]
+            hi = kn[min(j + p + 1, len(kn) - 1)]
+            es = [e for e in range(len(z) - 1) if z[e] >= lo and z[e + 1] <= hi]
+            out.append((min(es), max(es) + 1))
+        return out
+
+    def theta_grid(self, u_full, w_full):
+        """Theta of eq. (3.4) on the (X_t time) x (space) Greville grid: N_t x N_s."""
+        P, d = self.P, self.d
+        uq = self.ev(u_full, {})
+        wq = self.ev(w_full, {})
+        utq = self.ev(u_full, {d: 1})
+        R = P.Cm * utq + ionic_current(uq, wq, P)
+        for l in range(d):
+            R -= P.sigma[l] * self.ev(u_full, {l: 2})
+        if self.f is not None:
+            R -= self.f_at_quad()
+        den = P.Cm * (np.max(np.abs(uq)) / P.T + np.max(np.abs(utq)))
+        # element-wise maxima of |R|
+        nq = [self.p[self.dirs[a]] + 1 for a in range(d + 1)]
+        nel = [self.qshape[a] // nq[a] for a in range(d + 1)]
+        E = np.abs(R).reshape([v for a in range(d + 1) for v in (nel[a], nq[a])])
+        E = E.max(axis=tuple(2 * a + 1 for a in range(d + 1)))
+        # box maxima over the support-extension windows, axis by axis
+        for a in range(d + 1):
+            l = self.dirs[a]
+            wins = self.element_windows(l, 1 if l == d else 0)
+            E = np.stack([np.take(E, range(e0, e1), axis=a).max(axis=a) for e0, e1 in wins], axis=a)
+        num = E.reshape(self.n[d] - 1, -1)
+        if den > 0:
+            return np.minimum(num / den, 1.0)
+        return np.where(num > 0, 1.0, 0.0)
+
+    def greville_values(self, x_full):
+        """Spline values on the (X_t time) x (space) Greville grid: N_t x N_s."""
+        d = self.d
+        mats = [bspline_all(self.kn[l], self.p[l], self.grev_s[l], 0) for l in range(d)]
+        mats.append(bspline_all(self.kn[d], self.p[d], self.grev_t, 0))
+        X = x_full.reshape(self.shape)
+        for a in range(d + 1):
+            X = np.moveaxis(np.tensordot(mats[self.dirs[a]], X, axes=([1], [a])), 0, a)
+        return X.reshape(self.n[d] - 1, -1)
+
+    def coefficient_grid(self, u_full, w_full, newton: bool):
+        """dI_ion/du (Newton) or C_r (Picard) at the Greville grid: N_t x N_s."""
+        ug = self.greville_values(u_full)
+        wg = self.greville_values(w_full)
+        return ionic_du(ug, wg, self.P) if newton else reaction_coefficient(ug, wg, self.P)
+
+    def lowrank(self, grid: np.ndarray, eps: float) -> LowRank:
+        R, U, s, V = truncated_svd(grid, eps)
+        return LowRank(U, s, V)
