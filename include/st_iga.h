@@ -1,0 +1,211 @@
+/*
+ * st_iga.h -- C ABI of the MI355X space-time isogeometric solver for the
+ * monodomain equation with the Rogers-McCulloch ionic model, stabilized by
+ * Spline Upwind (Antonietti, Dede, Loli, Montardini, Sangalli, Tesini,
+ * "Space-time Isogeometric Analysis of cardiac electrophysiology").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Errors:   every call returns st_iga_status; nothing throws across the ABI.
+ *           A per-context message is available from st_iga_last_error.
+ * Memory:   the caller owns every device buffer (vectors and the workspace);
+ *           the library never allocates device memory.  The opaque context is
+ *           host memory owned by the library (freed by st_iga_destroy).
+ * Streams:  `stream` is a hipStream_t passed as void*; NULL means the null
+ *           stream.  apply/precond only enqueue work; calls that return
+ *           scalars (residuals, reports) synchronize that stream.
+ * Layout:   a space-time vector of unknowns has N_t * N_s FP64 entries laid
+ *           out [N_t][n_d]...[n_1] (x_1 fastest, time slowest: the
+ *           colexicographic order of Section 2), N_s = prod n_l, N_t = n_t - 1
+ *           (the time functions b_2..b_{n_t} of X_t, Section 2).  "Full"
+ *           vectors (u, w) have n_t * N_s entries; time layer 0 holds the
+ *           coefficients of b_1, the only time function non-zero at t = 0.
+ * Threads:  a context must not be used by two threads at once; different
+ *           contexts are independent.
+ */
+#ifndef ST_IGA_H
+#define ST_IGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct st_iga_ctx st_iga_ctx;
+
+typedef enum {
+  ST_IGA_OK = 0,
+  ST_IGA_EINVAL = -1,   /* invalid argument (knots, degrees, parameters, sizes, NULL) */
+  ST_IGA_ENOMEM = -2,   /* caller workspace smaller than st_iga_workspace_bytes */
+  ST_IGA_ENOCONV = -3,  /* iteration limit reached; best iterate written, report filled */
+  ST_IGA_EDEVICE = -4,  /* a HIP runtime call failed */
+  ST_IGA_ESTATE = -5    /* call out of order (e.g. apply before a linearization) */
+} st_iga_status;
+
+typedef enum {
+  ST_IGA_FP64 = 0,        /* every kernel in FP64 */
+  ST_IGA_MIXED_FP32 = 1,  /* apply/precond in FP32 inside FP64 FGMRES + iterative refinement */
+  ST_IGA_MIXED_BF16 = 2   /* apply/precond with BF16 storage, FP32 arithmetic, same FP64 loop */
+} st_iga_precision;
+
+/* Problem statement, paper Section 3, eq. (3.1), and Section 2 (knots).
+ * Domain (0,1)^d x (0,T) with the identity geometry map; homogeneous Neumann
+ * boundary conditions; D = diag(sigma). */
+typedef struct {
+  int32_t d;                 /* spatial dimension, 1..3 */
+  int32_t p_s, p_t;          /* spline degrees in space / time, >= 1 */
+  int32_t nknots[4];         /* knot-vector lengths: [0..d-1] space, [d] time */
+  const double* knots[4];    /* HOST pointers: open knot vectors on [0,1] (Section 2) */
+  double T;                  /* final time > 0 (time knots are scaled by T) */
+  double Cm;                 /* membrane capacitance > 0 */
+  double sigma[3];           /* diffusivities > 0 */
+  double a, b, c1, c2, de;   /* Rogers-McCulloch parameters of eq. (3.1), > 0 (c1, c2 >= 0) */
+} st_iga_problem;
+
+/* Stimulus: an initial datum u0 (lifted into time layer 0 by sampling at the
+ * spatial Greville abscissae).  Source terms are not supported (f_kind != 0
+ * is rejected with ST_IGA_EINVAL). */
+typedef struct {
+  int32_t u0_kind;           /* 0 none, 1 half-space x_1 < u0_center[0], 2 closed ball |x - c| <= r */
+  double u0_center[3];
+  double u0_radius;
+  double u0_value;
+  int32_t f_kind;            /* must be 0 */
+} st_iga_stimulus;
+
+typedef struct {
+  int32_t su;                /* 1: Spline Upwind term of eq. (3.2) on, 0: plain Galerkin */
+  double eps_theta;          /* relative Frobenius tolerance of the theta low rank, eq. (3.8) (paper: 0.1) */
+  double eps_react;          /* same tolerance for the reaction coefficient of the Jacobian */
+  int32_t max_rank;          /* cap on each low rank (sizes the workspace) */
+  int32_t outer;             /* 0: Newton (dI_ion/du), 1: Picard with C_r of eq. (3.6) */
+  double alpha;              /* relaxation of the update (paper: 0.5 for Picard) */
+  double theta_freeze;       /* theta is recomputed while ||delta||_inf > theta_freeze */
+  double tol_nonlin;         /* stop when ||delta||_inf <= tol_nonlin */
+  double tol_lin;            /* relative true residual of each linear solve */
+  double inner_tol;          /* mixed precision: relative residual of each inner FGMRES */
+  int32_t restart;           /* FGMRES restart length m (<= 64) */
+  int32_t max_outer;         /* nonlinear iteration cap */
+  int32_t max_krylov;        /* Krylov iteration cap per linear solve */
+  st_iga_precision prec;
+} st_iga_options;
+
+#define ST_IGA_MAX_OUTER_LOG 64
+typedef struct {
+  int32_t outer_iters;
+  int32_t krylov_total;                        /* Krylov iterations summed over linear solves */
+  int32_t refinements;                         /* iterative-refinement steps of the last solve */
+  int32_t krylov[ST_IGA_MAX_OUTER_LOG];        /* per outer iteration */
+  int32_t rank_theta[ST_IGA_MAX_OUTER_LOG];
+  int32_t rank_react[ST_IGA_MAX_OUTER_LOG];
+  double delta_inf[ST_IGA_MAX_OUTER_LOG];
+  double lin_relres[ST_IGA_MAX_OUTER_LOG];     /* FP64 true relative residual of each linear solve */
+  double final_delta_inf;
+  double seconds_linearize, seconds_krylov;
+} st_iga_report;
+
+/* Defaults: su=1, eps_theta=0.1, eps_react=1e-2, max_rank=48, outer=0,
+ * alpha=1 (Newton), theta_freeze=1e-4, tol_nonlin=1e-10, tol_lin=1e-10,
+ * inner_tol=1e-4, restart=30, max_outer=60, max_krylov=3000, prec=FP64. */
+void st_iga_default_options(st_iga_options* opt);
+
+/* Bytes of device workspace st_iga_setup needs for this problem/options
+ * (256-byte aligned sub-buffers included).  Returns 0 on invalid input. */
+size_t st_iga_workspace_bytes(const st_iga_problem* prob, const st_iga_options* opt);
+
+/* Build the 1D operators (Section 3.1.1), tau_k (eq. (3.3)) and the
+ * fast-diagonalization factors (Section 3.2) on the host in FP64 and upload
+ * them into `workspace` (device, >= st_iga_workspace_bytes, 256-byte aligned).
+ * Errors: EINVAL for invalid problems (knots not open/non-decreasing on
+ * [0,1], interior multiplicity > degree, interior time multiplicity > 1 when
+ * su = 1, d not in 1..3, non-positive T/Cm/sigma, NULL pointers);
+ * ENOMEM if workspace_bytes is too small; EDEVICE on HIP failures. */
+st_iga_status st_iga_setup(const st_iga_problem* prob, const st_iga_options* opt, void* workspace,
+                           size_t workspace_bytes, void* stream, st_iga_ctx** out);
+
+/* Linearize at (u, w) (full device vectors): theta of eq. (3.4) on the
+ * Greville grid (when su = 1 and refresh_theta != 0), its low rank (eq. (3.8)),
+ * the reaction coefficient (Newton: dI_ion/du; Picard: C_r) on the Greville
+ * grid and its low rank; the result defines J_k for apply/krylov.  Synchronizes. */
+st_iga_status st_iga_linearize(st_iga_ctx* ctx, const double* u, const double* w, int32_t refresh_theta,
+                               void* stream);
+
+/* Set J_k directly from low-rank factors given on the Greville grid (HOST
+ * pointers): theta ~ sum_r s_r U[:,r] V[:,r]^T with U (N_t x R) and V (N_s x R)
+ * row-major, same for the reaction coefficient.  R may be 0.  EINVAL if a
+ * rank exceeds max_rank. */
+st_iga_status st_iga_set_factors(st_iga_ctx* ctx, int32_t r_theta, const double* U_theta,
+                                 const double* s_theta, const double* V_theta, int32_t r_react,
+                                 const double* U_react, const double* s_react, const double* V_react);
+
+/* Copy the current low-rank factors to HOST buffers (capacities in entries:
+ * U needs N_t*max_rank, V N_s*max_rank, s max_rank).  Ranks are returned. */
+st_iga_status st_iga_get_factors(st_iga_ctx* ctx, int32_t* r_theta, double* U_theta, double* s_theta,
+                                 double* V_theta, int32_t* r_react, double* U_react, double* s_react,
+                                 double* V_react);
+
+/* Theta grid of eq. (3.4) before the low rank (N_t x N_s, device) at (u, w). */
+st_iga_status st_iga_theta_grid(st_iga_ctx* ctx, const double* u, const double* w, double* theta,
+                                void* stream);
+
+/* y = J_k x on unknown vectors (device).  Section 3.1.1: C_m W_t (x) M_s +
+ * M_t (x) K_s + the low-rank SU and reaction terms.  ESTATE before a
+ * linearization.  Asynchronous. */
+st_iga_status st_iga_apply(st_iga_ctx* ctx, const double* x, double* y, void* stream);
+
+/* z = A-hat^{-1} r (device): the fast-diagonalization preconditioner of
+ * eq. (3.10)-(3.11) with sigma-scaled stiffness.  Asynchronous. */
+st_iga_status st_iga_precond(st_iga_ctx* ctx, const double* r, double* z, void* stream);
+
+/* Residual N(u) (unknown-sized output) of eq. (3.2) at full vectors (u, w) with
+ * the current low-rank theta and the exact ionic current at the Gauss points. */
+st_iga_status st_iga_residual(st_iga_ctx* ctx, const double* u, const double* w, double* r,
+                              void* stream);
+
+/* w-update of Section 3.2: solves L w = g(u) (full vectors; w layer 0 = 0). */
+st_iga_status st_iga_w_update(st_iga_ctx* ctx, const double* u, double* w, void* stream);
+
+/* Solve J_k x = b (device, unknown-sized) with right-preconditioned FGMRES
+ * (FP64 Arnoldi with re-orthogonalization and Givens rotations); in mixed
+ * precision, inner FGMRES solves with low-precision apply/precond inside an
+ * FP64 iterative refinement on the true residual.  x is overwritten (zero
+ * initial guess).  Stops at ||b - J x|| <= tol ||b|| (FP64 true residual).
+ * iters/relres may be NULL.  ENOCONV after max_krylov iterations. */
+st_iga_status st_iga_krylov(st_iga_ctx* ctx, const double* b, double* x, double tol, int32_t* iters,
+                            double* relres, void* stream);
+
+/* Full nonlinear solve (Section 3.1 outer loop): lifts the initial datum,
+ * starts from u^0 = datum in every time layer and w^0 = 0, and iterates
+ * w-update, linearize, krylov, update until ||delta||_inf <= tol_nonlin.
+ * u, w: full device vectors (outputs). */
+st_iga_status st_iga_solve(st_iga_ctx* ctx, const st_iga_stimulus* stim, double* u, double* w,
+                           st_iga_report* rep, void* stream);
+
+/* Lifted initial datum (N_s entries, HOST output) and the number of spatial
+ * Greville points inside the stimulus. */
+st_iga_status st_iga_lift(st_iga_ctx* ctx, const st_iga_stimulus* stim, double* c0, int64_t* count);
+
+/* Sizes of a context: [d, n_1, n_2, n_3, n_t, N_s, N_t, unknowns(low), unknowns(high)]. */
+st_iga_status st_iga_sizes(const st_iga_ctx* ctx, int64_t* out9);
+
+st_iga_status st_iga_destroy(st_iga_ctx* ctx);
+const char* st_iga_last_error(const st_iga_ctx* ctx);
+
+/* Host-only queries of the setup (no device needed), for checks of the host
+ * logic.  `what`: 0 Greville abscissae of direction dir (n); 1 mass matrix
+ * (n*n, full basis); 2 stiffness; 3 time-derivative matrix W[i][j] = int b_j' b_i;
+ * 4 tau_k at the time Gauss points (p_t*Q); 5 generalized eigenvalues of
+ * (K_l, M_l) (n); 6 eigenvectors U_l (n*n, row-major); 7 time FD: U_t (N_t*N_t)
+ * then block values (N_t-1), arrow l (N_t-1), sigma (1); 8 Gauss points of dir
+ * (Q) then weights (Q); 9 first-basis index of each Gauss point of dir (Q, as
+ * doubles); 10 support-extension element windows of dir ([e0, e1) pairs).
+ * Writes at most `cap` doubles to out and the needed length to *len. */
+st_iga_status st_iga_host_query(const st_iga_problem* prob, int32_t what, int32_t dir, double* out,
+                                int64_t cap, int64_t* len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ST_IGA_H */

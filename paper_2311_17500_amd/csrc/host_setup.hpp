@@ -1,0 +1,79 @@
+// Host-side (CPU, FP64) setup of the space-time isogeometric operators.
+//
+// Everything computed here is small (1D data, at most a few hundred entries
+// per direction): knot spans, B-spline values/derivatives at Gauss points,
+// Greville abscissae, the univariate Galerkin matrices, the SU coefficients
+// tau_k, the generalized eigendecompositions of the fast-diagonalization
+// preconditioner and the gather tables that drive the GPU mode products.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace stiga {
+
+// One univariate direction (a spatial direction or time).
+struct Dir1D {
+  int p = 0;            // degree
+  int n = 0;            // number of B-splines
+  int nel = 0;          // number of non-empty elements
+  int nq = 0;           // Gauss points per element (p + 1)
+  int Q = 0;            // total Gauss points (nel * nq)
+  int nder = 0;         // highest stored derivative
+  std::vector<double> knots;   // physical knots (time scaled by T)
+  std::vector<double> brk;     // breakpoints
+  std::vector<double> xq, wq;  // Gauss points / weights, element-major
+  std::vector<int> first;      // index of the first non-zero basis function at each point
+  std::vector<std::vector<double>> B;  // B[k][q*(p+1)+j] = k-th derivative of basis first[q]+j at xq[q]
+  std::vector<double> grev;    // Greville abscissae
+};
+
+// Sparse row table for y[i] = sum_w coef[i*W+w] * x[col[i*W+w]].
+struct Gather {
+  int n_out = 0, W = 0;
+  std::vector<int> col;
+  std::vector<double> coef;
+};
+
+bool build_dir(const double* knots01, int nk, int p, double scale, int nder, Dir1D& out, std::string& err);
+
+// Dense n x n matrices on the full basis: [i*n + j].
+std::vector<double> gram1d(const Dir1D& D, int dtest, int dtrial, const std::vector<double>* wq_weight);
+
+// SU coefficients tau_k (k = 1..p_t) evaluated at the time Gauss points:
+// returns tauq[(k-1)*Q + q].  Square full-basis system, column-equilibrated LU.
+bool tau_at_quad(const Dir1D& T, std::vector<double>& tauq, std::vector<double>& coefs, std::string& err);
+
+// Symmetric-definite generalized eigenproblem K u = lambda M u (dense, n x n):
+// U (column j = eigenvector j, row-major U[i*n+j]) with U^T M U = I, ascending lambda.
+bool gen_eig_sym(const std::vector<double>& K, const std::vector<double>& M, int n,
+                 std::vector<double>& U, std::vector<double>& lam, std::string& err);
+
+// Fast-diagonalization data for the time pencil (Section 3.2), real block form.
+struct TimeFD {
+  int N = 0;                    // N_t
+  std::vector<double> U;        // N x N, row-major, U^T M_t U = I
+  std::vector<double> mu;       // N-1 entries: block (2m, 2m+1) has skew value mu[2m] (= -mu[2m+1] pairing)
+  std::vector<int> kind;        // N-1 entries: 0 = first of a 2x2 pair, 1 = second, 2 = single (zero block)
+  std::vector<double> l;        // N-1 arrow entries
+  double sigma = 0.0;           // corner
+};
+bool time_fd(const std::vector<double>& Wt, const std::vector<double>& Mt, int N, TimeFD& out, std::string& err);
+
+// Gather tables.
+Gather banded_table(const std::vector<double>& A, int n, int row0, int nrow, int bw);
+Gather eval_table(const Dir1D& D, int der);             // Q x n (expansion to Gauss points)
+Gather eval_table_T(const Dir1D& D, int der, const std::vector<double>* wscale);  // n x Q (projection)
+Gather dense_table(const std::vector<double>& A, int nrow, int ncol, bool transpose);
+
+// Hat-function interpolation weights from nodes to points (constant extension outside).
+void hat_weights(const std::vector<double>& nodes, const std::vector<double>& x,
+                 std::vector<int>& left, std::vector<double>& wleft);
+
+// B-spline values of all basis functions at arbitrary points (dense rows, n columns).
+std::vector<double> collocation(const Dir1D& D, const std::vector<double>& x, int der);
+
+// Element windows (support extensions) for full-basis indices [first, n): [e0, e1) per index.
+void support_windows(const Dir1D& D, int first, std::vector<int>& e0, std::vector<int>& e1);
+
+}  // namespace stiga

@@ -1,0 +1,595 @@
+// gfx950 kernels of the space-time isogeometric solver.
+//
+// Design notes (CDNA4: 64-wide wavefronts, 256 CUs in 8 XCDs, HBM3E):
+//  * Every 1D operator (banded Galerkin matrices, B-spline evaluation at
+//    Gauss points, their transposes, hat interpolation, dense eigenvector
+//    blocks) is a row table (col, coef) applied along one tensor axis.  The
+//    thread owning output (o, i, k) reads x[o][col][k]; consecutive lanes take
+//    consecutive k (or consecutive i on the fastest axis), so loads are
+//    coalesced and the 2p+1 overlapping rows are served from L1/L2.
+//  * The coefficient part of the operator runs one thread per spatial Gauss
+//    point sweeping all time rows with a (2p+1)-wide register window.
+//  * Reductions are two-stage with a fixed summation order, so results are
+//    bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace stiga {
+
+namespace {
+
+constexpr int TPB = 256;
+
+__device__ __forceinline__ double to_c(double v, double) { return v; }
+__device__ __forceinline__ float to_c(float v, float) { return v; }
+__device__ __forceinline__ double to_c(float v, double) { return static_cast<double>(v); }
+__device__ __forceinline__ float to_c(double v, float) { return static_cast<float>(v); }
+__device__ __forceinline__ float to_c(bf16 v, float) { return __bfloat162float(v); }
+__device__ __forceinline__ double to_c(bf16 v, double) { return static_cast<double>(__bfloat162float(v)); }
+
+template <class T>
+__device__ __forceinline__ T from_c(double v);
+template <class T>
+__device__ __forceinline__ T from_c(float v);
+template <>
+__device__ __forceinline__ double from_c<double>(double v) { return v; }
+template <>
+__device__ __forceinline__ float from_c<float>(double v) { return static_cast<float>(v); }
+template <>
+__device__ __forceinline__ float from_c<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ double from_c<double>(float v) { return static_cast<double>(v); }
+template <>
+__device__ __forceinline__ bf16 from_c<bf16>(float v) { return __float2bfloat16(v); }
+template <>
+__device__ __forceinline__ bf16 from_c<bf16>(double v) { return __float2bfloat16(static_cast<float>(v)); }
+
+inline unsigned grid_for(int64_t n, int tpb = TPB) { return static_cast<unsigned>((n + tpb - 1) / tpb); }
+
+// ---------------------------------------------------------------- gather
+template <class Ti, class To, class C>
+__global__ void __launch_bounds__(TPB) k_gather(const int* __restrict__ col, const C* __restrict__ coef, int W,
+                                                int n_out, const Ti* __restrict__ x, To* __restrict__ y,
+                                                int64_t inner, int n_in, int in_base, C alpha, C beta,
+                                                int64_t total) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int64_t k = idx % inner;
+  const int64_t t = idx / inner;
+  const int i = static_cast<int>(t % n_out);
+  const int64_t o = t / n_out;
+  const int* cr = col + static_cast<int64_t>(i) * W;
+  const C* cf = coef + static_cast<int64_t>(i) * W;
+  const Ti* xb = x + o * static_cast<int64_t>(n_in) * inner + k;
+  C acc = C(0);
+  for (int w = 0; w < W; ++w) {
+    const int c = cr[w] - in_base;
+    if (static_cast<unsigned>(c) < static_cast<unsigned>(n_in)) acc += cf[w] * to_c(xb[static_cast<int64_t>(c) * inner], C(0));
+  }
+  C r = alpha * acc;
+  if (beta != C(0)) r += beta * to_c(y[idx], C(0));
+  y[idx] = from_c<To>(r);
+}
+
+__global__ void __launch_bounds__(TPB) k_mode_max(const int* __restrict__ start, const int* __restrict__ cnt,
+                                                  int n_out, const double* __restrict__ x, double* __restrict__ y,
+                                                  int64_t inner, int n_in, int64_t total) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int64_t k = idx % inner;
+  const int64_t t = idx / inner;
+  const int i = static_cast<int>(t % n_out);
+  const int64_t o = t / n_out;
+  const double* xb = x + o * static_cast<int64_t>(n_in) * inner + k;
+  double m = 0.0;
+  const int s0 = start[i], c = cnt[i];
+  for (int w = 0; w < c; ++w) m = fmax(m, xb[static_cast<int64_t>(s0 + w) * inner]);
+  y[idx] = m;
+}
+
+// ---------------------------------------------------------------- time mixing
+template <class S, class C, int P>
+__global__ void __launch_bounds__(TPB) k_time_mix(const C* __restrict__ T, const S* __restrict__ Psi, int r0, int R,
+                                                  int Nt, const S* __restrict__ Z, int n_in, int in_base,
+                                                  S* __restrict__ out, int64_t Qs) {
+  extern __shared__ char smem_raw[];
+  C* ps = reinterpret_cast<C*>(smem_raw);
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= Qs) return;
+  for (int r = 0; r < R; ++r) ps[r * blockDim.x + threadIdx.x] = to_c(Psi[static_cast<int64_t>(r0 + r) * Qs + q], C(0));
+  constexpr int WB = 2 * P + 1;
+  C win[WB];
+#pragma unroll
+  for (int w = 0; w < WB; ++w) {
+    const int j = 1 - P + w - in_base;
+    win[w] = (static_cast<unsigned>(j) < static_cast<unsigned>(n_in)) ? to_c(Z[static_cast<int64_t>(j) * Qs + q], C(0)) : C(0);
+  }
+  for (int t = 0; t < Nt; ++t) {
+    C acc = C(0);
+    for (int r = 0; r < R; ++r) {
+      const C* Tr = T + (static_cast<int64_t>(r0 + r) * Nt + t) * WB;
+      C s = C(0);
+#pragma unroll
+      for (int w = 0; w < WB; ++w) s += Tr[w] * win[w];
+      acc += ps[r * blockDim.x + threadIdx.x] * s;
+    }
+    out[static_cast<int64_t>(t) * Qs + q] = from_c<S>(acc);
+#pragma unroll
+    for (int w = 0; w < WB - 1; ++w) win[w] = win[w + 1];
+    const int j = t + 2 + P - in_base;
+    win[WB - 1] = (static_cast<unsigned>(j) < static_cast<unsigned>(n_in)) ? to_c(Z[static_cast<int64_t>(j) * Qs + q], C(0)) : C(0);
+  }
+}
+
+// ---------------------------------------------------------------- arrowhead
+template <class S, class C>
+__global__ void __launch_bounds__(TPB) k_arrowhead(const S* __restrict__ r, S* __restrict__ y, const C* __restrict__ lam,
+                                                   const C* __restrict__ mu, const int* __restrict__ kind,
+                                                   const C* __restrict__ l, C sigma, C Cm, int Nt, int64_t Ns) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= Ns) return;
+  const C s = lam[j];
+  const int n = Nt - 1;
+  C acc = C(0), den = Cm * sigma + s;
+  for (int a = 0; a < n;) {
+    if (kind[a] == 0) {
+      const C dl = Cm * mu[a];
+      const C inv = C(1) / (s * s + dl * dl);
+      const C ra = to_c(r[static_cast<int64_t>(a) * Ns + j], C(0));
+      const C rb = to_c(r[static_cast<int64_t>(a + 1) * Ns + j], C(0));
+      const C la = l[a], lb = l[a + 1];
+      acc += inv * (la * (s * ra - dl * rb) + lb * (dl * ra + s * rb));
+      den += Cm * Cm * s * (la * la + lb * lb) * inv;
+      a += 2;
+    } else {
+      const C ra = to_c(r[static_cast<int64_t>(a) * Ns + j], C(0));
+      acc += l[a] * ra / s;
+      den += Cm * Cm * l[a] * l[a] / s;
+      a += 1;
+    }
+  }
+  const C yN = (to_c(r[static_cast<int64_t>(n) * Ns + j], C(0)) + Cm * acc) / den;
+  y[static_cast<int64_t>(n) * Ns + j] = from_c<S>(yN);
+  for (int a = 0; a < n;) {
+    if (kind[a] == 0) {
+      const C dl = Cm * mu[a];
+      const C inv = C(1) / (s * s + dl * dl);
+      const C ta = to_c(r[static_cast<int64_t>(a) * Ns + j], C(0)) - Cm * l[a] * yN;
+      const C tb = to_c(r[static_cast<int64_t>(a + 1) * Ns + j], C(0)) - Cm * l[a + 1] * yN;
+      y[static_cast<int64_t>(a) * Ns + j] = from_c<S>(inv * (s * ta - dl * tb));
+      y[static_cast<int64_t>(a + 1) * Ns + j] = from_c<S>(inv * (dl * ta + s * tb));
+      a += 2;
+    } else {
+      y[static_cast<int64_t>(a) * Ns + j] = from_c<S>((to_c(r[static_cast<int64_t>(a) * Ns + j], C(0)) - Cm * l[a] * yN) / s);
+      a += 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- reductions
+constexpr int RED_E = 16;                 // elements per thread
+constexpr int64_t RED_CHUNK = static_cast<int64_t>(TPB) * RED_E;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+// block-wide sum; result valid in thread 0
+__device__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (blockDim.x >> 6); ++i) r += sh[i];
+  return r;
+}
+__device__ double block_max(double v, double* sh) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (blockDim.x >> 6); ++i) r = fmax(r, sh[i]);
+  return r;
+}
+
+__global__ void __launch_bounds__(TPB) k_multidot(const double* __restrict__ V, int64_t ldv, int k,
+                                                  const double* __restrict__ w, int64_t n, double* __restrict__ part) {
+  __shared__ double sh[TPB / 64];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * RED_CHUNK + threadIdx.x;
+  double wr[RED_E];
+#pragma unroll
+  for (int e = 0; e < RED_E; ++e) {
+    const int64_t i = base + static_cast<int64_t>(e) * TPB;
+    wr[e] = (i < n) ? w[i] : 0.0;
+  }
+  for (int j = 0; j < k; ++j) {
+    const double* Vj = V + static_cast<int64_t>(j) * ldv;
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < RED_E; ++e) {
+      const int64_t i = base + static_cast<int64_t>(e) * TPB;
+      if (i < n) acc += Vj[i] * wr[e];
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[static_cast<int64_t>(blockIdx.x) * k + j] = s;
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_finalize_sum(const double* __restrict__ part, int nb, int k,
+                                                      double* __restrict__ out) {
+  __shared__ double sh[TPB / 64];
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += TPB) acc += part[static_cast<int64_t>(b) * k + j];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+__global__ void __launch_bounds__(TPB) k_finalize_max(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double sh[TPB / 64];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nb; b += TPB) m = fmax(m, part[b]);
+  const double s = block_max(m, sh);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+__global__ void __launch_bounds__(TPB) k_update_norm(const double* __restrict__ V, int64_t ldv, int k,
+                                                     const double* __restrict__ h, double* __restrict__ w, int64_t n,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[TPB / 64];
+  __shared__ double hs[128];
+  for (int j = threadIdx.x; j < k; j += TPB) hs[j] = h[j];
+  __syncthreads();
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * RED_CHUNK + threadIdx.x;
+  double acc = 0.0;
+  for (int e = 0; e < RED_E; ++e) {
+    const int64_t i = base + static_cast<int64_t>(e) * TPB;
+    if (i >= n) break;
+    double v = w[i];
+    for (int j = 0; j < k; ++j) v -= hs[j] * V[static_cast<int64_t>(j) * ldv + i];
+    w[i] = v;
+    acc += v * v;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(TPB) k_absmax(const double* __restrict__ x, int64_t n, double* __restrict__ part) {
+  __shared__ double sh[TPB / 64];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * RED_CHUNK + threadIdx.x;
+  double m = 0.0;
+  for (int e = 0; e < RED_E; ++e) {
+    const int64_t i = base + static_cast<int64_t>(e) * TPB;
+    if (i < n) m = fmax(m, fabs(x[i]));
+  }
+  const double s = block_max(m, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(TPB) k_sumsq(const double* __restrict__ x, int64_t n, double* __restrict__ part) {
+  __shared__ double sh[TPB / 64];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * RED_CHUNK + threadIdx.x;
+  double acc = 0.0;
+  for (int e = 0; e < RED_E; ++e) {
+    const int64_t i = base + static_cast<int64_t>(e) * TPB;
+    if (i < n) acc += x[i] * x[i];
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// ---------------------------------------------------------------- vector ops
+__global__ void k_scale_by_dev(double* __restrict__ x, int64_t n, const double* __restrict__ nrm2) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= 1.0 / sqrt(nrm2[0]);
+}
+__global__ void k_axpby(double a, const double* __restrict__ x, double b, double* __restrict__ y, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
+}
+__global__ void k_combine(const double* __restrict__ Z, int64_t ldz, int k, const double* __restrict__ c,
+                          double* __restrict__ x, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = x[i];
+  for (int j = 0; j < k; ++j) v += c[j] * Z[static_cast<int64_t>(j) * ldz + i];
+  x[i] = v;
+}
+template <class A, class B>
+__global__ void k_convert(const A* __restrict__ x, B* __restrict__ y, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = from_c<B>(to_c(x[i], float(0)));
+}
+__global__ void k_fill(double* __restrict__ x, double v, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+__global__ void k_add_unknowns(double* __restrict__ u, const double* __restrict__ d, double a, int64_t n, int64_t Ns) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) u[Ns + i] += a * d[i];
+}
+
+// ---------------------------------------------------------------- linearization
+__global__ void __launch_bounds__(TPB) k_pointwise_ionic(
+    const double* __restrict__ u, const double* __restrict__ ut, const double* __restrict__ lap,
+    const double* __restrict__ w, const double* __restrict__ wt, const double* __restrict__ ws, int64_t Qs,
+    int64_t total, double Cm, double a, double c1, double c2, double* __restrict__ g, double* __restrict__ absR,
+    double* __restrict__ part) {
+  __shared__ double sh[TPB / 64];
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  double mu = 0.0, mt = 0.0;
+  if (idx < total) {
+    const int64_t qt = idx / Qs, qs = idx - qt * Qs;
+    const double uu = u[idx], ww = w[idx], tt = ut[idx];
+    const double I = c1 * uu * (uu - a) * (uu - 1.0) + c2 * uu * ww;
+    g[idx] = wt[qt] * ws[qs] * I;
+    absR[idx] = fabs(Cm * tt - lap[idx] + I);
+    mu = fabs(uu);
+    mt = fabs(tt);
+  }
+  const double m1 = block_max(mu, sh);
+  if (threadIdx.x == 0) part[2 * blockIdx.x] = m1;
+  const double m2 = block_max(mt, sh);
+  if (threadIdx.x == 0) part[2 * blockIdx.x + 1] = m2;
+}
+
+__global__ void k_theta_finish(double* __restrict__ th, int64_t n, const double* __restrict__ maxes, double Cm,
+                               double invT) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double den = Cm * (maxes[0] * invT + maxes[1]);
+  const double num = th[i];
+  th[i] = (den > 0.0) ? fmin(num / den, 1.0) : (num > 0.0 ? 1.0 : 0.0);
+}
+
+__global__ void k_react_grid(const double* __restrict__ u, const double* __restrict__ w, double* __restrict__ c,
+                             int64_t n, double a, double c1, double c2, int newton) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double uu = u[i], ww = w[i];
+  c[i] = newton ? c1 * (3.0 * uu * uu - 2.0 * (1.0 + a) * uu + a) + c2 * ww
+                : c1 * (uu - a) * (uu - 1.0) + c2 * ww;
+}
+
+// Gram partials: block b accumulates C[:, cols] C[:, cols]^T over its column chunks.
+constexpr int GRAM_CH = 32;
+constexpr int GRAM_MAXE = 40;   // entries per thread (m(m+1)/2 <= 40*256)
+__global__ void __launch_bounds__(TPB) k_gram(const double* __restrict__ C, int m, int64_t n,
+                                              double* __restrict__ part) {
+  extern __shared__ char smem_raw[];
+  double* tile = reinterpret_cast<double*>(smem_raw);   // [m][GRAM_CH]
+  const int ne = m * (m + 1) / 2;
+  double acc[GRAM_MAXE];
+  int ei[GRAM_MAXE], ej[GRAM_MAXE];
+#pragma unroll
+  for (int k = 0; k < GRAM_MAXE; ++k) {
+    acc[k] = 0.0;
+    int e = threadIdx.x + k * TPB;
+    int i = 0;
+    if (e < ne) {   // e -> (i, j), j >= i, row-major over the upper triangle
+      int rem = e;
+      while (rem >= m - i) { rem -= m - i; ++i; }
+      ei[k] = i;
+      ej[k] = i + rem;
+    } else {
+      ei[k] = -1;
+      ej[k] = -1;
+    }
+  }
+  const int64_t nch = (n + GRAM_CH - 1) / GRAM_CH;
+  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < m * GRAM_CH; t += TPB) {
+      const int i = t / GRAM_CH, c = t % GRAM_CH;
+      const int64_t col = ch * GRAM_CH + c;
+      tile[t] = (col < n) ? C[static_cast<int64_t>(i) * n + col] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < GRAM_MAXE; ++k) {
+      if (ei[k] < 0) continue;
+      const double* a = tile + ei[k] * GRAM_CH;
+      const double* b = tile + ej[k] * GRAM_CH;
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < GRAM_CH; ++c) s += a[c] * b[c];
+      acc[k] += s;
+    }
+  }
+  const int64_t mm = static_cast<int64_t>(m) * m;
+#pragma unroll
+  for (int k = 0; k < GRAM_MAXE; ++k) {
+    if (ei[k] < 0) continue;
+    part[blockIdx.x * mm + static_cast<int64_t>(ei[k]) * m + ej[k]] = acc[k];
+    part[blockIdx.x * mm + static_cast<int64_t>(ej[k]) * m + ei[k]] = acc[k];
+  }
+}
+
+__global__ void k_right_factor(const double* __restrict__ C, int m, int64_t n, const double* __restrict__ U,
+                               const double* __restrict__ inv_s, int R, double* __restrict__ V) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  for (int r = 0; r < R; ++r) {
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) s += C[static_cast<int64_t>(i) * n + j] * U[i * R + r];
+    V[j * R + r] = s * inv_s[r];
+  }
+}
+
+__global__ void k_scale_rows(double* __restrict__ P, int64_t total, int64_t Qs, const double* __restrict__ wq) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < total) P[i] *= wq[i % Qs];
+}
+
+__global__ void k_transpose_nr(const double* __restrict__ V, int64_t N, int R, double* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= N * R) return;
+  const int64_t r = i / N, j = i - r * N;
+  out[i] = V[j * R + r];
+}
+
+}  // namespace
+
+// ======================================================================= wrappers
+template <class Ti, class To, class C>
+void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner, int n_in, int in_base, C alpha,
+            C beta, hipStream_t s) {
+  const int64_t total = outer * t.n_out * inner;
+  if (total == 0) return;
+  hipLaunchKernelGGL((k_gather<Ti, To, C>), dim3(grid_for(total)), dim3(TPB), 0, s, t.col, t.coef, t.W, t.n_out, x, y,
+                     inner, n_in, in_base, alpha, beta, total);
+}
+
+template <class Ti, class To, class C>
+void gather_rows(const DTable<C>& t, int r0, int nr, const Ti* x, To* y, int64_t outer, int64_t inner, int n_in,
+                 int in_base, C alpha, C beta, hipStream_t s) {
+  DTable<C> u;
+  u.col = t.col + static_cast<int64_t>(r0) * t.W;
+  u.coef = t.coef + static_cast<int64_t>(r0) * t.W;
+  u.W = t.W;
+  u.n_out = nr;
+  gather<Ti, To, C>(u, x, y, outer, inner, n_in, in_base, alpha, beta, s);
+}
+
+void mode_max(const int* start, const int* cnt, int n_out, const double* x, double* y, int64_t outer, int64_t inner,
+              int n_in, hipStream_t s) {
+  const int64_t total = outer * n_out * inner;
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_mode_max, dim3(grid_for(total)), dim3(TPB), 0, s, start, cnt, n_out, x, y, inner, n_in, total);
+}
+
+template <class S, class C>
+void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int p, const S* Z, int n_in, int in_base, S* out,
+              int64_t Qs, hipStream_t s) {
+  const int R = r1 - r0;
+  int tpb = TPB;
+  while (tpb > 64 && static_cast<size_t>(R) * tpb * sizeof(C) > 64 * 1024) tpb /= 2;
+  const size_t sh = static_cast<size_t>(R > 0 ? R : 1) * tpb * sizeof(C);
+  const dim3 g(grid_for(Qs, tpb)), b(tpb);
+  switch (p) {
+    case 1: hipLaunchKernelGGL((k_time_mix<S, C, 1>), g, b, sh, s, T, Psi, r0, R, Nt, Z, n_in, in_base, out, Qs); break;
+    case 2: hipLaunchKernelGGL((k_time_mix<S, C, 2>), g, b, sh, s, T, Psi, r0, R, Nt, Z, n_in, in_base, out, Qs); break;
+    case 3: hipLaunchKernelGGL((k_time_mix<S, C, 3>), g, b, sh, s, T, Psi, r0, R, Nt, Z, n_in, in_base, out, Qs); break;
+    case 4: hipLaunchKernelGGL((k_time_mix<S, C, 4>), g, b, sh, s, T, Psi, r0, R, Nt, Z, n_in, in_base, out, Qs); break;
+    default: hipLaunchKernelGGL((k_time_mix<S, C, 5>), g, b, sh, s, T, Psi, r0, R, Nt, Z, n_in, in_base, out, Qs); break;
+  }
+}
+
+template <class S, class C>
+void arrowhead(const S* r, S* y, const C* lam, const C* mu, const int* kind, const C* l, C sigma, C Cm, int Nt,
+               int64_t Ns, hipStream_t s) {
+  hipLaunchKernelGGL((k_arrowhead<S, C>), dim3(grid_for(Ns)), dim3(TPB), 0, s, r, y, lam, mu, kind, l, sigma, Cm, Nt, Ns);
+}
+
+int reduce_blocks(int64_t n) { return static_cast<int>((n + RED_CHUNK - 1) / RED_CHUNK); }
+
+void multidot_partial(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* part, int nb,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_multidot, dim3(nb), dim3(TPB), 0, s, V, ldv, k, w, n, part);
+}
+void finalize_sum(const double* part, int nb, int k, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_sum, dim3(k), dim3(TPB), 0, s, part, nb, k, out);
+}
+void update_norm_partial(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t n, double* part,
+                         int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_norm, dim3(nb), dim3(TPB), 0, s, V, ldv, k, h, w, n, part);
+}
+void absmax_partial(const double* x, int64_t n, double* part, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_absmax, dim3(nb), dim3(TPB), 0, s, x, n, part);
+}
+void sumsq_partial(const double* x, int64_t n, double* part, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(TPB), 0, s, x, n, part);
+}
+void finalize_max(const double* part, int nb, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_max, dim3(1), dim3(TPB), 0, s, part, nb, out);
+}
+void scale_by_dev(double* x, int64_t n, const double* nrm2, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_by_dev, dim3(grid_for(n)), dim3(TPB), 0, s, x, n, nrm2);
+}
+void axpy(double a, const double* x, double* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(TPB), 0, s, a, x, 1.0, y, n);
+}
+void axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(TPB), 0, s, a, x, b, y, n);
+}
+void combine(const double* Z, int64_t ldz, int k, const double* c, double* x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine, dim3(grid_for(n)), dim3(TPB), 0, s, Z, ldz, k, c, x, n);
+}
+template <class A, class B>
+void convert(const A* x, B* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<A, B>), dim3(grid_for(n)), dim3(TPB), 0, s, x, y, n);
+}
+void fill(double* x, double v, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(TPB), 0, s, x, v, n);
+}
+void pointwise_ionic(const double* u, const double* ut, const double* lap, const double* w, const double* wt_time,
+                     const double* wt_space, int64_t Qs, int nq_t, double Cm, double a, double c1, double c2,
+                     double* g, double* absR, double* part, int nb, hipStream_t s) {
+  const int64_t total = Qs * nq_t;
+  (void)nb;
+  hipLaunchKernelGGL(k_pointwise_ionic, dim3(grid_for(total)), dim3(TPB), 0, s, u, ut, lap, w, wt_time, wt_space, Qs,
+                     total, Cm, a, c1, c2, g, absR, part);
+}
+void theta_finish(double* th, int64_t n, const double* maxes, double Cm, double invT, hipStream_t s) {
+  hipLaunchKernelGGL(k_theta_finish, dim3(grid_for(n)), dim3(TPB), 0, s, th, n, maxes, Cm, invT);
+}
+void react_grid(const double* u, const double* w, double* c, int64_t n, double a, double c1, double c2, int newton,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_react_grid, dim3(grid_for(n)), dim3(TPB), 0, s, u, w, c, n, a, c1, c2, newton);
+}
+void gram_partial(const double* C, int m, int64_t n, double* part, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram, dim3(nb), dim3(TPB), static_cast<size_t>(m) * GRAM_CH * sizeof(double), s, C, m, n, part);
+}
+void right_factor(const double* C, int m, int64_t n, const double* U, const double* inv_s, int R, double* V,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_right_factor, dim3(grid_for(n)), dim3(TPB), 0, s, C, m, n, U, inv_s, R, V);
+}
+void scale_rows(double* Psi, int R, int64_t Qs, const double* wq, hipStream_t s) {
+  const int64_t total = static_cast<int64_t>(R) * Qs;
+  if (total > 0) hipLaunchKernelGGL(k_scale_rows, dim3(grid_for(total)), dim3(TPB), 0, s, Psi, total, Qs, wq);
+}
+void transpose_nr(const double* V, int64_t N, int R, double* out, hipStream_t s) {
+  if (N * R > 0) hipLaunchKernelGGL(k_transpose_nr, dim3(grid_for(N * R)), dim3(TPB), 0, s, V, N, R, out);
+}
+void add_unknowns(double* u_full, const double* delta, double alpha, int64_t n_unk, int64_t Ns, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_unknowns, dim3(grid_for(n_unk)), dim3(TPB), 0, s, u_full, delta, alpha, n_unk, Ns);
+}
+
+// explicit instantiations
+template void gather<double, double, double>(const DTable<double>&, const double*, double*, int64_t, int64_t, int,
+                                             int, double, double, hipStream_t);
+template void gather<float, float, float>(const DTable<float>&, const float*, float*, int64_t, int64_t, int, int,
+                                          float, float, hipStream_t);
+template void gather<bf16, bf16, float>(const DTable<float>&, const bf16*, bf16*, int64_t, int64_t, int, int, float,
+                                        float, hipStream_t);
+template void gather_rows<double, double, double>(const DTable<double>&, int, int, const double*, double*, int64_t,
+                                                  int64_t, int, int, double, double, hipStream_t);
+template void time_mix<double, double>(const double*, const double*, int, int, int, int, const double*, int, int,
+                                       double*, int64_t, hipStream_t);
+template void time_mix<float, float>(const float*, const float*, int, int, int, int, const float*, int, int, float*,
+                                     int64_t, hipStream_t);
+template void time_mix<bf16, float>(const float*, const bf16*, int, int, int, int, const bf16*, int, int, bf16*,
+                                    int64_t, hipStream_t);
+template void arrowhead<double, double>(const double*, double*, const double*, const double*, const int*,
+                                        const double*, double, double, int, int64_t, hipStream_t);
+template void arrowhead<float, float>(const float*, float*, const float*, const float*, const int*, const float*,
+                                      float, float, int, int64_t, hipStream_t);
+template void arrowhead<bf16, float>(const bf16*, bf16*, const float*, const float*, const int*, const float*, float,
+                                     float, int, int64_t, hipStream_t);
+template void convert<double, float>(const double*, float*, int64_t, hipStream_t);
+template void convert<float, double>(const float*, double*, int64_t, hipStream_t);
+template void convert<double, bf16>(const double*, bf16*, int64_t, hipStream_t);
+template void convert<bf16, double>(const bf16*, double*, int64_t, hipStream_t);
+
+}  // namespace stiga

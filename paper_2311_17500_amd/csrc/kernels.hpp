@@ -1,0 +1,100 @@
+// Launch wrappers of the gfx950 kernels (implemented in kernels.hip).
+//
+// Array views: a tensor is addressed as [outer][n][inner] around the axis a
+// kernel acts on (inner = product of the faster axes, outer = product of the
+// slower ones).  All index arithmetic is 64-bit.
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <hip/hip_bf16.h>
+#include <cstdint>
+
+namespace stiga {
+
+typedef __hip_bfloat16 bf16;
+
+// Device view of a gather table: y[i] = sum_w coef[i*W+w] * x[col[i*W+w] - in_base],
+// terms with the input index outside [0, n_in) skipped.
+template <class C>
+struct DTable {
+  const int* col = nullptr;
+  const C* coef = nullptr;
+  int n_out = 0, W = 0;
+};
+
+// y[o][i][k] = alpha * sum_w coef * x[o][col-in_base][k] + beta * y[o][i][k]
+// (beta == 0: y is not read).  Input element type Ti, output To, arithmetic C.
+template <class Ti, class To, class C>
+void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner, int n_in, int in_base,
+            C alpha, C beta, hipStream_t s);
+
+// Same, restricted to output rows [r0, r0 + nr) of the table (y holds only those rows).
+template <class Ti, class To, class C>
+void gather_rows(const DTable<C>& t, int r0, int nr, const Ti* x, To* y, int64_t outer, int64_t inner, int n_in,
+                 int in_base, C alpha, C beta, hipStream_t s);
+
+// y[o][i][k] = max_{w < cnt[i]} x[o][start[i]+w][k]
+void mode_max(const int* start, const int* cnt, int n_out, const double* x, double* y, int64_t outer,
+              int64_t inner, int n_in, hipStream_t s);
+
+// Coefficient part of the operator at the spatial Gauss points:
+//   out[t][q] = sum_{r in [r0,r1)} Psi[r][q] sum_w T[r][t][w] * Z[t+1-p+w - in_base][q]
+// (t = 0..N_t-1 rows of X_t; inputs outside [0, n_in) skipped).
+template <class S, class C>
+void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int p, const S* Z, int n_in, int in_base,
+              S* out, int64_t Qs, hipStream_t s);
+
+// Arrowhead solve of the fast-diagonalization core, one spatial mode per thread.
+template <class S, class C>
+void arrowhead(const S* r, S* y, const C* lam, const C* mu, const int* kind, const C* l, C sigma, C Cm,
+               int Nt, int64_t Ns, hipStream_t s);
+
+// Deterministic reductions (two stages, fixed order).
+int reduce_blocks(int64_t n);
+// part[b*k + j] = partial of <V_j, w> over block b; V_j = V + j*ldv
+void multidot_partial(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* part, int nb,
+                      hipStream_t s);
+// out[j] = sum_b part[b*k + j]
+void finalize_sum(const double* part, int nb, int k, double* out, hipStream_t s);
+// w -= sum_j h[j] V_j ; part[b] = partial ||w||^2 (h read from device)
+void update_norm_partial(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t n,
+                         double* part, int nb, hipStream_t s);
+// part[b] = partial max |x| (kind 0) or sum x^2 (kind 1)
+void absmax_partial(const double* x, int64_t n, double* part, int nb, hipStream_t s);
+void sumsq_partial(const double* x, int64_t n, double* part, int nb, hipStream_t s);
+void finalize_max(const double* part, int nb, double* out, hipStream_t s);
+
+// x = a * x (scale from a device scalar: x *= 1/sqrt(*nrm2) if inv_sqrt)
+void scale_by_dev(double* x, int64_t n, const double* nrm2, hipStream_t s);
+void axpy(double a, const double* x, double* y, int64_t n, hipStream_t s);            // y += a x
+void axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);  // y = a x + b y
+// x += sum_j c[j] Z_j (c on device)
+void combine(const double* Z, int64_t ldz, int k, const double* c, double* x, int64_t n, hipStream_t s);
+template <class A, class B>
+void convert(const A* x, B* y, int64_t n, hipStream_t s);
+void fill(double* x, double v, int64_t n, hipStream_t s);
+
+// Pointwise linearization at space-time Gauss points of one time chunk:
+//   g = omega * I_ion(u, w);  absR = |Cm ut - lap + I_ion(u, w)|;
+//   part[2b] = max |u|, part[2b+1] = max |ut| over block b.
+void pointwise_ionic(const double* u, const double* ut, const double* lap, const double* w,
+                     const double* wt_time, const double* wt_space, int64_t Qs, int nq_t, double Cm,
+                     double a, double c1, double c2, double* g, double* absR, double* part, int nb,
+                     hipStream_t s);
+// theta = min(num/den, 1) with den from device maxima (den = Cm (umax/T + utmax)); den == 0 -> num > 0
+void theta_finish(double* th, int64_t n, const double* maxes, double Cm, double invT, hipStream_t s);
+// coefficient grid: newton ? dI/du : C_r at (u, w)
+void react_grid(const double* u, const double* w, double* c, int64_t n, double a, double c1, double c2, int newton,
+                hipStream_t s);
+// Gram matrix G = C C^T of an (m x n) row-major matrix (partials per block, then reduce)
+void gram_partial(const double* C, int m, int64_t n, double* part, int nb, hipStream_t s);
+// V[j][r] = sum_i C[i][j] U[i][r] * inv_s[r]  (U: m x R row-major on device)
+void right_factor(const double* C, int m, int64_t n, const double* U, const double* inv_s, int R, double* V,
+                  hipStream_t s);
+// Psi[r][q] *= wq[q] (spatial weights, length Qs) for r in [0, R)
+void scale_rows(double* Psi, int R, int64_t Qs, const double* wq, hipStream_t s);
+// out[r][j] = V[j][r] (transpose N x R -> R x N)
+void transpose_nr(const double* V, int64_t N, int R, double* out, hipStream_t s);
+// Newton update u[layers 1..] += alpha * delta; returns nothing (norm via absmax)
+void add_unknowns(double* u_full, const double* delta, double alpha, int64_t n_unk, int64_t Ns, hipStream_t s);
+
+}  // namespace stiga

@@ -1,0 +1,1496 @@
+// C ABI of the space-time SU isogeometric solver (declared in include/st_iga.h).
+//
+// Host code orchestrates gfx950 kernels on the caller's stream; all device
+// memory is carved from the caller's workspace.  See kernels.hip for the
+// kernels and host_setup.cpp for the FP64 setup of the 1D data.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/st_iga.h"
+#include "host_setup.hpp"
+#include "kernels.hpp"
+
+using namespace stiga;
+
+namespace {
+
+struct Fail {
+  st_iga_status st;
+  std::string msg;
+};
+
+#define CK(call)                                                                       \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) throw Fail{ST_IGA_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Fail{ST_IGA_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e)};
+}
+
+// Bump allocator over the caller's workspace; in dry mode it only measures.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
+  bool dry = true;
+  void* take(size_t bytes) {
+    off = (off + 255) & ~static_cast<size_t>(255);
+    void* p = dry ? nullptr : base + off;
+    off += bytes;
+    if (!dry && off > cap) throw Fail{ST_IGA_ENOMEM, "workspace too small"};
+    return p;
+  }
+  template <class T>
+  T* get(int64_t n) { return static_cast<T*>(take(static_cast<size_t>(std::max<int64_t>(n, 1)) * sizeof(T))); }
+};
+
+// A table resident on the device in FP64 and FP32.
+struct Tab {
+  Gather h;
+  DTable<double> d;
+  DTable<float> f;
+};
+
+template <class C>
+struct Prec;   // per-precision device data of the operators
+}  // namespace
+
+struct st_iga_ctx {
+  st_iga_problem P{};
+  st_iga_options opt{};
+  int d = 0;
+  std::vector<Dir1D> dir;   // d spatial + time (last)
+  int n[3] = {1, 1, 1}, Q[3] = {1, 1, 1};
+  int nt = 0, Nt = 0, nqt = 0, nelt = 0, nel[3] = {1, 1, 1};
+  int64_t Ns = 0, Qs = 0, nunk = 0, nfull = 0, Nels = 0;
+  int chunk_el = 1;
+  int64_t big_len = 0;
+  Arena ar;
+  std::string err;
+  // host setup results
+  std::vector<double> Mt_full, Wt_full, tauq, lam_s_h;
+  std::vector<std::vector<double>> Us_h, lam_h;
+  TimeFD fd;
+  // tables
+  Tab Ms[3], Ks[3], Bq[3][3], BqT[3], Hs[3], Gs[3], Us[3], UsT[3];
+  Tab Mt_x, Wt_x, Bt0, Bt1, BtT, Gt, Ut, UtT, Ew;
+  // device data
+  double *lam_d = nullptr, *mu_d = nullptr, *l_d = nullptr;
+  float *lam_f = nullptr, *mu_f = nullptr, *l_f = nullptr;
+  int* kind_d = nullptr;
+  int *el_t_s = nullptr, *el_t_c = nullptr, *el_s_s[3] = {}, *el_s_c[3] = {};
+  int *win_t_s = nullptr, *win_t_c = nullptr, *win_s_s[3] = {}, *win_s_c[3] = {};
+  double *wq_s = nullptr, *wq_t = nullptr;
+  // low-rank factors
+  int maxR = 0, Rth = 0, Rc = 0;
+  std::vector<double> Uth_h, sth_h, Uc_h, sc_h;  // host copies: U (N_t x R), s
+  double *Vth = nullptr, *Vc = nullptr;          // device N_s x maxR
+  double *Psi = nullptr, *Tr = nullptr;
+  float *Psi_f = nullptr, *Tr_f = nullptr;
+  bf16* Psi_b = nullptr;
+  bool linearized = false;
+  // buffers
+  double *t4[4] = {}, *big[2] = {};
+  float *t4f[4] = {}, *bigf[2] = {}, *xf = nullptr, *yf = nullptr;
+  bf16 *t4b[4] = {}, *bigb[2] = {}, *xb = nullptr, *yb = nullptr;
+  double *Vk = nullptr, *Zk = nullptr, *rk = nullptr, *xk = nullptr, *wk = nullptr, *dk = nullptr, *bk = nullptr;
+  double *VT = nullptr, *sol_rhs = nullptr, *sol_dx = nullptr;
+  double *grid = nullptr, *grid2 = nullptr, *E = nullptr, *rfull = nullptr, *Cg = nullptr;
+  double *part = nullptr, *dsc = nullptr, *gram = nullptr, *tmpR = nullptr;
+  int nb_red = 0, nb_part = 0, gram_nb = 0;
+};
+
+namespace {
+
+// ------------------------------------------------------------------ host setup
+void validate(const st_iga_problem* P, const st_iga_options* O) {
+  if (!P || !O) throw Fail{ST_IGA_EINVAL, "null problem or options"};
+  if (P->d < 1 || P->d > 3) throw Fail{ST_IGA_EINVAL, "d must be 1, 2 or 3"};
+  if (P->p_s < 1 || P->p_t < 1) throw Fail{ST_IGA_EINVAL, "degrees must be >= 1"};
+  if (P->p_t > 5) throw Fail{ST_IGA_EINVAL, "time degree above 5 is not supported"};
+  if (!(P->T > 0) || !(P->Cm > 0)) throw Fail{ST_IGA_EINVAL, "T and Cm must be positive"};
+  for (int l = 0; l < P->d; ++l)
+    if (!(P->sigma[l] > 0)) throw Fail{ST_IGA_EINVAL, "sigma must be positive"};
+  if (!(P->a > 0) || !(P->b > 0) || !(P->de > 0) || P->c1 < 0 || P->c2 < 0)
+    throw Fail{ST_IGA_EINVAL, "Rogers-McCulloch parameters out of range"};
+  for (int l = 0; l <= P->d; ++l)
+    if (!P->knots[l]) throw Fail{ST_IGA_EINVAL, "null knot vector"};
+  if (O->restart < 1 || O->restart > 64) throw Fail{ST_IGA_EINVAL, "restart must be in 1..64"};
+  if (O->max_rank < 1 || O->max_rank > 128) throw Fail{ST_IGA_EINVAL, "max_rank must be in 1..128"};
+  if (O->prec < ST_IGA_FP64 || O->prec > ST_IGA_MIXED_BF16) throw Fail{ST_IGA_EINVAL, "bad precision"};
+  if (O->su) {  // SU needs C^{p_t - 1} in time: interior time multiplicity 1
+    const double* k = P->knots[P->d];
+    const int nk = P->nknots[P->d];
+    for (int i = P->p_t + 1; i + 1 <= nk - P->p_t - 2; ++i)   // interior knots only
+      if (k[i] == k[i + 1]) throw Fail{ST_IGA_EINVAL, "SU needs maximal time regularity"};
+  }
+}
+
+std::vector<double> sub_rows(const std::vector<double>& A, int n, int r0, int r1, int c0, int c1) {
+  std::vector<double> B(static_cast<size_t>(r1 - r0) * (c1 - c0));
+  for (int i = r0; i < r1; ++i)
+    for (int j = c0; j < c1; ++j) B[static_cast<size_t>(i - r0) * (c1 - c0) + (j - c0)] = A[static_cast<size_t>(i) * n + j];
+  return B;
+}
+
+Gather sparse_rows(const std::vector<double>& A, int nrow, int ncol) {
+  Gather G;
+  G.n_out = nrow;
+  G.W = 1;
+  for (int i = 0; i < nrow; ++i) {
+    int c = 0;
+    for (int j = 0; j < ncol; ++j) c += A[static_cast<size_t>(i) * ncol + j] != 0.0;
+    G.W = std::max(G.W, c);
+  }
+  G.col.assign(static_cast<size_t>(nrow) * G.W, 0);
+  G.coef.assign(static_cast<size_t>(nrow) * G.W, 0.0);
+  for (int i = 0; i < nrow; ++i) {
+    int k = 0;
+    for (int j = 0; j < ncol; ++j)
+      if (A[static_cast<size_t>(i) * ncol + j] != 0.0) {
+        G.col[static_cast<size_t>(i) * G.W + k] = j;
+        G.coef[static_cast<size_t>(i) * G.W + k] = A[static_cast<size_t>(i) * ncol + j];
+        ++k;
+      }
+    for (; k < G.W; ++k) G.col[static_cast<size_t>(i) * G.W + k] = 0;
+  }
+  return G;
+}
+
+Gather hat_table(const std::vector<double>& nodes, const std::vector<double>& x) {
+  std::vector<int> left;
+  std::vector<double> wl;
+  hat_weights(nodes, x, left, wl);
+  Gather G;
+  G.n_out = static_cast<int>(x.size());
+  G.W = 2;
+  G.col.resize(x.size() * 2);
+  G.coef.resize(x.size() * 2);
+  const int N = static_cast<int>(nodes.size());
+  for (size_t m = 0; m < x.size(); ++m) {
+    G.col[2 * m] = left[m];
+    G.coef[2 * m] = wl[m];
+    G.col[2 * m + 1] = std::min(left[m] + 1, N - 1);
+    G.coef[2 * m + 1] = (N == 1) ? 0.0 : 1.0 - wl[m];
+  }
+  return G;
+}
+
+void host_setup(st_iga_ctx* c) {
+  const st_iga_problem& P = c->P;
+  c->d = P.d;
+  c->dir.assign(P.d + 1, Dir1D());
+  std::string err;
+  for (int l = 0; l < P.d; ++l)
+    if (!build_dir(P.knots[l], P.nknots[l], P.p_s, 1.0, 2, c->dir[l], err)) throw Fail{ST_IGA_EINVAL, "space knots: " + err};
+  if (!build_dir(P.knots[P.d], P.nknots[P.d], P.p_t, P.T, P.p_t, c->dir[P.d], err))
+    throw Fail{ST_IGA_EINVAL, "time knots: " + err};
+  const Dir1D& T = c->dir[P.d];
+  c->Ns = 1;
+  c->Qs = 1;
+  c->Nels = 1;
+  for (int l = 0; l < P.d; ++l) {
+    c->n[l] = c->dir[l].n;
+    c->Q[l] = c->dir[l].Q;
+    c->nel[l] = c->dir[l].nel;
+    c->Ns *= c->n[l];
+    c->Qs *= c->Q[l];
+    c->Nels *= c->nel[l];
+  }
+  c->nt = T.n;
+  c->Nt = T.n - 1;
+  c->nqt = T.nq;
+  c->nelt = T.nel;
+  if (c->Nt < 2) throw Fail{ST_IGA_EINVAL, "need at least two time unknowns"};
+  if (c->Nt > 142) throw Fail{ST_IGA_EINVAL, "more than 142 time unknowns is not supported"};
+  c->nunk = c->Ns * c->Nt;
+  c->nfull = c->Ns * c->nt;
+  c->maxR = c->opt.max_rank;
+  // 1D matrices
+  c->Mt_full = gram1d(T, 0, 0, nullptr);
+  c->Wt_full = gram1d(T, 0, 1, nullptr);
+  const int nt = c->nt, Nt = c->Nt, pt = P.p_t;
+  c->Mt_x.h = banded_table(c->Mt_full, nt, 1, Nt, pt);
+  c->Wt_x.h = banded_table(c->Wt_full, nt, 1, Nt, pt);
+  c->Bt0.h = eval_table(T, 0);
+  c->Bt1.h = eval_table(T, 1);
+  c->BtT.h = eval_table_T(T, 0, nullptr);
+  std::vector<double> tau_coefs;
+  if (!tau_at_quad(T, c->tauq, tau_coefs, err)) throw Fail{ST_IGA_EINVAL, err};
+  c->Us_h.assign(P.d, {});
+  c->lam_h.assign(P.d, {});
+  for (int l = 0; l < P.d; ++l) {
+    const Dir1D& D = c->dir[l];
+    std::vector<double> M = gram1d(D, 0, 0, nullptr), K = gram1d(D, 1, 1, nullptr);
+    c->Ms[l].h = banded_table(M, D.n, 0, D.n, D.p);
+    c->Ks[l].h = banded_table(K, D.n, 0, D.n, D.p);
+    for (int k = 0; k <= 2; ++k) c->Bq[l][k].h = eval_table(D, k);
+    c->BqT[l].h = eval_table_T(D, 0, nullptr);
+    c->Hs[l].h = hat_table(D.grev, D.xq);
+    c->Gs[l].h = sparse_rows(collocation(D, D.grev, 0), D.n, D.n);
+    if (!gen_eig_sym(K, M, D.n, c->Us_h[l], c->lam_h[l], err)) throw Fail{ST_IGA_EINVAL, err};
+    c->Us[l].h = dense_table(c->Us_h[l], D.n, D.n, false);
+    c->UsT[l].h = dense_table(c->Us_h[l], D.n, D.n, true);
+  }
+  // time Greville collocation on X_t Greville points
+  std::vector<double> gt(T.grev.begin() + 1, T.grev.end());
+  c->Gt.h = sparse_rows(collocation(T, gt, 0), Nt, nt);
+  // FD time data on the X_t block
+  std::vector<double> Wx = sub_rows(c->Wt_full, nt, 1, nt, 1, nt), Mx = sub_rows(c->Mt_full, nt, 1, nt, 1, nt);
+  if (!time_fd(Wx, Mx, Nt, c->fd, err)) throw Fail{ST_IGA_EINVAL, err};
+  c->Ut.h = dense_table(c->fd.U, Nt, Nt, false);
+  c->UtT.h = dense_table(c->fd.U, Nt, Nt, true);
+  // spatial eigenvalue sums + shift
+  c->lam_s_h.assign(c->Ns, 0.0);
+  for (int64_t j = 0; j < c->Ns; ++j) {
+    int64_t r = j;
+    double s = P.a * P.c1;
+    for (int l = 0; l < P.d; ++l) {
+      const int il = static_cast<int>(r % c->n[l]);
+      r /= c->n[l];
+      s += P.sigma[l] * c->lam_h[l][il];
+    }
+    c->lam_s_h[j] = s;
+  }
+  // w-update operator: b (W + b de M)^{-1}_{XtXt} M_{Xt,full}
+  {
+    std::vector<double> L(static_cast<size_t>(Nt) * Nt), R(static_cast<size_t>(Nt) * nt);
+    for (int i = 0; i < Nt; ++i) {
+      for (int j = 0; j < Nt; ++j)
+        L[static_cast<size_t>(i) * Nt + j] = c->Wt_full[static_cast<size_t>(i + 1) * nt + j + 1] +
+                                             P.b * P.de * c->Mt_full[static_cast<size_t>(i + 1) * nt + j + 1];
+      for (int j = 0; j < nt; ++j) R[static_cast<size_t>(i) * nt + j] = P.b * c->Mt_full[static_cast<size_t>(i + 1) * nt + j];
+    }
+    // Gaussian elimination with partial pivoting on [L | R]
+    for (int col = 0; col < Nt; ++col) {
+      int pr = col;
+      for (int r = col + 1; r < Nt; ++r)
+        if (std::fabs(L[static_cast<size_t>(r) * Nt + col]) > std::fabs(L[static_cast<size_t>(pr) * Nt + col])) pr = r;
+      if (L[static_cast<size_t>(pr) * Nt + col] == 0.0) throw Fail{ST_IGA_EINVAL, "singular w-update matrix"};
+      if (pr != col) {
+        for (int k = 0; k < Nt; ++k) std::swap(L[static_cast<size_t>(col) * Nt + k], L[static_cast<size_t>(pr) * Nt + k]);
+        for (int k = 0; k < nt; ++k) std::swap(R[static_cast<size_t>(col) * nt + k], R[static_cast<size_t>(pr) * nt + k]);
+      }
+      for (int r = 0; r < Nt; ++r) {
+        if (r == col) continue;
+        const double f = L[static_cast<size_t>(r) * Nt + col] / L[static_cast<size_t>(col) * Nt + col];
+        if (f == 0.0) continue;
+        for (int k = col; k < Nt; ++k) L[static_cast<size_t>(r) * Nt + k] -= f * L[static_cast<size_t>(col) * Nt + k];
+        for (int k = 0; k < nt; ++k) R[static_cast<size_t>(r) * nt + k] -= f * R[static_cast<size_t>(col) * nt + k];
+      }
+    }
+    for (int r = 0; r < Nt; ++r)
+      for (int k = 0; k < nt; ++k) R[static_cast<size_t>(r) * nt + k] /= L[static_cast<size_t>(r) * Nt + r];
+    c->Ew.h = dense_table(R, Nt, nt, false);
+  }
+  // chunking of the quadrature pass: arrays per time Gauss point row
+  // the quadrature pass keeps 3 arrays of N_s and 3 of Q_s doubles per time
+  // Gauss point in the first big buffer and 5 of Q_s in the second
+  c->big_len = std::max<int64_t>({static_cast<int64_t>(c->nt) * c->Qs, 5LL * c->nqt * c->Qs,
+                                  3LL * c->nqt * (c->Ns + c->Qs), 2LL * c->Qs + 0});
+  const int64_t cq = std::min<int64_t>(c->big_len / (3 * (c->Ns + c->Qs)), c->big_len / (5 * c->Qs));
+  c->chunk_el = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(c->nelt, cq / c->nqt)));
+}
+
+// Reserve device memory for everything; in dry mode only sizes are computed.
+template <class C>
+void alloc_tab(Arena& a, Tab& t) {
+  const size_t n = t.h.col.size();
+  t.d.col = a.get<int>(n);
+  t.d.coef = a.get<double>(n);
+  t.f.col = t.d.col;
+  t.f.coef = a.get<float>(n);
+  t.d.n_out = t.f.n_out = t.h.n_out;
+  t.d.W = t.f.W = t.h.W;
+}
+
+void plan(st_iga_ctx* c) {
+  Arena& a = c->ar;
+  const bool mixed = c->opt.prec != ST_IGA_FP64;
+  const bool bf = c->opt.prec == ST_IGA_MIXED_BF16;
+  const int d = c->d;
+  auto T = [&](Tab& t) { alloc_tab<double>(a, t); };
+  for (int l = 0; l < d; ++l) {
+    T(c->Ms[l]); T(c->Ks[l]); T(c->BqT[l]); T(c->Hs[l]); T(c->Gs[l]); T(c->Us[l]); T(c->UsT[l]);
+    for (int k = 0; k <= 2; ++k) T(c->Bq[l][k]);
+  }
+  T(c->Mt_x); T(c->Wt_x); T(c->Bt0); T(c->Bt1); T(c->BtT); T(c->Gt); T(c->Ut); T(c->UtT); T(c->Ew);
+  c->lam_d = a.get<double>(c->Ns);
+  c->lam_f = a.get<float>(c->Ns);
+  c->mu_d = a.get<double>(c->Nt);
+  c->l_d = a.get<double>(c->Nt);
+  c->mu_f = a.get<float>(c->Nt);
+  c->l_f = a.get<float>(c->Nt);
+  c->kind_d = a.get<int>(c->Nt);
+  c->el_t_s = a.get<int>(c->nelt);
+  c->el_t_c = a.get<int>(c->nelt);
+  c->win_t_s = a.get<int>(c->Nt);
+  c->win_t_c = a.get<int>(c->Nt);
+  for (int l = 0; l < d; ++l) {
+    c->el_s_s[l] = a.get<int>(c->nel[l]);
+    c->el_s_c[l] = a.get<int>(c->nel[l]);
+    c->win_s_s[l] = a.get<int>(c->n[l]);
+    c->win_s_c[l] = a.get<int>(c->n[l]);
+  }
+  c->wq_s = a.get<double>(c->Qs);
+  c->wq_t = a.get<double>(c->dir[d].Q);
+  const int R2 = 2 * c->maxR;
+  const int WB = 2 * c->P.p_t + 1;
+  c->Vth = a.get<double>(c->Ns * c->maxR);
+  c->Vc = a.get<double>(c->Ns * c->maxR);
+  c->Psi = a.get<double>(static_cast<int64_t>(R2) * c->Qs);
+  c->Tr = a.get<double>(static_cast<int64_t>(R2) * c->Nt * WB);
+  c->Tr_f = a.get<float>(static_cast<int64_t>(R2) * c->Nt * WB);
+  for (int k = 0; k < 4; ++k) c->t4[k] = a.get<double>(c->nfull);
+  for (int k = 0; k < 2; ++k) c->big[k] = a.get<double>(c->big_len);
+  c->VT = a.get<double>(static_cast<int64_t>(c->maxR) * c->Ns);
+  c->sol_rhs = a.get<double>(c->nunk);
+  c->sol_dx = a.get<double>(c->nunk);
+  const int m = c->opt.restart;
+  c->Vk = a.get<double>(static_cast<int64_t>(m + 1) * c->nunk);
+  c->Zk = a.get<double>(static_cast<int64_t>(m) * c->nunk);
+  c->rk = a.get<double>(c->nunk);
+  c->xk = a.get<double>(c->nunk);
+  c->wk = a.get<double>(c->nunk);
+  c->dk = a.get<double>(c->nunk);
+  c->bk = a.get<double>(c->nunk);
+  c->grid = a.get<double>(c->nunk);
+  c->grid2 = a.get<double>(c->nunk);
+  c->Cg = a.get<double>(c->nunk);
+  c->E = a.get<double>(static_cast<int64_t>(c->nelt) * c->Nels);
+  c->rfull = a.get<double>(c->nfull);
+  c->nb_red = reduce_blocks(c->nfull);
+  const int64_t chunk_pts = static_cast<int64_t>(c->chunk_el) * c->nqt * c->Qs;
+  const int nchunks = (c->nelt + c->chunk_el - 1) / c->chunk_el;
+  c->nb_part = static_cast<int>((chunk_pts + 255) / 256) * nchunks + 1;
+  c->part = a.get<double>(std::max<int64_t>(static_cast<int64_t>(c->nb_red) * 70, 2 * static_cast<int64_t>(c->nb_part)));
+  c->dsc = a.get<double>(1024);
+  c->gram_nb = static_cast<int>(std::min<int64_t>(512, (c->Ns + 31) / 32));
+  c->gram = a.get<double>(static_cast<int64_t>(c->gram_nb) * c->Nt * c->Nt);
+  c->tmpR = a.get<double>(static_cast<int64_t>(c->Nt) * c->maxR + 2 * c->maxR);
+  if (mixed) {
+    c->Psi_f = a.get<float>(static_cast<int64_t>(R2) * c->Qs);
+    if (bf) {
+      c->Psi_b = a.get<bf16>(static_cast<int64_t>(R2) * c->Qs);
+      for (int k = 0; k < 4; ++k) c->t4b[k] = a.get<bf16>(c->nfull);
+      for (int k = 0; k < 2; ++k) c->bigb[k] = a.get<bf16>(c->big_len);
+      c->xb = a.get<bf16>(c->nunk);
+      c->yb = a.get<bf16>(c->nunk);
+    } else {
+      for (int k = 0; k < 4; ++k) c->t4f[k] = a.get<float>(c->nfull);
+      for (int k = 0; k < 2; ++k) c->bigf[k] = a.get<float>(c->big_len);
+      c->xf = a.get<float>(c->nunk);
+      c->yf = a.get<float>(c->nunk);
+    }
+  }
+}
+
+template <class X>
+void up(const std::vector<X>& h, const X* d, hipStream_t s) {
+  if (!h.empty()) CK(hipMemcpyAsync(const_cast<X*>(d), h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice, s));
+}
+
+void upload_tab(Tab& t, hipStream_t s, std::vector<std::vector<float>>& keep) {
+  up(t.h.col, t.d.col, s);
+  up(t.h.coef, t.d.coef, s);
+  keep.emplace_back(t.h.coef.begin(), t.h.coef.end());
+  up(keep.back(), t.f.coef, s);
+}
+
+void upload_all(st_iga_ctx* c, hipStream_t s) {
+  std::vector<std::vector<float>> keepf;
+  std::vector<std::vector<int>> keepi;
+  std::vector<std::vector<double>> keepd;
+  const int d = c->d;
+  for (int l = 0; l < d; ++l) {
+    for (Tab* t : {&c->Ms[l], &c->Ks[l], &c->BqT[l], &c->Hs[l], &c->Gs[l], &c->Us[l], &c->UsT[l], &c->Bq[l][0],
+                   &c->Bq[l][1], &c->Bq[l][2]})
+      upload_tab(*t, s, keepf);
+  }
+  for (Tab* t : {&c->Mt_x, &c->Wt_x, &c->Bt0, &c->Bt1, &c->BtT, &c->Gt, &c->Ut, &c->UtT, &c->Ew}) upload_tab(*t, s, keepf);
+  up(c->lam_s_h, static_cast<const double*>(c->lam_d), s);
+  keepf.emplace_back(c->lam_s_h.begin(), c->lam_s_h.end());
+  up(keepf.back(), static_cast<const float*>(c->lam_f), s);
+  std::vector<double> mu(c->Nt, 0.0), l(c->Nt, 0.0);
+  std::vector<int> kind(c->Nt, 2);
+  for (int i = 0; i < c->Nt - 1; ++i) { mu[i] = c->fd.mu[i]; l[i] = c->fd.l[i]; kind[i] = c->fd.kind[i]; }
+  keepd.push_back(mu); up(keepd.back(), static_cast<const double*>(c->mu_d), s);
+  keepd.push_back(l); up(keepd.back(), static_cast<const double*>(c->l_d), s);
+  keepf.emplace_back(mu.begin(), mu.end()); up(keepf.back(), static_cast<const float*>(c->mu_f), s);
+  keepf.emplace_back(l.begin(), l.end()); up(keepf.back(), static_cast<const float*>(c->l_f), s);
+  keepi.push_back(kind); up(keepi.back(), static_cast<const int*>(c->kind_d), s);
+  // element ranges (Gauss points of each element) and support-extension windows
+  const Dir1D& T = c->dir[d];
+  {
+    std::vector<int> st(c->nelt), ct(c->nelt, T.nq);
+    for (int e = 0; e < c->nelt; ++e) st[e] = e * T.nq;
+    keepi.push_back(st); up(keepi.back(), static_cast<const int*>(c->el_t_s), s);
+    keepi.push_back(ct); up(keepi.back(), static_cast<const int*>(c->el_t_c), s);
+    std::vector<int> e0, e1;
+    support_windows(T, 1, e0, e1);
+    std::vector<int> cnt(e0.size());
+    for (size_t i = 0; i < e0.size(); ++i) cnt[i] = e1[i] - e0[i];
+    keepi.push_back(e0); up(keepi.back(), static_cast<const int*>(c->win_t_s), s);
+    keepi.push_back(cnt); up(keepi.back(), static_cast<const int*>(c->win_t_c), s);
+  }
+  for (int l2 = 0; l2 < d; ++l2) {
+    const Dir1D& D = c->dir[l2];
+    std::vector<int> st(D.nel), ct(D.nel, D.nq);
+    for (int e = 0; e < D.nel; ++e) st[e] = e * D.nq;
+    keepi.push_back(st); up(keepi.back(), static_cast<const int*>(c->el_s_s[l2]), s);
+    keepi.push_back(ct); up(keepi.back(), static_cast<const int*>(c->el_s_c[l2]), s);
+    std::vector<int> e0, e1;
+    support_windows(D, 0, e0, e1);
+    std::vector<int> cnt(e0.size());
+    for (size_t i = 0; i < e0.size(); ++i) cnt[i] = e1[i] - e0[i];
+    keepi.push_back(e0); up(keepi.back(), static_cast<const int*>(c->win_s_s[l2]), s);
+    keepi.push_back(cnt); up(keepi.back(), static_cast<const int*>(c->win_s_c[l2]), s);
+  }
+  // tensor spatial weights and time weights
+  std::vector<double> ws(c->Qs, 1.0);
+  for (int64_t q = 0; q < c->Qs; ++q) {
+    int64_t r = q;
+    double w = 1.0;
+    for (int l2 = 0; l2 < d; ++l2) {
+      w *= c->dir[l2].wq[r % c->Q[l2]];
+      r /= c->Q[l2];
+    }
+    ws[q] = w;
+  }
+  keepd.push_back(ws); up(keepd.back(), static_cast<const double*>(c->wq_s), s);
+  up(T.wq, static_cast<const double*>(c->wq_t), s);
+  CK(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------------ operators
+template <class S, class C>
+struct Ops {
+  // per-precision accessors
+  static const DTable<C>& tab(const Tab& t);
+};
+template <>
+const DTable<double>& Ops<double, double>::tab(const Tab& t) { return t.d; }
+template <>
+const DTable<float>& Ops<float, float>::tab(const Tab& t) { return t.f; }
+template <>
+const DTable<float>& Ops<bf16, float>::tab(const Tab& t) { return t.f; }
+
+template <class S>
+struct Bufs {
+  S* t4[4];
+  S* big[2];
+  const S* Psi;
+};
+
+// Apply the tensor chain along spatial axes: x has layout [L][m_d]..[m_1] with
+// m_l = in dims; apply tabs[l] along axis l (output dims out[l]); ping-pong
+// between bufA/bufB; the last step writes to `dst` with (alpha, beta).
+template <class S, class C>
+const S* spatial_chain(st_iga_ctx* c, const Tab* const* tabs, const S* x, int64_t L, const int* in_dims,
+                       const int* out_dims, S* bufA, S* bufB, S* dst, C alpha, C beta, hipStream_t s) {
+  const int d = c->d;
+  int dims[3];
+  for (int l = 0; l < d; ++l) dims[l] = in_dims[l];
+  const S* cur = x;
+  S* bufs[2] = {bufA, bufB};
+  int pb = 0;
+  for (int l = 0; l < d; ++l) {
+    int64_t inner = 1, outer = L;
+    for (int k = 0; k < l; ++k) inner *= dims[k];
+    for (int k = l + 1; k < d; ++k) outer *= dims[k];
+    const bool last = (l == d - 1);
+    S* out = last ? dst : bufs[pb];
+    gather<S, S, C>(Ops<S, C>::tab(*tabs[l]), cur, out, outer, inner, dims[l], 0, last ? alpha : C(1), last ? beta : C(0), s);
+    dims[l] = out_dims[l];
+    cur = out;
+    pb ^= 1;
+  }
+  return cur;
+}
+
+// y (N_t layers) = A_lin x (+ reaction terms when with_react), x with L layers
+// (L = N_t, in_base 1: unknowns; L = n_t, in_base 0: full vectors).
+template <class S, class C>
+void apply_impl(st_iga_ctx* c, const S* x, S* y, int L, int in_base, bool with_su, bool with_react, Bufs<S>& B,
+                hipStream_t s) {
+  const int d = c->d;
+  const st_iga_problem& P = c->P;
+  const int64_t Ns = c->Ns;
+  S *a = B.t4[0], *b = B.t4[1], *e = B.t4[2], *f = B.t4[3];
+  const int nn[3] = {c->n[0], c->n[1], c->n[2]};
+  // spatial constant part: SM = (M_d..M_1) x, SK = K_s x
+  S* SM;
+  S* SK;
+  if (d == 1) {
+    gather<S, S, C>(Ops<S, C>::tab(c->Ms[0]), x, a, L, 1, nn[0], 0, C(1), C(0), s);
+    gather<S, S, C>(Ops<S, C>::tab(c->Ks[0]), x, b, L, 1, nn[0], 0, C(P.sigma[0]), C(0), s);
+    SM = a;
+    SK = b;
+  } else if (d == 2) {
+    gather<S, S, C>(Ops<S, C>::tab(c->Ms[0]), x, a, L * nn[1], 1, nn[0], 0, C(1), C(0), s);
+    gather<S, S, C>(Ops<S, C>::tab(c->Ks[0]), x, b, L * nn[1], 1, nn[0], 0, C(1), C(0), s);
+    gather<S, S, C>(Ops<S, C>::tab(c->Ms[1]), a, e, L, nn[0], nn[1], 0, C(1), C(0), s);
+    gather<S, S, C>(Ops<S, C>::tab(c->Ks[1]), a, f, L, nn[0], nn[1], 0, C(P.sigma[1]), C(0), s);
+    gather<S, S, C>(Ops<S, C>::tab(c->Ms[1]), b, f, L, nn[0], nn[1], 0, C(P.sigma[0]), C(1), s);
+    SM = e;
+    SK = f;
+  } else {
+    gather<S, S, C>(Ops<S, C>::tab(c->Ms[0]), x, a, L * nn[1] * nn[2], 1, nn[0], 0, C(1), C(0), s);
+    gather<S, S, C>(Ops<S, C>::tab(c->Ks[0]), x, b, L * nn[1] * nn[2], 1, nn[0], 0, C(1), C(0), s);
+    gather<S, S, C>(Ops<S, C>::tab(c->Ms[1]), a, e, L * nn[2], nn[0], nn[1], 0, C(1), C(0), s);           // aa
+    gather<S, S, C>(Ops<S, C>::tab(c->Ks[1]), a, f, L * nn[2], nn[0], nn[1], 0, C(P.sigma[1]), C(0), s);  // c
+    gather<S, S, C>(Ops<S, C>::tab(c->Ms[1]), b, f, L * nn[2], nn[0], nn[1], 0, C(P.sigma[0]), C(1), s);
+    const int64_t in2 = static_cast<int64_t>(nn[0]) * nn[1];
+    gather<S, S, C>(Ops<S, C>::tab(c->Ms[2]), e, a, L, in2, nn[2], 0, C(1), C(0), s);                     // SM
+    gather<S, S, C>(Ops<S, C>::tab(c->Ks[2]), e, b, L, in2, nn[2], 0, C(P.sigma[2]), C(0), s);            // SK
+    gather<S, S, C>(Ops<S, C>::tab(c->Ms[2]), f, b, L, in2, nn[2], 0, C(1), C(1), s);
+    SM = a;
+    SK = b;
+  }
+  // time: y = Cm W_t SM + M_t SK (rows X_t, columns per in_base)
+  gather<S, S, C>(Ops<S, C>::tab(c->Wt_x), SM, y, 1, Ns, L, in_base, C(P.Cm), C(0), s);
+  gather<S, S, C>(Ops<S, C>::tab(c->Mt_x), SK, y, 1, Ns, L, in_base, C(1), C(1), s);
+  // low-rank coefficient terms
+  const int r0 = with_su ? 0 : c->Rth;
+  const int r1 = with_react ? c->Rth + c->Rc : c->Rth;
+  if (r1 <= r0) return;
+  const Tab* ex[3] = {&c->Bq[0][0], &c->Bq[1][0], &c->Bq[2][0]};
+  const Tab* pr[3] = {&c->BqT[0], &c->BqT[1], &c->BqT[2]};
+  const int qd[3] = {c->Q[0], c->Q[1], c->Q[2]};
+  S* Z = B.big[0];
+  S* W2 = B.big[1];
+  // expansion x -> Z [L][Q_s] (scratch: W2 and Z alternate)
+  S* bufA = (d == 3) ? Z : W2;   // intermediates never alias the step that reads them
+  S* bufB = W2;
+  if (d == 1) {
+    gather<S, S, C>(Ops<S, C>::tab(*ex[0]), x, Z, L, 1, nn[0], 0, C(1), C(0), s);
+  } else {
+    spatial_chain<S, C>(c, ex, x, L, nn, qd, bufA, bufB, Z, C(1), C(0), s);
+  }
+  const C* Tr = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->Tr) : reinterpret_cast<const C*>(c->Tr_f);
+  time_mix<S, C>(Tr, B.Psi, r0, r1, c->Nt, P.p_t, Z, L, in_base + 0, W2, c->Qs, s);
+  // project W2 [N_t][Q_s] -> y += ...
+  if (d == 1) {
+    gather<S, S, C>(Ops<S, C>::tab(*pr[0]), W2, y, c->Nt, 1, qd[0], 0, C(1), C(1), s);
+  } else {
+    spatial_chain<S, C>(c, pr, W2, c->Nt, qd, nn, Z, (d == 3 ? W2 : Z), y, C(1), C(1), s);
+  }
+}
+
+// The time-mix kernel indexes inputs by full time index minus in_base; for
+// unknown vectors (layer k = full index k+1) in_base = 1, for full vectors 0.
+
+template <class S, class C>
+void precond_impl(st_iga_ctx* c, const S* r, S* z, Bufs<S>& B, hipStream_t s) {
+  const int d = c->d;
+  const int64_t Ns = c->Ns;
+  const int Nt = c->Nt;
+  const Tab* UT[3] = {&c->UsT[0], &c->UsT[1], &c->UsT[2]};
+  const Tab* U[3] = {&c->Us[0], &c->Us[1], &c->Us[2]};
+  const int nn[3] = {c->n[0], c->n[1], c->n[2]};
+  S *a = B.t4[0], *b = B.t4[1], *e = B.t4[2];
+  // spatial forward transforms: a = (U_d^T .. U_1^T) r
+  if (d == 1) gather<S, S, C>(Ops<S, C>::tab(*UT[0]), r, a, Nt, 1, nn[0], 0, C(1), C(0), s);
+  else spatial_chain<S, C>(c, UT, r, Nt, nn, nn, b, e, a, C(1), C(0), s);
+  // time forward: b = U_t^T a
+  gather<S, S, C>(Ops<S, C>::tab(c->UtT), a, b, 1, Ns, Nt, 0, C(1), C(0), s);
+  // arrowhead core
+  const C* lam = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->lam_d) : reinterpret_cast<const C*>(c->lam_f);
+  const C* mu = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->mu_d) : reinterpret_cast<const C*>(c->mu_f);
+  const C* l = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->l_d) : reinterpret_cast<const C*>(c->l_f);
+  arrowhead<S, C>(b, a, lam, mu, c->kind_d, l, C(c->fd.sigma), C(c->P.Cm), Nt, Ns, s);
+  // time backward: b = U_t a
+  gather<S, S, C>(Ops<S, C>::tab(c->Ut), a, b, 1, Ns, Nt, 0, C(1), C(0), s);
+  // spatial backward: z = (U_d .. U_1) b
+  if (d == 1) gather<S, S, C>(Ops<S, C>::tab(*U[0]), b, z, Nt, 1, nn[0], 0, C(1), C(0), s);
+  else spatial_chain<S, C>(c, U, b, Nt, nn, nn, a, e, z, C(1), C(0), s);
+}
+
+Bufs<double> bufs64(st_iga_ctx* c) {
+  Bufs<double> B;
+  for (int k = 0; k < 4; ++k) B.t4[k] = c->t4[k];
+  B.big[0] = c->big[0];
+  B.big[1] = c->big[1];
+  B.Psi = c->Psi;
+  return B;
+}
+
+// ------------------------------------------------------------------ reductions
+double dev_norm(st_iga_ctx* c, const double* x, int64_t n, hipStream_t s) {
+  const int nb = reduce_blocks(n);
+  sumsq_partial(x, n, c->part, nb, s);
+  finalize_sum(c->part, nb, 1, c->dsc + 900, s);
+  double h;
+  CK(hipMemcpyAsync(&h, c->dsc + 900, sizeof(double), hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  return std::sqrt(h);
+}
+
+double dev_absmax(st_iga_ctx* c, const double* x, int64_t n, hipStream_t s) {
+  const int nb = reduce_blocks(n);
+  absmax_partial(x, n, c->part, nb, s);
+  finalize_max(c->part, nb, c->dsc + 901, s);
+  double h;
+  CK(hipMemcpyAsync(&h, c->dsc + 901, sizeof(double), hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  return h;
+}
+
+using Op = std::function<void(const double*, double*)>;
+
+// Right-preconditioned FGMRES(m) on A x = b from x = 0 (FP64 Arnoldi, CGS with
+// one re-orthogonalization pass, Givens rotations on the host).  Returns the
+// number of iterations; *est = last residual estimate / ||b||.
+int fgmres(st_iga_ctx* c, const Op& A, const Op& Pc, const double* b, double* x, double rtol, int maxit, double bnorm,
+           double* est, hipStream_t s) {
+  const int64_t n = c->nunk;
+  const int m = c->opt.restart;
+  const int nb = reduce_blocks(n);
+  fill(x, 0.0, n, s);
+  int it = 0;
+  double rn = bnorm;
+  // r = b
+  CK(hipMemcpyAsync(c->rk, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  double hbuf[2 * 66 + 2];
+  while (it < maxit) {
+    // V_0 = r / ||r||
+    axpby(1.0 / rn, c->rk, 0.0, c->Vk, n, s);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = rn;
+    int j = 0;
+    bool done = false;
+    for (; j < m && it < maxit; ++j) {
+      double* Vj = c->Vk + static_cast<int64_t>(j) * n;
+      double* Zj = c->Zk + static_cast<int64_t>(j) * n;
+      double* w = c->Vk + static_cast<int64_t>(j + 1) * n;
+      Pc(Vj, Zj);
+      A(Zj, w);
+      // classical Gram-Schmidt, twice
+      multidot_partial(c->Vk, n, j + 1, w, n, c->part, nb, s);
+      finalize_sum(c->part, nb, j + 1, c->dsc, s);
+      update_norm_partial(c->Vk, n, j + 1, c->dsc, w, n, c->part, nb, s);
+      multidot_partial(c->Vk, n, j + 1, w, n, c->part, nb, s);
+      finalize_sum(c->part, nb, j + 1, c->dsc + 128, s);
+      update_norm_partial(c->Vk, n, j + 1, c->dsc + 128, w, n, c->part, nb, s);
+      finalize_sum(c->part, nb, 1, c->dsc + 256, s);
+      CK(hipMemcpyAsync(hbuf, c->dsc, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      CK(hipMemcpyAsync(hbuf + 66, c->dsc + 128, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      CK(hipMemcpyAsync(hbuf + 132, c->dsc + 256, sizeof(double), hipMemcpyDeviceToHost, s));
+      CK(hipStreamSynchronize(s));
+      check_launch();
+      ++it;
+      double* h = &H[static_cast<size_t>(j)];   // column j: H[i*m + j]
+      for (int i = 0; i <= j; ++i) H[static_cast<size_t>(i) * m + j] = hbuf[i] + hbuf[66 + i];
+      const double hn = std::sqrt(std::max(hbuf[132], 0.0));
+      (void)h;
+      if (!std::isfinite(hn)) throw Fail{ST_IGA_ENOCONV, "non-finite Arnoldi norm"};
+      scale_by_dev(w, n, c->dsc + 256, s);
+      // apply previous rotations
+      for (int i = 0; i < j; ++i) {
+        const double t1 = H[static_cast<size_t>(i) * m + j], t2 = H[static_cast<size_t>(i + 1) * m + j];
+        H[static_cast<size_t>(i) * m + j] = cs[i] * t1 + sn[i] * t2;
+        H[static_cast<size_t>(i + 1) * m + j] = -sn[i] * t1 + cs[i] * t2;
+      }
+      const double hjj = H[static_cast<size_t>(j) * m + j];
+      const double den = std::hypot(hjj, hn);
+      cs[j] = den == 0.0 ? 1.0 : hjj / den;
+      sn[j] = den == 0.0 ? 0.0 : hn / den;
+      H[static_cast<size_t>(j) * m + j] = den;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      if (std::fabs(g[j + 1]) <= rtol * bnorm || hn == 0.0) {
+        ++j;
+        done = true;
+        break;
+      }
+    }
+    // solve H y = g (upper triangular j x j)
+    for (int i = j - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int k = i + 1; k < j; ++k) t -= H[static_cast<size_t>(i) * m + k] * y[k];
+      y[i] = t / H[static_cast<size_t>(i) * m + i];
+    }
+    CK(hipMemcpyAsync(c->dsc + 512, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
+    combine(c->Zk, n, j, c->dsc + 512, x, n, s);
+    // true residual r = b - A x
+    A(x, c->rk);
+    axpby(1.0, b, -1.0, c->rk, n, s);
+    rn = dev_norm(c, c->rk, n, s);
+    *est = rn / bnorm;
+    if (rn <= rtol * bnorm) break;
+    (void)done;
+    if (!std::isfinite(rn)) throw Fail{ST_IGA_ENOCONV, "non-finite residual"};
+  }
+  return it;
+}
+
+void ensure_lin(st_iga_ctx* c) {
+  if (!c->linearized) throw Fail{ST_IGA_ESTATE, "no linearization set (call st_iga_linearize or st_iga_set_factors)"};
+}
+
+void apply64(st_iga_ctx* c, const double* x, double* y, hipStream_t s) {
+  Bufs<double> B = bufs64(c);
+  apply_impl<double, double>(c, x, y, c->Nt, 1, true, true, B, s);
+}
+void precond64(st_iga_ctx* c, const double* r, double* z, hipStream_t s) {
+  Bufs<double> B = bufs64(c);
+  precond_impl<double, double>(c, r, z, B, s);
+}
+
+template <class S>
+void lowp_ops(st_iga_ctx* c, Op& A, Op& Pc, hipStream_t s);
+
+template <>
+void lowp_ops<float>(st_iga_ctx* c, Op& A, Op& Pc, hipStream_t s) {
+  A = [c, s](const double* x, double* y) {
+    Bufs<float> B;
+    for (int k = 0; k < 4; ++k) B.t4[k] = c->t4f[k];
+    B.big[0] = c->bigf[0];
+    B.big[1] = c->bigf[1];
+    B.Psi = c->Psi_f;
+    convert<double, float>(x, c->xf, c->nunk, s);
+    apply_impl<float, float>(c, c->xf, c->yf, c->Nt, 1, true, true, B, s);
+    convert<float, double>(c->yf, y, c->nunk, s);
+  };
+  Pc = [c, s](const double* r, double* z) {
+    Bufs<float> B;
+    for (int k = 0; k < 4; ++k) B.t4[k] = c->t4f[k];
+    B.big[0] = c->bigf[0];
+    B.big[1] = c->bigf[1];
+    B.Psi = c->Psi_f;
+    convert<double, float>(r, c->xf, c->nunk, s);
+    precond_impl<float, float>(c, c->xf, c->yf, B, s);
+    convert<float, double>(c->yf, z, c->nunk, s);
+  };
+}
+template <>
+void lowp_ops<bf16>(st_iga_ctx* c, Op& A, Op& Pc, hipStream_t s) {
+  A = [c, s](const double* x, double* y) {
+    Bufs<bf16> B;
+    for (int k = 0; k < 4; ++k) B.t4[k] = c->t4b[k];
+    B.big[0] = c->bigb[0];
+    B.big[1] = c->bigb[1];
+    B.Psi = c->Psi_b;
+    convert<double, bf16>(x, c->xb, c->nunk, s);
+    apply_impl<bf16, float>(c, c->xb, c->yb, c->Nt, 1, true, true, B, s);
+    convert<bf16, double>(c->yb, y, c->nunk, s);
+  };
+  Pc = [c, s](const double* r, double* z) {
+    Bufs<bf16> B;
+    for (int k = 0; k < 4; ++k) B.t4[k] = c->t4b[k];
+    B.big[0] = c->bigb[0];
+    B.big[1] = c->bigb[1];
+    B.Psi = c->Psi_b;
+    convert<double, bf16>(r, c->xb, c->nunk, s);
+    precond_impl<bf16, float>(c, c->xb, c->yb, B, s);
+    convert<bf16, double>(c->yb, z, c->nunk, s);
+  };
+}
+
+// Linear solve with the configured precision.  Returns iterations.
+int krylov(st_iga_ctx* c, const double* b, double* x, double tol, double* relres, hipStream_t s) {
+  ensure_lin(c);
+  const int64_t n = c->nunk;
+  const double bnorm = dev_norm(c, b, n, s);
+  if (bnorm == 0.0) {
+    fill(x, 0.0, n, s);
+    *relres = 0.0;
+    return 0;
+  }
+  Op A64 = [c, s](const double* xx, double* yy) { apply64(c, xx, yy, s); };
+  Op P64 = [c, s](const double* rr, double* zz) { precond64(c, rr, zz, s); };
+  double est = 1.0;
+  if (c->opt.prec == ST_IGA_FP64) {
+    const int it = fgmres(c, A64, P64, b, x, tol, c->opt.max_krylov, bnorm, &est, s);
+    *relres = est;
+    if (est > tol) throw Fail{ST_IGA_ENOCONV, "FGMRES reached max_krylov"};
+    return it;
+  }
+  Op Al, Pl;
+  if (c->opt.prec == ST_IGA_MIXED_FP32) lowp_ops<float>(c, Al, Pl, s);
+  else lowp_ops<bf16>(c, Al, Pl, s);
+  // iterative refinement on the FP64 true residual
+  fill(x, 0.0, n, s);
+  CK(hipMemcpyAsync(c->bk, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));   // bk = current residual
+  double rn = bnorm;
+  int total = 0, refinements = 0;
+  while (rn > tol * bnorm) {
+    if (total >= c->opt.max_krylov || refinements >= 60) throw Fail{ST_IGA_ENOCONV, "refinement did not converge"};
+    const double itol = std::max(c->opt.inner_tol, 0.5 * tol * bnorm / rn);
+    double e2 = 1.0;
+    total += fgmres(c, Al, Pl, c->bk, c->dk, itol, c->opt.max_krylov - total, rn, &e2, s);
+    axpy(1.0, c->dk, x, n, s);
+    A64(x, c->wk);
+    axpby(1.0, b, -1.0, c->wk, n, s);
+    CK(hipMemcpyAsync(c->bk, c->wk, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    rn = dev_norm(c, c->bk, n, s);
+    ++refinements;
+    if (!std::isfinite(rn)) throw Fail{ST_IGA_ENOCONV, "non-finite residual"};
+  }
+  *relres = rn / bnorm;
+  return total;
+}
+
+// ------------------------------------------------------------------ linearization
+// Spatial expansion of an array [L][n_d..n_1] with per-axis tables into dst [L][Q_d..Q_1].
+void expand_space(st_iga_ctx* c, const Tab* const* tabs, const double* x, int64_t L, double* tA, double* tB, double* dst,
+                  double alpha, double beta, hipStream_t s) {
+  const int nn[3] = {c->n[0], c->n[1], c->n[2]};
+  const int qd[3] = {c->Q[0], c->Q[1], c->Q[2]};
+  if (c->d == 1) {
+    gather<double, double, double>(tabs[0]->d, x, dst, L, 1, nn[0], 0, alpha, beta, s);
+    return;
+  }
+  spatial_chain<double, double>(c, tabs, x, L, nn, qd, tA, tB, dst, alpha, beta, s);
+}
+void project_space(st_iga_ctx* c, const double* g, int64_t L, double* tA, double* tB, double* dst, double beta,
+                   hipStream_t s) {
+  const int nn[3] = {c->n[0], c->n[1], c->n[2]};
+  const int qd[3] = {c->Q[0], c->Q[1], c->Q[2]};
+  const Tab* pr[3] = {&c->BqT[0], &c->BqT[1], &c->BqT[2]};
+  if (c->d == 1) {
+    gather<double, double, double>(pr[0]->d, g, dst, L, 1, qd[0], 0, 1.0, beta, s);
+    return;
+  }
+  spatial_chain<double, double>(c, pr, g, L, qd, nn, tA, tB, dst, 1.0, beta, s);
+}
+
+// One pass over all space-time Gauss points (time-chunked): ionic part of the
+// residual into rfull (full rows) and/or the element maxima of |R| into E; the
+// maxima of |u| and |u_t| into dsc[300], dsc[301].
+void quad_pass(st_iga_ctx* c, const double* u, const double* w, bool want_res, bool want_theta, hipStream_t s) {
+  const int d = c->d;
+  const st_iga_problem& P = c->P;
+  const int64_t Ns = c->Ns, Qs = c->Qs;
+  const int nq = c->nqt;
+  double* pool = c->big[0];    // both big buffers are contiguous-enough scratch: carve sequentially
+  const int64_t cq = static_cast<int64_t>(c->chunk_el) * nq;
+  double* U0 = pool;
+  double* Ut = U0 + cq * Ns;
+  double* W0 = Ut + cq * Ns;
+  double* uq = c->big[1];
+  double* utq = uq + cq * Qs;
+  double* wq = utq + cq * Qs;
+  double* lap = wq + cq * Qs;
+  double* g = W0 + cq * Ns;          // in big[0] after W0
+  double* absR = g + cq * Qs;
+  double* tA = absR + cq * Qs;
+  double* tB = lap + cq * Qs;        // in big[1]
+  // capacity check (both regions hold nt*Qs doubles)
+  const int64_t capb = c->big_len;
+  if (3 * cq * Ns + 3 * cq * Qs > capb || 5 * cq * Qs > capb) throw Fail{ST_IGA_EDEVICE, "quadrature chunk does not fit"};
+  if (want_res) fill(c->rfull, 0.0, c->nfull, s);
+  const Tab* B0[3] = {&c->Bq[0][0], &c->Bq[1][0], &c->Bq[2][0]};
+  int boff = 0;
+  double* part_u = c->part;
+  double* part_t = c->part + c->nb_part;
+  const int nel_s[3] = {c->nel[0], c->nel[1], c->nel[2]};
+  for (int e0 = 0; e0 < c->nelt; e0 += c->chunk_el) {
+    const int ne = std::min(c->chunk_el, c->nelt - e0);
+    const int q0 = e0 * nq, nqc = ne * nq;
+    gather_rows<double, double, double>(c->Bt0.d, q0, nqc, u, U0, 1, Ns, c->nt, 0, 1.0, 0.0, s);
+    gather_rows<double, double, double>(c->Bt1.d, q0, nqc, u, Ut, 1, Ns, c->nt, 0, 1.0, 0.0, s);
+    gather_rows<double, double, double>(c->Bt0.d, q0, nqc, w, W0, 1, Ns, c->nt, 0, 1.0, 0.0, s);
+    expand_space(c, B0, U0, nqc, tA, tB, uq, 1.0, 0.0, s);
+    expand_space(c, B0, Ut, nqc, tA, tB, utq, 1.0, 0.0, s);
+    expand_space(c, B0, W0, nqc, tA, tB, wq, 1.0, 0.0, s);
+    for (int l = 0; l < d; ++l) {
+      const Tab* tl[3] = {B0[0], B0[1], B0[2]};
+      tl[l] = &c->Bq[l][2];
+      expand_space(c, tl, U0, nqc, tA, tB, lap, P.sigma[l], l == 0 ? 0.0 : 1.0, s);
+    }
+    const int nbp = static_cast<int>((static_cast<int64_t>(nqc) * Qs + 255) / 256);
+    pointwise_ionic(uq, utq, lap, wq, c->wq_t + q0, c->wq_s, Qs, nqc, P.Cm, P.a, P.c1, P.c2, g, absR,
+                    part_u + boff, nbp, s);
+    // the kernel writes [2b], [2b+1] pairs: keep them interleaved in part_u region
+    boff += 2 * nbp;
+    if (want_theta) {
+      // element maxima: time axis (within chunk), then spatial axes
+      double* cur = absR;
+      int dims[4];
+      dims[0] = nqc;
+      for (int l = 0; l < d; ++l) dims[1 + l] = c->Q[l];
+      // time axis: [nqc][Qs] -> [ne][Qs]
+      mode_max(c->el_t_s, c->el_t_c, ne, cur, tA, 1, Qs, nqc, s);
+      cur = tA;
+      dims[0] = ne;
+      double* nxt = tB;
+      for (int l = 0; l < d; ++l) {
+        int64_t inner = 1, outer = ne;
+        for (int k = 0; k < l; ++k) inner *= nel_s[k];
+        for (int k = l + 1; k < d; ++k) outer *= c->Q[k];
+        double* out = (l == d - 1) ? c->E + static_cast<int64_t>(e0) * c->Nels : nxt;
+        mode_max(c->el_s_s[l], c->el_s_c[l], nel_s[l], cur, out, outer, inner, c->Q[l], s);
+        nxt = cur;
+        cur = out;
+      }
+    }
+    if (want_res) {
+      // project g over space into U0 region (reuse), then over time into rfull
+      project_space(c, g, nqc, tA, tB, U0, 0.0, s);
+      DTable<double> tt = c->BtT.d;
+      gather<double, double, double>(tt, U0, c->rfull, 1, Ns, nqc, q0, 1.0, 1.0, s);
+    }
+  }
+  (void)part_t;
+  // maxima of |u| and |u_t|: interleaved partials
+  const int nbt = boff / 2;
+  // reuse finalize_max on strided data: copy via a small kernel is avoided by two passes
+  // (the partial array is [2b] = |u| max, [2b+1] = |u_t| max)
+  std::vector<double> hp(boff);
+  CK(hipMemcpyAsync(hp.data(), part_u, boff * sizeof(double), hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  check_launch();
+  double mu = 0.0, mt = 0.0;
+  for (int b = 0; b < nbt; ++b) {
+    mu = std::max(mu, hp[2 * b]);
+    mt = std::max(mt, hp[2 * b + 1]);
+  }
+  double mm[2] = {mu, mt};
+  CK(hipMemcpyAsync(c->dsc + 300, mm, 2 * sizeof(double), hipMemcpyHostToDevice, s));
+  CK(hipStreamSynchronize(s));
+}
+
+// Theta grid (N_t x N_s) of eq. (3.4) into dst.
+void theta_grid(st_iga_ctx* c, const double* u, const double* w, double* dst, hipStream_t s) {
+  const int d = c->d;
+  quad_pass(c, u, w, false, true, s);
+  // window maxima: time then spatial axes; E is [nelt][nel_d..nel_1]
+  double* tA = c->big[0];
+  double* tB = c->big[1];
+  mode_max(c->win_t_s, c->win_t_c, c->Nt, c->E, tA, 1, c->Nels, c->nelt, s);
+  int dims[3] = {c->nel[0], c->nel[1], c->nel[2]};
+  double* cur = tA;
+  for (int l = 0; l < d; ++l) {
+    int64_t inner = 1, outer = c->Nt;
+    for (int k = 0; k < l; ++k) inner *= c->n[k];
+    for (int k = l + 1; k < d; ++k) outer *= dims[k];
+    double* out = (l == d - 1) ? dst : (cur == tA ? tB : tA);
+    mode_max(c->win_s_s[l], c->win_s_c[l], c->n[l], cur, out, outer, inner, dims[l], s);
+    dims[l] = c->n[l];
+    cur = out;
+  }
+  theta_finish(dst, c->nunk, c->dsc + 300, c->P.Cm, 1.0 / c->P.T, s);
+  check_launch();
+}
+
+// Values at the (X_t time) x (space) Greville grid of a full vector.
+void greville_values(st_iga_ctx* c, const double* x, double* dst, hipStream_t s) {
+  const int d = c->d;
+  const int64_t Ns = c->Ns;
+  double* tA = c->t4[2];
+  double* tB = c->t4[3];
+  // time first: [n_t][Ns] -> [N_t][Ns]
+  gather<double, double, double>(c->Gt.d, x, tA, 1, Ns, c->nt, 0, 1.0, 0.0, s);
+  const Tab* G[3] = {&c->Gs[0], &c->Gs[1], &c->Gs[2]};
+  const int nn[3] = {c->n[0], c->n[1], c->n[2]};
+  if (d == 1) {
+    gather<double, double, double>(G[0]->d, tA, dst, c->Nt, 1, nn[0], 0, 1.0, 0.0, s);
+    return;
+  }
+  spatial_chain<double, double>(c, G, tA, c->Nt, nn, nn, tB, tA, dst, 1.0, 0.0, s);
+}
+
+// Truncated SVD of an N_t x N_s device matrix through its Gram matrix.
+// Returns R; U (N_t x R, host), s (host), V (device N_s x R, into Vdst).
+int lowrank(st_iga_ctx* c, const double* C, double eps, std::vector<double>& U, std::vector<double>& sv, double* Vdst,
+            hipStream_t s) {
+  const int m = c->Nt;
+  const int64_t n = c->Ns;
+  gram_partial(C, m, n, c->gram, c->gram_nb, s);
+  finalize_sum(c->gram, c->gram_nb, m * m, c->big[0], s);
+  std::vector<double> G(static_cast<size_t>(m) * m);
+  CK(hipMemcpyAsync(G.data(), c->big[0], G.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  check_launch();
+  std::vector<double> Q, lam;
+  std::vector<double> I(static_cast<size_t>(m) * m, 0.0);
+  for (int i = 0; i < m; ++i) I[static_cast<size_t>(i) * m + i] = 1.0;
+  std::string err;
+  if (!gen_eig_sym(G, I, m, Q, lam, err)) throw Fail{ST_IGA_EDEVICE, "Gram eigendecomposition: " + err};
+  // descending order
+  double tot = 0.0;
+  for (double& v : lam) { v = std::max(v, 0.0); tot += v; }
+  if (tot == 0.0) { U.clear(); sv.clear(); return 0; }
+  std::vector<int> idx(m);
+  for (int i = 0; i < m; ++i) idx[i] = m - 1 - i;
+  int R = m;
+  double tail = 0.0;
+  // smallest R with sum_{k >= R} lam_k <= eps^2 tot
+  for (int r = m; r >= 0; --r) {
+    if (r < m) tail += lam[idx[r]];
+    if (tail <= eps * eps * tot) R = r;
+    else break;
+  }
+  if (R > c->maxR) throw Fail{ST_IGA_EINVAL, "low rank exceeds max_rank"};
+  U.assign(static_cast<size_t>(m) * R, 0.0);
+  sv.assign(R, 0.0);
+  std::vector<double> inv(R);
+  for (int r = 0; r < R; ++r) {
+    sv[r] = std::sqrt(lam[idx[r]]);
+    inv[r] = 1.0 / sv[r];
+    for (int i = 0; i < m; ++i) U[static_cast<size_t>(i) * R + r] = Q[static_cast<size_t>(i) * m + idx[r]];
+  }
+  if (R > 0) {
+    CK(hipMemcpyAsync(c->tmpR, U.data(), U.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(c->tmpR + static_cast<int64_t>(m) * c->maxR, inv.data(), R * sizeof(double), hipMemcpyHostToDevice, s));
+    right_factor(C, m, n, c->tmpR, c->tmpR + static_cast<int64_t>(m) * c->maxR, R, Vdst, s);
+    CK(hipStreamSynchronize(s));
+    check_launch();
+  }
+  return R;
+}
+
+// Rebuild Psi (spatial factors at Gauss points times weights) and the time
+// tables T_r for both factor sets: theta in [0, Rth), reaction in [Rth, Rth+Rc).
+void rebuild_coefficients(st_iga_ctx* c, hipStream_t s) {
+  const int d = c->d;
+  const st_iga_problem& P = c->P;
+  const Dir1D& T = c->dir[d];
+  const int Nt = c->Nt, pt = P.p_t, WB = 2 * pt + 1;
+  const int Rt = c->Rth + c->Rc;
+  // spatial factors
+  const Tab* Hs[3] = {&c->Hs[0], &c->Hs[1], &c->Hs[2]};
+  const int nn[3] = {c->n[0], c->n[1], c->n[2]};
+  const int qd[3] = {c->Q[0], c->Q[1], c->Q[2]};
+  for (int set = 0; set < 2; ++set) {
+    const int R = set == 0 ? c->Rth : c->Rc;
+    if (R == 0) continue;
+    const double* V = set == 0 ? c->Vth : c->Vc;
+    double* dst = c->Psi + static_cast<int64_t>(set == 0 ? 0 : c->Rth) * c->Qs;
+    transpose_nr(V, c->Ns, R, c->VT, s);
+    for (int r = 0; r < R; ++r) {
+      const double* src = c->VT + static_cast<int64_t>(r) * c->Ns;
+      double* out = dst + static_cast<int64_t>(r) * c->Qs;
+      if (d == 1) gather<double, double, double>(Hs[0]->d, src, out, 1, 1, nn[0], 0, 1.0, 0.0, s);
+      else spatial_chain<double, double>(c, Hs, src, 1, nn, qd, c->big[1], c->big[1] + c->Qs, out, 1.0, 0.0, s);
+    }
+  }
+  scale_rows(c->Psi, Rt, c->Qs, c->wq_s, s);
+  if (c->Psi_f) convert<double, float>(c->Psi, c->Psi_f, static_cast<int64_t>(Rt) * c->Qs, s);
+  if (c->Psi_b) convert<double, bf16>(c->Psi, c->Psi_b, static_cast<int64_t>(Rt) * c->Qs, s);
+  // time tables
+  std::vector<double> nodes(T.grev.begin() + 1, T.grev.end());
+  std::vector<int> left;
+  std::vector<double> wl;
+  hat_weights(nodes, T.xq, left, wl);
+  std::vector<double> Tr(static_cast<size_t>(std::max(Rt, 1)) * Nt * WB, 0.0);
+  for (int set = 0; set < 2; ++set) {
+    const int R = set == 0 ? c->Rth : c->Rc;
+    const std::vector<double>& U = set == 0 ? c->Uth_h : c->Uc_h;
+    const std::vector<double>& sv = set == 0 ? c->sth_h : c->sc_h;
+    const int roff = set == 0 ? 0 : c->Rth;
+    for (int r = 0; r < R; ++r) {
+      double* Trr = &Tr[static_cast<size_t>(roff + r) * Nt * WB];
+      for (int q = 0; q < T.Q; ++q) {
+        const int g0 = left[q];
+        const int g1 = std::min(g0 + 1, Nt - 1);
+        const double phi = wl[q] * U[static_cast<size_t>(g0) * R + r] + (1.0 - wl[q]) * U[static_cast<size_t>(g1) * R + r];
+        const int f = T.first[q];
+        for (int a = 0; a <= pt; ++a) {
+          const int i = f + a;             // full row index
+          if (i < 1) continue;             // rows of X_t only
+          for (int bb = 0; bb <= pt; ++bb) {
+            const int j = f + bb;          // full column
+            const int w = j - i + pt;      // = j - (i - pt); row t = i - 1 has window start (t+1) - pt
+            double val;
+            if (set == 0) {
+              val = 0.0;
+              for (int k = 1; k <= pt; ++k)
+                val += c->tauq[static_cast<size_t>(k - 1) * T.Q + q] * T.B[k][static_cast<size_t>(q) * (pt + 1) + a] *
+                       T.B[k][static_cast<size_t>(q) * (pt + 1) + bb];
+              val *= P.Cm;
+            } else {
+              val = T.B[0][static_cast<size_t>(q) * (pt + 1) + a] * T.B[0][static_cast<size_t>(q) * (pt + 1) + bb];
+            }
+            Trr[static_cast<size_t>(i - 1) * WB + w] += sv[r] * T.wq[q] * phi * val;
+          }
+        }
+      }
+    }
+  }
+  std::vector<float> Trf(Tr.begin(), Tr.end());
+  CK(hipMemcpyAsync(c->Tr, Tr.data(), Tr.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  CK(hipMemcpyAsync(c->Tr_f, Trf.data(), Trf.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  CK(hipStreamSynchronize(s));
+  check_launch();
+  c->linearized = true;
+}
+
+void linearize(st_iga_ctx* c, const double* u, const double* w, bool refresh_theta, hipStream_t s) {
+  const bool newton = c->opt.outer == 0;
+  if (c->opt.su && refresh_theta) {
+    theta_grid(c, u, w, c->grid, s);
+    c->Rth = lowrank(c, c->grid, c->opt.eps_theta, c->Uth_h, c->sth_h, c->Vth, s);
+  } else if (!c->opt.su) {
+    c->Rth = 0;
+  }
+  greville_values(c, u, c->grid, s);
+  greville_values(c, w, c->grid2, s);
+  react_grid(c->grid, c->grid2, c->Cg, c->nunk, c->P.a, c->P.c1, c->P.c2, newton ? 1 : 0, s);
+  c->Rc = lowrank(c, c->Cg, c->opt.eps_react, c->Uc_h, c->sc_h, c->Vc, s);
+  rebuild_coefficients(c, s);
+}
+
+void residual(st_iga_ctx* c, const double* u, const double* w, double* r, hipStream_t s) {
+  ensure_lin(c);
+  quad_pass(c, u, w, true, false, s);
+  Bufs<double> B = bufs64(c);
+  apply_impl<double, double>(c, u, r, c->nt, 0, true, false, B, s);
+  axpy(1.0, c->rfull + c->Ns, r, c->nunk, s);
+  check_launch();
+}
+
+void w_update(st_iga_ctx* c, const double* u, double* w, hipStream_t s) {
+  fill(w, 0.0, c->Ns, s);
+  gather<double, double, double>(c->Ew.d, u, w + c->Ns, 1, c->Ns, c->nt, 0, 1.0, 0.0, s);
+  check_launch();
+}
+
+std::vector<double> lift_host(st_iga_ctx* c, const st_iga_stimulus* st, int64_t* count) {
+  std::vector<double> c0(c->Ns, 0.0);
+  int64_t cnt = 0;
+  for (int64_t j = 0; j < c->Ns; ++j) {
+    double x[3] = {0, 0, 0};
+    int64_t r = j;
+    for (int l = 0; l < c->d; ++l) {
+      x[l] = c->dir[l].grev[r % c->n[l]];
+      r /= c->n[l];
+    }
+    bool in = false;
+    if (st->u0_kind == 1) in = x[0] < st->u0_center[0];
+    else if (st->u0_kind == 2) {
+      double r2 = 0.0;
+      for (int l = 0; l < c->d; ++l) r2 += (x[l] - st->u0_center[l]) * (x[l] - st->u0_center[l]);
+      in = r2 <= st->u0_radius * st->u0_radius;
+    }
+    if (in) {
+      c0[j] = st->u0_value;
+      ++cnt;
+    }
+  }
+  if (count) *count = cnt;
+  return c0;
+}
+
+template <class F>
+st_iga_status guard(st_iga_ctx* c, F&& f) {
+  try {
+    f();
+    return ST_IGA_OK;
+  } catch (const Fail& e) {
+    if (c) c->err = e.msg;
+    return e.st;
+  } catch (const std::exception& e) {
+    if (c) c->err = e.what();
+    return ST_IGA_EINVAL;
+  }
+}
+
+thread_local std::string g_last_err;
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+void st_iga_default_options(st_iga_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->su = 1;
+  o->eps_theta = 0.1;
+  o->eps_react = 1e-2;
+  o->max_rank = 48;
+  o->outer = 0;
+  o->alpha = 1.0;
+  o->theta_freeze = 1e-4;
+  o->tol_nonlin = 1e-10;
+  o->tol_lin = 1e-10;
+  o->inner_tol = 1e-4;
+  o->restart = 30;
+  o->max_outer = 60;
+  o->max_krylov = 3000;
+  o->prec = ST_IGA_FP64;
+}
+
+size_t st_iga_workspace_bytes(const st_iga_problem* prob, const st_iga_options* opt) {
+  st_iga_ctx c;
+  try {
+    validate(prob, opt);
+    c.P = *prob;
+    c.opt = *opt;
+    host_setup(&c);
+    c.ar = Arena();
+    plan(&c);
+    return c.ar.off + 256;
+  } catch (...) {
+    return 0;
+  }
+}
+
+st_iga_status st_iga_setup(const st_iga_problem* prob, const st_iga_options* opt, void* workspace,
+                           size_t workspace_bytes, void* stream, st_iga_ctx** out) {
+  if (!out) return ST_IGA_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<st_iga_ctx> c(new st_iga_ctx());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  st_iga_status st = guard(c.get(), [&] {
+    validate(prob, opt);
+    if (!workspace) throw Fail{ST_IGA_EINVAL, "null workspace"};
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) throw Fail{ST_IGA_EINVAL, "workspace must be 256-byte aligned"};
+    c->P = *prob;
+    c->opt = *opt;
+    host_setup(c.get());
+    c->ar = Arena();
+    plan(c.get());
+    const size_t need = c->ar.off;
+    if (workspace_bytes < need) throw Fail{ST_IGA_ENOMEM, "workspace too small"};
+    c->ar = Arena();
+    c->ar.base = static_cast<char*>(workspace);
+    c->ar.cap = workspace_bytes;
+    c->ar.dry = false;
+    plan(c.get());
+    upload_all(c.get(), s);
+    for (int l = 0; l < 4; ++l) c->P.knots[l] = nullptr;
+  });
+  if (st != ST_IGA_OK) {
+    g_last_err = c->err;
+    return st;
+  }
+  *out = c.release();
+  return ST_IGA_OK;
+}
+
+st_iga_status st_iga_linearize(st_iga_ctx* c, const double* u, const double* w, int32_t refresh_theta, void* stream) {
+  if (!c || !u || !w) return ST_IGA_EINVAL;
+  return guard(c, [&] {
+    if (!c->linearized && c->opt.su && !refresh_theta) throw Fail{ST_IGA_ESTATE, "theta has never been computed"};
+    linearize(c, u, w, refresh_theta != 0, static_cast<hipStream_t>(stream));
+  });
+}
+
+st_iga_status st_iga_set_factors(st_iga_ctx* c, int32_t rt, const double* Ut, const double* st, const double* Vt,
+                                 int32_t rc, const double* Uc, const double* sc, const double* Vc) {
+  if (!c) return ST_IGA_EINVAL;
+  return guard(c, [&] {
+    if (rt < 0 || rc < 0 || rt > c->maxR || rc > c->maxR) throw Fail{ST_IGA_EINVAL, "rank out of range"};
+    if ((rt > 0 && (!Ut || !st || !Vt)) || (rc > 0 && (!Uc || !sc || !Vc))) throw Fail{ST_IGA_EINVAL, "null factor"};
+    hipStream_t s = nullptr;
+    c->Rth = rt;
+    c->Rc = rc;
+    c->Uth_h.assign(Ut, Ut + static_cast<size_t>(c->Nt) * rt);
+    c->sth_h.assign(st, st + rt);
+    c->Uc_h.assign(Uc, Uc + static_cast<size_t>(c->Nt) * rc);
+    c->sc_h.assign(sc, sc + rc);
+    if (rt > 0) CK(hipMemcpy(c->Vth, Vt, static_cast<size_t>(c->Ns) * rt * sizeof(double), hipMemcpyHostToDevice));
+    if (rc > 0) CK(hipMemcpy(c->Vc, Vc, static_cast<size_t>(c->Ns) * rc * sizeof(double), hipMemcpyHostToDevice));
+    rebuild_coefficients(c, s);
+  });
+}
+
+st_iga_status st_iga_get_factors(st_iga_ctx* c, int32_t* rt, double* Ut, double* st, double* Vt, int32_t* rc,
+                                 double* Uc, double* sc, double* Vc) {
+  if (!c || !rt || !rc) return ST_IGA_EINVAL;
+  return guard(c, [&] {
+    *rt = c->Rth;
+    *rc = c->Rc;
+    if (Ut) std::copy(c->Uth_h.begin(), c->Uth_h.end(), Ut);
+    if (st) std::copy(c->sth_h.begin(), c->sth_h.end(), st);
+    if (Uc) std::copy(c->Uc_h.begin(), c->Uc_h.end(), Uc);
+    if (sc) std::copy(c->sc_h.begin(), c->sc_h.end(), sc);
+    if (Vt && c->Rth > 0) CK(hipMemcpy(Vt, c->Vth, static_cast<size_t>(c->Ns) * c->Rth * sizeof(double), hipMemcpyDeviceToHost));
+    if (Vc && c->Rc > 0) CK(hipMemcpy(Vc, c->Vc, static_cast<size_t>(c->Ns) * c->Rc * sizeof(double), hipMemcpyDeviceToHost));
+  });
+}
+
+st_iga_status st_iga_theta_grid(st_iga_ctx* c, const double* u, const double* w, double* th, void* stream) {
+  if (!c || !u || !w || !th) return ST_IGA_EINVAL;
+  return guard(c, [&] {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    theta_grid(c, u, w, th, s);
+    CK(hipStreamSynchronize(s));
+  });
+}
+
+st_iga_status st_iga_apply(st_iga_ctx* c, const double* x, double* y, void* stream) {
+  if (!c || !x || !y) return ST_IGA_EINVAL;
+  return guard(c, [&] {
+    ensure_lin(c);
+    apply64(c, x, y, static_cast<hipStream_t>(stream));
+    check_launch();
+  });
+}
+
+st_iga_status st_iga_precond(st_iga_ctx* c, const double* r, double* z, void* stream) {
+  if (!c || !r || !z) return ST_IGA_EINVAL;
+  return guard(c, [&] {
+    precond64(c, r, z, static_cast<hipStream_t>(stream));
+    check_launch();
+  });
+}
+
+st_iga_status st_iga_residual(st_iga_ctx* c, const double* u, const double* w, double* r, void* stream) {
+  if (!c || !u || !w || !r) return ST_IGA_EINVAL;
+  return guard(c, [&] {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    residual(c, u, w, r, s);
+    CK(hipStreamSynchronize(s));
+  });
+}
+
+st_iga_status st_iga_w_update(st_iga_ctx* c, const double* u, double* w, void* stream) {
+  if (!c || !u || !w) return ST_IGA_EINVAL;
+  return guard(c, [&] { w_update(c, u, w, static_cast<hipStream_t>(stream)); });
+}
+
+st_iga_status st_iga_krylov(st_iga_ctx* c, const double* b, double* x, double tol, int32_t* iters, double* relres,
+                            void* stream) {
+  if (!c || !b || !x || !(tol > 0)) return ST_IGA_EINVAL;
+  int it = 0;
+  double rr = 1.0;
+  st_iga_status st = guard(c, [&] {
+    it = krylov(c, b, x, tol, &rr, static_cast<hipStream_t>(stream));
+  });
+  if (iters) *iters = it;
+  if (relres) *relres = rr;
+  return st;
+}
+
+st_iga_status st_iga_lift(st_iga_ctx* c, const st_iga_stimulus* stim, double* c0, int64_t* count) {
+  if (!c || !stim || !c0) return ST_IGA_EINVAL;
+  return guard(c, [&] {
+    if (stim->f_kind != 0) throw Fail{ST_IGA_EINVAL, "source terms are not supported"};
+    std::vector<double> v = lift_host(c, stim, count);
+    std::copy(v.begin(), v.end(), c0);
+  });
+}
+
+st_iga_status st_iga_solve(st_iga_ctx* c, const st_iga_stimulus* stim, double* u, double* w, st_iga_report* rep,
+                           void* stream) {
+  if (!c || !stim || !u || !w) return ST_IGA_EINVAL;
+  return guard(c, [&] {
+    if (stim->f_kind != 0) throw Fail{ST_IGA_EINVAL, "source terms are not supported"};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st_iga_report R;
+    std::memset(&R, 0, sizeof(R));
+    std::vector<double> c0 = lift_host(c, stim, nullptr);
+    for (int k = 0; k < c->nt; ++k)
+      CK(hipMemcpyAsync(u + static_cast<int64_t>(k) * c->Ns, c0.data(), c->Ns * sizeof(double), hipMemcpyHostToDevice, s));
+    CK(hipStreamSynchronize(s));
+    bool frozen = false;
+    bool converged = false;
+    for (int k = 0; k < c->opt.max_outer; ++k) {
+      auto t0 = std::chrono::steady_clock::now();
+      w_update(c, u, w, s);
+      linearize(c, u, w, c->opt.su && !frozen, s);
+      residual(c, u, w, c->sol_rhs, s);
+      axpby(-1.0, c->sol_rhs, 0.0, c->sol_rhs, c->nunk, s);   // rhs = -N(u)
+      CK(hipStreamSynchronize(s));
+      auto t1 = std::chrono::steady_clock::now();
+      double rr = 1.0;
+      const int it = krylov(c, c->sol_rhs, c->sol_dx, c->opt.tol_lin, &rr, s);
+      add_unknowns(u, c->sol_dx, c->opt.alpha, c->nunk, c->Ns, s);
+      const double dinf = c->opt.alpha * dev_absmax(c, c->sol_dx, c->nunk, s);
+      auto t2 = std::chrono::steady_clock::now();
+      R.seconds_linearize += std::chrono::duration<double>(t1 - t0).count();
+      R.seconds_krylov += std::chrono::duration<double>(t2 - t1).count();
+      if (k < ST_IGA_MAX_OUTER_LOG) {
+        R.krylov[k] = it;
+        R.rank_theta[k] = c->Rth;
+        R.rank_react[k] = c->Rc;
+        R.delta_inf[k] = dinf;
+        R.lin_relres[k] = rr;
+      }
+      R.krylov_total += it;
+      R.outer_iters = k + 1;
+      R.final_delta_inf = dinf;
+      if (dinf <= c->opt.theta_freeze) frozen = true;
+      if (dinf <= c->opt.tol_nonlin) {
+        converged = true;
+        break;
+      }
+    }
+    w_update(c, u, w, s);
+    CK(hipStreamSynchronize(s));
+    if (rep) *rep = R;
+    if (!converged) throw Fail{ST_IGA_ENOCONV, "outer iteration limit reached"};
+  });
+}
+
+st_iga_status st_iga_sizes(const st_iga_ctx* c, int64_t* o) {
+  if (!c || !o) return ST_IGA_EINVAL;
+  o[0] = c->d;
+  o[1] = c->n[0];
+  o[2] = c->n[1];
+  o[3] = c->n[2];
+  o[4] = c->nt;
+  o[5] = c->Ns;
+  o[6] = c->Nt;
+  o[7] = c->nunk & 0xffffffffLL;
+  o[8] = c->nunk >> 32;
+  return ST_IGA_OK;
+}
+
+st_iga_status st_iga_destroy(st_iga_ctx* c) {
+  delete c;
+  return ST_IGA_OK;
+}
+
+const char* st_iga_last_error(const st_iga_ctx* c) { return c ? c->err.c_str() : g_last_err.c_str(); }
+
+st_iga_status st_iga_host_query(const st_iga_problem* prob, int32_t what, int32_t dir, double* out, int64_t cap,
+                                int64_t* len) {
+  st_iga_ctx c;
+  st_iga_options o;
+  st_iga_default_options(&o);
+  return guard(&c, [&] {
+    validate(prob, &o);
+    c.P = *prob;
+    c.opt = o;
+    host_setup(&c);
+    if (dir < 0 || dir > c.d) throw Fail{ST_IGA_EINVAL, "bad direction"};
+    const Dir1D& D = c.dir[dir];
+    std::vector<double> v;
+    switch (what) {
+      case 0: v = D.grev; break;
+      case 1: v = gram1d(D, 0, 0, nullptr); break;
+      case 2: v = gram1d(D, 1, 1, nullptr); break;
+      case 3: v = gram1d(D, 0, 1, nullptr); break;
+      case 4: v = c.tauq; break;
+      case 5: if (dir == c.d) throw Fail{ST_IGA_EINVAL, "spatial only"}; v = c.lam_h[dir]; break;
+      case 6: if (dir == c.d) throw Fail{ST_IGA_EINVAL, "spatial only"}; v = c.Us_h[dir]; break;
+      case 7: {
+        v = c.fd.U;
+        v.insert(v.end(), c.fd.mu.begin(), c.fd.mu.end());
+        v.insert(v.end(), c.fd.l.begin(), c.fd.l.end());
+        v.push_back(c.fd.sigma);
+        break;
+      }
+      case 8: v = D.xq; v.insert(v.end(), D.wq.begin(), D.wq.end()); break;
+      case 9: for (int f : D.first) v.push_back(f); break;
+      case 10: {
+        std::vector<int> e0, e1;
+        support_windows(D, dir == c.d ? 1 : 0, e0, e1);
+        for (size_t i = 0; i < e0.size(); ++i) { v.push_back(e0[i]); v.push_back(e1[i]); }
+        break;
+      }
+      default: throw Fail{ST_IGA_EINVAL, "unknown query"};
+    }
+    if (len) *len = static_cast<int64_t>(v.size());
+    if (out) std::copy(v.begin(), v.begin() + std::min<int64_t>(cap, v.size()), out);
+  });
+}
+
+}  // extern "C"

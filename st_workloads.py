@@ -180,3 +180,15 @@ def smooth_state(prob: Problem, seed: int = 0):
     u = u + 0.01 * rng.standard_normal(u.shape)
     w = 0.05 * tt * u
     return u.reshape(-1), w.reshape(-1)
+
+
+def random_factors(prob: Problem, R: int, seed: int = 0, scale: float = 1.0):
+    """Seeded low-rank factors (U: N_t x R, s: R, V: N_s x R) for a coefficient
+    field given on the Greville grid; rows are smooth random walks so that the
+    field resembles a sampled function.  Used to exercise the operator with
+    the same coefficient on both sides."""
+    rng = np.random.default_rng(seed)
+    U = np.cumsum(rng.standard_normal((prob.N_t, R)), axis=0) / np.sqrt(prob.N_t)
+    V = np.cumsum(rng.standard_normal((prob.N_s, R)), axis=0) / np.sqrt(prob.N_s)
+    s = scale * 0.5 ** np.arange(R)
+    return U, s, V

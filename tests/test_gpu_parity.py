@@ -1,0 +1,145 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs, element by element.  Tolerances: FP64 paths 1e-10
+relative (operators agree to ~1e-13; solves are limited by the Krylov
+tolerance), integer data bit-exact."""
+import numpy as np
+import pytest
+
+import st_workloads as W
+from oracle import solver
+from oracle.spacetime import LowRank, SpaceTime
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [("1d_p2", W.tiny(1, 2, 9, nel_t=7)),
+         ("2d_p3", W.tiny(2, 3, 5, nel_t=6)),
+         ("3d_p2", W.tiny(3, 2, 3, nel_t=5)),
+         ("3d_p1", W.tiny(3, 1, 4, nel_t=4)),
+         ("cfg0", W.config(0))]
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+def solver_for(prob, **kw):
+    from paper_2311_17500_amd.binding import Solver
+    return Solver(prob, **kw)
+
+
+def to_dev(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+def lowrank_product(f):
+    U, s, V = f
+    return (U * s) @ V.T
+
+
+@pytest.mark.parametrize("name,prob", SMALL, ids=[n for n, _ in SMALL])
+def test_lift_bit_exact(gpu_lib, name, prob):
+    S = solver_for(prob)
+    st = SpaceTime(prob)
+    c0, cnt = S.lift()
+    want = st.lift()
+    assert np.array_equal(c0, want) and cnt == int(np.sum(want != 0))
+
+
+@pytest.mark.parametrize("name,prob", SMALL, ids=[n for n, _ in SMALL])
+def test_theta_grid(gpu_lib, torch, name, prob):
+    S = solver_for(prob)
+    st = SpaceTime(prob)
+    u, w = W.smooth_state(prob, 3)
+    got = S.theta_grid(to_dev(torch, u), to_dev(torch, w)).cpu().numpy()
+    want = st.theta_grid(u, w).reshape(-1)
+    assert np.max(np.abs(got - want)) < 1e-12
+
+
+@pytest.mark.parametrize("name,prob", SMALL, ids=[n for n, _ in SMALL])
+def test_linearize_apply(gpu_lib, torch, name, prob):
+    """Linearization (theta, reaction coefficient, low ranks) and y = J x."""
+    S = solver_for(prob)
+    st = SpaceTime(prob)
+    u, w = W.smooth_state(prob, 5)
+    S.linearize(to_dev(torch, u), to_dev(torch, w))
+    lin = solver.linearize(st, u, w)
+    (gt, gc) = S.get_factors()
+    assert len(gt[1]) == lin.theta_lr.R and len(gc[1]) == lin.coef_lr.R
+    for g, o in ((gt, lin.theta_lr), (gc, lin.coef_lr)):
+        if o.R:
+            assert rel(lowrank_product(g), lowrank_product((o.U, o.s, o.V))) < 1e-11
+    x = W.random_vector(prob.unknowns, 11)
+    y = S.apply(to_dev(torch, x)).cpu().numpy()
+    assert rel(y, st.apply_J(x, lin.coef_q, lin.theta_q)) < 1e-11
+
+
+@pytest.mark.parametrize("name,prob", SMALL, ids=[n for n, _ in SMALL])
+def test_apply_with_given_factors(gpu_lib, torch, name, prob):
+    S = solver_for(prob)
+    st = SpaceTime(prob)
+    ft = W.random_factors(prob, 3, 1)
+    fc = W.random_factors(prob, 4, 2, scale=5.0)
+    S.set_factors(ft, fc)
+    x = W.random_vector(prob.unknowns, 12)
+    y = S.apply(to_dev(torch, x)).cpu().numpy()
+    thq = st.lowrank_at_quad(LowRank(*ft))
+    cq = st.lowrank_at_quad(LowRank(*fc))
+    assert rel(y, st.apply_J(x, cq, thq)) < 1e-12
+
+
+@pytest.mark.parametrize("name,prob", SMALL, ids=[n for n, _ in SMALL])
+def test_precond(gpu_lib, torch, name, prob):
+    S = solver_for(prob)
+    st = SpaceTime(prob)
+    r = W.random_vector(prob.unknowns, 13)
+    z = S.precond(to_dev(torch, r)).cpu().numpy()
+    assert rel(z, solver.precond_solve(st, r)) < 1e-11
+
+
+@pytest.mark.parametrize("name,prob", SMALL, ids=[n for n, _ in SMALL])
+def test_residual_and_w(gpu_lib, torch, name, prob):
+    S = solver_for(prob)
+    st = SpaceTime(prob)
+    u, w = W.smooth_state(prob, 6)
+    ud, wd = to_dev(torch, u), to_dev(torch, w)
+    wg = S.w_update(ud).cpu().numpy()
+    assert rel(wg, st.w_update_explicit(u)) < 1e-12
+    S.linearize(ud, wd)
+    lin = solver.linearize(st, u, w)
+    r = S.residual(ud, wd).cpu().numpy()
+    assert rel(r, st.residual(u, w, lin.theta_q)) < 1e-11
+
+
+@pytest.mark.parametrize("name,prob", SMALL, ids=[n for n, _ in SMALL])
+def test_krylov_solve(gpu_lib, torch, name, prob):
+    import scipy.sparse.linalg as spla
+    S = solver_for(prob)
+    st = SpaceTime(prob)
+    u, w = W.smooth_state(prob, 8)
+    S.linearize(to_dev(torch, u), to_dev(torch, w))
+    lin = solver.linearize(st, u, w)
+    b = W.random_vector(prob.unknowns, 14)
+    x, it, rr = S.krylov(to_dev(torch, b), tol=1e-12)
+    want = spla.splu(st.assemble_J(lin.coef_q, lin.theta_q).tocsc()).solve(b)
+    assert rr <= 1e-12 and it > 0
+    assert rel(x.cpu().numpy(), want) < 1e-9
+
+
+@pytest.mark.parametrize("name,prob", [SMALL[0], SMALL[1], SMALL[4]], ids=["1d_p2", "2d_p3", "cfg0"])
+def test_full_nonlinear_solve(gpu_lib, name, prob):
+    """Whole outer loop: Newton with lagged w, theta frozen below 1e-4."""
+    S = solver_for(prob, tol_nonlin=1e-11, tol_lin=1e-12)
+    st = SpaceTime(prob)
+    u, w, rep = S.solve()
+    uo, wo, log = solver.solve(st, tol=1e-11)
+    assert rep.outer_iters == len(log.deltas)
+    assert list(rep.rank_theta[: rep.outer_iters]) == log.ranks_theta
+    assert rel(u.cpu().numpy(), uo) < 1e-10
+    assert rel(w.cpu().numpy(), wo) < 1e-10
