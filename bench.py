@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the space-time SU solver hot path on one MI355X.
+
+One step = one full outer (Newton) iteration of the space-time solver from a
+fixed state u^1 (the iterate after one FP64 Newton step from the lifted
+initial datum): w-update, linearization (theta on the Greville grid, truncated
+SVDs of theta and of the reaction coefficient), residual N(u^1) with the exact
+ionic current at the Gauss points, FGMRES(30) with the fast-diagonalization
+preconditioner to an FP64 true relative residual of 1e-8 (mixed precision:
+FP32 or BF16 operator/preconditioner inside FP64 iterative refinement), and
+the Newton update.  Every step solves the identical system, so FP64 and mixed
+runs are comparable.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line (see the fields below).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12          # bytes/s, MI355X HBM3E
+PEAK_FP64 = 78.6e12        # flop/s, vector and matrix FP64
+PEAK_FP32 = 157.3e12       # flop/s, FP32 vector
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2, choices=[0, 1, 2, 4])
+    ap.add_argument("--prec", default="mixed_fp32", choices=["fp64", "mixed_fp32", "mixed_bf16"])
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    return ap.parse_args()
+
+
+def time_region(torch, S, u1, u2, w, steps, warmup, tol):
+    """Warm up, then time exactly `steps` steps between synchronizations."""
+    for _ in range(warmup):
+        S.newton_step(u1, u2, w, True, tol)
+    torch.cuda.synchronize()
+    S.profile(True)
+    S.profile_read(reset=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    its = []
+    rr = []
+    for _ in range(steps):
+        it, r, dinf = S.newton_step(u1, u2, w, True, tol)
+        its.append(it)
+        rr.append(r)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = S.profile_read(reset=True)
+    S.profile(False)
+    return ev0.elapsed_time(ev1) / steps, wall / steps * 1e3, its, rr, prof
+
+
+def kernel_bytes(S, prob, prec_bytes):
+    """Algorithmic bytes of one launch of the low-rank time-mixing kernel:
+    read Z ((N_t) layers x Q_s), the spatial factors (R x Q_s), write N_t x Q_s."""
+    (ft, fc) = S.get_factors()
+    R = len(ft[1]) + len(fc[1])
+    Qs = 1
+    for n in prob.nel_s:
+        Qs *= (prob.p_s + 1) * n
+    Nt = prob.N_t
+    by = (Nt + R + Nt) * Qs * prec_bytes
+    fl = Nt * Qs * (R * 2 * (2 * prob.p_t + 1) + 2 * R)
+    return by, fl, R
+
+
+def cpu_baseline(cfg):
+    """The oracle as it stands on the host cores: one Newton step (explicit
+    assembly + sparse LU) of the same physics on a reduced mesh."""
+    import numpy as np
+    import st_workloads as W
+    from oracle import solver as osolver
+    from oracle.spacetime import SpaceTime
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    base = W.config(cfg)
+    nel = {0: 32, 1: 10, 2: 6, 4: 5}[cfg]
+    prob = W.tiny(base.d, base.p_s, nel, nel_t=nel, sigma=base.sigma, u0_radius=base.u0_radius,
+                  u0_center=base.u0_center, u0_kind=base.u0_kind)
+    st = SpaceTime(prob)
+    u0 = np.tile(st.lift(), st.n[-1])
+    t0 = time.perf_counter()
+    w = st.w_update_explicit(u0)
+    lin = osolver.linearize(st, u0, w)
+    J = st.assemble_J(lin.coef_q, lin.theta_q)
+    r = st.residual(u0, w, lin.theta_q)
+    import scipy.sparse.linalg as spla
+    spla.splu(J.tocsc()).solve(-r)
+    dt = time.perf_counter() - t0
+    return {"value": prob.dof / dt, "unit": "DOF/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"one oracle Newton step (explicit sparse assembly by Gauss quadrature + scipy splu) of "
+                       f"the same physics at d={prob.d}, p={prob.p_s}, {nel}^{prob.d}x{nel} elements "
+                       f"({prob.dof} DOF) in {dt:.2f} s; splu is single-threaded, BLAS pool {cores}")}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
+              f"(the multi-GPU layout is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import st_workloads as W
+    from paper_2311_17500_amd.binding import Solver, FP64, MIXED_FP32, MIXED_BF16
+
+    prob = W.config(a.config)
+    prec_code = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}[a.prec]
+    prec_bytes = {"fp64": 8, "mixed_fp32": 4, "mixed_bf16": 2}[a.prec]
+
+    # the fixed state u^1: one FP64 Newton step from the lifted datum
+    S64 = Solver(prob, prec=FP64, tol_lin=a.tol)
+    c0, _ = S64.lift()
+    u0 = torch.tensor(np.tile(c0, prob.n_t), dtype=torch.float64, device="cuda:0")
+    u1, w = S64.vec(S64.full), S64.vec(S64.full)
+    S64.newton_step(u0, u1, w, True, a.tol)
+    u2 = S64.vec(S64.full)
+    torch.cuda.synchronize()
+
+    res = {}
+    if a.prec == "fp64" or not a.no_fp64_compare:
+        ms, wall, its, rr, prof = time_region(torch, S64, u1, u2, w, a.steps, a.warmup, a.tol)
+        res["fp64"] = dict(ms=ms, wall=wall, its=its, rr=rr, prof=prof, S=S64)
+    if a.prec != "fp64":
+        Sm = Solver(prob, prec=prec_code, tol_lin=a.tol)
+        ms, wall, its, rr, prof = time_region(torch, Sm, u1, u2, w, a.steps, a.warmup, a.tol)
+        res[a.prec] = dict(ms=ms, wall=wall, its=its, rr=rr, prof=prof, S=Sm)
+    main_r = res[a.prec]
+    ms = main_r["ms"]
+    value = prob.dof / (ms / 1e3)
+    # dominant kernel class over the timed region
+    prof = main_r["prof"]
+    dom = max(prof.items(), key=lambda kv: kv[1][0])
+    tm_ms, tm_n = prof["time_mix"]
+    by, fl, R = kernel_bytes(main_r["S"], prob, prec_bytes)
+    achieved = by / (tm_ms / tm_n / 1e3) if tm_n else None
+    roof = {"kernel": "time_mix (low-rank SU + reaction terms at the spatial Gauss points)",
+            "bound": "hbm", "achieved": achieved / 1e9 if achieved else None, "peak": PEAK_HBM / 1e9,
+            "unit": "GB/s", "frac": (achieved / PEAK_HBM) if achieved else None, "traffic": None,
+            "avg_launch_ms": tm_ms / tm_n if tm_n else None, "launches": tm_n,
+            "alg_bytes_per_launch": by, "rank_total": R,
+            "dominant_class": dom[0], "class_ms_per_step": {k: v[0] / a.steps for k, v in prof.items()}}
+    out = {
+        "metric": "space-time DOF/s to rel. residual 1e-8 (mixed vs FP64); p50/p99 solve latency",
+        "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "mixed_fp32": "f32+f64", "mixed_bf16": "bf16+f64"}[a.prec],
+        "data": "synthetic",
+        "config": {"workload": f"config{a.config}: d={prob.d} p={prob.p_s} "
+                               f"{'x'.join(map(str, prob.nel_s))}x{prob.nel_t} elements, "
+                               f"{prob.dof} DOF ({prob.unknowns} unknowns), {a.prec}",
+                   "dof": prob.dof, "unknowns": prob.unknowns, "precision": a.prec,
+                   "tol": a.tol, "step": "one Newton iteration (linearize + residual + FGMRES/FD to 1e-8)"},
+        "krylov_iters_per_step": main_r["its"][0], "final_relres": main_r["rr"][-1],
+        "wall_ms_per_step": main_r["wall"],
+        "roofline": roof,
+    }
+    if "fp64" in res and a.prec != "fp64":
+        f = res["fp64"]
+        out["fp64_dof_per_s"] = prob.dof / (f["ms"] / 1e3)
+        out["fp64_ms_per_step"] = f["ms"]
+        out["fp64_krylov_iters_per_step"] = f["its"][0]
+        out["speedup_vs_fp64"] = f["ms"] / ms
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(a.config)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

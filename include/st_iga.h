@@ -183,6 +183,27 @@ st_iga_status st_iga_krylov(st_iga_ctx* ctx, const double* b, double* x, double 
 st_iga_status st_iga_solve(st_iga_ctx* ctx, const st_iga_stimulus* stim, double* u, double* w,
                            st_iga_report* rep, void* stream);
 
+/* One outer iteration from the state u_in (full, device; unchanged unless
+ * u_out == u_in): w = w(u) (Section 3.2), linearize (theta refreshed when
+ * refresh_theta != 0), r = N(u), solve J delta = -r to relative residual tol,
+ * u_out = u_in + alpha delta.  Reports Krylov iterations, the FP64 true
+ * relative residual and ||alpha delta||_inf.  Synchronizes. */
+st_iga_status st_iga_newton_step(st_iga_ctx* ctx, const double* u_in, double* u_out, double* w,
+                                 int32_t refresh_theta, double tol, int32_t* iters, double* relres,
+                                 double* delta_inf, void* stream);
+
+/* Kernel-class timing with HIP events recorded around each launch on its
+ * stream (process-wide switch).  Classes: 0 other gathers, 1 time mixing of
+ * the low-rank terms, 2 arrowhead core, 3 Arnoldi multi-dot, 4 Arnoldi
+ * update+norm, 5 pointwise ionic quadrature, 6 element/window maxima,
+ * 7 banded mode products (constant part of the operator), 8 spline
+ * expansion/projection at Gauss points, 9 dense eigenvector mode products of
+ * the preconditioner.  profile_read returns the summed duration (ms) and the
+ * launch count since the last reset and synchronizes the recorded events. */
+st_iga_status st_iga_profile(st_iga_ctx* ctx, int32_t enable);
+st_iga_status st_iga_profile_read(st_iga_ctx* ctx, int32_t kernel_class, double* ms, int64_t* launches,
+                                  int32_t reset);
+
 /* Lifted initial datum (N_s entries, HOST output) and the number of spatial
  * Greville points inside the stimulus. */
 st_iga_status st_iga_lift(st_iga_ctx* ctx, const st_iga_stimulus* stim, double* c0, int64_t* count);

@@ -22,7 +22,8 @@ _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", ENOCONV: "ENOCONV", EDEVICE: "EDEV
 EXPORTS = ["st_iga_default_options", "st_iga_workspace_bytes", "st_iga_setup", "st_iga_linearize",
            "st_iga_set_factors", "st_iga_get_factors", "st_iga_theta_grid", "st_iga_apply", "st_iga_precond",
            "st_iga_residual", "st_iga_w_update", "st_iga_krylov", "st_iga_solve", "st_iga_lift", "st_iga_sizes",
-           "st_iga_destroy", "st_iga_last_error", "st_iga_host_query"]
+           "st_iga_destroy", "st_iga_last_error", "st_iga_host_query", "st_iga_newton_step", "st_iga_profile",
+           "st_iga_profile_read"]
 
 
 class Problem(C.Structure):
@@ -91,6 +92,10 @@ def load(path: str = LIB_PATH):
     lib.st_iga_destroy.argtypes = [P]
     lib.st_iga_last_error.argtypes = [P]
     lib.st_iga_last_error.restype = C.c_char_p
+    lib.st_iga_newton_step.argtypes = [P, V, V, V, C.c_int32, C.c_double, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double), V]
+    lib.st_iga_profile.argtypes = [P, C.c_int32]
+    lib.st_iga_profile_read.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
     lib.st_iga_host_query.argtypes = [C.POINTER(Problem), C.c_int32, C.c_int32, V, C.c_int64, C.POINTER(C.c_int64)]
     for name in EXPORTS:
         if name not in ("st_iga_default_options", "st_iga_workspace_bytes", "st_iga_last_error"):
@@ -250,6 +255,30 @@ class Solver:
         it, rr = C.c_int32(0), C.c_double(0)
         self._chk(self.lib.st_iga_krylov(self.ctx, self._p(b), self._p(x), tol, C.byref(it), C.byref(rr), self._s()))
         return x, it.value, rr.value
+
+    def newton_step(self, u_in, u_out, w, refresh_theta=True, tol=1e-8):
+        it, rr, dinf = C.c_int32(0), C.c_double(0), C.c_double(0)
+        self._chk(self.lib.st_iga_newton_step(self.ctx, self._p(u_in), self._p(u_out), self._p(w),
+                                              int(refresh_theta), tol, C.byref(it), C.byref(rr), C.byref(dinf),
+                                              self._s()))
+        return it.value, rr.value, dinf.value
+
+    KCLASSES = ["gather", "time_mix", "arrowhead", "multidot", "update_norm", "pointwise_ionic", "maxima",
+                "banded", "expand", "dense_fd"]
+
+    def profile(self, on=True):
+        self._chk(self.lib.st_iga_profile(self.ctx, int(on)))
+
+    def profile_read(self, reset=True):
+        out = {}
+        for k, name in enumerate(self.KCLASSES):
+            ms, n = C.c_double(0), C.c_int64(0)
+            self._chk(self.lib.st_iga_profile_read(self.ctx, k, C.byref(ms), C.byref(n), 0))
+            out[name] = (ms.value, n.value)
+        if reset:
+            ms, n = C.c_double(0), C.c_int64(0)
+            self._chk(self.lib.st_iga_profile_read(self.ctx, 0, C.byref(ms), C.byref(n), 1))
+        return out
 
     def lift(self):
         c0 = np.zeros(self.N_s)

@@ -13,6 +13,11 @@
 //    bitwise reproducible run to run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <type_traits>
+#include <utility>
+#include <vector>
+
 #include "kernels.hpp"
 
 namespace stiga {
@@ -47,29 +52,181 @@ __device__ __forceinline__ bf16 from_c<bf16>(double v) { return __float2bfloat16
 
 inline unsigned grid_for(int64_t n, int tpb = TPB) { return static_cast<unsigned>((n + tpb - 1) / tpb); }
 
+// ---------------------------------------------------------------- profiler
+struct ProfState {
+  bool on = false;
+  int gather_cls = 0;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> rec;
+};
+ProfState& prof() {
+  static ProfState p;
+  return p;
+}
+hipEvent_t prof_event() {
+  ProfState& p = prof();
+  if (p.used == p.pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    p.pool.push_back(e);
+  }
+  return p.pool[p.used++];
+}
+// RAII bracket around one launch
+struct ProfScope {
+  int cls;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(int c, hipStream_t st) : cls(c), s(st) {
+    if (prof().on) {
+      a = prof_event();
+      if (a) hipEventRecord(a, s);
+    }
+  }
+  ~ProfScope() {
+    if (a) {
+      hipEvent_t b = prof_event();
+      if (b) {
+        hipEventRecord(b, s);
+        prof().rec.push_back({cls, {a, b}});
+      }
+    }
+  }
+};
+
 // ---------------------------------------------------------------- gather
-template <class Ti, class To, class C>
+template <class Ti, class To, class C, class I>
 __global__ void __launch_bounds__(TPB) k_gather(const int* __restrict__ col, const C* __restrict__ coef, int W,
                                                 int n_out, const Ti* __restrict__ x, To* __restrict__ y,
-                                                int64_t inner, int n_in, int in_base, C alpha, C beta,
-                                                int64_t total) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+                                                I inner, int n_in, int in_base, C alpha, C beta, I total) {
+  const I idx = static_cast<I>(blockIdx.x) * static_cast<I>(blockDim.x) + static_cast<I>(threadIdx.x);
   if (idx >= total) return;
-  const int64_t k = idx % inner;
-  const int64_t t = idx / inner;
-  const int i = static_cast<int>(t % n_out);
-  const int64_t o = t / n_out;
+  const I k = idx % inner;
+  const I t = idx / inner;
+  const int i = static_cast<int>(t % static_cast<I>(n_out));
+  const I o = t / static_cast<I>(n_out);
   const int* cr = col + static_cast<int64_t>(i) * W;
   const C* cf = coef + static_cast<int64_t>(i) * W;
-  const Ti* xb = x + o * static_cast<int64_t>(n_in) * inner + k;
+  const Ti* xb = x + static_cast<int64_t>(o) * n_in * static_cast<int64_t>(inner) + k;
   C acc = C(0);
   for (int w = 0; w < W; ++w) {
     const int c = cr[w] - in_base;
-    if (static_cast<unsigned>(c) < static_cast<unsigned>(n_in)) acc += cf[w] * to_c(xb[static_cast<int64_t>(c) * inner], C(0));
+    if (static_cast<unsigned>(c) < static_cast<unsigned>(n_in))
+      acc += cf[w] * to_c(xb[static_cast<int64_t>(c) * static_cast<int64_t>(inner)], C(0));
   }
   C r = alpha * acc;
   if (beta != C(0)) r += beta * to_c(y[idx], C(0));
   y[idx] = from_c<To>(r);
+}
+
+
+// Vectorized variant for inner % 4 == 0: each thread produces 4 consecutive k
+// of one output row.  Threads of a block share one row block (o, i) when
+// inner >= 4 * blockDim, so the table row is read once per wave.
+template <class T> struct V4;
+template <> struct V4<double> { typedef double4 T; };
+template <> struct V4<float> { typedef float4 T; };
+
+template <class S, class C>
+__device__ __forceinline__ void load4(const S* p, C* v) {
+  typedef typename V4<S>::T T4;
+  const T4 t = *reinterpret_cast<const T4*>(p);
+  v[0] = static_cast<C>(t.x); v[1] = static_cast<C>(t.y); v[2] = static_cast<C>(t.z); v[3] = static_cast<C>(t.w);
+}
+template <>
+__device__ __forceinline__ void load4<bf16, float>(const bf16* p, float* v) {
+  for (int e = 0; e < 4; ++e) v[e] = __bfloat162float(p[e]);
+}
+template <class S, class C>
+__device__ __forceinline__ void store4(S* p, const C* v) {
+  typedef typename V4<S>::T T4;
+  T4 t;
+  t.x = static_cast<S>(v[0]); t.y = static_cast<S>(v[1]); t.z = static_cast<S>(v[2]); t.w = static_cast<S>(v[3]);
+  *reinterpret_cast<T4*>(p) = t;
+}
+template <>
+__device__ __forceinline__ void store4<bf16, float>(bf16* p, const float* v) {
+  for (int e = 0; e < 4; ++e) p[e] = __float2bfloat16(v[e]);
+}
+
+// Thread t of block b: rows are (o * n_out + i); a row has inner/4 vector
+// slots.  When a row has fewer than TPB slots, a block packs TPB / slots
+// rows; otherwise a row spans kchunks blocks.
+template <class S, class C>
+__global__ void __launch_bounds__(TPB) k_gather_v4(const int* __restrict__ col, const C* __restrict__ coef, int W,
+                                                   int n_out, const S* __restrict__ x, S* __restrict__ y,
+                                                   uint32_t inner, int n_in, int in_base, C alpha, C beta,
+                                                   uint32_t nrows, uint32_t slots, uint32_t rpb, uint32_t kchunks) {
+  uint32_t row, slot;
+  if (rpb > 1) {
+    row = blockIdx.x * rpb + threadIdx.x / slots;
+    slot = threadIdx.x % slots;
+    if (threadIdx.x >= rpb * slots) return;
+  } else {
+    row = blockIdx.x / kchunks;
+    slot = (blockIdx.x % kchunks) * TPB + threadIdx.x;
+    if (slot >= slots) return;
+  }
+  if (row >= nrows) return;
+  const uint32_t k = slot * 4;
+  const int i = static_cast<int>(row % static_cast<uint32_t>(n_out));
+  const uint32_t o = row / static_cast<uint32_t>(n_out);
+  const int* cr = col + static_cast<int64_t>(i) * W;
+  const C* cf = coef + static_cast<int64_t>(i) * W;
+  const S* xb = x + (static_cast<int64_t>(o) * n_in) * inner + k;
+  C acc[4] = {C(0), C(0), C(0), C(0)};
+  for (int w = 0; w < W; ++w) {
+    const int c = cr[w] - in_base;
+    if (static_cast<unsigned>(c) < static_cast<unsigned>(n_in)) {
+      C v[4];
+      load4<S, C>(xb + static_cast<int64_t>(c) * inner, v);
+      const C a = cf[w];
+      acc[0] += a * v[0]; acc[1] += a * v[1]; acc[2] += a * v[2]; acc[3] += a * v[3];
+    }
+  }
+  S* yp = y + static_cast<int64_t>(row) * inner + k;
+  C r[4];
+  if (beta != C(0)) {
+    C old[4];
+    load4<S, C>(yp, old);
+    for (int e = 0; e < 4; ++e) r[e] = alpha * acc[e] + beta * old[e];
+  } else {
+    for (int e = 0; e < 4; ++e) r[e] = alpha * acc[e];
+  }
+  store4<S, C>(yp, r);
+}
+
+// Fastest-axis variant (inner == 1): a block stages RB consecutive input rows
+// (contiguous, coalesced) in LDS, then produces the RB output rows from LDS
+// and writes them contiguously.
+template <class S, class C>
+__global__ void __launch_bounds__(TPB) k_gather_rows(const int* __restrict__ col, const C* __restrict__ coef, int W,
+                                                     int n_out, const S* __restrict__ x, S* __restrict__ y, int n_in,
+                                                     int in_base, C alpha, C beta, int64_t nrows, int RB) {
+  extern __shared__ char smem_raw[];
+  C* xs = reinterpret_cast<C*>(smem_raw);
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RB;
+  const int rb = static_cast<int>(min(static_cast<int64_t>(RB), nrows - r0));
+  const S* xb = x + r0 * n_in;
+  for (int t = threadIdx.x; t < rb * n_in; t += TPB) xs[t] = to_c(xb[t], C(0));
+  __syncthreads();
+  S* yb = y + r0 * n_out;
+  const int tot = rb * n_out;
+  for (int t = threadIdx.x; t < tot; t += TPB) {
+    const int r = t / n_out, i = t - r * n_out;
+    const int* cr = col + static_cast<int64_t>(i) * W;
+    const C* cf = coef + static_cast<int64_t>(i) * W;
+    const C* xr = xs + r * n_in;
+    C acc = C(0);
+    for (int w = 0; w < W; ++w) {
+      const int c = cr[w] - in_base;
+      if (static_cast<unsigned>(c) < static_cast<unsigned>(n_in)) acc += cf[w] * xr[c];
+    }
+    C v = alpha * acc;
+    if (beta != C(0)) v += beta * to_c(yb[t], C(0));
+    yb[t] = from_c<S>(v);
+  }
 }
 
 __global__ void __launch_bounds__(TPB) k_mode_max(const int* __restrict__ start, const int* __restrict__ cnt,
@@ -120,6 +277,71 @@ __global__ void __launch_bounds__(TPB) k_time_mix(const C* __restrict__ T, const
     const int j = t + 2 + P - in_base;
     win[WB - 1] = (static_cast<unsigned>(j) < static_cast<unsigned>(n_in)) ? to_c(Z[static_cast<int64_t>(j) * Qs + q], C(0)) : C(0);
   }
+}
+
+
+// ---------------------------------------------------------------- dense mode product on MFMA
+// Y[o][i][k] = sum_j A[i][j] X[o][j][k] as a GEMM D = A X_cols over the
+// columns c = (o, k).  Each wave owns 16 columns and every output row (n
+// padded to NT*16); the K loop steps over j by 4 with the 16x16x4 MFMA
+// (FP64 or FP32 accumulate).  Operand layouts of v_mfma_*_16x16x4: A lane l
+// holds A[l%16][l/16], B lane l holds B[l/16][l%16]; result element v of lane
+// l is D[4*(l/16)+v][l%16] for the FP32 form and D[l/16+4v][l%16] for the
+// FP64 form (checked on gfx950).  A is zero-padded to npad x npad; X rows j >= n and
+// columns c >= ncols read as 0, so all loads stay in bounds.
+typedef double dx4 __attribute__((ext_vector_type(4)));
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ dx4 mfma16x16x4(double a, double b, dx4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ fx4 mfma16x16x4(float a, float b, fx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <class C> struct Acc4;
+template <> struct Acc4<double> { typedef dx4 T; };
+template <> struct Acc4<float> { typedef fx4 T; };
+
+template <class S, class C, int NT, bool LDS_A>
+__global__ void __launch_bounds__(256) k_dense_mode(const C* __restrict__ Ap, int n, int npad,
+                                                    const S* __restrict__ x, S* __restrict__ y, int64_t inner,
+                                                    int64_t ncols) {
+  extern __shared__ char smem_raw[];
+  C* As = reinterpret_cast<C*>(smem_raw);
+  if (LDS_A) {
+    for (int t = threadIdx.x; t < npad * npad; t += blockDim.x) As[t] = Ap[t];
+    __syncthreads();
+  }
+  const C* Asrc = LDS_A ? As : Ap;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t c = (static_cast<int64_t>(blockIdx.x) * 4 + wv) * 16 + (lane & 15);
+  const bool cv = c < ncols;
+  const int64_t o = cv ? c / inner : 0;
+  const int64_t kq = cv ? c - o * inner : 0;
+  const S* xb = x + o * static_cast<int64_t>(n) * inner + kq;
+  typedef typename Acc4<C>::T A4;
+  A4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = A4{0, 0, 0, 0};
+  const int r16 = lane & 15, q4 = lane >> 4;
+  for (int kk = 0; kk < npad; kk += 4) {
+    const int j = kk + q4;
+    const C b = (cv && j < n) ? to_c(xb[static_cast<int64_t>(j) * inner], C(0)) : C(0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const C a = Asrc[(t * 16 + r16) * npad + j];
+      acc[t] = mfma16x16x4(a, b, acc[t]);
+    }
+  }
+  if (!cv) return;
+  S* yb = y + o * static_cast<int64_t>(n) * inner + kq;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = t * 16 + (std::is_same<C, double>::value ? q4 + 4 * v : 4 * q4 + v);
+      if (i < n) yb[static_cast<int64_t>(i) * inner] = from_c<S>(acc[t][v]);
+    }
 }
 
 // ---------------------------------------------------------------- arrowhead
@@ -447,8 +669,41 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
             C beta, hipStream_t s) {
   const int64_t total = outer * t.n_out * inner;
   if (total == 0) return;
-  hipLaunchKernelGGL((k_gather<Ti, To, C>), dim3(grid_for(total)), dim3(TPB), 0, s, t.col, t.coef, t.W, t.n_out, x, y,
-                     inner, n_in, in_base, alpha, beta, total);
+  ProfScope ps(prof().gather_cls, s);
+  const int64_t nrows = outer * t.n_out;
+  if (std::is_same<Ti, To>::value && inner % 4 == 0 && inner < (static_cast<int64_t>(1) << 31) &&
+      (reinterpret_cast<uintptr_t>(x) % (4 * sizeof(Ti))) == 0 && (reinterpret_cast<uintptr_t>(y) % (4 * sizeof(To))) == 0) {
+    const int64_t slots = inner / 4;
+    const int64_t rpb = slots < TPB ? TPB / slots : 1;
+    const int64_t kchunks = rpb > 1 ? 1 : (slots + TPB - 1) / TPB;
+    const int64_t blocks = rpb > 1 ? (nrows + rpb - 1) / rpb : kchunks * nrows;
+    if (blocks < (static_cast<int64_t>(1) << 31) && nrows < (static_cast<int64_t>(1) << 32)) {
+      hipLaunchKernelGGL((k_gather_v4<Ti, C>), dim3(static_cast<unsigned>(blocks)), dim3(TPB), 0, s, t.col, t.coef,
+                         t.W, t.n_out, x, reinterpret_cast<Ti*>(y), static_cast<uint32_t>(inner), n_in, in_base, alpha,
+                         beta, static_cast<uint32_t>(nrows), static_cast<uint32_t>(slots), static_cast<uint32_t>(rpb),
+                         static_cast<uint32_t>(kchunks));
+      return;
+    }
+  }
+  if (inner == 1 && std::is_same<Ti, To>::value) {
+    // rows per block: stage about 2048 input values
+    const int RB = std::max(1, std::min(64, 2048 / std::max(n_in, 1)));
+    // here a "row" is one outer index: n_in inputs in, t.n_out outputs out
+    const int64_t blocks = (outer + RB - 1) / RB;
+    const size_t sh = static_cast<size_t>(RB) * n_in * sizeof(C);
+    if (blocks < (static_cast<int64_t>(1) << 31) && sh <= 48 * 1024) {
+      hipLaunchKernelGGL((k_gather_rows<Ti, C>), dim3(static_cast<unsigned>(blocks)), dim3(TPB), sh, s, t.col, t.coef,
+                         t.W, t.n_out, x, reinterpret_cast<Ti*>(y), n_in, in_base, alpha, beta, outer, RB);
+      return;
+    }
+  }
+  if (total < (static_cast<int64_t>(1) << 32))
+    hipLaunchKernelGGL((k_gather<Ti, To, C, uint32_t>), dim3(grid_for(total)), dim3(TPB), 0, s, t.col, t.coef, t.W,
+                       t.n_out, x, y, static_cast<uint32_t>(inner), n_in, in_base, alpha, beta,
+                       static_cast<uint32_t>(total));
+  else
+    hipLaunchKernelGGL((k_gather<Ti, To, C, int64_t>), dim3(grid_for(total)), dim3(TPB), 0, s, t.col, t.coef, t.W,
+                       t.n_out, x, y, inner, n_in, in_base, alpha, beta, total);
 }
 
 template <class Ti, class To, class C>
@@ -466,6 +721,7 @@ void mode_max(const int* start, const int* cnt, int n_out, const double* x, doub
               int n_in, hipStream_t s) {
   const int64_t total = outer * n_out * inner;
   if (total == 0) return;
+  ProfScope ps(K_MAX, s);
   hipLaunchKernelGGL(k_mode_max, dim3(grid_for(total)), dim3(TPB), 0, s, start, cnt, n_out, x, y, inner, n_in, total);
 }
 
@@ -477,6 +733,7 @@ void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int p, const S* 
   while (tpb > 64 && static_cast<size_t>(R) * tpb * sizeof(C) > 64 * 1024) tpb /= 2;
   const size_t sh = static_cast<size_t>(R > 0 ? R : 1) * tpb * sizeof(C);
   const dim3 g(grid_for(Qs, tpb)), b(tpb);
+  ProfScope ps(K_TIME_MIX, s);
   switch (p) {
     case 1: hipLaunchKernelGGL((k_time_mix<S, C, 1>), g, b, sh, s, T, Psi, r0, R, Nt, Z, n_in, in_base, out, Qs); break;
     case 2: hipLaunchKernelGGL((k_time_mix<S, C, 2>), g, b, sh, s, T, Psi, r0, R, Nt, Z, n_in, in_base, out, Qs); break;
@@ -486,16 +743,63 @@ void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int p, const S* 
   }
 }
 
+
+template <class S, class C>
+void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, int64_t inner, hipStream_t s) {
+  const int64_t ncols = outer * inner;
+  if (ncols == 0) return;
+  const unsigned grid = static_cast<unsigned>((ncols + 63) / 64);
+  const int NT = npad / 16;
+  const size_t abytes = static_cast<size_t>(npad) * npad * sizeof(C);
+  const bool lds = abytes <= 64 * 1024;
+  ProfScope ps(K_DENSE, s);
+#define DM_CASE(nt)                                                                                          \
+  case nt:                                                                                                   \
+    if (lds) hipLaunchKernelGGL((k_dense_mode<S, C, nt, true>), dim3(grid), dim3(256), abytes, s, Ap, n, npad, x, y, inner, ncols); \
+    else hipLaunchKernelGGL((k_dense_mode<S, C, nt, false>), dim3(grid), dim3(256), 0, s, Ap, n, npad, x, y, inner, ncols);  \
+    break;
+  switch (NT) {
+    DM_CASE(1) DM_CASE(2) DM_CASE(3) DM_CASE(4) DM_CASE(5) DM_CASE(6) DM_CASE(7) DM_CASE(8) DM_CASE(9)
+    default: break;
+  }
+#undef DM_CASE
+}
+
 template <class S, class C>
 void arrowhead(const S* r, S* y, const C* lam, const C* mu, const int* kind, const C* l, C sigma, C Cm, int Nt,
                int64_t Ns, hipStream_t s) {
+  ProfScope ps(K_ARROW, s);
   hipLaunchKernelGGL((k_arrowhead<S, C>), dim3(grid_for(Ns)), dim3(TPB), 0, s, r, y, lam, mu, kind, l, sigma, Cm, Nt, Ns);
+}
+
+void kprof_enable(bool on) { prof().on = on; }
+void kprof_gather_class(int cls) { prof().gather_cls = cls; }
+
+void kprof_read(int cls, double* ms, int64_t* launches, int reset) {
+  ProfState& p = prof();
+  double tot = 0.0;
+  int64_t n = 0;
+  for (auto& r : p.rec) {
+    if (r.first != cls) continue;
+    hipEventSynchronize(r.second.second);
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, r.second.first, r.second.second) == hipSuccess) tot += t;
+    ++n;
+  }
+  if (ms) *ms = tot;
+  if (launches) *launches = n;
+  if (reset) {
+    for (auto& r : p.rec) hipEventSynchronize(r.second.second);
+    p.rec.clear();
+    p.used = 0;
+  }
 }
 
 int reduce_blocks(int64_t n) { return static_cast<int>((n + RED_CHUNK - 1) / RED_CHUNK); }
 
 void multidot_partial(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* part, int nb,
                       hipStream_t s) {
+  ProfScope ps(K_MULTIDOT, s);
   hipLaunchKernelGGL(k_multidot, dim3(nb), dim3(TPB), 0, s, V, ldv, k, w, n, part);
 }
 void finalize_sum(const double* part, int nb, int k, double* out, hipStream_t s) {
@@ -503,6 +807,7 @@ void finalize_sum(const double* part, int nb, int k, double* out, hipStream_t s)
 }
 void update_norm_partial(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t n, double* part,
                          int nb, hipStream_t s) {
+  ProfScope ps(K_UPDATE, s);
   hipLaunchKernelGGL(k_update_norm, dim3(nb), dim3(TPB), 0, s, V, ldv, k, h, w, n, part);
 }
 void absmax_partial(const double* x, int64_t n, double* part, int nb, hipStream_t s) {
@@ -538,6 +843,7 @@ void pointwise_ionic(const double* u, const double* ut, const double* lap, const
                      double* g, double* absR, double* part, int nb, hipStream_t s) {
   const int64_t total = Qs * nq_t;
   (void)nb;
+  ProfScope ps(K_POINTWISE, s);
   hipLaunchKernelGGL(k_pointwise_ionic, dim3(grid_for(total)), dim3(TPB), 0, s, u, ut, lap, w, wt_time, wt_space, Qs,
                      total, Cm, a, c1, c2, g, absR, part);
 }
@@ -581,6 +887,10 @@ template void time_mix<float, float>(const float*, const float*, int, int, int, 
                                      int64_t, hipStream_t);
 template void time_mix<bf16, float>(const float*, const bf16*, int, int, int, int, const bf16*, int, int, bf16*,
                                     int64_t, hipStream_t);
+template void dense_mode<double, double>(const double*, int, int, const double*, double*, int64_t, int64_t,
+                                         hipStream_t);
+template void dense_mode<float, float>(const float*, int, int, const float*, float*, int64_t, int64_t, hipStream_t);
+template void dense_mode<bf16, float>(const float*, int, int, const bf16*, bf16*, int64_t, int64_t, hipStream_t);
 template void arrowhead<double, double>(const double*, double*, const double*, const double*, const int*,
                                         const double*, double, double, int, int64_t, hipStream_t);
 template void arrowhead<float, float>(const float*, float*, const float*, const float*, const int*, const float*,

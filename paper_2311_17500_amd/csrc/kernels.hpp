@@ -12,6 +12,17 @@ namespace stiga {
 
 typedef __hip_bfloat16 bf16;
 
+// Kernel classes for the optional HIP-event profiler (host-side timing of
+// individual launches on the stream they run on).
+enum KClass { K_GATHER = 0, K_TIME_MIX, K_ARROW, K_MULTIDOT, K_UPDATE, K_POINTWISE, K_MAX, K_BANDED, K_EXPAND,
+              K_DENSE, K_NCLASS };
+void kprof_enable(bool on);
+// class recorded for gather launches until changed (K_GATHER by default)
+void kprof_gather_class(int cls);
+// Sum of launch durations (ms) and launch count of a class since the last reset;
+// synchronizes the recorded events.  Resets when reset != 0.
+void kprof_read(int cls, double* ms, int64_t* launches, int reset);
+
 // Device view of a gather table: y[i] = sum_w coef[i*W+w] * x[col[i*W+w] - in_base],
 // terms with the input index outside [0, n_in) skipped.
 template <class C>
@@ -42,6 +53,11 @@ void mode_max(const int* start, const int* cnt, int n_out, const double* x, doub
 template <class S, class C>
 void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int p, const S* Z, int n_in, int in_base,
               S* out, int64_t Qs, hipStream_t s);
+
+// Dense mode product on MFMA: y[o][i][k] = sum_j A[i][j] x[o][j][k], A given
+// zero-padded as npad x npad (npad = 16 * ceil(n / 16) <= 144), row-major.
+template <class S, class C>
+void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, int64_t inner, hipStream_t s);
 
 // Arrowhead solve of the fast-diagonalization core, one spatial mode per thread.
 template <class S, class C>

@@ -85,6 +85,13 @@ struct st_iga_ctx {
   // tables
   Tab Ms[3], Ks[3], Bq[3][3], BqT[3], Hs[3], Gs[3], Us[3], UsT[3];
   Tab Mt_x, Wt_x, Bt0, Bt1, BtT, Gt, Ut, UtT, Ew;
+  // zero-padded dense FD matrices for the MFMA mode products (A[i][j] applied as sum_j A[i][j] x_j)
+  struct Dense {
+    std::vector<double> h;
+    double* d = nullptr;
+    float* f = nullptr;
+    int n = 0, npad = 0;
+  } DUsT[3], DUs[3], DUtT, DUt;
   // device data
   double *lam_d = nullptr, *mu_d = nullptr, *l_d = nullptr;
   float *lam_f = nullptr, *mu_f = nullptr, *l_f = nullptr;
@@ -251,6 +258,22 @@ void host_setup(st_iga_ctx* c) {
   if (!time_fd(Wx, Mx, Nt, c->fd, err)) throw Fail{ST_IGA_EINVAL, err};
   c->Ut.h = dense_table(c->fd.U, Nt, Nt, false);
   c->UtT.h = dense_table(c->fd.U, Nt, Nt, true);
+  auto pad = [](st_iga_ctx::Dense& D, const std::vector<double>& U, int n, bool transpose) {
+    D.n = n;
+    D.npad = 16 * ((n + 15) / 16);
+    D.h.assign(static_cast<size_t>(D.npad) * D.npad, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        D.h[static_cast<size_t>(i) * D.npad + j] = transpose ? U[static_cast<size_t>(j) * n + i] : U[static_cast<size_t>(i) * n + j];
+  };
+  if (Nt > 144) throw Fail{ST_IGA_EINVAL, "more than 144 time unknowns is not supported"};
+  pad(c->DUt, c->fd.U, Nt, false);
+  pad(c->DUtT, c->fd.U, Nt, true);
+  for (int l = 0; l < P.d; ++l) {
+    if (c->n[l] > 144) throw Fail{ST_IGA_EINVAL, "more than 144 basis functions per direction is not supported"};
+    pad(c->DUs[l], c->Us_h[l], c->n[l], false);
+    pad(c->DUsT[l], c->Us_h[l], c->n[l], true);
+  }
   // spatial eigenvalue sums + shift
   c->lam_s_h.assign(c->Ns, 0.0);
   for (int64_t j = 0; j < c->Ns; ++j) {
@@ -326,6 +349,12 @@ void plan(st_iga_ctx* c) {
     for (int k = 0; k <= 2; ++k) T(c->Bq[l][k]);
   }
   T(c->Mt_x); T(c->Wt_x); T(c->Bt0); T(c->Bt1); T(c->BtT); T(c->Gt); T(c->Ut); T(c->UtT); T(c->Ew);
+  for (st_iga_ctx::Dense* D : {&c->DUt, &c->DUtT, &c->DUs[0], &c->DUs[1], &c->DUs[2], &c->DUsT[0], &c->DUsT[1],
+                               &c->DUsT[2]}) {
+    if (D->npad == 0) continue;
+    D->d = a.get<double>(static_cast<int64_t>(D->npad) * D->npad);
+    D->f = a.get<float>(static_cast<int64_t>(D->npad) * D->npad);
+  }
   c->lam_d = a.get<double>(c->Ns);
   c->lam_f = a.get<float>(c->Ns);
   c->mu_d = a.get<double>(c->Nt);
@@ -419,6 +448,13 @@ void upload_all(st_iga_ctx* c, hipStream_t s) {
       upload_tab(*t, s, keepf);
   }
   for (Tab* t : {&c->Mt_x, &c->Wt_x, &c->Bt0, &c->Bt1, &c->BtT, &c->Gt, &c->Ut, &c->UtT, &c->Ew}) upload_tab(*t, s, keepf);
+  for (st_iga_ctx::Dense* D : {&c->DUt, &c->DUtT, &c->DUs[0], &c->DUs[1], &c->DUs[2], &c->DUsT[0], &c->DUsT[1],
+                               &c->DUsT[2]}) {
+    if (D->npad == 0) continue;
+    up(D->h, static_cast<const double*>(D->d), s);
+    keepf.emplace_back(D->h.begin(), D->h.end());
+    up(keepf.back(), static_cast<const float*>(D->f), s);
+  }
   up(c->lam_s_h, static_cast<const double*>(c->lam_d), s);
   keepf.emplace_back(c->lam_s_h.begin(), c->lam_s_h.end());
   up(keepf.back(), static_cast<const float*>(c->lam_f), s);
@@ -495,21 +531,29 @@ struct Bufs {
 
 // Apply the tensor chain along spatial axes: x has layout [L][m_d]..[m_1] with
 // m_l = in dims; apply tabs[l] along axis l (output dims out[l]); ping-pong
-// between bufA/bufB; the last step writes to `dst` with (alpha, beta).
+// between bufA/bufB; the last step writes to `dst` with (alpha, beta).  Axes
+// are taken x_1 first when the chain grows the array (expansion to Gauss
+// points) and x_d first when it shrinks it, so the fastest-axis step always
+// works on the smallest array.
 template <class S, class C>
 const S* spatial_chain(st_iga_ctx* c, const Tab* const* tabs, const S* x, int64_t L, const int* in_dims,
                        const int* out_dims, S* bufA, S* bufB, S* dst, C alpha, C beta, hipStream_t s) {
   const int d = c->d;
   int dims[3];
-  for (int l = 0; l < d; ++l) dims[l] = in_dims[l];
+  int64_t grow = 0;
+  for (int l = 0; l < d; ++l) {
+    dims[l] = in_dims[l];
+    grow += out_dims[l] - in_dims[l];
+  }
   const S* cur = x;
   S* bufs[2] = {bufA, bufB};
   int pb = 0;
-  for (int l = 0; l < d; ++l) {
+  for (int step = 0; step < d; ++step) {
+    const int l = grow >= 0 ? step : d - 1 - step;
     int64_t inner = 1, outer = L;
     for (int k = 0; k < l; ++k) inner *= dims[k];
     for (int k = l + 1; k < d; ++k) outer *= dims[k];
-    const bool last = (l == d - 1);
+    const bool last = (step == d - 1);
     S* out = last ? dst : bufs[pb];
     gather<S, S, C>(Ops<S, C>::tab(*tabs[l]), cur, out, outer, inner, dims[l], 0, last ? alpha : C(1), last ? beta : C(0), s);
     dims[l] = out_dims[l];
@@ -532,6 +576,7 @@ void apply_impl(st_iga_ctx* c, const S* x, S* y, int L, int in_base, bool with_s
   // spatial constant part: SM = (M_d..M_1) x, SK = K_s x
   S* SM;
   S* SK;
+  kprof_gather_class(K_BANDED);
   if (d == 1) {
     gather<S, S, C>(Ops<S, C>::tab(c->Ms[0]), x, a, L, 1, nn[0], 0, C(1), C(0), s);
     gather<S, S, C>(Ops<S, C>::tab(c->Ks[0]), x, b, L, 1, nn[0], 0, C(P.sigma[0]), C(0), s);
@@ -564,6 +609,8 @@ void apply_impl(st_iga_ctx* c, const S* x, S* y, int L, int in_base, bool with_s
   // low-rank coefficient terms
   const int r0 = with_su ? 0 : c->Rth;
   const int r1 = with_react ? c->Rth + c->Rc : c->Rth;
+  kprof_gather_class(K_EXPAND);
+  struct Reset { ~Reset() { kprof_gather_class(K_GATHER); } } reset_cls;
   if (r1 <= r0) return;
   const Tab* ex[3] = {&c->Bq[0][0], &c->Bq[1][0], &c->Bq[2][0]};
   const Tab* pr[3] = {&c->BqT[0], &c->BqT[1], &c->BqT[2]};
@@ -591,30 +638,52 @@ void apply_impl(st_iga_ctx* c, const S* x, S* y, int L, int in_base, bool with_s
 // The time-mix kernel indexes inputs by full time index minus in_base; for
 // unknown vectors (layer k = full index k+1) in_base = 1, for full vectors 0.
 
+template <class C>
+const C* dmat(const st_iga_ctx::Dense& D);
+template <>
+const double* dmat<double>(const st_iga_ctx::Dense& D) { return D.d; }
+template <>
+const float* dmat<float>(const st_iga_ctx::Dense& D) { return D.f; }
+
+// Dense matrices along every spatial axis: x [L][n_d..n_1] -> dst; intermediates alternate bufA/bufB.
+template <class S, class C>
+void dense_spatial(st_iga_ctx* c, const st_iga_ctx::Dense* const* M, const S* x, int64_t L, S* bufA, S* bufB, S* dst,
+                   hipStream_t s) {
+  const int d = c->d;
+  const S* cur = x;
+  S* bufs[2] = {bufA, bufB};
+  int pb = 0;
+  for (int l = 0; l < d; ++l) {
+    int64_t inner = 1, outer = L;
+    for (int k = 0; k < l; ++k) inner *= c->n[k];
+    for (int k = l + 1; k < d; ++k) outer *= c->n[k];
+    S* out = (l == d - 1) ? dst : bufs[pb];
+    dense_mode<S, C>(dmat<C>(*M[l]), M[l]->n, M[l]->npad, cur, out, outer, inner, s);
+    cur = out;
+    pb ^= 1;
+  }
+}
+
 template <class S, class C>
 void precond_impl(st_iga_ctx* c, const S* r, S* z, Bufs<S>& B, hipStream_t s) {
-  const int d = c->d;
   const int64_t Ns = c->Ns;
   const int Nt = c->Nt;
-  const Tab* UT[3] = {&c->UsT[0], &c->UsT[1], &c->UsT[2]};
-  const Tab* U[3] = {&c->Us[0], &c->Us[1], &c->Us[2]};
-  const int nn[3] = {c->n[0], c->n[1], c->n[2]};
+  const st_iga_ctx::Dense* UT[3] = {&c->DUsT[0], &c->DUsT[1], &c->DUsT[2]};
+  const st_iga_ctx::Dense* U[3] = {&c->DUs[0], &c->DUs[1], &c->DUs[2]};
   S *a = B.t4[0], *b = B.t4[1], *e = B.t4[2];
   // spatial forward transforms: a = (U_d^T .. U_1^T) r
-  if (d == 1) gather<S, S, C>(Ops<S, C>::tab(*UT[0]), r, a, Nt, 1, nn[0], 0, C(1), C(0), s);
-  else spatial_chain<S, C>(c, UT, r, Nt, nn, nn, b, e, a, C(1), C(0), s);
+  dense_spatial<S, C>(c, UT, r, Nt, b, e, a, s);
   // time forward: b = U_t^T a
-  gather<S, S, C>(Ops<S, C>::tab(c->UtT), a, b, 1, Ns, Nt, 0, C(1), C(0), s);
+  dense_mode<S, C>(dmat<C>(c->DUtT), Nt, c->DUtT.npad, a, b, 1, Ns, s);
   // arrowhead core
   const C* lam = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->lam_d) : reinterpret_cast<const C*>(c->lam_f);
   const C* mu = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->mu_d) : reinterpret_cast<const C*>(c->mu_f);
   const C* l = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->l_d) : reinterpret_cast<const C*>(c->l_f);
   arrowhead<S, C>(b, a, lam, mu, c->kind_d, l, C(c->fd.sigma), C(c->P.Cm), Nt, Ns, s);
   // time backward: b = U_t a
-  gather<S, S, C>(Ops<S, C>::tab(c->Ut), a, b, 1, Ns, Nt, 0, C(1), C(0), s);
+  dense_mode<S, C>(dmat<C>(c->DUt), Nt, c->DUt.npad, a, b, 1, Ns, s);
   // spatial backward: z = (U_d .. U_1) b
-  if (d == 1) gather<S, S, C>(Ops<S, C>::tab(*U[0]), b, z, Nt, 1, nn[0], 0, C(1), C(0), s);
-  else spatial_chain<S, C>(c, U, b, Nt, nn, nn, a, e, z, C(1), C(0), s);
+  dense_spatial<S, C>(c, U, b, Nt, a, e, z, s);
 }
 
 Bufs<double> bufs64(st_iga_ctx* c) {
@@ -1427,6 +1496,38 @@ st_iga_status st_iga_solve(st_iga_ctx* c, const st_iga_stimulus* stim, double* u
     if (rep) *rep = R;
     if (!converged) throw Fail{ST_IGA_ENOCONV, "outer iteration limit reached"};
   });
+}
+
+st_iga_status st_iga_newton_step(st_iga_ctx* c, const double* u_in, double* u_out, double* w, int32_t refresh_theta,
+                                 double tol, int32_t* iters, double* relres, double* delta_inf, void* stream) {
+  if (!c || !u_in || !u_out || !w || !(tol > 0)) return ST_IGA_EINVAL;
+  return guard(c, [&] {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (u_out != u_in) CK(hipMemcpyAsync(u_out, u_in, c->nfull * sizeof(double), hipMemcpyDeviceToDevice, s));
+    w_update(c, u_out, w, s);
+    if (!c->linearized && c->opt.su && !refresh_theta) throw Fail{ST_IGA_ESTATE, "theta has never been computed"};
+    linearize(c, u_out, w, refresh_theta != 0, s);
+    residual(c, u_out, w, c->sol_rhs, s);
+    axpby(-1.0, c->sol_rhs, 0.0, c->sol_rhs, c->nunk, s);
+    double rr = 1.0;
+    const int it = krylov(c, c->sol_rhs, c->sol_dx, tol, &rr, s);
+    add_unknowns(u_out, c->sol_dx, c->opt.alpha, c->nunk, c->Ns, s);
+    const double dinf = c->opt.alpha * dev_absmax(c, c->sol_dx, c->nunk, s);
+    if (iters) *iters = it;
+    if (relres) *relres = rr;
+    if (delta_inf) *delta_inf = dinf;
+  });
+}
+
+st_iga_status st_iga_profile(st_iga_ctx* c, int32_t enable) {
+  if (!c) return ST_IGA_EINVAL;
+  kprof_enable(enable != 0);
+  return ST_IGA_OK;
+}
+
+st_iga_status st_iga_profile_read(st_iga_ctx* c, int32_t cls, double* ms, int64_t* launches, int32_t reset) {
+  if (!c || cls < 0 || cls >= K_NCLASS) return ST_IGA_EINVAL;
+  return guard(c, [&] { kprof_read(cls, ms, launches, reset); });
 }
 
 st_iga_status st_iga_sizes(const st_iga_ctx* c, int64_t* o) {
