@@ -67,20 +67,6 @@ def time_region(torch, S, u1, u2, w, steps, warmup, tol):
     return ev0.elapsed_time(ev1) / steps, wall / steps * 1e3, its, rr, prof
 
 
-def kernel_bytes(S, prob, prec_bytes):
-    """Algorithmic bytes of one launch of the low-rank time-mixing kernel:
-    read Z ((N_t) layers x Q_s), the spatial factors (R x Q_s), write N_t x Q_s."""
-    (ft, fc) = S.get_factors()
-    R = len(ft[1]) + len(fc[1])
-    Qs = 1
-    for n in prob.nel_s:
-        Qs *= (prob.p_s + 1) * n
-    Nt = prob.N_t
-    by = (Nt + R + Nt) * Qs * prec_bytes
-    fl = Nt * Qs * (R * 2 * (2 * prob.p_t + 1) + 2 * R)
-    return by, fl, R
-
-
 def cpu_baseline(cfg):
     """The oracle as it stands on the host cores: one Newton step (explicit
     assembly + sparse LU) of the same physics on a reduced mesh."""
@@ -148,18 +134,19 @@ def main():
     main_r = res[a.prec]
     ms = main_r["ms"]
     value = prob.dof / (ms / 1e3)
-    # dominant kernel class over the timed region
+    # dominant kernel function over the timed region, achieved bandwidth from
+    # the algorithmic bytes the library records per launch
     prof = main_r["prof"]
-    dom = max(prof.items(), key=lambda kv: kv[1][0])
-    tm_ms, tm_n = prof["time_mix"]
-    by, fl, R = kernel_bytes(main_r["S"], prob, prec_bytes)
-    achieved = by / (tm_ms / tm_n / 1e3) if tm_n else None
-    roof = {"kernel": "time_mix (low-rank SU + reaction terms at the spatial Gauss points)",
-            "bound": "hbm", "achieved": achieved / 1e9 if achieved else None, "peak": PEAK_HBM / 1e9,
-            "unit": "GB/s", "frac": (achieved / PEAK_HBM) if achieved else None, "traffic": None,
-            "avg_launch_ms": tm_ms / tm_n if tm_n else None, "launches": tm_n,
-            "alg_bytes_per_launch": by, "rank_total": R,
-            "dominant_class": dom[0], "class_ms_per_step": {k: v[0] / a.steps for k, v in prof.items()}}
+    fns = {k: v for k, v in prof.items() if k.startswith("fn:") and v[1] > 0}
+    dom_name, (dom_ms, dom_n, dom_by) = max(fns.items(), key=lambda kv: kv[1][0])
+    achieved = dom_by / (dom_ms / 1e3)
+    roof = {"kernel": dom_name[3:], "bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
+            "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": None,
+            "avg_launch_ms": dom_ms / dom_n, "launches": dom_n, "alg_bytes_per_launch": dom_by / dom_n,
+            "kernels": {k[3:]: {"ms_per_step": v[0] / a.steps, "launches_per_step": v[1] / a.steps,
+                                "GB_per_s": (v[2] / (v[0] / 1e3) / 1e9) if v[0] > 0 else None}
+                        for k, v in sorted(fns.items(), key=lambda kv: -kv[1][0])},
+            "purpose_ms_per_step": {k: v[0] / a.steps for k, v in prof.items() if not k.startswith("fn:")}}
     out = {
         "metric": "space-time DOF/s to rel. residual 1e-8 (mixed vs FP64); p50/p99 solve latency",
         "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -175,6 +162,27 @@ def main():
         "wall_ms_per_step": main_r["wall"],
         "roofline": roof,
     }
+    # linear solve alone (the Krylov part of the step), same system
+    solve = {}
+    for name, r in res.items():
+        S = r["S"]
+        S.linearize(u1, w, True)
+        b = -S.residual(u1, w)
+        x = S.vec()
+        for _ in range(a.warmup):
+            S.krylov(b, a.tol, x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            _, its, rr = S.krylov(b, a.tol, x)
+        e1.record()
+        torch.cuda.synchronize()
+        sm = e0.elapsed_time(e1) / a.steps
+        solve[name] = {"ms": sm, "dof_per_s": prob.dof / (sm / 1e3), "krylov_iters": its, "relres": rr}
+    if len(solve) == 2:
+        solve["speedup_mixed_vs_fp64"] = solve["fp64"]["ms"] / solve[a.prec]["ms"]
+    out["linear_solve_only"] = solve
     if "fp64" in res and a.prec != "fp64":
         f = res["fp64"]
         out["fp64_dof_per_s"] = prob.dof / (f["ms"] / 1e3)

@@ -47,7 +47,7 @@ typedef enum {
 typedef enum {
   ST_IGA_FP64 = 0,        /* every kernel in FP64 */
   ST_IGA_MIXED_FP32 = 1,  /* apply/precond in FP32 inside FP64 FGMRES + iterative refinement */
-  ST_IGA_MIXED_BF16 = 2   /* apply/precond with BF16 storage, FP32 arithmetic, same FP64 loop */
+  ST_IGA_MIXED_BF16 = 2   /* FP32 apply, preconditioner with BF16 storage and FP32 arithmetic, same FP64 loop */
 } st_iga_precision;
 
 /* Problem statement, paper Section 3, eq. (3.1), and Section 2 (knots).
@@ -159,6 +159,14 @@ st_iga_status st_iga_apply(st_iga_ctx* ctx, const double* x, double* y, void* st
  * eq. (3.10)-(3.11) with sigma-scaled stiffness.  Asynchronous. */
 st_iga_status st_iga_precond(st_iga_ctx* ctx, const double* r, double* z, void* stream);
 
+/* The same two operators in the context's low precision (FP32; in BF16 mode
+ * the preconditioner uses BF16 storage with FP32 arithmetic and the operator
+ * stays FP32): FP64 in and out, converted at the boundary.
+ * These are the operators of the inner FGMRES of a mixed-precision solve.
+ * EINVAL for an FP64 context.  Asynchronous. */
+st_iga_status st_iga_apply_lowp(st_iga_ctx* ctx, const double* x, double* y, void* stream);
+st_iga_status st_iga_precond_lowp(st_iga_ctx* ctx, const double* r, double* z, void* stream);
+
 /* Residual N(u) (unknown-sized output) of eq. (3.2) at full vectors (u, w) with
  * the current low-rank theta and the exact ionic current at the Gauss points. */
 st_iga_status st_iga_residual(st_iga_ctx* ctx, const double* u, const double* w, double* r,
@@ -198,11 +206,17 @@ st_iga_status st_iga_newton_step(st_iga_ctx* ctx, const double* u_in, double* u_
  * update+norm, 5 pointwise ionic quadrature, 6 element/window maxima,
  * 7 banded mode products (constant part of the operator), 8 spline
  * expansion/projection at Gauss points, 9 dense eigenvector mode products of
- * the preconditioner.  profile_read returns the summed duration (ms) and the
- * launch count since the last reset and synchronizes the recorded events. */
+ * the preconditioner.  Classes 100 + f + 16 q select one kernel function f
+ * (0 scalar gather, 1 4-wide gather, 2 LDS row gather, 3 time mixing,
+ * 4 MFMA dense mode product, 5 arrowhead, 6 multi-dot, 7 update+norm,
+ * 8 pointwise ionic, 9 maxima) in storage precision q (0 FP64, 1 FP32,
+ * 2 BF16; the reductions are FP64 only).  profile_read returns the summed duration (ms), the
+ * launch count and the summed algorithmic bytes (each input and output array
+ * counted once per launch) since the last reset, and synchronizes the
+ * recorded events.  Any output pointer may be NULL. */
 st_iga_status st_iga_profile(st_iga_ctx* ctx, int32_t enable);
 st_iga_status st_iga_profile_read(st_iga_ctx* ctx, int32_t kernel_class, double* ms, int64_t* launches,
-                                  int32_t reset);
+                                  double* bytes, int32_t reset);
 
 /* Lifted initial datum (N_s entries, HOST output) and the number of spatial
  * Greville points inside the stimulus. */

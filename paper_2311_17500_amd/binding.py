@@ -23,7 +23,7 @@ EXPORTS = ["st_iga_default_options", "st_iga_workspace_bytes", "st_iga_setup", "
            "st_iga_set_factors", "st_iga_get_factors", "st_iga_theta_grid", "st_iga_apply", "st_iga_precond",
            "st_iga_residual", "st_iga_w_update", "st_iga_krylov", "st_iga_solve", "st_iga_lift", "st_iga_sizes",
            "st_iga_destroy", "st_iga_last_error", "st_iga_host_query", "st_iga_newton_step", "st_iga_profile",
-           "st_iga_profile_read"]
+           "st_iga_profile_read", "st_iga_apply_lowp", "st_iga_precond_lowp"]
 
 
 class Problem(C.Structure):
@@ -83,6 +83,8 @@ def load(path: str = LIB_PATH):
     lib.st_iga_theta_grid.argtypes = [P, V, V, V, V]
     lib.st_iga_apply.argtypes = [P, V, V, V]
     lib.st_iga_precond.argtypes = [P, V, V, V]
+    lib.st_iga_apply_lowp.argtypes = [P, V, V, V]
+    lib.st_iga_precond_lowp.argtypes = [P, V, V, V]
     lib.st_iga_residual.argtypes = [P, V, V, V, V]
     lib.st_iga_w_update.argtypes = [P, V, V, V]
     lib.st_iga_krylov.argtypes = [P, V, V, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double), V]
@@ -95,7 +97,8 @@ def load(path: str = LIB_PATH):
     lib.st_iga_newton_step.argtypes = [P, V, V, V, C.c_int32, C.c_double, C.POINTER(C.c_int32),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double), V]
     lib.st_iga_profile.argtypes = [P, C.c_int32]
-    lib.st_iga_profile_read.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
+    lib.st_iga_profile_read.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                        C.POINTER(C.c_double), C.c_int32]
     lib.st_iga_host_query.argtypes = [C.POINTER(Problem), C.c_int32, C.c_int32, V, C.c_int64, C.POINTER(C.c_int64)]
     for name in EXPORTS:
         if name not in ("st_iga_default_options", "st_iga_workspace_bytes", "st_iga_last_error"):
@@ -240,6 +243,16 @@ class Solver:
         self._chk(self.lib.st_iga_precond(self.ctx, self._p(r), self._p(z), self._s()))
         return z
 
+    def apply_lowp(self, x, y=None):
+        y = self.vec() if y is None else y
+        self._chk(self.lib.st_iga_apply_lowp(self.ctx, self._p(x), self._p(y), self._s()))
+        return y
+
+    def precond_lowp(self, r, z=None):
+        z = self.vec() if z is None else z
+        self._chk(self.lib.st_iga_precond_lowp(self.ctx, self._p(r), self._p(z), self._s()))
+        return z
+
     def residual(self, u, w):
         r = self.vec()
         self._chk(self.lib.st_iga_residual(self.ctx, self._p(u), self._p(w), self._p(r), self._s()))
@@ -270,14 +283,23 @@ class Solver:
         self._chk(self.lib.st_iga_profile(self.ctx, int(on)))
 
     def profile_read(self, reset=True):
+        """{class: (ms, launches, algorithmic bytes)} since the last reset."""
         out = {}
         for k, name in enumerate(self.KCLASSES):
-            ms, n = C.c_double(0), C.c_int64(0)
-            self._chk(self.lib.st_iga_profile_read(self.ctx, k, C.byref(ms), C.byref(n), 0))
-            out[name] = (ms.value, n.value)
+            ms, n, by = C.c_double(0), C.c_int64(0), C.c_double(0)
+            self._chk(self.lib.st_iga_profile_read(self.ctx, k, C.byref(ms), C.byref(n), C.byref(by), 0))
+            out[name] = (ms.value, n.value, by.value)
+        fnames = ["gather_scalar", "gather_v4", "gather_rows", "time_mix", "dense_mode_mfma", "arrowhead",
+                  "multidot", "update_norm", "pointwise_ionic", "mode_max"]
+        for q, pn in enumerate(["f64", "f32", "bf16"]):
+            for f, fname in enumerate(fnames):
+                ms, n, by = C.c_double(0), C.c_int64(0), C.c_double(0)
+                self._chk(self.lib.st_iga_profile_read(self.ctx, 100 + f + 16 * q, C.byref(ms), C.byref(n),
+                                                       C.byref(by), 0))
+                if n.value:
+                    out[f"fn:{fname}<{pn}>"] = (ms.value, n.value, by.value)
         if reset:
-            ms, n = C.c_double(0), C.c_int64(0)
-            self._chk(self.lib.st_iga_profile_read(self.ctx, 0, C.byref(ms), C.byref(n), 1))
+            self._chk(self.lib.st_iga_profile_read(self.ctx, 0, None, None, None, 1))
         return out
 
     def lift(self):

@@ -58,7 +58,13 @@ struct ProfState {
   int gather_cls = 0;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> rec;
+  struct Rec {
+    int cls;   // purpose class
+    int fn;    // kernel function id + 16 * precision (0 f64, 1 f32, 2 bf16)
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<Rec> rec;
 };
 ProfState& prof() {
   static ProfState p;
@@ -74,11 +80,13 @@ hipEvent_t prof_event() {
   return p.pool[p.used++];
 }
 // RAII bracket around one launch
+template <class S> constexpr int prec_code() { return std::is_same<S, double>::value ? 0 : (std::is_same<S, float>::value ? 1 : 2); }
 struct ProfScope {
-  int cls;
+  int cls, fn;
   hipStream_t s;
   hipEvent_t a = nullptr;
-  ProfScope(int c, hipStream_t st) : cls(c), s(st) {
+  double bytes;
+  ProfScope(int c, int f, hipStream_t st, double by) : cls(c), fn(f), s(st), bytes(by) {
     if (prof().on) {
       a = prof_event();
       if (a) hipEventRecord(a, s);
@@ -89,7 +97,7 @@ struct ProfScope {
       hipEvent_t b = prof_event();
       if (b) {
         hipEventRecord(b, s);
-        prof().rec.push_back({cls, {a, b}});
+        prof().rec.push_back({cls, fn, a, b, bytes});
       }
     }
   }
@@ -669,7 +677,8 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
             C beta, hipStream_t s) {
   const int64_t total = outer * t.n_out * inner;
   if (total == 0) return;
-  ProfScope ps(prof().gather_cls, s);
+  const double gbytes = static_cast<double>(outer) * n_in * inner * sizeof(Ti) +
+                        static_cast<double>(total) * sizeof(To) * (beta != C(0) ? 2 : 1);
   const int64_t nrows = outer * t.n_out;
   if (std::is_same<Ti, To>::value && inner % 4 == 0 && inner < (static_cast<int64_t>(1) << 31) &&
       (reinterpret_cast<uintptr_t>(x) % (4 * sizeof(Ti))) == 0 && (reinterpret_cast<uintptr_t>(y) % (4 * sizeof(To))) == 0) {
@@ -678,6 +687,7 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
     const int64_t kchunks = rpb > 1 ? 1 : (slots + TPB - 1) / TPB;
     const int64_t blocks = rpb > 1 ? (nrows + rpb - 1) / rpb : kchunks * nrows;
     if (blocks < (static_cast<int64_t>(1) << 31) && nrows < (static_cast<int64_t>(1) << 32)) {
+      ProfScope ps(prof().gather_cls, 1 + 16 * prec_code<Ti>(), s, gbytes);
       hipLaunchKernelGGL((k_gather_v4<Ti, C>), dim3(static_cast<unsigned>(blocks)), dim3(TPB), 0, s, t.col, t.coef,
                          t.W, t.n_out, x, reinterpret_cast<Ti*>(y), static_cast<uint32_t>(inner), n_in, in_base, alpha,
                          beta, static_cast<uint32_t>(nrows), static_cast<uint32_t>(slots), static_cast<uint32_t>(rpb),
@@ -692,11 +702,13 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
     const int64_t blocks = (outer + RB - 1) / RB;
     const size_t sh = static_cast<size_t>(RB) * n_in * sizeof(C);
     if (blocks < (static_cast<int64_t>(1) << 31) && sh <= 48 * 1024) {
+      ProfScope ps(prof().gather_cls, 2 + 16 * prec_code<Ti>(), s, gbytes);
       hipLaunchKernelGGL((k_gather_rows<Ti, C>), dim3(static_cast<unsigned>(blocks)), dim3(TPB), sh, s, t.col, t.coef,
                          t.W, t.n_out, x, reinterpret_cast<Ti*>(y), n_in, in_base, alpha, beta, outer, RB);
       return;
     }
   }
+  ProfScope ps(prof().gather_cls, 0 + 16 * prec_code<Ti>(), s, gbytes);
   if (total < (static_cast<int64_t>(1) << 32))
     hipLaunchKernelGGL((k_gather<Ti, To, C, uint32_t>), dim3(grid_for(total)), dim3(TPB), 0, s, t.col, t.coef, t.W,
                        t.n_out, x, y, static_cast<uint32_t>(inner), n_in, in_base, alpha, beta,
@@ -721,7 +733,7 @@ void mode_max(const int* start, const int* cnt, int n_out, const double* x, doub
               int n_in, hipStream_t s) {
   const int64_t total = outer * n_out * inner;
   if (total == 0) return;
-  ProfScope ps(K_MAX, s);
+  ProfScope ps(K_MAX, 9, s, static_cast<double>(outer) * (n_in + n_out) * inner * sizeof(double));
   hipLaunchKernelGGL(k_mode_max, dim3(grid_for(total)), dim3(TPB), 0, s, start, cnt, n_out, x, y, inner, n_in, total);
 }
 
@@ -733,7 +745,7 @@ void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int p, const S* 
   while (tpb > 64 && static_cast<size_t>(R) * tpb * sizeof(C) > 64 * 1024) tpb /= 2;
   const size_t sh = static_cast<size_t>(R > 0 ? R : 1) * tpb * sizeof(C);
   const dim3 g(grid_for(Qs, tpb)), b(tpb);
-  ProfScope ps(K_TIME_MIX, s);
+  ProfScope ps(K_TIME_MIX, 3 + 16 * prec_code<S>(), s, (static_cast<double>(n_in) + R + Nt) * Qs * sizeof(S));
   switch (p) {
     case 1: hipLaunchKernelGGL((k_time_mix<S, C, 1>), g, b, sh, s, T, Psi, r0, R, Nt, Z, n_in, in_base, out, Qs); break;
     case 2: hipLaunchKernelGGL((k_time_mix<S, C, 2>), g, b, sh, s, T, Psi, r0, R, Nt, Z, n_in, in_base, out, Qs); break;
@@ -752,7 +764,7 @@ void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, i
   const int NT = npad / 16;
   const size_t abytes = static_cast<size_t>(npad) * npad * sizeof(C);
   const bool lds = abytes <= 64 * 1024;
-  ProfScope ps(K_DENSE, s);
+  ProfScope ps(K_DENSE, 4 + 16 * prec_code<S>(), s, 2.0 * ncols * n * sizeof(S));
 #define DM_CASE(nt)                                                                                          \
   case nt:                                                                                                   \
     if (lds) hipLaunchKernelGGL((k_dense_mode<S, C, nt, true>), dim3(grid), dim3(256), abytes, s, Ap, n, npad, x, y, inner, ncols); \
@@ -768,28 +780,30 @@ void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, i
 template <class S, class C>
 void arrowhead(const S* r, S* y, const C* lam, const C* mu, const int* kind, const C* l, C sigma, C Cm, int Nt,
                int64_t Ns, hipStream_t s) {
-  ProfScope ps(K_ARROW, s);
+  ProfScope ps(K_ARROW, 5 + 16 * prec_code<S>(), s, 2.0 * Nt * Ns * sizeof(S));
   hipLaunchKernelGGL((k_arrowhead<S, C>), dim3(grid_for(Ns)), dim3(TPB), 0, s, r, y, lam, mu, kind, l, sigma, Cm, Nt, Ns);
 }
 
 void kprof_enable(bool on) { prof().on = on; }
 void kprof_gather_class(int cls) { prof().gather_cls = cls; }
 
-void kprof_read(int cls, double* ms, int64_t* launches, int reset) {
+void kprof_read(int cls, double* ms, int64_t* launches, double* bytes, int reset) {
   ProfState& p = prof();
-  double tot = 0.0;
+  double tot = 0.0, by = 0.0;
   int64_t n = 0;
   for (auto& r : p.rec) {
-    if (r.first != cls) continue;
-    hipEventSynchronize(r.second.second);
+    if (cls < 100 ? r.cls != cls : r.fn != cls - 100) continue;
+    hipEventSynchronize(r.b);
     float t = 0.0f;
-    if (hipEventElapsedTime(&t, r.second.first, r.second.second) == hipSuccess) tot += t;
+    if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) tot += t;
+    by += r.bytes;
     ++n;
   }
   if (ms) *ms = tot;
   if (launches) *launches = n;
+  if (bytes) *bytes = by;
   if (reset) {
-    for (auto& r : p.rec) hipEventSynchronize(r.second.second);
+    for (auto& r : p.rec) hipEventSynchronize(r.b);
     p.rec.clear();
     p.used = 0;
   }
@@ -799,7 +813,7 @@ int reduce_blocks(int64_t n) { return static_cast<int>((n + RED_CHUNK - 1) / RED
 
 void multidot_partial(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* part, int nb,
                       hipStream_t s) {
-  ProfScope ps(K_MULTIDOT, s);
+  ProfScope ps(K_MULTIDOT, 6, s, (k + 1.0) * n * sizeof(double));
   hipLaunchKernelGGL(k_multidot, dim3(nb), dim3(TPB), 0, s, V, ldv, k, w, n, part);
 }
 void finalize_sum(const double* part, int nb, int k, double* out, hipStream_t s) {
@@ -807,7 +821,7 @@ void finalize_sum(const double* part, int nb, int k, double* out, hipStream_t s)
 }
 void update_norm_partial(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t n, double* part,
                          int nb, hipStream_t s) {
-  ProfScope ps(K_UPDATE, s);
+  ProfScope ps(K_UPDATE, 7, s, (k + 2.0) * n * sizeof(double));
   hipLaunchKernelGGL(k_update_norm, dim3(nb), dim3(TPB), 0, s, V, ldv, k, h, w, n, part);
 }
 void absmax_partial(const double* x, int64_t n, double* part, int nb, hipStream_t s) {
@@ -843,7 +857,7 @@ void pointwise_ionic(const double* u, const double* ut, const double* lap, const
                      double* g, double* absR, double* part, int nb, hipStream_t s) {
   const int64_t total = Qs * nq_t;
   (void)nb;
-  ProfScope ps(K_POINTWISE, s);
+  ProfScope ps(K_POINTWISE, 8, s, 6.0 * total * sizeof(double));
   hipLaunchKernelGGL(k_pointwise_ionic, dim3(grid_for(total)), dim3(TPB), 0, s, u, ut, lap, w, wt_time, wt_space, Qs,
                      total, Cm, a, c1, c2, g, absR, part);
 }

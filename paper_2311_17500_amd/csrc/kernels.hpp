@@ -19,9 +19,9 @@ enum KClass { K_GATHER = 0, K_TIME_MIX, K_ARROW, K_MULTIDOT, K_UPDATE, K_POINTWI
 void kprof_enable(bool on);
 // class recorded for gather launches until changed (K_GATHER by default)
 void kprof_gather_class(int cls);
-// Sum of launch durations (ms) and launch count of a class since the last reset;
+// Sum of launch durations (ms), launch count and algorithmic bytes of a class since the last reset;
 // synchronizes the recorded events.  Resets when reset != 0.
-void kprof_read(int cls, double* ms, int64_t* launches, int reset);
+void kprof_read(int cls, double* ms, int64_t* launches, double* bytes, int reset);
 
 // Device view of a gather table: y[i] = sum_w coef[i*W+w] * x[col[i*W+w] - in_base],
 // terms with the input index outside [0, n_in) skipped.

@@ -105,12 +105,11 @@ struct st_iga_ctx {
   double *Vth = nullptr, *Vc = nullptr;          // device N_s x maxR
   double *Psi = nullptr, *Tr = nullptr;
   float *Psi_f = nullptr, *Tr_f = nullptr;
-  bf16* Psi_b = nullptr;
   bool linearized = false;
   // buffers
   double *t4[4] = {}, *big[2] = {};
   float *t4f[4] = {}, *bigf[2] = {}, *xf = nullptr, *yf = nullptr;
-  bf16 *t4b[4] = {}, *bigb[2] = {}, *xb = nullptr, *yb = nullptr;
+  bf16 *t4b[4] = {}, *xb = nullptr, *yb = nullptr;
   double *Vk = nullptr, *Zk = nullptr, *rk = nullptr, *xk = nullptr, *wk = nullptr, *dk = nullptr, *bk = nullptr;
   double *VT = nullptr, *sol_rhs = nullptr, *sol_dx = nullptr;
   double *grid = nullptr, *grid2 = nullptr, *E = nullptr, *rfull = nullptr, *Cg = nullptr;
@@ -409,18 +408,16 @@ void plan(st_iga_ctx* c) {
   c->gram = a.get<double>(static_cast<int64_t>(c->gram_nb) * c->Nt * c->Nt);
   c->tmpR = a.get<double>(static_cast<int64_t>(c->Nt) * c->maxR + 2 * c->maxR);
   if (mixed) {
+    // low-precision operator: FP32 in both mixed modes
     c->Psi_f = a.get<float>(static_cast<int64_t>(R2) * c->Qs);
-    if (bf) {
-      c->Psi_b = a.get<bf16>(static_cast<int64_t>(R2) * c->Qs);
+    for (int k = 0; k < 4; ++k) c->t4f[k] = a.get<float>(c->nfull);
+    for (int k = 0; k < 2; ++k) c->bigf[k] = a.get<float>(c->big_len);
+    c->xf = a.get<float>(c->nunk);
+    c->yf = a.get<float>(c->nunk);
+    if (bf) {  // BF16-storage preconditioner
       for (int k = 0; k < 4; ++k) c->t4b[k] = a.get<bf16>(c->nfull);
-      for (int k = 0; k < 2; ++k) c->bigb[k] = a.get<bf16>(c->big_len);
       c->xb = a.get<bf16>(c->nunk);
       c->yb = a.get<bf16>(c->nunk);
-    } else {
-      for (int k = 0; k < 4; ++k) c->t4f[k] = a.get<float>(c->nfull);
-      for (int k = 0; k < 2; ++k) c->bigf[k] = a.get<float>(c->big_len);
-      c->xf = a.get<float>(c->nunk);
-      c->yf = a.get<float>(c->nunk);
     }
   }
 }
@@ -844,24 +841,18 @@ void lowp_ops<float>(st_iga_ctx* c, Op& A, Op& Pc, hipStream_t s) {
     convert<float, double>(c->yf, z, c->nunk, s);
   };
 }
+// BF16 mode: the operator stays FP32 (BF16 rounding of the operator makes
+// iterative refinement non-contractive on these systems); the preconditioner's
+// mode products and arrowhead run with BF16 storage and FP32 arithmetic.
 template <>
 void lowp_ops<bf16>(st_iga_ctx* c, Op& A, Op& Pc, hipStream_t s) {
-  A = [c, s](const double* x, double* y) {
-    Bufs<bf16> B;
-    for (int k = 0; k < 4; ++k) B.t4[k] = c->t4b[k];
-    B.big[0] = c->bigb[0];
-    B.big[1] = c->bigb[1];
-    B.Psi = c->Psi_b;
-    convert<double, bf16>(x, c->xb, c->nunk, s);
-    apply_impl<bf16, float>(c, c->xb, c->yb, c->Nt, 1, true, true, B, s);
-    convert<bf16, double>(c->yb, y, c->nunk, s);
-  };
+  Op unused;
+  lowp_ops<float>(c, A, unused, s);
   Pc = [c, s](const double* r, double* z) {
     Bufs<bf16> B;
     for (int k = 0; k < 4; ++k) B.t4[k] = c->t4b[k];
-    B.big[0] = c->bigb[0];
-    B.big[1] = c->bigb[1];
-    B.Psi = c->Psi_b;
+    B.big[0] = B.big[1] = nullptr;
+    B.Psi = nullptr;
     convert<double, bf16>(r, c->xb, c->nunk, s);
     precond_impl<bf16, float>(c, c->xb, c->yb, B, s);
     convert<bf16, double>(c->yb, z, c->nunk, s);
@@ -1149,7 +1140,6 @@ void rebuild_coefficients(st_iga_ctx* c, hipStream_t s) {
   }
   scale_rows(c->Psi, Rt, c->Qs, c->wq_s, s);
   if (c->Psi_f) convert<double, float>(c->Psi, c->Psi_f, static_cast<int64_t>(Rt) * c->Qs, s);
-  if (c->Psi_b) convert<double, bf16>(c->Psi, c->Psi_b, static_cast<int64_t>(Rt) * c->Qs, s);
   // time tables
   std::vector<double> nodes(T.grev.begin() + 1, T.grev.end());
   std::vector<int> left;
@@ -1410,6 +1400,31 @@ st_iga_status st_iga_precond(st_iga_ctx* c, const double* r, double* z, void* st
   });
 }
 
+st_iga_status st_iga_apply_lowp(st_iga_ctx* c, const double* x, double* y, void* stream) {
+  if (!c || !x || !y) return ST_IGA_EINVAL;
+  return guard(c, [&] {
+    ensure_lin(c);
+    if (c->opt.prec == ST_IGA_FP64) throw Fail{ST_IGA_EINVAL, "context has no low-precision operators"};
+    Op A, Pc;
+    if (c->opt.prec == ST_IGA_MIXED_FP32) lowp_ops<float>(c, A, Pc, static_cast<hipStream_t>(stream));
+    else lowp_ops<bf16>(c, A, Pc, static_cast<hipStream_t>(stream));
+    A(x, y);
+    check_launch();
+  });
+}
+
+st_iga_status st_iga_precond_lowp(st_iga_ctx* c, const double* r, double* z, void* stream) {
+  if (!c || !r || !z) return ST_IGA_EINVAL;
+  return guard(c, [&] {
+    if (c->opt.prec == ST_IGA_FP64) throw Fail{ST_IGA_EINVAL, "context has no low-precision operators"};
+    Op A, Pc;
+    if (c->opt.prec == ST_IGA_MIXED_FP32) lowp_ops<float>(c, A, Pc, static_cast<hipStream_t>(stream));
+    else lowp_ops<bf16>(c, A, Pc, static_cast<hipStream_t>(stream));
+    Pc(r, z);
+    check_launch();
+  });
+}
+
 st_iga_status st_iga_residual(st_iga_ctx* c, const double* u, const double* w, double* r, void* stream) {
   if (!c || !u || !w || !r) return ST_IGA_EINVAL;
   return guard(c, [&] {
@@ -1525,9 +1540,10 @@ st_iga_status st_iga_profile(st_iga_ctx* c, int32_t enable) {
   return ST_IGA_OK;
 }
 
-st_iga_status st_iga_profile_read(st_iga_ctx* c, int32_t cls, double* ms, int64_t* launches, int32_t reset) {
-  if (!c || cls < 0 || cls >= K_NCLASS) return ST_IGA_EINVAL;
-  return guard(c, [&] { kprof_read(cls, ms, launches, reset); });
+st_iga_status st_iga_profile_read(st_iga_ctx* c, int32_t cls, double* ms, int64_t* launches, double* bytes,
+                                  int32_t reset) {
+  if (!c || cls < 0 || (cls >= K_NCLASS && (cls < 100 || cls >= 148))) return ST_IGA_EINVAL;
+  return guard(c, [&] { kprof_read(cls, ms, launches, bytes, reset); });
 }
 
 st_iga_status st_iga_sizes(const st_iga_ctx* c, int64_t* o) {

@@ -163,11 +163,11 @@ def random_vector(n: int, seed: int = 0) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal(n)
 
 
-def smooth_state(prob: Problem, seed: int = 0):
+def smooth_state(prob: Problem, seed: int = 0, noise: float = 0.01):
     """A smooth synthetic (u, w) coefficient state of length N_s * n_t each.
 
-    Coefficients are samples of a moving tanh front plus a small seeded
-    perturbation, laid out [time][x_d]...[x_1] (x_1 fastest).  Used to exercise
+    Coefficients are samples of a moving tanh front plus a seeded perturbation
+    of size `noise`, laid out [time][x_d]...[x_1] (x_1 fastest).  Used to exercise
     the linearisation at states that are not the initial guess.
     """
     rng = np.random.default_rng(seed)
@@ -177,7 +177,7 @@ def smooth_state(prob: Problem, seed: int = 0):
     tt = mesh[0]
     r = np.sqrt(sum(m ** 2 for m in mesh[1:]))
     u = 0.5 * (1.0 - np.tanh((r - 0.15 - 0.2 * tt) / 0.05))
-    u = u + 0.01 * rng.standard_normal(u.shape)
+    u = u + noise * rng.standard_normal(u.shape)
     w = 0.05 * tt * u
     return u.reshape(-1), w.reshape(-1)
 
@@ -192,3 +192,14 @@ def random_factors(prob: Problem, R: int, seed: int = 0, scale: float = 1.0):
     V = np.cumsum(rng.standard_normal((prob.N_s, R)), axis=0) / np.sqrt(prob.N_s)
     s = scale * 0.5 ** np.arange(R)
     return U, s, V
+
+
+def coefficient_factors(prob: Problem, R: int, seed: int = 0, base: float = 1.5, spread: float = 0.3):
+    """Low-rank factors of a coefficient field of the shape the linearization
+    produces: a constant level `base` (rank one) plus R-1 smooth random-walk
+    modes of relative size `spread`."""
+    U, s, V = random_factors(prob, max(R - 1, 0), seed, scale=base * spread)
+    U = np.concatenate([np.ones((prob.N_t, 1)), U], axis=1)
+    V = np.concatenate([np.ones((prob.N_s, 1)), V], axis=1)
+    s = np.concatenate([[base], s])
+    return U[:, :R], s[:R], V[:, :R]

@@ -390,3 +390,22 @@ def test_stimulus_greville_counts():
         P = W.config(idx)
         st = SpaceTime(P, mode="tensor")
         assert int(np.sum(st.lift() > 0)) == direct(nel, p, d, 0.1)
+
+
+@pytest.mark.parametrize("d,p,nel", [(1, 2, 6), (2, 3, 4), (3, 2, 3)])
+def test_rowsample_matches_full_apply(d, p, nel):
+    """The row-sampled local-quadrature evaluator equals the full-grid one."""
+    from oracle.rowsample import RowSampler
+    P = W.tiny(d, p, nel)
+    st = SpaceTime(P, mode="tensor")
+    ft, fc = W.random_factors(P, 2, 1), W.random_factors(P, 3, 2, scale=4.0)
+    x = W.random_vector(P.unknowns, 3)
+    full = st.apply_J(x, st.lowrank_at_quad(LowRank(*fc)), st.lowrank_at_quad(LowRank(*ft)))
+    rows = np.random.default_rng(0).choice(P.unknowns, 25, replace=False)
+    rs = RowSampler(P)
+    got = rs.apply_rows(x, rows, theta=ft, coef=fc)
+    assert np.allclose(got, full[rows], rtol=1e-12, atol=1e-12 * np.abs(full).max())
+    # constant reaction, no SU: the preconditioner operator
+    Ahat = st.assemble_precond() @ x
+    got = rs.apply_rows(x, rows, coef_const=P.a * P.c1)
+    assert np.allclose(got, Ahat[rows], rtol=1e-12, atol=1e-12 * np.abs(Ahat).max())
