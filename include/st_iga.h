@@ -209,7 +209,7 @@ st_iga_status st_iga_newton_step(st_iga_ctx* ctx, const double* u_in, double* u_
  * the preconditioner.  Classes 100 + f + 16 q select one kernel function f
  * (0 scalar gather, 1 4-wide gather, 2 LDS row gather, 3 time mixing,
  * 4 MFMA dense mode product, 5 arrowhead, 6 multi-dot, 7 update+norm,
- * 8 pointwise ionic, 9 maxima) in storage precision q (0 FP64, 1 FP32,
+ * 8 pointwise ionic, 9 maxima, 10 column-sweep gather) in storage precision q (0 FP64, 1 FP32,
  * 2 BF16; the reductions are FP64 only).  profile_read returns the summed duration (ms), the
  * launch count and the summed algorithmic bytes (each input and output array
  * counted once per launch) since the last reset, and synchronizes the

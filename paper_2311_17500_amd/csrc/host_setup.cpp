@@ -648,6 +648,42 @@ Gather dense_table(const std::vector<double>& A, int nrow, int ncol, bool transp
   return G;
 }
 
+void make_contiguous(Gather& G, int n_in) {
+  G.c0.clear();
+  const int W = G.W;
+  if (W <= 0 || W > n_in) return;
+  std::vector<int> c0(G.n_out);
+  std::vector<int> col(G.col.size());
+  std::vector<double> coef(G.coef.size(), 0.0);
+  for (int i = 0; i < G.n_out; ++i) {
+    int lo = n_in, hi = -1;
+    for (int w = 0; w < W; ++w) {
+      const size_t o = static_cast<size_t>(i) * W + w;
+      if (G.coef[o] == 0.0) continue;
+      lo = std::min(lo, G.col[o]);
+      hi = std::max(hi, G.col[o]);
+    }
+    if (hi < 0) lo = hi = (i > 0 ? c0[i - 1] : 0);
+    if (hi - lo + 1 > W) return;                       // not representable
+    int start = std::min(std::max(lo, 0), n_in - W);
+    if (start > lo) start = lo;                        // keep every non-zero inside the window
+    if (i > 0 && start < c0[i - 1]) start = std::min(c0[i - 1], lo);
+    if (start + W - 1 < hi || start < 0) return;
+    c0[i] = start;
+    for (int w = 0; w < W; ++w) col[static_cast<size_t>(i) * W + w] = start + w;
+    for (int w = 0; w < W; ++w) {
+      const size_t o = static_cast<size_t>(i) * W + w;
+      if (G.coef[o] == 0.0) continue;
+      coef[static_cast<size_t>(i) * W + (G.col[o] - start)] += G.coef[o];
+    }
+  }
+  for (int i = 1; i < G.n_out; ++i)
+    if (c0[i] < c0[i - 1]) return;                     // windows must not move backwards
+  G.col = col;
+  G.coef = coef;
+  G.c0 = c0;
+}
+
 void hat_weights(const std::vector<double>& nodes, const std::vector<double>& x, std::vector<int>& left,
                  std::vector<double>& wl) {
   const int N = static_cast<int>(nodes.size());

@@ -33,7 +33,14 @@ struct Gather {
   int n_out = 0, W = 0;
   std::vector<int> col;
   std::vector<double> coef;
+  // when every row reads the contiguous columns [c0[i], c0[i] + W) and c0 is
+  // non-decreasing, c0 holds the window starts (empty otherwise)
+  std::vector<int> c0;
 };
+
+// Rewrite each row of G as a contiguous window of W columns inside [0, n_in)
+// (zero coefficients for padding) and fill G.c0 if the windows are monotone.
+void make_contiguous(Gather& G, int n_in);
 
 bool build_dir(const double* knots01, int nk, int p, double scale, int nder, Dir1D& out, std::string& err);
 

@@ -158,14 +158,50 @@ __device__ __forceinline__ void store4<bf16, float>(bf16* p, const float* v) {
   for (int e = 0; e < 4; ++e) p[e] = __float2bfloat16(v[e]);
 }
 
+
+template <int VEC, class S, class C>
+__device__ __forceinline__ void loadv(const S* p, C* v) {
+  if constexpr (VEC == 4) {
+    load4<S, C>(p, v);
+  } else if constexpr (VEC == 1) {
+    v[0] = to_c(p[0], C(0));
+  } else {
+    if constexpr (std::is_same<S, bf16>::value) {
+      v[0] = __bfloat162float(p[0]); v[1] = __bfloat162float(p[1]);
+    } else {
+      typedef typename std::conditional<std::is_same<S, double>::value, double2, float2>::type T2;
+      const T2 t = *reinterpret_cast<const T2*>(p);
+      v[0] = static_cast<C>(t.x); v[1] = static_cast<C>(t.y);
+    }
+  }
+}
+template <int VEC, class S, class C>
+__device__ __forceinline__ void storev(S* p, const C* v) {
+  if constexpr (VEC == 4) {
+    store4<S, C>(p, v);
+  } else if constexpr (VEC == 1) {
+    p[0] = from_c<S>(v[0]);
+  } else {
+    if constexpr (std::is_same<S, bf16>::value) {
+      p[0] = __float2bfloat16(v[0]); p[1] = __float2bfloat16(v[1]);
+    } else {
+      typedef typename std::conditional<std::is_same<S, double>::value, double2, float2>::type T2;
+      T2 t;
+      t.x = static_cast<S>(v[0]); t.y = static_cast<S>(v[1]);
+      *reinterpret_cast<T2*>(p) = t;
+    }
+  }
+}
+
 // Thread t of block b: rows are (o * n_out + i); a row has inner/4 vector
 // slots.  When a row has fewer than TPB slots, a block packs TPB / slots
 // rows; otherwise a row spans kchunks blocks.
-template <class S, class C>
-__global__ void __launch_bounds__(TPB) k_gather_v4(const int* __restrict__ col, const C* __restrict__ coef, int W,
+template <class S, class C, int WC, int VEC>
+__global__ void __launch_bounds__(TPB) k_gather_v4(const int* __restrict__ col, const C* __restrict__ coef, int Wr,
                                                    int n_out, const S* __restrict__ x, S* __restrict__ y,
                                                    uint32_t inner, int n_in, int in_base, C alpha, C beta,
                                                    uint32_t nrows, uint32_t slots, uint32_t rpb, uint32_t kchunks) {
+  const int W = WC > 0 ? WC : Wr;
   uint32_t row, slot;
   if (rpb > 1) {
     row = blockIdx.x * rpb + threadIdx.x / slots;
@@ -177,32 +213,127 @@ __global__ void __launch_bounds__(TPB) k_gather_v4(const int* __restrict__ col, 
     if (slot >= slots) return;
   }
   if (row >= nrows) return;
-  const uint32_t k = slot * 4;
+  const uint32_t k = slot * VEC;
   const int i = static_cast<int>(row % static_cast<uint32_t>(n_out));
   const uint32_t o = row / static_cast<uint32_t>(n_out);
   const int* cr = col + static_cast<int64_t>(i) * W;
   const C* cf = coef + static_cast<int64_t>(i) * W;
   const S* xb = x + (static_cast<int64_t>(o) * n_in) * inner + k;
-  C acc[4] = {C(0), C(0), C(0), C(0)};
-  for (int w = 0; w < W; ++w) {
-    const int c = cr[w] - in_base;
-    if (static_cast<unsigned>(c) < static_cast<unsigned>(n_in)) {
-      C v[4];
-      load4<S, C>(xb + static_cast<int64_t>(c) * inner, v);
-      const C a = cf[w];
-      acc[0] += a * v[0]; acc[1] += a * v[1]; acc[2] += a * v[2]; acc[3] += a * v[3];
+  C acc[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) acc[e] = C(0);
+  if (WC > 0) {
+    // all loads of the row issued before the arithmetic
+    C v[WC > 0 ? WC : 1][VEC];
+    C a[WC > 0 ? WC : 1];
+#pragma unroll
+    for (int w = 0; w < WC; ++w) {
+      const int c = cr[w] - in_base;
+      const bool ok = static_cast<unsigned>(c) < static_cast<unsigned>(n_in);
+      a[w] = ok ? cf[w] : C(0);
+      loadv<VEC, S, C>(xb + static_cast<int64_t>(ok ? c : 0) * inner, v[w]);
+    }
+#pragma unroll
+    for (int w = 0; w < WC; ++w)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[e] += a[w] * v[w][e];
+  } else {
+    for (int w = 0; w < W; ++w) {
+      const int c = cr[w] - in_base;
+      if (static_cast<unsigned>(c) < static_cast<unsigned>(n_in)) {
+        C v[VEC];
+        loadv<VEC, S, C>(xb + static_cast<int64_t>(c) * inner, v);
+        const C a = cf[w];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] += a * v[e];
+      }
     }
   }
   S* yp = y + static_cast<int64_t>(row) * inner + k;
-  C r[4];
+  C r[VEC];
   if (beta != C(0)) {
-    C old[4];
-    load4<S, C>(yp, old);
-    for (int e = 0; e < 4; ++e) r[e] = alpha * acc[e] + beta * old[e];
+    C old[VEC];
+    loadv<VEC, S, C>(yp, old);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) r[e] = alpha * acc[e] + beta * old[e];
   } else {
-    for (int e = 0; e < 4; ++e) r[e] = alpha * acc[e];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) r[e] = alpha * acc[e];
   }
-  store4<S, C>(yp, r);
+  storev<VEC, S, C>(yp, r);
+}
+
+
+// Column sweep for tables whose rows read contiguous, non-decreasing windows
+// [c0[i], c0[i] + W): one thread owns VEC consecutive k of one outer index and
+// a chunk of output rows, keeps the W input rows of the current window in
+// registers and loads each new input row once as the window slides.  Every
+// input row is fetched once per chunk (plus W-1 rows of overlap) and every
+// output once, so the cache traffic equals the algorithmic traffic.
+template <class S, class C, int W, int VEC>
+__global__ void __launch_bounds__(TPB) k_sweep(const int* __restrict__ c0, const C* __restrict__ coef, int n_out,
+                                               const S* __restrict__ x, S* __restrict__ y, uint32_t inner, int n_in,
+                                               int in_base, C alpha, C beta, uint32_t slots, int rc, uint32_t nchunks,
+                                               uint32_t total) {
+  const uint32_t tid = blockIdx.x * TPB + threadIdx.x;
+  if (tid >= total) return;
+  const uint32_t slot = tid % slots;
+  const uint32_t rest = tid / slots;
+  const uint32_t chunk = rest % nchunks;
+  const uint32_t o = rest / nchunks;
+  const int i0 = static_cast<int>(chunk) * rc;
+  const int i1 = min(n_out, i0 + rc);
+  if (i0 >= i1) return;
+  const uint32_t k = slot * VEC;
+  const S* xb = x + static_cast<int64_t>(o) * n_in * inner + k;
+  S* yb = y + static_cast<int64_t>(o) * n_out * inner + k;
+  C ring[W][VEC];
+  int base = c0[i0] - in_base;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const int r = base + w;
+    if (static_cast<unsigned>(r) < static_cast<unsigned>(n_in)) loadv<VEC, S, C>(xb + static_cast<int64_t>(r) * inner, ring[w]);
+    else
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) ring[w][e] = C(0);
+  }
+  for (int i = i0; i < i1; ++i) {
+    const int cb = c0[i] - in_base;
+    while (base < cb) {
+#pragma unroll
+      for (int w = 0; w < W - 1; ++w)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) ring[w][e] = ring[w + 1][e];
+      ++base;
+      const int r = base + W - 1;
+      if (static_cast<unsigned>(r) < static_cast<unsigned>(n_in)) loadv<VEC, S, C>(xb + static_cast<int64_t>(r) * inner, ring[W - 1]);
+      else
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) ring[W - 1][e] = C(0);
+    }
+    const C* cf = coef + static_cast<int64_t>(i) * W;
+    C acc[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[e] = C(0);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const C a = cf[w];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[e] += a * ring[w][e];
+    }
+    S* yp = yb + static_cast<int64_t>(i) * inner;
+    C r[VEC];
+    if (beta != C(0)) {
+      C old[VEC];
+      loadv<VEC, S, C>(yp, old);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) r[e] = alpha * acc[e] + beta * old[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) r[e] = alpha * acc[e];
+    }
+    storev<VEC, S, C>(yp, r);
+  }
 }
 
 // Fastest-axis variant (inner == 1): a block stages RB consecutive input rows
@@ -213,24 +344,29 @@ __global__ void __launch_bounds__(TPB) k_gather_rows(const int* __restrict__ col
                                                      int n_out, const S* __restrict__ x, S* __restrict__ y, int n_in,
                                                      int in_base, C alpha, C beta, int64_t nrows, int RB) {
   extern __shared__ char smem_raw[];
-  C* xs = reinterpret_cast<C*>(smem_raw);
+  C* xs = reinterpret_cast<C*>(smem_raw);                       // RB * n_in
+  C* cs = xs + RB * n_in;                                       // n_out * W coefficients
+  int* is = reinterpret_cast<int*>(cs + n_out * W);             // n_out * W local columns (-1: skip)
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RB;
   const int rb = static_cast<int>(min(static_cast<int64_t>(RB), nrows - r0));
   const S* xb = x + r0 * n_in;
   for (int t = threadIdx.x; t < rb * n_in; t += TPB) xs[t] = to_c(xb[t], C(0));
+  for (int t = threadIdx.x; t < n_out * W; t += TPB) {
+    const int c = col[t] - in_base;
+    const bool ok = static_cast<unsigned>(c) < static_cast<unsigned>(n_in);
+    cs[t] = ok ? coef[t] : C(0);
+    is[t] = ok ? c : 0;
+  }
   __syncthreads();
   S* yb = y + r0 * n_out;
   const int tot = rb * n_out;
   for (int t = threadIdx.x; t < tot; t += TPB) {
     const int r = t / n_out, i = t - r * n_out;
-    const int* cr = col + static_cast<int64_t>(i) * W;
-    const C* cf = coef + static_cast<int64_t>(i) * W;
+    const C* cf = cs + i * W;
+    const int* ci = is + i * W;
     const C* xr = xs + r * n_in;
     C acc = C(0);
-    for (int w = 0; w < W; ++w) {
-      const int c = cr[w] - in_base;
-      if (static_cast<unsigned>(c) < static_cast<unsigned>(n_in)) acc += cf[w] * xr[c];
-    }
+    for (int w = 0; w < W; ++w) acc += cf[w] * xr[ci[w]];
     C v = alpha * acc;
     if (beta != C(0)) v += beta * to_c(yb[t], C(0));
     yb[t] = from_c<S>(v);
@@ -433,26 +569,44 @@ __device__ double block_max(double v, double* sh) {
   return r;
 }
 
-__global__ void __launch_bounds__(TPB) k_multidot(const double* __restrict__ V, int64_t ldv, int k,
-                                                  const double* __restrict__ w, int64_t n, double* __restrict__ part) {
-  __shared__ double sh[TPB / 64];
+template <class T>
+__global__ void __launch_bounds__(TPB) k_multidot(const T* __restrict__ V, int64_t ldv, int k,
+                                                  const T* __restrict__ w, int64_t n, double* __restrict__ part) {
+  // groups of 8 dot products share one block reduction
+  __shared__ double sh[(TPB / 64) * 8];
   const int64_t base = static_cast<int64_t>(blockIdx.x) * RED_CHUNK + threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double wr[RED_E];
 #pragma unroll
   for (int e = 0; e < RED_E; ++e) {
     const int64_t i = base + static_cast<int64_t>(e) * TPB;
-    wr[e] = (i < n) ? w[i] : 0.0;
+    wr[e] = (i < n) ? static_cast<double>(w[i]) : 0.0;
   }
-  for (int j = 0; j < k; ++j) {
-    const double* Vj = V + static_cast<int64_t>(j) * ldv;
-    double acc = 0.0;
+  for (int jg = 0; jg < k; jg += 8) {
+    double acc[8];
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) acc[jj] = 0.0;
 #pragma unroll
     for (int e = 0; e < RED_E; ++e) {
       const int64_t i = base + static_cast<int64_t>(e) * TPB;
-      if (i < n) acc += Vj[i] * wr[e];
+      if (i < n) {
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj)
+          if (jg + jj < k) acc[jj] += static_cast<double>(V[static_cast<int64_t>(jg + jj) * ldv + i]) * wr[e];
+      }
     }
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[static_cast<int64_t>(blockIdx.x) * k + j] = s;
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) acc[jj] = wave_sum(acc[jj]);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) sh[wv * 8 + jj] = acc[jj];
+    __syncthreads();
+    if (threadIdx.x < 8 && jg + static_cast<int>(threadIdx.x) < k) {
+      double s = 0.0;
+      for (int q = 0; q < (TPB / 64); ++q) s += sh[q * 8 + threadIdx.x];
+      part[static_cast<int64_t>(blockIdx.x) * k + jg + threadIdx.x] = s;
+    }
   }
 }
 
@@ -474,8 +628,9 @@ __global__ void __launch_bounds__(TPB) k_finalize_max(const double* __restrict__
   if (threadIdx.x == 0) out[0] = s;
 }
 
-__global__ void __launch_bounds__(TPB) k_update_norm(const double* __restrict__ V, int64_t ldv, int k,
-                                                     const double* __restrict__ h, double* __restrict__ w, int64_t n,
+template <class T>
+__global__ void __launch_bounds__(TPB) k_update_norm(const T* __restrict__ V, int64_t ldv, int k,
+                                                     const double* __restrict__ h, T* __restrict__ w, int64_t n,
                                                      double* __restrict__ part) {
   __shared__ double sh[TPB / 64];
   __shared__ double hs[128];
@@ -486,10 +641,11 @@ __global__ void __launch_bounds__(TPB) k_update_norm(const double* __restrict__ 
   for (int e = 0; e < RED_E; ++e) {
     const int64_t i = base + static_cast<int64_t>(e) * TPB;
     if (i >= n) break;
-    double v = w[i];
-    for (int j = 0; j < k; ++j) v -= hs[j] * V[static_cast<int64_t>(j) * ldv + i];
-    w[i] = v;
-    acc += v * v;
+    double v = static_cast<double>(w[i]);
+    for (int j = 0; j < k; ++j) v -= hs[j] * static_cast<double>(V[static_cast<int64_t>(j) * ldv + i]);
+    const T vt = static_cast<T>(v);
+    w[i] = vt;
+    acc += static_cast<double>(vt) * static_cast<double>(vt);
   }
   const double s = block_sum(acc, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -520,20 +676,34 @@ __global__ void __launch_bounds__(TPB) k_sumsq(const double* __restrict__ x, int
 }
 
 // ---------------------------------------------------------------- vector ops
-__global__ void k_scale_by_dev(double* __restrict__ x, int64_t n, const double* __restrict__ nrm2) {
+template <class T>
+__global__ void k_scale_by_dev(T* __restrict__ x, int64_t n, const double* __restrict__ nrm2) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) x[i] *= 1.0 / sqrt(nrm2[0]);
+  if (i < n) x[i] = static_cast<T>(static_cast<double>(x[i]) * (1.0 / sqrt(nrm2[0])));
+}
+// y = a * x (FP64 in, basis type out)
+template <class T>
+__global__ void k_scale_to(const double* __restrict__ x, double a, T* __restrict__ y, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = static_cast<T>(a * x[i]);
+}
+// r = b - y (y in basis type)
+template <class T>
+__global__ void k_sub_from(const double* __restrict__ b, const T* __restrict__ y, double* __restrict__ r, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) r[i] = b[i] - static_cast<double>(y[i]);
 }
 __global__ void k_axpby(double a, const double* __restrict__ x, double b, double* __restrict__ y, int64_t n) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
 }
-__global__ void k_combine(const double* __restrict__ Z, int64_t ldz, int k, const double* __restrict__ c,
+template <class T>
+__global__ void k_combine(const T* __restrict__ Z, int64_t ldz, int k, const double* __restrict__ c,
                           double* __restrict__ x, int64_t n) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double v = x[i];
-  for (int j = 0; j < k; ++j) v += c[j] * Z[static_cast<int64_t>(j) * ldz + i];
+  for (int j = 0; j < k; ++j) v += c[j] * static_cast<double>(Z[static_cast<int64_t>(j) * ldz + i]);
   x[i] = v;
 }
 template <class A, class B>
@@ -680,18 +850,67 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
   const double gbytes = static_cast<double>(outer) * n_in * inner * sizeof(Ti) +
                         static_cast<double>(total) * sizeof(To) * (beta != C(0) ? 2 : 1);
   const int64_t nrows = outer * t.n_out;
-  if (std::is_same<Ti, To>::value && inner % 4 == 0 && inner < (static_cast<int64_t>(1) << 31) &&
-      (reinterpret_cast<uintptr_t>(x) % (4 * sizeof(Ti))) == 0 && (reinterpret_cast<uintptr_t>(y) % (4 * sizeof(To))) == 0) {
-    const int64_t slots = inner / 4;
+  const int vec = (inner % 4 == 0) ? 4 : (inner % 2 == 0 ? 2 : 1);
+  if (std::is_same<Ti, To>::value && t.c0 != nullptr && inner >= 2 && inner < (static_cast<int64_t>(1) << 31) &&
+      (t.W == 2 || t.W == 3 || t.W == 4 || t.W == 5 || t.W == 7 || t.W == 9 || t.W == 16) &&
+      (reinterpret_cast<uintptr_t>(x) % (vec * sizeof(Ti))) == 0 && (reinterpret_cast<uintptr_t>(y) % (vec * sizeof(To))) == 0) {
+    const int64_t slots = inner / vec;
+    // enough threads to fill the chip: chunk the output rows
+    const int64_t want = 1 << 18;
+    int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>(t.n_out / 4 + 1, (want + outer * slots - 1) / (outer * slots)));
+    const int rc = static_cast<int>((t.n_out + nchunks - 1) / nchunks);
+    nchunks = (t.n_out + rc - 1) / rc;
+    const int64_t total_t = outer * nchunks * slots;
+    if (total_t < (static_cast<int64_t>(1) << 32)) {
+      ProfScope ps(prof().gather_cls, 10 + 16 * prec_code<Ti>(), s, gbytes);
+      const unsigned blocks = static_cast<unsigned>((total_t + TPB - 1) / TPB);
+#define SW(w, v)                                                                                                    \
+  hipLaunchKernelGGL((k_sweep<Ti, C, w, v>), dim3(blocks), dim3(TPB), 0, s, t.c0, t.coef, t.n_out, x,                \
+                     reinterpret_cast<Ti*>(y), static_cast<uint32_t>(inner), n_in, in_base, alpha, beta,             \
+                     static_cast<uint32_t>(slots), rc, static_cast<uint32_t>(nchunks), static_cast<uint32_t>(total_t))
+#define SWW(v)                  \
+  switch (t.W) {                \
+    case 2: SW(2, v); break;    \
+    case 3: SW(3, v); break;    \
+    case 4: SW(4, v); break;    \
+    case 5: SW(5, v); break;    \
+    case 7: SW(7, v); break;    \
+    case 9: SW(9, v); break;    \
+    default: SW(16, v); break;  \
+  }
+      if (vec == 4) { SWW(4) } else if (vec == 2) { SWW(2) } else { SWW(1) }
+#undef SWW
+#undef SW
+      return;
+    }
+  }
+  if (std::is_same<Ti, To>::value && vec > 1 && inner < (static_cast<int64_t>(1) << 31) &&
+      (reinterpret_cast<uintptr_t>(x) % (vec * sizeof(Ti))) == 0 && (reinterpret_cast<uintptr_t>(y) % (vec * sizeof(To))) == 0) {
+    const int64_t slots = inner / vec;
     const int64_t rpb = slots < TPB ? TPB / slots : 1;
     const int64_t kchunks = rpb > 1 ? 1 : (slots + TPB - 1) / TPB;
     const int64_t blocks = rpb > 1 ? (nrows + rpb - 1) / rpb : kchunks * nrows;
     if (blocks < (static_cast<int64_t>(1) << 31) && nrows < (static_cast<int64_t>(1) << 32)) {
       ProfScope ps(prof().gather_cls, 1 + 16 * prec_code<Ti>(), s, gbytes);
-      hipLaunchKernelGGL((k_gather_v4<Ti, C>), dim3(static_cast<unsigned>(blocks)), dim3(TPB), 0, s, t.col, t.coef,
-                         t.W, t.n_out, x, reinterpret_cast<Ti*>(y), static_cast<uint32_t>(inner), n_in, in_base, alpha,
-                         beta, static_cast<uint32_t>(nrows), static_cast<uint32_t>(slots), static_cast<uint32_t>(rpb),
-                         static_cast<uint32_t>(kchunks));
+#define GV(wc, v)                                                                                              \
+  hipLaunchKernelGGL((k_gather_v4<Ti, C, wc, v>), dim3(static_cast<unsigned>(blocks)), dim3(TPB), 0, s, t.col, t.coef, \
+                     t.W, t.n_out, x, reinterpret_cast<Ti*>(y), static_cast<uint32_t>(inner), n_in, in_base, alpha,  \
+                     beta, static_cast<uint32_t>(nrows), static_cast<uint32_t>(slots), static_cast<uint32_t>(rpb),   \
+                     static_cast<uint32_t>(kchunks))
+#define GVW(v)                  \
+  switch (t.W) {                \
+    case 2: GV(2, v); break;    \
+    case 3: GV(3, v); break;    \
+    case 4: GV(4, v); break;    \
+    case 5: GV(5, v); break;    \
+    case 7: GV(7, v); break;    \
+    case 9: GV(9, v); break;    \
+    case 16: GV(16, v); break;  \
+    default: GV(0, v); break;   \
+  }
+      if (vec == 4) { GVW(4) } else { GVW(2) }
+#undef GVW
+#undef GV
       return;
     }
   }
@@ -700,7 +919,7 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
     const int RB = std::max(1, std::min(64, 2048 / std::max(n_in, 1)));
     // here a "row" is one outer index: n_in inputs in, t.n_out outputs out
     const int64_t blocks = (outer + RB - 1) / RB;
-    const size_t sh = static_cast<size_t>(RB) * n_in * sizeof(C);
+    const size_t sh = static_cast<size_t>(RB) * n_in * sizeof(C) + static_cast<size_t>(t.n_out) * t.W * (sizeof(C) + sizeof(int));
     if (blocks < (static_cast<int64_t>(1) << 31) && sh <= 48 * 1024) {
       ProfScope ps(prof().gather_cls, 2 + 16 * prec_code<Ti>(), s, gbytes);
       hipLaunchKernelGGL((k_gather_rows<Ti, C>), dim3(static_cast<unsigned>(blocks)), dim3(TPB), sh, s, t.col, t.coef,
@@ -724,6 +943,7 @@ void gather_rows(const DTable<C>& t, int r0, int nr, const Ti* x, To* y, int64_t
   DTable<C> u;
   u.col = t.col + static_cast<int64_t>(r0) * t.W;
   u.coef = t.coef + static_cast<int64_t>(r0) * t.W;
+  u.c0 = t.c0 ? t.c0 + r0 : nullptr;
   u.W = t.W;
   u.n_out = nr;
   gather<Ti, To, C>(u, x, y, outer, inner, n_in, in_base, alpha, beta, s);
@@ -811,18 +1031,19 @@ void kprof_read(int cls, double* ms, int64_t* launches, double* bytes, int reset
 
 int reduce_blocks(int64_t n) { return static_cast<int>((n + RED_CHUNK - 1) / RED_CHUNK); }
 
-void multidot_partial(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* part, int nb,
-                      hipStream_t s) {
-  ProfScope ps(K_MULTIDOT, 6, s, (k + 1.0) * n * sizeof(double));
-  hipLaunchKernelGGL(k_multidot, dim3(nb), dim3(TPB), 0, s, V, ldv, k, w, n, part);
+template <class T>
+void multidot_partial(const T* V, int64_t ldv, int k, const T* w, int64_t n, double* part, int nb, hipStream_t s) {
+  ProfScope ps(K_MULTIDOT, 6 + 16 * prec_code<T>(), s, (k + 1.0) * n * sizeof(T));
+  hipLaunchKernelGGL((k_multidot<T>), dim3(nb), dim3(TPB), 0, s, V, ldv, k, w, n, part);
 }
 void finalize_sum(const double* part, int nb, int k, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize_sum, dim3(k), dim3(TPB), 0, s, part, nb, k, out);
 }
-void update_norm_partial(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t n, double* part,
-                         int nb, hipStream_t s) {
-  ProfScope ps(K_UPDATE, 7, s, (k + 2.0) * n * sizeof(double));
-  hipLaunchKernelGGL(k_update_norm, dim3(nb), dim3(TPB), 0, s, V, ldv, k, h, w, n, part);
+template <class T>
+void update_norm_partial(const T* V, int64_t ldv, int k, const double* h, T* w, int64_t n, double* part, int nb,
+                         hipStream_t s) {
+  ProfScope ps(K_UPDATE, 7 + 16 * prec_code<T>(), s, (k + 2.0) * n * sizeof(T));
+  hipLaunchKernelGGL((k_update_norm<T>), dim3(nb), dim3(TPB), 0, s, V, ldv, k, h, w, n, part);
 }
 void absmax_partial(const double* x, int64_t n, double* part, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_absmax, dim3(nb), dim3(TPB), 0, s, x, n, part);
@@ -833,8 +1054,17 @@ void sumsq_partial(const double* x, int64_t n, double* part, int nb, hipStream_t
 void finalize_max(const double* part, int nb, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize_max, dim3(1), dim3(TPB), 0, s, part, nb, out);
 }
-void scale_by_dev(double* x, int64_t n, const double* nrm2, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_by_dev, dim3(grid_for(n)), dim3(TPB), 0, s, x, n, nrm2);
+template <class T>
+void scale_by_dev(T* x, int64_t n, const double* nrm2, hipStream_t s) {
+  hipLaunchKernelGGL((k_scale_by_dev<T>), dim3(grid_for(n)), dim3(TPB), 0, s, x, n, nrm2);
+}
+template <class T>
+void scale_to(const double* x, double a, T* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_scale_to<T>), dim3(grid_for(n)), dim3(TPB), 0, s, x, a, y, n);
+}
+template <class T>
+void sub_from(const double* b, const T* y, double* r, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_sub_from<T>), dim3(grid_for(n)), dim3(TPB), 0, s, b, y, r, n);
 }
 void axpy(double a, const double* x, double* y, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(TPB), 0, s, a, x, 1.0, y, n);
@@ -842,8 +1072,9 @@ void axpy(double a, const double* x, double* y, int64_t n, hipStream_t s) {
 void axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(TPB), 0, s, a, x, b, y, n);
 }
-void combine(const double* Z, int64_t ldz, int k, const double* c, double* x, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_combine, dim3(grid_for(n)), dim3(TPB), 0, s, Z, ldz, k, c, x, n);
+template <class T>
+void combine(const T* Z, int64_t ldz, int k, const double* c, double* x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_combine<T>), dim3(grid_for(n)), dim3(TPB), 0, s, Z, ldz, k, c, x, n);
 }
 template <class A, class B>
 void convert(const A* x, B* y, int64_t n, hipStream_t s) {
@@ -912,6 +1143,22 @@ template void arrowhead<float, float>(const float*, float*, const float*, const 
 template void arrowhead<bf16, float>(const bf16*, bf16*, const float*, const float*, const int*, const float*, float,
                                      float, int, int64_t, hipStream_t);
 template void convert<double, float>(const double*, float*, int64_t, hipStream_t);
+template void multidot_partial<double>(const double*, int64_t, int, const double*, int64_t, double*, int, hipStream_t);
+template void multidot_partial<float>(const float*, int64_t, int, const float*, int64_t, double*, int, hipStream_t);
+template void update_norm_partial<double>(const double*, int64_t, int, const double*, double*, int64_t, double*, int,
+                                          hipStream_t);
+template void update_norm_partial<float>(const float*, int64_t, int, const double*, float*, int64_t, double*, int,
+                                         hipStream_t);
+template void scale_by_dev<double>(double*, int64_t, const double*, hipStream_t);
+template void scale_by_dev<float>(float*, int64_t, const double*, hipStream_t);
+template void scale_to<double>(const double*, double, double*, int64_t, hipStream_t);
+template void scale_to<float>(const double*, double, float*, int64_t, hipStream_t);
+template void sub_from<double>(const double*, const double*, double*, int64_t, hipStream_t);
+template void sub_from<float>(const double*, const float*, double*, int64_t, hipStream_t);
+template void combine<double>(const double*, int64_t, int, const double*, double*, int64_t, hipStream_t);
+template void combine<float>(const float*, int64_t, int, const double*, double*, int64_t, hipStream_t);
+template void convert<float, bf16>(const float*, bf16*, int64_t, hipStream_t);
+template void convert<bf16, float>(const bf16*, float*, int64_t, hipStream_t);
 template void convert<float, double>(const float*, double*, int64_t, hipStream_t);
 template void convert<double, bf16>(const double*, bf16*, int64_t, hipStream_t);
 template void convert<bf16, double>(const bf16*, double*, int64_t, hipStream_t);

@@ -29,6 +29,7 @@ template <class C>
 struct DTable {
   const int* col = nullptr;
   const C* coef = nullptr;
+  const int* c0 = nullptr;   // contiguous window starts (see make_contiguous), or null
   int n_out = 0, W = 0;
 };
 
@@ -66,25 +67,32 @@ void arrowhead(const S* r, S* y, const C* lam, const C* mu, const int* kind, con
 
 // Deterministic reductions (two stages, fixed order).
 int reduce_blocks(int64_t n);
-// part[b*k + j] = partial of <V_j, w> over block b; V_j = V + j*ldv
-void multidot_partial(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* part, int nb,
-                      hipStream_t s);
+// part[b*k + j] = partial of <V_j, w> over block b; V_j = V + j*ldv (T: basis storage, FP64 accumulation)
+template <class T>
+void multidot_partial(const T* V, int64_t ldv, int k, const T* w, int64_t n, double* part, int nb, hipStream_t s);
 // out[j] = sum_b part[b*k + j]
 void finalize_sum(const double* part, int nb, int k, double* out, hipStream_t s);
 // w -= sum_j h[j] V_j ; part[b] = partial ||w||^2 (h read from device)
-void update_norm_partial(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t n,
-                         double* part, int nb, hipStream_t s);
+template <class T>
+void update_norm_partial(const T* V, int64_t ldv, int k, const double* h, T* w, int64_t n, double* part, int nb,
+                         hipStream_t s);
 // part[b] = partial max |x| (kind 0) or sum x^2 (kind 1)
 void absmax_partial(const double* x, int64_t n, double* part, int nb, hipStream_t s);
 void sumsq_partial(const double* x, int64_t n, double* part, int nb, hipStream_t s);
 void finalize_max(const double* part, int nb, double* out, hipStream_t s);
 
 // x = a * x (scale from a device scalar: x *= 1/sqrt(*nrm2) if inv_sqrt)
-void scale_by_dev(double* x, int64_t n, const double* nrm2, hipStream_t s);
+template <class T>
+void scale_by_dev(T* x, int64_t n, const double* nrm2, hipStream_t s);
+template <class T>
+void scale_to(const double* x, double a, T* y, int64_t n, hipStream_t s);      // y = a x
+template <class T>
+void sub_from(const double* b, const T* y, double* r, int64_t n, hipStream_t s);  // r = b - y
 void axpy(double a, const double* x, double* y, int64_t n, hipStream_t s);            // y += a x
 void axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);  // y = a x + b y
 // x += sum_j c[j] Z_j (c on device)
-void combine(const double* Z, int64_t ldz, int k, const double* c, double* x, int64_t n, hipStream_t s);
+template <class T>
+void combine(const T* Z, int64_t ldz, int k, const double* c, double* x, int64_t n, hipStream_t s);
 template <class A, class B>
 void convert(const A* x, B* y, int64_t n, hipStream_t s);
 void fill(double* x, double v, int64_t n, hipStream_t s);

@@ -110,7 +110,9 @@ struct st_iga_ctx {
   double *t4[4] = {}, *big[2] = {};
   float *t4f[4] = {}, *bigf[2] = {}, *xf = nullptr, *yf = nullptr;
   bf16 *t4b[4] = {}, *xb = nullptr, *yb = nullptr;
-  double *Vk = nullptr, *Zk = nullptr, *rk = nullptr, *xk = nullptr, *wk = nullptr, *dk = nullptr, *bk = nullptr;
+  void *Vb = nullptr, *Zb = nullptr;
+  int last_refinements = 0;
+  double *rk = nullptr, *xk = nullptr, *wk = nullptr, *dk = nullptr, *bk = nullptr;
   double *VT = nullptr, *sol_rhs = nullptr, *sol_dx = nullptr;
   double *grid = nullptr, *grid2 = nullptr, *E = nullptr, *rfull = nullptr, *Cg = nullptr;
   double *part = nullptr, *dsc = nullptr, *gram = nullptr, *tmpR = nullptr;
@@ -317,6 +319,22 @@ void host_setup(st_iga_ctx* c) {
     c->Ew.h = dense_table(R, Nt, nt, false);
   }
   // chunking of the quadrature pass: arrays per time Gauss point row
+  // contiguous windows for the sweep kernels
+  for (int l = 0; l < P.d; ++l) {
+    const Dir1D& D = c->dir[l];
+    make_contiguous(c->Ms[l].h, D.n);
+    make_contiguous(c->Ks[l].h, D.n);
+    for (int k2 = 0; k2 <= 2; ++k2) make_contiguous(c->Bq[l][k2].h, D.n);
+    make_contiguous(c->BqT[l].h, D.Q);
+    make_contiguous(c->Hs[l].h, D.n);
+    make_contiguous(c->Gs[l].h, D.n);
+  }
+  make_contiguous(c->Mt_x.h, c->nt);
+  make_contiguous(c->Wt_x.h, c->nt);
+  make_contiguous(c->Bt0.h, c->nt);
+  make_contiguous(c->Bt1.h, c->nt);
+  make_contiguous(c->BtT.h, T.Q);
+  make_contiguous(c->Gt.h, c->nt);
   // the quadrature pass keeps 3 arrays of N_s and 3 of Q_s doubles per time
   // Gauss point in the first big buffer and 5 of Q_s in the second
   c->big_len = std::max<int64_t>({static_cast<int64_t>(c->nt) * c->Qs, 5LL * c->nqt * c->Qs,
@@ -329,6 +347,10 @@ void host_setup(st_iga_ctx* c) {
 template <class C>
 void alloc_tab(Arena& a, Tab& t) {
   const size_t n = t.h.col.size();
+  if (!t.h.c0.empty()) {
+    t.d.c0 = a.get<int>(static_cast<int64_t>(t.h.c0.size()));
+    t.f.c0 = t.d.c0;
+  }
   t.d.col = a.get<int>(n);
   t.d.coef = a.get<double>(n);
   t.f.col = t.d.col;
@@ -386,8 +408,9 @@ void plan(st_iga_ctx* c) {
   c->sol_rhs = a.get<double>(c->nunk);
   c->sol_dx = a.get<double>(c->nunk);
   const int m = c->opt.restart;
-  c->Vk = a.get<double>(static_cast<int64_t>(m + 1) * c->nunk);
-  c->Zk = a.get<double>(static_cast<int64_t>(m) * c->nunk);
+  const size_t bsz = mixed ? sizeof(float) : sizeof(double);   // Krylov basis storage
+  c->Vb = a.take(static_cast<size_t>(m + 1) * c->nunk * bsz);
+  c->Zb = a.take(static_cast<size_t>(m) * c->nunk * bsz);
   c->rk = a.get<double>(c->nunk);
   c->xk = a.get<double>(c->nunk);
   c->wk = a.get<double>(c->nunk);
@@ -428,6 +451,7 @@ void up(const std::vector<X>& h, const X* d, hipStream_t s) {
 }
 
 void upload_tab(Tab& t, hipStream_t s, std::vector<std::vector<float>>& keep) {
+  if (!t.h.c0.empty()) up(t.h.c0, t.d.c0, s);
   up(t.h.col, t.d.col, s);
   up(t.h.coef, t.d.coef, s);
   keep.emplace_back(t.h.coef.begin(), t.h.coef.end());
@@ -714,42 +738,44 @@ double dev_absmax(st_iga_ctx* c, const double* x, int64_t n, hipStream_t s) {
 }
 
 using Op = std::function<void(const double*, double*)>;
+template <class T>
+using OpT = std::function<void(const T*, T*)>;
 
-// Right-preconditioned FGMRES(m) on A x = b from x = 0 (FP64 Arnoldi, CGS with
-// one re-orthogonalization pass, Givens rotations on the host).  Returns the
-// number of iterations; *est = last residual estimate / ||b||.
-int fgmres(st_iga_ctx* c, const Op& A, const Op& Pc, const double* b, double* x, double rtol, int maxit, double bnorm,
-           double* est, hipStream_t s) {
+// Right-preconditioned FGMRES(m) on A x = b from x = 0.  The Krylov basis V
+// (m+1 vectors) and Z (m vectors) are stored in T (FP64, or FP32 for the inner
+// solves of mixed precision); Arnoldi dot products, the Gram-Schmidt updates
+// (classical, twice) and the Givens rotations are carried out in FP64.  b, x
+// and the restart residual are FP64.  Returns the iteration count; *est is the
+// relative residual of the last restart check, computed with the same A.
+template <class T>
+int fgmres(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const double* b, double* x, double rtol, int maxit,
+           double bnorm, double* est, T* V, T* Z, T* xt, T* yt, hipStream_t s) {
   const int64_t n = c->nunk;
   const int m = c->opt.restart;
   const int nb = reduce_blocks(n);
   fill(x, 0.0, n, s);
   int it = 0;
   double rn = bnorm;
-  // r = b
   CK(hipMemcpyAsync(c->rk, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   double hbuf[2 * 66 + 2];
   while (it < maxit) {
-    // V_0 = r / ||r||
-    axpby(1.0 / rn, c->rk, 0.0, c->Vk, n, s);
+    scale_to<T>(c->rk, 1.0 / rn, V, n, s);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = rn;
     int j = 0;
-    bool done = false;
     for (; j < m && it < maxit; ++j) {
-      double* Vj = c->Vk + static_cast<int64_t>(j) * n;
-      double* Zj = c->Zk + static_cast<int64_t>(j) * n;
-      double* w = c->Vk + static_cast<int64_t>(j + 1) * n;
+      T* Vj = V + static_cast<int64_t>(j) * n;
+      T* Zj = Z + static_cast<int64_t>(j) * n;
+      T* w = V + static_cast<int64_t>(j + 1) * n;
       Pc(Vj, Zj);
       A(Zj, w);
-      // classical Gram-Schmidt, twice
-      multidot_partial(c->Vk, n, j + 1, w, n, c->part, nb, s);
+      multidot_partial<T>(V, n, j + 1, w, n, c->part, nb, s);
       finalize_sum(c->part, nb, j + 1, c->dsc, s);
-      update_norm_partial(c->Vk, n, j + 1, c->dsc, w, n, c->part, nb, s);
-      multidot_partial(c->Vk, n, j + 1, w, n, c->part, nb, s);
+      update_norm_partial<T>(V, n, j + 1, c->dsc, w, n, c->part, nb, s);
+      multidot_partial<T>(V, n, j + 1, w, n, c->part, nb, s);
       finalize_sum(c->part, nb, j + 1, c->dsc + 128, s);
-      update_norm_partial(c->Vk, n, j + 1, c->dsc + 128, w, n, c->part, nb, s);
+      update_norm_partial<T>(V, n, j + 1, c->dsc + 128, w, n, c->part, nb, s);
       finalize_sum(c->part, nb, 1, c->dsc + 256, s);
       CK(hipMemcpyAsync(hbuf, c->dsc, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
       CK(hipMemcpyAsync(hbuf + 66, c->dsc + 128, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -757,13 +783,10 @@ int fgmres(st_iga_ctx* c, const Op& A, const Op& Pc, const double* b, double* x,
       CK(hipStreamSynchronize(s));
       check_launch();
       ++it;
-      double* h = &H[static_cast<size_t>(j)];   // column j: H[i*m + j]
       for (int i = 0; i <= j; ++i) H[static_cast<size_t>(i) * m + j] = hbuf[i] + hbuf[66 + i];
       const double hn = std::sqrt(std::max(hbuf[132], 0.0));
-      (void)h;
       if (!std::isfinite(hn)) throw Fail{ST_IGA_ENOCONV, "non-finite Arnoldi norm"};
-      scale_by_dev(w, n, c->dsc + 256, s);
-      // apply previous rotations
+      scale_by_dev<T>(w, n, c->dsc + 256, s);
       for (int i = 0; i < j; ++i) {
         const double t1 = H[static_cast<size_t>(i) * m + j], t2 = H[static_cast<size_t>(i + 1) * m + j];
         H[static_cast<size_t>(i) * m + j] = cs[i] * t1 + sn[i] * t2;
@@ -778,25 +801,27 @@ int fgmres(st_iga_ctx* c, const Op& A, const Op& Pc, const double* b, double* x,
       g[j] = cs[j] * g[j];
       if (std::fabs(g[j + 1]) <= rtol * bnorm || hn == 0.0) {
         ++j;
-        done = true;
         break;
       }
     }
-    // solve H y = g (upper triangular j x j)
     for (int i = j - 1; i >= 0; --i) {
       double t = g[i];
       for (int k = i + 1; k < j; ++k) t -= H[static_cast<size_t>(i) * m + k] * y[k];
       y[i] = t / H[static_cast<size_t>(i) * m + i];
     }
     CK(hipMemcpyAsync(c->dsc + 512, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
-    combine(c->Zk, n, j, c->dsc + 512, x, n, s);
-    // true residual r = b - A x
-    A(x, c->rk);
-    axpby(1.0, b, -1.0, c->rk, n, s);
+    combine<T>(Z, n, j, c->dsc + 512, x, n, s);
+    // restart residual r = b - A x with the same operator
+    if (std::is_same<T, double>::value) {
+      A(reinterpret_cast<const T*>(x), yt);
+    } else {
+      convert<double, float>(x, reinterpret_cast<float*>(xt), n, s);
+      A(xt, yt);
+    }
+    sub_from<T>(b, yt, c->rk, n, s);
     rn = dev_norm(c, c->rk, n, s);
     *est = rn / bnorm;
     if (rn <= rtol * bnorm) break;
-    (void)done;
     if (!std::isfinite(rn)) throw Fail{ST_IGA_ENOCONV, "non-finite residual"};
   }
   return it;
@@ -859,6 +884,38 @@ void lowp_ops<bf16>(st_iga_ctx* c, Op& A, Op& Pc, hipStream_t s) {
   };
 }
 
+// Low-precision operators on FP32 buffers for the inner solves.
+void lowp_ops_f32(st_iga_ctx* c, OpT<float>& A, OpT<float>& Pc, hipStream_t s) {
+  A = [c, s](const float* x, float* y) {
+    Bufs<float> B;
+    for (int k = 0; k < 4; ++k) B.t4[k] = c->t4f[k];
+    B.big[0] = c->bigf[0];
+    B.big[1] = c->bigf[1];
+    B.Psi = c->Psi_f;
+    apply_impl<float, float>(c, x, y, c->Nt, 1, true, true, B, s);
+  };
+  if (c->opt.prec == ST_IGA_MIXED_FP32) {
+    Pc = [c, s](const float* r, float* z) {
+      Bufs<float> B;
+      for (int k = 0; k < 4; ++k) B.t4[k] = c->t4f[k];
+      B.big[0] = c->bigf[0];
+      B.big[1] = c->bigf[1];
+      B.Psi = c->Psi_f;
+      precond_impl<float, float>(c, r, z, B, s);
+    };
+  } else {
+    Pc = [c, s](const float* r, float* z) {
+      Bufs<bf16> B;
+      for (int k = 0; k < 4; ++k) B.t4[k] = c->t4b[k];
+      B.big[0] = B.big[1] = nullptr;
+      B.Psi = nullptr;
+      convert<float, bf16>(r, c->xb, c->nunk, s);
+      precond_impl<bf16, float>(c, c->xb, c->yb, B, s);
+      convert<bf16, float>(c->yb, z, c->nunk, s);
+    };
+  }
+}
+
 // Linear solve with the configured precision.  Returns iterations.
 int krylov(st_iga_ctx* c, const double* b, double* x, double tol, double* relres, hipStream_t s) {
   ensure_lin(c);
@@ -869,18 +926,18 @@ int krylov(st_iga_ctx* c, const double* b, double* x, double tol, double* relres
     *relres = 0.0;
     return 0;
   }
-  Op A64 = [c, s](const double* xx, double* yy) { apply64(c, xx, yy, s); };
-  Op P64 = [c, s](const double* rr, double* zz) { precond64(c, rr, zz, s); };
   double est = 1.0;
   if (c->opt.prec == ST_IGA_FP64) {
-    const int it = fgmres(c, A64, P64, b, x, tol, c->opt.max_krylov, bnorm, &est, s);
+    OpT<double> A64 = [c, s](const double* xx, double* yy) { apply64(c, xx, yy, s); };
+    OpT<double> P64 = [c, s](const double* rr, double* zz) { precond64(c, rr, zz, s); };
+    const int it = fgmres<double>(c, A64, P64, b, x, tol, c->opt.max_krylov, bnorm, &est,
+                                  static_cast<double*>(c->Vb), static_cast<double*>(c->Zb), nullptr, c->wk, s);
     *relres = est;
     if (est > tol) throw Fail{ST_IGA_ENOCONV, "FGMRES reached max_krylov"};
     return it;
   }
-  Op Al, Pl;
-  if (c->opt.prec == ST_IGA_MIXED_FP32) lowp_ops<float>(c, Al, Pl, s);
-  else lowp_ops<bf16>(c, Al, Pl, s);
+  OpT<float> Al, Pl;
+  lowp_ops_f32(c, Al, Pl, s);
   // iterative refinement on the FP64 true residual
   fill(x, 0.0, n, s);
   CK(hipMemcpyAsync(c->bk, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));   // bk = current residual
@@ -890,15 +947,17 @@ int krylov(st_iga_ctx* c, const double* b, double* x, double tol, double* relres
     if (total >= c->opt.max_krylov || refinements >= 60) throw Fail{ST_IGA_ENOCONV, "refinement did not converge"};
     const double itol = std::max(c->opt.inner_tol, 0.5 * tol * bnorm / rn);
     double e2 = 1.0;
-    total += fgmres(c, Al, Pl, c->bk, c->dk, itol, c->opt.max_krylov - total, rn, &e2, s);
+    total += fgmres<float>(c, Al, Pl, c->bk, c->dk, itol, c->opt.max_krylov - total, rn, &e2,
+                           static_cast<float*>(c->Vb), static_cast<float*>(c->Zb), c->xf, c->yf, s);
     axpy(1.0, c->dk, x, n, s);
-    A64(x, c->wk);
+    apply64(c, x, c->wk, s);
     axpby(1.0, b, -1.0, c->wk, n, s);
     CK(hipMemcpyAsync(c->bk, c->wk, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     rn = dev_norm(c, c->bk, n, s);
     ++refinements;
     if (!std::isfinite(rn)) throw Fail{ST_IGA_ENOCONV, "non-finite residual"};
   }
+  c->last_refinements = refinements;
   *relres = rn / bnorm;
   return total;
 }
