@@ -39,7 +39,25 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--serve", action="store_true", help="run only the serving stream (512 requests)")
+    ap.add_argument("--serve-requests", type=int, default=128,
+                    help="requests of the serving stream sampled in the default run (0: skip)")
+    ap.add_argument("--serve-slots", type=int, default=8)
     return ap.parse_args()
+
+
+def serving(n_requests, slots):
+    """Config 3: seeded stream of 2D solves, Poisson arrivals at 20 req/s,
+    mixed FP32, linear and nonlinear tolerance 1e-8, continuous batching."""
+    import st_workloads as W
+    from paper_2311_17500_amd.binding import MIXED_FP32
+    from paper_2311_17500_amd.serve import Server, summarize
+    reqs = W.serve_stream(512, 0)[:n_requests]
+    srv = Server(slots=slots, prec=MIXED_FP32, tol_lin=1e-8, tol_nonlin=1e-8, lin_forcing=0.1)
+    out = summarize(srv.run(reqs))
+    out.update({"slots": slots, "arrival_rate_per_s": 20.0, "stream": f"first {n_requests} of 512 (seed 0)",
+                "hbm_budget_bytes": srv.budget})
+    return out
 
 
 def time_region(torch, S, u1, u2, w, steps, warmup, tol):
@@ -109,6 +127,14 @@ def main():
     import torch
     import st_workloads as W
     from paper_2311_17500_amd.binding import Solver, FP64, MIXED_FP32, MIXED_BF16
+    if a.serve:
+        s = serving(512, a.serve_slots)
+        print(json.dumps({"metric": "p50/p99 solve latency, 512-request serving stream (config 3)",
+                          "value": s["p99_latency_s"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+                          "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+                          "data": "synthetic", "config": {"workload": "config3: 512 seeded 2D solves at 20 req/s"},
+                          "serving": s}), flush=True)
+        return
 
     prob = W.config(a.config)
     prec_code = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}[a.prec]
@@ -189,6 +215,12 @@ def main():
         out["fp64_ms_per_step"] = f["ms"]
         out["fp64_krylov_iters_per_step"] = f["its"][0]
         out["speedup_vs_fp64"] = f["ms"] / ms
+    if a.serve_requests > 0:
+        for r in res.values():         # release the single-solve workspaces first
+            r["S"].close()
+            r["S"].ws = None
+        torch.cuda.empty_cache()
+        out["serving"] = serving(a.serve_requests, a.serve_slots)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.config)
     print(json.dumps(out), flush=True)

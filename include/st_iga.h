@@ -79,7 +79,7 @@ typedef struct {
   int32_t su;                /* 1: Spline Upwind term of eq. (3.2) on, 0: plain Galerkin */
   double eps_theta;          /* relative Frobenius tolerance of the theta low rank, eq. (3.8) (paper: 0.1) */
   double eps_react;          /* same tolerance for the reaction coefficient of the Jacobian */
-  int32_t max_rank;          /* cap on each low rank (sizes the workspace) */
+  int32_t max_rank;          /* cap on each low rank (sizes the workspace); a capped rank misses eps */
   int32_t outer;             /* 0: Newton (dI_ion/du), 1: Picard with C_r of eq. (3.6) */
   double alpha;              /* relaxation of the update (paper: 0.5 for Picard) */
   double theta_freeze;       /* theta is recomputed while ||delta||_inf > theta_freeze */
@@ -90,6 +90,7 @@ typedef struct {
   int32_t max_outer;         /* nonlinear iteration cap */
   int32_t max_krylov;        /* Krylov iteration cap per linear solve */
   st_iga_precision prec;
+  double lin_forcing;        /* > 0: outer iteration k solves to max(tol_lin, min(1e-2, lin_forcing*||delta_{k-1}||_inf)) */
 } st_iga_options;
 
 #define ST_IGA_MAX_OUTER_LOG 64
@@ -108,7 +109,7 @@ typedef struct {
 
 /* Defaults: su=1, eps_theta=0.1, eps_react=1e-2, max_rank=48, outer=0,
  * alpha=1 (Newton), theta_freeze=1e-4, tol_nonlin=1e-10, tol_lin=1e-10,
- * inner_tol=1e-4, restart=30, max_outer=60, max_krylov=3000, prec=FP64. */
+ * inner_tol=1e-4, restart=30, max_outer=60, max_krylov=3000, prec=FP64, lin_forcing=0. */
 void st_iga_default_options(st_iga_options* opt);
 
 /* Bytes of device workspace st_iga_setup needs for this problem/options

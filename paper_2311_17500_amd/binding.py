@@ -42,7 +42,8 @@ class Options(C.Structure):
     _fields_ = [("su", C.c_int32), ("eps_theta", C.c_double), ("eps_react", C.c_double), ("max_rank", C.c_int32),
                 ("outer", C.c_int32), ("alpha", C.c_double), ("theta_freeze", C.c_double),
                 ("tol_nonlin", C.c_double), ("tol_lin", C.c_double), ("inner_tol", C.c_double),
-                ("restart", C.c_int32), ("max_outer", C.c_int32), ("max_krylov", C.c_int32), ("prec", C.c_int32)]
+                ("restart", C.c_int32), ("max_outer", C.c_int32), ("max_krylov", C.c_int32), ("prec", C.c_int32),
+                ("lin_forcing", C.c_double)]
 
 
 LOG = 64
@@ -145,6 +146,14 @@ def default_options(**kw):
     return O
 
 
+def workspace_bytes(prob, knots=None, **options) -> int:
+    """Device workspace one context of this problem needs (host-only call)."""
+    lib = load()
+    P, keep = make_problem(prob, knots)
+    O = default_options(**options)
+    return int(lib.st_iga_workspace_bytes(C.byref(P), C.byref(O)))
+
+
 def host_query(prob, what: int, direction: int, knots=None) -> np.ndarray:
     """Host-only setup data (no GPU), see st_iga_host_query."""
     lib = load()
@@ -161,7 +170,7 @@ def host_query(prob, what: int, direction: int, knots=None) -> np.ndarray:
 class Solver:
     """One problem on one GPU: owns a torch workspace and the library context."""
 
-    def __init__(self, prob, knots=None, device="cuda:0", **options):
+    def __init__(self, prob, knots=None, device="cuda:0", stream=None, **options):
         import torch
         self.torch = torch
         self.lib = load()
@@ -172,11 +181,13 @@ class Solver:
         if nbytes == 0:
             raise StIgaError(EINVAL, "invalid problem or options")
         self.device = torch.device(device)
-        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self.tstream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.stream(self.tstream):
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
         off = (-base) % 256
         self.ctx = C.c_void_p()
-        self.stream = torch.cuda.current_stream(self.device).cuda_stream
+        self.stream = self.tstream.cuda_stream
         st = self.lib.st_iga_setup(C.byref(self.P), C.byref(self.O), C.c_void_p(base + off), nbytes, self._s(),
                                    C.byref(self.ctx))
         if st != OK:
@@ -200,7 +211,8 @@ class Solver:
         return C.c_void_p(t.data_ptr())
 
     def vec(self, n=None):
-        return self.torch.zeros(self.unknowns if n is None else n, dtype=self.torch.float64, device=self.device)
+        with self.torch.cuda.stream(self.tstream):
+            return self.torch.zeros(self.unknowns if n is None else n, dtype=self.torch.float64, device=self.device)
 
     def linearize(self, u, w, refresh_theta=True):
         self._chk(self.lib.st_iga_linearize(self.ctx, self._p(u), self._p(w), int(refresh_theta), self._s()))

@@ -53,9 +53,11 @@ __device__ __forceinline__ bf16 from_c<bf16>(double v) { return __float2bfloat16
 inline unsigned grid_for(int64_t n, int tpb = TPB) { return static_cast<unsigned>((n + tpb - 1) / tpb); }
 
 // ---------------------------------------------------------------- profiler
+// Process-wide profiler; enabling it is meant for one solver thread at a time
+// (benchmarks).  The gather tag is per thread so concurrent contexts never race.
+thread_local int t_gather_cls = 0;
 struct ProfState {
   bool on = false;
-  int gather_cls = 0;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   struct Rec {
@@ -488,6 +490,64 @@ __global__ void __launch_bounds__(256) k_dense_mode(const C* __restrict__ Ap, in
     }
 }
 
+
+// Variant for inner % 4 == 0: a wave owns 64 columns as four 16-column MFMA
+// tiles; lane l feeds columns c0 + 4(l%16) + e of tile e from one 4-wide load
+// and stores the four results of a row with one 4-wide store.
+template <class S, class C, int NT, bool LDS_A>
+__global__ void __launch_bounds__(256) k_dense_mode4(const C* __restrict__ Ap, int n, int npad,
+                                                     const S* __restrict__ x, S* __restrict__ y, int64_t inner,
+                                                     int64_t ncols) {
+  extern __shared__ char smem_raw[];
+  C* As = reinterpret_cast<C*>(smem_raw);
+  if (LDS_A) {
+    for (int t = threadIdx.x; t < npad * npad; t += blockDim.x) As[t] = Ap[t];
+    __syncthreads();
+  }
+  const C* Asrc = LDS_A ? As : Ap;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int64_t c = (static_cast<int64_t>(blockIdx.x) * 4 + wv) * 64 + 4 * r16;
+  const bool cv = c < ncols;
+  const int64_t o = cv ? c / inner : 0;
+  const int64_t kq = cv ? c - o * inner : 0;
+  const S* xb = x + o * static_cast<int64_t>(n) * inner + kq;
+  typedef typename Acc4<C>::T A4;
+  A4 acc[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[t][e] = A4{0, 0, 0, 0};
+  for (int kk = 0; kk < npad; kk += 4) {
+    const int j = kk + q4;
+    C b[4];
+    const bool ok = cv && j < n;
+    loadv<4, S, C>(xb + static_cast<int64_t>(ok ? j : 0) * inner, b);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) b[e] = ok ? b[e] : C(0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const C a = Asrc[(t * 16 + r16) * npad + j];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[t][e] = mfma16x16x4(a, b[e], acc[t][e]);
+    }
+  }
+  if (!cv) return;
+  S* yb = y + o * static_cast<int64_t>(n) * inner + kq;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = t * 16 + (std::is_same<C, double>::value ? q4 + 4 * v : 4 * q4 + v);
+      if (i < n) {
+        C r[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) r[e] = acc[t][e][v];
+        storev<4, S, C>(yb + static_cast<int64_t>(i) * inner, r);
+      }
+    }
+}
+
 // ---------------------------------------------------------------- arrowhead
 template <class S, class C>
 __global__ void __launch_bounds__(TPB) k_arrowhead(const S* __restrict__ r, S* __restrict__ y, const C* __restrict__ lam,
@@ -593,6 +653,59 @@ __global__ void __launch_bounds__(TPB) k_multidot(const T* __restrict__ V, int64
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj)
           if (jg + jj < k) acc[jj] += static_cast<double>(V[static_cast<int64_t>(jg + jj) * ldv + i]) * wr[e];
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) acc[jj] = wave_sum(acc[jj]);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) sh[wv * 8 + jj] = acc[jj];
+    __syncthreads();
+    if (threadIdx.x < 8 && jg + static_cast<int>(threadIdx.x) < k) {
+      double s = 0.0;
+      for (int q = 0; q < (TPB / 64); ++q) s += sh[q * 8 + threadIdx.x];
+      part[static_cast<int64_t>(blockIdx.x) * k + jg + threadIdx.x] = s;
+    }
+  }
+}
+
+
+// Vector-load variant (n % VEC == 0, 16-byte aligned): loads are clamped and
+// unconditional so a thread issues all of them before accumulating.
+template <class T, int VEC>
+__global__ void __launch_bounds__(TPB) k_multidot_v(const T* __restrict__ V, int64_t ldv, int k,
+                                                    const T* __restrict__ w, int64_t n, double* __restrict__ part) {
+  __shared__ double sh[(TPB / 64) * 8];
+  constexpr int NV = RED_E / VEC;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * RED_CHUNK + static_cast<int64_t>(threadIdx.x) * VEC;
+  double wr[NV][VEC];
+  int64_t ic[NV];
+#pragma unroll
+  for (int e = 0; e < NV; ++e) {
+    const int64_t i = base + static_cast<int64_t>(e) * TPB * VEC;
+    const bool ok = i < n;
+    ic[e] = ok ? i : 0;
+    double t[VEC];
+    loadv<VEC, T, double>(w + ic[e], t);
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) wr[e][q] = ok ? t[q] : 0.0;
+  }
+  for (int jg = 0; jg < k; jg += 8) {
+    double acc[8];
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) acc[jj] = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+      const int jv = min(jg + jj, k - 1);
+      const T* Vj = V + static_cast<int64_t>(jv) * ldv;
+#pragma unroll
+      for (int e = 0; e < NV; ++e) {
+        double t[VEC];
+        loadv<VEC, T, double>(Vj + ic[e], t);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc[jj] += t[q] * wr[e][q];
       }
     }
 #pragma unroll
@@ -862,7 +975,7 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
     nchunks = (t.n_out + rc - 1) / rc;
     const int64_t total_t = outer * nchunks * slots;
     if (total_t < (static_cast<int64_t>(1) << 32)) {
-      ProfScope ps(prof().gather_cls, 10 + 16 * prec_code<Ti>(), s, gbytes);
+      ProfScope ps(t_gather_cls, 10 + 16 * prec_code<Ti>(), s, gbytes);
       const unsigned blocks = static_cast<unsigned>((total_t + TPB - 1) / TPB);
 #define SW(w, v)                                                                                                    \
   hipLaunchKernelGGL((k_sweep<Ti, C, w, v>), dim3(blocks), dim3(TPB), 0, s, t.c0, t.coef, t.n_out, x,                \
@@ -891,7 +1004,7 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
     const int64_t kchunks = rpb > 1 ? 1 : (slots + TPB - 1) / TPB;
     const int64_t blocks = rpb > 1 ? (nrows + rpb - 1) / rpb : kchunks * nrows;
     if (blocks < (static_cast<int64_t>(1) << 31) && nrows < (static_cast<int64_t>(1) << 32)) {
-      ProfScope ps(prof().gather_cls, 1 + 16 * prec_code<Ti>(), s, gbytes);
+      ProfScope ps(t_gather_cls, 1 + 16 * prec_code<Ti>(), s, gbytes);
 #define GV(wc, v)                                                                                              \
   hipLaunchKernelGGL((k_gather_v4<Ti, C, wc, v>), dim3(static_cast<unsigned>(blocks)), dim3(TPB), 0, s, t.col, t.coef, \
                      t.W, t.n_out, x, reinterpret_cast<Ti*>(y), static_cast<uint32_t>(inner), n_in, in_base, alpha,  \
@@ -921,13 +1034,13 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
     const int64_t blocks = (outer + RB - 1) / RB;
     const size_t sh = static_cast<size_t>(RB) * n_in * sizeof(C) + static_cast<size_t>(t.n_out) * t.W * (sizeof(C) + sizeof(int));
     if (blocks < (static_cast<int64_t>(1) << 31) && sh <= 48 * 1024) {
-      ProfScope ps(prof().gather_cls, 2 + 16 * prec_code<Ti>(), s, gbytes);
+      ProfScope ps(t_gather_cls, 2 + 16 * prec_code<Ti>(), s, gbytes);
       hipLaunchKernelGGL((k_gather_rows<Ti, C>), dim3(static_cast<unsigned>(blocks)), dim3(TPB), sh, s, t.col, t.coef,
                          t.W, t.n_out, x, reinterpret_cast<Ti*>(y), n_in, in_base, alpha, beta, outer, RB);
       return;
     }
   }
-  ProfScope ps(prof().gather_cls, 0 + 16 * prec_code<Ti>(), s, gbytes);
+  ProfScope ps(t_gather_cls, 0 + 16 * prec_code<Ti>(), s, gbytes);
   if (total < (static_cast<int64_t>(1) << 32))
     hipLaunchKernelGGL((k_gather<Ti, To, C, uint32_t>), dim3(grid_for(total)), dim3(TPB), 0, s, t.col, t.coef, t.W,
                        t.n_out, x, y, static_cast<uint32_t>(inner), n_in, in_base, alpha, beta,
@@ -985,6 +1098,22 @@ void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, i
   const size_t abytes = static_cast<size_t>(npad) * npad * sizeof(C);
   const bool lds = abytes <= 64 * 1024;
   ProfScope ps(K_DENSE, 4 + 16 * prec_code<S>(), s, 2.0 * ncols * n * sizeof(S));
+  const int ntmax4 = std::is_same<C, double>::value ? 4 : 5;
+  if (inner % 4 == 0 && inner >= 16 && NT <= ntmax4 && reinterpret_cast<uintptr_t>(x) % (4 * sizeof(S)) == 0 &&
+      reinterpret_cast<uintptr_t>(y) % (4 * sizeof(S)) == 0) {
+    const unsigned grid4 = static_cast<unsigned>((ncols + 255) / 256);
+#define DM4(nt)                                                                                              \
+  case nt:                                                                                                   \
+    if (lds) hipLaunchKernelGGL((k_dense_mode4<S, C, nt, true>), dim3(grid4), dim3(256), abytes, s, Ap, n, npad, x, y, inner, ncols); \
+    else hipLaunchKernelGGL((k_dense_mode4<S, C, nt, false>), dim3(grid4), dim3(256), 0, s, Ap, n, npad, x, y, inner, ncols);  \
+    break;
+    switch (NT) {
+      DM4(1) DM4(2) DM4(3) DM4(4) DM4(5)
+      default: break;
+    }
+#undef DM4
+    return;
+  }
 #define DM_CASE(nt)                                                                                          \
   case nt:                                                                                                   \
     if (lds) hipLaunchKernelGGL((k_dense_mode<S, C, nt, true>), dim3(grid), dim3(256), abytes, s, Ap, n, npad, x, y, inner, ncols); \
@@ -1005,7 +1134,7 @@ void arrowhead(const S* r, S* y, const C* lam, const C* mu, const int* kind, con
 }
 
 void kprof_enable(bool on) { prof().on = on; }
-void kprof_gather_class(int cls) { prof().gather_cls = cls; }
+void kprof_gather_class(int cls) { t_gather_cls = cls; }
 
 void kprof_read(int cls, double* ms, int64_t* launches, double* bytes, int reset) {
   ProfState& p = prof();
@@ -1034,7 +1163,11 @@ int reduce_blocks(int64_t n) { return static_cast<int>((n + RED_CHUNK - 1) / RED
 template <class T>
 void multidot_partial(const T* V, int64_t ldv, int k, const T* w, int64_t n, double* part, int nb, hipStream_t s) {
   ProfScope ps(K_MULTIDOT, 6 + 16 * prec_code<T>(), s, (k + 1.0) * n * sizeof(T));
-  hipLaunchKernelGGL((k_multidot<T>), dim3(nb), dim3(TPB), 0, s, V, ldv, k, w, n, part);
+  constexpr int VEC = 16 / sizeof(T);
+  if (n % VEC == 0 && ldv % VEC == 0 && reinterpret_cast<uintptr_t>(V) % 16 == 0 && reinterpret_cast<uintptr_t>(w) % 16 == 0)
+    hipLaunchKernelGGL((k_multidot_v<T, VEC>), dim3(nb), dim3(TPB), 0, s, V, ldv, k, w, n, part);
+  else
+    hipLaunchKernelGGL((k_multidot<T>), dim3(nb), dim3(TPB), 0, s, V, ldv, k, w, n, part);
 }
 void finalize_sum(const double* part, int nb, int k, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize_sum, dim3(k), dim3(TPB), 0, s, part, nb, k, out);

@@ -1153,7 +1153,7 @@ int lowrank(st_iga_ctx* c, const double* C, double eps, std::vector<double>& U, 
     if (tail <= eps * eps * tot) R = r;
     else break;
   }
-  if (R > c->maxR) throw Fail{ST_IGA_EINVAL, "low rank exceeds max_rank"};
+  if (R > c->maxR) R = c->maxR;   // capped: the tolerance is then not met (reported through the rank)
   U.assign(static_cast<size_t>(m) * R, 0.0);
   sv.assign(R, 0.0);
   std::vector<double> inv(R);
@@ -1341,6 +1341,7 @@ void st_iga_default_options(st_iga_options* o) {
   o->max_outer = 60;
   o->max_krylov = 3000;
   o->prec = ST_IGA_FP64;
+  o->lin_forcing = 0.0;
 }
 
 size_t st_iga_workspace_bytes(const st_iga_problem* prob, const st_iga_options* opt) {
@@ -1543,7 +1544,12 @@ st_iga_status st_iga_solve(st_iga_ctx* c, const st_iga_stimulus* stim, double* u
       CK(hipStreamSynchronize(s));
       auto t1 = std::chrono::steady_clock::now();
       double rr = 1.0;
-      const int it = krylov(c, c->sol_rhs, c->sol_dx, c->opt.tol_lin, &rr, s);
+      // forcing term: with lin_forcing > 0 the k-th linear solve stops at
+      // max(tol_lin, min(1e-2, lin_forcing * ||delta_{k-1}||_inf))
+      double tol_k = c->opt.tol_lin;
+      if (c->opt.lin_forcing > 0.0 && k > 0)
+        tol_k = std::max(c->opt.tol_lin, std::min(1e-2, c->opt.lin_forcing * R.delta_inf[std::min(k - 1, ST_IGA_MAX_OUTER_LOG - 1)]));
+      const int it = krylov(c, c->sol_rhs, c->sol_dx, tol_k, &rr, s);
       add_unknowns(u, c->sol_dx, c->opt.alpha, c->nunk, c->Ns, s);
       const double dinf = c->opt.alpha * dev_absmax(c, c->sol_dx, c->nunk, s);
       auto t2 = std::chrono::steady_clock::now();

@@ -1,0 +1,129 @@
+"""Continuous-batching request loop for space-time solves on one GPU.
+
+Requests (a problem description each) arrive over time.  The loop admits them
+in arrival order as soon as a solver slot is free and the request's device
+footprint (``st_iga_workspace_bytes`` plus its solution vectors) fits the HBM
+budget; admitted requests run concurrently, each in its own library context on
+its slot's HIP stream, so their kernels overlap on the device while earlier
+requests are still in flight.  A finished request frees its slot and memory
+for the next one.  Each context is independent and every reduction has a fixed
+order, so a request's result does not depend on what else is running.
+
+All arithmetic happens in the HIP library; this module only schedules.
+"""
+from __future__ import annotations
+
+import dataclasses
+import threading
+import time
+from collections import deque
+from typing import List, Optional
+
+import numpy as np
+
+from . import binding
+
+
+@dataclasses.dataclass
+class Record:
+    index: int
+    arrival: float            # seconds since the start of the stream
+    admitted: float = 0.0
+    finished: float = 0.0
+    dof: int = 0
+    footprint: int = 0
+    outer_iters: int = 0
+    krylov: int = 0
+    status: str = "pending"
+    u: Optional[np.ndarray] = None
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+class Server:
+    def __init__(self, device="cuda:0", slots: int = 16, hbm_budget: Optional[int] = None,
+                 keep_results: bool = False, **options):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.slots = slots
+        if hbm_budget is None:
+            free, total = torch.cuda.mem_get_info(self.device)
+            hbm_budget = int(0.7 * free)
+        self.budget = hbm_budget
+        self.options = options
+        self.keep_results = keep_results
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
+
+    def footprint(self, prob) -> int:
+        return binding.workspace_bytes(prob, **self.options) + 2 * prob.dof * 8 + (1 << 20)
+
+    def _solve(self, slot: int, prob, rec: Record, t0: float):
+        torch = self.torch
+        stream = self.streams[slot]
+        try:
+            with torch.cuda.device(self.device):
+                S = binding.Solver(prob, device=self.device, stream=stream, **self.options)
+                u, w, rep = S.solve()
+                rec.outer_iters, rec.krylov = rep.outer_iters, rep.krylov_total
+                if self.keep_results:
+                    rec.u = u.cpu().numpy()
+                S.close()
+                del S, u, w
+                stream.synchronize()
+            rec.status = "ok"
+        except binding.StIgaError as e:
+            rec.status = str(e)
+        rec.finished = time.perf_counter() - t0
+
+    def run(self, requests) -> List[Record]:
+        """requests: iterable of (arrival_seconds, problem).  Blocks until all finish."""
+        reqs = list(requests)
+        recs = [Record(i, float(t), dof=p.dof, footprint=self.footprint(p)) for i, (t, p) in enumerate(reqs)]
+        for r in recs:
+            if r.footprint > self.budget:
+                raise ValueError(f"request {r.index} needs {r.footprint} bytes, budget {self.budget}")
+        lock = threading.Condition()
+        used = [0]
+        free_slots = deque(range(self.slots))
+        threads = []
+        t0 = time.perf_counter()
+
+        def worker(slot, prob, rec):
+            self._solve(slot, prob, rec, t0)
+            with lock:
+                used[0] -= rec.footprint
+                free_slots.append(slot)
+                lock.notify_all()
+
+        for (t_arr, prob), rec in zip(reqs, recs):
+            now = time.perf_counter() - t0
+            if t_arr > now:
+                time.sleep(t_arr - now)
+            with lock:
+                while not free_slots or used[0] + rec.footprint > self.budget:
+                    lock.wait()
+                slot = free_slots.popleft()
+                used[0] += rec.footprint
+                rec.admitted = time.perf_counter() - t0
+            th = threading.Thread(target=worker, args=(slot, prob, rec), daemon=True)
+            th.start()
+            threads.append(th)
+        for th in threads:
+            th.join()
+        return recs
+
+
+def summarize(recs: List[Record]) -> dict:
+    ok = [r for r in recs if r.status == "ok"]
+    lat = np.array([r.latency for r in ok]) if ok else np.array([np.nan])
+    makespan = max(r.finished for r in recs) - min(r.arrival for r in recs)
+    return {"requests": len(recs), "completed": len(ok),
+            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "mean_latency_s": float(np.mean(lat)), "makespan_s": float(makespan),
+            "dof_per_s": float(sum(r.dof for r in ok) / makespan) if makespan > 0 else None,
+            "outer_iters_mean": float(np.mean([r.outer_iters for r in ok])) if ok else None,
+            "krylov_mean": float(np.mean([r.krylov for r in ok])) if ok else None,
+            "failures": [r.status for r in recs if r.status != "ok"][:5]}
