@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--max-rank", type=int, default=None,
+                    help="cap of each low rank (default 48; 16 for config 4 to fit HBM)")
     ap.add_argument("--serve", action="store_true", help="run only the serving stream (512 requests)")
     ap.add_argument("--serve-requests", type=int, default=128,
                     help="requests of the serving stream sampled in the default run (0: skip)")
@@ -60,10 +62,16 @@ def serving(n_requests, slots):
     return out
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def time_region(torch, S, u1, u2, w, steps, warmup, tol):
     """Warm up, then time exactly `steps` steps between synchronizations."""
     for _ in range(warmup):
         S.newton_step(u1, u2, w, True, tol)
+        log("warmup step done")
     torch.cuda.synchronize()
     S.profile(True)
     S.profile_read(reset=True)
@@ -77,6 +85,7 @@ def time_region(torch, S, u1, u2, w, steps, warmup, tol):
         it, r, dinf = S.newton_step(u1, u2, w, True, tol)
         its.append(it)
         rr.append(r)
+        log(f"step: {it} Krylov iterations, relres {r:.2e}")
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -137,26 +146,58 @@ def main():
         return
 
     prob = W.config(a.config)
+    if a.max_rank is None:
+        a.max_rank = 16 if a.config == 4 else 48
     prec_code = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}[a.prec]
     prec_bytes = {"fp64": 8, "mixed_fp32": 4, "mixed_bf16": 2}[a.prec]
 
     # the fixed state u^1: one FP64 Newton step from the lifted datum
-    S64 = Solver(prob, prec=FP64, tol_lin=a.tol)
+    S64 = Solver(prob, prec=FP64, tol_lin=a.tol, max_rank=a.max_rank)
     c0, _ = S64.lift()
     u0 = torch.tensor(np.tile(c0, prob.n_t), dtype=torch.float64, device="cuda:0")
     u1, w = S64.vec(S64.full), S64.vec(S64.full)
+    log(f"config {a.config}: {prob.dof} DOF, workspace {S64.workspace_bytes / 1e9:.1f} GB (FP64)")
     S64.newton_step(u0, u1, w, True, a.tol)
+    log("state u1 ready")
     u2 = S64.vec(S64.full)
     torch.cuda.synchronize()
 
+    def solve_only(S):
+        """The linear solve alone (the Krylov part of the step) on the same system."""
+        S.linearize(u1, w, True)
+        b = -S.residual(u1, w)
+        x = S.vec()
+        for _ in range(a.warmup):
+            S.krylov(b, a.tol, x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            _, its, rr = S.krylov(b, a.tol, x)
+        e1.record()
+        torch.cuda.synchronize()
+        sm = e0.elapsed_time(e1) / a.steps
+        return {"ms": sm, "dof_per_s": prob.dof / (sm / 1e3), "krylov_iters": its, "relres": rr}
+
     res = {}
+    solve = {}
     if a.prec == "fp64" or not a.no_fp64_compare:
         ms, wall, its, rr, prof = time_region(torch, S64, u1, u2, w, a.steps, a.warmup, a.tol)
         res["fp64"] = dict(ms=ms, wall=wall, its=its, rr=rr, prof=prof, S=S64)
+        log("fp64 Newton steps timed")
+        solve["fp64"] = solve_only(S64)
+        log("fp64 solve-only timed")
     if a.prec != "fp64":
-        Sm = Solver(prob, prec=prec_code, tol_lin=a.tol)
+        # one large context at a time: release the FP64 workspace first
+        S64.close()
+        S64.ws = None
+        torch.cuda.empty_cache()
+        Sm = Solver(prob, prec=prec_code, tol_lin=a.tol, max_rank=a.max_rank)
         ms, wall, its, rr, prof = time_region(torch, Sm, u1, u2, w, a.steps, a.warmup, a.tol)
         res[a.prec] = dict(ms=ms, wall=wall, its=its, rr=rr, prof=prof, S=Sm)
+        log(f"{a.prec} Newton steps timed")
+        solve[a.prec] = solve_only(Sm)
+        log(f"{a.prec} solve-only timed")
     main_r = res[a.prec]
     ms = main_r["ms"]
     value = prob.dof / (ms / 1e3)
@@ -188,24 +229,6 @@ def main():
         "wall_ms_per_step": main_r["wall"],
         "roofline": roof,
     }
-    # linear solve alone (the Krylov part of the step), same system
-    solve = {}
-    for name, r in res.items():
-        S = r["S"]
-        S.linearize(u1, w, True)
-        b = -S.residual(u1, w)
-        x = S.vec()
-        for _ in range(a.warmup):
-            S.krylov(b, a.tol, x)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(a.steps):
-            _, its, rr = S.krylov(b, a.tol, x)
-        e1.record()
-        torch.cuda.synchronize()
-        sm = e0.elapsed_time(e1) / a.steps
-        solve[name] = {"ms": sm, "dof_per_s": prob.dof / (sm / 1e3), "krylov_iters": its, "relres": rr}
     if len(solve) == 2:
         solve["speedup_mixed_vs_fp64"] = solve["fp64"]["ms"] / solve[a.prec]["ms"]
     out["linear_solve_only"] = solve
@@ -217,11 +240,14 @@ def main():
         out["speedup_vs_fp64"] = f["ms"] / ms
     if a.serve_requests > 0:
         for r in res.values():         # release the single-solve workspaces first
-            r["S"].close()
+            if r["S"].ctx:
+                r["S"].close()
             r["S"].ws = None
         torch.cuda.empty_cache()
+        log("serving sample")
         out["serving"] = serving(a.serve_requests, a.serve_slots)
     if not a.no_cpu_baseline:
+        log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(a.config)
     print(json.dumps(out), flush=True)
 

@@ -91,6 +91,7 @@ typedef struct {
   int32_t max_krylov;        /* Krylov iteration cap per linear solve */
   st_iga_precision prec;
   double lin_forcing;        /* > 0: outer iteration k solves to max(tol_lin, min(1e-2, lin_forcing*||delta_{k-1}||_inf)) */
+  int32_t coef_slab;         /* time rows per slab of the low-rank operator terms (0: automatic) */
 } st_iga_options;
 
 #define ST_IGA_MAX_OUTER_LOG 64
@@ -109,7 +110,8 @@ typedef struct {
 
 /* Defaults: su=1, eps_theta=0.1, eps_react=1e-2, max_rank=48, outer=0,
  * alpha=1 (Newton), theta_freeze=1e-4, tol_nonlin=1e-10, tol_lin=1e-10,
- * inner_tol=1e-4, restart=30, max_outer=60, max_krylov=3000, prec=FP64, lin_forcing=0. */
+ * inner_tol=1e-4, restart=30, max_outer=60, max_krylov=3000, prec=FP64, lin_forcing=0,
+ * coef_slab=0. */
 void st_iga_default_options(st_iga_options* opt);
 
 /* Bytes of device workspace st_iga_setup needs for this problem/options
@@ -236,7 +238,10 @@ const char* st_iga_last_error(const st_iga_ctx* ctx);
  * (K_l, M_l) (n); 6 eigenvectors U_l (n*n, row-major); 7 time FD: U_t (N_t*N_t)
  * then block values (N_t-1), arrow l (N_t-1), sigma (1); 8 Gauss points of dir
  * (Q) then weights (Q); 9 first-basis index of each Gauss point of dir (Q, as
- * doubles); 10 support-extension element windows of dir ([e0, e1) pairs).
+ * doubles); 10 support-extension element windows of dir ([e0, e1) pairs);
+ * 11 plan of the fused coefficient kernel along the slowest spatial axis
+ * (dir ignored): {enabled, time rows per slab, nchunk, then nchunk x
+ * {first element, end element, first B-spline, end B-spline}}.
  * Writes at most `cap` doubles to out and the needed length to *len. */
 st_iga_status st_iga_host_query(const st_iga_problem* prob, int32_t what, int32_t dir, double* out,
                                 int64_t cap, int64_t* len);

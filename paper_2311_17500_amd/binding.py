@@ -43,7 +43,7 @@ class Options(C.Structure):
                 ("outer", C.c_int32), ("alpha", C.c_double), ("theta_freeze", C.c_double),
                 ("tol_nonlin", C.c_double), ("tol_lin", C.c_double), ("inner_tol", C.c_double),
                 ("restart", C.c_int32), ("max_outer", C.c_int32), ("max_krylov", C.c_int32), ("prec", C.c_int32),
-                ("lin_forcing", C.c_double)]
+                ("lin_forcing", C.c_double), ("coef_slab", C.c_int32)]
 
 
 LOG = 64
@@ -289,7 +289,7 @@ class Solver:
         return it.value, rr.value, dinf.value
 
     KCLASSES = ["gather", "time_mix", "arrowhead", "multidot", "update_norm", "pointwise_ionic", "maxima",
-                "banded", "expand", "dense_fd"]
+                "banded", "expand", "dense_fd", "coefficient"]
 
     def profile(self, on=True):
         self._chk(self.lib.st_iga_profile(self.ctx, int(on)))
@@ -302,7 +302,7 @@ class Solver:
             self._chk(self.lib.st_iga_profile_read(self.ctx, k, C.byref(ms), C.byref(n), C.byref(by), 0))
             out[name] = (ms.value, n.value, by.value)
         fnames = ["gather_scalar", "gather_v4", "gather_rows", "time_mix", "dense_mode_mfma", "arrowhead",
-                  "multidot", "update_norm", "pointwise_ionic", "mode_max", "gather_sweep"]
+                  "multidot", "update_norm", "pointwise_ionic", "mode_max", "gather_sweep", "coef_fused"]
         for q, pn in enumerate(["f64", "f32", "bf16"]):
             for f, fname in enumerate(fnames):
                 ms, n, by = C.c_double(0), C.c_int64(0), C.c_double(0)

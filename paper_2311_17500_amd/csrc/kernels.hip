@@ -394,8 +394,8 @@ __global__ void __launch_bounds__(TPB) k_mode_max(const int* __restrict__ start,
 // ---------------------------------------------------------------- time mixing
 template <class S, class C, int P>
 __global__ void __launch_bounds__(TPB) k_time_mix(const C* __restrict__ T, const S* __restrict__ Psi, int r0, int R,
-                                                  int Nt, const S* __restrict__ Z, int n_in, int in_base,
-                                                  S* __restrict__ out, int64_t Qs) {
+                                                  int Nt, int t0, int t1, const S* __restrict__ Z, int n_in,
+                                                  int in_base, S* __restrict__ out, int64_t Qs) {
   extern __shared__ char smem_raw[];
   C* ps = reinterpret_cast<C*>(smem_raw);
   const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -405,10 +405,10 @@ __global__ void __launch_bounds__(TPB) k_time_mix(const C* __restrict__ T, const
   C win[WB];
 #pragma unroll
   for (int w = 0; w < WB; ++w) {
-    const int j = 1 - P + w - in_base;
+    const int j = t0 + 1 - P + w - in_base;
     win[w] = (static_cast<unsigned>(j) < static_cast<unsigned>(n_in)) ? to_c(Z[static_cast<int64_t>(j) * Qs + q], C(0)) : C(0);
   }
-  for (int t = 0; t < Nt; ++t) {
+  for (int t = t0; t < t1; ++t) {
     C acc = C(0);
     for (int r = 0; r < R; ++r) {
       const C* Tr = T + (static_cast<int64_t>(r0 + r) * Nt + t) * WB;
@@ -417,11 +417,129 @@ __global__ void __launch_bounds__(TPB) k_time_mix(const C* __restrict__ T, const
       for (int w = 0; w < WB; ++w) s += Tr[w] * win[w];
       acc += ps[r * blockDim.x + threadIdx.x] * s;
     }
-    out[static_cast<int64_t>(t) * Qs + q] = from_c<S>(acc);
+    out[static_cast<int64_t>(t - t0) * Qs + q] = from_c<S>(acc);
 #pragma unroll
     for (int w = 0; w < WB - 1; ++w) win[w] = win[w + 1];
     const int j = t + 2 + P - in_base;
     win[WB - 1] = (static_cast<unsigned>(j) < static_cast<unsigned>(n_in)) ? to_c(Z[static_cast<int64_t>(j) * Qs + q], C(0)) : C(0);
+  }
+}
+
+
+// ---------------------------------------------------------------- fused coefficient terms
+// The low-rank coefficient terms along the slowest spatial axis in one pass:
+// expansion of the input to the axis' Gauss points, the time mixing with the
+// rank weights (as in k_time_mix) and the projection back onto the axis'
+// B-splines, without storing Gauss-point arrays.  Z and out have layout
+// [layer][nd][Qin] (Qin = Gauss points of the faster axes, already expanded).
+// A thread owns one column c, TS consecutive output rows (blockIdx.y) and
+// the B-spline range [d0, d1) of chunk blockIdx.z, whose elements are
+// [e0, e1).  It walks the elements in order with a ring of the KP = p + 1
+// input B-spline rows an element touches (each over the NL input layers the
+// rows' time windows read) and a ring of their partial outputs; a B-spline is
+// complete, and stored, once the walk has passed its last element.
+template <class S, class C, int P, int KP, int TS>
+__global__ void __launch_bounds__(256) k_coef_fused(const C* __restrict__ T, const S* __restrict__ Psi, int r0, int R,
+                                                    int Nt, int t0, int t1, const S* __restrict__ Z, int n_in,
+                                                    int in_base, const C* __restrict__ Bl,
+                                                    const int* __restrict__ efirst, const int* __restrict__ chunks,
+                                                    int nd, int64_t Qin, S* __restrict__ out, int64_t Qs) {
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= Qin) return;
+  constexpr int WB = 2 * P + 1, NL = TS + 2 * P;
+  const int ta = t0 + static_cast<int>(blockIdx.y) * TS;
+  const int e0 = chunks[4 * blockIdx.z], e1 = chunks[4 * blockIdx.z + 1];
+  const int d0 = chunks[4 * blockIdx.z + 2], d1 = chunks[4 * blockIdx.z + 3];
+  const int nrow = min(TS, t1 - ta);
+  const int64_t lay = static_cast<int64_t>(nd) * Qin;
+  const int jb = ta + 1 - P - in_base;   // input layer of window slot 0
+  C zr[KP][NL], yr[KP][TS];
+  int f = efirst[e0];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int dof = f + k;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const int j = jb + l;
+      zr[k][l] = (static_cast<unsigned>(j) < static_cast<unsigned>(n_in) && dof < nd)
+                     ? to_c(Z[j * lay + static_cast<int64_t>(dof) * Qin + c], C(0))
+                     : C(0);
+    }
+#pragma unroll
+    for (int t = 0; t < TS; ++t) yr[k][t] = C(0);
+  }
+  for (int e = e0; e < e1; ++e) {
+    const int fn = efirst[e];
+    for (; f < fn; ++f) {
+      if (f >= d0 && f < d1) {
+        S* o = out + static_cast<int64_t>(ta - t0) * lay + static_cast<int64_t>(f) * Qin + c;
+#pragma unroll
+        for (int t = 0; t < TS; ++t)
+          if (t < nrow) o[t * lay] = from_c<S>(yr[0][t]);
+      }
+#pragma unroll
+      for (int k = 0; k < KP - 1; ++k) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) zr[k][l] = zr[k + 1][l];
+#pragma unroll
+        for (int t = 0; t < TS; ++t) yr[k][t] = yr[k + 1][t];
+      }
+      const int dof = f + KP;
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        const int j = jb + l;
+        zr[KP - 1][l] = (static_cast<unsigned>(j) < static_cast<unsigned>(n_in) && dof < nd)
+                            ? to_c(Z[j * lay + static_cast<int64_t>(dof) * Qin + c], C(0))
+                            : C(0);
+      }
+#pragma unroll
+      for (int t = 0; t < TS; ++t) yr[KP - 1][t] = C(0);
+    }
+#pragma unroll
+    for (int g = 0; g < KP; ++g) {
+      const int qd = e * KP + g;
+      C b[KP];
+#pragma unroll
+      for (int k = 0; k < KP; ++k) b[k] = Bl[qd * KP + k];
+      C zg[NL];
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        C v = C(0);
+#pragma unroll
+        for (int k = 0; k < KP; ++k) v += b[k] * zr[k][l];
+        zg[l] = v;
+      }
+      C m[TS];
+#pragma unroll
+      for (int t = 0; t < TS; ++t) m[t] = C(0);
+      const S* ps = Psi + static_cast<int64_t>(r0) * Qs + static_cast<int64_t>(qd) * Qin + c;
+      for (int r = 0; r < R; ++r) {
+        const C psi = to_c(ps[static_cast<int64_t>(r) * Qs], C(0));
+        const C* Tr = T + static_cast<int64_t>(r0 + r) * Nt * WB;
+#pragma unroll
+        for (int t = 0; t < TS; ++t) {
+          const C* Tt = Tr + min(ta + t, Nt - 1) * WB;
+          C sacc = C(0);
+#pragma unroll
+          for (int w = 0; w < WB; ++w) sacc += Tt[w] * zg[t + w];
+          m[t] += psi * sacc;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < KP; ++k)
+#pragma unroll
+        for (int t = 0; t < TS; ++t) yr[k][t] += b[k] * m[t];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int dof = f + k;
+    if (dof >= d0 && dof < d1 && dof < nd) {
+      S* o = out + static_cast<int64_t>(ta - t0) * lay + static_cast<int64_t>(dof) * Qin + c;
+#pragma unroll
+      for (int t = 0; t < TS; ++t)
+        if (t < nrow) o[t * lay] = from_c<S>(yr[k][t]);
+    }
   }
 }
 
@@ -491,11 +609,11 @@ __global__ void __launch_bounds__(256) k_dense_mode(const C* __restrict__ Ap, in
 }
 
 
-// Variant for inner % 4 == 0: a wave owns 64 columns as four 16-column MFMA
-// tiles; lane l feeds columns c0 + 4(l%16) + e of tile e from one 4-wide load
-// and stores the four results of a row with one 4-wide store.
-template <class S, class C, int NT, bool LDS_A>
-__global__ void __launch_bounds__(256) k_dense_mode4(const C* __restrict__ Ap, int n, int npad,
+// Variant for inner % E == 0 (E = 2 or 4): a wave owns 16E columns as E
+// 16-column MFMA tiles; lane l feeds columns c0 + E(l%16) + e of tile e from
+// one E-wide load and stores the E results of a row with one E-wide store.
+template <class S, class C, int NT, int E, bool LDS_A>
+__global__ void __launch_bounds__(256) k_dense_modeE(const C* __restrict__ Ap, int n, int npad,
                                                      const S* __restrict__ x, S* __restrict__ y, int64_t inner,
                                                      int64_t ncols) {
   extern __shared__ char smem_raw[];
@@ -507,29 +625,29 @@ __global__ void __launch_bounds__(256) k_dense_mode4(const C* __restrict__ Ap, i
   const C* Asrc = LDS_A ? As : Ap;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
-  const int64_t c = (static_cast<int64_t>(blockIdx.x) * 4 + wv) * 64 + 4 * r16;
+  const int64_t c = (static_cast<int64_t>(blockIdx.x) * 4 + wv) * (16 * E) + E * r16;
   const bool cv = c < ncols;
   const int64_t o = cv ? c / inner : 0;
   const int64_t kq = cv ? c - o * inner : 0;
   const S* xb = x + o * static_cast<int64_t>(n) * inner + kq;
   typedef typename Acc4<C>::T A4;
-  A4 acc[NT][4];
+  A4 acc[NT][E];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) acc[t][e] = A4{0, 0, 0, 0};
+    for (int e = 0; e < E; ++e) acc[t][e] = A4{0, 0, 0, 0};
   for (int kk = 0; kk < npad; kk += 4) {
     const int j = kk + q4;
-    C b[4];
+    C b[E];
     const bool ok = cv && j < n;
-    loadv<4, S, C>(xb + static_cast<int64_t>(ok ? j : 0) * inner, b);
+    loadv<E, S, C>(xb + static_cast<int64_t>(ok ? j : 0) * inner, b);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) b[e] = ok ? b[e] : C(0);
+    for (int e = 0; e < E; ++e) b[e] = ok ? b[e] : C(0);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const C a = Asrc[(t * 16 + r16) * npad + j];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) acc[t][e] = mfma16x16x4(a, b[e], acc[t][e]);
+      for (int e = 0; e < E; ++e) acc[t][e] = mfma16x16x4(a, b[e], acc[t][e]);
     }
   }
   if (!cv) return;
@@ -540,10 +658,10 @@ __global__ void __launch_bounds__(256) k_dense_mode4(const C* __restrict__ Ap, i
     for (int v = 0; v < 4; ++v) {
       const int i = t * 16 + (std::is_same<C, double>::value ? q4 + 4 * v : 4 * q4 + v);
       if (i < n) {
-        C r[4];
+        C r[E];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) r[e] = acc[t][e][v];
-        storev<4, S, C>(yb + static_cast<int64_t>(i) * inner, r);
+        for (int e = 0; e < E; ++e) r[e] = acc[t][e][v];
+        storev<E, S, C>(yb + static_cast<int64_t>(i) * inner, r);
       }
     }
 }
@@ -671,8 +789,9 @@ __global__ void __launch_bounds__(TPB) k_multidot(const T* __restrict__ V, int64
 }
 
 
-// Vector-load variant (n % VEC == 0, 16-byte aligned): loads are clamped and
-// unconditional so a thread issues all of them before accumulating.
+// Vector-load variant (16-byte aligned columns): loads are clamped and
+// unconditional so a thread issues all of them before accumulating.  The
+// n % VEC trailing elements are added by the first threads of block 0.
 template <class T, int VEC>
 __global__ void __launch_bounds__(TPB) k_multidot_v(const T* __restrict__ V, int64_t ldv, int k,
                                                     const T* __restrict__ w, int64_t n, double* __restrict__ part) {
@@ -680,12 +799,16 @@ __global__ void __launch_bounds__(TPB) k_multidot_v(const T* __restrict__ V, int
   constexpr int NV = RED_E / VEC;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t base = static_cast<int64_t>(blockIdx.x) * RED_CHUNK + static_cast<int64_t>(threadIdx.x) * VEC;
+  const int64_t nv = n - n % VEC;
+  const int64_t it = nv + threadIdx.x;   // tail element of this thread (block 0)
+  const bool tail = blockIdx.x == 0 && it < n;
+  const double wt = tail ? static_cast<double>(w[it]) : 0.0;
   double wr[NV][VEC];
   int64_t ic[NV];
 #pragma unroll
   for (int e = 0; e < NV; ++e) {
     const int64_t i = base + static_cast<int64_t>(e) * TPB * VEC;
-    const bool ok = i < n;
+    const bool ok = i < nv;
     ic[e] = ok ? i : 0;
     double t[VEC];
     loadv<VEC, T, double>(w + ic[e], t);
@@ -707,6 +830,7 @@ __global__ void __launch_bounds__(TPB) k_multidot_v(const T* __restrict__ V, int
 #pragma unroll
         for (int q = 0; q < VEC; ++q) acc[jj] += t[q] * wr[e][q];
       }
+      if (tail) acc[jj] += static_cast<double>(Vj[it]) * wt;
     }
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj) acc[jj] = wave_sum(acc[jj]);
@@ -1071,23 +1195,56 @@ void mode_max(const int* start, const int* cnt, int n_out, const double* x, doub
 }
 
 template <class S, class C>
-void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int p, const S* Z, int n_in, int in_base, S* out,
-              int64_t Qs, hipStream_t s) {
+void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1, int p, const S* Z, int n_in,
+              int in_base, S* out, int64_t Qs, hipStream_t s) {
   const int R = r1 - r0;
   int tpb = TPB;
   while (tpb > 64 && static_cast<size_t>(R) * tpb * sizeof(C) > 64 * 1024) tpb /= 2;
   const size_t sh = static_cast<size_t>(R > 0 ? R : 1) * tpb * sizeof(C);
   const dim3 g(grid_for(Qs, tpb)), b(tpb);
-  ProfScope ps(K_TIME_MIX, 3 + 16 * prec_code<S>(), s, (static_cast<double>(n_in) + R + Nt) * Qs * sizeof(S));
+  ProfScope ps(K_TIME_MIX, 3 + 16 * prec_code<S>(), s, (static_cast<double>(n_in) + R + (t1 - t0)) * Qs * sizeof(S));
   switch (p) {
-    case 1: hipLaunchKernelGGL((k_time_mix<S, C, 1>), g, b, sh, s, T, Psi, r0, R, Nt, Z, n_in, in_base, out, Qs); break;
-    case 2: hipLaunchKernelGGL((k_time_mix<S, C, 2>), g, b, sh, s, T, Psi, r0, R, Nt, Z, n_in, in_base, out, Qs); break;
-    case 3: hipLaunchKernelGGL((k_time_mix<S, C, 3>), g, b, sh, s, T, Psi, r0, R, Nt, Z, n_in, in_base, out, Qs); break;
-    case 4: hipLaunchKernelGGL((k_time_mix<S, C, 4>), g, b, sh, s, T, Psi, r0, R, Nt, Z, n_in, in_base, out, Qs); break;
-    default: hipLaunchKernelGGL((k_time_mix<S, C, 5>), g, b, sh, s, T, Psi, r0, R, Nt, Z, n_in, in_base, out, Qs); break;
+    case 1: hipLaunchKernelGGL((k_time_mix<S, C, 1>), g, b, sh, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, out, Qs); break;
+    case 2: hipLaunchKernelGGL((k_time_mix<S, C, 2>), g, b, sh, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, out, Qs); break;
+    case 3: hipLaunchKernelGGL((k_time_mix<S, C, 3>), g, b, sh, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, out, Qs); break;
+    case 4: hipLaunchKernelGGL((k_time_mix<S, C, 4>), g, b, sh, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, out, Qs); break;
+    default: hipLaunchKernelGGL((k_time_mix<S, C, 5>), g, b, sh, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, out, Qs); break;
   }
 }
 
+template <class S, class C>
+bool coef_fused(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1, int pt, int ps, const S* Z,
+                int n_in, int in_base, const C* Bl, const int* efirst, const int* chunks, int nchunk, int nd,
+                int64_t Qin, S* out, int64_t Qs, hipStream_t s) {
+  // output rows per thread: 8 in FP32, 4 in FP64 (register rings of the same size)
+  constexpr int TS = std::is_same<C, double>::value ? 4 : 8;
+  if (pt < 1 || pt > 5 || ps < 1 || ps > 4) return false;
+  if (t1 <= t0 || Qin == 0) return true;
+  const int R = r1 - r0;
+  const dim3 g(static_cast<unsigned>((Qin + TPB - 1) / TPB), static_cast<unsigned>((t1 - t0 + TS - 1) / TS),
+               static_cast<unsigned>(nchunk));
+  const double rows = static_cast<double>(t1 - t0);
+  ProfScope pr(K_COEF, 11 + 16 * prec_code<S>(), s,
+               (static_cast<double>(n_in) * nd * Qin + rows * nd * Qin + static_cast<double>(R) * Qs) * sizeof(S));
+#define CF(P_, K_) hipLaunchKernelGGL((k_coef_fused<S, C, P_, K_, TS>), g, dim3(TPB), 0, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, Bl, efirst, chunks, nd, Qin, out, Qs)
+#define CFP(P_)                 \
+  switch (ps) {                 \
+    case 1: CF(P_, 2); break;   \
+    case 2: CF(P_, 3); break;   \
+    case 3: CF(P_, 4); break;   \
+    default: CF(P_, 5); break;  \
+  }
+  switch (pt) {
+    case 1: CFP(1); break;
+    case 2: CFP(2); break;
+    case 3: CFP(3); break;
+    case 4: CFP(4); break;
+    default: CFP(5); break;
+  }
+#undef CFP
+#undef CF
+  return true;
+}
 
 template <class S, class C>
 void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, int64_t inner, hipStream_t s) {
@@ -1098,20 +1255,32 @@ void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, i
   const size_t abytes = static_cast<size_t>(npad) * npad * sizeof(C);
   const bool lds = abytes <= 64 * 1024;
   ProfScope ps(K_DENSE, 4 + 16 * prec_code<S>(), s, 2.0 * ncols * n * sizeof(S));
-  const int ntmax4 = std::is_same<C, double>::value ? 4 : 5;
-  if (inner % 4 == 0 && inner >= 16 && NT <= ntmax4 && reinterpret_cast<uintptr_t>(x) % (4 * sizeof(S)) == 0 &&
-      reinterpret_cast<uintptr_t>(y) % (4 * sizeof(S)) == 0) {
-    const unsigned grid4 = static_cast<unsigned>((ncols + 255) / 256);
-#define DM4(nt)                                                                                              \
-  case nt:                                                                                                   \
-    if (lds) hipLaunchKernelGGL((k_dense_mode4<S, C, nt, true>), dim3(grid4), dim3(256), abytes, s, Ap, n, npad, x, y, inner, ncols); \
-    else hipLaunchKernelGGL((k_dense_mode4<S, C, nt, false>), dim3(grid4), dim3(256), 0, s, Ap, n, npad, x, y, inner, ncols);  \
+  // columns per lane: 4 while the accumulators fit (FP32 up to 9 row tiles,
+  // FP64 up to 4), else 2; the E-wide loads need inner % E == 0 and aligned x, y
+  const bool f64 = std::is_same<C, double>::value;
+  const int ntmax4 = f64 ? 4 : 9;
+  auto aligned = [&](int e) {
+    return inner % e == 0 && inner >= 4 * e && reinterpret_cast<uintptr_t>(x) % (e * sizeof(S)) == 0 &&
+           reinterpret_cast<uintptr_t>(y) % (e * sizeof(S)) == 0;
+  };
+  const int E = (NT <= ntmax4 && aligned(4)) ? 4 : (NT <= 9 && aligned(2)) ? 2 : 1;
+  if (E > 1) {
+    const unsigned gridE = static_cast<unsigned>((ncols + 64 * E - 1) / (64 * E));
+#define DME(nt, e)                                                                                              \
+  case nt:                                                                                                      \
+    if (lds) hipLaunchKernelGGL((k_dense_modeE<S, C, nt, e, true>), dim3(gridE), dim3(256), abytes, s, Ap, n, npad, x, y, inner, ncols); \
+    else hipLaunchKernelGGL((k_dense_modeE<S, C, nt, e, false>), dim3(gridE), dim3(256), 0, s, Ap, n, npad, x, y, inner, ncols);  \
     break;
-    switch (NT) {
-      DM4(1) DM4(2) DM4(3) DM4(4) DM4(5)
-      default: break;
+    if (E == 4) {
+      if (f64) {
+        switch (NT) { DME(1, 4) DME(2, 4) DME(3, 4) DME(4, 4) default: break; }
+      } else {
+        switch (NT) { DME(1, 4) DME(2, 4) DME(3, 4) DME(4, 4) DME(5, 4) DME(6, 4) DME(7, 4) DME(8, 4) DME(9, 4) default: break; }
+      }
+    } else {
+      switch (NT) { DME(1, 2) DME(2, 2) DME(3, 2) DME(4, 2) DME(5, 2) DME(6, 2) DME(7, 2) DME(8, 2) DME(9, 2) default: break; }
     }
-#undef DM4
+#undef DME
     return;
   }
 #define DM_CASE(nt)                                                                                          \
@@ -1164,7 +1333,7 @@ template <class T>
 void multidot_partial(const T* V, int64_t ldv, int k, const T* w, int64_t n, double* part, int nb, hipStream_t s) {
   ProfScope ps(K_MULTIDOT, 6 + 16 * prec_code<T>(), s, (k + 1.0) * n * sizeof(T));
   constexpr int VEC = 16 / sizeof(T);
-  if (n % VEC == 0 && ldv % VEC == 0 && reinterpret_cast<uintptr_t>(V) % 16 == 0 && reinterpret_cast<uintptr_t>(w) % 16 == 0)
+  if (ldv % VEC == 0 && reinterpret_cast<uintptr_t>(V) % 16 == 0 && reinterpret_cast<uintptr_t>(w) % 16 == 0)
     hipLaunchKernelGGL((k_multidot_v<T, VEC>), dim3(nb), dim3(TPB), 0, s, V, ldv, k, w, n, part);
   else
     hipLaunchKernelGGL((k_multidot<T>), dim3(nb), dim3(TPB), 0, s, V, ldv, k, w, n, part);
@@ -1259,12 +1428,16 @@ template void gather<bf16, bf16, float>(const DTable<float>&, const bf16*, bf16*
                                         float, hipStream_t);
 template void gather_rows<double, double, double>(const DTable<double>&, int, int, const double*, double*, int64_t,
                                                   int64_t, int, int, double, double, hipStream_t);
-template void time_mix<double, double>(const double*, const double*, int, int, int, int, const double*, int, int,
-                                       double*, int64_t, hipStream_t);
-template void time_mix<float, float>(const float*, const float*, int, int, int, int, const float*, int, int, float*,
-                                     int64_t, hipStream_t);
-template void time_mix<bf16, float>(const float*, const bf16*, int, int, int, int, const bf16*, int, int, bf16*,
-                                    int64_t, hipStream_t);
+template bool coef_fused<double, double>(const double*, const double*, int, int, int, int, int, int, int,
+                                         const double*, int, int, const double*, const int*, const int*, int, int,
+                                         int64_t, double*, int64_t, hipStream_t);
+template bool coef_fused<float, float>(const float*, const float*, int, int, int, int, int, int, int, const float*, int,
+                                       int, const float*, const int*, const int*, int, int, int64_t, float*, int64_t,
+                                       hipStream_t);
+template void time_mix<double, double>(const double*, const double*, int, int, int, int, int, int, const double*,
+                                       int, int, double*, int64_t, hipStream_t);
+template void time_mix<float, float>(const float*, const float*, int, int, int, int, int, int, const float*, int, int,
+                                     float*, int64_t, hipStream_t);
 template void dense_mode<double, double>(const double*, int, int, const double*, double*, int64_t, int64_t,
                                          hipStream_t);
 template void dense_mode<float, float>(const float*, int, int, const float*, float*, int64_t, int64_t, hipStream_t);

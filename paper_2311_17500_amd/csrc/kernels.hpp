@@ -15,7 +15,7 @@ typedef __hip_bfloat16 bf16;
 // Kernel classes for the optional HIP-event profiler (host-side timing of
 // individual launches on the stream they run on).
 enum KClass { K_GATHER = 0, K_TIME_MIX, K_ARROW, K_MULTIDOT, K_UPDATE, K_POINTWISE, K_MAX, K_BANDED, K_EXPAND,
-              K_DENSE, K_NCLASS };
+              K_DENSE, K_COEF, K_NCLASS };
 void kprof_enable(bool on);
 // class recorded for gather launches until changed (K_GATHER by default)
 void kprof_gather_class(int cls);
@@ -48,12 +48,27 @@ void gather_rows(const DTable<C>& t, int r0, int nr, const Ti* x, To* y, int64_t
 void mode_max(const int* start, const int* cnt, int n_out, const double* x, double* y, int64_t outer,
               int64_t inner, int n_in, hipStream_t s);
 
-// Coefficient part of the operator at the spatial Gauss points:
-//   out[t][q] = sum_{r in [r0,r1)} Psi[r][q] sum_w T[r][t][w] * Z[t+1-p+w - in_base][q]
-// (t = 0..N_t-1 rows of X_t; inputs outside [0, n_in) skipped).
+// Coefficient part of the operator at the spatial Gauss points, rows t in [t0, t1):
+//   out[t - t0][q] = sum_{r in [r0,r1)} Psi[r][q] sum_w T[r][t][w] * Z[t+1-p+w - in_base][q]
+// (T has N_t rows of X_t; inputs outside [0, n_in) skipped).
 template <class S, class C>
-void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int p, const S* Z, int n_in, int in_base,
-              S* out, int64_t Qs, hipStream_t s);
+void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1, int p, const S* Z, int n_in,
+              int in_base, S* out, int64_t Qs, hipStream_t s);
+
+// Coefficient part along the slowest spatial axis in one kernel (time_mix
+// between the expansion to that axis' Gauss points and the projection back):
+//   out[t - t0][i][c] = sum_{q in axis Gauss points} Bl[q][i - efirst(q)] *
+//                       sum_{r in [r0,r1)} Psi[r][q*Qin + c] sum_w T[r][t][w] z[t+1-p+w - in_base][q][c],
+//   z[j][q][c] = sum_k Bl[q][k] Z[j][efirst(q)+k][c],
+// Z: [n_in][nd][Qin], out: [t1-t0][nd][Qin], Bl: [Q][ps+1] basis values at the
+// axis' Gauss points (element-major, ps+1 points per element), efirst: first
+// B-spline of each element, chunks: nchunk x {e0, e1, d0, d1} (elements
+// walked and B-splines stored by one thread).  Returns false (nothing
+// launched) for degrees outside p_t <= 5, p_s <= 4.
+template <class S, class C>
+bool coef_fused(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1, int pt, int ps, const S* Z,
+                int n_in, int in_base, const C* Bl, const int* efirst, const int* chunks, int nchunk, int nd,
+                int64_t Qin, S* out, int64_t Qs, hipStream_t s);
 
 // Dense mode product on MFMA: y[o][i][k] = sum_j A[i][j] x[o][j][k], A given
 // zero-padded as npad x npad (npad = 16 * ceil(n / 16) <= 144), row-major.

@@ -76,6 +76,16 @@ struct st_iga_ctx {
   int64_t Ns = 0, Qs = 0, nunk = 0, nfull = 0, Nels = 0;
   int chunk_el = 1;
   int64_t big_len = 0;
+  int slab = 1;
+  int64_t slab_layers = 1;
+  // fused coefficient kernel along the slowest spatial axis (d >= 2)
+  bool cf = false;
+  int cf_slab = 1, cf_nchunk = 1;
+  std::vector<double> cf_Bl_h;
+  std::vector<int> cf_first_h, cf_chunks_h;
+  double* cf_Bl_d = nullptr;
+  float* cf_Bl_f = nullptr;
+  int *cf_first = nullptr, *cf_chunks = nullptr;
   Arena ar;
   std::string err;
   // host setup results
@@ -111,9 +121,11 @@ struct st_iga_ctx {
   float *t4f[4] = {}, *bigf[2] = {}, *xf = nullptr, *yf = nullptr;
   bf16 *t4b[4] = {}, *xb = nullptr, *yb = nullptr;
   void *Vb = nullptr, *Zb = nullptr;
+  int64_t ldb = 0;   // column stride of Vb, Zb (elements)
   int last_refinements = 0;
   double *rk = nullptr, *xk = nullptr, *wk = nullptr, *dk = nullptr, *bk = nullptr;
   double *VT = nullptr, *sol_rhs = nullptr, *sol_dx = nullptr;
+  const double *rfull_u = nullptr, *rfull_w = nullptr;   // (u, w) whose ionic residual part is in rfull
   double *grid = nullptr, *grid2 = nullptr, *E = nullptr, *rfull = nullptr, *Cg = nullptr;
   double *part = nullptr, *dsc = nullptr, *gram = nullptr, *tmpR = nullptr;
   int nb_red = 0, nb_part = 0, gram_nb = 0;
@@ -193,6 +205,65 @@ Gather hat_table(const std::vector<double>& nodes, const std::vector<double>& x)
     G.coef[2 * m + 1] = (N == 1) ? 0.0 : 1.0 - wl[m];
   }
   return G;
+}
+
+// Plan of the fused coefficient kernel along the slowest spatial axis: basis
+// values at that axis' Gauss points, the first B-spline of each element,
+// time slabs sized to the two scratch buffers (expanded arrays of the faster
+// axes only) and, when columns x time slabs give too few threads for the
+// device, a split of the axis into B-spline ranges walked independently.
+void plan_fused_coef(st_iga_ctx* c) {
+  const int d = c->d;
+  c->cf = d >= 2 && c->P.p_s <= 4 && c->P.p_t <= 5;
+  if (!c->cf) return;
+  const Dir1D& D = c->dir[d - 1];
+  const int kp = D.p + 1;
+  if (D.nq != kp) {
+    c->cf = false;
+    return;
+  }
+  c->cf_Bl_h.assign(static_cast<size_t>(D.Q) * kp, 0.0);
+  for (int q = 0; q < D.Q; ++q)
+    for (int k = 0; k < kp; ++k) c->cf_Bl_h[static_cast<size_t>(q) * kp + k] = D.B[0][static_cast<size_t>(q) * kp + k];
+  c->cf_first_h.resize(D.nel);
+  for (int e = 0; e < D.nel; ++e) c->cf_first_h[e] = D.first[static_cast<size_t>(e) * D.nq];
+  // per-layer footprint of the expanded arrays in each scratch buffer
+  int64_t Qin = 1;
+  for (int l = 0; l < d - 1; ++l) Qin *= c->Q[l];
+  const int64_t nd = D.n;
+  const int64_t fl = (d == 3) ? nd * c->n[1] * c->Q[0] + nd * Qin : nd * Qin;
+  const int halo = 2 * c->P.p_t + 1;
+  const int64_t fit = c->big_len / std::max<int64_t>(fl, 1) - halo;
+  c->cf_slab = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(c->Nt, fit)));
+  if (c->opt.coef_slab > 0) c->cf_slab = std::min(c->Nt, c->opt.coef_slab);
+  if (static_cast<int64_t>(c->cf_slab + halo) * fl > c->big_len) {
+    c->cf = false;
+    return;
+  }
+  const int64_t threads = Qin * ((c->cf_slab + 7) / 8);
+  const int64_t want = 1 << 17;
+  int nch = static_cast<int>(std::min<int64_t>(std::max<int64_t>(1, (want + threads - 1) / threads),
+                                               std::max(1, D.nel / 4)));
+  nch = std::max(1, std::min(nch, D.n));
+  c->cf_nchunk = nch;
+  c->cf_chunks_h.assign(4 * static_cast<size_t>(nch), 0);
+  for (int k = 0; k < nch; ++k) {
+    const int d0 = static_cast<int>(static_cast<int64_t>(k) * D.n / nch);
+    const int d1 = static_cast<int>(static_cast<int64_t>(k + 1) * D.n / nch);
+    int e0 = D.nel, e1 = 0;
+    for (int e = 0; e < D.nel; ++e) {
+      const int f = c->cf_first_h[e];
+      if (f + D.p >= d0 && f < d1) {   // element touches a B-spline of [d0, d1)
+        e0 = std::min(e0, e);
+        e1 = std::max(e1, e + 1);
+      }
+    }
+    if (e0 >= e1) e0 = e1 = 0;
+    c->cf_chunks_h[4 * k] = e0;
+    c->cf_chunks_h[4 * k + 1] = e1;
+    c->cf_chunks_h[4 * k + 2] = d0;
+    c->cf_chunks_h[4 * k + 3] = d1;
+  }
 }
 
 void host_setup(st_iga_ctx* c) {
@@ -337,10 +408,20 @@ void host_setup(st_iga_ctx* c) {
   make_contiguous(c->Gt.h, c->nt);
   // the quadrature pass keeps 3 arrays of N_s and 3 of Q_s doubles per time
   // Gauss point in the first big buffer and 5 of Q_s in the second
-  c->big_len = std::max<int64_t>({static_cast<int64_t>(c->nt) * c->Qs, 5LL * c->nqt * c->Qs,
+  // time slabs of the coefficient part: whole time axis unless the two
+  // scratch buffers would exceed about 24 GB in FP64
+  {
+    const int64_t cap_layers = std::max<int64_t>(8, (int64_t(3) << 29) / std::max<int64_t>(c->Qs, 1));
+    const int halo = 2 * c->P.p_t + 1;
+    c->slab = (c->nt <= cap_layers) ? c->Nt : static_cast<int>(std::max<int64_t>(4, cap_layers - halo));
+    if (c->opt.coef_slab > 0) c->slab = std::min(c->Nt, c->opt.coef_slab);
+    c->slab_layers = std::min<int64_t>(c->nt, c->slab + halo);
+  }
+  c->big_len = std::max<int64_t>({c->slab_layers * c->Qs, 5LL * c->nqt * c->Qs,
                                   3LL * c->nqt * (c->Ns + c->Qs), 2LL * c->Qs + 0});
   const int64_t cq = std::min<int64_t>(c->big_len / (3 * (c->Ns + c->Qs)), c->big_len / (5 * c->Qs));
   c->chunk_el = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(c->nelt, cq / c->nqt)));
+  plan_fused_coef(c);
 }
 
 // Reserve device memory for everything; in dry mode only sizes are computed.
@@ -368,6 +449,12 @@ void plan(st_iga_ctx* c) {
   for (int l = 0; l < d; ++l) {
     T(c->Ms[l]); T(c->Ks[l]); T(c->BqT[l]); T(c->Hs[l]); T(c->Gs[l]); T(c->Us[l]); T(c->UsT[l]);
     for (int k = 0; k <= 2; ++k) T(c->Bq[l][k]);
+  }
+  if (c->cf) {
+    c->cf_Bl_d = a.get<double>(static_cast<int64_t>(c->cf_Bl_h.size()));
+    c->cf_Bl_f = a.get<float>(static_cast<int64_t>(c->cf_Bl_h.size()));
+    c->cf_first = a.get<int>(static_cast<int64_t>(c->cf_first_h.size()));
+    c->cf_chunks = a.get<int>(static_cast<int64_t>(c->cf_chunks_h.size()));
   }
   T(c->Mt_x); T(c->Wt_x); T(c->Bt0); T(c->Bt1); T(c->BtT); T(c->Gt); T(c->Ut); T(c->UtT); T(c->Ew);
   for (st_iga_ctx::Dense* D : {&c->DUt, &c->DUtT, &c->DUs[0], &c->DUs[1], &c->DUs[2], &c->DUsT[0], &c->DUsT[1],
@@ -409,8 +496,11 @@ void plan(st_iga_ctx* c) {
   c->sol_dx = a.get<double>(c->nunk);
   const int m = c->opt.restart;
   const size_t bsz = mixed ? sizeof(float) : sizeof(double);   // Krylov basis storage
-  c->Vb = a.take(static_cast<size_t>(m + 1) * c->nunk * bsz);
-  c->Zb = a.take(static_cast<size_t>(m) * c->nunk * bsz);
+  // basis columns padded to 64 elements so every column keeps the alignment
+  // of the vectorised kernels
+  c->ldb = (c->nunk + 63) & ~static_cast<int64_t>(63);
+  c->Vb = a.take(static_cast<size_t>(m + 1) * c->ldb * bsz);
+  c->Zb = a.take(static_cast<size_t>(m) * c->ldb * bsz);
   c->rk = a.get<double>(c->nunk);
   c->xk = a.get<double>(c->nunk);
   c->wk = a.get<double>(c->nunk);
@@ -469,6 +559,13 @@ void upload_all(st_iga_ctx* c, hipStream_t s) {
       upload_tab(*t, s, keepf);
   }
   for (Tab* t : {&c->Mt_x, &c->Wt_x, &c->Bt0, &c->Bt1, &c->BtT, &c->Gt, &c->Ut, &c->UtT, &c->Ew}) upload_tab(*t, s, keepf);
+  if (c->cf) {
+    up(c->cf_Bl_h, static_cast<const double*>(c->cf_Bl_d), s);
+    keepf.emplace_back(c->cf_Bl_h.begin(), c->cf_Bl_h.end());
+    up(keepf.back(), static_cast<const float*>(c->cf_Bl_f), s);
+    up(c->cf_first_h, static_cast<const int*>(c->cf_first), s);
+    up(c->cf_chunks_h, static_cast<const int*>(c->cf_chunks), s);
+  }
   for (st_iga_ctx::Dense* D : {&c->DUt, &c->DUtT, &c->DUs[0], &c->DUs[1], &c->DUs[2], &c->DUsT[0], &c->DUsT[1],
                                &c->DUsT[2]}) {
     if (D->npad == 0) continue;
@@ -638,21 +735,61 @@ void apply_impl(st_iga_ctx* c, const S* x, S* y, int L, int in_base, bool with_s
   const int qd[3] = {c->Q[0], c->Q[1], c->Q[2]};
   S* Z = B.big[0];
   S* W2 = B.big[1];
-  // expansion x -> Z [L][Q_s] (scratch: W2 and Z alternate)
   S* bufA = (d == 3) ? Z : W2;   // intermediates never alias the step that reads them
   S* bufB = W2;
-  if (d == 1) {
-    gather<S, S, C>(Ops<S, C>::tab(*ex[0]), x, Z, L, 1, nn[0], 0, C(1), C(0), s);
-  } else {
-    spatial_chain<S, C>(c, ex, x, L, nn, qd, bufA, bufB, Z, C(1), C(0), s);
-  }
   const C* Tr = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->Tr) : reinterpret_cast<const C*>(c->Tr_f);
-  time_mix<S, C>(Tr, B.Psi, r0, r1, c->Nt, P.p_t, Z, L, in_base + 0, W2, c->Qs, s);
-  // project W2 [N_t][Q_s] -> y += ...
-  if (d == 1) {
-    gather<S, S, C>(Ops<S, C>::tab(*pr[0]), W2, y, c->Nt, 1, qd[0], 0, C(1), C(1), s);
-  } else {
-    spatial_chain<S, C>(c, pr, W2, c->Nt, qd, nn, Z, (d == 3 ? W2 : Z), y, C(1), C(1), s);
+  const int p = P.p_t;
+  if (c->cf) {
+    // expand along the faster axes, then one fused kernel along the slowest
+    const C* Bl = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->cf_Bl_d)
+                                                 : reinterpret_cast<const C*>(c->cf_Bl_f);
+    const int nd = nn[d - 1];
+    const int64_t Qin = (d == 3) ? static_cast<int64_t>(qd[0]) * qd[1] : qd[0];
+    for (int t0 = 0; t0 < c->Nt; t0 += c->cf_slab) {
+      const int t1 = std::min(c->Nt, t0 + c->cf_slab);
+      const int lo = std::max(0, t0 + 1 - p - in_base);
+      const int hi = std::min(L - 1, t1 + p - in_base);
+      const int nl = hi - lo + 1;
+      const int rows = t1 - t0;
+      const S* xs = x + static_cast<int64_t>(lo) * Ns;
+      S* ys = y + static_cast<int64_t>(t0) * Ns;
+      S* X1 = B.big[0];
+      S* Y2 = B.big[1];
+      if (d == 2) {
+        gather<S, S, C>(Ops<S, C>::tab(*ex[0]), xs, X1, static_cast<int64_t>(nl) * nn[1], 1, nn[0], 0, C(1), C(0), s);
+        coef_fused<S, C>(Tr, B.Psi, r0, r1, c->Nt, t0, t1, p, P.p_s, X1, nl, in_base + lo, Bl, c->cf_first,
+                         c->cf_chunks, c->cf_nchunk, nd, Qin, Y2, c->Qs, s);
+        gather<S, S, C>(Ops<S, C>::tab(*pr[0]), Y2, ys, static_cast<int64_t>(rows) * nn[1], 1, qd[0], 0, C(1), C(1), s);
+      } else {
+        S* X2 = X1 + static_cast<int64_t>(nl) * nn[2] * nn[1] * qd[0];
+        S* Y1 = Y2 + static_cast<int64_t>(rows) * nn[2] * Qin;
+        gather<S, S, C>(Ops<S, C>::tab(*ex[0]), xs, X1, static_cast<int64_t>(nl) * nn[2] * nn[1], 1, nn[0], 0, C(1),
+                        C(0), s);
+        gather<S, S, C>(Ops<S, C>::tab(*ex[1]), X1, X2, static_cast<int64_t>(nl) * nn[2], qd[0], nn[1], 0, C(1), C(0),
+                        s);
+        coef_fused<S, C>(Tr, B.Psi, r0, r1, c->Nt, t0, t1, p, P.p_s, X2, nl, in_base + lo, Bl, c->cf_first,
+                         c->cf_chunks, c->cf_nchunk, nd, Qin, Y2, c->Qs, s);
+        gather<S, S, C>(Ops<S, C>::tab(*pr[1]), Y2, Y1, static_cast<int64_t>(rows) * nn[2], qd[0], qd[1], 0, C(1), C(0),
+                        s);
+        gather<S, S, C>(Ops<S, C>::tab(*pr[0]), Y1, ys, static_cast<int64_t>(rows) * nn[2] * nn[1], 1, qd[0], 0, C(1),
+                        C(1), s);
+      }
+    }
+    return;
+  }
+  // slabs of output time rows; each expands only the input layers its time window reads
+  for (int t0 = 0; t0 < c->Nt; t0 += c->slab) {
+    const int t1 = std::min(c->Nt, t0 + c->slab);
+    const int lo = std::max(0, t0 + 1 - p - in_base);
+    const int hi = std::min(L - 1, t1 + p - in_base);
+    const int nl = hi - lo + 1;
+    const S* xs = x + static_cast<int64_t>(lo) * Ns;
+    if (d == 1) gather<S, S, C>(Ops<S, C>::tab(*ex[0]), xs, Z, nl, 1, nn[0], 0, C(1), C(0), s);
+    else spatial_chain<S, C>(c, ex, xs, nl, nn, qd, bufA, bufB, Z, C(1), C(0), s);
+    time_mix<S, C>(Tr, B.Psi, r0, r1, c->Nt, t0, t1, p, Z, nl, in_base + lo, W2, c->Qs, s);
+    S* ys = y + static_cast<int64_t>(t0) * Ns;
+    if (d == 1) gather<S, S, C>(Ops<S, C>::tab(*pr[0]), W2, ys, t1 - t0, 1, qd[0], 0, C(1), C(1), s);
+    else spatial_chain<S, C>(c, pr, W2, t1 - t0, qd, nn, Z, (d == 3 ? W2 : Z), ys, C(1), C(1), s);
   }
 }
 
@@ -750,7 +887,7 @@ using OpT = std::function<void(const T*, T*)>;
 template <class T>
 int fgmres(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const double* b, double* x, double rtol, int maxit,
            double bnorm, double* est, T* V, T* Z, T* xt, T* yt, hipStream_t s) {
-  const int64_t n = c->nunk;
+  const int64_t n = c->nunk, ld = c->ldb;
   const int m = c->opt.restart;
   const int nb = reduce_blocks(n);
   fill(x, 0.0, n, s);
@@ -765,17 +902,17 @@ int fgmres(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const double* b, do
     g[0] = rn;
     int j = 0;
     for (; j < m && it < maxit; ++j) {
-      T* Vj = V + static_cast<int64_t>(j) * n;
-      T* Zj = Z + static_cast<int64_t>(j) * n;
-      T* w = V + static_cast<int64_t>(j + 1) * n;
+      T* Vj = V + static_cast<int64_t>(j) * ld;
+      T* Zj = Z + static_cast<int64_t>(j) * ld;
+      T* w = V + static_cast<int64_t>(j + 1) * ld;
       Pc(Vj, Zj);
       A(Zj, w);
-      multidot_partial<T>(V, n, j + 1, w, n, c->part, nb, s);
+      multidot_partial<T>(V, ld, j + 1, w, n, c->part, nb, s);
       finalize_sum(c->part, nb, j + 1, c->dsc, s);
-      update_norm_partial<T>(V, n, j + 1, c->dsc, w, n, c->part, nb, s);
-      multidot_partial<T>(V, n, j + 1, w, n, c->part, nb, s);
+      update_norm_partial<T>(V, ld, j + 1, c->dsc, w, n, c->part, nb, s);
+      multidot_partial<T>(V, ld, j + 1, w, n, c->part, nb, s);
       finalize_sum(c->part, nb, j + 1, c->dsc + 128, s);
-      update_norm_partial<T>(V, n, j + 1, c->dsc + 128, w, n, c->part, nb, s);
+      update_norm_partial<T>(V, ld, j + 1, c->dsc + 128, w, n, c->part, nb, s);
       finalize_sum(c->part, nb, 1, c->dsc + 256, s);
       CK(hipMemcpyAsync(hbuf, c->dsc, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
       CK(hipMemcpyAsync(hbuf + 66, c->dsc + 128, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -810,7 +947,7 @@ int fgmres(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const double* b, do
       y[i] = t / H[static_cast<size_t>(i) * m + i];
     }
     CK(hipMemcpyAsync(c->dsc + 512, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
-    combine<T>(Z, n, j, c->dsc + 512, x, n, s);
+    combine<T>(Z, ld, j, c->dsc + 512, x, n, s);
     // restart residual r = b - A x with the same operator
     if (std::is_same<T, double>::value) {
       A(reinterpret_cast<const T*>(x), yt);
@@ -1022,13 +1159,39 @@ void quad_pass(st_iga_ctx* c, const double* u, const double* w, bool want_res, b
     gather_rows<double, double, double>(c->Bt0.d, q0, nqc, u, U0, 1, Ns, c->nt, 0, 1.0, 0.0, s);
     gather_rows<double, double, double>(c->Bt1.d, q0, nqc, u, Ut, 1, Ns, c->nt, 0, 1.0, 0.0, s);
     gather_rows<double, double, double>(c->Bt0.d, q0, nqc, w, W0, 1, Ns, c->nt, 0, 1.0, 0.0, s);
-    expand_space(c, B0, U0, nqc, tA, tB, uq, 1.0, 0.0, s);
     expand_space(c, B0, Ut, nqc, tA, tB, utq, 1.0, 0.0, s);
     expand_space(c, B0, W0, nqc, tA, tB, wq, 1.0, 0.0, s);
-    for (int l = 0; l < d; ++l) {
-      const Tab* tl[3] = {B0[0], B0[1], B0[2]};
-      tl[l] = &c->Bq[l][2];
-      expand_space(c, tl, U0, nqc, tA, tB, lap, P.sigma[l], l == 0 ? 0.0 : 1.0, s);
+    // u and sum_l sigma_l d_ll u with shared partial expansions (g and absR
+    // are free until the pointwise kernel)
+    {
+      const int n1 = c->n[0], n2 = c->n[1], n3 = c->n[2], Q1 = c->Q[0], Q2 = c->Q[1];
+      auto ax = [&](const Tab& t, const double* xin, double* yout, int64_t outer, int64_t inner, int nin, double al,
+                    double be) { gather<double, double, double>(t.d, xin, yout, outer, inner, nin, 0, al, be, s); };
+      const Tab &E0 = c->Bq[0][0], &E2 = c->Bq[0][2];
+      if (d == 1) {
+        ax(E0, U0, uq, nqc, 1, n1, 1.0, 0.0);
+        ax(E2, U0, lap, nqc, 1, n1, P.sigma[0], 0.0);
+      } else if (d == 2) {
+        const Tab &F0 = c->Bq[1][0], &F2 = c->Bq[1][2];
+        ax(E0, U0, tA, static_cast<int64_t>(nqc) * n2, 1, n1, 1.0, 0.0);       // a = B0 x1
+        ax(E2, U0, tB, static_cast<int64_t>(nqc) * n2, 1, n1, 1.0, 0.0);       // b = B2 x1
+        ax(F0, tA, uq, nqc, Q1, n2, 1.0, 0.0);
+        ax(F2, tA, lap, nqc, Q1, n2, P.sigma[1], 0.0);
+        ax(F0, tB, lap, nqc, Q1, n2, P.sigma[0], 1.0);
+      } else {
+        const Tab &F0 = c->Bq[1][0], &F2 = c->Bq[1][2], &G0 = c->Bq[2][0], &G2 = c->Bq[2][2];
+        const int64_t o1 = static_cast<int64_t>(nqc) * n3 * n2, o2 = static_cast<int64_t>(nqc) * n3;
+        ax(E0, U0, tA, o1, 1, n1, 1.0, 0.0);                    // a  = B0 x1
+        ax(E2, U0, tB, o1, 1, n1, 1.0, 0.0);                    // b  = B2 x1
+        ax(F0, tA, g, o2, Q1, n2, 1.0, 0.0);                    // aa = B0 x2 a
+        ax(F2, tA, absR, o2, Q1, n2, 1.0, 0.0);                 // ab = B2 x2 a
+        ax(F0, tB, tA, o2, Q1, n2, 1.0, 0.0);                   // ba = B0 x2 b
+        const int64_t in3 = static_cast<int64_t>(Q1) * Q2;
+        ax(G0, g, uq, nqc, in3, n3, 1.0, 0.0);
+        ax(G2, g, lap, nqc, in3, n3, P.sigma[2], 0.0);
+        ax(G0, absR, lap, nqc, in3, n3, P.sigma[1], 1.0);
+        ax(G0, tA, lap, nqc, in3, n3, P.sigma[0], 1.0);
+      }
     }
     const int nbp = static_cast<int>((static_cast<int64_t>(nqc) * Qs + 255) / 256);
     pointwise_ionic(uq, utq, lap, wq, c->wq_t + q0, c->wq_s, Qs, nqc, P.Cm, P.a, P.c1, P.c2, g, absR,
@@ -1083,9 +1246,9 @@ void quad_pass(st_iga_ctx* c, const double* u, const double* w, bool want_res, b
 }
 
 // Theta grid (N_t x N_s) of eq. (3.4) into dst.
-void theta_grid(st_iga_ctx* c, const double* u, const double* w, double* dst, hipStream_t s) {
+void theta_grid(st_iga_ctx* c, const double* u, const double* w, double* dst, hipStream_t s, bool with_res = false) {
   const int d = c->d;
-  quad_pass(c, u, w, false, true, s);
+  quad_pass(c, u, w, with_res, true, s);
   // window maxima: time then spatial axes; E is [nelt][nel_d..nel_1]
   double* tA = c->big[0];
   double* tB = c->big[1];
@@ -1247,10 +1410,18 @@ void rebuild_coefficients(st_iga_ctx* c, hipStream_t s) {
   c->linearized = true;
 }
 
-void linearize(st_iga_ctx* c, const double* u, const double* w, bool refresh_theta, hipStream_t s) {
+void linearize(st_iga_ctx* c, const double* u, const double* w, bool refresh_theta, hipStream_t s,
+               bool with_residual = false) {
   const bool newton = c->opt.outer == 0;
+  c->rfull_u = c->rfull_w = nullptr;
   if (c->opt.su && refresh_theta) {
-    theta_grid(c, u, w, c->grid, s);
+    // one quadrature pass gives the theta maxima and, on request, the ionic
+    // part of the residual at the same (u, w)
+    theta_grid(c, u, w, c->grid, s, with_residual);
+    if (with_residual) {
+      c->rfull_u = u;
+      c->rfull_w = w;
+    }
     c->Rth = lowrank(c, c->grid, c->opt.eps_theta, c->Uth_h, c->sth_h, c->Vth, s);
   } else if (!c->opt.su) {
     c->Rth = 0;
@@ -1264,7 +1435,8 @@ void linearize(st_iga_ctx* c, const double* u, const double* w, bool refresh_the
 
 void residual(st_iga_ctx* c, const double* u, const double* w, double* r, hipStream_t s) {
   ensure_lin(c);
-  quad_pass(c, u, w, true, false, s);
+  if (!(c->rfull_u == u && c->rfull_w == w)) quad_pass(c, u, w, true, false, s);
+  c->rfull_u = c->rfull_w = nullptr;
   Bufs<double> B = bufs64(c);
   apply_impl<double, double>(c, u, r, c->nt, 0, true, false, B, s);
   axpy(1.0, c->rfull + c->Ns, r, c->nunk, s);
@@ -1342,6 +1514,7 @@ void st_iga_default_options(st_iga_options* o) {
   o->max_krylov = 3000;
   o->prec = ST_IGA_FP64;
   o->lin_forcing = 0.0;
+  o->coef_slab = 0;
 }
 
 size_t st_iga_workspace_bytes(const st_iga_problem* prob, const st_iga_options* opt) {
@@ -1397,6 +1570,7 @@ st_iga_status st_iga_linearize(st_iga_ctx* c, const double* u, const double* w, 
   return guard(c, [&] {
     if (!c->linearized && c->opt.su && !refresh_theta) throw Fail{ST_IGA_ESTATE, "theta has never been computed"};
     linearize(c, u, w, refresh_theta != 0, static_cast<hipStream_t>(stream));
+    c->rfull_u = c->rfull_w = nullptr;
   });
 }
 
@@ -1538,7 +1712,7 @@ st_iga_status st_iga_solve(st_iga_ctx* c, const st_iga_stimulus* stim, double* u
     for (int k = 0; k < c->opt.max_outer; ++k) {
       auto t0 = std::chrono::steady_clock::now();
       w_update(c, u, w, s);
-      linearize(c, u, w, c->opt.su && !frozen, s);
+      linearize(c, u, w, c->opt.su && !frozen, s, true);
       residual(c, u, w, c->sol_rhs, s);
       axpby(-1.0, c->sol_rhs, 0.0, c->sol_rhs, c->nunk, s);   // rhs = -N(u)
       CK(hipStreamSynchronize(s));
@@ -1586,7 +1760,7 @@ st_iga_status st_iga_newton_step(st_iga_ctx* c, const double* u_in, double* u_ou
     if (u_out != u_in) CK(hipMemcpyAsync(u_out, u_in, c->nfull * sizeof(double), hipMemcpyDeviceToDevice, s));
     w_update(c, u_out, w, s);
     if (!c->linearized && c->opt.su && !refresh_theta) throw Fail{ST_IGA_ESTATE, "theta has never been computed"};
-    linearize(c, u_out, w, refresh_theta != 0, s);
+    linearize(c, u_out, w, refresh_theta != 0, s, true);
     residual(c, u_out, w, c->sol_rhs, s);
     axpby(-1.0, c->sol_rhs, 0.0, c->sol_rhs, c->nunk, s);
     double rr = 1.0;
@@ -1666,6 +1840,11 @@ st_iga_status st_iga_host_query(const st_iga_problem* prob, int32_t what, int32_
         std::vector<int> e0, e1;
         support_windows(D, dir == c.d ? 1 : 0, e0, e1);
         for (size_t i = 0; i < e0.size(); ++i) { v.push_back(e0[i]); v.push_back(e1[i]); }
+        break;
+      }
+      case 11: {
+        v = {c.cf ? 1.0 : 0.0, static_cast<double>(c.cf_slab), static_cast<double>(c.cf_nchunk)};
+        for (int x : c.cf_chunks_h) v.push_back(x);
         break;
       }
       default: throw Fail{ST_IGA_EINVAL, "unknown query"};

@@ -143,3 +143,67 @@ def test_full_nonlinear_solve(gpu_lib, name, prob):
     assert list(rep.rank_theta[: rep.outer_iters]) == log.ranks_theta
     assert rel(u.cpu().numpy(), uo) < 1e-10
     assert rel(w.cpu().numpy(), wo) < 1e-10
+
+
+@pytest.mark.parametrize("name,prob", [SMALL[1], SMALL[2], SMALL[3]], ids=["2d_p3", "3d_p2", "3d_p1"])
+@pytest.mark.parametrize("slab", [1, 2, 3])
+def test_apply_time_slabs(gpu_lib, torch, name, prob, slab):
+    """The low-rank terms computed over time slabs (with their input halos)
+    equal the oracle's operator, for the unknown and the full-vector forms."""
+    S = solver_for(prob, coef_slab=slab)
+    st = SpaceTime(prob)
+    ft = W.random_factors(prob, 3, 1)
+    fc = W.random_factors(prob, 4, 2, scale=5.0)
+    S.set_factors(ft, fc)
+    x = W.random_vector(prob.unknowns, 17)
+    y = S.apply(to_dev(torch, x)).cpu().numpy()
+    thq = st.lowrank_at_quad(LowRank(*ft))
+    cq = st.lowrank_at_quad(LowRank(*fc))
+    assert rel(y, st.apply_J(x, cq, thq)) < 1e-12
+    u, w = W.smooth_state(prob, 4)
+    r = S.residual(to_dev(torch, u), to_dev(torch, w)).cpu().numpy()
+    assert rel(r, st.residual(u, w, thq)) < 1e-11
+
+
+# Cases for the fused coefficient kernel along the slowest spatial axis: few
+# columns, so the axis is split into B-spline ranges walked independently
+# (with the elements at each range boundary walked by both neighbours).
+CHUNKED = [("2d_p2_chunked", W.tiny(2, 2, 12, nel_t=5)),
+           ("3d_p1_chunked", W.tiny(3, 1, 8, nel_t=3))]
+
+
+@pytest.mark.parametrize("name,prob", CHUNKED, ids=[n for n, _ in CHUNKED])
+def test_apply_chunked_axis(gpu_lib, torch, name, prob):
+    from paper_2311_17500_amd.binding import MIXED_FP32
+    st = SpaceTime(prob)
+    ft = W.random_factors(prob, 2, 3)
+    fc = W.random_factors(prob, 3, 4, scale=5.0)
+    thq = st.lowrank_at_quad(LowRank(*ft))
+    cq = st.lowrank_at_quad(LowRank(*fc))
+    x = W.random_vector(prob.unknowns, 18)
+    want = st.apply_J(x, cq, thq)
+    S = solver_for(prob, prec=MIXED_FP32)
+    S.set_factors(ft, fc)
+    xd = to_dev(torch, x)
+    assert rel(S.apply(xd).cpu().numpy(), want) < 1e-12
+    # the FP32 operator: relative error a modest multiple of the unit roundoff
+    assert rel(S.apply_lowp(xd).cpu().numpy(), want) < 1e-5
+
+
+def test_apply_nonuniform_knots(gpu_lib, torch):
+    """Graded spatial knots with a double interior knot on the slowest axis:
+    consecutive elements there start one or two B-splines apart."""
+    prob = W.tiny(2, 2, 6, nel_t=4)
+    kn = prob.uniform_knots()
+    kn[0] = np.array([0, 0, 0, 0.2, 0.3, 0.55, 0.7, 0.9, 1, 1, 1], float)
+    kn[1] = np.array([0, 0, 0, 0.1, 0.25, 0.25, 0.5, 0.8, 1, 1, 1], float)
+    st = SpaceTime(prob, knots=kn)
+    S = solver_for(prob, knots=kn)
+    assert S.N_s == prob.N_s and S.unknowns == prob.unknowns
+    ft = W.random_factors(prob, 2, 5)
+    fc = W.random_factors(prob, 2, 6, scale=5.0)
+    S.set_factors(ft, fc)
+    x = W.random_vector(prob.unknowns, 19)
+    y = S.apply(to_dev(torch, x)).cpu().numpy()
+    want = st.apply_J(x, st.lowrank_at_quad(LowRank(*fc)), st.lowrank_at_quad(LowRank(*ft)))
+    assert rel(y, want) < 1e-12

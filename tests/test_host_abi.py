@@ -150,3 +150,44 @@ def test_invalid_problems_rejected(lib):
         binding.host_query(dataclasses.replace(prob, sigma=(-1.0,)), 0, 0)
     with pytest.raises(binding.StIgaError):
         binding.host_query(dataclasses.replace(prob, T=0.0), 0, 0)
+
+
+def _graded_knots(prob):
+    kn = prob.uniform_knots()
+    kn[0] = np.array([0, 0, 0, 0.2, 0.3, 0.55, 0.7, 0.9, 1, 1, 1], float)
+    kn[1] = np.array([0, 0, 0, 0.1, 0.25, 0.25, 0.5, 0.8, 1, 1, 1], float)
+    return kn
+
+
+@pytest.mark.parametrize("case", ["2d_p2_12", "3d_p1_8", "2d_p3_5", "cfg2", "cfg4", "graded", "1d", "2d_p5"])
+def test_fused_coefficient_plan(lib, case):
+    """The B-spline ranges of the fused coefficient kernel partition the
+    slowest spatial axis in order, and each range walks exactly the elements
+    whose B-splines meet it (checked by brute force over the elements)."""
+    knots = None
+    prob = {"2d_p2_12": W.tiny(2, 2, 12, nel_t=5), "3d_p1_8": W.tiny(3, 1, 8, nel_t=3),
+            "2d_p3_5": W.tiny(2, 3, 5, nel_t=6), "cfg2": W.config(2), "cfg4": W.config(4),
+            "graded": W.tiny(2, 2, 6, nel_t=4), "1d": W.tiny(1, 2, 9, nel_t=7),
+            "2d_p5": W.tiny(2, 5, 4, nel_t=3)}[case]
+    if case == "graded":
+        knots = _graded_knots(prob)
+    plan = binding.host_query(prob, 11, 0, knots=knots)
+    enabled, slab, nch = int(plan[0]), int(plan[1]), int(plan[2])
+    assert enabled == (prob.d >= 2 and prob.p_s <= 4)
+    if not enabled:
+        return
+    ax = prob.d - 1
+    first_q = binding.host_query(prob, 9, ax, knots=knots).astype(int)
+    p = prob.p_s
+    efirst = first_q[:: p + 1]
+    n = len(knots[ax]) - p - 1 if knots is not None else prob.nel_s[ax] + p
+    assert 1 <= slab <= prob.N_t
+    ch = plan[3:].astype(int).reshape(nch, 4)
+    assert ch[0, 2] == 0 and ch[-1, 3] == n
+    assert np.all(ch[1:, 2] == ch[:-1, 3]) and np.all(ch[:, 3] > ch[:, 2])
+    for e0, e1, d0, d1 in ch:
+        touch = [e for e, f in enumerate(efirst) if f + p >= d0 and f < d1]
+        assert (e0, e1) == (min(touch), max(touch) + 1)
+        assert np.all(np.diff(efirst[e0:e1]) >= 1) and np.all(np.diff(efirst[e0:e1]) <= p + 1)
+    if case in ("2d_p2_12", "3d_p1_8"):
+        assert nch > 1      # the GPU parity cases for split axes
