@@ -302,7 +302,8 @@ class Solver:
             self._chk(self.lib.st_iga_profile_read(self.ctx, k, C.byref(ms), C.byref(n), C.byref(by), 0))
             out[name] = (ms.value, n.value, by.value)
         fnames = ["gather_scalar", "gather_v4", "gather_rows", "time_mix", "dense_mode_mfma", "arrowhead",
-                  "multidot", "update_norm", "pointwise_ionic", "mode_max", "gather_sweep", "coef_fused"]
+                  "multidot", "update_norm", "pointwise_ionic", "mode_max", "gather_sweep", "coef_fused",
+                  "quad_fused"]
         for q, pn in enumerate(["f64", "f32", "bf16"]):
             for f, fname in enumerate(fnames):
                 ms, n, by = C.c_double(0), C.c_int64(0), C.c_double(0)

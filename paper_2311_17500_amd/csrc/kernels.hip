@@ -981,6 +981,121 @@ __global__ void __launch_bounds__(TPB) k_pointwise_ionic(
   if (threadIdx.x == 0) part[2 * blockIdx.x + 1] = m2;
 }
 
+// Quadrature pass fused along the slowest spatial axis (FP64): from the
+// arrays expanded along the faster axes (layout [row][nd][Qin], one row per
+// time Gauss point) it forms, at every Gauss point of the axis,
+//   u = B0 A0,  lap = sL B2 A0 + sM B0 A1 + sF B0 A2,  u_t = B0 UT,  w = B0 WW,
+// then I = c1 u (u - a)(u - 1) + c2 u w, |R| = |Cm u_t - lap + I|, and
+//   - M[et][e][c]: max of |R| over the Gauss points of space-time element
+//     (et, e) in column c (when M is given),
+//   - G[row][i][c]: sum over the axis' Gauss points of B0 wt ws I
+//     (projection onto the axis' B-splines, when G is given),
+//   - block maxima of |u| and |u_t| into part[2 b], part[2 b + 1] (b = boff +
+//     linear block index).
+// A block has one wave per time Gauss row of time element et (blockIdx.y);
+// lane l owns column 64 blockIdx.x + l.  Each thread walks the elements of
+// chunk blockIdx.z with rings of the KP input rows an element touches; the
+// element maximum over the time rows is taken across the waves through LDS
+// (double-buffered, one barrier per element).  With D == 2, A1 is not read.
+template <int D, int KP>
+__global__ void __launch_bounds__(384) k_quad_fused(
+    const double* __restrict__ A0, const double* __restrict__ A1, const double* __restrict__ A2,
+    const double* __restrict__ UT, const double* __restrict__ WW, int nd, int64_t Qin,
+    const double* __restrict__ B0, const double* __restrict__ B2, const int* __restrict__ efirst,
+    const int* __restrict__ chunks, const double* __restrict__ wt, const double* __restrict__ ws, double sL,
+    double sM, double sF, double Cm, double a, double c1, double c2, double* __restrict__ G,
+    double* __restrict__ M, int nel_d, double* __restrict__ part, int64_t boff) {
+  __shared__ double sh[8];
+  __shared__ double smax[2][6][64];
+  const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+  const int nqt = blockDim.x >> 6;
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+  const bool cv = c < Qin;
+  const int64_t cc = cv ? c : 0;
+  const int et = blockIdx.y;
+  const int e0 = chunks[4 * blockIdx.z], e1 = chunks[4 * blockIdx.z + 1];
+  const int d0 = chunks[4 * blockIdx.z + 2], d1 = chunks[4 * blockIdx.z + 3];
+  const int64_t lay = static_cast<int64_t>(nd) * Qin;
+  const int tr = et * nqt + row;
+  const int64_t rb = static_cast<int64_t>(tr) * lay + cc;
+  const double wtr = wt[tr];
+  double a0[KP], a1[D == 3 ? KP : 1], a2[KP], ut[KP], ww[KP], gr[KP];
+  auto load = [&](int k, int dof) {
+    const bool ok = dof < nd;
+    const int64_t o = rb + static_cast<int64_t>(ok ? dof : 0) * Qin;
+    a0[k] = ok ? A0[o] : 0.0;
+    if constexpr (D == 3) a1[k] = ok ? A1[o] : 0.0;
+    a2[k] = ok ? A2[o] : 0.0;
+    ut[k] = ok ? UT[o] : 0.0;
+    ww[k] = ok ? WW[o] : 0.0;
+    gr[k] = 0.0;
+  };
+  auto store = [&](int k, int dof) {
+    if (G && cv && dof >= d0 && dof < d1 && dof < nd) G[rb + static_cast<int64_t>(dof) * Qin] = gr[k];
+  };
+  int f = efirst[e0];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) load(k, f + k);
+  double mu = 0.0, mt = 0.0;
+  for (int e = e0; e < e1; ++e) {
+    const int fn = efirst[e];
+    for (; f < fn; ++f) {
+      store(0, f);
+#pragma unroll
+      for (int k = 0; k < KP - 1; ++k) {
+        a0[k] = a0[k + 1];
+        if constexpr (D == 3) a1[k] = a1[k + 1];
+        a2[k] = a2[k + 1];
+        ut[k] = ut[k + 1];
+        ww[k] = ww[k + 1];
+        gr[k] = gr[k + 1];
+      }
+      load(KP - 1, f + KP);
+    }
+    double emax = 0.0;
+#pragma unroll
+    for (int g = 0; g < KP; ++g) {
+      const int qd = e * KP + g;
+      double u = 0.0, l2 = 0.0, l1 = 0.0, l0 = 0.0, tt = 0.0, w = 0.0;
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        const double b0 = B0[qd * KP + k], b2 = B2[qd * KP + k];
+        u += b0 * a0[k];
+        l2 += b2 * a0[k];
+        if constexpr (D == 3) l1 += b0 * a1[k];
+        l0 += b0 * a2[k];
+        tt += b0 * ut[k];
+        w += b0 * ww[k];
+      }
+      const double lap = sL * l2 + sM * l1 + sF * l0;
+      const double I = c1 * u * (u - a) * (u - 1.0) + c2 * u * w;
+      emax = fmax(emax, fabs(Cm * tt - lap + I));
+      mu = fmax(mu, fabs(u));
+      mt = fmax(mt, fabs(tt));
+      const double gv = wtr * ws[static_cast<int64_t>(qd) * Qin + cc] * I;
+#pragma unroll
+      for (int k = 0; k < KP; ++k) gr[k] += B0[qd * KP + k] * gv;
+    }
+    if (M) {
+      smax[e & 1][row][lane] = emax;
+      __syncthreads();
+      if (row == 0 && cv) {
+        double m = smax[e & 1][0][lane];
+        for (int r = 1; r < nqt; ++r) m = fmax(m, smax[e & 1][r][lane]);
+        M[(static_cast<int64_t>(et) * nel_d + e) * Qin + c] = m;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KP; ++k) store(k, f + k);
+  if (!cv) mu = mt = 0.0;
+  const int64_t b = boff + blockIdx.x + static_cast<int64_t>(gridDim.x) * (blockIdx.y + static_cast<int64_t>(gridDim.y) * blockIdx.z);
+  const double m1 = block_max(mu, sh);
+  if (threadIdx.x == 0) part[2 * b] = m1;
+  const double m2 = block_max(mt, sh);
+  if (threadIdx.x == 0) part[2 * b + 1] = m2;
+}
+
 __global__ void k_theta_finish(double* __restrict__ th, int64_t n, const double* __restrict__ maxes, double Cm,
                                double invT) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1393,6 +1508,35 @@ void pointwise_ionic(const double* u, const double* ut, const double* lap, const
   ProfScope ps(K_POINTWISE, 8, s, 6.0 * total * sizeof(double));
   hipLaunchKernelGGL(k_pointwise_ionic, dim3(grid_for(total)), dim3(TPB), 0, s, u, ut, lap, w, wt_time, wt_space, Qs,
                      total, Cm, a, c1, c2, g, absR, part);
+}
+int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, const double* A2, const double* UT,
+                   const double* WW, int nd, int64_t Qin, int ne, const double* B0, const double* B2,
+                   const int* efirst, const int* chunks, int nchunk, const double* wt, const double* ws, double sL,
+                   double sM, double sF, double Cm, double a, double c1, double c2, double* G, double* M, int nel_d,
+                   double* part, int64_t boff, hipStream_t s) {
+  if (d < 2 || d > 3 || ps < 1 || ps > 4 || nqt < 1 || nqt > 6) return -1;
+  const dim3 g(static_cast<unsigned>((Qin + 63) / 64), static_cast<unsigned>(ne), static_cast<unsigned>(nchunk));
+  const dim3 blk(static_cast<unsigned>(64 * nqt));
+  const double rows = static_cast<double>(ne) * nqt;
+  ProfScope pr(K_POINTWISE, 12, s,
+               (rows * nd * Qin * ((d == 3 ? 5.0 : 4.0) + (G ? 1.0 : 0.0)) + (M ? static_cast<double>(ne) * nel_d * Qin : 0.0) +
+                static_cast<double>(nel_d) * (ps + 1) * Qin) * sizeof(double));
+#define QF(D_, K_) hipLaunchKernelGGL((k_quad_fused<D_, K_>), g, blk, 0, s, A0, A1, A2, UT, WW, nd, Qin, B0, B2, efirst, chunks, wt, ws, sL, sM, sF, Cm, a, c1, c2, G, M, nel_d, part, boff)
+#define QFK(D_)                         \
+  switch (ps) {                         \
+    case 1: QF(D_, 2); break;           \
+    case 2: QF(D_, 3); break;           \
+    case 3: QF(D_, 4); break;           \
+    default: QF(D_, 5); break;          \
+  }
+  if (d == 3) {
+    QFK(3);
+  } else {
+    QFK(2);
+  }
+#undef QFK
+#undef QF
+  return static_cast<int64_t>(g.x) * g.y * g.z;
 }
 void theta_finish(double* th, int64_t n, const double* maxes, double Cm, double invT, hipStream_t s) {
   hipLaunchKernelGGL(k_theta_finish, dim3(grid_for(n)), dim3(TPB), 0, s, th, n, maxes, Cm, invT);

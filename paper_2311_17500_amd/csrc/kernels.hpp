@@ -70,6 +70,24 @@ bool coef_fused(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1
                 int n_in, int in_base, const C* Bl, const int* efirst, const int* chunks, int nchunk, int nd,
                 int64_t Qin, S* out, int64_t Qs, hipStream_t s);
 
+// Quadrature pass fused along the slowest spatial axis (FP64), see
+// k_quad_fused: inputs [ne*nqt][nd][Qin] expanded along the faster axes
+// (d = 3: A0 = B0 B0 u, A1 = B0 B2 u (x1 value, x2 second derivative),
+// A2 = B2 B0 u; d = 2: A0 = B0 u, A2 = B2 u, A1 unused), UT and WW the
+// value expansions of u_t and w; B0, B2: [Q][ps+1] basis values and second
+// derivatives at the axis' Gauss points; wt: time weights of the ne*nqt
+// rows; ws: spatial weights [Qs].  Outputs (each optional): G [ne*nqt][nd][Qin]
+// (weighted ionic current projected onto the axis' B-splines), M
+// [ne][nel_d][Qin] (element maxima of |R| over the axis and time), and block
+// maxima of |u|, |u_t| at part[2(boff + b)], part[2(boff + b) + 1].  Returns
+// the number of blocks written (or -1 if the degrees are not supported:
+// d in {2, 3}, ps <= 4, nqt <= 6).
+int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, const double* A2, const double* UT,
+                   const double* WW, int nd, int64_t Qin, int ne, const double* B0, const double* B2,
+                   const int* efirst, const int* chunks, int nchunk, const double* wt, const double* ws, double sL,
+                   double sM, double sF, double Cm, double a, double c1, double c2, double* G, double* M, int nel_d,
+                   double* part, int64_t boff, hipStream_t s);
+
 // Dense mode product on MFMA: y[o][i][k] = sum_j A[i][j] x[o][j][k], A given
 // zero-padded as npad x npad (npad = 16 * ceil(n / 16) <= 144), row-major.
 template <class S, class C>

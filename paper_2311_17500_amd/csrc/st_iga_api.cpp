@@ -85,6 +85,12 @@ struct st_iga_ctx {
   std::vector<int> cf_first_h, cf_chunks_h;
   double* cf_Bl_d = nullptr;
   float* cf_Bl_f = nullptr;
+  // fused quadrature pass along the same axis: second derivatives there and
+  // time elements per chunk
+  bool qf = false;
+  int qf_ne = 1;
+  std::vector<double> cf_B2_h;
+  double* cf_B2_d = nullptr;
   int *cf_first = nullptr, *cf_chunks = nullptr;
   Arena ar;
   std::string err;
@@ -264,6 +270,20 @@ void plan_fused_coef(st_iga_ctx* c) {
     c->cf_chunks_h[4 * k + 2] = d0;
     c->cf_chunks_h[4 * k + 3] = d1;
   }
+  // quadrature pass: per time element, the first buffer holds the time
+  // gathers (3 N_s per Gauss row) and, in 3D, the four x1 expansions; the
+  // second holds the five inputs of the fused kernel, its projection output
+  // and the element maxima before and after the x1 reduction
+  c->cf_B2_h.assign(static_cast<size_t>(D.Q) * kp, 0.0);
+  for (int q = 0; q < D.Q; ++q)
+    for (int k = 0; k < kp; ++k) c->cf_B2_h[static_cast<size_t>(q) * kp + k] = D.B[2][static_cast<size_t>(q) * kp + k];
+  const int nqt = c->nqt;
+  const int64_t x1 = (d == 3) ? static_cast<int64_t>(c->n[2]) * c->n[1] * c->Q[0] : 0;
+  const int64_t per0 = nqt * (3 * c->Ns + 4 * x1);
+  const int64_t per1 = nqt * 6 * nd * Qin + 2LL * D.nel * Qin;
+  const int64_t ne = std::min(c->big_len / per0, c->big_len / per1);
+  c->qf = nqt >= 1 && nqt <= 6 && ne >= 1;
+  c->qf_ne = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(c->nelt, ne)));
 }
 
 void host_setup(st_iga_ctx* c) {
@@ -455,6 +475,7 @@ void plan(st_iga_ctx* c) {
     c->cf_Bl_f = a.get<float>(static_cast<int64_t>(c->cf_Bl_h.size()));
     c->cf_first = a.get<int>(static_cast<int64_t>(c->cf_first_h.size()));
     c->cf_chunks = a.get<int>(static_cast<int64_t>(c->cf_chunks_h.size()));
+    c->cf_B2_d = a.get<double>(static_cast<int64_t>(c->cf_B2_h.size()));
   }
   T(c->Mt_x); T(c->Wt_x); T(c->Bt0); T(c->Bt1); T(c->BtT); T(c->Gt); T(c->Ut); T(c->UtT); T(c->Ew);
   for (st_iga_ctx::Dense* D : {&c->DUt, &c->DUtT, &c->DUs[0], &c->DUs[1], &c->DUs[2], &c->DUsT[0], &c->DUsT[1],
@@ -515,6 +536,11 @@ void plan(st_iga_ctx* c) {
   const int64_t chunk_pts = static_cast<int64_t>(c->chunk_el) * c->nqt * c->Qs;
   const int nchunks = (c->nelt + c->chunk_el - 1) / c->chunk_el;
   c->nb_part = static_cast<int>((chunk_pts + 255) / 256) * nchunks + 1;
+  if (c->qf) {
+    const int64_t Qin = (d == 3) ? static_cast<int64_t>(c->Q[0]) * c->Q[1] : c->Q[0];
+    const int64_t nbf = (Qin + 63) / 64 * c->nelt * c->cf_nchunk + 1;
+    c->nb_part = static_cast<int>(std::max<int64_t>(c->nb_part, nbf));
+  }
   c->part = a.get<double>(std::max<int64_t>(static_cast<int64_t>(c->nb_red) * 70, 2 * static_cast<int64_t>(c->nb_part)));
   c->dsc = a.get<double>(1024);
   c->gram_nb = static_cast<int>(std::min<int64_t>(512, (c->Ns + 31) / 32));
@@ -565,6 +591,7 @@ void upload_all(st_iga_ctx* c, hipStream_t s) {
     up(keepf.back(), static_cast<const float*>(c->cf_Bl_f), s);
     up(c->cf_first_h, static_cast<const int*>(c->cf_first), s);
     up(c->cf_chunks_h, static_cast<const int*>(c->cf_chunks), s);
+    up(c->cf_B2_h, static_cast<const double*>(c->cf_B2_d), s);
   }
   for (st_iga_ctx::Dense* D : {&c->DUt, &c->DUtT, &c->DUs[0], &c->DUs[1], &c->DUs[2], &c->DUsT[0], &c->DUsT[1],
                                &c->DUsT[2]}) {
@@ -1126,7 +1153,124 @@ void project_space(st_iga_ctx* c, const double* g, int64_t L, double* tA, double
 // One pass over all space-time Gauss points (time-chunked): ionic part of the
 // residual into rfull (full rows) and/or the element maxima of |R| into E; the
 // maxima of |u| and |u_t| into dsc[300], dsc[301].
+// Host side of the partial maxima of |u| and |u_t|: nb interleaved pairs in
+// part; the two maxima go to dsc[300], dsc[301].
+void finish_uv_maxima(st_iga_ctx* c, int64_t nb, hipStream_t s) {
+  std::vector<double> hp(2 * nb);
+  CK(hipMemcpyAsync(hp.data(), c->part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  check_launch();
+  double mm[2] = {0.0, 0.0};
+  for (int64_t b = 0; b < nb; ++b) {
+    mm[0] = std::max(mm[0], hp[2 * b]);
+    mm[1] = std::max(mm[1], hp[2 * b + 1]);
+  }
+  CK(hipMemcpyAsync(c->dsc + 300, mm, 2 * sizeof(double), hipMemcpyHostToDevice, s));
+  CK(hipStreamSynchronize(s));
+}
+
+// The quadrature pass with the slowest spatial axis fused (d >= 2): per
+// chunk of time elements, time gathers, expansions along the faster axes,
+// one k_quad_fused launch, then the element-maxima reductions and the
+// projection of the ionic current back to the B-splines.
+void quad_pass_fused(st_iga_ctx* c, const double* u, const double* w, bool want_res, bool want_theta,
+                     hipStream_t s) {
+  const int d = c->d;
+  const st_iga_problem& P = c->P;
+  const int64_t Ns = c->Ns;
+  const int nq = c->nqt;
+  const int nd = c->n[d - 1], neld = c->nel[d - 1];
+  const int64_t Qin = (d == 3) ? static_cast<int64_t>(c->Q[0]) * c->Q[1] : c->Q[0];
+  const int64_t L2 = static_cast<int64_t>(nd) * Qin;
+  const int64_t X1 = (d == 3) ? static_cast<int64_t>(c->n[2]) * c->n[1] * c->Q[0] : 0;
+  const int ne_max = c->qf_ne;
+  const int64_t rmax = static_cast<int64_t>(ne_max) * nq;
+  if (rmax * (3 * Ns + 4 * X1) > c->big_len || rmax * 6 * L2 + 2LL * ne_max * neld * Qin > c->big_len)
+    throw Fail{ST_IGA_EDEVICE, "quadrature chunk does not fit"};
+  double* U0 = c->big[0];
+  double* Ut = U0 + rmax * Ns;
+  double* W0 = Ut + rmax * Ns;
+  double* Xa = W0 + rmax * Ns;              // 3D: x1 expansions a, b, u_t, w
+  double* Xb = Xa + rmax * X1;
+  double* Xt = Xb + rmax * X1;
+  double* Xw = Xt + rmax * X1;
+  double* in[5];
+  for (int k = 0; k < 5; ++k) in[k] = c->big[1] + k * rmax * L2;
+  double* Gp = c->big[1] + 5 * rmax * L2;
+  double* Mp = Gp + rmax * L2;
+  double* Mx = Mp + static_cast<int64_t>(ne_max) * neld * Qin;
+  if (want_res) fill(c->rfull, 0.0, c->nfull, s);
+  const int n1 = c->n[0], n2 = c->n[1], n3 = c->n[2], Q1 = c->Q[0], Q2 = c->Q[1];
+  auto ax = [&](const Tab& t, const double* xin, double* yout, int64_t outer, int64_t inner, int nin) {
+    gather<double, double, double>(t.d, xin, yout, outer, inner, nin, 0, 1.0, 0.0, s);
+  };
+  int64_t boff = 0;
+  for (int e0 = 0; e0 < c->nelt; e0 += ne_max) {
+    const int ne = std::min(ne_max, c->nelt - e0);
+    const int q0 = e0 * nq, nqc = ne * nq;
+    gather_rows<double, double, double>(c->Bt0.d, q0, nqc, u, U0, 1, Ns, c->nt, 0, 1.0, 0.0, s);
+    gather_rows<double, double, double>(c->Bt1.d, q0, nqc, u, Ut, 1, Ns, c->nt, 0, 1.0, 0.0, s);
+    gather_rows<double, double, double>(c->Bt0.d, q0, nqc, w, W0, 1, Ns, c->nt, 0, 1.0, 0.0, s);
+    const Tab &E0 = c->Bq[0][0], &E2 = c->Bq[0][2];
+    double sL, sM, sF;
+    if (d == 3) {
+      const Tab &F0 = c->Bq[1][0], &F2 = c->Bq[1][2];
+      const int64_t o1 = static_cast<int64_t>(nqc) * n3 * n2, o2 = static_cast<int64_t>(nqc) * n3;
+      ax(E0, U0, Xa, o1, 1, n1);
+      ax(E2, U0, Xb, o1, 1, n1);
+      ax(E0, Ut, Xt, o1, 1, n1);
+      ax(E0, W0, Xw, o1, 1, n1);
+      ax(F0, Xa, in[0], o2, Q1, n2);   // B0 B0 u
+      ax(F2, Xa, in[1], o2, Q1, n2);   // x2 second derivative
+      ax(F0, Xb, in[2], o2, Q1, n2);   // x1 second derivative
+      ax(F0, Xt, in[3], o2, Q1, n2);
+      ax(F0, Xw, in[4], o2, Q1, n2);
+      sL = P.sigma[2];
+      sM = P.sigma[1];
+      sF = P.sigma[0];
+    } else {
+      const int64_t o1 = static_cast<int64_t>(nqc) * n2;
+      ax(E0, U0, in[0], o1, 1, n1);
+      ax(E2, U0, in[2], o1, 1, n1);
+      ax(E0, Ut, in[3], o1, 1, n1);
+      ax(E0, W0, in[4], o1, 1, n1);
+      sL = P.sigma[1];
+      sM = 0.0;
+      sF = P.sigma[0];
+    }
+    const int64_t nb = quad_fused(d, P.p_s, nq, in[0], in[1], in[2], in[3], in[4], nd, Qin, ne, c->cf_Bl_d,
+                                  c->cf_B2_d, c->cf_first, c->cf_chunks, c->cf_nchunk, c->wq_t + q0, c->wq_s, sL, sM,
+                                  sF, P.Cm, P.a, P.c1, P.c2, want_res ? Gp : nullptr, want_theta ? Mp : nullptr, neld,
+                                  c->part, boff, s);
+    if (nb < 0) throw Fail{ST_IGA_EINVAL, "fused quadrature pass: unsupported degrees"};
+    boff += nb;
+    if (want_theta) {
+      double* Edst = c->E + static_cast<int64_t>(e0) * c->Nels;
+      if (d == 3) {
+        mode_max(c->el_s_s[0], c->el_s_c[0], c->nel[0], Mp, Mx, static_cast<int64_t>(ne) * neld * Q2, 1, Q1, s);
+        mode_max(c->el_s_s[1], c->el_s_c[1], c->nel[1], Mx, Edst, static_cast<int64_t>(ne) * neld, c->nel[0], Q2, s);
+      } else {
+        mode_max(c->el_s_s[0], c->el_s_c[0], c->nel[0], Mp, Edst, static_cast<int64_t>(ne) * neld, 1, Q1, s);
+      }
+    }
+    if (want_res) {
+      if (d == 3) {
+        ax(c->BqT[1], Gp, Xa, static_cast<int64_t>(nqc) * n3, Q1, Q2);
+        ax(c->BqT[0], Xa, U0, static_cast<int64_t>(nqc) * n3 * n2, 1, Q1);
+      } else {
+        ax(c->BqT[0], Gp, U0, static_cast<int64_t>(nqc) * n2, 1, Q1);
+      }
+      gather<double, double, double>(c->BtT.d, U0, c->rfull, 1, Ns, nqc, q0, 1.0, 1.0, s);
+    }
+  }
+  finish_uv_maxima(c, boff, s);
+}
+
 void quad_pass(st_iga_ctx* c, const double* u, const double* w, bool want_res, bool want_theta, hipStream_t s) {
+  if (c->qf) {
+    quad_pass_fused(c, u, w, want_res, want_theta, s);
+    return;
+  }
   const int d = c->d;
   const st_iga_problem& P = c->P;
   const int64_t Ns = c->Ns, Qs = c->Qs;
