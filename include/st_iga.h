@@ -92,6 +92,8 @@ typedef struct {
   st_iga_precision prec;
   double lin_forcing;        /* > 0: outer iteration k solves to max(tol_lin, min(1e-2, lin_forcing*||delta_{k-1}||_inf)) */
   int32_t coef_slab;         /* time rows per slab of the low-rank operator terms (0: automatic) */
+  int32_t reorth;            /* Arnoldi Gram-Schmidt: 0 second pass only when the first removes more
+                                than 1 - 1/sqrt(2) of the norm, 1 always two passes */
 } st_iga_options;
 
 #define ST_IGA_MAX_OUTER_LOG 64
@@ -111,7 +113,7 @@ typedef struct {
 /* Defaults: su=1, eps_theta=0.1, eps_react=1e-2, max_rank=48, outer=0,
  * alpha=1 (Newton), theta_freeze=1e-4, tol_nonlin=1e-10, tol_lin=1e-10,
  * inner_tol=1e-4, restart=30, max_outer=60, max_krylov=3000, prec=FP64, lin_forcing=0,
- * coef_slab=0. */
+ * coef_slab=0, reorth=0. */
 void st_iga_default_options(st_iga_options* opt);
 
 /* Bytes of device workspace st_iga_setup needs for this problem/options
@@ -209,17 +211,22 @@ st_iga_status st_iga_newton_step(st_iga_ctx* ctx, const double* u_in, double* u_
  * update+norm, 5 pointwise ionic quadrature, 6 element/window maxima,
  * 7 banded mode products (constant part of the operator), 8 spline
  * expansion/projection at Gauss points, 9 dense eigenvector mode products of
- * the preconditioner.  Classes 100 + f + 16 q select one kernel function f
+ * the preconditioner, 10 fused coefficient terms.  Classes 100 + f + 16 q
+ * select one kernel function f
  * (0 scalar gather, 1 4-wide gather, 2 LDS row gather, 3 time mixing,
  * 4 MFMA dense mode product, 5 arrowhead, 6 multi-dot, 7 update+norm,
- * 8 pointwise ionic, 9 maxima, 10 column-sweep gather) in storage precision q (0 FP64, 1 FP32,
+ * 8 pointwise ionic, 9 maxima, 10 column-sweep gather, 11 fused coefficient
+ * terms, 12 fused quadrature pass, 13 dual-table sweep) in storage precision q (0 FP64, 1 FP32,
  * 2 BF16; the reductions are FP64 only).  profile_read returns the summed duration (ms), the
  * launch count and the summed algorithmic bytes (each input and output array
  * counted once per launch) since the last reset, and synchronizes the
- * recorded events.  Any output pointer may be NULL. */
+ * recorded events.  Any output pointer may be NULL.  profile_record returns
+ * launch i (in launch order since the last reset): function id f + 16 q,
+ * duration (ms) and algorithmic bytes; EINVAL past the last launch. */
 st_iga_status st_iga_profile(st_iga_ctx* ctx, int32_t enable);
 st_iga_status st_iga_profile_read(st_iga_ctx* ctx, int32_t kernel_class, double* ms, int64_t* launches,
                                   double* bytes, int32_t reset);
+st_iga_status st_iga_profile_record(st_iga_ctx* ctx, int64_t i, int32_t* fn, double* ms, double* bytes);
 
 /* Lifted initial datum (N_s entries, HOST output) and the number of spatial
  * Greville points inside the stimulus. */

@@ -23,7 +23,7 @@ EXPORTS = ["st_iga_default_options", "st_iga_workspace_bytes", "st_iga_setup", "
            "st_iga_set_factors", "st_iga_get_factors", "st_iga_theta_grid", "st_iga_apply", "st_iga_precond",
            "st_iga_residual", "st_iga_w_update", "st_iga_krylov", "st_iga_solve", "st_iga_lift", "st_iga_sizes",
            "st_iga_destroy", "st_iga_last_error", "st_iga_host_query", "st_iga_newton_step", "st_iga_profile",
-           "st_iga_profile_read", "st_iga_apply_lowp", "st_iga_precond_lowp"]
+           "st_iga_profile_read", "st_iga_apply_lowp", "st_iga_precond_lowp", "st_iga_profile_record"]
 
 
 class Problem(C.Structure):
@@ -43,7 +43,7 @@ class Options(C.Structure):
                 ("outer", C.c_int32), ("alpha", C.c_double), ("theta_freeze", C.c_double),
                 ("tol_nonlin", C.c_double), ("tol_lin", C.c_double), ("inner_tol", C.c_double),
                 ("restart", C.c_int32), ("max_outer", C.c_int32), ("max_krylov", C.c_int32), ("prec", C.c_int32),
-                ("lin_forcing", C.c_double), ("coef_slab", C.c_int32)]
+                ("lin_forcing", C.c_double), ("coef_slab", C.c_int32), ("reorth", C.c_int32)]
 
 
 LOG = 64
@@ -290,9 +290,22 @@ class Solver:
 
     KCLASSES = ["gather", "time_mix", "arrowhead", "multidot", "update_norm", "pointwise_ionic", "maxima",
                 "banded", "expand", "dense_fd", "coefficient"]
+    FNAMES = ["gather_scalar", "gather_v4", "gather_rows", "time_mix", "dense_mode_mfma", "arrowhead",
+              "multidot", "update_norm", "pointwise_ionic", "mode_max", "gather_sweep", "coef_fused",
+              "quad_fused", "sweep_dual"]
 
     def profile(self, on=True):
         self._chk(self.lib.st_iga_profile(self.ctx, int(on)))
+
+    def profile_records(self):
+        """[(function name, ms, algorithmic bytes)] of every launch since the last reset."""
+        out, i = [], 0
+        fn, ms, by = C.c_int32(0), C.c_double(0), C.c_double(0)
+        while self.lib.st_iga_profile_record(self.ctx, i, C.byref(fn), C.byref(ms), C.byref(by)) == OK:
+            name = self.FNAMES[fn.value % 16] + "<" + ["f64", "f32", "bf16"][fn.value // 16] + ">"
+            out.append((name, ms.value, by.value))
+            i += 1
+        return out
 
     def profile_read(self, reset=True):
         """{class: (ms, launches, algorithmic bytes)} since the last reset."""
@@ -301,9 +314,7 @@ class Solver:
             ms, n, by = C.c_double(0), C.c_int64(0), C.c_double(0)
             self._chk(self.lib.st_iga_profile_read(self.ctx, k, C.byref(ms), C.byref(n), C.byref(by), 0))
             out[name] = (ms.value, n.value, by.value)
-        fnames = ["gather_scalar", "gather_v4", "gather_rows", "time_mix", "dense_mode_mfma", "arrowhead",
-                  "multidot", "update_norm", "pointwise_ionic", "mode_max", "gather_sweep", "coef_fused",
-                  "quad_fused"]
+        fnames = self.FNAMES
         for q, pn in enumerate(["f64", "f32", "bf16"]):
             for f, fname in enumerate(fnames):
                 ms, n, by = C.c_double(0), C.c_int64(0), C.c_double(0)

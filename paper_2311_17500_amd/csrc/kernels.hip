@@ -338,40 +338,211 @@ __global__ void __launch_bounds__(TPB) k_sweep(const int* __restrict__ c0, const
   }
 }
 
-// Fastest-axis variant (inner == 1): a block stages RB consecutive input rows
-// (contiguous, coalesced) in LDS, then produces the RB output rows from LDS
-// and writes them contiguously.
+// Column-sweep for any inner extent: the (outer, inner) columns are
+// flattened and lane l of a wave owns columns base + l + 64 e (e < E), so
+// every load and store instruction is coalesced whatever the alignment of
+// inner; the window logic is that of k_sweep.
+template <class S, class C, int W, int E>
+__global__ void __launch_bounds__(TPB) k_sweep_flat(const int* __restrict__ c0, const C* __restrict__ coef, int n_out,
+                                                    const S* __restrict__ x, S* __restrict__ y, int64_t inner,
+                                                    int n_in, int in_base, C alpha, C beta, int64_t ncols, int rc,
+                                                    int nchunks) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * TPB + threadIdx.x) >> 6;
+  const int chunk = static_cast<int>(wave % nchunks);
+  const int64_t grp = wave / nchunks;
+  const int i0 = chunk * rc;
+  const int i1 = min(n_out, i0 + rc);
+  if (i0 >= i1) return;
+  int64_t xo[E], yo[E];
+  bool ok[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int64_t c = grp * (64 * E) + lane + 64 * e;
+    ok[e] = c < ncols;
+    const int64_t cc = ok[e] ? c : 0;
+    const int64_t o = cc / inner, k = cc - o * inner;
+    xo[e] = o * n_in * inner + k;
+    yo[e] = o * static_cast<int64_t>(n_out) * inner + k;
+  }
+  C ring[W][E];
+  int base = c0[i0] - in_base;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const int r = base + w;
+    const bool rin = static_cast<unsigned>(r) < static_cast<unsigned>(n_in);
+#pragma unroll
+    for (int e = 0; e < E; ++e) ring[w][e] = (rin && ok[e]) ? to_c(x[xo[e] + static_cast<int64_t>(r) * inner], C(0)) : C(0);
+  }
+  for (int i = i0; i < i1; ++i) {
+    const int cb = c0[i] - in_base;
+    while (base < cb) {
+#pragma unroll
+      for (int w = 0; w < W - 1; ++w)
+#pragma unroll
+        for (int e = 0; e < E; ++e) ring[w][e] = ring[w + 1][e];
+      ++base;
+      const int r = base + W - 1;
+      const bool rin = static_cast<unsigned>(r) < static_cast<unsigned>(n_in);
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        ring[W - 1][e] = (rin && ok[e]) ? to_c(x[xo[e] + static_cast<int64_t>(r) * inner], C(0)) : C(0);
+    }
+    const C* cf = coef + static_cast<int64_t>(i) * W;
+    C acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = C(0);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const C a = cf[w];
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc[e] += a * ring[w][e];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (!ok[e]) continue;
+      S* yp = y + yo[e] + static_cast<int64_t>(i) * inner;
+      C r = alpha * acc[e];
+      if (beta != C(0)) r += beta * to_c(*yp, C(0));
+      *yp = from_c<S>(r);
+    }
+  }
+}
+
+// Two tables P, Q with the same windows applied along one axis in one pass
+// (flattened columns as in k_sweep_flat):
+//   out1 = P x (when out1 is given),  out2 = alpha Q x + beta P z.
+// One sweep of the constant Kronecker part needs exactly this at every axis
+// after the first (mass and stiffness share their band).
+template <class S, class C, int W, int E>
+__global__ void __launch_bounds__(TPB) k_sweep_dual(const int* __restrict__ c0, const C* __restrict__ P,
+                                                    const C* __restrict__ Q, int n_out, const S* __restrict__ x,
+                                                    const S* __restrict__ z, S* __restrict__ out1,
+                                                    S* __restrict__ out2, int64_t inner, int n_in, int in_base,
+                                                    C alpha, C beta, int64_t ncols, int rc, int nchunks) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * TPB + threadIdx.x) >> 6;
+  const int chunk = static_cast<int>(wave % nchunks);
+  const int64_t grp = wave / nchunks;
+  const int i0 = chunk * rc;
+  const int i1 = min(n_out, i0 + rc);
+  if (i0 >= i1) return;
+  int64_t xo[E], yo[E];
+  bool ok[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int64_t c = grp * (64 * E) + lane + 64 * e;
+    ok[e] = c < ncols;
+    const int64_t cc = ok[e] ? c : 0;
+    const int64_t o = cc / inner, k = cc - o * inner;
+    xo[e] = o * n_in * inner + k;
+    yo[e] = o * static_cast<int64_t>(n_out) * inner + k;
+  }
+  C rx[W][E], rz[W][E];
+  int base = c0[i0] - in_base;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const int r = base + w;
+    const bool rin = static_cast<unsigned>(r) < static_cast<unsigned>(n_in);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int64_t off = xo[e] + static_cast<int64_t>(r) * inner;
+      rx[w][e] = (rin && ok[e]) ? to_c(x[off], C(0)) : C(0);
+      rz[w][e] = (rin && ok[e]) ? to_c(z[off], C(0)) : C(0);
+    }
+  }
+  for (int i = i0; i < i1; ++i) {
+    const int cb = c0[i] - in_base;
+    while (base < cb) {
+#pragma unroll
+      for (int w = 0; w < W - 1; ++w)
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          rx[w][e] = rx[w + 1][e];
+          rz[w][e] = rz[w + 1][e];
+        }
+      ++base;
+      const int r = base + W - 1;
+      const bool rin = static_cast<unsigned>(r) < static_cast<unsigned>(n_in);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int64_t off = xo[e] + static_cast<int64_t>(r) * inner;
+        rx[W - 1][e] = (rin && ok[e]) ? to_c(x[off], C(0)) : C(0);
+        rz[W - 1][e] = (rin && ok[e]) ? to_c(z[off], C(0)) : C(0);
+      }
+    }
+    const C* pf = P + static_cast<int64_t>(i) * W;
+    const C* qf = Q + static_cast<int64_t>(i) * W;
+    C px[E], qx[E], pz[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) px[e] = qx[e] = pz[e] = C(0);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const C pw = pf[w], qw = qf[w];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        px[e] += pw * rx[w][e];
+        qx[e] += qw * rx[w][e];
+        pz[e] += pw * rz[w][e];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (!ok[e]) continue;
+      const int64_t off = yo[e] + static_cast<int64_t>(i) * inner;
+      if (out1) out1[off] = from_c<S>(px[e]);
+      out2[off] = from_c<S>(alpha * qx[e] + beta * pz[e]);
+    }
+  }
+}
+
+// Fastest-axis variant (inner == 1): the table is staged in LDS once per
+// block; the block then loops over groups of RB consecutive input rows (one
+// contiguous span, staged with coalesced 16-byte loads when aligned),
+// produces the RB output rows from LDS and writes them contiguously.
 template <class S, class C>
 __global__ void __launch_bounds__(TPB) k_gather_rows(const int* __restrict__ col, const C* __restrict__ coef, int W,
                                                      int n_out, const S* __restrict__ x, S* __restrict__ y, int n_in,
                                                      int in_base, C alpha, C beta, int64_t nrows, int RB) {
   extern __shared__ char smem_raw[];
-  C* xs = reinterpret_cast<C*>(smem_raw);                       // RB * n_in
-  C* cs = xs + RB * n_in;                                       // n_out * W coefficients
-  int* is = reinterpret_cast<int*>(cs + n_out * W);             // n_out * W local columns (-1: skip)
-  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RB;
-  const int rb = static_cast<int>(min(static_cast<int64_t>(RB), nrows - r0));
-  const S* xb = x + r0 * n_in;
-  for (int t = threadIdx.x; t < rb * n_in; t += TPB) xs[t] = to_c(xb[t], C(0));
+  // table staged tap-major ([w][i]) so that lanes reading consecutive output
+  // rows hit consecutive LDS words
+  C* cs = reinterpret_cast<C*>(smem_raw);                       // W * n_out coefficients
+  int* is = reinterpret_cast<int*>(cs + n_out * W);             // W * n_out local columns
+  S* xs = reinterpret_cast<S*>(smem_raw + ((static_cast<size_t>(n_out) * W * (sizeof(C) + sizeof(int)) + 15) & ~static_cast<size_t>(15)));
   for (int t = threadIdx.x; t < n_out * W; t += TPB) {
+    const int i = t / W, w = t - i * W;
     const int c = col[t] - in_base;
     const bool ok = static_cast<unsigned>(c) < static_cast<unsigned>(n_in);
-    cs[t] = ok ? coef[t] : C(0);
-    is[t] = ok ? c : 0;
+    cs[w * n_out + i] = ok ? coef[t] : C(0);
+    is[w * n_out + i] = ok ? c : 0;
   }
-  __syncthreads();
-  S* yb = y + r0 * n_out;
-  const int tot = rb * n_out;
-  for (int t = threadIdx.x; t < tot; t += TPB) {
-    const int r = t / n_out, i = t - r * n_out;
-    const C* cf = cs + i * W;
-    const int* ci = is + i * W;
-    const C* xr = xs + r * n_in;
-    C acc = C(0);
-    for (int w = 0; w < W; ++w) acc += cf[w] * xr[ci[w]];
-    C v = alpha * acc;
-    if (beta != C(0)) v += beta * to_c(yb[t], C(0));
-    yb[t] = from_c<S>(v);
+  constexpr int V = 16 / sizeof(S);
+  typedef struct { S v[V]; } __attribute__((aligned(16))) Vec;
+  for (int64_t r0 = static_cast<int64_t>(blockIdx.x) * RB; r0 < nrows; r0 += static_cast<int64_t>(gridDim.x) * RB) {
+    const int rb = static_cast<int>(min(static_cast<int64_t>(RB), nrows - r0));
+    const S* xb = x + r0 * n_in;
+    const int span = rb * n_in;
+    const int nv = (reinterpret_cast<uintptr_t>(xb) % 16 == 0) ? span / V : 0;
+    __syncthreads();   // the previous group's reads of xs are done
+    {
+      const Vec* src = reinterpret_cast<const Vec*>(xb);
+      Vec* dst = reinterpret_cast<Vec*>(xs);
+      for (int t = threadIdx.x; t < nv; t += TPB) dst[t] = src[t];
+    }
+    for (int t = nv * V + threadIdx.x; t < span; t += TPB) xs[t] = xb[t];
+    __syncthreads();
+    S* yb = y + r0 * n_out;
+    const int tot = rb * n_out;
+    for (int t = threadIdx.x; t < tot; t += TPB) {
+      const int r = t / n_out, i = t - r * n_out;
+      const S* xr = xs + r * n_in;
+      C acc = C(0);
+      for (int w = 0; w < W; ++w) acc += cs[w * n_out + i] * to_c(xr[is[w * n_out + i]], C(0));
+      C v = alpha * acc;
+      if (beta != C(0)) v += beta * to_c(yb[t], C(0));
+      yb[t] = from_c<S>(v);
+    }
   }
 }
 
@@ -588,7 +759,7 @@ __global__ void __launch_bounds__(256) k_dense_mode(const C* __restrict__ Ap, in
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = A4{0, 0, 0, 0};
   const int r16 = lane & 15, q4 = lane >> 4;
-  for (int kk = 0; kk < npad; kk += 4) {
+  for (int kk = 0; kk < ((n + 3) & ~3); kk += 4) {
     const int j = kk + q4;
     const C b = (cv && j < n) ? to_c(xb[static_cast<int64_t>(j) * inner], C(0)) : C(0);
 #pragma unroll
@@ -636,7 +807,7 @@ __global__ void __launch_bounds__(256) k_dense_modeE(const C* __restrict__ Ap, i
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[t][e] = A4{0, 0, 0, 0};
-  for (int kk = 0; kk < npad; kk += 4) {
+  for (int kk = 0; kk < ((n + 3) & ~3); kk += 4) {
     const int j = kk + q4;
     C b[E];
     const bool ok = cv && j < n;
@@ -664,6 +835,143 @@ __global__ void __launch_bounds__(256) k_dense_modeE(const C* __restrict__ Ap, i
         storev<E, S, C>(yb + static_cast<int64_t>(i) * inner, r);
       }
     }
+}
+
+// Variant for any inner extent: the (outer, inner) columns are flattened; a
+// wave owns 16E consecutive columns as E MFMA tiles, lane l feeding column
+// base + 16 e + l%16 of tile e, so each load instruction reads 16
+// consecutive columns of 4 rows whatever the alignment of inner.
+template <class S, class C, int NT, int E, bool LDS_A>
+__global__ void __launch_bounds__(256) k_dense_modeU(const C* __restrict__ Ap, int n, int npad,
+                                                     const S* __restrict__ x, S* __restrict__ y, int64_t inner,
+                                                     int64_t ncols) {
+  extern __shared__ char smem_raw[];
+  C* As = reinterpret_cast<C*>(smem_raw);
+  if (LDS_A) {
+    for (int t = threadIdx.x; t < npad * npad; t += blockDim.x) As[t] = Ap[t];
+    __syncthreads();
+  }
+  const C* Asrc = LDS_A ? As : Ap;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int64_t base = (static_cast<int64_t>(blockIdx.x) * 4 + wv) * (16 * E) + r16;
+  int64_t off[E];
+  bool ok[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int64_t c = base + 16 * e;
+    ok[e] = c < ncols;
+    const int64_t cc = ok[e] ? c : 0;
+    const int64_t o = cc / inner;
+    off[e] = o * static_cast<int64_t>(n) * inner + (cc - o * inner);
+  }
+  typedef typename Acc4<C>::T A4;
+  A4 acc[NT][E];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[t][e] = A4{0, 0, 0, 0};
+  const int n4 = (n + 3) & ~3;
+  for (int kk = 0; kk < n4; kk += 4) {
+    const int j = kk + q4;
+    C b[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) b[e] = (j < n && ok[e]) ? to_c(x[off[e] + static_cast<int64_t>(j) * inner], C(0)) : C(0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const C a = Asrc[(t * 16 + r16) * npad + j];
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc[t][e] = mfma16x16x4(a, b[e], acc[t][e]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = t * 16 + (std::is_same<C, double>::value ? q4 + 4 * v : 4 * q4 + v);
+      if (i < n) {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (ok[e]) y[off[e] + static_cast<int64_t>(i) * inner] = from_c<S>(acc[t][e][v]);
+      }
+    }
+}
+
+// Variant for inner == 1 (the fastest axis): a one-wave block stages 16E
+// consecutive rows x[o][0..n) (one contiguous span) in LDS with coalesced
+// loads, multiplies them as E MFMA column tiles (each A fragment serves E
+// products), writes the results back over the staged rows and stores the
+// span coalesced.
+template <class S, class C, int NT, int E>
+__global__ void __launch_bounds__(64) k_dense_rows(const C* __restrict__ Ap, int n, int npad, const S* __restrict__ x,
+                                                   S* __restrict__ y, int64_t outer) {
+  extern __shared__ char smem_raw[];
+  S* Xs = reinterpret_cast<S*>(smem_raw);
+  constexpr int RB = 16 * E;
+  const int64_t o0 = static_cast<int64_t>(blockIdx.x) * RB;
+  const int rows = static_cast<int>(min<int64_t>(RB, outer - o0));
+  const int span = rows * n;
+  const S* xs = x + o0 * n;
+  // the span starts at a multiple of 16 n elements: 16-byte aligned when x is
+  constexpr int V = 16 / sizeof(S);
+  typedef struct { S v[V]; } __attribute__((aligned(16))) Vec;
+  const int lane = threadIdx.x;
+  const int nv = (reinterpret_cast<uintptr_t>(xs) % 16 == 0) ? span / V : 0;
+  {
+    const Vec* src = reinterpret_cast<const Vec*>(xs);
+    Vec* dst = reinterpret_cast<Vec*>(Xs);
+#pragma unroll 4
+    for (int t = lane; t < nv; t += 64) dst[t] = src[t];
+  }
+  for (int t = nv * V + lane; t < span; t += 64) Xs[t] = xs[t];
+  __syncthreads();
+  const int r16 = lane & 15, q4 = lane >> 4;
+  typedef typename Acc4<C>::T A4;
+  A4 acc[NT][E];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[t][e] = A4{0, 0, 0, 0};
+  const int n4 = (n + 3) & ~3;
+  for (int kk = 0; kk < n4; kk += 4) {
+    const int j = kk + q4;
+    C b[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int rr = 16 * e + r16;
+      b[e] = (rr < rows && j < n) ? to_c(Xs[rr * n + j], C(0)) : C(0);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const C av = Ap[(t * 16 + r16) * npad + j];
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc[t][e] = mfma16x16x4(av, b[e], acc[t][e]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int rr = 16 * e + r16;
+    if (rr < rows) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = t * 16 + (std::is_same<C, double>::value ? q4 + 4 * v : 4 * q4 + v);
+          if (i < n) Xs[rr * n + i] = from_c<S>(acc[t][e][v]);
+        }
+    }
+  }
+  __syncthreads();
+  S* ys = y + o0 * n;
+  const int mv = (reinterpret_cast<uintptr_t>(ys) % 16 == 0) ? span / V : 0;
+  {
+    const Vec* src = reinterpret_cast<const Vec*>(Xs);
+    Vec* dst = reinterpret_cast<Vec*>(ys);
+#pragma unroll 4
+    for (int t = lane; t < mv; t += 64) dst[t] = src[t];
+  }
+  for (int t = mv * V + lane; t < span; t += 64) ys[t] = Xs[t];
 }
 
 // ---------------------------------------------------------------- arrowhead
@@ -1203,8 +1511,38 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
                         static_cast<double>(total) * sizeof(To) * (beta != C(0) ? 2 : 1);
   const int64_t nrows = outer * t.n_out;
   const int vec = (inner % 4 == 0) ? 4 : (inner % 2 == 0 ? 2 : 1);
+  const bool sweep_w = t.W == 2 || t.W == 3 || t.W == 4 || t.W == 5 || t.W == 7 || t.W == 9 || t.W == 16;
+  if (std::is_same<Ti, To>::value && t.c0 != nullptr && sweep_w && inner >= 32 &&
+      !(vec == 4 && (reinterpret_cast<uintptr_t>(x) % (4 * sizeof(Ti))) == 0 &&
+        (reinterpret_cast<uintptr_t>(y) % (4 * sizeof(To))) == 0)) {
+    // inner not a multiple of 4 (or unaligned): flattened columns, E per lane
+    const int64_t ncols = outer * inner;
+    const int E = 4;
+    const int64_t groups = (ncols + 64 * E - 1) / (64 * E);
+    const int64_t want = 1 << 12;   // waves
+    int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>(t.n_out / 4 + 1, (want + groups - 1) / groups));
+    const int rc = static_cast<int>((t.n_out + nchunks - 1) / nchunks);
+    nchunks = (t.n_out + rc - 1) / rc;
+    const int64_t waves = groups * nchunks;
+    ProfScope ps(t_gather_cls, 10 + 16 * prec_code<Ti>(), s, gbytes);
+    const unsigned blocks = static_cast<unsigned>((waves * 64 + TPB - 1) / TPB);
+#define SF(w)                                                                                                        \
+  hipLaunchKernelGGL((k_sweep_flat<Ti, C, w, 4>), dim3(blocks), dim3(TPB), 0, s, t.c0, t.coef, t.n_out, x,              \
+                     reinterpret_cast<Ti*>(y), inner, n_in, in_base, alpha, beta, ncols, rc, static_cast<int>(nchunks))
+    switch (t.W) {
+      case 2: SF(2); break;
+      case 3: SF(3); break;
+      case 4: SF(4); break;
+      case 5: SF(5); break;
+      case 7: SF(7); break;
+      case 9: SF(9); break;
+      default: SF(16); break;
+    }
+#undef SF
+    return;
+  }
   if (std::is_same<Ti, To>::value && t.c0 != nullptr && inner >= 2 && inner < (static_cast<int64_t>(1) << 31) &&
-      (t.W == 2 || t.W == 3 || t.W == 4 || t.W == 5 || t.W == 7 || t.W == 9 || t.W == 16) &&
+      sweep_w &&
       (reinterpret_cast<uintptr_t>(x) % (vec * sizeof(Ti))) == 0 && (reinterpret_cast<uintptr_t>(y) % (vec * sizeof(To))) == 0) {
     const int64_t slots = inner / vec;
     // enough threads to fill the chip: chunk the output rows
@@ -1267,13 +1605,16 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
     }
   }
   if (inner == 1 && std::is_same<Ti, To>::value) {
-    // rows per block: stage about 2048 input values
-    const int RB = std::max(1, std::min(64, 2048 / std::max(n_in, 1)));
-    // here a "row" is one outer index: n_in inputs in, t.n_out outputs out
-    const int64_t blocks = (outer + RB - 1) / RB;
-    const size_t sh = static_cast<size_t>(RB) * n_in * sizeof(C) + static_cast<size_t>(t.n_out) * t.W * (sizeof(C) + sizeof(int));
-    if (blocks < (static_cast<int64_t>(1) << 31) && sh <= 48 * 1024) {
+    // rows per group: about 4096 staged input values, a multiple of 4 rows
+    // (the group spans then stay 16-byte aligned)
+    int RB = std::max(1, std::min(256, 4096 / std::max(n_in, 1)));
+    if (RB >= 4) RB &= ~3;
+    const size_t tab = (static_cast<size_t>(t.n_out) * t.W * (sizeof(C) + sizeof(int)) + 15) & ~static_cast<size_t>(15);
+    const size_t sh = tab + static_cast<size_t>(RB) * n_in * sizeof(Ti);
+    const int64_t groups = (outer + RB - 1) / RB;
+    if (sh <= 64 * 1024) {
       ProfScope ps(t_gather_cls, 2 + 16 * prec_code<Ti>(), s, gbytes);
+      const int64_t blocks = std::min<int64_t>(groups, 2048);
       hipLaunchKernelGGL((k_gather_rows<Ti, C>), dim3(static_cast<unsigned>(blocks)), dim3(TPB), sh, s, t.col, t.coef,
                          t.W, t.n_out, x, reinterpret_cast<Ti*>(y), n_in, in_base, alpha, beta, outer, RB);
       return;
@@ -1287,6 +1628,40 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
   else
     hipLaunchKernelGGL((k_gather<Ti, To, C, int64_t>), dim3(grid_for(total)), dim3(TPB), 0, s, t.col, t.coef, t.W,
                        t.n_out, x, y, inner, n_in, in_base, alpha, beta, total);
+}
+
+template <class S, class C>
+bool gather_dual(const DTable<C>& P, const DTable<C>& Q, const S* x, const S* z, S* out1, S* out2, int64_t outer,
+                 int64_t inner, int n_in, int in_base, C alpha, C beta, hipStream_t s) {
+  if (P.c0 == nullptr || P.W != Q.W || P.n_out != Q.n_out || inner < 2) return false;
+  const int W = P.W;
+  if (!(W == 2 || W == 3 || W == 4 || W == 5 || W == 7 || W == 9 || W == 11)) return false;
+  const int64_t ncols = outer * inner;
+  if (ncols == 0) return true;
+  constexpr int E = 4;
+  const int64_t groups = (ncols + 64 * E - 1) / (64 * E);
+  const int64_t want = 1 << 12;   // waves
+  int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>(P.n_out / 4 + 1, (want + groups - 1) / groups));
+  const int rc = static_cast<int>((P.n_out + nchunks - 1) / nchunks);
+  nchunks = (P.n_out + rc - 1) / rc;
+  const int64_t waves = groups * nchunks;
+  const double by = (2.0 * outer * n_in * inner + (out1 ? 2.0 : 1.0) * outer * P.n_out * inner) * sizeof(S);
+  ProfScope ps(t_gather_cls, 13 + 16 * prec_code<S>(), s, by);
+  const unsigned blocks = static_cast<unsigned>((waves * 64 + TPB - 1) / TPB);
+#define SD(w)                                                                                                      \
+  hipLaunchKernelGGL((k_sweep_dual<S, C, w, E>), dim3(blocks), dim3(TPB), 0, s, P.c0, P.coef, Q.coef, P.n_out, x, z, \
+                     out1, out2, inner, n_in, in_base, alpha, beta, ncols, rc, static_cast<int>(nchunks))
+  switch (W) {
+    case 2: SD(2); break;
+    case 3: SD(3); break;
+    case 4: SD(4); break;
+    case 5: SD(5); break;
+    case 7: SD(7); break;
+    case 9: SD(9); break;
+    default: SD(11); break;
+  }
+#undef SD
+  return true;
 }
 
 template <class Ti, class To, class C>
@@ -1370,6 +1745,23 @@ void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, i
   const size_t abytes = static_cast<size_t>(npad) * npad * sizeof(C);
   const bool lds = abytes <= 64 * 1024;
   ProfScope ps(K_DENSE, 4 + 16 * prec_code<S>(), s, 2.0 * ncols * n * sizeof(S));
+  if (inner == 1 && NT <= 9) {
+    // one wave per block; 4 column tiles (64 rows) unless the accumulators
+    // (FP64 beyond 4 row tiles) or the staged rows would not fit
+    const int ER = (std::is_same<C, double>::value && NT > 4) ? 2 : 4;
+    const size_t xbytes = static_cast<size_t>(16 * ER) * n * sizeof(S);
+    if (xbytes <= 64 * 1024) {
+      const unsigned gridR = static_cast<unsigned>((outer + 16 * ER - 1) / (16 * ER));
+#define DMR(nt, e) case nt: hipLaunchKernelGGL((k_dense_rows<S, C, nt, e>), dim3(gridR), dim3(64), xbytes, s, Ap, n, npad, x, y, outer); break;
+      if constexpr (std::is_same<C, double>::value) {
+        switch (NT) { DMR(1, 4) DMR(2, 4) DMR(3, 4) DMR(4, 4) DMR(5, 2) DMR(6, 2) DMR(7, 2) DMR(8, 2) DMR(9, 2) default: break; }
+      } else {
+        switch (NT) { DMR(1, 4) DMR(2, 4) DMR(3, 4) DMR(4, 4) DMR(5, 4) DMR(6, 4) DMR(7, 4) DMR(8, 4) DMR(9, 4) default: break; }
+      }
+#undef DMR
+      return;
+    }
+  }
   // columns per lane: 4 while the accumulators fit (FP32 up to 9 row tiles,
   // FP64 up to 4), else 2; the E-wide loads need inner % E == 0 and aligned x, y
   const bool f64 = std::is_same<C, double>::value;
@@ -1387,7 +1779,7 @@ void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, i
     else hipLaunchKernelGGL((k_dense_modeE<S, C, nt, e, false>), dim3(gridE), dim3(256), 0, s, Ap, n, npad, x, y, inner, ncols);  \
     break;
     if (E == 4) {
-      if (f64) {
+      if constexpr (std::is_same<C, double>::value) {
         switch (NT) { DME(1, 4) DME(2, 4) DME(3, 4) DME(4, 4) default: break; }
       } else {
         switch (NT) { DME(1, 4) DME(2, 4) DME(3, 4) DME(4, 4) DME(5, 4) DME(6, 4) DME(7, 4) DME(8, 4) DME(9, 4) default: break; }
@@ -1396,6 +1788,28 @@ void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, i
       switch (NT) { DME(1, 2) DME(2, 2) DME(3, 2) DME(4, 2) DME(5, 2) DME(6, 2) DME(7, 2) DME(8, 2) DME(9, 2) default: break; }
     }
 #undef DME
+    return;
+  }
+  if (NT <= 9) {
+    // any inner extent: tiles of 16 EU columns inside one outer index
+    const int EU = (std::is_same<C, double>::value ? NT <= 4 : true) ? 4 : 2;
+    const int64_t tiles = (ncols + 16 * EU - 1) / (16 * EU);
+    const unsigned gridU = static_cast<unsigned>((tiles + 3) / 4);
+#define DMU(nt, e)                                                                                              \
+  case nt:                                                                                                      \
+    if (lds) hipLaunchKernelGGL((k_dense_modeU<S, C, nt, e, true>), dim3(gridU), dim3(256), abytes, s, Ap, n, npad, x, y, inner, ncols); \
+    else hipLaunchKernelGGL((k_dense_modeU<S, C, nt, e, false>), dim3(gridU), dim3(256), 0, s, Ap, n, npad, x, y, inner, ncols);  \
+    break;
+    if (EU == 4) {
+      if constexpr (std::is_same<C, double>::value) {
+        switch (NT) { DMU(1, 4) DMU(2, 4) DMU(3, 4) DMU(4, 4) default: break; }
+      } else {
+        switch (NT) { DMU(1, 4) DMU(2, 4) DMU(3, 4) DMU(4, 4) DMU(5, 4) DMU(6, 4) DMU(7, 4) DMU(8, 4) DMU(9, 4) default: break; }
+      }
+    } else {
+      switch (NT) { DMU(5, 2) DMU(6, 2) DMU(7, 2) DMU(8, 2) DMU(9, 2) default: break; }
+    }
+#undef DMU
     return;
   }
 #define DM_CASE(nt)                                                                                          \
@@ -1440,6 +1854,19 @@ void kprof_read(int cls, double* ms, int64_t* launches, double* bytes, int reset
     p.rec.clear();
     p.used = 0;
   }
+}
+
+bool kprof_record(int64_t i, int* fn, double* ms, double* bytes) {
+  ProfState& p = prof();
+  if (i < 0 || i >= static_cast<int64_t>(p.rec.size())) return false;
+  const auto& r = p.rec[static_cast<size_t>(i)];
+  hipEventSynchronize(r.b);
+  float t = 0.0f;
+  hipEventElapsedTime(&t, r.a, r.b);
+  if (fn) *fn = r.fn;
+  if (ms) *ms = t;
+  if (bytes) *bytes = r.bytes;
+  return true;
 }
 
 int reduce_blocks(int64_t n) { return static_cast<int>((n + RED_CHUNK - 1) / RED_CHUNK); }
@@ -1572,6 +1999,10 @@ template void gather<bf16, bf16, float>(const DTable<float>&, const bf16*, bf16*
                                         float, hipStream_t);
 template void gather_rows<double, double, double>(const DTable<double>&, int, int, const double*, double*, int64_t,
                                                   int64_t, int, int, double, double, hipStream_t);
+template bool gather_dual<double, double>(const DTable<double>&, const DTable<double>&, const double*, const double*,
+                                          double*, double*, int64_t, int64_t, int, int, double, double, hipStream_t);
+template bool gather_dual<float, float>(const DTable<float>&, const DTable<float>&, const float*, const float*, float*,
+                                        float*, int64_t, int64_t, int, int, float, float, hipStream_t);
 template bool coef_fused<double, double>(const double*, const double*, int, int, int, int, int, int, int,
                                          const double*, int, int, const double*, const int*, const int*, int, int,
                                          int64_t, double*, int64_t, hipStream_t);

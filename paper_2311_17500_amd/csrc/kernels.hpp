@@ -22,6 +22,8 @@ void kprof_gather_class(int cls);
 // Sum of launch durations (ms), launch count and algorithmic bytes of a class since the last reset;
 // synchronizes the recorded events.  Resets when reset != 0.
 void kprof_read(int cls, double* ms, int64_t* launches, double* bytes, int reset);
+// Launch i since the last reset (function id, duration, bytes); false past the end.
+bool kprof_record(int64_t i, int* fn, double* ms, double* bytes);
 
 // Device view of a gather table: y[i] = sum_w coef[i*W+w] * x[col[i*W+w] - in_base],
 // terms with the input index outside [0, n_in) skipped.
@@ -43,6 +45,14 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
 template <class Ti, class To, class C>
 void gather_rows(const DTable<C>& t, int r0, int nr, const Ti* x, To* y, int64_t outer, int64_t inner, int n_in,
                  int in_base, C alpha, C beta, hipStream_t s);
+
+// Two tables with the same contiguous windows (P.c0) along one axis in one
+// pass: out1 = P x (skipped when out1 is null), out2 = alpha Q x + beta P z.
+// Returns false (nothing launched) when the tables do not qualify (no
+// windows, different widths, W not in {2,3,4,5,7,9,11}, inner < 2).
+template <class S, class C>
+bool gather_dual(const DTable<C>& P, const DTable<C>& Q, const S* x, const S* z, S* out1, S* out2, int64_t outer,
+                 int64_t inner, int n_in, int in_base, C alpha, C beta, hipStream_t s);
 
 // y[o][i][k] = max_{w < cnt[i]} x[o][start[i]+w][k]
 void mode_max(const int* start, const int* cnt, int n_out, const double* x, double* y, int64_t outer,

@@ -78,6 +78,9 @@ struct st_iga_ctx {
   int64_t big_len = 0;
   int slab = 1;
   int64_t slab_layers = 1;
+  // mass and stiffness tables of an axis (index d: the time tables W_t, M_t)
+  // share their windows, so one dual sweep applies both
+  bool dual[4] = {false, false, false, false};
   // fused coefficient kernel along the slowest spatial axis (d >= 2)
   bool cf = false;
   int cf_slab = 1, cf_nchunk = 1;
@@ -247,7 +250,7 @@ void plan_fused_coef(st_iga_ctx* c) {
     return;
   }
   const int64_t threads = Qin * ((c->cf_slab + 7) / 8);
-  const int64_t want = 1 << 17;
+  const int64_t want = 1 << 19;
   int nch = static_cast<int>(std::min<int64_t>(std::max<int64_t>(1, (want + threads - 1) / threads),
                                                std::max(1, D.nel / 4)));
   nch = std::max(1, std::min(nch, D.n));
@@ -422,6 +425,11 @@ void host_setup(st_iga_ctx* c) {
   }
   make_contiguous(c->Mt_x.h, c->nt);
   make_contiguous(c->Wt_x.h, c->nt);
+  auto same_windows = [](const Gather& A, const Gather& B) {
+    return !A.c0.empty() && A.c0 == B.c0 && A.W == B.W && A.n_out == B.n_out;
+  };
+  for (int l = 0; l < P.d; ++l) c->dual[l] = same_windows(c->Ms[l].h, c->Ks[l].h);
+  c->dual[P.d] = same_windows(c->Mt_x.h, c->Wt_x.h);
   make_contiguous(c->Bt0.h, c->nt);
   make_contiguous(c->Bt1.h, c->nt);
   make_contiguous(c->BtT.h, T.Q);
@@ -727,30 +735,38 @@ void apply_impl(st_iga_ctx* c, const S* x, S* y, int L, int in_base, bool with_s
     gather<S, S, C>(Ops<S, C>::tab(c->Ks[0]), x, b, L, 1, nn[0], 0, C(P.sigma[0]), C(0), s);
     SM = a;
     SK = b;
-  } else if (d == 2) {
-    gather<S, S, C>(Ops<S, C>::tab(c->Ms[0]), x, a, L * nn[1], 1, nn[0], 0, C(1), C(0), s);
-    gather<S, S, C>(Ops<S, C>::tab(c->Ks[0]), x, b, L * nn[1], 1, nn[0], 0, C(1), C(0), s);
-    gather<S, S, C>(Ops<S, C>::tab(c->Ms[1]), a, e, L, nn[0], nn[1], 0, C(1), C(0), s);
-    gather<S, S, C>(Ops<S, C>::tab(c->Ks[1]), a, f, L, nn[0], nn[1], 0, C(P.sigma[1]), C(0), s);
-    gather<S, S, C>(Ops<S, C>::tab(c->Ms[1]), b, f, L, nn[0], nn[1], 0, C(P.sigma[0]), C(1), s);
-    SM = e;
-    SK = f;
   } else {
-    gather<S, S, C>(Ops<S, C>::tab(c->Ms[0]), x, a, L * nn[1] * nn[2], 1, nn[0], 0, C(1), C(0), s);
-    gather<S, S, C>(Ops<S, C>::tab(c->Ks[0]), x, b, L * nn[1] * nn[2], 1, nn[0], 0, C(1), C(0), s);
-    gather<S, S, C>(Ops<S, C>::tab(c->Ms[1]), a, e, L * nn[2], nn[0], nn[1], 0, C(1), C(0), s);           // aa
-    gather<S, S, C>(Ops<S, C>::tab(c->Ks[1]), a, f, L * nn[2], nn[0], nn[1], 0, C(P.sigma[1]), C(0), s);  // c
-    gather<S, S, C>(Ops<S, C>::tab(c->Ms[1]), b, f, L * nn[2], nn[0], nn[1], 0, C(P.sigma[0]), C(1), s);
-    const int64_t in2 = static_cast<int64_t>(nn[0]) * nn[1];
-    gather<S, S, C>(Ops<S, C>::tab(c->Ms[2]), e, a, L, in2, nn[2], 0, C(1), C(0), s);                     // SM
-    gather<S, S, C>(Ops<S, C>::tab(c->Ks[2]), e, b, L, in2, nn[2], 0, C(P.sigma[2]), C(0), s);            // SK
-    gather<S, S, C>(Ops<S, C>::tab(c->Ms[2]), f, b, L, in2, nn[2], 0, C(1), C(1), s);
-    SM = a;
-    SK = b;
+    // axis l >= 1: (M_l a, sigma_l K_l a + s M_l b) in one dual sweep when
+    // the two tables share their windows, else three gathers
+    auto axis = [&](int l, const S* xa, const S* xb, S* oa, S* ob, int64_t outer, int64_t inner, C sb) {
+      if (c->dual[l] && gather_dual<S, C>(Ops<S, C>::tab(c->Ms[l]), Ops<S, C>::tab(c->Ks[l]), xa, xb, oa, ob, outer,
+                                          inner, nn[l], 0, C(P.sigma[l]), sb, s))
+        return;
+      gather<S, S, C>(Ops<S, C>::tab(c->Ms[l]), xa, oa, outer, inner, nn[l], 0, C(1), C(0), s);
+      gather<S, S, C>(Ops<S, C>::tab(c->Ks[l]), xa, ob, outer, inner, nn[l], 0, C(P.sigma[l]), C(0), s);
+      gather<S, S, C>(Ops<S, C>::tab(c->Ms[l]), xb, ob, outer, inner, nn[l], 0, sb, C(1), s);
+    };
+    if (d == 2) {
+      gather<S, S, C>(Ops<S, C>::tab(c->Ms[0]), x, a, L * nn[1], 1, nn[0], 0, C(1), C(0), s);
+      gather<S, S, C>(Ops<S, C>::tab(c->Ks[0]), x, b, L * nn[1], 1, nn[0], 0, C(1), C(0), s);
+      axis(1, a, b, e, f, L, nn[0], C(P.sigma[0]));
+      SM = e;
+      SK = f;
+    } else {
+      gather<S, S, C>(Ops<S, C>::tab(c->Ms[0]), x, a, L * nn[1] * nn[2], 1, nn[0], 0, C(1), C(0), s);
+      gather<S, S, C>(Ops<S, C>::tab(c->Ks[0]), x, b, L * nn[1] * nn[2], 1, nn[0], 0, C(1), C(0), s);
+      axis(1, a, b, e, f, L * nn[2], nn[0], C(P.sigma[0]));     // M2 M1 x, sigma2 M1 K2 x + sigma1 K1 M2 x
+      axis(2, e, f, a, b, L, static_cast<int64_t>(nn[0]) * nn[1], C(1));
+      SM = a;
+      SK = b;
+    }
   }
   // time: y = Cm W_t SM + M_t SK (rows X_t, columns per in_base)
-  gather<S, S, C>(Ops<S, C>::tab(c->Wt_x), SM, y, 1, Ns, L, in_base, C(P.Cm), C(0), s);
-  gather<S, S, C>(Ops<S, C>::tab(c->Mt_x), SK, y, 1, Ns, L, in_base, C(1), C(1), s);
+  if (!(c->dual[d] && gather_dual<S, C>(Ops<S, C>::tab(c->Mt_x), Ops<S, C>::tab(c->Wt_x), SM, SK, nullptr, y, 1, Ns,
+                                        L, in_base, C(P.Cm), C(1), s))) {
+    gather<S, S, C>(Ops<S, C>::tab(c->Wt_x), SM, y, 1, Ns, L, in_base, C(P.Cm), C(0), s);
+    gather<S, S, C>(Ops<S, C>::tab(c->Mt_x), SK, y, 1, Ns, L, in_base, C(1), C(1), s);
+  }
   // low-rank coefficient terms
   const int r0 = with_su ? 0 : c->Rth;
   const int r1 = with_react ? c->Rth + c->Rc : c->Rth;
@@ -934,18 +950,29 @@ int fgmres(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const double* b, do
       T* w = V + static_cast<int64_t>(j + 1) * ld;
       Pc(Vj, Zj);
       A(Zj, w);
-      multidot_partial<T>(V, ld, j + 1, w, n, c->part, nb, s);
-      finalize_sum(c->part, nb, j + 1, c->dsc, s);
+      // classical Gram-Schmidt; w is column j+1 of V, so the same multi-dot
+      // also gives ||w||^2 before the projection
+      multidot_partial<T>(V, ld, j + 2, w, n, c->part, nb, s);
+      finalize_sum(c->part, nb, j + 2, c->dsc, s);
       update_norm_partial<T>(V, ld, j + 1, c->dsc, w, n, c->part, nb, s);
-      multidot_partial<T>(V, ld, j + 1, w, n, c->part, nb, s);
-      finalize_sum(c->part, nb, j + 1, c->dsc + 128, s);
-      update_norm_partial<T>(V, ld, j + 1, c->dsc + 128, w, n, c->part, nb, s);
       finalize_sum(c->part, nb, 1, c->dsc + 256, s);
-      CK(hipMemcpyAsync(hbuf, c->dsc, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-      CK(hipMemcpyAsync(hbuf + 66, c->dsc + 128, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      CK(hipMemcpyAsync(hbuf, c->dsc, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
       CK(hipMemcpyAsync(hbuf + 132, c->dsc + 256, sizeof(double), hipMemcpyDeviceToHost, s));
       CK(hipStreamSynchronize(s));
       check_launch();
+      for (int i = 0; i <= j; ++i) hbuf[66 + i] = 0.0;
+      // second pass when the first removed most of w (norm ratio below
+      // 1/sqrt(2)), or always when requested
+      if (c->opt.reorth != 0 || 2.0 * hbuf[132] < hbuf[j + 1]) {
+        multidot_partial<T>(V, ld, j + 1, w, n, c->part, nb, s);
+        finalize_sum(c->part, nb, j + 1, c->dsc + 128, s);
+        update_norm_partial<T>(V, ld, j + 1, c->dsc + 128, w, n, c->part, nb, s);
+        finalize_sum(c->part, nb, 1, c->dsc + 256, s);
+        CK(hipMemcpyAsync(hbuf + 66, c->dsc + 128, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(hbuf + 132, c->dsc + 256, sizeof(double), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        check_launch();
+      }
       ++it;
       for (int i = 0; i <= j; ++i) H[static_cast<size_t>(i) * m + j] = hbuf[i] + hbuf[66 + i];
       const double hn = std::sqrt(std::max(hbuf[132], 0.0));
@@ -1659,6 +1686,7 @@ void st_iga_default_options(st_iga_options* o) {
   o->prec = ST_IGA_FP64;
   o->lin_forcing = 0.0;
   o->coef_slab = 0;
+  o->reorth = 0;
 }
 
 size_t st_iga_workspace_bytes(const st_iga_problem* prob, const st_iga_options* opt) {
@@ -1927,6 +1955,14 @@ st_iga_status st_iga_profile_read(st_iga_ctx* c, int32_t cls, double* ms, int64_
                                   int32_t reset) {
   if (!c || cls < 0 || (cls >= K_NCLASS && (cls < 100 || cls >= 148))) return ST_IGA_EINVAL;
   return guard(c, [&] { kprof_read(cls, ms, launches, bytes, reset); });
+}
+
+st_iga_status st_iga_profile_record(st_iga_ctx* c, int64_t i, int32_t* fn, double* ms, double* bytes) {
+  if (!c) return ST_IGA_EINVAL;
+  int f = 0;
+  if (!kprof_record(i, &f, ms, bytes)) return ST_IGA_EINVAL;
+  if (fn) *fn = f;
+  return ST_IGA_OK;
 }
 
 st_iga_status st_iga_sizes(const st_iga_ctx* c, int64_t* o) {

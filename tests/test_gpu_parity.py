@@ -188,6 +188,10 @@ def test_apply_chunked_axis(gpu_lib, torch, name, prob):
     assert rel(S.apply(xd).cpu().numpy(), want) < 1e-12
     # the FP32 operator: relative error a modest multiple of the unit roundoff
     assert rel(S.apply_lowp(xd).cpu().numpy(), want) < 1e-5
+    # FP32 preconditioner (mode products along odd and even axis lengths)
+    # against the FP64 one, which the oracle pins in test_precond
+    z64 = S.precond(xd).cpu().numpy()
+    assert rel(S.precond_lowp(xd).cpu().numpy(), z64) < 1e-5
 
 
 def test_apply_nonuniform_knots(gpu_lib, torch):
