@@ -25,8 +25,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12          # bytes/s, MI355X HBM3E
-PEAK_FP64 = 78.6e12        # flop/s, vector and matrix FP64
-PEAK_FP32 = 157.3e12       # flop/s, FP32 vector
+PEAK_FP64 = 78.6e12        # flop/s, FP64 vector and dense MFMA
+PEAK_FP32 = 157.3e12       # flop/s, FP32 vector and dense MFMA
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def parse():
@@ -45,6 +46,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=128,
                     help="requests of the serving stream sampled in the default run (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--kernel-probe", type=int, default=0, metavar="REPS",
+                    help="run only the hardware-counter probe (1 GiB copy, then REPS operator applications)")
     return ap.parse_args()
 
 
@@ -94,6 +97,82 @@ def time_region(torch, S, u1, u2, w, steps, warmup, tol):
     return ev0.elapsed_time(ev1) / steps, wall / steps * 1e3, its, rr, prof
 
 
+def roofline(prof, steps):
+    """Roofline entry of the kernel function with the largest summed duration:
+    achieved rate from the algorithmic bytes (and flops, where recorded) of
+    its launches over their HIP-event durations; the bound is the resource it
+    uses the larger fraction of.  `traffic`: HBM bytes per launch measured
+    with rocprofv3 counters (profiles/traffic.json), null when the kernel
+    sources changed since."""
+    fns = {k: v for k, v in prof.items() if k.startswith("fn:") and v[1] > 0}
+    dom_name, (dom_ms, dom_n, dom_by, dom_fl) = max(fns.items(), key=lambda kv: kv[1][0])
+    name = dom_name[3:]
+    sec = dom_ms / 1e3
+    f64 = "<f64>" in name
+    hbm_frac = dom_by / sec / PEAK_HBM
+    comp_frac, comp_peak, comp_bound = 0.0, None, None
+    if dom_fl > 0:
+        comp_peak = PEAK_FP64 if f64 else PEAK_FP32
+        comp_bound = "mfma" if name.startswith("dense_mode_mfma") else "alu"
+        comp_frac = dom_fl / sec / comp_peak
+    traffic = None
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+        from paper_2311_17500_amd.profiling import kernel_source_hash
+        if t.get("kernel_source_sha256") == kernel_source_hash() and name in t.get("kernels", {}):
+            traffic = t["kernels"][name]["hbm_bytes_per_launch"]
+    except (OSError, ValueError):
+        pass
+    if comp_bound is not None and comp_frac >= hbm_frac:
+        roof = {"kernel": name, "bound": comp_bound, "achieved": dom_fl / sec / 1e12, "peak": comp_peak / 1e12,
+                "unit": "TFLOP/s", "frac": comp_frac}
+    else:
+        roof = {"kernel": name, "bound": "hbm", "achieved": dom_by / sec / 1e9, "peak": PEAK_HBM / 1e9,
+                "unit": "GB/s", "frac": hbm_frac}
+    roof.update({"traffic": traffic, "hbm_frac": hbm_frac, "compute_frac": comp_frac if comp_bound else None,
+                 "avg_launch_ms": dom_ms / dom_n, "launches": dom_n, "alg_bytes_per_launch": dom_by / dom_n,
+                 "alg_flops_per_launch": dom_fl / dom_n,
+                 "kernels": {k[3:]: {"ms_per_step": v[0] / steps, "launches_per_step": v[1] / steps,
+                                     "GB_per_s": (v[2] / (v[0] / 1e3) / 1e9) if v[0] > 0 else None,
+                                     "TFLOP_per_s": (v[3] / (v[0] / 1e3) / 1e12) if v[0] > 0 and v[3] > 0 else None}
+                             for k, v in sorted(fns.items(), key=lambda kv: -kv[1][0])},
+                 "purpose_ms_per_step": {k: v[0] / steps for k, v in prof.items() if not k.startswith("fn:")}})
+    return roof
+
+
+def kernel_probe(cfg, reps):
+    """For hardware-counter runs: a 1 GiB device copy (the calibration of the
+    byte counters) followed by `reps` applications of the low-precision
+    operator and preconditioner of the workload at the benchmark state."""
+    import numpy as np
+    import torch
+    import st_workloads as W
+    from paper_2311_17500_amd.binding import Solver, FP64, MIXED_FP32
+    prob = W.config(cfg)
+    mr = 16 if cfg == 4 else 48
+    S = Solver(prob, prec=MIXED_FP32, tol_lin=1e-8, max_rank=mr)
+    c0, _ = S.lift()
+    u0 = torch.tensor(np.tile(c0, prob.n_t), dtype=torch.float64, device="cuda:0")
+    u1, w = S.vec(S.full), S.vec(S.full)
+    S.newton_step(u0, u1, w, True, 1e-8)
+    S.linearize(u1, w, True)
+    x = S.vec()
+    x.copy_(torch.from_numpy(W.random_vector(prob.unknowns, 1)))
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    log("state ready; copy of 1 GiB")
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    for i in range(reps):
+        S.apply_lowp(x)
+        S.precond_lowp(x)
+        torch.cuda.synchronize()
+        log(f"probe rep {i} done")
+    print(json.dumps({"kernel_probe": True, "config": cfg, "reps": reps, "copy_bytes": 2 * (1 << 30)}), flush=True)
+
+
 def cpu_baseline(cfg):
     """The oracle as it stands on the host cores: one Newton step (explicit
     assembly + sparse LU) of the same physics on a reduced mesh."""
@@ -136,6 +215,9 @@ def main():
     import torch
     import st_workloads as W
     from paper_2311_17500_amd.binding import Solver, FP64, MIXED_FP32, MIXED_BF16
+    if a.kernel_probe > 0:
+        kernel_probe(a.config, a.kernel_probe)
+        return
     if a.serve:
         s = serving(512, a.serve_slots)
         print(json.dumps({"metric": "p50/p99 solve latency, 512-request serving stream (config 3)",
@@ -204,16 +286,7 @@ def main():
     # dominant kernel function over the timed region, achieved bandwidth from
     # the algorithmic bytes the library records per launch
     prof = main_r["prof"]
-    fns = {k: v for k, v in prof.items() if k.startswith("fn:") and v[1] > 0}
-    dom_name, (dom_ms, dom_n, dom_by) = max(fns.items(), key=lambda kv: kv[1][0])
-    achieved = dom_by / (dom_ms / 1e3)
-    roof = {"kernel": dom_name[3:], "bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
-            "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": None,
-            "avg_launch_ms": dom_ms / dom_n, "launches": dom_n, "alg_bytes_per_launch": dom_by / dom_n,
-            "kernels": {k[3:]: {"ms_per_step": v[0] / a.steps, "launches_per_step": v[1] / a.steps,
-                                "GB_per_s": (v[2] / (v[0] / 1e3) / 1e9) if v[0] > 0 else None}
-                        for k, v in sorted(fns.items(), key=lambda kv: -kv[1][0])},
-            "purpose_ms_per_step": {k: v[0] / a.steps for k, v in prof.items() if not k.startswith("fn:")}}
+    roof = roofline(prof, a.steps)
     out = {
         "metric": "space-time DOF/s to rel. residual 1e-8 (mixed vs FP64); p50/p99 solve latency",
         "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,

@@ -219,14 +219,17 @@ st_iga_status st_iga_newton_step(st_iga_ctx* ctx, const double* u_in, double* u_
  * terms, 12 fused quadrature pass, 13 dual-table sweep) in storage precision q (0 FP64, 1 FP32,
  * 2 BF16; the reductions are FP64 only).  profile_read returns the summed duration (ms), the
  * launch count and the summed algorithmic bytes (each input and output array
- * counted once per launch) since the last reset, and synchronizes the
- * recorded events.  Any output pointer may be NULL.  profile_record returns
- * launch i (in launch order since the last reset): function id f + 16 q,
- * duration (ms) and algorithmic bytes; EINVAL past the last launch. */
+ * counted once per launch), the summed algorithmic flops (recorded for the
+ * time mixing, the fused coefficient kernel and the dense mode products, 0
+ * elsewhere) since the last reset, and synchronizes the recorded events.  Any
+ * output pointer may be NULL.  profile_record returns launch i (in launch
+ * order since the last reset): function id f + 16 q, duration (ms),
+ * algorithmic bytes and flops; EINVAL past the last launch. */
 st_iga_status st_iga_profile(st_iga_ctx* ctx, int32_t enable);
 st_iga_status st_iga_profile_read(st_iga_ctx* ctx, int32_t kernel_class, double* ms, int64_t* launches,
-                                  double* bytes, int32_t reset);
-st_iga_status st_iga_profile_record(st_iga_ctx* ctx, int64_t i, int32_t* fn, double* ms, double* bytes);
+                                  double* bytes, double* flops, int32_t reset);
+st_iga_status st_iga_profile_record(st_iga_ctx* ctx, int64_t i, int32_t* fn, double* ms, double* bytes,
+                                    double* flops);
 
 /* Lifted initial datum (N_s entries, HOST output) and the number of spatial
  * Greville points inside the stimulus. */

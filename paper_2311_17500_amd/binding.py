@@ -99,7 +99,9 @@ def load(path: str = LIB_PATH):
                                        C.POINTER(C.c_double), C.POINTER(C.c_double), V]
     lib.st_iga_profile.argtypes = [P, C.c_int32]
     lib.st_iga_profile_read.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
-                                        C.POINTER(C.c_double), C.c_int32]
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32]
+    lib.st_iga_profile_record.argtypes = [P, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.st_iga_host_query.argtypes = [C.POINTER(Problem), C.c_int32, C.c_int32, V, C.c_int64, C.POINTER(C.c_int64)]
     for name in EXPORTS:
         if name not in ("st_iga_default_options", "st_iga_workspace_bytes", "st_iga_last_error"):
@@ -298,32 +300,32 @@ class Solver:
         self._chk(self.lib.st_iga_profile(self.ctx, int(on)))
 
     def profile_records(self):
-        """[(function name, ms, algorithmic bytes)] of every launch since the last reset."""
+        """[(function name, ms, algorithmic bytes, algorithmic flops)] of every launch since the last reset."""
         out, i = [], 0
-        fn, ms, by = C.c_int32(0), C.c_double(0), C.c_double(0)
-        while self.lib.st_iga_profile_record(self.ctx, i, C.byref(fn), C.byref(ms), C.byref(by)) == OK:
+        fn, ms, by, fl = C.c_int32(0), C.c_double(0), C.c_double(0), C.c_double(0)
+        while self.lib.st_iga_profile_record(self.ctx, i, C.byref(fn), C.byref(ms), C.byref(by), C.byref(fl)) == OK:
             name = self.FNAMES[fn.value % 16] + "<" + ["f64", "f32", "bf16"][fn.value // 16] + ">"
-            out.append((name, ms.value, by.value))
+            out.append((name, ms.value, by.value, fl.value))
             i += 1
         return out
 
     def profile_read(self, reset=True):
-        """{class: (ms, launches, algorithmic bytes)} since the last reset."""
+        """{class: (ms, launches, algorithmic bytes, algorithmic flops)} since the last reset; per kernel
+        function under "fn:<name><<precision>>"."""
         out = {}
         for k, name in enumerate(self.KCLASSES):
-            ms, n, by = C.c_double(0), C.c_int64(0), C.c_double(0)
-            self._chk(self.lib.st_iga_profile_read(self.ctx, k, C.byref(ms), C.byref(n), C.byref(by), 0))
-            out[name] = (ms.value, n.value, by.value)
-        fnames = self.FNAMES
+            ms, n, by, fl = C.c_double(0), C.c_int64(0), C.c_double(0), C.c_double(0)
+            self._chk(self.lib.st_iga_profile_read(self.ctx, k, C.byref(ms), C.byref(n), C.byref(by), C.byref(fl), 0))
+            out[name] = (ms.value, n.value, by.value, fl.value)
         for q, pn in enumerate(["f64", "f32", "bf16"]):
-            for f, fname in enumerate(fnames):
-                ms, n, by = C.c_double(0), C.c_int64(0), C.c_double(0)
+            for f, fname in enumerate(self.FNAMES):
+                ms, n, by, fl = C.c_double(0), C.c_int64(0), C.c_double(0), C.c_double(0)
                 self._chk(self.lib.st_iga_profile_read(self.ctx, 100 + f + 16 * q, C.byref(ms), C.byref(n),
-                                                       C.byref(by), 0))
+                                                       C.byref(by), C.byref(fl), 0))
                 if n.value:
-                    out[f"fn:{fname}<{pn}>"] = (ms.value, n.value, by.value)
+                    out[f"fn:{fname}<{pn}>"] = (ms.value, n.value, by.value, fl.value)
         if reset:
-            self._chk(self.lib.st_iga_profile_read(self.ctx, 0, None, None, None, 1))
+            self._chk(self.lib.st_iga_profile_read(self.ctx, 0, None, None, None, None, 1))
         return out
 
     def lift(self):

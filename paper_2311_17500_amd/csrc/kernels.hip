@@ -64,7 +64,7 @@ struct ProfState {
     int cls;   // purpose class
     int fn;    // kernel function id + 16 * precision (0 f64, 1 f32, 2 bf16)
     hipEvent_t a, b;
-    double bytes;
+    double bytes, flops;
   };
   std::vector<Rec> rec;
 };
@@ -87,8 +87,8 @@ struct ProfScope {
   int cls, fn;
   hipStream_t s;
   hipEvent_t a = nullptr;
-  double bytes;
-  ProfScope(int c, int f, hipStream_t st, double by) : cls(c), fn(f), s(st), bytes(by) {
+  double bytes, flops;
+  ProfScope(int c, int f, hipStream_t st, double by, double fl = 0.0) : cls(c), fn(f), s(st), bytes(by), flops(fl) {
     if (prof().on) {
       a = prof_event();
       if (a) hipEventRecord(a, s);
@@ -99,7 +99,7 @@ struct ProfScope {
       hipEvent_t b = prof_event();
       if (b) {
         hipEventRecord(b, s);
-        prof().rec.push_back({cls, fn, a, b, bytes});
+        prof().rec.push_back({cls, fn, a, b, bytes, flops});
       }
     }
   }
@@ -700,6 +700,172 @@ __global__ void __launch_bounds__(256) k_coef_fused(const C* __restrict__ T, con
       for (int k = 0; k < KP; ++k)
 #pragma unroll
         for (int t = 0; t < TS; ++t) yr[k][t] += b[k] * m[t];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int dof = f + k;
+    if (dof >= d0 && dof < d1 && dof < nd) {
+      S* o = out + static_cast<int64_t>(ta - t0) * lay + static_cast<int64_t>(dof) * Qin + c;
+#pragma unroll
+      for (int t = 0; t < TS; ++t)
+        if (t < nrow) o[t * lay] = from_c<S>(yr[k][t]);
+    }
+  }
+}
+
+
+// Same computation with the next element's input row and rank weights
+// loaded one element ahead (more registers, fewer exposed load latencies;
+// used in FP64, where occupancy is low anyway).
+template <class S, class C, int P, int KP, int TS, int RM, bool PF>
+__global__ void __launch_bounds__(256) k_coef_fused_pf(const C* __restrict__ T, const S* __restrict__ Psi, int r0, int R,
+                                                    int Nt, int t0, int t1, const S* __restrict__ Z, int n_in,
+                                                    int in_base, const C* __restrict__ Bl,
+                                                    const int* __restrict__ efirst, const int* __restrict__ chunks,
+                                                    int nd, int64_t Qin, S* __restrict__ out, int64_t Qs) {
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= Qin) return;
+  constexpr int WB = 2 * P + 1, NL = TS + 2 * P;
+  const int ta = t0 + static_cast<int>(blockIdx.y) * TS;
+  const int e0 = chunks[4 * blockIdx.z], e1 = chunks[4 * blockIdx.z + 1];
+  const int d0 = chunks[4 * blockIdx.z + 2], d1 = chunks[4 * blockIdx.z + 3];
+  const int nrow = min(TS, t1 - ta);
+  const int64_t lay = static_cast<int64_t>(nd) * Qin;
+  const int jb = ta + 1 - P - in_base;   // input layer of window slot 0
+  // one B-spline row of the input over the NL window layers
+  auto load_row = [&](C* row, int dof) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const int j = jb + l;
+      row[l] = (static_cast<unsigned>(j) < static_cast<unsigned>(n_in) && dof < nd)
+                   ? to_c(Z[j * lay + static_cast<int64_t>(dof) * Qin + c], C(0))
+                   : C(0);
+    }
+  };
+  // rank weights of the KP Gauss points of element e (RM > 0: all R <= RM of them)
+  auto load_psi = [&](C (*pv)[RM > 0 ? RM : 1], int e) {
+    if constexpr (RM > 0) {
+      const S* ps = Psi + static_cast<int64_t>(r0) * Qs + static_cast<int64_t>(e) * KP * Qin + c;
+#pragma unroll
+      for (int g = 0; g < KP; ++g)
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+          pv[g][r] = (r < R) ? to_c(ps[static_cast<int64_t>(r) * Qs + static_cast<int64_t>(g) * Qin], C(0)) : C(0);
+    }
+  };
+  C zr[KP][NL], yr[KP][TS];
+  int f = efirst[e0];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    load_row(zr[k], f + k);
+#pragma unroll
+    for (int t = 0; t < TS; ++t) yr[k][t] = C(0);
+  }
+  // PF: prefetch, one element ahead, of the row entering the ring when the
+  // next element starts one B-spline later (the usual case) and of its rank
+  // weights; this costs registers, so it pays where occupancy is low anyway
+  C nx[PF ? NL : 1];
+  int nxdof = -1;
+  C pv[KP][RM > 0 ? RM : 1], pn[KP][RM > 0 && PF ? RM : 1];
+  if constexpr (PF) load_psi(pv, e0);
+  for (int e = e0; e < e1; ++e) {
+    const int fn = efirst[e];
+    if (PF && fn == f + 1 && nxdof == f + KP) {
+      if (f >= d0 && f < d1) {
+        S* o = out + static_cast<int64_t>(ta - t0) * lay + static_cast<int64_t>(f) * Qin + c;
+#pragma unroll
+        for (int t = 0; t < TS; ++t)
+          if (t < nrow) o[t * lay] = from_c<S>(yr[0][t]);
+      }
+#pragma unroll
+      for (int k = 0; k < KP - 1; ++k) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) zr[k][l] = zr[k + 1][l];
+#pragma unroll
+        for (int t = 0; t < TS; ++t) yr[k][t] = yr[k + 1][t];
+      }
+#pragma unroll
+      for (int l = 0; l < NL; ++l) zr[KP - 1][l] = nx[l];
+#pragma unroll
+      for (int t = 0; t < TS; ++t) yr[KP - 1][t] = C(0);
+      f = fn;
+    }
+    for (; f < fn; ++f) {
+      if (f >= d0 && f < d1) {
+        S* o = out + static_cast<int64_t>(ta - t0) * lay + static_cast<int64_t>(f) * Qin + c;
+#pragma unroll
+        for (int t = 0; t < TS; ++t)
+          if (t < nrow) o[t * lay] = from_c<S>(yr[0][t]);
+      }
+#pragma unroll
+      for (int k = 0; k < KP - 1; ++k) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) zr[k][l] = zr[k + 1][l];
+#pragma unroll
+        for (int t = 0; t < TS; ++t) yr[k][t] = yr[k + 1][t];
+      }
+      load_row(zr[KP - 1], f + KP);
+#pragma unroll
+      for (int t = 0; t < TS; ++t) yr[KP - 1][t] = C(0);
+    }
+    // issue the next element's loads before this element's arithmetic
+    if constexpr (PF) {
+      nxdof = -1;
+      if (e + 1 < e1) {
+        if (efirst[e + 1] == fn + 1) {
+          nxdof = fn + KP;
+          load_row(nx, nxdof);
+        }
+        load_psi(pn, e + 1);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < KP; ++g) {
+      const int qd = e * KP + g;
+      C b[KP];
+#pragma unroll
+      for (int k = 0; k < KP; ++k) b[k] = Bl[qd * KP + k];
+      C zg[NL];
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        C v = C(0);
+#pragma unroll
+        for (int k = 0; k < KP; ++k) v += b[k] * zr[k][l];
+        zg[l] = v;
+      }
+      C m[TS];
+#pragma unroll
+      for (int t = 0; t < TS; ++t) m[t] = C(0);
+      auto mix = [&](int r, C psi) {
+        const C* Tr = T + static_cast<int64_t>(r0 + r) * Nt * WB;
+#pragma unroll
+        for (int t = 0; t < TS; ++t) {
+          const C* Tt = Tr + min(ta + t, Nt - 1) * WB;
+          C sacc = C(0);
+#pragma unroll
+          for (int w = 0; w < WB; ++w) sacc += Tt[w] * zg[t + w];
+          m[t] += psi * sacc;
+        }
+      };
+      if constexpr (RM > 0 && PF) {
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+          if (r < R) mix(r, pv[g][r]);
+      } else {
+        const S* ps = Psi + static_cast<int64_t>(r0) * Qs + static_cast<int64_t>(qd) * Qin + c;
+        for (int r = 0; r < R; ++r) mix(r, to_c(ps[static_cast<int64_t>(r) * Qs], C(0)));
+      }
+#pragma unroll
+      for (int k = 0; k < KP; ++k)
+#pragma unroll
+        for (int t = 0; t < TS; ++t) yr[k][t] += b[k] * m[t];
+    }
+    if constexpr (RM > 0 && PF) {
+#pragma unroll
+      for (int g = 0; g < KP; ++g)
+#pragma unroll
+        for (int r = 0; r < RM; ++r) pv[g][r] = pn[g][r];
     }
   }
 #pragma unroll
@@ -1692,7 +1858,8 @@ void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1, 
   while (tpb > 64 && static_cast<size_t>(R) * tpb * sizeof(C) > 64 * 1024) tpb /= 2;
   const size_t sh = static_cast<size_t>(R > 0 ? R : 1) * tpb * sizeof(C);
   const dim3 g(grid_for(Qs, tpb)), b(tpb);
-  ProfScope ps(K_TIME_MIX, 3 + 16 * prec_code<S>(), s, (static_cast<double>(n_in) + R + (t1 - t0)) * Qs * sizeof(S));
+  ProfScope ps(K_TIME_MIX, 3 + 16 * prec_code<S>(), s, (static_cast<double>(n_in) + R + (t1 - t0)) * Qs * sizeof(S),
+               2.0 * R * (2 * p + 2) * static_cast<double>(t1 - t0) * Qs);
   switch (p) {
     case 1: hipLaunchKernelGGL((k_time_mix<S, C, 1>), g, b, sh, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, out, Qs); break;
     case 2: hipLaunchKernelGGL((k_time_mix<S, C, 2>), g, b, sh, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, out, Qs); break;
@@ -1708,15 +1875,29 @@ bool coef_fused(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1
                 int64_t Qin, S* out, int64_t Qs, hipStream_t s) {
   // output rows per thread: 8 in FP32, 4 in FP64 (register rings of the same size)
   constexpr int TS = std::is_same<C, double>::value ? 4 : 8;
+  constexpr bool f64 = std::is_same<C, double>::value;
   if (pt < 1 || pt > 5 || ps < 1 || ps > 4) return false;
   if (t1 <= t0 || Qin == 0) return true;
   const int R = r1 - r0;
   const dim3 g(static_cast<unsigned>((Qin + TPB - 1) / TPB), static_cast<unsigned>((t1 - t0 + TS - 1) / TS),
                static_cast<unsigned>(nchunk));
   const double rows = static_cast<double>(t1 - t0);
+  // algorithmic flops per output row and Gauss point: the time mixing
+  // (2 R (2 p_t + 2)) plus the expansion and projection along the axis (4 (p_s + 1))
+  const double fl = rows * static_cast<double>(Qs) * (2.0 * R * (2 * pt + 2) + 4.0 * (ps + 1));
   ProfScope pr(K_COEF, 11 + 16 * prec_code<S>(), s,
-               (static_cast<double>(n_in) * nd * Qin + rows * nd * Qin + static_cast<double>(R) * Qs) * sizeof(S));
-#define CF(P_, K_) hipLaunchKernelGGL((k_coef_fused<S, C, P_, K_, TS>), g, dim3(TPB), 0, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, Bl, efirst, chunks, nd, Qin, out, Qs)
+               (static_cast<double>(n_in) * nd * Qin + rows * nd * Qin + static_cast<double>(R) * Qs) * sizeof(S), fl);
+#define CF(P_, K_)                                                                                                \
+  do {                                                                                                            \
+    bool done_ = false;                                                                                           \
+    if constexpr (f64) {                                                                                          \
+      if (R <= 4) {                                                                                               \
+        hipLaunchKernelGGL((k_coef_fused_pf<S, C, P_, K_, TS, 4, true>), g, dim3(TPB), 0, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, Bl, efirst, chunks, nd, Qin, out, Qs); \
+        done_ = true;                                                                                             \
+      }                                                                                                           \
+    }                                                                                                             \
+    if (!done_) hipLaunchKernelGGL((k_coef_fused<S, C, P_, K_, TS>), g, dim3(TPB), 0, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, Bl, efirst, chunks, nd, Qin, out, Qs); \
+  } while (0)
 #define CFP(P_)                 \
   switch (ps) {                 \
     case 1: CF(P_, 2); break;   \
@@ -1744,7 +1925,7 @@ void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, i
   const int NT = npad / 16;
   const size_t abytes = static_cast<size_t>(npad) * npad * sizeof(C);
   const bool lds = abytes <= 64 * 1024;
-  ProfScope ps(K_DENSE, 4 + 16 * prec_code<S>(), s, 2.0 * ncols * n * sizeof(S));
+  ProfScope ps(K_DENSE, 4 + 16 * prec_code<S>(), s, 2.0 * ncols * n * sizeof(S), 2.0 * ncols * n * n);
   if (inner == 1 && NT <= 9) {
     // one wave per block; 4 column tiles (64 rows) unless the accumulators
     // (FP64 beyond 4 row tiles) or the staged rows would not fit
@@ -1834,9 +2015,9 @@ void arrowhead(const S* r, S* y, const C* lam, const C* mu, const int* kind, con
 void kprof_enable(bool on) { prof().on = on; }
 void kprof_gather_class(int cls) { t_gather_cls = cls; }
 
-void kprof_read(int cls, double* ms, int64_t* launches, double* bytes, int reset) {
+void kprof_read(int cls, double* ms, int64_t* launches, double* bytes, double* flops, int reset) {
   ProfState& p = prof();
-  double tot = 0.0, by = 0.0;
+  double tot = 0.0, by = 0.0, fl = 0.0;
   int64_t n = 0;
   for (auto& r : p.rec) {
     if (cls < 100 ? r.cls != cls : r.fn != cls - 100) continue;
@@ -1844,11 +2025,13 @@ void kprof_read(int cls, double* ms, int64_t* launches, double* bytes, int reset
     float t = 0.0f;
     if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) tot += t;
     by += r.bytes;
+    fl += r.flops;
     ++n;
   }
   if (ms) *ms = tot;
   if (launches) *launches = n;
   if (bytes) *bytes = by;
+  if (flops) *flops = fl;
   if (reset) {
     for (auto& r : p.rec) hipEventSynchronize(r.b);
     p.rec.clear();
@@ -1856,7 +2039,7 @@ void kprof_read(int cls, double* ms, int64_t* launches, double* bytes, int reset
   }
 }
 
-bool kprof_record(int64_t i, int* fn, double* ms, double* bytes) {
+bool kprof_record(int64_t i, int* fn, double* ms, double* bytes, double* flops) {
   ProfState& p = prof();
   if (i < 0 || i >= static_cast<int64_t>(p.rec.size())) return false;
   const auto& r = p.rec[static_cast<size_t>(i)];
@@ -1866,6 +2049,7 @@ bool kprof_record(int64_t i, int* fn, double* ms, double* bytes) {
   if (fn) *fn = r.fn;
   if (ms) *ms = t;
   if (bytes) *bytes = r.bytes;
+  if (flops) *flops = r.flops;
   return true;
 }
 

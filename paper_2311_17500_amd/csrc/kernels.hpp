@@ -21,9 +21,9 @@ void kprof_enable(bool on);
 void kprof_gather_class(int cls);
 // Sum of launch durations (ms), launch count and algorithmic bytes of a class since the last reset;
 // synchronizes the recorded events.  Resets when reset != 0.
-void kprof_read(int cls, double* ms, int64_t* launches, double* bytes, int reset);
-// Launch i since the last reset (function id, duration, bytes); false past the end.
-bool kprof_record(int64_t i, int* fn, double* ms, double* bytes);
+void kprof_read(int cls, double* ms, int64_t* launches, double* bytes, double* flops, int reset);
+// Launch i since the last reset (function id, duration, bytes, flops); false past the end.
+bool kprof_record(int64_t i, int* fn, double* ms, double* bytes, double* flops);
 
 // Device view of a gather table: y[i] = sum_w coef[i*W+w] * x[col[i*W+w] - in_base],
 // terms with the input index outside [0, n_in) skipped.

@@ -1952,15 +1952,16 @@ st_iga_status st_iga_profile(st_iga_ctx* c, int32_t enable) {
 }
 
 st_iga_status st_iga_profile_read(st_iga_ctx* c, int32_t cls, double* ms, int64_t* launches, double* bytes,
-                                  int32_t reset) {
+                                  double* flops, int32_t reset) {
   if (!c || cls < 0 || (cls >= K_NCLASS && (cls < 100 || cls >= 148))) return ST_IGA_EINVAL;
-  return guard(c, [&] { kprof_read(cls, ms, launches, bytes, reset); });
+  return guard(c, [&] { kprof_read(cls, ms, launches, bytes, flops, reset); });
 }
 
-st_iga_status st_iga_profile_record(st_iga_ctx* c, int64_t i, int32_t* fn, double* ms, double* bytes) {
+st_iga_status st_iga_profile_record(st_iga_ctx* c, int64_t i, int32_t* fn, double* ms, double* bytes,
+                                    double* flops) {
   if (!c) return ST_IGA_EINVAL;
   int f = 0;
-  if (!kprof_record(i, &f, ms, bytes)) return ST_IGA_EINVAL;
+  if (!kprof_record(i, &f, ms, bytes, flops)) return ST_IGA_EINVAL;
   if (fn) *fn = f;
   return ST_IGA_OK;
 }

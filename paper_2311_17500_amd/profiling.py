@@ -1,0 +1,135 @@
+"""Summaries of rocprofv3 output for the kernels of this library.
+
+    python -m paper_2311_17500_amd.profiling stats <kernel_stats.csv> <out.txt> "<command>"
+    python -m paper_2311_17500_amd.profiling traffic <fetch_dir> <write_dir> <out.json> "<command>"
+
+`stats` turns the per-kernel statistics of a `rocprofv3 --kernel-trace
+--stats` run into a short text table (kernel, calls, total and average
+duration).  `traffic` takes two counter runs of `bench.py --kernel-probe`
+(`--pmc FETCH_SIZE` and `--pmc WRITE_SIZE`, KiB per dispatch), calibrates the
+counters on the probe's 1 GiB device copy (1 GiB read, 1 GiB written) and
+writes the HBM bytes per launch of each library kernel, with the hash of the
+kernel sources they were measured on.  Kernel names are reduced to the
+library's short form, e.g. ``k_coef_fused<float, ...>`` -> ``coef_fused<f32>``.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import json
+import os
+import re
+import sys
+from collections import defaultdict
+
+_PREC = {"double": "f64", "float": "f32", "__hip_bfloat16": "bf16"}
+_FN = {"k_sweep": "gather_sweep", "k_sweep_flat": "gather_sweep", "k_sweep_dual": "sweep_dual",
+       "k_gather": "gather_scalar", "k_gather_v4": "gather_v4", "k_gather_rows": "gather_rows",
+       "k_dense_mode": "dense_mode_mfma", "k_dense_modeE": "dense_mode_mfma", "k_dense_modeU": "dense_mode_mfma",
+       "k_dense_rows": "dense_mode_mfma", "k_coef_fused": "coef_fused", "k_coef_fused_pf": "coef_fused",
+       "k_quad_fused": "quad_fused", "k_time_mix": "time_mix", "k_arrowhead": "arrowhead",
+       "k_multidot": "multidot", "k_multidot_v": "multidot", "k_update_norm": "update_norm",
+       "k_pointwise_ionic": "pointwise_ionic", "k_mode_max": "mode_max"}
+
+
+def short_name(full: str) -> str:
+    """Library short name of a (demangled) kernel name, else the name cut at '('."""
+    m = re.search(r"\b(k_\w+)(?:<([^,>]+))?", full)
+    if m:
+        base = _FN.get(m.group(1), m.group(1)[2:])
+        prec = _PREC.get((m.group(2) or "").strip(), "")
+        if m.group(1) in ("k_quad_fused", "k_mode_max", "k_pointwise_ionic"):
+            prec = "f64"
+        return f"{base}<{prec}>" if prec else base
+    return re.sub(r"\(anonymous namespace\)::", "", full).split("(")[0][:80]
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 of the kernel sources (measured traffic is valid for these only)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp"):
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _rows(path):
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _find(d, suffix):
+    hits = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def stats(stats_csv: str, out_txt: str, command: str, top: int = 30) -> None:
+    rows = _rows(stats_csv)
+    agg = defaultdict(lambda: [0, 0.0])
+    for r in rows:
+        name = short_name(r.get("Name") or r.get("KernelName") or "")
+        agg[name][0] += int(float(r.get("Calls", 0)))
+        agg[name][1] += float(r.get("TotalDurationNs", 0.0))
+    tot = sum(v[1] for v in agg.values()) or 1.0
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}",
+             f"# kernels grouped by library function and storage precision", "",
+             f"{'kernel':40s} {'calls':>8s} {'total ms':>10s} {'avg us':>10s} {'share':>7s}"]
+    for name, (calls, ns) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
+        lines.append(f"{name:40s} {calls:8d} {ns / 1e6:10.2f} {ns / max(calls, 1) / 1e3:10.2f} {100 * ns / tot:6.1f}%")
+    lines.append("")
+    lines.append(f"all kernels: {tot / 1e6:.2f} ms")
+    with open(out_txt, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def _per_kernel(counter_dir: str, counter: str):
+    rows = _rows(_find(counter_dir, "counter_collection.csv"))
+    per = defaultdict(list)
+    for r in rows:
+        if r.get("Counter_Name", counter) != counter:
+            continue
+        name = r.get("Kernel_Name") or r.get("KernelName") or ""
+        per[name].append(float(r["Counter_Value"]))
+    return per
+
+
+def traffic(fetch_dir: str, write_dir: str, out_json: str, command: str, copy_bytes: int = 1 << 30) -> None:
+    fetch = _per_kernel(fetch_dir, "FETCH_SIZE")
+    write = _per_kernel(write_dir, "WRITE_SIZE")
+    # the copy: the non-library kernel (library kernels live in namespace
+    # stiga) with the largest fetch, i.e. the probe's 1 GiB device copy
+    cands = [n for n in fetch if "stiga" not in n and n in write]
+    copy = max(cands, key=lambda n: max(fetch[n]))
+    f_scale = copy_bytes / (max(fetch[copy]) * 1024.0)
+    w_scale = copy_bytes / (max(write[copy]) * 1024.0)
+    kern = {}
+    for n in fetch:
+        if n not in write or "stiga" not in n:
+            continue
+        s = short_name(n)
+        rd = sum(fetch[n]) / len(fetch[n]) * 1024.0 * f_scale
+        wr = sum(write[n]) / len(write[n]) * 1024.0 * w_scale
+        k = kern.setdefault(s, {"reads": [], "writes": []})
+        k["reads"].append(rd)
+        k["writes"].append(wr)
+    out = {}
+    for s, k in kern.items():
+        rd = sum(k["reads"]) / len(k["reads"])
+        wr = sum(k["writes"]) / len(k["writes"])
+        out[s] = {"fetch_bytes_per_launch": rd, "write_bytes_per_launch": wr, "hbm_bytes_per_launch": rd + wr}
+    doc = {"command": command, "copy_kernel": copy[:120], "fetch_scale": f_scale, "write_scale": w_scale,
+           "kernel_source_sha256": kernel_source_hash(), "kernels": out}
+    with open(out_json, "w") as fh:
+        json.dump(doc, fh, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    if len(sys.argv) >= 5 and sys.argv[1] == "stats":
+        stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif len(sys.argv) >= 6 and sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+    else:
+        sys.exit(__doc__)
