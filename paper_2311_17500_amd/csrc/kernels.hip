@@ -609,18 +609,38 @@ __global__ void __launch_bounds__(TPB) k_time_mix(const C* __restrict__ T, const
 // input B-spline rows an element touches (each over the NL input layers the
 // rows' time windows read) and a ring of their partial outputs; a B-spline is
 // complete, and stored, once the walk has passed its last element.
-template <class S, class C, int P, int KP, int TS>
+// Block order of the fused coefficient kernels, XCD-aware: consecutive
+// workgroups go to the 8 XCDs in turn, so the nslab time slabs of one column
+// block (which read the same rank weights and overlapping input layers) are
+// given ids 8 apart and run back to back on one XCD, sharing its L2.  The
+// grid has ceil(ncb * nchunk / 8) * 8 * nslab blocks; the padding ones exit.
+__device__ __forceinline__ bool coef_block(int nslab, int64_t ncb, int nchunk, int& slab, int64_t& cb, int& ch) {
+  const int64_t L = blockIdx.x;
+  const int64_t k = L >> 3;
+  slab = static_cast<int>(k % nslab);
+  const int64_t g = (k / nslab) * 8 + (L & 7);
+  if (g >= ncb * nchunk) return false;
+  cb = g % ncb;
+  ch = static_cast<int>(g / ncb);
+  return true;
+}
+
+template <class S, class C, int P, int KP, int TS, int RM>
 __global__ void __launch_bounds__(256) k_coef_fused(const C* __restrict__ T, const S* __restrict__ Psi, int r0, int R,
                                                     int Nt, int t0, int t1, const S* __restrict__ Z, int n_in,
                                                     int in_base, const C* __restrict__ Bl,
                                                     const int* __restrict__ efirst, const int* __restrict__ chunks,
-                                                    int nd, int64_t Qin, S* __restrict__ out, int64_t Qs) {
-  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+                                                    int nd, int64_t Qin, S* __restrict__ out, int64_t Qs, int nslab,
+                                                    int64_t ncb, int nchunk) {
+  int slab, ch;
+  int64_t cb;
+  if (!coef_block(nslab, ncb, nchunk, slab, cb, ch)) return;
+  const int64_t c = cb * blockDim.x + threadIdx.x;
   if (c >= Qin) return;
   constexpr int WB = 2 * P + 1, NL = TS + 2 * P;
-  const int ta = t0 + static_cast<int>(blockIdx.y) * TS;
-  const int e0 = chunks[4 * blockIdx.z], e1 = chunks[4 * blockIdx.z + 1];
-  const int d0 = chunks[4 * blockIdx.z + 2], d1 = chunks[4 * blockIdx.z + 3];
+  const int ta = t0 + slab * TS;
+  const int e0 = chunks[4 * ch], e1 = chunks[4 * ch + 1];
+  const int d0 = chunks[4 * ch + 2], d1 = chunks[4 * ch + 3];
   const int nrow = min(TS, t1 - ta);
   const int64_t lay = static_cast<int64_t>(nd) * Qin;
   const int jb = ta + 1 - P - in_base;   // input layer of window slot 0
@@ -666,6 +686,17 @@ __global__ void __launch_bounds__(256) k_coef_fused(const C* __restrict__ T, con
 #pragma unroll
       for (int t = 0; t < TS; ++t) yr[KP - 1][t] = C(0);
     }
+    // RM > 0 (R <= RM): the element's rank weights are loaded up front, so
+    // their latency is paid once per element instead of once per rank
+    C pv[KP][RM > 0 ? RM : 1];
+    if constexpr (RM > 0) {
+      const S* pe = Psi + static_cast<int64_t>(r0) * Qs + static_cast<int64_t>(e) * KP * Qin + c;
+#pragma unroll
+      for (int g = 0; g < KP; ++g)
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+          pv[g][r] = (r < R) ? to_c(pe[static_cast<int64_t>(r) * Qs + static_cast<int64_t>(g) * Qin], C(0)) : C(0);
+    }
 #pragma unroll
     for (int g = 0; g < KP; ++g) {
       const int qd = e * KP + g;
@@ -683,18 +714,24 @@ __global__ void __launch_bounds__(256) k_coef_fused(const C* __restrict__ T, con
       C m[TS];
 #pragma unroll
       for (int t = 0; t < TS; ++t) m[t] = C(0);
-      const S* ps = Psi + static_cast<int64_t>(r0) * Qs + static_cast<int64_t>(qd) * Qin + c;
-      for (int r = 0; r < R; ++r) {
-        const C psi = to_c(ps[static_cast<int64_t>(r) * Qs], C(0));
-        const C* Tr = T + static_cast<int64_t>(r0 + r) * Nt * WB;
+      auto mix = [&](int r, C psi) {
+        const C* Tr = T + (static_cast<int64_t>(r0 + r) * Nt + ta) * WB;
 #pragma unroll
         for (int t = 0; t < TS; ++t) {
-          const C* Tt = Tr + min(ta + t, Nt - 1) * WB;
+          const C* Tt = Tr + t * WB;
           C sacc = C(0);
 #pragma unroll
           for (int w = 0; w < WB; ++w) sacc += Tt[w] * zg[t + w];
           m[t] += psi * sacc;
         }
+      };
+      if constexpr (RM > 0) {
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+          if (r < R) mix(r, pv[g][r]);
+      } else {
+        const S* ps = Psi + static_cast<int64_t>(r0) * Qs + static_cast<int64_t>(qd) * Qin + c;
+        for (int r = 0; r < R; ++r) mix(r, to_c(ps[static_cast<int64_t>(r) * Qs], C(0)));
       }
 #pragma unroll
       for (int k = 0; k < KP; ++k)
@@ -723,13 +760,17 @@ __global__ void __launch_bounds__(256) k_coef_fused_pf(const C* __restrict__ T, 
                                                     int Nt, int t0, int t1, const S* __restrict__ Z, int n_in,
                                                     int in_base, const C* __restrict__ Bl,
                                                     const int* __restrict__ efirst, const int* __restrict__ chunks,
-                                                    int nd, int64_t Qin, S* __restrict__ out, int64_t Qs) {
-  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+                                                    int nd, int64_t Qin, S* __restrict__ out, int64_t Qs, int nslab,
+                                                    int64_t ncb, int nchunk) {
+  int slab, ch;
+  int64_t cb;
+  if (!coef_block(nslab, ncb, nchunk, slab, cb, ch)) return;
+  const int64_t c = cb * blockDim.x + threadIdx.x;
   if (c >= Qin) return;
   constexpr int WB = 2 * P + 1, NL = TS + 2 * P;
-  const int ta = t0 + static_cast<int>(blockIdx.y) * TS;
-  const int e0 = chunks[4 * blockIdx.z], e1 = chunks[4 * blockIdx.z + 1];
-  const int d0 = chunks[4 * blockIdx.z + 2], d1 = chunks[4 * blockIdx.z + 3];
+  const int ta = t0 + slab * TS;
+  const int e0 = chunks[4 * ch], e1 = chunks[4 * ch + 1];
+  const int d0 = chunks[4 * ch + 2], d1 = chunks[4 * ch + 3];
   const int nrow = min(TS, t1 - ta);
   const int64_t lay = static_cast<int64_t>(nd) * Qin;
   const int jb = ta + 1 - P - in_base;   // input layer of window slot 0
@@ -838,10 +879,10 @@ __global__ void __launch_bounds__(256) k_coef_fused_pf(const C* __restrict__ T, 
 #pragma unroll
       for (int t = 0; t < TS; ++t) m[t] = C(0);
       auto mix = [&](int r, C psi) {
-        const C* Tr = T + static_cast<int64_t>(r0 + r) * Nt * WB;
+        const C* Tr = T + (static_cast<int64_t>(r0 + r) * Nt + ta) * WB;
 #pragma unroll
         for (int t = 0; t < TS; ++t) {
-          const C* Tt = Tr + min(ta + t, Nt - 1) * WB;
+          const C* Tt = Tr + t * WB;
           C sacc = C(0);
 #pragma unroll
           for (int w = 0; w < WB; ++w) sacc += Tt[w] * zg[t + w];
@@ -1476,7 +1517,8 @@ __global__ void __launch_bounds__(384) k_quad_fused(
     const double* __restrict__ A0, const double* __restrict__ A1, const double* __restrict__ A2,
     const double* __restrict__ UT, const double* __restrict__ WW, int nd, int64_t Qin,
     const double* __restrict__ B0, const double* __restrict__ B2, const int* __restrict__ efirst,
-    const int* __restrict__ chunks, const double* __restrict__ wt, const double* __restrict__ ws, double sL,
+    const int* __restrict__ chunks, const double* __restrict__ wt, const double* __restrict__ win,
+    const double* __restrict__ wd, double sL,
     double sM, double sF, double Cm, double a, double c1, double c2, double* __restrict__ G,
     double* __restrict__ M, int nel_d, double* __restrict__ part, int64_t boff) {
   __shared__ double sh[8];
@@ -1493,6 +1535,7 @@ __global__ void __launch_bounds__(384) k_quad_fused(
   const int tr = et * nqt + row;
   const int64_t rb = static_cast<int64_t>(tr) * lay + cc;
   const double wtr = wt[tr];
+  const double wc = win[cc];   // product of the faster axes' Gauss weights of column c
   double a0[KP], a1[D == 3 ? KP : 1], a2[KP], ut[KP], ww[KP], gr[KP];
   auto load = [&](int k, int dof) {
     const bool ok = dof < nd;
@@ -1546,7 +1589,7 @@ __global__ void __launch_bounds__(384) k_quad_fused(
       emax = fmax(emax, fabs(Cm * tt - lap + I));
       mu = fmax(mu, fabs(u));
       mt = fmax(mt, fabs(tt));
-      const double gv = wtr * ws[static_cast<int64_t>(qd) * Qin + cc] * I;
+      const double gv = wtr * (wc * wd[qd]) * I;
 #pragma unroll
       for (int k = 0; k < KP; ++k) gr[k] += B0[qd * KP + k] * gv;
     }
@@ -1879,8 +1922,9 @@ bool coef_fused(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1
   if (pt < 1 || pt > 5 || ps < 1 || ps > 4) return false;
   if (t1 <= t0 || Qin == 0) return true;
   const int R = r1 - r0;
-  const dim3 g(static_cast<unsigned>((Qin + TPB - 1) / TPB), static_cast<unsigned>((t1 - t0 + TS - 1) / TS),
-               static_cast<unsigned>(nchunk));
+  const int nslab = (t1 - t0 + TS - 1) / TS;
+  const int64_t ncb = (Qin + TPB - 1) / TPB;
+  const dim3 g(static_cast<unsigned>((ncb * nchunk + 7) / 8 * 8 * nslab));
   const double rows = static_cast<double>(t1 - t0);
   // algorithmic flops per output row and Gauss point: the time mixing
   // (2 R (2 p_t + 2)) plus the expansion and projection along the axis (4 (p_s + 1))
@@ -1892,11 +1936,12 @@ bool coef_fused(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1
     bool done_ = false;                                                                                           \
     if constexpr (f64) {                                                                                          \
       if (R <= 4) {                                                                                               \
-        hipLaunchKernelGGL((k_coef_fused_pf<S, C, P_, K_, TS, 4, true>), g, dim3(TPB), 0, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, Bl, efirst, chunks, nd, Qin, out, Qs); \
+        hipLaunchKernelGGL((k_coef_fused_pf<S, C, P_, K_, TS, 4, true>), g, dim3(TPB), 0, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, Bl, efirst, chunks, nd, Qin, out, Qs, nslab, ncb, nchunk); \
         done_ = true;                                                                                             \
       }                                                                                                           \
     }                                                                                                             \
-    if (!done_) hipLaunchKernelGGL((k_coef_fused<S, C, P_, K_, TS>), g, dim3(TPB), 0, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, Bl, efirst, chunks, nd, Qin, out, Qs); \
+    if (!done_ && R <= 4) hipLaunchKernelGGL((k_coef_fused<S, C, P_, K_, TS, 4>), g, dim3(TPB), 0, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, Bl, efirst, chunks, nd, Qin, out, Qs, nslab, ncb, nchunk); \
+    else if (!done_) hipLaunchKernelGGL((k_coef_fused<S, C, P_, K_, TS, 0>), g, dim3(TPB), 0, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, Bl, efirst, chunks, nd, Qin, out, Qs, nslab, ncb, nchunk); \
   } while (0)
 #define CFP(P_)                 \
   switch (ps) {                 \
@@ -2122,7 +2167,8 @@ void pointwise_ionic(const double* u, const double* ut, const double* lap, const
 }
 int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, const double* A2, const double* UT,
                    const double* WW, int nd, int64_t Qin, int ne, const double* B0, const double* B2,
-                   const int* efirst, const int* chunks, int nchunk, const double* wt, const double* ws, double sL,
+                   const int* efirst, const int* chunks, int nchunk, const double* wt, const double* win,
+                   const double* wd, double sL,
                    double sM, double sF, double Cm, double a, double c1, double c2, double* G, double* M, int nel_d,
                    double* part, int64_t boff, hipStream_t s) {
   if (d < 2 || d > 3 || ps < 1 || ps > 4 || nqt < 1 || nqt > 6) return -1;
@@ -2132,7 +2178,7 @@ int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, c
   ProfScope pr(K_POINTWISE, 12, s,
                (rows * nd * Qin * ((d == 3 ? 5.0 : 4.0) + (G ? 1.0 : 0.0)) + (M ? static_cast<double>(ne) * nel_d * Qin : 0.0) +
                 static_cast<double>(nel_d) * (ps + 1) * Qin) * sizeof(double));
-#define QF(D_, K_) hipLaunchKernelGGL((k_quad_fused<D_, K_>), g, blk, 0, s, A0, A1, A2, UT, WW, nd, Qin, B0, B2, efirst, chunks, wt, ws, sL, sM, sF, Cm, a, c1, c2, G, M, nel_d, part, boff)
+#define QF(D_, K_) hipLaunchKernelGGL((k_quad_fused<D_, K_>), g, blk, 0, s, A0, A1, A2, UT, WW, nd, Qin, B0, B2, efirst, chunks, wt, win, wd, sL, sM, sF, Cm, a, c1, c2, G, M, nel_d, part, boff)
 #define QFK(D_)                         \
   switch (ps) {                         \
     case 1: QF(D_, 2); break;           \

@@ -60,7 +60,7 @@ void mode_max(const int* start, const int* cnt, int n_out, const double* x, doub
 
 // Coefficient part of the operator at the spatial Gauss points, rows t in [t0, t1):
 //   out[t - t0][q] = sum_{r in [r0,r1)} Psi[r][q] sum_w T[r][t][w] * Z[t+1-p+w - in_base][q]
-// (T has N_t rows of X_t; inputs outside [0, n_in) skipped).
+// (T has Nt rows per rank, at least t1; inputs outside [0, n_in) skipped).
 template <class S, class C>
 void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1, int p, const S* Z, int n_in,
               int in_base, S* out, int64_t Qs, hipStream_t s);
@@ -70,6 +70,8 @@ void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1, 
 //   out[t - t0][i][c] = sum_{q in axis Gauss points} Bl[q][i - efirst(q)] *
 //                       sum_{r in [r0,r1)} Psi[r][q*Qin + c] sum_w T[r][t][w] z[t+1-p+w - in_base][q][c],
 //   z[j][q][c] = sum_k Bl[q][k] Z[j][efirst(q)+k][c],
+// T: [rank][Nt][2 p_t + 1] with Nt >= t1 + 7 rows per rank (rows past the
+// last time row zero; a thread reads 8 rows from its first),
 // Z: [n_in][nd][Qin], out: [t1-t0][nd][Qin], Bl: [Q][ps+1] basis values at the
 // axis' Gauss points (element-major, ps+1 points per element), efirst: first
 // B-spline of each element, chunks: nchunk x {e0, e1, d0, d1} (elements
@@ -86,7 +88,8 @@ bool coef_fused(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1
 // A2 = B2 B0 u; d = 2: A0 = B0 u, A2 = B2 u, A1 unused), UT and WW the
 // value expansions of u_t and w; B0, B2: [Q][ps+1] basis values and second
 // derivatives at the axis' Gauss points; wt: time weights of the ne*nqt
-// rows; ws: spatial weights [Qs].  Outputs (each optional): G [ne*nqt][nd][Qin]
+// rows; win: products of the faster axes' Gauss weights [Qin]; wd: Gauss
+// weights of the axis [Q].  Outputs (each optional): G [ne*nqt][nd][Qin]
 // (weighted ionic current projected onto the axis' B-splines), M
 // [ne][nel_d][Qin] (element maxima of |R| over the axis and time), and block
 // maxima of |u|, |u_t| at part[2(boff + b)], part[2(boff + b) + 1].  Returns
@@ -94,7 +97,8 @@ bool coef_fused(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1
 // d in {2, 3}, ps <= 4, nqt <= 6).
 int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, const double* A2, const double* UT,
                    const double* WW, int nd, int64_t Qin, int ne, const double* B0, const double* B2,
-                   const int* efirst, const int* chunks, int nchunk, const double* wt, const double* ws, double sL,
+                   const int* efirst, const int* chunks, int nchunk, const double* wt, const double* win,
+                   const double* wd, double sL,
                    double sM, double sF, double Cm, double a, double c1, double c2, double* G, double* M, int nel_d,
                    double* part, int64_t boff, hipStream_t s);
 

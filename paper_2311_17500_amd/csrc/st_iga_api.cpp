@@ -73,6 +73,7 @@ struct st_iga_ctx {
   std::vector<Dir1D> dir;   // d spatial + time (last)
   int n[3] = {1, 1, 1}, Q[3] = {1, 1, 1};
   int nt = 0, Nt = 0, nqt = 0, nelt = 0, nel[3] = {1, 1, 1};
+  int NtP = 0;   // row stride of the low-rank time tables (N_t plus zero rows)
   int64_t Ns = 0, Qs = 0, nunk = 0, nfull = 0, Nels = 0;
   int chunk_el = 1;
   int64_t big_len = 0;
@@ -92,8 +93,8 @@ struct st_iga_ctx {
   // time elements per chunk
   bool qf = false;
   int qf_ne = 1;
-  std::vector<double> cf_B2_h;
-  double* cf_B2_d = nullptr;
+  std::vector<double> cf_B2_h, qf_win_h, qf_wd_h;
+  double *cf_B2_d = nullptr, *qf_win = nullptr, *qf_wd = nullptr;
   int *cf_first = nullptr, *cf_chunks = nullptr;
   Arena ar;
   std::string err;
@@ -286,6 +287,19 @@ void plan_fused_coef(st_iga_ctx* c) {
   const int64_t per1 = nqt * 6 * nd * Qin + 2LL * D.nel * Qin;
   const int64_t ne = std::min(c->big_len / per0, c->big_len / per1);
   c->qf = nqt >= 1 && nqt <= 6 && ne >= 1;
+  // spatial Gauss weights factored as (faster axes) x (this axis), each
+  // product formed in the same order as the full tensor weights
+  c->qf_win_h.assign(Qin, 1.0);
+  for (int64_t q = 0; q < Qin; ++q) {
+    int64_t r = q;
+    double w = 1.0;
+    for (int l = 0; l < d - 1; ++l) {
+      w *= c->dir[l].wq[r % c->Q[l]];
+      r /= c->Q[l];
+    }
+    c->qf_win_h[q] = w;
+  }
+  c->qf_wd_h = D.wq;
   c->qf_ne = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(c->nelt, ne)));
 }
 
@@ -484,6 +498,8 @@ void plan(st_iga_ctx* c) {
     c->cf_first = a.get<int>(static_cast<int64_t>(c->cf_first_h.size()));
     c->cf_chunks = a.get<int>(static_cast<int64_t>(c->cf_chunks_h.size()));
     c->cf_B2_d = a.get<double>(static_cast<int64_t>(c->cf_B2_h.size()));
+    c->qf_win = a.get<double>(static_cast<int64_t>(c->qf_win_h.size()));
+    c->qf_wd = a.get<double>(static_cast<int64_t>(c->qf_wd_h.size()));
   }
   T(c->Mt_x); T(c->Wt_x); T(c->Bt0); T(c->Bt1); T(c->BtT); T(c->Gt); T(c->Ut); T(c->UtT); T(c->Ew);
   for (st_iga_ctx::Dense* D : {&c->DUt, &c->DUtT, &c->DUs[0], &c->DUs[1], &c->DUs[2], &c->DUsT[0], &c->DUsT[1],
@@ -516,8 +532,9 @@ void plan(st_iga_ctx* c) {
   c->Vth = a.get<double>(c->Ns * c->maxR);
   c->Vc = a.get<double>(c->Ns * c->maxR);
   c->Psi = a.get<double>(static_cast<int64_t>(R2) * c->Qs);
-  c->Tr = a.get<double>(static_cast<int64_t>(R2) * c->Nt * WB);
-  c->Tr_f = a.get<float>(static_cast<int64_t>(R2) * c->Nt * WB);
+  c->NtP = c->Nt + 8;   // row stride of the time tables: 8 zero rows past the last
+  c->Tr = a.get<double>(static_cast<int64_t>(R2) * c->NtP * WB);
+  c->Tr_f = a.get<float>(static_cast<int64_t>(R2) * c->NtP * WB);
   for (int k = 0; k < 4; ++k) c->t4[k] = a.get<double>(c->nfull);
   for (int k = 0; k < 2; ++k) c->big[k] = a.get<double>(c->big_len);
   c->VT = a.get<double>(static_cast<int64_t>(c->maxR) * c->Ns);
@@ -600,6 +617,8 @@ void upload_all(st_iga_ctx* c, hipStream_t s) {
     up(c->cf_first_h, static_cast<const int*>(c->cf_first), s);
     up(c->cf_chunks_h, static_cast<const int*>(c->cf_chunks), s);
     up(c->cf_B2_h, static_cast<const double*>(c->cf_B2_d), s);
+    up(c->qf_win_h, static_cast<const double*>(c->qf_win), s);
+    up(c->qf_wd_h, static_cast<const double*>(c->qf_wd), s);
   }
   for (st_iga_ctx::Dense* D : {&c->DUt, &c->DUtT, &c->DUs[0], &c->DUs[1], &c->DUs[2], &c->DUsT[0], &c->DUsT[1],
                                &c->DUsT[2]}) {
@@ -800,7 +819,7 @@ void apply_impl(st_iga_ctx* c, const S* x, S* y, int L, int in_base, bool with_s
       S* Y2 = B.big[1];
       if (d == 2) {
         gather<S, S, C>(Ops<S, C>::tab(*ex[0]), xs, X1, static_cast<int64_t>(nl) * nn[1], 1, nn[0], 0, C(1), C(0), s);
-        coef_fused<S, C>(Tr, B.Psi, r0, r1, c->Nt, t0, t1, p, P.p_s, X1, nl, in_base + lo, Bl, c->cf_first,
+        coef_fused<S, C>(Tr, B.Psi, r0, r1, c->NtP, t0, t1, p, P.p_s, X1, nl, in_base + lo, Bl, c->cf_first,
                          c->cf_chunks, c->cf_nchunk, nd, Qin, Y2, c->Qs, s);
         gather<S, S, C>(Ops<S, C>::tab(*pr[0]), Y2, ys, static_cast<int64_t>(rows) * nn[1], 1, qd[0], 0, C(1), C(1), s);
       } else {
@@ -810,7 +829,7 @@ void apply_impl(st_iga_ctx* c, const S* x, S* y, int L, int in_base, bool with_s
                         C(0), s);
         gather<S, S, C>(Ops<S, C>::tab(*ex[1]), X1, X2, static_cast<int64_t>(nl) * nn[2], qd[0], nn[1], 0, C(1), C(0),
                         s);
-        coef_fused<S, C>(Tr, B.Psi, r0, r1, c->Nt, t0, t1, p, P.p_s, X2, nl, in_base + lo, Bl, c->cf_first,
+        coef_fused<S, C>(Tr, B.Psi, r0, r1, c->NtP, t0, t1, p, P.p_s, X2, nl, in_base + lo, Bl, c->cf_first,
                          c->cf_chunks, c->cf_nchunk, nd, Qin, Y2, c->Qs, s);
         gather<S, S, C>(Ops<S, C>::tab(*pr[1]), Y2, Y1, static_cast<int64_t>(rows) * nn[2], qd[0], qd[1], 0, C(1), C(0),
                         s);
@@ -829,7 +848,7 @@ void apply_impl(st_iga_ctx* c, const S* x, S* y, int L, int in_base, bool with_s
     const S* xs = x + static_cast<int64_t>(lo) * Ns;
     if (d == 1) gather<S, S, C>(Ops<S, C>::tab(*ex[0]), xs, Z, nl, 1, nn[0], 0, C(1), C(0), s);
     else spatial_chain<S, C>(c, ex, xs, nl, nn, qd, bufA, bufB, Z, C(1), C(0), s);
-    time_mix<S, C>(Tr, B.Psi, r0, r1, c->Nt, t0, t1, p, Z, nl, in_base + lo, W2, c->Qs, s);
+    time_mix<S, C>(Tr, B.Psi, r0, r1, c->NtP, t0, t1, p, Z, nl, in_base + lo, W2, c->Qs, s);
     S* ys = y + static_cast<int64_t>(t0) * Ns;
     if (d == 1) gather<S, S, C>(Ops<S, C>::tab(*pr[0]), W2, ys, t1 - t0, 1, qd[0], 0, C(1), C(1), s);
     else spatial_chain<S, C>(c, pr, W2, t1 - t0, qd, nn, Z, (d == 3 ? W2 : Z), ys, C(1), C(1), s);
@@ -1266,7 +1285,8 @@ void quad_pass_fused(st_iga_ctx* c, const double* u, const double* w, bool want_
       sF = P.sigma[0];
     }
     const int64_t nb = quad_fused(d, P.p_s, nq, in[0], in[1], in[2], in[3], in[4], nd, Qin, ne, c->cf_Bl_d,
-                                  c->cf_B2_d, c->cf_first, c->cf_chunks, c->cf_nchunk, c->wq_t + q0, c->wq_s, sL, sM,
+                                  c->cf_B2_d, c->cf_first, c->cf_chunks, c->cf_nchunk, c->wq_t + q0, c->qf_win,
+                                  c->qf_wd, sL, sM,
                                   sF, P.Cm, P.a, P.c1, P.c2, want_res ? Gp : nullptr, want_theta ? Mp : nullptr, neld,
                                   c->part, boff, s);
     if (nb < 0) throw Fail{ST_IGA_EINVAL, "fused quadrature pass: unsupported degrees"};
@@ -1538,14 +1558,15 @@ void rebuild_coefficients(st_iga_ctx* c, hipStream_t s) {
   std::vector<int> left;
   std::vector<double> wl;
   hat_weights(nodes, T.xq, left, wl);
-  std::vector<double> Tr(static_cast<size_t>(std::max(Rt, 1)) * Nt * WB, 0.0);
+  const int NtP = c->NtP;
+  std::vector<double> Tr(static_cast<size_t>(std::max(Rt, 1)) * NtP * WB, 0.0);
   for (int set = 0; set < 2; ++set) {
     const int R = set == 0 ? c->Rth : c->Rc;
     const std::vector<double>& U = set == 0 ? c->Uth_h : c->Uc_h;
     const std::vector<double>& sv = set == 0 ? c->sth_h : c->sc_h;
     const int roff = set == 0 ? 0 : c->Rth;
     for (int r = 0; r < R; ++r) {
-      double* Trr = &Tr[static_cast<size_t>(roff + r) * Nt * WB];
+      double* Trr = &Tr[static_cast<size_t>(roff + r) * NtP * WB];
       for (int q = 0; q < T.Q; ++q) {
         const int g0 = left[q];
         const int g1 = std::min(g0 + 1, Nt - 1);
