@@ -256,6 +256,13 @@ const char* st_iga_last_error(const st_iga_ctx* ctx);
 st_iga_status st_iga_host_query(const st_iga_problem* prob, int32_t what, int32_t dir, double* out,
                                 int64_t cap, int64_t* len);
 
+/* Host-only check of the symmetric eigensolver used for the truncated SVDs of
+ * eq. (3.8) (through the N_t x N_t Gram matrix): A (n x n, row-major,
+ * symmetric, HOST) = Q diag(lam) Q^T with lam ascending and the eigenvectors
+ * in the columns of the row-major Q (n*n, HOST).  ENOCONV if the QL
+ * iteration fails. */
+st_iga_status st_iga_host_symeig(int32_t n, const double* A, double* Q, double* lam);
+
 #ifdef __cplusplus
 }
 #endif

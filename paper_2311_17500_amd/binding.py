@@ -23,7 +23,8 @@ EXPORTS = ["st_iga_default_options", "st_iga_workspace_bytes", "st_iga_setup", "
            "st_iga_set_factors", "st_iga_get_factors", "st_iga_theta_grid", "st_iga_apply", "st_iga_precond",
            "st_iga_residual", "st_iga_w_update", "st_iga_krylov", "st_iga_solve", "st_iga_lift", "st_iga_sizes",
            "st_iga_destroy", "st_iga_last_error", "st_iga_host_query", "st_iga_newton_step", "st_iga_profile",
-           "st_iga_profile_read", "st_iga_apply_lowp", "st_iga_precond_lowp", "st_iga_profile_record"]
+           "st_iga_profile_read", "st_iga_apply_lowp", "st_iga_precond_lowp", "st_iga_profile_record",
+           "st_iga_host_symeig"]
 
 
 class Problem(C.Structure):
@@ -103,6 +104,7 @@ def load(path: str = LIB_PATH):
     lib.st_iga_profile_record.argtypes = [P, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                           C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.st_iga_host_query.argtypes = [C.POINTER(Problem), C.c_int32, C.c_int32, V, C.c_int64, C.POINTER(C.c_int64)]
+    lib.st_iga_host_symeig.argtypes = [C.c_int32, V, V, V]
     for name in EXPORTS:
         if name not in ("st_iga_default_options", "st_iga_workspace_bytes", "st_iga_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -167,6 +169,18 @@ def host_query(prob, what: int, direction: int, knots=None) -> np.ndarray:
     out = np.zeros(max(n.value, 1))
     lib.st_iga_host_query(C.byref(P), what, direction, _dptr(out), n.value, C.byref(n))
     return out[: n.value]
+
+
+def host_symeig(A: np.ndarray):
+    """Eigen-decomposition of a symmetric matrix by the library's host solver: (lam ascending, Q)."""
+    lib = load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    Q, lam = np.zeros((n, n)), np.zeros(n)
+    st = lib.st_iga_host_symeig(n, _dptr(A), _dptr(Q), _dptr(lam))
+    if st != OK:
+        raise StIgaError(st, lib.st_iga_last_error(None).decode())
+    return lam, Q
 
 
 class Solver:

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <numeric>
 
 namespace stiga {
@@ -380,6 +381,135 @@ bool tau_at_quad(const Dir1D& T, std::vector<double>& tauq, std::vector<double>&
       tauq[static_cast<size_t>(k - 1) * T.Q + qq] = v;
     }
     c0 += s.n;
+  }
+  return true;
+}
+
+// Symmetric eigenproblem A = Q diag(lam) Q^T by Householder reduction to
+// tridiagonal form followed by the QL iteration with implicit shifts (the
+// classical two-phase method; O(n^3) with small constants, unlike the cyclic
+// Jacobi sweeps).  Output as gen_eig_sym: lam ascending, eigenvectors in the
+// columns of the row-major Q.
+bool sym_eig(const std::vector<double>& A, int n, std::vector<double>& Q, std::vector<double>& lam, std::string& err) {
+  std::vector<double> Z(A), d(n, 0.0), e(n, 0.0);
+  auto z = [&](int i, int j) -> double& { return Z[static_cast<size_t>(i) * n + j]; };
+  // Householder: step i annihilates row i left of the subdiagonal
+  for (int i = n - 1; i >= 1; --i) {
+    const int l = i - 1;
+    double h = 0.0;
+    if (l > 0) {
+      double scale = 0.0;
+      for (int k = 0; k <= l; ++k) scale += std::fabs(z(i, k));
+      if (scale == 0.0) {
+        e[i] = z(i, l);
+      } else {
+        for (int k = 0; k <= l; ++k) {
+          z(i, k) /= scale;
+          h += z(i, k) * z(i, k);
+        }
+        double f = z(i, l);
+        const double g0 = f >= 0.0 ? -std::sqrt(h) : std::sqrt(h);
+        e[i] = scale * g0;
+        h -= f * g0;
+        z(i, l) = f - g0;
+        f = 0.0;
+        for (int j = 0; j <= l; ++j) {
+          z(j, i) = z(i, j) / h;
+          double g = 0.0;
+          for (int k = 0; k <= j; ++k) g += z(j, k) * z(i, k);
+          for (int k = j + 1; k <= l; ++k) g += z(k, j) * z(i, k);
+          e[j] = g / h;
+          f += e[j] * z(i, j);
+        }
+        const double hh = f / (h + h);
+        for (int j = 0; j <= l; ++j) {
+          const double fj = z(i, j);
+          const double gj = e[j] - hh * fj;
+          e[j] = gj;
+          for (int k = 0; k <= j; ++k) z(j, k) -= fj * e[k] + gj * z(i, k);
+        }
+      }
+    } else {
+      e[i] = z(i, l);
+    }
+    d[i] = h;
+  }
+  d[0] = 0.0;
+  e[0] = 0.0;
+  // accumulate the transformations
+  for (int i = 0; i < n; ++i) {
+    const int l = i - 1;
+    if (d[i] != 0.0) {
+      for (int j = 0; j <= l; ++j) {
+        double g = 0.0;
+        for (int k = 0; k <= l; ++k) g += z(i, k) * z(k, j);
+        for (int k = 0; k <= l; ++k) z(k, j) -= g * z(k, i);
+      }
+    }
+    d[i] = z(i, i);
+    z(i, i) = 1.0;
+    for (int j = 0; j <= l; ++j) z(j, i) = z(i, j) = 0.0;
+  }
+  // QL with implicit shifts on (d, e)
+  for (int i = 1; i < n; ++i) e[i - 1] = e[i];
+  if (n > 0) e[n - 1] = 0.0;
+  for (int l = 0; l < n; ++l) {
+    int iter = 0, m;
+    do {
+      for (m = l; m < n - 1; ++m) {
+        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+        if (std::fabs(e[m]) <= std::numeric_limits<double>::epsilon() * dd) break;
+      }
+      if (m != l) {
+        if (iter++ == 64) {
+          err = "QL iteration did not converge";
+          return false;
+        }
+        double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+        double r = std::hypot(g, 1.0);
+        g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? std::fabs(r) : -std::fabs(r)));
+        double s = 1.0, c = 1.0, p = 0.0;
+        int i;
+        bool deflated = false;
+        for (i = m - 1; i >= l; --i) {
+          double f = s * e[i];
+          const double b = c * e[i];
+          r = std::hypot(f, g);
+          e[i + 1] = r;
+          if (r == 0.0) {
+            d[i + 1] -= p;
+            e[m] = 0.0;
+            deflated = true;
+            break;
+          }
+          s = f / r;
+          c = g / r;
+          g = d[i + 1] - p;
+          r = (d[i] - g) * s + 2.0 * c * b;
+          p = s * r;
+          d[i + 1] = g + p;
+          g = c * r - b;
+          for (int k = 0; k < n; ++k) {
+            f = z(k, i + 1);
+            z(k, i + 1) = s * z(k, i) + c * f;
+            z(k, i) = c * z(k, i) - s * f;
+          }
+        }
+        if (deflated) continue;
+        d[l] -= p;
+        e[l] = g;
+        e[m] = 0.0;
+      }
+    } while (m != l);
+  }
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
+  Q.assign(static_cast<size_t>(n) * n, 0.0);
+  lam.resize(n);
+  for (int j = 0; j < n; ++j) {
+    lam[j] = d[idx[j]];
+    for (int i = 0; i < n; ++i) Q[static_cast<size_t>(i) * n + j] = z(i, idx[j]);
   }
   return true;
 }

@@ -53,6 +53,9 @@ bool tau_at_quad(const Dir1D& T, std::vector<double>& tauq, std::vector<double>&
 
 // Symmetric-definite generalized eigenproblem K u = lambda M u (dense, n x n):
 // U (column j = eigenvector j, row-major U[i*n+j]) with U^T M U = I, ascending lambda.
+// Symmetric eigenproblem (Householder tridiagonalization + implicit-shift QL):
+// lam ascending, eigenvectors in the columns of the row-major Q.
+bool sym_eig(const std::vector<double>& A, int n, std::vector<double>& Q, std::vector<double>& lam, std::string& err);
 bool gen_eig_sym(const std::vector<double>& K, const std::vector<double>& M, int n,
                  std::vector<double>& U, std::vector<double>& lam, std::string& err);
 

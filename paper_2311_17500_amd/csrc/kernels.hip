@@ -1372,6 +1372,15 @@ __global__ void __launch_bounds__(TPB) k_finalize_sum(const double* __restrict__
   if (threadIdx.x == 0) out[j] = s;
 }
 
+// out[q] = max_b part[2 b + q], q = 0, 1 (one block per q)
+__global__ void __launch_bounds__(TPB) k_finalize_max2(const double* __restrict__ part, int64_t nb, double* __restrict__ out) {
+  __shared__ double sh[TPB / 64];
+  double m = 0.0;
+  for (int64_t b = threadIdx.x; b < nb; b += TPB) m = fmax(m, part[2 * b + blockIdx.x]);
+  const double s = block_max(m, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
 __global__ void __launch_bounds__(TPB) k_finalize_max(const double* __restrict__ part, int nb, double* __restrict__ out) {
   __shared__ double sh[TPB / 64];
   double m = 0.0;
@@ -2126,6 +2135,9 @@ void sumsq_partial(const double* x, int64_t n, double* part, int nb, hipStream_t
 }
 void finalize_max(const double* part, int nb, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize_max, dim3(1), dim3(TPB), 0, s, part, nb, out);
+}
+void finalize_max2(const double* part, int64_t nb, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_max2, dim3(2), dim3(TPB), 0, s, part, nb, out);
 }
 template <class T>
 void scale_by_dev(T* x, int64_t n, const double* nrm2, hipStream_t s) {

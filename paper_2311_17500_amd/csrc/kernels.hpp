@@ -127,6 +127,8 @@ void update_norm_partial(const T* V, int64_t ldv, int k, const double* h, T* w, 
 void absmax_partial(const double* x, int64_t n, double* part, int nb, hipStream_t s);
 void sumsq_partial(const double* x, int64_t n, double* part, int nb, hipStream_t s);
 void finalize_max(const double* part, int nb, double* out, hipStream_t s);
+// out[q] = max_b part[2 b + q] for q = 0, 1 (interleaved pairs of nb blocks)
+void finalize_max2(const double* part, int64_t nb, double* out, hipStream_t s);
 
 // x = a * x (scale from a device scalar: x *= 1/sqrt(*nrm2) if inv_sqrt)
 template <class T>

@@ -1196,23 +1196,11 @@ void project_space(st_iga_ctx* c, const double* g, int64_t L, double* tA, double
   spatial_chain<double, double>(c, pr, g, L, qd, nn, tA, tB, dst, 1.0, beta, s);
 }
 
-// One pass over all space-time Gauss points (time-chunked): ionic part of the
-// residual into rfull (full rows) and/or the element maxima of |R| into E; the
-// maxima of |u| and |u_t| into dsc[300], dsc[301].
-// Host side of the partial maxima of |u| and |u_t|: nb interleaved pairs in
-// part; the two maxima go to dsc[300], dsc[301].
+// Maxima of |u| and |u_t| from nb interleaved block partials in part; the
+// two maxima go to dsc[300], dsc[301].
 void finish_uv_maxima(st_iga_ctx* c, int64_t nb, hipStream_t s) {
-  std::vector<double> hp(2 * nb);
-  CK(hipMemcpyAsync(hp.data(), c->part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-  CK(hipStreamSynchronize(s));
+  finalize_max2(c->part, nb, c->dsc + 300, s);
   check_launch();
-  double mm[2] = {0.0, 0.0};
-  for (int64_t b = 0; b < nb; ++b) {
-    mm[0] = std::max(mm[0], hp[2 * b]);
-    mm[1] = std::max(mm[1], hp[2 * b + 1]);
-  }
-  CK(hipMemcpyAsync(c->dsc + 300, mm, 2 * sizeof(double), hipMemcpyHostToDevice, s));
-  CK(hipStreamSynchronize(s));
 }
 
 // The quadrature pass with the slowest spatial axis fused (d >= 2): per
@@ -1313,6 +1301,9 @@ void quad_pass_fused(st_iga_ctx* c, const double* u, const double* w, bool want_
   finish_uv_maxima(c, boff, s);
 }
 
+// One pass over all space-time Gauss points (time-chunked): ionic part of the
+// residual into rfull (full rows) and/or the element maxima of |R| into E; the
+// maxima of |u| and |u_t| into dsc[300], dsc[301].
 void quad_pass(st_iga_ctx* c, const double* u, const double* w, bool want_res, bool want_theta, hipStream_t s) {
   if (c->qf) {
     quad_pass_fused(c, u, w, want_res, want_theta, s);
@@ -1418,22 +1409,8 @@ void quad_pass(st_iga_ctx* c, const double* u, const double* w, bool want_res, b
     }
   }
   (void)part_t;
-  // maxima of |u| and |u_t|: interleaved partials
-  const int nbt = boff / 2;
-  // reuse finalize_max on strided data: copy via a small kernel is avoided by two passes
-  // (the partial array is [2b] = |u| max, [2b+1] = |u_t| max)
-  std::vector<double> hp(boff);
-  CK(hipMemcpyAsync(hp.data(), part_u, boff * sizeof(double), hipMemcpyDeviceToHost, s));
-  CK(hipStreamSynchronize(s));
-  check_launch();
-  double mu = 0.0, mt = 0.0;
-  for (int b = 0; b < nbt; ++b) {
-    mu = std::max(mu, hp[2 * b]);
-    mt = std::max(mt, hp[2 * b + 1]);
-  }
-  double mm[2] = {mu, mt};
-  CK(hipMemcpyAsync(c->dsc + 300, mm, 2 * sizeof(double), hipMemcpyHostToDevice, s));
-  CK(hipStreamSynchronize(s));
+  // maxima of |u| and |u_t| from the interleaved partials ([2b] |u|, [2b+1] |u_t|)
+  finish_uv_maxima(c, boff / 2, s);
 }
 
 // Theta grid (N_t x N_s) of eq. (3.4) into dst.
@@ -1489,10 +1466,8 @@ int lowrank(st_iga_ctx* c, const double* C, double eps, std::vector<double>& U, 
   CK(hipStreamSynchronize(s));
   check_launch();
   std::vector<double> Q, lam;
-  std::vector<double> I(static_cast<size_t>(m) * m, 0.0);
-  for (int i = 0; i < m; ++i) I[static_cast<size_t>(i) * m + i] = 1.0;
   std::string err;
-  if (!gen_eig_sym(G, I, m, Q, lam, err)) throw Fail{ST_IGA_EDEVICE, "Gram eigendecomposition: " + err};
+  if (!sym_eig(G, m, Q, lam, err)) throw Fail{ST_IGA_EDEVICE, "Gram eigendecomposition: " + err};
   // descending order
   double tot = 0.0;
   for (double& v : lam) { v = std::max(v, 0.0); tot += v; }
@@ -2007,6 +1982,18 @@ st_iga_status st_iga_destroy(st_iga_ctx* c) {
 }
 
 const char* st_iga_last_error(const st_iga_ctx* c) { return c ? c->err.c_str() : g_last_err.c_str(); }
+
+st_iga_status st_iga_host_symeig(int32_t n, const double* A, double* Q, double* lam) {
+  if (n < 1 || !A || !Q || !lam) return ST_IGA_EINVAL;
+  st_iga_ctx c;
+  return guard(&c, [&] {
+    std::vector<double> M(A, A + static_cast<size_t>(n) * n), U, l;
+    std::string err;
+    if (!sym_eig(M, n, U, l, err)) throw Fail{ST_IGA_ENOCONV, err};
+    std::copy(U.begin(), U.end(), Q);
+    std::copy(l.begin(), l.end(), lam);
+  });
+}
 
 st_iga_status st_iga_host_query(const st_iga_problem* prob, int32_t what, int32_t dir, double* out, int64_t cap,
                                 int64_t* len) {

@@ -191,3 +191,20 @@ def test_fused_coefficient_plan(lib, case):
         assert np.all(np.diff(efirst[e0:e1]) >= 1) and np.all(np.diff(efirst[e0:e1]) <= p + 1)
     if case in ("2d_p2_12", "3d_p1_8"):
         assert nch > 1      # the GPU parity cases for split axes
+
+
+@pytest.mark.parametrize("n,rank", [(1, 1), (2, 0), (5, 2), (49, 3), (49, 49), (130, 4), (130, 130)])
+def test_host_symeig(lib, n, rank):
+    """The Gram-matrix eigensolver of the truncated SVD: A Q = Q diag(lam),
+    Q orthogonal, lam ascending and equal to LAPACK's, the null space of a
+    rank-deficient Gram matrix resolved (eigenvalues ~ 0)."""
+    rng = np.random.default_rng(n * 1000 + rank)
+    X = rng.standard_normal((n, max(rank, 1))) * (1.0 if rank else 0.0)
+    A = X @ X.T
+    lam, Q = binding.host_symeig(A)
+    scale = max(np.max(np.abs(lam)), 1e-300) if rank else 1.0
+    assert np.all(np.diff(lam) >= 0)
+    assert np.max(np.abs(A @ Q - Q * lam)) <= 1e-13 * scale
+    assert np.max(np.abs(Q.T @ Q - np.eye(n))) <= 1e-12
+    assert np.max(np.abs(lam - np.linalg.eigvalsh(A))) <= 1e-12 * scale
+    assert np.sum(np.abs(lam) > 1e-10 * scale) == (min(rank, n) if rank else 0)
