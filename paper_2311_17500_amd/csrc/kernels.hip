@@ -1184,46 +1184,45 @@ __global__ void __launch_bounds__(64) k_dense_rows(const C* __restrict__ Ap, int
 // ---------------------------------------------------------------- arrowhead
 template <class S, class C>
 __global__ void __launch_bounds__(TPB) k_arrowhead(const S* __restrict__ r, S* __restrict__ y, const C* __restrict__ lam,
-                                                   const C* __restrict__ mu, const int* __restrict__ kind,
-                                                   const C* __restrict__ l, C sigma, C Cm, int Nt, int64_t Ns) {
+                                                   const C* __restrict__ mu, const C* __restrict__ l, C sigma, C Cm,
+                                                   int Nt, int np, int64_t Ns) {
   const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= Ns) return;
   const C s = lam[j];
   const int n = Nt - 1;
   C acc = C(0), den = Cm * sigma + s;
-  for (int a = 0; a < n;) {
-    if (kind[a] == 0) {
-      const C dl = Cm * mu[a];
-      const C inv = C(1) / (s * s + dl * dl);
-      const C ra = to_c(r[static_cast<int64_t>(a) * Ns + j], C(0));
-      const C rb = to_c(r[static_cast<int64_t>(a + 1) * Ns + j], C(0));
-      const C la = l[a], lb = l[a + 1];
-      acc += inv * (la * (s * ra - dl * rb) + lb * (dl * ra + s * rb));
-      den += Cm * Cm * s * (la * la + lb * lb) * inv;
-      a += 2;
-    } else {
-      const C ra = to_c(r[static_cast<int64_t>(a) * Ns + j], C(0));
-      acc += l[a] * ra / s;
-      den += Cm * Cm * l[a] * l[a] / s;
-      a += 1;
-    }
+  // the np 2x2 blocks come first, then 1x1 (zero-mode) blocks; the block
+  // loops are unrolled so that several rows' loads are in flight together
+#pragma unroll 4
+  for (int q = 0; q < np; ++q) {
+    const int a = 2 * q;
+    const C dl = Cm * mu[a];
+    const C inv = C(1) / (s * s + dl * dl);
+    const C ra = to_c(r[static_cast<int64_t>(a) * Ns + j], C(0));
+    const C rb = to_c(r[static_cast<int64_t>(a + 1) * Ns + j], C(0));
+    const C la = l[a], lb = l[a + 1];
+    acc += inv * (la * (s * ra - dl * rb) + lb * (dl * ra + s * rb));
+    den += Cm * Cm * s * (la * la + lb * lb) * inv;
+  }
+  for (int a = 2 * np; a < n; ++a) {
+    const C ra = to_c(r[static_cast<int64_t>(a) * Ns + j], C(0));
+    acc += l[a] * ra / s;
+    den += Cm * Cm * l[a] * l[a] / s;
   }
   const C yN = (to_c(r[static_cast<int64_t>(n) * Ns + j], C(0)) + Cm * acc) / den;
   y[static_cast<int64_t>(n) * Ns + j] = from_c<S>(yN);
-  for (int a = 0; a < n;) {
-    if (kind[a] == 0) {
-      const C dl = Cm * mu[a];
-      const C inv = C(1) / (s * s + dl * dl);
-      const C ta = to_c(r[static_cast<int64_t>(a) * Ns + j], C(0)) - Cm * l[a] * yN;
-      const C tb = to_c(r[static_cast<int64_t>(a + 1) * Ns + j], C(0)) - Cm * l[a + 1] * yN;
-      y[static_cast<int64_t>(a) * Ns + j] = from_c<S>(inv * (s * ta - dl * tb));
-      y[static_cast<int64_t>(a + 1) * Ns + j] = from_c<S>(inv * (dl * ta + s * tb));
-      a += 2;
-    } else {
-      y[static_cast<int64_t>(a) * Ns + j] = from_c<S>((to_c(r[static_cast<int64_t>(a) * Ns + j], C(0)) - Cm * l[a] * yN) / s);
-      a += 1;
-    }
+#pragma unroll 4
+  for (int q = 0; q < np; ++q) {
+    const int a = 2 * q;
+    const C dl = Cm * mu[a];
+    const C inv = C(1) / (s * s + dl * dl);
+    const C ta = to_c(r[static_cast<int64_t>(a) * Ns + j], C(0)) - Cm * l[a] * yN;
+    const C tb = to_c(r[static_cast<int64_t>(a + 1) * Ns + j], C(0)) - Cm * l[a + 1] * yN;
+    y[static_cast<int64_t>(a) * Ns + j] = from_c<S>(inv * (s * ta - dl * tb));
+    y[static_cast<int64_t>(a + 1) * Ns + j] = from_c<S>(inv * (dl * ta + s * tb));
   }
+  for (int a = 2 * np; a < n; ++a)
+    y[static_cast<int64_t>(a) * Ns + j] = from_c<S>((to_c(r[static_cast<int64_t>(a) * Ns + j], C(0)) - Cm * l[a] * yN) / s);
 }
 
 // ---------------------------------------------------------------- reductions
@@ -2060,10 +2059,10 @@ void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, i
 }
 
 template <class S, class C>
-void arrowhead(const S* r, S* y, const C* lam, const C* mu, const int* kind, const C* l, C sigma, C Cm, int Nt,
+void arrowhead(const S* r, S* y, const C* lam, const C* mu, int np, const C* l, C sigma, C Cm, int Nt,
                int64_t Ns, hipStream_t s) {
   ProfScope ps(K_ARROW, 5 + 16 * prec_code<S>(), s, 2.0 * Nt * Ns * sizeof(S));
-  hipLaunchKernelGGL((k_arrowhead<S, C>), dim3(grid_for(Ns)), dim3(TPB), 0, s, r, y, lam, mu, kind, l, sigma, Cm, Nt, Ns);
+  hipLaunchKernelGGL((k_arrowhead<S, C>), dim3(grid_for(Ns)), dim3(TPB), 0, s, r, y, lam, mu, l, sigma, Cm, Nt, np, Ns);
 }
 
 void kprof_enable(bool on) { prof().on = on; }
@@ -2259,11 +2258,11 @@ template void dense_mode<double, double>(const double*, int, int, const double*,
                                          hipStream_t);
 template void dense_mode<float, float>(const float*, int, int, const float*, float*, int64_t, int64_t, hipStream_t);
 template void dense_mode<bf16, float>(const float*, int, int, const bf16*, bf16*, int64_t, int64_t, hipStream_t);
-template void arrowhead<double, double>(const double*, double*, const double*, const double*, const int*,
+template void arrowhead<double, double>(const double*, double*, const double*, const double*, int,
                                         const double*, double, double, int, int64_t, hipStream_t);
-template void arrowhead<float, float>(const float*, float*, const float*, const float*, const int*, const float*,
+template void arrowhead<float, float>(const float*, float*, const float*, const float*, int, const float*,
                                       float, float, int, int64_t, hipStream_t);
-template void arrowhead<bf16, float>(const bf16*, bf16*, const float*, const float*, const int*, const float*, float,
+template void arrowhead<bf16, float>(const bf16*, bf16*, const float*, const float*, int, const float*, float,
                                      float, int, int64_t, hipStream_t);
 template void convert<double, float>(const double*, float*, int64_t, hipStream_t);
 template void multidot_partial<double>(const double*, int64_t, int, const double*, int64_t, double*, int, hipStream_t);

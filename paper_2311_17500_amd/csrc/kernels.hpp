@@ -107,9 +107,11 @@ int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, c
 template <class S, class C>
 void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, int64_t inner, hipStream_t s);
 
-// Arrowhead solve of the fast-diagonalization core, one spatial mode per thread.
+// Arrowhead solve of the fast-diagonalization core, one spatial mode per thread:
+// the first np time-mode pairs are 2x2 blocks (values mu), the remaining
+// N_t - 1 - 2 np modes 1x1 zero blocks, the last mode the arrow (l, sigma).
 template <class S, class C>
-void arrowhead(const S* r, S* y, const C* lam, const C* mu, const int* kind, const C* l, C sigma, C Cm,
+void arrowhead(const S* r, S* y, const C* lam, const C* mu, int np, const C* l, C sigma, C Cm,
                int Nt, int64_t Ns, hipStream_t s);
 
 // Deterministic reductions (two stages, fixed order).

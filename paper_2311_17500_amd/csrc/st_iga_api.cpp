@@ -74,6 +74,7 @@ struct st_iga_ctx {
   int n[3] = {1, 1, 1}, Q[3] = {1, 1, 1};
   int nt = 0, Nt = 0, nqt = 0, nelt = 0, nel[3] = {1, 1, 1};
   int NtP = 0;   // row stride of the low-rank time tables (N_t plus zero rows)
+  int fd_np = 0; // leading 2x2 blocks of the time FD (the rest are 1x1 zero blocks)
   int64_t Ns = 0, Qs = 0, nunk = 0, nfull = 0, Nels = 0;
   int chunk_el = 1;
   int64_t big_len = 0;
@@ -365,6 +366,11 @@ void host_setup(st_iga_ctx* c) {
   // FD time data on the X_t block
   std::vector<double> Wx = sub_rows(c->Wt_full, nt, 1, nt, 1, nt), Mx = sub_rows(c->Mt_full, nt, 1, nt, 1, nt);
   if (!time_fd(Wx, Mx, Nt, c->fd, err)) throw Fail{ST_IGA_EINVAL, err};
+  // the 2x2 blocks lead, 1x1 blocks follow (checked: the kernel relies on it)
+  c->fd_np = 0;
+  while (2 * c->fd_np + 1 < Nt - 1 && c->fd.kind[2 * c->fd_np] == 0 && c->fd.kind[2 * c->fd_np + 1] == 1) ++c->fd_np;
+  for (int i = 2 * c->fd_np; i < Nt - 1; ++i)
+    if (c->fd.kind[i] != 2) throw Fail{ST_IGA_EINVAL, "time fast diagonalization: unexpected block order"};
   c->Ut.h = dense_table(c->fd.U, Nt, Nt, false);
   c->UtT.h = dense_table(c->fd.U, Nt, Nt, true);
   auto pad = [](st_iga_ctx::Dense& D, const std::vector<double>& U, int n, bool transpose) {
@@ -899,7 +905,7 @@ void precond_impl(st_iga_ctx* c, const S* r, S* z, Bufs<S>& B, hipStream_t s) {
   const C* lam = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->lam_d) : reinterpret_cast<const C*>(c->lam_f);
   const C* mu = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->mu_d) : reinterpret_cast<const C*>(c->mu_f);
   const C* l = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->l_d) : reinterpret_cast<const C*>(c->l_f);
-  arrowhead<S, C>(b, a, lam, mu, c->kind_d, l, C(c->fd.sigma), C(c->P.Cm), Nt, Ns, s);
+  arrowhead<S, C>(b, a, lam, mu, c->fd_np, l, C(c->fd.sigma), C(c->P.Cm), Nt, Ns, s);
   // time backward: b = U_t a
   dense_mode<S, C>(dmat<C>(c->DUt), Nt, c->DUt.npad, a, b, 1, Ns, s);
   // spatial backward: z = (U_d .. U_1) b
