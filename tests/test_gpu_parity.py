@@ -211,3 +211,27 @@ def test_apply_nonuniform_knots(gpu_lib, torch):
     y = S.apply(to_dev(torch, x)).cpu().numpy()
     want = st.apply_J(x, st.lowrank_at_quad(LowRank(*fc)), st.lowrank_at_quad(LowRank(*ft)))
     assert rel(y, want) < 1e-12
+
+
+@pytest.mark.parametrize("reorth", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
+def test_krylov_gram_schmidt_modes(gpu_lib, torch, reorth, prec):
+    """Both Gram-Schmidt modes (second pass always, or only after heavy
+    cancellation) reach the requested true residual against the oracle's
+    assembled operator."""
+    import scipy.sparse.linalg as spla
+    from paper_2311_17500_amd.binding import FP64, MIXED_FP32
+    prob = SMALL[2][1]
+    S = solver_for(prob, reorth=reorth, prec={"fp64": FP64, "mixed_fp32": MIXED_FP32}[prec])
+    st = SpaceTime(prob)
+    u, w = W.smooth_state(prob, 9)
+    S.linearize(to_dev(torch, u), to_dev(torch, w))
+    lin = solver.linearize(st, u, w)
+    J = st.assemble_J(lin.coef_q, lin.theta_q)
+    b = W.random_vector(prob.unknowns, 15)
+    tol = 1e-11 if prec == "fp64" else 1e-8
+    x, it, rr = S.krylov(to_dev(torch, b), tol=tol)
+    x = x.cpu().numpy()
+    assert rr <= tol and it > 0
+    assert rel(J @ x, b) <= 1.05 * tol
+    assert rel(x, spla.splu(J.tocsc()).solve(b)) < 1e4 * tol
