@@ -71,15 +71,14 @@ def log(msg):
 
 
 def time_region(torch, S, u1, u2, w, steps, warmup, tol):
-    """Warm up, then time exactly `steps` steps between synchronizations."""
+    """Warm up, time exactly `steps` steps between synchronizations with the
+    kernel profiler off, then run the same steps again with the profiler on
+    for the per-kernel figures (HIP events around every launch)."""
     for _ in range(warmup):
         S.newton_step(u1, u2, w, True, tol)
         log("warmup step done")
     torch.cuda.synchronize()
-    S.profile(True)
-    S.profile_read(reset=True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record()
     its = []
@@ -92,9 +91,16 @@ def time_region(torch, S, u1, u2, w, steps, warmup, tol):
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / steps
+    S.profile(True)
+    S.profile_read(reset=True)
+    for _ in range(steps):
+        S.newton_step(u1, u2, w, True, tol)
+    torch.cuda.synchronize()
     prof = S.profile_read(reset=True)
     S.profile(False)
-    return ev0.elapsed_time(ev1) / steps, wall / steps * 1e3, its, rr, prof
+    log("profiled steps done")
+    return ms, wall / steps * 1e3, its, rr, prof
 
 
 def roofline(prof, steps):
