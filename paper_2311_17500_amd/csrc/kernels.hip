@@ -944,6 +944,20 @@ template <class C> struct Acc4;
 template <> struct Acc4<double> { typedef dx4 T; };
 template <> struct Acc4<float> { typedef fx4 T; };
 
+// Copy of the padded npad x npad matrix into LDS with 16-byte loads, several
+// in flight per thread (npad is a multiple of 16, the source 16-byte aligned).
+template <class C>
+__device__ __forceinline__ void stage_matrix(const C* __restrict__ Ap, C* As, int count) {
+  constexpr int V = 16 / sizeof(C);
+  typedef struct { C v[V]; } __attribute__((aligned(16))) Vec;
+  const Vec* src = reinterpret_cast<const Vec*>(Ap);
+  Vec* dst = reinterpret_cast<Vec*>(As);
+  const int nv = count / V;
+#pragma unroll 8
+  for (int t = threadIdx.x; t < nv; t += blockDim.x) dst[t] = src[t];
+  __syncthreads();
+}
+
 template <class S, class C, int NT, bool LDS_A>
 __global__ void __launch_bounds__(256) k_dense_mode(const C* __restrict__ Ap, int n, int npad,
                                                     const S* __restrict__ x, S* __restrict__ y, int64_t inner,
@@ -951,8 +965,7 @@ __global__ void __launch_bounds__(256) k_dense_mode(const C* __restrict__ Ap, in
   extern __shared__ char smem_raw[];
   C* As = reinterpret_cast<C*>(smem_raw);
   if (LDS_A) {
-    for (int t = threadIdx.x; t < npad * npad; t += blockDim.x) As[t] = Ap[t];
-    __syncthreads();
+    stage_matrix<C>(Ap, As, npad * npad);
   }
   const C* Asrc = LDS_A ? As : Ap;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -996,52 +1009,61 @@ __global__ void __launch_bounds__(256) k_dense_modeE(const C* __restrict__ Ap, i
                                                      int64_t ncols) {
   extern __shared__ char smem_raw[];
   C* As = reinterpret_cast<C*>(smem_raw);
-  if (LDS_A) {
-    for (int t = threadIdx.x; t < npad * npad; t += blockDim.x) As[t] = Ap[t];
-    __syncthreads();
-  }
+  if (LDS_A) stage_matrix<C>(Ap, As, npad * npad);
   const C* Asrc = LDS_A ? As : Ap;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
-  const int64_t c = (static_cast<int64_t>(blockIdx.x) * 4 + wv) * (16 * E) + E * r16;
-  const bool cv = c < ncols;
-  const int64_t o = cv ? c / inner : 0;
-  const int64_t kq = cv ? c - o * inner : 0;
-  const S* xb = x + o * static_cast<int64_t>(n) * inner + kq;
-  typedef typename Acc4<C>::T A4;
-  A4 acc[NT][E];
+  // persistent: the block walks groups of 4 waves' columns, staging A once
+  const int64_t ngroups = (ncols + 64 * E - 1) / (64 * E);
+  auto body = [&](int64_t grp) {
+    const int64_t c = (grp * 4 + wv) * (16 * E) + E * r16;
+    const bool cv = c < ncols;
+    const int64_t o = cv ? c / inner : 0;
+    const int64_t kq = cv ? c - o * inner : 0;
+    const S* xb = x + o * static_cast<int64_t>(n) * inner + kq;
+    typedef typename Acc4<C>::T A4;
+    A4 acc[NT][E];
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int e = 0; e < E; ++e) acc[t][e] = A4{0, 0, 0, 0};
-  for (int kk = 0; kk < ((n + 3) & ~3); kk += 4) {
-    const int j = kk + q4;
-    C b[E];
-    const bool ok = cv && j < n;
-    loadv<E, S, C>(xb + static_cast<int64_t>(ok ? j : 0) * inner, b);
+      for (int e = 0; e < E; ++e) acc[t][e] = A4{0, 0, 0, 0};
+    for (int kk = 0; kk < ((n + 3) & ~3); kk += 4) {
+      const int j = kk + q4;
+      C b[E];
+      const bool ok = cv && j < n;
+      loadv<E, S, C>(xb + static_cast<int64_t>(ok ? j : 0) * inner, b);
 #pragma unroll
-    for (int e = 0; e < E; ++e) b[e] = ok ? b[e] : C(0);
+      for (int e = 0; e < E; ++e) b[e] = ok ? b[e] : C(0);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const C a = Asrc[(t * 16 + r16) * npad + j];
+      for (int t = 0; t < NT; ++t) {
+        const C av = Asrc[(t * 16 + r16) * npad + j];
 #pragma unroll
-      for (int e = 0; e < E; ++e) acc[t][e] = mfma16x16x4(a, b[e], acc[t][e]);
-    }
-  }
-  if (!cv) return;
-  S* yb = y + o * static_cast<int64_t>(n) * inner + kq;
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = t * 16 + (std::is_same<C, double>::value ? q4 + 4 * v : 4 * q4 + v);
-      if (i < n) {
-        C r[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) r[e] = acc[t][e][v];
-        storev<E, S, C>(yb + static_cast<int64_t>(i) * inner, r);
+        for (int e = 0; e < E; ++e) acc[t][e] = mfma16x16x4(av, b[e], acc[t][e]);
       }
     }
+    if (cv) {
+      S* yb = y + o * static_cast<int64_t>(n) * inner + kq;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = t * 16 + (std::is_same<C, double>::value ? q4 + 4 * v : 4 * q4 + v);
+          if (i < n) {
+            C r[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) r[e] = acc[t][e][v];
+            storev<E, S, C>(yb + static_cast<int64_t>(i) * inner, r);
+          }
+        }
+    }
+  };
+  // with the matrix in LDS the block walks several groups (staging it once);
+  // otherwise each block owns exactly one group
+  if constexpr (LDS_A) {
+    for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) body(grp);
+  } else {
+    body(blockIdx.x);
+  }
 }
 
 // Variant for any inner extent: the (outer, inner) columns are flattened; a
@@ -1054,54 +1076,63 @@ __global__ void __launch_bounds__(256) k_dense_modeU(const C* __restrict__ Ap, i
                                                      int64_t ncols) {
   extern __shared__ char smem_raw[];
   C* As = reinterpret_cast<C*>(smem_raw);
-  if (LDS_A) {
-    for (int t = threadIdx.x; t < npad * npad; t += blockDim.x) As[t] = Ap[t];
-    __syncthreads();
-  }
+  if (LDS_A) stage_matrix<C>(Ap, As, npad * npad);
   const C* Asrc = LDS_A ? As : Ap;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
-  const int64_t base = (static_cast<int64_t>(blockIdx.x) * 4 + wv) * (16 * E) + r16;
-  int64_t off[E];
-  bool ok[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int64_t c = base + 16 * e;
-    ok[e] = c < ncols;
-    const int64_t cc = ok[e] ? c : 0;
-    const int64_t o = cc / inner;
-    off[e] = o * static_cast<int64_t>(n) * inner + (cc - o * inner);
-  }
-  typedef typename Acc4<C>::T A4;
-  A4 acc[NT][E];
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int e = 0; e < E; ++e) acc[t][e] = A4{0, 0, 0, 0};
   const int n4 = (n + 3) & ~3;
-  for (int kk = 0; kk < n4; kk += 4) {
-    const int j = kk + q4;
-    C b[E];
+  // persistent: the block walks groups of 4 waves' columns, staging A once
+  const int64_t ngroups = (ncols + 64 * E - 1) / (64 * E);
+  auto body = [&](int64_t grp) {
+    const int64_t base = (grp * 4 + wv) * (16 * E) + r16;
+    int64_t off[E];
+    bool ok[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) b[e] = (j < n && ok[e]) ? to_c(x[off[e] + static_cast<int64_t>(j) * inner], C(0)) : C(0);
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const C a = Asrc[(t * 16 + r16) * npad + j];
-#pragma unroll
-      for (int e = 0; e < E; ++e) acc[t][e] = mfma16x16x4(a, b[e], acc[t][e]);
+    for (int e = 0; e < E; ++e) {
+      const int64_t c = base + 16 * e;
+      ok[e] = c < ncols;
+      const int64_t cc = ok[e] ? c : 0;
+      const int64_t o = cc / inner;
+      off[e] = o * static_cast<int64_t>(n) * inner + (cc - o * inner);
     }
-  }
+    typedef typename Acc4<C>::T A4;
+    A4 acc[NT][E];
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = t * 16 + (std::is_same<C, double>::value ? q4 + 4 * v : 4 * q4 + v);
-      if (i < n) {
+      for (int e = 0; e < E; ++e) acc[t][e] = A4{0, 0, 0, 0};
+    for (int kk = 0; kk < n4; kk += 4) {
+      const int j = kk + q4;
+      C b[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e)
-          if (ok[e]) y[off[e] + static_cast<int64_t>(i) * inner] = from_c<S>(acc[t][e][v]);
+      for (int e = 0; e < E; ++e)
+        b[e] = (j < n && ok[e]) ? to_c(x[off[e] + static_cast<int64_t>(j) * inner], C(0)) : C(0);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const C av = Asrc[(t * 16 + r16) * npad + j];
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[t][e] = mfma16x16x4(av, b[e], acc[t][e]);
       }
     }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = t * 16 + (std::is_same<C, double>::value ? q4 + 4 * v : 4 * q4 + v);
+        if (i < n) {
+#pragma unroll
+          for (int e = 0; e < E; ++e)
+            if (ok[e]) y[off[e] + static_cast<int64_t>(i) * inner] = from_c<S>(acc[t][e][v]);
+        }
+      }
+  };
+  // with the matrix in LDS the block walks several groups (staging it once);
+  // otherwise each block owns exactly one group
+  if constexpr (LDS_A) {
+    for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) body(grp);
+  } else {
+    body(blockIdx.x);
+  }
 }
 
 // Variant for inner == 1 (the fastest axis): a one-wave block stages 16E
@@ -1977,7 +2008,8 @@ void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, i
   const unsigned grid = static_cast<unsigned>((ncols + 63) / 64);
   const int NT = npad / 16;
   const size_t abytes = static_cast<size_t>(npad) * npad * sizeof(C);
-  const bool lds = abytes <= 64 * 1024;
+  // the matrix goes to LDS up to 96 KB (gfx950 allows 160 KB per workgroup)
+  const bool lds = abytes <= 96 * 1024;
   ProfScope ps(K_DENSE, 4 + 16 * prec_code<S>(), s, 2.0 * ncols * n * sizeof(S), 2.0 * ncols * n * n);
   if (inner == 1 && NT <= 9) {
     // one wave per block; 4 column tiles (64 rows) unless the accumulators
@@ -2006,7 +2038,10 @@ void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, i
   };
   const int E = (NT <= ntmax4 && aligned(4)) ? 4 : (NT <= 9 && aligned(2)) ? 2 : 1;
   if (E > 1) {
-    const unsigned gridE = static_cast<unsigned>((ncols + 64 * E - 1) / (64 * E));
+    // persistent blocks (a few per CU, each staging the matrix once) when the
+    // matrix is staged in LDS; one group per block otherwise
+    const int64_t groupsE = (ncols + 64 * E - 1) / (64 * E);
+    const unsigned gridE = static_cast<unsigned>(lds ? std::min<int64_t>(groupsE, 2048) : groupsE);
 #define DME(nt, e)                                                                                              \
   case nt:                                                                                                      \
     if (lds) hipLaunchKernelGGL((k_dense_modeE<S, C, nt, e, true>), dim3(gridE), dim3(256), abytes, s, Ap, n, npad, x, y, inner, ncols); \
@@ -2027,8 +2062,8 @@ void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, i
   if (NT <= 9) {
     // any inner extent: tiles of 16 EU columns inside one outer index
     const int EU = (std::is_same<C, double>::value ? NT <= 4 : true) ? 4 : 2;
-    const int64_t tiles = (ncols + 16 * EU - 1) / (16 * EU);
-    const unsigned gridU = static_cast<unsigned>((tiles + 3) / 4);
+    const int64_t groups = (ncols + 64 * EU - 1) / (64 * EU);
+    const unsigned gridU = static_cast<unsigned>(lds ? std::min<int64_t>(groups, 2048) : groups);
 #define DMU(nt, e)                                                                                              \
   case nt:                                                                                                      \
     if (lds) hipLaunchKernelGGL((k_dense_modeU<S, C, nt, e, true>), dim3(gridU), dim3(256), abytes, s, Ap, n, npad, x, y, inner, ncols); \
