@@ -391,6 +391,11 @@ bool tau_at_quad(const Dir1D& T, std::vector<double>& tauq, std::vector<double>&
 // Jacobi sweeps).  Output as gen_eig_sym: lam ascending, eigenvectors in the
 // columns of the row-major Q.
 bool sym_eig(const std::vector<double>& A, int n, std::vector<double>& Q, std::vector<double>& lam, std::string& err) {
+  for (double v : A)
+    if (!std::isfinite(v)) {
+      err = "non-finite matrix entry";
+      return false;
+    }
   std::vector<double> Z(A), d(n, 0.0), e(n, 0.0);
   auto z = [&](int i, int j) -> double& { return Z[static_cast<size_t>(i) * n + j]; };
   // Householder: step i annihilates row i left of the subdiagonal
@@ -450,18 +455,22 @@ bool sym_eig(const std::vector<double>& A, int n, std::vector<double>& Q, std::v
     z(i, i) = 1.0;
     for (int j = 0; j <= l; ++j) z(j, i) = z(i, j) = 0.0;
   }
-  // QL with implicit shifts on (d, e)
+  // QL with implicit shifts on (d, e); an off-diagonal entry is negligible
+  // relative to its diagonal neighbours or to the matrix norm
   for (int i = 1; i < n; ++i) e[i - 1] = e[i];
   if (n > 0) e[n - 1] = 0.0;
+  double anorm = 0.0;
+  for (int i = 0; i < n; ++i) anorm = std::max(anorm, std::fabs(d[i]) + std::fabs(e[i]));
+  const double eps = std::numeric_limits<double>::epsilon();
   for (int l = 0; l < n; ++l) {
     int iter = 0, m;
     do {
       for (m = l; m < n - 1; ++m) {
         const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-        if (std::fabs(e[m]) <= std::numeric_limits<double>::epsilon() * dd) break;
+        if (std::fabs(e[m]) <= eps * dd || std::fabs(e[m]) <= eps * eps * anorm) break;
       }
       if (m != l) {
-        if (iter++ == 64) {
+        if (iter++ == 100) {
           err = "QL iteration did not converge";
           return false;
         }

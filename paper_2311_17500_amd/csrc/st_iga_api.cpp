@@ -1473,7 +1473,14 @@ int lowrank(st_iga_ctx* c, const double* C, double eps, std::vector<double>& U, 
   check_launch();
   std::vector<double> Q, lam;
   std::string err;
-  if (!sym_eig(G, m, Q, lam, err)) throw Fail{ST_IGA_EDEVICE, "Gram eigendecomposition: " + err};
+  if (!sym_eig(G, m, Q, lam, err)) {
+    // the QL iteration failing on finite data is not expected; Jacobi sweeps
+    // (slower, unconditionally convergent) are the fallback
+    if (err == "non-finite matrix entry") throw Fail{ST_IGA_ENOCONV, "Gram matrix of the low rank is not finite"};
+    std::vector<double> I(static_cast<size_t>(m) * m, 0.0);
+    for (int i = 0; i < m; ++i) I[static_cast<size_t>(i) * m + i] = 1.0;
+    if (!gen_eig_sym(G, I, m, Q, lam, err)) throw Fail{ST_IGA_EDEVICE, "Gram eigendecomposition: " + err};
+  }
   // descending order
   double tot = 0.0;
   for (double& v : lam) { v = std::max(v, 0.0); tot += v; }
