@@ -44,7 +44,8 @@ class Options(C.Structure):
                 ("outer", C.c_int32), ("alpha", C.c_double), ("theta_freeze", C.c_double),
                 ("tol_nonlin", C.c_double), ("tol_lin", C.c_double), ("inner_tol", C.c_double),
                 ("restart", C.c_int32), ("max_outer", C.c_int32), ("max_krylov", C.c_int32), ("prec", C.c_int32),
-                ("lin_forcing", C.c_double), ("coef_slab", C.c_int32), ("reorth", C.c_int32)]
+                ("lin_forcing", C.c_double), ("coef_slab", C.c_int32), ("reorth", C.c_int32),
+                ("graphs", C.c_int32)]
 
 
 LOG = 64

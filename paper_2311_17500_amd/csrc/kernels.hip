@@ -2101,6 +2101,7 @@ void arrowhead(const S* r, S* y, const C* lam, const C* mu, int np, const C* l, 
 }
 
 void kprof_enable(bool on) { prof().on = on; }
+bool kprof_enabled() { return prof().on; }
 void kprof_gather_class(int cls) { t_gather_cls = cls; }
 
 void kprof_read(int cls, double* ms, int64_t* launches, double* bytes, double* flops, int reset) {

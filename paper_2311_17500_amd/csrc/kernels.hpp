@@ -17,6 +17,7 @@ typedef __hip_bfloat16 bf16;
 enum KClass { K_GATHER = 0, K_TIME_MIX, K_ARROW, K_MULTIDOT, K_UPDATE, K_POINTWISE, K_MAX, K_BANDED, K_EXPAND,
               K_DENSE, K_COEF, K_NCLASS };
 void kprof_enable(bool on);
+bool kprof_enabled();
 // class recorded for gather launches until changed (K_GATHER by default)
 void kprof_gather_class(int cls);
 // Sum of launch durations (ms), launch count and algorithmic bytes of a class since the last reset;

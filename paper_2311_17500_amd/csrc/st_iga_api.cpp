@@ -133,6 +133,24 @@ struct st_iga_ctx {
   bf16 *t4b[4] = {}, *xb = nullptr, *yb = nullptr;
   void *Vb = nullptr, *Zb = nullptr;
   int64_t ldb = 0;   // column stride of Vb, Zb (elements)
+  // HIP graphs of the Arnoldi steps (preconditioner, operator, Gram-Schmidt),
+  // one per basis column and basis precision, valid for the ranks they were
+  // captured with
+  struct StepGraph {
+    hipGraphExec_t exec = nullptr;
+    int rth = -1, rc = -1;
+  };
+  std::vector<StepGraph> graphs[2];
+  // stream the Krylov operators launch on: the caller's stream, or the
+  // library's capture stream while a step graph is recorded (work cannot be
+  // captured on the null stream)
+  hipStream_t op_stream = nullptr, cap_stream = nullptr;
+  ~st_iga_ctx() {
+    for (auto& v : graphs)
+      for (auto& g : v)
+        if (g.exec) hipGraphExecDestroy(g.exec);
+    if (cap_stream) hipStreamDestroy(cap_stream);
+  }
   int last_refinements = 0;
   double *rk = nullptr, *xk = nullptr, *wk = nullptr, *dk = nullptr, *bk = nullptr;
   double *VT = nullptr, *sol_rhs = nullptr, *sol_dx = nullptr;
@@ -963,7 +981,7 @@ int fgmres(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const double* b, do
   double rn = bnorm;
   CK(hipMemcpyAsync(c->rk, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-  double hbuf[2 * 66 + 2];
+  double hbuf[258];
   while (it < maxit) {
     scale_to<T>(c->rk, 1.0 / rn, V, n, s);
     std::fill(g.begin(), g.end(), 0.0);
@@ -973,30 +991,84 @@ int fgmres(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const double* b, do
       T* Vj = V + static_cast<int64_t>(j) * ld;
       T* Zj = Z + static_cast<int64_t>(j) * ld;
       T* w = V + static_cast<int64_t>(j + 1) * ld;
-      Pc(Vj, Zj);
-      A(Zj, w);
-      // classical Gram-Schmidt; w is column j+1 of V, so the same multi-dot
-      // also gives ||w||^2 before the projection
-      multidot_partial<T>(V, ld, j + 2, w, n, c->part, nb, s);
-      finalize_sum(c->part, nb, j + 2, c->dsc, s);
-      update_norm_partial<T>(V, ld, j + 1, c->dsc, w, n, c->part, nb, s);
-      finalize_sum(c->part, nb, 1, c->dsc + 256, s);
-      CK(hipMemcpyAsync(hbuf, c->dsc, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
-      CK(hipMemcpyAsync(hbuf + 132, c->dsc + 256, sizeof(double), hipMemcpyDeviceToHost, s));
-      CK(hipStreamSynchronize(s));
-      check_launch();
-      for (int i = 0; i <= j; ++i) hbuf[66 + i] = 0.0;
-      // second pass when the first removed most of w (norm ratio below
-      // 1/sqrt(2)), or always when requested
-      if (c->opt.reorth != 0 || 2.0 * hbuf[132] < hbuf[j + 1]) {
-        multidot_partial<T>(V, ld, j + 1, w, n, c->part, nb, s);
-        finalize_sum(c->part, nb, j + 1, c->dsc + 128, s);
-        update_norm_partial<T>(V, ld, j + 1, c->dsc + 128, w, n, c->part, nb, s);
+      if (c->opt.reorth != 0 && c->opt.graphs != 0 && !kprof_enabled()) {
+        // classical Gram-Schmidt twice, the whole step replayed from a HIP
+        // graph (captured on first use of column j with the current ranks)
+        auto body = [&](hipStream_t ss) {
+          c->op_stream = ss;
+          Pc(Vj, Zj);
+          A(Zj, w);
+          c->op_stream = s;
+          multidot_partial<T>(V, ld, j + 1, w, n, c->part, nb, ss);
+          finalize_sum(c->part, nb, j + 1, c->dsc, ss);
+          update_norm_partial<T>(V, ld, j + 1, c->dsc, w, n, c->part, nb, ss);
+          multidot_partial<T>(V, ld, j + 1, w, n, c->part, nb, ss);
+          finalize_sum(c->part, nb, j + 1, c->dsc + 128, ss);
+          update_norm_partial<T>(V, ld, j + 1, c->dsc + 128, w, n, c->part, nb, ss);
+          finalize_sum(c->part, nb, 1, c->dsc + 256, ss);
+        };
+        auto& gv = c->graphs[std::is_same<T, double>::value ? 0 : 1];
+        if (gv.size() < static_cast<size_t>(m)) gv.resize(m);
+        auto& g = gv[j];
+        if (g.exec && (g.rth != c->Rth || g.rc != c->Rc)) {
+          CK(hipGraphExecDestroy(g.exec));
+          g.exec = nullptr;
+        }
+        if (!g.exec) {
+          if (!c->cap_stream) CK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+          const hipStream_t cs = c->cap_stream;
+          hipGraph_t graph = nullptr;
+          CK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+          try {
+            body(cs);
+          } catch (...) {
+            c->op_stream = s;
+            hipStreamEndCapture(cs, &graph);
+            if (graph) hipGraphDestroy(graph);
+            throw;
+          }
+          CK(hipStreamEndCapture(cs, &graph));
+          const hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+          hipGraphDestroy(graph);
+          if (ie != hipSuccess) {
+            g.exec = nullptr;
+            throw Fail{ST_IGA_EDEVICE, std::string("graph instantiation: ") + hipGetErrorString(ie)};
+          }
+          g.rth = c->Rth;
+          g.rc = c->Rc;
+        }
+        CK(hipGraphLaunch(g.exec, s));
+        CK(hipMemcpyAsync(hbuf, c->dsc, 257 * sizeof(double), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        check_launch();
+        for (int i = 0; i <= j; ++i) hbuf[66 + i] = hbuf[128 + i];
+        hbuf[132] = hbuf[256];
+      } else {
+        Pc(Vj, Zj);
+        A(Zj, w);
+        // classical Gram-Schmidt; w is column j+1 of V, so the same multi-dot
+        // also gives ||w||^2 before the projection
+        multidot_partial<T>(V, ld, j + 2, w, n, c->part, nb, s);
+        finalize_sum(c->part, nb, j + 2, c->dsc, s);
+        update_norm_partial<T>(V, ld, j + 1, c->dsc, w, n, c->part, nb, s);
         finalize_sum(c->part, nb, 1, c->dsc + 256, s);
-        CK(hipMemcpyAsync(hbuf + 66, c->dsc + 128, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(hbuf, c->dsc, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
         CK(hipMemcpyAsync(hbuf + 132, c->dsc + 256, sizeof(double), hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
         check_launch();
+        for (int i = 0; i <= j; ++i) hbuf[66 + i] = 0.0;
+        // second pass when the first removed most of w (norm ratio below
+        // 1/sqrt(2)), or always when requested
+        if (c->opt.reorth != 0 || 2.0 * hbuf[132] < hbuf[j + 1]) {
+          multidot_partial<T>(V, ld, j + 1, w, n, c->part, nb, s);
+          finalize_sum(c->part, nb, j + 1, c->dsc + 128, s);
+          update_norm_partial<T>(V, ld, j + 1, c->dsc + 128, w, n, c->part, nb, s);
+          finalize_sum(c->part, nb, 1, c->dsc + 256, s);
+          CK(hipMemcpyAsync(hbuf + 66, c->dsc + 128, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+          CK(hipMemcpyAsync(hbuf + 132, c->dsc + 256, sizeof(double), hipMemcpyDeviceToHost, s));
+          CK(hipStreamSynchronize(s));
+          check_launch();
+        }
       }
       ++it;
       for (int i = 0; i <= j; ++i) H[static_cast<size_t>(i) * m + j] = hbuf[i] + hbuf[66 + i];
@@ -1102,7 +1174,9 @@ void lowp_ops<bf16>(st_iga_ctx* c, Op& A, Op& Pc, hipStream_t s) {
 
 // Low-precision operators on FP32 buffers for the inner solves.
 void lowp_ops_f32(st_iga_ctx* c, OpT<float>& A, OpT<float>& Pc, hipStream_t s) {
-  A = [c, s](const float* x, float* y) {
+  c->op_stream = s;
+  A = [c](const float* x, float* y) {
+    const hipStream_t s = c->op_stream;
     Bufs<float> B;
     for (int k = 0; k < 4; ++k) B.t4[k] = c->t4f[k];
     B.big[0] = c->bigf[0];
@@ -1111,7 +1185,8 @@ void lowp_ops_f32(st_iga_ctx* c, OpT<float>& A, OpT<float>& Pc, hipStream_t s) {
     apply_impl<float, float>(c, x, y, c->Nt, 1, true, true, B, s);
   };
   if (c->opt.prec == ST_IGA_MIXED_FP32) {
-    Pc = [c, s](const float* r, float* z) {
+    Pc = [c](const float* r, float* z) {
+      const hipStream_t s = c->op_stream;
       Bufs<float> B;
       for (int k = 0; k < 4; ++k) B.t4[k] = c->t4f[k];
       B.big[0] = c->bigf[0];
@@ -1120,7 +1195,8 @@ void lowp_ops_f32(st_iga_ctx* c, OpT<float>& A, OpT<float>& Pc, hipStream_t s) {
       precond_impl<float, float>(c, r, z, B, s);
     };
   } else {
-    Pc = [c, s](const float* r, float* z) {
+    Pc = [c](const float* r, float* z) {
+      const hipStream_t s = c->op_stream;
       Bufs<bf16> B;
       for (int k = 0; k < 4; ++k) B.t4[k] = c->t4b[k];
       B.big[0] = B.big[1] = nullptr;
@@ -1144,8 +1220,9 @@ int krylov(st_iga_ctx* c, const double* b, double* x, double tol, double* relres
   }
   double est = 1.0;
   if (c->opt.prec == ST_IGA_FP64) {
-    OpT<double> A64 = [c, s](const double* xx, double* yy) { apply64(c, xx, yy, s); };
-    OpT<double> P64 = [c, s](const double* rr, double* zz) { precond64(c, rr, zz, s); };
+    c->op_stream = s;
+    OpT<double> A64 = [c](const double* xx, double* yy) { apply64(c, xx, yy, c->op_stream); };
+    OpT<double> P64 = [c](const double* rr, double* zz) { precond64(c, rr, zz, c->op_stream); };
     const int it = fgmres<double>(c, A64, P64, b, x, tol, c->opt.max_krylov, bnorm, &est,
                                   static_cast<double*>(c->Vb), static_cast<double*>(c->Zb), nullptr, c->wk, s);
     *relres = est;
@@ -1695,7 +1772,8 @@ void st_iga_default_options(st_iga_options* o) {
   o->prec = ST_IGA_FP64;
   o->lin_forcing = 0.0;
   o->coef_slab = 0;
-  o->reorth = 0;
+  o->reorth = 1;
+  o->graphs = 1;
 }
 
 size_t st_iga_workspace_bytes(const st_iga_problem* prob, const st_iga_options* opt) {

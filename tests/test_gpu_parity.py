@@ -235,3 +235,32 @@ def test_krylov_gram_schmidt_modes(gpu_lib, torch, reorth, prec):
     assert rr <= tol and it > 0
     assert rel(J @ x, b) <= 1.05 * tol
     assert rel(x, spla.splu(J.tocsc()).solve(b)) < 1e4 * tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
+def test_krylov_graph_replay(gpu_lib, torch, prec):
+    """Arnoldi steps replayed from HIP graphs give bit-identical solves to
+    eager launches, on every replay, with eager work and synchronizations in
+    between, and after a relinearization (graphs re-captured when the ranks
+    change)."""
+    from paper_2311_17500_amd.binding import FP64, MIXED_FP32
+    code = {"fp64": FP64, "mixed_fp32": MIXED_FP32}[prec]
+    prob = SMALL[2][1]
+    Sg = solver_for(prob, prec=code, graphs=1)
+    Se = solver_for(prob, prec=code, graphs=0)
+    tol = 1e-11 if prec == "fp64" else 1e-8
+    for seed in (10, 11):
+        u, w = W.smooth_state(prob, seed)
+        ud, wd = to_dev(torch, u), to_dev(torch, w)
+        Sg.linearize(ud, wd)
+        Se.linearize(ud, wd)
+        b = to_dev(torch, W.random_vector(prob.unknowns, seed + 20))
+        xe, ite, rre = Se.krylov(b, tol=tol)
+        xe = xe.cpu().numpy()
+        for rep in range(3):
+            xg, itg, rrg = Sg.krylov(b, tol=tol)
+            torch.cuda.synchronize()
+            assert itg == ite and rrg == rre
+            assert np.array_equal(xg.cpu().numpy(), xe)
+            Sg.apply(xg)                # eager work between the replays
+            torch.cuda.synchronize()
