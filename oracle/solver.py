@@ -69,7 +69,9 @@ def solve(st: SpaceTime, newton=True, alpha=None, eps_theta=0.1, eps_react=1e-2,
         r = st.residual(u, w, lin.theta_q)
         delta = -spla.splu(J.tocsc()).solve(r)
         u = u + alpha * st.full(delta)
-        dinf = float(np.max(np.abs(delta)))
+        # the stopping quantity is the change of the iterate, ||u^{k+1} - u^k||_inf
+        # (Section 4), i.e. the relaxed update
+        dinf = float(alpha * np.max(np.abs(delta)))
         log.deltas.append(dinf)
         log.ranks_theta.append(theta_lr.R if theta_lr is not None else 0)
         log.ranks_react.append(lin.coef_lr.R)

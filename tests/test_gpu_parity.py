@@ -264,3 +264,52 @@ def test_krylov_graph_replay(gpu_lib, torch, prec):
             assert np.array_equal(xg.cpu().numpy(), xe)
             Sg.apply(xg)                # eager work between the replays
             torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name,prob", [SMALL[1], SMALL[2]], ids=["2d_p3", "3d_p2"])
+def test_linearize_picard(gpu_lib, torch, name, prob):
+    """Picard linearization (reaction coefficient C_r of eq. (3.6)): ranks,
+    low-rank products and the operator against the oracle."""
+    S = solver_for(prob, outer=1, alpha=0.5)
+    st = SpaceTime(prob)
+    u, w = W.smooth_state(prob, 7)
+    S.linearize(to_dev(torch, u), to_dev(torch, w))
+    lin = solver.linearize(st, u, w, newton=False)
+    (gt, gc) = S.get_factors()
+    assert len(gt[1]) == lin.theta_lr.R and len(gc[1]) == lin.coef_lr.R
+    for g, o in ((gt, lin.theta_lr), (gc, lin.coef_lr)):
+        if o.R:
+            assert rel(lowrank_product(g), lowrank_product((o.U, o.s, o.V))) < 1e-11
+    x = W.random_vector(prob.unknowns, 21)
+    y = S.apply(to_dev(torch, x)).cpu().numpy()
+    assert rel(y, st.apply_J(x, lin.coef_q, lin.theta_q)) < 1e-11
+
+
+def test_full_nonlinear_solve_picard(gpu_lib):
+    """Whole outer loop in the Picard mode (C_r, relaxation 0.5) against the
+    oracle's Picard loop: same iteration count and solution."""
+    prob = SMALL[0][1]
+    S = solver_for(prob, outer=1, alpha=0.5, tol_nonlin=1e-11, tol_lin=1e-12, max_outer=200)
+    st = SpaceTime(prob)
+    u, w, rep = S.solve()
+    uo, wo, log = solver.solve(st, newton=False, tol=1e-11, max_outer=200)
+    assert rep.outer_iters == len(log.deltas)
+    assert rel(u.cpu().numpy(), uo) < 1e-10
+    assert rel(w.cpu().numpy(), wo) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["mixed_fp32", "mixed_bf16"])
+def test_full_nonlinear_solve_mixed(gpu_lib, prec):
+    """Whole outer loop with low-precision inner solves: the FP64 refinement
+    makes each linear solve meet tol_lin in FP64, so the solution matches the
+    oracle's FP64 loop to the nonlinear tolerance."""
+    from paper_2311_17500_amd.binding import MIXED_FP32, MIXED_BF16
+    prob = SMALL[2][1]
+    S = solver_for(prob, prec={"mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}[prec],
+                   tol_nonlin=1e-9, tol_lin=1e-10)
+    st = SpaceTime(prob)
+    u, w, rep = S.solve()
+    uo, wo, log = solver.solve(st, tol=1e-9)
+    assert abs(rep.outer_iters - len(log.deltas)) <= 1
+    assert rel(u.cpu().numpy(), uo) < 1e-8
+    assert rel(w.cpu().numpy(), wo) < 1e-8
