@@ -92,10 +92,16 @@ typedef struct {
   st_iga_precision prec;
   double lin_forcing;        /* > 0: outer iteration k solves to max(tol_lin, min(1e-2, lin_forcing*||delta_{k-1}||_inf)) */
   int32_t coef_slab;         /* time rows per slab of the low-rank operator terms (0: automatic) */
-  int32_t reorth;            /* Arnoldi Gram-Schmidt: 1 always two passes, 0 second pass only when the
-                                first removes more than 1 - 1/sqrt(2) of the norm */
-  int32_t graphs;            /* 1: with reorth = 1, replay each Arnoldi step (preconditioner, operator,
-                                Gram-Schmidt) from a HIP graph captured on first use; 0: eager launches */
+  int32_t reorth;            /* Arnoldi classical Gram-Schmidt (CGS): 2 two passes with the second pass
+                                of each basis vector merged into the next step (one multi-dot of V
+                                against the new and the previous vector, one fused update: V read
+                                twice per step; the last column of a restart cycle keeps one pass),
+                                1 two passes in the same step (V read four times), 0 second pass
+                                only when the first removes more than 1 - 1/sqrt(2) of the norm.
+                                Other values: ST_IGA_EINVAL */
+  int32_t graphs;            /* 1: with reorth = 1 or 2, replay each Arnoldi step (preconditioner,
+                                operator, Gram-Schmidt) from a HIP graph captured on first use;
+                                0: eager launches */
 } st_iga_options;
 
 #define ST_IGA_MAX_OUTER_LOG 64
@@ -115,7 +121,7 @@ typedef struct {
 /* Defaults: su=1, eps_theta=0.1, eps_react=1e-2, max_rank=48, outer=0,
  * alpha=1 (Newton), theta_freeze=1e-4, tol_nonlin=1e-10, tol_lin=1e-10,
  * inner_tol=1e-4, restart=30, max_outer=60, max_krylov=3000, prec=FP64, lin_forcing=0,
- * coef_slab=0, reorth=1, graphs=1. */
+ * coef_slab=0, reorth=2, graphs=1. */
 void st_iga_default_options(st_iga_options* opt);
 
 /* Bytes of device workspace st_iga_setup needs for this problem/options

@@ -1392,6 +1392,143 @@ __global__ void __launch_bounds__(TPB) k_multidot_v(const T* __restrict__ V, int
   }
 }
 
+// Two right-hand sides in one pass over V: partial sums of V_i . a and
+// V_i . b (i < k) into part[blk][2k] = {V_i . a ..., V_i . b ...}.  a and b
+// are kept in registers in their storage type; products and sums are FP64.
+template <class T, int VEC>
+__global__ void __launch_bounds__(TPB) k_multidot2(const T* __restrict__ V, int64_t ldv, int k,
+                                                   const T* __restrict__ a, const T* __restrict__ b, int64_t n,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[(TPB / 64) * 8];
+  constexpr int NV = RED_E / VEC;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * RED_CHUNK + static_cast<int64_t>(threadIdx.x) * VEC;
+  const int64_t nv = n - n % VEC;
+  const int64_t it = nv + threadIdx.x;   // tail element of this thread (block 0)
+  const bool tail = blockIdx.x == 0 && it < n;
+  const double at = tail ? static_cast<double>(a[it]) : 0.0;
+  const double bt = tail ? static_cast<double>(b[it]) : 0.0;
+  T ar[NV][VEC], br[NV][VEC];
+  int64_t ic[NV];
+#pragma unroll
+  for (int e = 0; e < NV; ++e) {
+    const int64_t i = base + static_cast<int64_t>(e) * TPB * VEC;
+    const bool ok = i < nv;
+    ic[e] = ok ? i : 0;
+    loadv<VEC, T, T>(a + ic[e], ar[e]);
+    loadv<VEC, T, T>(b + ic[e], br[e]);
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      if (!ok) ar[e][q] = T(0);
+      if (!ok) br[e][q] = T(0);
+    }
+  }
+  for (int jg = 0; jg < k; jg += 4) {
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int jv = min(jg + jj, k - 1);
+      const T* Vj = V + static_cast<int64_t>(jv) * ldv;
+#pragma unroll
+      for (int e = 0; e < NV; ++e) {
+        T t[VEC];
+        loadv<VEC, T, T>(Vj + ic[e], t);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+          const double tv = static_cast<double>(t[q]);
+          acc[jj] += tv * static_cast<double>(ar[e][q]);
+          acc[4 + jj] += tv * static_cast<double>(br[e][q]);
+        }
+      }
+      if (tail) {
+        const double tv = static_cast<double>(Vj[it]);
+        acc[jj] += tv * at;
+        acc[4 + jj] += tv * bt;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = wave_sum(acc[q]);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sh[wv * 8 + q] = acc[q];
+    __syncthreads();
+    if (threadIdx.x < 8) {
+      const int q = threadIdx.x;
+      const int col = jg + (q & 3);
+      if (col < k) {
+        double s = 0.0;
+        for (int w = 0; w < (TPB / 64); ++w) s += sh[w * 8 + q];
+        part[static_cast<int64_t>(blockIdx.x) * 2 * k + (q >= 4 ? k : 0) + col] = s;
+      }
+    }
+  }
+}
+
+// One Arnoldi step's Gram-Schmidt with the second pass of the previous
+// vector merged in.  Column j of V holds u (normalized, orthogonalized once),
+// column j + 1 holds w; dots = {V_i . u (i <= j), V_i . w (i <= j)} from
+// k_multidot2 over the j + 1 first columns.  With s_i = V_i . u, t_i = V_i . w
+// (i < j), alpha = sqrt(u.u - s.s) and h = (u.w - s.t) / alpha, it writes
+//   v = (u - sum_i s_i V_i) / alpha        into column j  (u made orthonormal),
+//   w' = w - sum_i t_i V_i - h v           into column j + 1,
+// the partial sums of |w'|^2 into part, and {alpha, h} into sc (block 0).
+// alpha is 0 when u.u - s.s <= 0 (u numerically in the span of V); v is then 0.
+template <class T>
+__global__ void __launch_bounds__(TPB) k_dcgs_update(T* __restrict__ V, int64_t ldv, int j,
+                                                     const double* __restrict__ dots, int64_t n,
+                                                     double* __restrict__ part, double* __restrict__ sc) {
+  __shared__ double sh[TPB / 64];
+  __shared__ double ss[64], ts[64], hs[3];
+  const int k = j + 1;
+  for (int i = threadIdx.x; i < j; i += TPB) {
+    ss[i] = dots[i];
+    ts[i] = dots[k + i];
+  }
+  if (threadIdx.x == 0) {
+    double s2 = 0.0, st = 0.0;
+    for (int i = 0; i < j; ++i) {
+      s2 += dots[i] * dots[i];
+      st += dots[i] * dots[k + i];
+    }
+    const double a2 = dots[j] - s2;
+    const double al = a2 > 0.0 ? sqrt(a2) : 0.0;
+    const double inv = al > 0.0 ? 1.0 / al : 0.0;
+    hs[0] = al;
+    hs[1] = (dots[k + j] - st) * inv;
+    hs[2] = inv;
+    if (blockIdx.x == 0) {
+      sc[0] = hs[0];
+      sc[1] = hs[1];
+    }
+  }
+  __syncthreads();
+  const double h = hs[1], inv = hs[2];
+  T* u = V + static_cast<int64_t>(j) * ldv;
+  T* w = u + ldv;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * RED_CHUNK + threadIdx.x;
+  double acc = 0.0;
+  for (int e = 0; e < RED_E; ++e) {
+    const int64_t i = base + static_cast<int64_t>(e) * TPB;
+    if (i >= n) break;
+    double pv = 0.0, pw = 0.0;
+    for (int l = 0; l < j; ++l) {
+      const double vl = static_cast<double>(V[static_cast<int64_t>(l) * ldv + i]);
+      pv += ss[l] * vl;
+      pw += ts[l] * vl;
+    }
+    const T vt = static_cast<T>((static_cast<double>(u[i]) - pv) * inv);
+    u[i] = vt;
+    const T wt = static_cast<T>(static_cast<double>(w[i]) - pw - h * static_cast<double>(vt));
+    w[i] = wt;
+    acc += static_cast<double>(wt) * static_cast<double>(wt);
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 __global__ void __launch_bounds__(TPB) k_finalize_sum(const double* __restrict__ part, int nb, int k,
                                                       double* __restrict__ out) {
   __shared__ double sh[TPB / 64];
@@ -2153,6 +2290,23 @@ void multidot_partial(const T* V, int64_t ldv, int k, const T* w, int64_t n, dou
   else
     hipLaunchKernelGGL((k_multidot<T>), dim3(nb), dim3(TPB), 0, s, V, ldv, k, w, n, part);
 }
+template <class T>
+void multidot2_partial(const T* V, int64_t ldv, int k, const T* a, const T* b, int64_t n, double* part, int nb,
+                       hipStream_t s) {
+  ProfScope ps(K_MULTIDOT, 6 + 16 * prec_code<T>(), s, (k + 2.0) * n * sizeof(T));
+  constexpr int VEC = 16 / sizeof(T);
+  if (ldv % VEC == 0 && reinterpret_cast<uintptr_t>(V) % 16 == 0 && reinterpret_cast<uintptr_t>(a) % 16 == 0 &&
+      reinterpret_cast<uintptr_t>(b) % 16 == 0)
+    hipLaunchKernelGGL((k_multidot2<T, VEC>), dim3(nb), dim3(TPB), 0, s, V, ldv, k, a, b, n, part);
+  else
+    hipLaunchKernelGGL((k_multidot2<T, 1>), dim3(nb), dim3(TPB), 0, s, V, ldv, k, a, b, n, part);
+}
+template <class T>
+void dcgs_update_partial(T* V, int64_t ldv, int j, const double* dots, int64_t n, double* part, int nb, double* sc,
+                         hipStream_t s) {
+  ProfScope ps(K_UPDATE, 7 + 16 * prec_code<T>(), s, (j + 4.0) * n * sizeof(T));
+  hipLaunchKernelGGL((k_dcgs_update<T>), dim3(nb), dim3(TPB), 0, s, V, ldv, j, dots, n, part, sc);
+}
 void finalize_sum(const double* part, int nb, int k, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize_sum, dim3(k), dim3(TPB), 0, s, part, nb, k, out);
 }
@@ -2303,6 +2457,14 @@ template void arrowhead<bf16, float>(const bf16*, bf16*, const float*, const flo
 template void convert<double, float>(const double*, float*, int64_t, hipStream_t);
 template void multidot_partial<double>(const double*, int64_t, int, const double*, int64_t, double*, int, hipStream_t);
 template void multidot_partial<float>(const float*, int64_t, int, const float*, int64_t, double*, int, hipStream_t);
+template void multidot2_partial<double>(const double*, int64_t, int, const double*, const double*, int64_t, double*,
+                                        int, hipStream_t);
+template void multidot2_partial<float>(const float*, int64_t, int, const float*, const float*, int64_t, double*, int,
+                                       hipStream_t);
+template void dcgs_update_partial<double>(double*, int64_t, int, const double*, int64_t, double*, int, double*,
+                                          hipStream_t);
+template void dcgs_update_partial<float>(float*, int64_t, int, const double*, int64_t, double*, int, double*,
+                                         hipStream_t);
 template void update_norm_partial<double>(const double*, int64_t, int, const double*, double*, int64_t, double*, int,
                                           hipStream_t);
 template void update_norm_partial<float>(const float*, int64_t, int, const double*, float*, int64_t, double*, int,

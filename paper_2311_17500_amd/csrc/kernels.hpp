@@ -121,6 +121,18 @@ int reduce_blocks(int64_t n);
 template <class T>
 void multidot_partial(const T* V, int64_t ldv, int k, const T* w, int64_t n, double* part, int nb, hipStream_t s);
 // out[j] = sum_b part[b*k + j]
+// Partial sums of V_i . a and V_i . b for i < k in one pass over V:
+// part[b][2k] = {V_i . a ..., V_i . b ...}; finalize_sum with 2k values.
+template <class T>
+void multidot2_partial(const T* V, int64_t ldv, int k, const T* a, const T* b, int64_t n, double* part, int nb,
+                       hipStream_t s);
+// Delayed second Gram-Schmidt pass (columns j, j + 1 of V hold u and w, dots
+// the 2(j + 1) finalized sums of multidot2 over the first j + 1 columns):
+// column j <- (u - sum_{i<j} s_i V_i) / alpha, column j + 1 <- w - sum_{i<j}
+// t_i V_i - h v, partial |w'|^2 into part, {alpha, h} into sc[0], sc[1].
+template <class T>
+void dcgs_update_partial(T* V, int64_t ldv, int j, const double* dots, int64_t n, double* part, int nb, double* sc,
+                         hipStream_t s);
 void finalize_sum(const double* part, int nb, int k, double* out, hipStream_t s);
 // w -= sum_j h[j] V_j ; part[b] = partial ||w||^2 (h read from device)
 template <class T>

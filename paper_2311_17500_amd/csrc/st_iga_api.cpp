@@ -140,7 +140,7 @@ struct st_iga_ctx {
     hipGraphExec_t exec = nullptr;
     int rth = -1, rc = -1;
   };
-  std::vector<StepGraph> graphs[2];
+  std::vector<StepGraph> graphs[4];   // [basis FP64, FP32] x [two passes, delayed second pass]
   // stream the Krylov operators launch on: the caller's stream, or the
   // library's capture stream while a step graph is recorded (work cannot be
   // captured on the null stream)
@@ -176,6 +176,7 @@ void validate(const st_iga_problem* P, const st_iga_options* O) {
   for (int l = 0; l <= P->d; ++l)
     if (!P->knots[l]) throw Fail{ST_IGA_EINVAL, "null knot vector"};
   if (O->restart < 1 || O->restart > 64) throw Fail{ST_IGA_EINVAL, "restart must be in 1..64"};
+  if (O->reorth < 0 || O->reorth > 2) throw Fail{ST_IGA_EINVAL, "reorth must be 0, 1 or 2"};
   if (O->max_rank < 1 || O->max_rank > 128) throw Fail{ST_IGA_EINVAL, "max_rank must be in 1..128"};
   if (O->prec < ST_IGA_FP64 || O->prec > ST_IGA_MIXED_BF16) throw Fail{ST_IGA_EINVAL, "bad precision"};
   if (O->su) {  // SU needs C^{p_t - 1} in time: interior time multiplicity 1
@@ -590,7 +591,8 @@ void plan(st_iga_ctx* c) {
     const int64_t nbf = (Qin + 63) / 64 * c->nelt * c->cf_nchunk + 1;
     c->nb_part = static_cast<int>(std::max<int64_t>(c->nb_part, nbf));
   }
-  c->part = a.get<double>(std::max<int64_t>(static_cast<int64_t>(c->nb_red) * 70, 2 * static_cast<int64_t>(c->nb_part)));
+  // reduction partials: up to 2 (m + 1) <= 130 sums per block (two-vector multi-dot)
+  c->part = a.get<double>(std::max<int64_t>(static_cast<int64_t>(c->nb_red) * 130, 2 * static_cast<int64_t>(c->nb_part)));
   c->dsc = a.get<double>(1024);
   c->gram_nb = static_cast<int>(std::min<int64_t>(512, (c->Ns + 31) / 32));
   c->gram = a.get<double>(static_cast<int64_t>(c->gram_nb) * c->Nt * c->Nt);
@@ -970,9 +972,169 @@ using OpT = std::function<void(const T*, T*)>;
 // (classical, twice) and the Givens rotations are carried out in FP64.  b, x
 // and the restart residual are FP64.  Returns the iteration count; *est is the
 // relative residual of the last restart check, computed with the same A.
+// Replays fn(stream) from the HIP graph cached for basis column j (captured
+// on the library's capture stream on first use, re-captured when the ranks
+// changed), or runs it eagerly on s when graphs are off or the per-launch
+// profiler is on.
+void run_step(st_iga_ctx* c, std::vector<st_iga_ctx::StepGraph>& gv, int j, int m,
+              const std::function<void(hipStream_t)>& fn, hipStream_t s) {
+  if (c->opt.graphs == 0 || kprof_enabled()) {
+    fn(s);
+    return;
+  }
+  if (gv.size() < static_cast<size_t>(m)) gv.resize(m);
+  auto& g = gv[j];
+  if (g.exec && (g.rth != c->Rth || g.rc != c->Rc)) {
+    CK(hipGraphExecDestroy(g.exec));
+    g.exec = nullptr;
+  }
+  if (!g.exec) {
+    if (!c->cap_stream) CK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    const hipStream_t cs = c->cap_stream;
+    hipGraph_t graph = nullptr;
+    CK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    try {
+      fn(cs);
+    } catch (...) {
+      c->op_stream = s;
+      hipStreamEndCapture(cs, &graph);
+      if (graph) hipGraphDestroy(graph);
+      throw;
+    }
+    CK(hipStreamEndCapture(cs, &graph));
+    const hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      g.exec = nullptr;
+      throw Fail{ST_IGA_EDEVICE, std::string("graph instantiation: ") + hipGetErrorString(ie)};
+    }
+    g.rth = c->Rth;
+    g.rc = c->Rc;
+  }
+  CK(hipGraphLaunch(g.exec, s));
+}
+
+// FGMRES(m) as below with the second classical Gram-Schmidt pass of each
+// basis vector delayed into the next Arnoldi step (one multi-dot over V for
+// both the new vector w and the previous vector u, one fused update): per
+// step the basis is read twice instead of four times.  Step j orthogonalizes
+// u = column j against columns < j (coefficients s, norm alpha), which
+// completes Hessenberg column j - 1 (entries += beta_{j-1} s, subdiagonal
+// beta_{j-1} alpha), and projects w on the finished columns <= j.  The last
+// column of a cycle keeps its once-orthogonalized subdiagonal.  The
+// preconditioner is applied to u before its second pass; flexible GMRES
+// only needs the pairs (z_j, A z_j) that the Hessenberg matrix describes.
+template <class T>
+int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const double* b, double* x, double rtol,
+                   int maxit, double bnorm, double* est, T* V, T* Z, T* xt, T* yt, hipStream_t s) {
+  const int64_t n = c->nunk, ld = c->ldb;
+  const int m = c->opt.restart;
+  const int nb = reduce_blocks(n);
+  fill(x, 0.0, n, s);
+  int it = 0;
+  double rn = bnorm;
+  CK(hipMemcpyAsync(c->rk, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // Hr: Hessenberg matrix as computed (unrotated); R: rotated copy
+  std::vector<double> Hr(static_cast<size_t>(m + 1) * m), R(static_cast<size_t>(m + 1) * m), cs(m), sn(m),
+      g(m + 1), gpre(m + 1), y(m);
+  double hb[260];
+  auto& gv = c->graphs[(std::is_same<T, double>::value ? 0 : 1) + 2];
+  // Givens rotation of column k from its raw entries and the rotations of the
+  // columns before it; g[k], g[k + 1] from gpre[k]
+  auto rotate = [&](int k) {
+    for (int i = 0; i <= k + 1; ++i) R[static_cast<size_t>(i) * m + k] = Hr[static_cast<size_t>(i) * m + k];
+    for (int i = 0; i < k; ++i) {
+      const double t1 = R[static_cast<size_t>(i) * m + k], t2 = R[static_cast<size_t>(i + 1) * m + k];
+      R[static_cast<size_t>(i) * m + k] = cs[i] * t1 + sn[i] * t2;
+      R[static_cast<size_t>(i + 1) * m + k] = -sn[i] * t1 + cs[i] * t2;
+    }
+    const double hkk = R[static_cast<size_t>(k) * m + k], hn = R[static_cast<size_t>(k + 1) * m + k];
+    const double den = std::hypot(hkk, hn);
+    cs[k] = den == 0.0 ? 1.0 : hkk / den;
+    sn[k] = den == 0.0 ? 0.0 : hn / den;
+    R[static_cast<size_t>(k) * m + k] = den;
+    g[k + 1] = -sn[k] * gpre[k];
+    g[k] = cs[k] * gpre[k];
+    gpre[k + 1] = g[k + 1];
+  };
+  while (it < maxit) {
+    scale_to<T>(c->rk, 1.0 / rn, V, n, s);
+    std::fill(Hr.begin(), Hr.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    gpre[0] = rn;
+    double beta_prev = 0.0;
+    int ncol = 0;
+    for (int j = 0; j < m && it < maxit; ++j) {
+      T* Vj = V + static_cast<int64_t>(j) * ld;
+      T* Zj = Z + static_cast<int64_t>(j) * ld;
+      T* w = V + static_cast<int64_t>(j + 1) * ld;
+      auto body = [&](hipStream_t ss) {
+        c->op_stream = ss;
+        Pc(Vj, Zj);
+        A(Zj, w);
+        c->op_stream = s;
+        multidot2_partial<T>(V, ld, j + 1, Vj, w, n, c->part, nb, ss);
+        finalize_sum(c->part, nb, 2 * (j + 1), c->dsc, ss);
+        dcgs_update_partial<T>(V, ld, j, c->dsc, n, c->part, nb, c->dsc + 128, ss);
+        finalize_sum(c->part, nb, 1, c->dsc + 256, ss);
+        scale_by_dev<T>(w, n, c->dsc + 256, ss);
+      };
+      run_step(c, gv, j, m, body, s);
+      CK(hipMemcpyAsync(hb, c->dsc, 257 * sizeof(double), hipMemcpyDeviceToHost, s));
+      CK(hipStreamSynchronize(s));
+      check_launch();
+      ++it;
+      const double alpha = hb[128], h = hb[129];
+      const double beta = std::sqrt(std::max(hb[256], 0.0));
+      if (!std::isfinite(alpha) || !std::isfinite(h) || !std::isfinite(beta))
+        throw Fail{ST_IGA_ENOCONV, "non-finite Arnoldi coefficients"};
+      if (j == 0) {
+        // u = r / |r| in the basis precision: |r| alpha is the exact start norm
+        if (alpha == 0.0) throw Fail{ST_IGA_ENOCONV, "zero Krylov start vector"};
+        gpre[0] = rn * alpha;
+      } else {
+        // u = beta_{j-1}^{-1} (A z_{j-1} - sum h v) = sum_{i<j} s_i v_i + alpha v_j
+        for (int i = 0; i < j; ++i) Hr[static_cast<size_t>(i) * m + j - 1] += beta_prev * hb[i];
+        Hr[static_cast<size_t>(j) * m + j - 1] = beta_prev * alpha;
+        rotate(j - 1);
+        ncol = j;
+        if (alpha == 0.0 || std::fabs(g[j]) <= rtol * bnorm) break;   // breakdown, or converged
+      }
+      for (int i = 0; i < j; ++i) Hr[static_cast<size_t>(i) * m + j] = hb[j + 1 + i];
+      Hr[static_cast<size_t>(j) * m + j] = h;
+      Hr[static_cast<size_t>(j + 1) * m + j] = beta;
+      rotate(j);   // provisional subdiagonal until step j + 1
+      ncol = j + 1;
+      beta_prev = beta;
+      if (std::fabs(g[j + 1]) <= rtol * bnorm || beta == 0.0) break;
+    }
+    const int jn = ncol;
+    for (int i = jn - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int k = i + 1; k < jn; ++k) t -= R[static_cast<size_t>(i) * m + k] * y[k];
+      y[i] = t / R[static_cast<size_t>(i) * m + i];
+    }
+    CK(hipMemcpyAsync(c->dsc + 512, y.data(), jn * sizeof(double), hipMemcpyHostToDevice, s));
+    combine<T>(Z, ld, jn, c->dsc + 512, x, n, s);
+    if (std::is_same<T, double>::value) {
+      A(reinterpret_cast<const T*>(x), yt);
+    } else {
+      convert<double, float>(x, reinterpret_cast<float*>(xt), n, s);
+      A(xt, yt);
+    }
+    sub_from<T>(b, yt, c->rk, n, s);
+    rn = dev_norm(c, c->rk, n, s);
+    *est = rn / bnorm;
+    if (rn <= rtol * bnorm) break;
+    if (!std::isfinite(rn)) throw Fail{ST_IGA_ENOCONV, "non-finite residual"};
+  }
+  return it;
+}
+
 template <class T>
 int fgmres(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const double* b, double* x, double rtol, int maxit,
            double bnorm, double* est, T* V, T* Z, T* xt, T* yt, hipStream_t s) {
+  if (c->opt.reorth == 2) return fgmres_delayed<T>(c, A, Pc, b, x, rtol, maxit, bnorm, est, V, Z, xt, yt, s);
   const int64_t n = c->nunk, ld = c->ldb;
   const int m = c->opt.restart;
   const int nb = reduce_blocks(n);
@@ -991,7 +1153,7 @@ int fgmres(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const double* b, do
       T* Vj = V + static_cast<int64_t>(j) * ld;
       T* Zj = Z + static_cast<int64_t>(j) * ld;
       T* w = V + static_cast<int64_t>(j + 1) * ld;
-      if (c->opt.reorth != 0 && c->opt.graphs != 0 && !kprof_enabled()) {
+      if (c->opt.reorth == 1 && c->opt.graphs != 0 && !kprof_enabled()) {
         // classical Gram-Schmidt twice, the whole step replayed from a HIP
         // graph (captured on first use of column j with the current ranks)
         auto body = [&](hipStream_t ss) {
@@ -1007,37 +1169,7 @@ int fgmres(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const double* b, do
           update_norm_partial<T>(V, ld, j + 1, c->dsc + 128, w, n, c->part, nb, ss);
           finalize_sum(c->part, nb, 1, c->dsc + 256, ss);
         };
-        auto& gv = c->graphs[std::is_same<T, double>::value ? 0 : 1];
-        if (gv.size() < static_cast<size_t>(m)) gv.resize(m);
-        auto& g = gv[j];
-        if (g.exec && (g.rth != c->Rth || g.rc != c->Rc)) {
-          CK(hipGraphExecDestroy(g.exec));
-          g.exec = nullptr;
-        }
-        if (!g.exec) {
-          if (!c->cap_stream) CK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-          const hipStream_t cs = c->cap_stream;
-          hipGraph_t graph = nullptr;
-          CK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-          try {
-            body(cs);
-          } catch (...) {
-            c->op_stream = s;
-            hipStreamEndCapture(cs, &graph);
-            if (graph) hipGraphDestroy(graph);
-            throw;
-          }
-          CK(hipStreamEndCapture(cs, &graph));
-          const hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
-          hipGraphDestroy(graph);
-          if (ie != hipSuccess) {
-            g.exec = nullptr;
-            throw Fail{ST_IGA_EDEVICE, std::string("graph instantiation: ") + hipGetErrorString(ie)};
-          }
-          g.rth = c->Rth;
-          g.rc = c->Rc;
-        }
-        CK(hipGraphLaunch(g.exec, s));
+        run_step(c, c->graphs[std::is_same<T, double>::value ? 0 : 1], j, m, body, s);
         CK(hipMemcpyAsync(hbuf, c->dsc, 257 * sizeof(double), hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
         check_launch();
@@ -1772,7 +1904,7 @@ void st_iga_default_options(st_iga_options* o) {
   o->prec = ST_IGA_FP64;
   o->lin_forcing = 0.0;
   o->coef_slab = 0;
-  o->reorth = 1;
+  o->reorth = 2;
   o->graphs = 1;
 }
 

@@ -213,12 +213,12 @@ def test_apply_nonuniform_knots(gpu_lib, torch):
     assert rel(y, want) < 1e-12
 
 
-@pytest.mark.parametrize("reorth", [0, 1])
+@pytest.mark.parametrize("reorth", [0, 1, 2])
 @pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
 def test_krylov_gram_schmidt_modes(gpu_lib, torch, reorth, prec):
-    """Both Gram-Schmidt modes (second pass always, or only after heavy
-    cancellation) reach the requested true residual against the oracle's
-    assembled operator."""
+    """Every Gram-Schmidt mode (second pass only after heavy cancellation,
+    always in the same step, or delayed into the next step) reaches the
+    requested true residual against the oracle's assembled operator."""
     import scipy.sparse.linalg as spla
     from paper_2311_17500_amd.binding import FP64, MIXED_FP32
     prob = SMALL[2][1]
@@ -237,8 +237,9 @@ def test_krylov_gram_schmidt_modes(gpu_lib, torch, reorth, prec):
     assert rel(x, spla.splu(J.tocsc()).solve(b)) < 1e4 * tol
 
 
+@pytest.mark.parametrize("reorth", [1, 2])
 @pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
-def test_krylov_graph_replay(gpu_lib, torch, prec):
+def test_krylov_graph_replay(gpu_lib, torch, prec, reorth):
     """Arnoldi steps replayed from HIP graphs give bit-identical solves to
     eager launches, on every replay, with eager work and synchronizations in
     between, and after a relinearization (graphs re-captured when the ranks
@@ -246,8 +247,8 @@ def test_krylov_graph_replay(gpu_lib, torch, prec):
     from paper_2311_17500_amd.binding import FP64, MIXED_FP32
     code = {"fp64": FP64, "mixed_fp32": MIXED_FP32}[prec]
     prob = SMALL[2][1]
-    Sg = solver_for(prob, prec=code, graphs=1)
-    Se = solver_for(prob, prec=code, graphs=0)
+    Sg = solver_for(prob, prec=code, graphs=1, reorth=reorth)
+    Se = solver_for(prob, prec=code, graphs=0, reorth=reorth)
     tol = 1e-11 if prec == "fp64" else 1e-8
     for seed in (10, 11):
         u, w = W.smooth_state(prob, seed)

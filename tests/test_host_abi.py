@@ -208,3 +208,14 @@ def test_host_symeig(lib, n, rank):
     assert np.max(np.abs(Q.T @ Q - np.eye(n))) <= 1e-12
     assert np.max(np.abs(lam - np.linalg.eigvalsh(A))) <= 1e-12 * scale
     assert np.sum(np.abs(lam) > 1e-10 * scale) == (min(rank, n) if rank else 0)
+
+
+def test_invalid_options_rejected(lib):
+    """Options outside their documented ranges give no workspace size (the
+    same validation rejects them in setup with EINVAL)."""
+    prob = W.tiny(2, 2, 4)
+    assert binding.workspace_bytes(prob) > 0
+    for kw in ({"reorth": 3}, {"reorth": -1}, {"restart": 0}, {"restart": 65}):
+        assert binding.workspace_bytes(prob, **kw) == 0, kw
+    for r in (0, 1, 2):
+        assert binding.workspace_bytes(prob, reorth=r) > 0
