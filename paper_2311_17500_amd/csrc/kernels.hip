@@ -1468,7 +1468,7 @@ __global__ void __launch_bounds__(TPB) k_multidot2(const T* __restrict__ V, int6
 }
 
 // One Arnoldi step's Gram-Schmidt with the second pass of the previous
-// vector merged in.  Column j of V holds u (normalized, orthogonalized once),
+// vector merged in.  Column j of V holds u (orthogonalized once),
 // column j + 1 holds w; dots = {V_i . u (i <= j), V_i . w (i <= j)} from
 // k_multidot2 over the j + 1 first columns.  With s_i = V_i . u, t_i = V_i . w
 // (i < j), alpha = sqrt(u.u - s.s) and h = (u.w - s.t) / alpha, it writes

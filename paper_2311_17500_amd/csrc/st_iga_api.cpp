@@ -1019,11 +1019,12 @@ void run_step(st_iga_ctx* c, std::vector<st_iga_ctx::StepGraph>& gv, int j, int 
 // both the new vector w and the previous vector u, one fused update): per
 // step the basis is read twice instead of four times.  Step j orthogonalizes
 // u = column j against columns < j (coefficients s, norm alpha), which
-// completes Hessenberg column j - 1 (entries += beta_{j-1} s, subdiagonal
-// beta_{j-1} alpha), and projects w on the finished columns <= j.  The last
-// column of a cycle keeps its once-orthogonalized subdiagonal.  The
-// preconditioner is applied to u before its second pass; flexible GMRES
-// only needs the pairs (z_j, A z_j) that the Hessenberg matrix describes.
+// completes Hessenberg column j - 1 (entries += s, subdiagonal alpha), and
+// projects w on the finished columns <= j.  The last column of a cycle
+// keeps its once-orthogonalized subdiagonal (the norm of the projected w).
+// u is neither normalized nor twice orthogonalized when the preconditioner
+// is applied to it; flexible GMRES only needs the pairs (z_j, A z_j) that the
+// Hessenberg matrix describes.
 template <class T>
 int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const double* b, double* x, double rtol,
                    int maxit, double bnorm, double* est, T* V, T* Z, T* xt, T* yt, hipStream_t s) {
@@ -1062,7 +1063,6 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
     std::fill(Hr.begin(), Hr.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
     gpre[0] = rn;
-    double beta_prev = 0.0;
     int ncol = 0;
     for (int j = 0; j < m && it < maxit; ++j) {
       T* Vj = V + static_cast<int64_t>(j) * ld;
@@ -1077,7 +1077,6 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
         finalize_sum(c->part, nb, 2 * (j + 1), c->dsc, ss);
         dcgs_update_partial<T>(V, ld, j, c->dsc, n, c->part, nb, c->dsc + 128, ss);
         finalize_sum(c->part, nb, 1, c->dsc + 256, ss);
-        scale_by_dev<T>(w, n, c->dsc + 256, ss);
       };
       run_step(c, gv, j, m, body, s);
       CK(hipMemcpyAsync(hb, c->dsc, 257 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1093,9 +1092,9 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
         if (alpha == 0.0) throw Fail{ST_IGA_ENOCONV, "zero Krylov start vector"};
         gpre[0] = rn * alpha;
       } else {
-        // u = beta_{j-1}^{-1} (A z_{j-1} - sum h v) = sum_{i<j} s_i v_i + alpha v_j
-        for (int i = 0; i < j; ++i) Hr[static_cast<size_t>(i) * m + j - 1] += beta_prev * hb[i];
-        Hr[static_cast<size_t>(j) * m + j - 1] = beta_prev * alpha;
+        // u = A z_{j-1} - sum_{i<j} h_{i,j-1} v_i = sum_{i<j} s_i v_i + alpha v_j
+        for (int i = 0; i < j; ++i) Hr[static_cast<size_t>(i) * m + j - 1] += hb[i];
+        Hr[static_cast<size_t>(j) * m + j - 1] = alpha;
         rotate(j - 1);
         ncol = j;
         if (alpha == 0.0 || std::fabs(g[j]) <= rtol * bnorm) break;   // breakdown, or converged
@@ -1105,7 +1104,6 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
       Hr[static_cast<size_t>(j + 1) * m + j] = beta;
       rotate(j);   // provisional subdiagonal until step j + 1
       ncol = j + 1;
-      beta_prev = beta;
       if (std::fabs(g[j + 1]) <= rtol * bnorm || beta == 0.0) break;
     }
     const int jn = ncol;
