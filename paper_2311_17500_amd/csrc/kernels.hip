@@ -944,17 +944,27 @@ template <class C> struct Acc4;
 template <> struct Acc4<double> { typedef dx4 T; };
 template <> struct Acc4<float> { typedef fx4 T; };
 
-// Copy of the padded npad x npad matrix into LDS with 16-byte loads, several
-// in flight per thread (npad is a multiple of 16, the source 16-byte aligned).
+// Row stride of the matrix in LDS: npad plus 16 bytes.  A wave reads rows
+// t*16 + l%16 at column j + l/16; with a stride of npad (a multiple of 16
+// elements) the 16 rows fall into one bank (16-way conflict), with 16 bytes
+// more every lane of an access hits its own bank, in FP32 and FP64.
 template <class C>
-__device__ __forceinline__ void stage_matrix(const C* __restrict__ Ap, C* As, int count) {
+__host__ __device__ constexpr int lds_stride(int npad) {
+  return npad + static_cast<int>(16 / sizeof(C));
+}
+// Copy of the padded npad x npad matrix into LDS (row stride lds_stride)
+// with 16-byte loads, several in flight per thread (npad is a multiple of
+// 16, the source 16-byte aligned).
+template <class C>
+__device__ __forceinline__ void stage_matrix(const C* __restrict__ Ap, C* As, int npad) {
   constexpr int V = 16 / sizeof(C);
   typedef struct { C v[V]; } __attribute__((aligned(16))) Vec;
   const Vec* src = reinterpret_cast<const Vec*>(Ap);
   Vec* dst = reinterpret_cast<Vec*>(As);
-  const int nv = count / V;
+  const int vpr = npad / V;          // 16-byte vectors per row
+  const int nv = npad * vpr;
 #pragma unroll 8
-  for (int t = threadIdx.x; t < nv; t += blockDim.x) dst[t] = src[t];
+  for (int t = threadIdx.x; t < nv; t += blockDim.x) dst[t + t / vpr] = src[t];
   __syncthreads();
 }
 
@@ -965,9 +975,10 @@ __global__ void __launch_bounds__(256) k_dense_mode(const C* __restrict__ Ap, in
   extern __shared__ char smem_raw[];
   C* As = reinterpret_cast<C*>(smem_raw);
   if (LDS_A) {
-    stage_matrix<C>(Ap, As, npad * npad);
+    stage_matrix<C>(Ap, As, npad);
   }
   const C* Asrc = LDS_A ? As : Ap;
+  const int lda = LDS_A ? lds_stride<C>(npad) : npad;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t c = (static_cast<int64_t>(blockIdx.x) * 4 + wv) * 16 + (lane & 15);
   const bool cv = c < ncols;
@@ -984,7 +995,7 @@ __global__ void __launch_bounds__(256) k_dense_mode(const C* __restrict__ Ap, in
     const C b = (cv && j < n) ? to_c(xb[static_cast<int64_t>(j) * inner], C(0)) : C(0);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const C a = Asrc[(t * 16 + r16) * npad + j];
+      const C a = Asrc[(t * 16 + r16) * lda + j];
       acc[t] = mfma16x16x4(a, b, acc[t]);
     }
   }
@@ -1009,8 +1020,9 @@ __global__ void __launch_bounds__(256) k_dense_modeE(const C* __restrict__ Ap, i
                                                      int64_t ncols) {
   extern __shared__ char smem_raw[];
   C* As = reinterpret_cast<C*>(smem_raw);
-  if (LDS_A) stage_matrix<C>(Ap, As, npad * npad);
+  if (LDS_A) stage_matrix<C>(Ap, As, npad);
   const C* Asrc = LDS_A ? As : Ap;
+  const int lda = LDS_A ? lds_stride<C>(npad) : npad;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
   // persistent: the block walks groups of 4 waves' columns, staging A once
@@ -1036,7 +1048,7 @@ __global__ void __launch_bounds__(256) k_dense_modeE(const C* __restrict__ Ap, i
       for (int e = 0; e < E; ++e) b[e] = ok ? b[e] : C(0);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const C av = Asrc[(t * 16 + r16) * npad + j];
+        const C av = Asrc[(t * 16 + r16) * lda + j];
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[t][e] = mfma16x16x4(av, b[e], acc[t][e]);
       }
@@ -1076,8 +1088,9 @@ __global__ void __launch_bounds__(256) k_dense_modeU(const C* __restrict__ Ap, i
                                                      int64_t ncols) {
   extern __shared__ char smem_raw[];
   C* As = reinterpret_cast<C*>(smem_raw);
-  if (LDS_A) stage_matrix<C>(Ap, As, npad * npad);
+  if (LDS_A) stage_matrix<C>(Ap, As, npad);
   const C* Asrc = LDS_A ? As : Ap;
+  const int lda = LDS_A ? lds_stride<C>(npad) : npad;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
   const int n4 = (n + 3) & ~3;
@@ -1109,7 +1122,7 @@ __global__ void __launch_bounds__(256) k_dense_modeU(const C* __restrict__ Ap, i
         b[e] = (j < n && ok[e]) ? to_c(x[off[e] + static_cast<int64_t>(j) * inner], C(0)) : C(0);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const C av = Asrc[(t * 16 + r16) * npad + j];
+        const C av = Asrc[(t * 16 + r16) * lda + j];
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[t][e] = mfma16x16x4(av, b[e], acc[t][e]);
       }
@@ -2144,7 +2157,7 @@ void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, i
   if (ncols == 0) return;
   const unsigned grid = static_cast<unsigned>((ncols + 63) / 64);
   const int NT = npad / 16;
-  const size_t abytes = static_cast<size_t>(npad) * npad * sizeof(C);
+  const size_t abytes = static_cast<size_t>(npad) * lds_stride<C>(npad) * sizeof(C);
   // the matrix goes to LDS up to 96 KB (gfx950 allows 160 KB per workgroup)
   const bool lds = abytes <= 96 * 1024;
   ProfScope ps(K_DENSE, 4 + 16 * prec_code<S>(), s, 2.0 * ncols * n * sizeof(S), 2.0 * ncols * n * n);
