@@ -224,7 +224,8 @@ st_iga_status st_iga_newton_step(st_iga_ctx* ctx, const double* u_in, double* u_
  * (0 scalar gather, 1 4-wide gather, 2 LDS row gather, 3 time mixing,
  * 4 MFMA dense mode product, 5 arrowhead, 6 multi-dot, 7 update+norm,
  * 8 pointwise ionic, 9 maxima, 10 column-sweep gather, 11 fused coefficient
- * terms, 12 fused quadrature pass, 13 dual-table sweep) in storage precision q (0 FP64, 1 FP32,
+ * terms, 12 fused quadrature pass, 13 dual-table sweep, 14 fused time transforms and arrowhead
+ * core of the preconditioner, counted in class 9) in storage precision q (0 FP64, 1 FP32,
  * 2 BF16; the reductions are FP64 only).  profile_read returns the summed duration (ms), the
  * launch count and the summed algorithmic bytes (each input and output array
  * counted once per launch), the summed algorithmic flops (recorded for the

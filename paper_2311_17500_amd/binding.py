@@ -309,7 +309,7 @@ class Solver:
                 "banded", "expand", "dense_fd", "coefficient"]
     FNAMES = ["gather_scalar", "gather_v4", "gather_rows", "time_mix", "dense_mode_mfma", "arrowhead",
               "multidot", "update_norm", "pointwise_ionic", "mode_max", "gather_sweep", "coef_fused",
-              "quad_fused", "sweep_dual"]
+              "quad_fused", "sweep_dual", "time_core"]
 
     def profile(self, on=True):
         self._chk(self.lib.st_iga_profile(self.ctx, int(on)))

@@ -1269,6 +1269,141 @@ __global__ void __launch_bounds__(TPB) k_arrowhead(const S* __restrict__ r, S* _
     y[static_cast<int64_t>(a) * Ns + j] = from_c<S>((to_c(r[static_cast<int64_t>(a) * Ns + j], C(0)) - Cm * l[a] * yN) / s);
 }
 
+// ---------------------------------------------------------------- time core
+// The time part of the FD preconditioner in one pass, FP32 arithmetic:
+// for every spatial mode j, b = U_t^T x[., j] (MFMA over the Nt time rows),
+// the arrowhead solve of k_arrowhead on b, and z[., j] = U_t y.  A block
+// stages both padded time matrices in LDS once (row stride lds_stride);
+// then every wave independently walks tiles of 16 consecutive spatial modes
+// (persistent, no block barriers).  The first product takes its operand
+// straight from registers (lane l loads rows 4 e + l/16 of column l%16: the
+// MFMA B layout of K step e), prefetched one tile ahead; its result goes to
+// the wave's LDS tile (row stride TC_W: at most 2-way bank conflicts for the
+// result writes, the arrowhead's row reads and the second product's operand
+// reads), where 4 lanes per column solve the arrowhead (lane & 3 takes every
+// 4th block of the sums, combined by lane shuffles); the second product is
+// stored from the accumulators.  Requires npad = 16 NT <= 64.
+constexpr int TC_W = 18, TC_WAVES = 8;
+// LDS accesses of one wave are performed in issue order; this only keeps the
+// compiler from moving LDS accesses across the point
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+template <class S, int NT>
+__global__ void __launch_bounds__(64 * TC_WAVES) k_time_core(const float* __restrict__ UtT, const float* __restrict__ Ut,
+                                                           int Nt, int npad, const S* __restrict__ x,
+                                                           S* __restrict__ z, int64_t Ns,
+                                                           const float* __restrict__ lam, const float* __restrict__ mu,
+                                                           int np, const float* __restrict__ l, float sigma, float Cm) {
+  extern __shared__ char smem_raw[];
+  const int lda = lds_stride<float>(npad);
+  float* A1 = reinterpret_cast<float*>(smem_raw);
+  float* A2 = A1 + npad * lda;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float* Tw = A2 + npad * lda + wv * npad * TC_W;
+  stage_matrix<float>(UtT, A1, npad);
+  stage_matrix<float>(Ut, A2, npad);
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int n4 = (Nt + 3) & ~3;
+  const int64_t ntiles = (Ns + 15) / 16;
+  const int64_t GW = static_cast<int64_t>(gridDim.x) * TC_WAVES;
+  constexpr int PE = 4 * NT;   // K steps of 4 rows (Nt <= npad = 16 NT)
+  float pre[PE];
+  auto fetch = [&](int64_t tile) {
+    const int64_t j = tile * 16 + r16;
+#pragma unroll
+    for (int e = 0; e < PE; ++e) {
+      const int t = 4 * e + q4;
+      pre[e] = (t < Nt && j < Ns) ? to_c(x[static_cast<int64_t>(t) * Ns + j], 0.f) : 0.f;
+    }
+  };
+  typedef typename Acc4<float>::T A4;
+  int64_t tile = static_cast<int64_t>(blockIdx.x) * TC_WAVES + wv;
+  if (tile < ntiles) fetch(tile);
+  for (; tile < ntiles; tile += GW) {
+    const int64_t j0 = tile * 16;
+    float b0[PE];
+#pragma unroll
+    for (int e = 0; e < PE; ++e) b0[e] = pre[e];
+    if (tile + GW < ntiles) fetch(tile + GW);
+    A4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = A4{0, 0, 0, 0};
+    // b = U_t^T x (rows >= Nt of U_t^T are zero)
+#pragma unroll
+    for (int e = 0; e < PE; ++e) {
+      if (4 * e >= Nt) break;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = mfma16x16x4(A1[(t * 16 + r16) * lda + 4 * e + q4], b0[e], acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Tw[(t * 16 + 4 * q4 + v) * TC_W + r16] = acc[t][v];
+    wave_lds_sync();
+    {
+      const int cc = lane >> 2, part = lane & 3;
+      const int64_t j = j0 + cc;
+      const float s = j < Ns ? lam[j] : 1.f;
+      const int nA = Nt - 1;
+      float sa = 0.f, sd = 0.f;
+      for (int q = part; q < np; q += 4) {
+        const int a = 2 * q;
+        const float dl = Cm * mu[a];
+        const float inv = 1.f / (s * s + dl * dl);
+        const float ra = Tw[a * TC_W + cc], rb = Tw[(a + 1) * TC_W + cc];
+        const float la = l[a], lb = l[a + 1];
+        sa += inv * (la * (s * ra - dl * rb) + lb * (dl * ra + s * rb));
+        sd += Cm * Cm * s * (la * la + lb * lb) * inv;
+      }
+      for (int a = 2 * np + part; a < nA; a += 4) {
+        const float ra = Tw[a * TC_W + cc];
+        sa += l[a] * ra / s;
+        sd += Cm * Cm * l[a] * l[a] / s;
+      }
+      sa += __shfl_xor(sa, 1, 64);
+      sa += __shfl_xor(sa, 2, 64);
+      sd += __shfl_xor(sd, 1, 64);
+      sd += __shfl_xor(sd, 2, 64);
+      // the 4 lanes of a column read r_N (one instruction) before any writes y_N
+      const float yN = (Tw[nA * TC_W + cc] + Cm * sa) / (Cm * sigma + s + sd);
+      for (int q = part; q < np; q += 4) {
+        const int a = 2 * q;
+        const float dl = Cm * mu[a];
+        const float inv = 1.f / (s * s + dl * dl);
+        const float ta = Tw[a * TC_W + cc] - Cm * l[a] * yN;
+        const float tb = Tw[(a + 1) * TC_W + cc] - Cm * l[a + 1] * yN;
+        Tw[a * TC_W + cc] = inv * (s * ta - dl * tb);
+        Tw[(a + 1) * TC_W + cc] = inv * (dl * ta + s * tb);
+      }
+      for (int a = 2 * np + part; a < nA; a += 4) Tw[a * TC_W + cc] = (Tw[a * TC_W + cc] - Cm * l[a] * yN) / s;
+      if (part == 0) Tw[nA * TC_W + cc] = yN;
+    }
+    wave_lds_sync();
+    // z = U_t y (rows >= Nt of the tile hold zeros of the first product)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = A4{0, 0, 0, 0};
+    for (int kk = 0; kk < n4; kk += 4) {
+      const float b = Tw[(kk + q4) * TC_W + r16];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = mfma16x16x4(A2[(t * 16 + r16) * lda + kk + q4], b, acc[t]);
+    }
+    wave_lds_sync();   // the tile's reads are issued before the next tile's writes
+    const int64_t j = j0 + r16;
+    if (j < Ns) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = t * 16 + 4 * q4 + v;
+          if (row < Nt) z[static_cast<int64_t>(row) * Ns + j] = from_c<S>(acc[t][v]);
+        }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- reductions
 constexpr int RED_E = 16;                 // elements per thread
 constexpr int64_t RED_CHUNK = static_cast<int64_t>(TPB) * RED_E;
@@ -2292,6 +2427,29 @@ bool kprof_record(int64_t i, int* fn, double* ms, double* bytes, double* flops) 
   return true;
 }
 
+template <class S>
+bool time_core(const float* UtT, const float* Ut, int Nt, int npad, const S* x, S* z, int64_t Ns, const float* lam,
+               const float* mu, int np, const float* l, float sigma, float Cm, hipStream_t s) {
+  if (npad < 16 || npad > 64 || npad % 16 != 0 || Nt < 2 || Nt > npad || 2 * np > Nt - 1) return false;
+  if (Ns <= 0) return true;
+  const size_t lds = (2 * static_cast<size_t>(npad) * lds_stride<float>(npad) +
+                      static_cast<size_t>(TC_WAVES) * npad * TC_W) * sizeof(float);
+  // two blocks of TC_WAVES waves per CU (LDS bound) on 256 CUs
+  const int64_t ntiles = (Ns + 15) / 16;
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>((ntiles + TC_WAVES - 1) / TC_WAVES, 512));
+  ProfScope ps(K_DENSE, 14 + 16 * prec_code<S>(), s, 2.0 * Nt * Ns * sizeof(S) + Ns * sizeof(float),
+               4.0 * Nt * Nt * Ns + 12.0 * Nt * Ns);
+#define TCK(nt) hipLaunchKernelGGL((k_time_core<S, nt>), dim3(grid), dim3(64 * TC_WAVES), lds, s, UtT, Ut, Nt, npad, x, z, Ns, lam, mu, np, l, sigma, Cm)
+  switch (npad / 16) {
+    case 1: TCK(1); break;
+    case 2: TCK(2); break;
+    case 3: TCK(3); break;
+    default: TCK(4); break;
+  }
+#undef TCK
+  return true;
+}
+
 int reduce_blocks(int64_t n) { return static_cast<int>((n + RED_CHUNK - 1) / RED_CHUNK); }
 
 template <class T>
@@ -2470,6 +2628,10 @@ template void arrowhead<bf16, float>(const bf16*, bf16*, const float*, const flo
 template void convert<double, float>(const double*, float*, int64_t, hipStream_t);
 template void multidot_partial<double>(const double*, int64_t, int, const double*, int64_t, double*, int, hipStream_t);
 template void multidot_partial<float>(const float*, int64_t, int, const float*, int64_t, double*, int, hipStream_t);
+template bool time_core<float>(const float*, const float*, int, int, const float*, float*, int64_t, const float*,
+                               const float*, int, const float*, float, float, hipStream_t);
+template bool time_core<bf16>(const float*, const float*, int, int, const bf16*, bf16*, int64_t, const float*,
+                              const float*, int, const float*, float, float, hipStream_t);
 template void multidot2_partial<double>(const double*, int64_t, int, const double*, const double*, int64_t, double*,
                                         int, hipStream_t);
 template void multidot2_partial<float>(const float*, int64_t, int, const float*, const float*, int64_t, double*, int,

@@ -116,6 +116,15 @@ void arrowhead(const S* r, S* y, const C* lam, const C* mu, int np, const C* l, 
                int Nt, int64_t Ns, hipStream_t s);
 
 // Deterministic reductions (two stages, fixed order).
+// Time part of the FD preconditioner in one pass (FP32 arithmetic): z[., j]
+// = U_t core_j^{-1} U_t^T x[., j] for every spatial mode j < Ns, with the
+// arrowhead core of arrowhead() (same lam, mu, l, np, sigma, Cm).  UtT, Ut:
+// padded npad x npad FP32 matrices; x, z: [Nt][Ns].  Returns false (nothing
+// launched) unless npad is 16, 32, 48 or 64 and Nt <= npad.
+template <class S>
+bool time_core(const float* UtT, const float* Ut, int Nt, int npad, const S* x, S* z, int64_t Ns, const float* lam,
+               const float* mu, int np, const float* l, float sigma, float Cm, hipStream_t s);
+
 int reduce_blocks(int64_t n);
 // part[b*k + j] = partial of <V_j, w> over block b; V_j = V + j*ldv (T: basis storage, FP64 accumulation)
 template <class T>

@@ -919,15 +919,24 @@ void precond_impl(st_iga_ctx* c, const S* r, S* z, Bufs<S>& B, hipStream_t s) {
   S *a = B.t4[0], *b = B.t4[1], *e = B.t4[2];
   // spatial forward transforms: a = (U_d^T .. U_1^T) r
   dense_spatial<S, C>(c, UT, r, Nt, b, e, a, s);
-  // time forward: b = U_t^T a
-  dense_mode<S, C>(dmat<C>(c->DUtT), Nt, c->DUtT.npad, a, b, 1, Ns, s);
-  // arrowhead core
   const C* lam = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->lam_d) : reinterpret_cast<const C*>(c->lam_f);
   const C* mu = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->mu_d) : reinterpret_cast<const C*>(c->mu_f);
   const C* l = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->l_d) : reinterpret_cast<const C*>(c->l_f);
-  arrowhead<S, C>(b, a, lam, mu, c->fd_np, l, C(c->fd.sigma), C(c->P.Cm), Nt, Ns, s);
-  // time backward: b = U_t a
-  dense_mode<S, C>(dmat<C>(c->DUt), Nt, c->DUt.npad, a, b, 1, Ns, s);
+  bool fused = false;
+  if constexpr (std::is_same<C, float>::value) {
+    // FP32: time transforms and arrowhead in one pass, b = U_t core^{-1} U_t^T a
+    fused = c->DUtT.npad == c->DUt.npad &&
+            time_core<S>(dmat<C>(c->DUtT), dmat<C>(c->DUt), Nt, c->DUtT.npad, a, b, Ns, lam, mu, c->fd_np, l,
+                         static_cast<float>(c->fd.sigma), static_cast<float>(c->P.Cm), s);
+  }
+  if (!fused) {
+    // time forward: b = U_t^T a
+    dense_mode<S, C>(dmat<C>(c->DUtT), Nt, c->DUtT.npad, a, b, 1, Ns, s);
+    // arrowhead core
+    arrowhead<S, C>(b, a, lam, mu, c->fd_np, l, C(c->fd.sigma), C(c->P.Cm), Nt, Ns, s);
+    // time backward: b = U_t a
+    dense_mode<S, C>(dmat<C>(c->DUt), Nt, c->DUt.npad, a, b, 1, Ns, s);
+  }
   // spatial backward: z = (U_d .. U_1) b
   dense_spatial<S, C>(c, U, b, Nt, a, e, z, s);
 }
