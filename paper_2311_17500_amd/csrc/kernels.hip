@@ -1620,10 +1620,13 @@ __global__ void __launch_bounds__(TPB) k_multidot2(const T* __restrict__ V, int6
 // column j + 1 holds w; dots = {V_i . u (i <= j), V_i . w (i <= j)} from
 // k_multidot2 over the j + 1 first columns.  With s_i = V_i . u, t_i = V_i . w
 // (i < j), alpha = sqrt(u.u - s.s) and h = (u.w - s.t) / alpha, it writes
-//   v = (u - sum_i s_i V_i) / alpha        into column j  (u made orthonormal),
-//   w' = w - sum_i t_i V_i - h v           into column j + 1,
+//   v = (u - sum_i s_i V_i) / alpha          into column j  (u made orthonormal),
+//   w' = (w - sum_i t_i V_i - h v) / alpha   into column j + 1,
 // the partial sums of |w'|^2 into part, and {alpha, h} into sc (block 0).
-// alpha is 0 when u.u - s.s <= 0 (u numerically in the span of V); v is then 0.
+// The division of w' by alpha keeps the basis vectors of order one: w scales
+// with u, and u with the previous w', so unscaled norms would multiply along
+// a restart cycle.  alpha is 0 when u.u - s.s <= 0 (u numerically in the
+// span of V); v and w' are then 0.
 template <class T>
 __global__ void __launch_bounds__(TPB) k_dcgs_update(T* __restrict__ V, int64_t ldv, int j,
                                                      const double* __restrict__ dots, int64_t n,
@@ -1669,7 +1672,7 @@ __global__ void __launch_bounds__(TPB) k_dcgs_update(T* __restrict__ V, int64_t 
     }
     const T vt = static_cast<T>((static_cast<double>(u[i]) - pv) * inv);
     u[i] = vt;
-    const T wt = static_cast<T>(static_cast<double>(w[i]) - pw - h * static_cast<double>(vt));
+    const T wt = static_cast<T>((static_cast<double>(w[i]) - pw - h * static_cast<double>(vt)) * inv);
     w[i] = wt;
     acc += static_cast<double>(wt) * static_cast<double>(wt);
   }

@@ -137,8 +137,8 @@ void multidot2_partial(const T* V, int64_t ldv, int k, const T* a, const T* b, i
                        hipStream_t s);
 // Delayed second Gram-Schmidt pass (columns j, j + 1 of V hold u and w, dots
 // the 2(j + 1) finalized sums of multidot2 over the first j + 1 columns):
-// column j <- (u - sum_{i<j} s_i V_i) / alpha, column j + 1 <- w - sum_{i<j}
-// t_i V_i - h v, partial |w'|^2 into part, {alpha, h} into sc[0], sc[1].
+// column j <- (u - sum_{i<j} s_i V_i) / alpha, column j + 1 <- (w - sum_{i<j}
+// t_i V_i - h v) / alpha, partial |w'|^2 into part, {alpha, h} into sc[0], sc[1].
 template <class T>
 void dcgs_update_partial(T* V, int64_t ldv, int j, const double* dots, int64_t n, double* part, int nb, double* sc,
                          hipStream_t s);

@@ -1028,11 +1028,12 @@ void run_step(st_iga_ctx* c, std::vector<st_iga_ctx::StepGraph>& gv, int j, int 
 // both the new vector w and the previous vector u, one fused update): per
 // step the basis is read twice instead of four times.  Step j orthogonalizes
 // u = column j against columns < j (coefficients s, norm alpha), which
-// completes Hessenberg column j - 1 (entries += s, subdiagonal alpha), and
-// projects w on the finished columns <= j.  The last column of a cycle
-// keeps its once-orthogonalized subdiagonal (the norm of the projected w).
-// u is neither normalized nor twice orthogonalized when the preconditioner
-// is applied to it; flexible GMRES only needs the pairs (z_j, A z_j) that the
+// completes Hessenberg column j - 1 (u is stored divided by alpha_{j-1}:
+// entries += alpha_{j-1} s, subdiagonal alpha_{j-1} alpha), and projects w
+// on the finished columns <= j.  The last column of a cycle keeps its
+// once-orthogonalized subdiagonal (the norm of the projected w).  u is
+// neither normalized nor twice orthogonalized when the preconditioner is
+// applied to it; flexible GMRES only needs the pairs (z_j, A z_j) that the
 // Hessenberg matrix describes.
 template <class T>
 int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const double* b, double* x, double rtol,
@@ -1073,6 +1074,7 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
     std::fill(g.begin(), g.end(), 0.0);
     gpre[0] = rn;
     int ncol = 0;
+    double alpha_prev = 1.0;
     for (int j = 0; j < m && it < maxit; ++j) {
       T* Vj = V + static_cast<int64_t>(j) * ld;
       T* Zj = Z + static_cast<int64_t>(j) * ld;
@@ -1093,7 +1095,8 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
       check_launch();
       ++it;
       const double alpha = hb[128], h = hb[129];
-      const double beta = std::sqrt(std::max(hb[256], 0.0));
+      // the stored next vector is the projected w divided by alpha
+      const double beta = alpha * std::sqrt(std::max(hb[256], 0.0));
       if (!std::isfinite(alpha) || !std::isfinite(h) || !std::isfinite(beta))
         throw Fail{ST_IGA_ENOCONV, "non-finite Arnoldi coefficients"};
       if (j == 0) {
@@ -1101,9 +1104,10 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
         if (alpha == 0.0) throw Fail{ST_IGA_ENOCONV, "zero Krylov start vector"};
         gpre[0] = rn * alpha;
       } else {
-        // u = A z_{j-1} - sum_{i<j} h_{i,j-1} v_i = sum_{i<j} s_i v_i + alpha v_j
-        for (int i = 0; i < j; ++i) Hr[static_cast<size_t>(i) * m + j - 1] += hb[i];
-        Hr[static_cast<size_t>(j) * m + j - 1] = alpha;
+        // u = (A z_{j-1} - sum_{i<j} h_{i,j-1} v_i) / alpha_{j-1}
+        //   = sum_{i<j} s_i v_i + alpha v_j
+        for (int i = 0; i < j; ++i) Hr[static_cast<size_t>(i) * m + j - 1] += alpha_prev * hb[i];
+        Hr[static_cast<size_t>(j) * m + j - 1] = alpha_prev * alpha;
         rotate(j - 1);
         ncol = j;
         if (alpha == 0.0 || std::fabs(g[j]) <= rtol * bnorm) break;   // breakdown, or converged
@@ -1113,6 +1117,7 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
       Hr[static_cast<size_t>(j + 1) * m + j] = beta;
       rotate(j);   // provisional subdiagonal until step j + 1
       ncol = j + 1;
+      alpha_prev = alpha;
       if (std::fabs(g[j + 1]) <= rtol * bnorm || beta == 0.0) break;
     }
     const int jn = ncol;

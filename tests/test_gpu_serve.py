@@ -42,3 +42,16 @@ def test_served_matches_oracle(gpu_lib):
         uo, wo, log = osolver.solve(SpaceTime(prob), tol=1e-10)
         assert r.status == "ok"
         assert np.linalg.norm(r.u - uo) / np.linalg.norm(uo) < 1e-8
+
+
+def test_stream_prefix_completes(gpu_lib):
+    """The first 128 requests of the seeded serving stream (2D, up to 130
+    time layers, several hundred Krylov iterations per request) all converge
+    with the default Arnoldi options: long restart cycles keep the basis
+    vectors of order one."""
+    from paper_2311_17500_amd.binding import MIXED_FP32
+    from paper_2311_17500_amd.serve import Server
+    reqs = W.serve_stream(512, 0)[:128]
+    recs = Server(slots=8, prec=MIXED_FP32, tol_lin=1e-8, tol_nonlin=1e-8, lin_forcing=0.1).run(reqs)
+    bad = [(i, r.status) for i, r in enumerate(recs) if r.status != "ok"]
+    assert not bad, bad[:5]
