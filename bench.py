@@ -26,7 +26,10 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12          # bytes/s, MI355X HBM3E
 PEAK_FP64 = 78.6e12        # flop/s, FP64 vector and dense MFMA
-PEAK_FP32 = 157.3e12       # flop/s, FP32 vector and dense MFMA
+PEAK_FP32 = 157.3e12       # flop/s, FP32 dense MFMA (and the published FP32 vector figure)
+# FP32 vector arithmetic without packed FP32 instructions (the kernels are
+# built without them): 256 CUs x 64 lanes x 2 flop per FMA x 2.4 GHz
+PEAK_FP32_VALU = 256 * 64 * 2 * 2.4e9
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -118,8 +121,9 @@ def roofline(prof, steps):
     hbm_frac = dom_by / sec / PEAK_HBM
     comp_frac, comp_peak, comp_bound = 0.0, None, None
     if dom_fl > 0:
-        comp_peak = PEAK_FP64 if f64 else PEAK_FP32
-        comp_bound = "mfma" if name.startswith("dense_mode_mfma") else "alu"
+        mfma = name.startswith("dense_mode_mfma") or name.startswith("time_core")
+        comp_peak = PEAK_FP64 if f64 else (PEAK_FP32 if mfma else PEAK_FP32_VALU)
+        comp_bound = "mfma" if mfma else "alu"
         comp_frac = dom_fl / sec / comp_peak
     traffic = None
     try:
@@ -137,6 +141,8 @@ def roofline(prof, steps):
         roof = {"kernel": name, "bound": "hbm", "achieved": dom_by / sec / 1e9, "peak": PEAK_HBM / 1e9,
                 "unit": "GB/s", "frac": hbm_frac}
     roof.update({"traffic": traffic, "hbm_frac": hbm_frac, "compute_frac": comp_frac if comp_bound else None,
+                 "compute_frac_vs_published_peak": (dom_fl / sec / (PEAK_FP64 if f64 else PEAK_FP32)
+                                                    if comp_bound else None),
                  "avg_launch_ms": dom_ms / dom_n, "launches": dom_n, "alg_bytes_per_launch": dom_by / dom_n,
                  "alg_flops_per_launch": dom_fl / dom_n,
                  "kernels": {k[3:]: {"ms_per_step": v[0] / steps, "launches_per_step": v[1] / steps,
