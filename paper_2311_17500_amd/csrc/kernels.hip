@@ -625,7 +625,9 @@ __device__ __forceinline__ bool coef_block(int nslab, int64_t ncb, int nchunk, i
   return true;
 }
 
-template <class S, class C, int P, int KP, int TS, int RM>
+// IX: element index type (uint32_t when every index of Z, out and Psi fits,
+// which keeps the per-layer offsets in 32-bit registers; else int64_t).
+template <class S, class C, int P, int KP, int TS, int RM, class IX>
 __global__ void __launch_bounds__(256) k_coef_fused(const C* __restrict__ T, const S* __restrict__ Psi, int r0, int R,
                                                     int Nt, int t0, int t1, const S* __restrict__ Z, int n_in,
                                                     int in_base, const C* __restrict__ Bl,
@@ -643,6 +645,10 @@ __global__ void __launch_bounds__(256) k_coef_fused(const C* __restrict__ T, con
   const int d0 = chunks[4 * ch + 2], d1 = chunks[4 * ch + 3];
   const int nrow = min(TS, t1 - ta);
   const int64_t lay = static_cast<int64_t>(nd) * Qin;
+  const IX layI = static_cast<IX>(lay), QinI = static_cast<IX>(Qin), QsI = static_cast<IX>(Qs);
+  const S* Zc = Z + c;
+  S* oc = out + c;
+  const S* Pc = Psi + c;
   const int jb = ta + 1 - P - in_base;   // input layer of window slot 0
   C zr[KP][NL], yr[KP][TS];
   int f = efirst[e0];
@@ -653,7 +659,7 @@ __global__ void __launch_bounds__(256) k_coef_fused(const C* __restrict__ T, con
     for (int l = 0; l < NL; ++l) {
       const int j = jb + l;
       zr[k][l] = (static_cast<unsigned>(j) < static_cast<unsigned>(n_in) && dof < nd)
-                     ? to_c(Z[j * lay + static_cast<int64_t>(dof) * Qin + c], C(0))
+                     ? to_c(Zc[static_cast<IX>(j) * layI + static_cast<IX>(dof) * QinI], C(0))
                      : C(0);
     }
 #pragma unroll
@@ -663,10 +669,10 @@ __global__ void __launch_bounds__(256) k_coef_fused(const C* __restrict__ T, con
     const int fn = efirst[e];
     for (; f < fn; ++f) {
       if (f >= d0 && f < d1) {
-        S* o = out + static_cast<int64_t>(ta - t0) * lay + static_cast<int64_t>(f) * Qin + c;
+        S* o = oc + (static_cast<IX>(ta - t0) * layI + static_cast<IX>(f) * QinI);
 #pragma unroll
         for (int t = 0; t < TS; ++t)
-          if (t < nrow) o[t * lay] = from_c<S>(yr[0][t]);
+          if (t < nrow) o[static_cast<IX>(t) * layI] = from_c<S>(yr[0][t]);
       }
 #pragma unroll
       for (int k = 0; k < KP - 1; ++k) {
@@ -680,7 +686,7 @@ __global__ void __launch_bounds__(256) k_coef_fused(const C* __restrict__ T, con
       for (int l = 0; l < NL; ++l) {
         const int j = jb + l;
         zr[KP - 1][l] = (static_cast<unsigned>(j) < static_cast<unsigned>(n_in) && dof < nd)
-                            ? to_c(Z[j * lay + static_cast<int64_t>(dof) * Qin + c], C(0))
+                            ? to_c(Zc[static_cast<IX>(j) * layI + static_cast<IX>(dof) * QinI], C(0))
                             : C(0);
       }
 #pragma unroll
@@ -690,12 +696,12 @@ __global__ void __launch_bounds__(256) k_coef_fused(const C* __restrict__ T, con
     // their latency is paid once per element instead of once per rank
     C pv[KP][RM > 0 ? RM : 1];
     if constexpr (RM > 0) {
-      const S* pe = Psi + static_cast<int64_t>(r0) * Qs + static_cast<int64_t>(e) * KP * Qin + c;
+      const S* pe = Pc + (static_cast<IX>(r0) * QsI + static_cast<IX>(e * KP) * QinI);
 #pragma unroll
       for (int g = 0; g < KP; ++g)
 #pragma unroll
         for (int r = 0; r < RM; ++r)
-          pv[g][r] = (r < R) ? to_c(pe[static_cast<int64_t>(r) * Qs + static_cast<int64_t>(g) * Qin], C(0)) : C(0);
+          pv[g][r] = (r < R) ? to_c(pe[static_cast<IX>(r) * QsI + static_cast<IX>(g) * QinI], C(0)) : C(0);
     }
 #pragma unroll
     for (int g = 0; g < KP; ++g) {
@@ -730,8 +736,8 @@ __global__ void __launch_bounds__(256) k_coef_fused(const C* __restrict__ T, con
         for (int r = 0; r < RM; ++r)
           if (r < R) mix(r, pv[g][r]);
       } else {
-        const S* ps = Psi + static_cast<int64_t>(r0) * Qs + static_cast<int64_t>(qd) * Qin + c;
-        for (int r = 0; r < R; ++r) mix(r, to_c(ps[static_cast<int64_t>(r) * Qs], C(0)));
+        const S* ps = Pc + (static_cast<IX>(r0) * QsI + static_cast<IX>(qd) * QinI);
+        for (int r = 0; r < R; ++r) mix(r, to_c(ps[static_cast<IX>(r) * QsI], C(0)));
       }
 #pragma unroll
       for (int k = 0; k < KP; ++k)
@@ -743,10 +749,10 @@ __global__ void __launch_bounds__(256) k_coef_fused(const C* __restrict__ T, con
   for (int k = 0; k < KP; ++k) {
     const int dof = f + k;
     if (dof >= d0 && dof < d1 && dof < nd) {
-      S* o = out + static_cast<int64_t>(ta - t0) * lay + static_cast<int64_t>(dof) * Qin + c;
+      S* o = oc + (static_cast<IX>(ta - t0) * layI + static_cast<IX>(dof) * QinI);
 #pragma unroll
       for (int t = 0; t < TS; ++t)
-        if (t < nrow) o[t * lay] = from_c<S>(yr[k][t]);
+        if (t < nrow) o[static_cast<IX>(t) * layI] = from_c<S>(yr[k][t]);
     }
   }
 }
@@ -2256,6 +2262,10 @@ bool coef_fused(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1
   // algorithmic flops per output row and Gauss point: the time mixing
   // (2 R (2 p_t + 2)) plus the expansion and projection along the axis (4 (p_s + 1))
   const double fl = rows * static_cast<double>(Qs) * (2.0 * R * (2 * pt + 2) + 4.0 * (ps + 1));
+  // 32-bit element indices when every index of Z, out and Psi fits
+  const double lim = 4294967295.0;
+  const bool i32 = static_cast<double>(n_in) * nd * Qin < lim && static_cast<double>(t1 - t0 + TS) * nd * Qin < lim &&
+                   static_cast<double>(r1) * Qs < lim;
   ProfScope pr(K_COEF, 11 + 16 * prec_code<S>(), s,
                (static_cast<double>(n_in) * nd * Qin + rows * nd * Qin + static_cast<double>(R) * Qs) * sizeof(S), fl);
 #define CF(P_, K_)                                                                                                \
@@ -2267,8 +2277,9 @@ bool coef_fused(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1
         done_ = true;                                                                                             \
       }                                                                                                           \
     }                                                                                                             \
-    if (!done_ && R <= 4) hipLaunchKernelGGL((k_coef_fused<S, C, P_, K_, TS, 4>), g, dim3(TPB), 0, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, Bl, efirst, chunks, nd, Qin, out, Qs, nslab, ncb, nchunk); \
-    else if (!done_) hipLaunchKernelGGL((k_coef_fused<S, C, P_, K_, TS, 0>), g, dim3(TPB), 0, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, Bl, efirst, chunks, nd, Qin, out, Qs, nslab, ncb, nchunk); \
+    if (!done_ && R <= 4 && i32) hipLaunchKernelGGL((k_coef_fused<S, C, P_, K_, TS, 4, uint32_t>), g, dim3(TPB), 0, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, Bl, efirst, chunks, nd, Qin, out, Qs, nslab, ncb, nchunk); \
+    else if (!done_ && R <= 4) hipLaunchKernelGGL((k_coef_fused<S, C, P_, K_, TS, 4, int64_t>), g, dim3(TPB), 0, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, Bl, efirst, chunks, nd, Qin, out, Qs, nslab, ncb, nchunk); \
+    else if (!done_) hipLaunchKernelGGL((k_coef_fused<S, C, P_, K_, TS, 0, int64_t>), g, dim3(TPB), 0, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, Bl, efirst, chunks, nd, Qin, out, Qs, nslab, ncb, nchunk); \
   } while (0)
 #define CFP(P_)                 \
   switch (ps) {                 \
