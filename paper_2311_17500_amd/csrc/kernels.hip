@@ -500,7 +500,7 @@ __global__ void __launch_bounds__(TPB) k_sweep_dual(const int* __restrict__ c0, 
 // block; the block then loops over groups of RB consecutive input rows (one
 // contiguous span, staged with coalesced 16-byte loads when aligned),
 // produces the RB output rows from LDS and writes them contiguously.
-template <class S, class C>
+template <class S, class C, int WT>
 __global__ void __launch_bounds__(TPB) k_gather_rows(const int* __restrict__ col, const C* __restrict__ coef, int W,
                                                      int n_out, const S* __restrict__ x, S* __restrict__ y, int n_in,
                                                      int in_base, C alpha, C beta, int64_t nrows, int RB) {
@@ -519,6 +519,7 @@ __global__ void __launch_bounds__(TPB) k_gather_rows(const int* __restrict__ col
   }
   constexpr int V = 16 / sizeof(S);
   typedef struct { S v[V]; } __attribute__((aligned(16))) Vec;
+  const int dq = TPB / n_out, dr = TPB - dq * n_out;
   for (int64_t r0 = static_cast<int64_t>(blockIdx.x) * RB; r0 < nrows; r0 += static_cast<int64_t>(gridDim.x) * RB) {
     const int rb = static_cast<int>(min(static_cast<int64_t>(RB), nrows - r0));
     const S* xb = x + r0 * n_in;
@@ -533,15 +534,27 @@ __global__ void __launch_bounds__(TPB) k_gather_rows(const int* __restrict__ col
     for (int t = nv * V + threadIdx.x; t < span; t += TPB) xs[t] = xb[t];
     __syncthreads();
     S* yb = y + r0 * n_out;
-    const int tot = rb * n_out;
-    for (int t = threadIdx.x; t < tot; t += TPB) {
-      const int r = t / n_out, i = t - r * n_out;
+    // output (row r, entry i) of flat index t, stepped by TPB without divisions
+    int r = threadIdx.x / n_out, i = threadIdx.x - (threadIdx.x / n_out) * n_out;
+    for (; r < rb;) {
       const S* xr = xs + r * n_in;
       C acc = C(0);
-      for (int w = 0; w < W; ++w) acc += cs[w * n_out + i] * to_c(xr[is[w * n_out + i]], C(0));
+      if constexpr (WT > 0) {
+#pragma unroll
+        for (int w = 0; w < WT; ++w) acc += cs[w * n_out + i] * to_c(xr[is[w * n_out + i]], C(0));
+      } else {
+        for (int w = 0; w < W; ++w) acc += cs[w * n_out + i] * to_c(xr[is[w * n_out + i]], C(0));
+      }
+      const int t = r * n_out + i;
       C v = alpha * acc;
       if (beta != C(0)) v += beta * to_c(yb[t], C(0));
       yb[t] = from_c<S>(v);
+      r += dq;
+      i += dr;
+      if (i >= n_out) {
+        i -= n_out;
+        ++r;
+      }
     }
   }
 }
@@ -2157,8 +2170,17 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
     if (sh <= 64 * 1024) {
       ProfScope ps(t_gather_cls, 2 + 16 * prec_code<Ti>(), s, gbytes);
       const int64_t blocks = std::min<int64_t>(groups, 2048);
-      hipLaunchKernelGGL((k_gather_rows<Ti, C>), dim3(static_cast<unsigned>(blocks)), dim3(TPB), sh, s, t.col, t.coef,
-                         t.W, t.n_out, x, reinterpret_cast<Ti*>(y), n_in, in_base, alpha, beta, outer, RB);
+#define GR(wt) hipLaunchKernelGGL((k_gather_rows<Ti, C, wt>), dim3(static_cast<unsigned>(blocks)), dim3(TPB), sh, s, t.col, t.coef, t.W, t.n_out, x, reinterpret_cast<Ti*>(y), n_in, in_base, alpha, beta, outer, RB)
+      switch (t.W) {
+        case 3: GR(3); break;
+        case 4: GR(4); break;
+        case 5: GR(5); break;
+        case 7: GR(7); break;
+        case 9: GR(9); break;
+        case 16: GR(16); break;
+        default: GR(0); break;
+      }
+#undef GR
       return;
     }
   }
