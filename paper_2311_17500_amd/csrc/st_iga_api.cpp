@@ -145,11 +145,18 @@ struct st_iga_ctx {
   // library's capture stream while a step graph is recorded (work cannot be
   // captured on the null stream)
   hipStream_t op_stream = nullptr, cap_stream = nullptr;
+  // pinned host copies of two Arnoldi steps' scalars and the events that
+  // mark their arrival (the next step may run meanwhile)
+  double* step_host = nullptr;
+  hipEvent_t step_ev[2] = {nullptr, nullptr};
   ~st_iga_ctx() {
     for (auto& v : graphs)
       for (auto& g : v)
         if (g.exec) hipGraphExecDestroy(g.exec);
     if (cap_stream) hipStreamDestroy(cap_stream);
+    for (auto& e : step_ev)
+      if (e) hipEventDestroy(e);
+    if (step_host) hipHostFree(step_host);
   }
   int last_refinements = 0;
   double *rk = nullptr, *xk = nullptr, *wk = nullptr, *dk = nullptr, *bk = nullptr;
@@ -1048,8 +1055,15 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
   // Hr: Hessenberg matrix as computed (unrotated); R: rotated copy
   std::vector<double> Hr(static_cast<size_t>(m + 1) * m), R(static_cast<size_t>(m + 1) * m), cs(m), sn(m),
       g(m + 1), gpre(m + 1), y(m);
-  double hb[260];
+  constexpr int HS = 264;   // per step: dots [0, 128), {alpha, h} at 128, |w'|^2 at 256
+  if (!c->step_host) CK(hipHostMalloc(reinterpret_cast<void**>(&c->step_host), 2 * HS * sizeof(double), 0));
+  for (auto& ev : c->step_ev)
+    if (!ev) CK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   auto& gv = c->graphs[(std::is_same<T, double>::value ? 0 : 1) + 2];
+  // steps alternate between two scalar regions of dsc and of the pinned
+  // buffer, so step j + 1 can run while the host reads step j
+  auto region = [&](int j) { return c->dsc + (j & 1) * 640; };
+  const bool overlap = c->opt.graphs != 0 && !kprof_enabled();
   // Givens rotation of column k from its raw entries and the rotations of the
   // columns before it; g[k], g[k + 1] from gpre[k]
   auto rotate = [&](int k) {
@@ -1075,24 +1089,44 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
     gpre[0] = rn;
     int ncol = 0;
     double alpha_prev = 1.0;
-    for (int j = 0; j < m && it < maxit; ++j) {
+    // step j on the stream, followed by the copy of its scalars and its event
+    auto launch = [&](int j) {
       T* Vj = V + static_cast<int64_t>(j) * ld;
       T* Zj = Z + static_cast<int64_t>(j) * ld;
       T* w = V + static_cast<int64_t>(j + 1) * ld;
+      double* D = region(j);
       auto body = [&](hipStream_t ss) {
         c->op_stream = ss;
         Pc(Vj, Zj);
         A(Zj, w);
         c->op_stream = s;
         multidot2_partial<T>(V, ld, j + 1, Vj, w, n, c->part, nb, ss);
-        finalize_sum(c->part, nb, 2 * (j + 1), c->dsc, ss);
-        dcgs_update_partial<T>(V, ld, j, c->dsc, n, c->part, nb, c->dsc + 128, ss);
-        finalize_sum(c->part, nb, 1, c->dsc + 256, ss);
+        finalize_sum(c->part, nb, 2 * (j + 1), D, ss);
+        dcgs_update_partial<T>(V, ld, j, D, n, c->part, nb, D + 128, ss);
+        finalize_sum(c->part, nb, 1, D + 256, ss);
       };
       run_step(c, gv, j, m, body, s);
-      CK(hipMemcpyAsync(hb, c->dsc, 257 * sizeof(double), hipMemcpyDeviceToHost, s));
-      CK(hipStreamSynchronize(s));
+      CK(hipMemcpyAsync(c->step_host + (j & 1) * HS, D, 257 * sizeof(double), hipMemcpyDeviceToHost, s));
+      CK(hipEventRecord(c->step_ev[j & 1], s));
+    };
+    int queued = -1;          // last step already on the stream
+    double res_prev = -1.0;   // residual estimate one step earlier
+    for (int j = 0; j < m && it < maxit; ++j) {
+      if (queued < j) launch(j);
+      queued = j;
+      // step j + 1 needs only device data: queue it before reading step j
+      // while the residual estimate is far from the tolerance (a step that
+      // turns out unneeded writes only basis columns the solution ignores)
+      const double res = std::fabs(j == 0 ? gpre[0] : g[j]);
+      const double q = res_prev > 0.0 ? std::min(1.0, res / res_prev) : 0.0;
+      if (overlap && j + 1 < m && it + 1 < maxit && res * (j == 0 ? 1.0 / 64 : q) > 4.0 * rtol * bnorm) {
+        launch(j + 1);
+        queued = j + 1;
+      }
+      res_prev = res;
+      CK(hipEventSynchronize(c->step_ev[j & 1]));
       check_launch();
+      const double* hb = c->step_host + (j & 1) * HS;
       ++it;
       const double alpha = hb[128], h = hb[129];
       // the stored next vector is the projected w divided by alpha
