@@ -10,7 +10,10 @@
  *           A per-context message is available from st_iga_last_error.
  * Memory:   the caller owns every device buffer (vectors and the workspace);
  *           the library never allocates device memory.  The opaque context is
- *           host memory owned by the library (freed by st_iga_destroy).
+ *           host memory owned by the library (freed by st_iga_destroy); on the
+ *           first Krylov solve it also takes a 4 KB pinned host buffer, two
+ *           HIP events, a capture stream and the Arnoldi step graphs, all
+ *           released by st_iga_destroy.
  * Streams:  `stream` is a hipStream_t passed as void*; NULL means the null
  *           stream.  apply/precond only enqueue work; calls that return
  *           scalars (residuals, reports) synchronize that stream.
