@@ -1858,7 +1858,7 @@ __global__ void __launch_bounds__(TPB) k_pointwise_ionic(
 // chunk blockIdx.z with rings of the KP input rows an element touches; the
 // element maximum over the time rows is taken across the waves through LDS
 // (double-buffered, one barrier per element).  With D == 2, A1 is not read.
-template <int D, int KP>
+template <int D, int KP, bool X2>
 __global__ void __launch_bounds__(384) k_quad_fused(
     const double* __restrict__ A0, const double* __restrict__ A1, const double* __restrict__ A2,
     const double* __restrict__ UT, const double* __restrict__ WW, int nd, int64_t Qin,
@@ -1866,7 +1866,8 @@ __global__ void __launch_bounds__(384) k_quad_fused(
     const int* __restrict__ chunks, const double* __restrict__ wt, const double* __restrict__ win,
     const double* __restrict__ wd, double sL,
     double sM, double sF, double Cm, double a, double c1, double c2, double* __restrict__ G,
-    double* __restrict__ M, int nel_d, double* __restrict__ part, int64_t boff) {
+    double* __restrict__ M, int nel_d, double* __restrict__ part, int64_t boff, int n2, int Q1,
+    const double* __restrict__ e0x2, const double* __restrict__ e2x2, const int* __restrict__ f2x) {
   __shared__ double sh[8];
   __shared__ double smax[2][6][64];
   const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
@@ -1883,14 +1884,50 @@ __global__ void __launch_bounds__(384) k_quad_fused(
   const double wtr = wt[tr];
   const double wc = win[cc];   // product of the faster axes' Gauss weights of column c
   double a0[KP], a1[D == 3 ? KP : 1], a2[KP], ut[KP], ww[KP], gr[KP];
+  // X2 (D == 3): the inputs are expanded along x1 only ([row][nd][n2][Q1]:
+  // A0 = B0 u, A2 = B2 u along x1, UT, WW) and the x2 expansion is formed
+  // here, column c = q1 + Q1 q2 reading rows f2x[q2] + k with the weights
+  // e0x2 / e2x2 (values / second derivatives), summed in the order of the
+  // x2 gathers it replaces
+  int64_t ib = rb, istep = Qin;
+  double w0[X2 ? KP : 1], w2[X2 ? KP : 1];
+  if constexpr (X2) {
+    const int q2 = static_cast<int>(cc / Q1);
+    istep = static_cast<int64_t>(n2) * Q1;
+    ib = static_cast<int64_t>(tr) * nd * istep + static_cast<int64_t>(f2x[q2]) * Q1 + (cc - static_cast<int64_t>(q2) * Q1);
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      w0[k] = e0x2[q2 * KP + k];
+      w2[k] = e2x2[q2 * KP + k];
+    }
+  }
   auto load = [&](int k, int dof) {
     const bool ok = dof < nd;
-    const int64_t o = rb + static_cast<int64_t>(ok ? dof : 0) * Qin;
-    a0[k] = ok ? A0[o] : 0.0;
-    if constexpr (D == 3) a1[k] = ok ? A1[o] : 0.0;
-    a2[k] = ok ? A2[o] : 0.0;
-    ut[k] = ok ? UT[o] : 0.0;
-    ww[k] = ok ? WW[o] : 0.0;
+    const int64_t o = ib + static_cast<int64_t>(ok ? dof : 0) * istep;
+    if constexpr (X2) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+#pragma unroll
+      for (int k2 = 0; k2 < KP; ++k2) {
+        const int64_t ok2 = o + static_cast<int64_t>(k2) * Q1;
+        const double xa = A0[ok2], xb = A2[ok2], xt = UT[ok2], xw = WW[ok2];
+        s0 += w0[k2] * xa;
+        s1 += w2[k2] * xa;
+        s2 += w0[k2] * xb;
+        s3 += w0[k2] * xt;
+        s4 += w0[k2] * xw;
+      }
+      a0[k] = ok ? s0 : 0.0;
+      if constexpr (D == 3) a1[k] = ok ? s1 : 0.0;
+      a2[k] = ok ? s2 : 0.0;
+      ut[k] = ok ? s3 : 0.0;
+      ww[k] = ok ? s4 : 0.0;
+    } else {
+      a0[k] = ok ? A0[o] : 0.0;
+      if constexpr (D == 3) a1[k] = ok ? A1[o] : 0.0;
+      a2[k] = ok ? A2[o] : 0.0;
+      ut[k] = ok ? UT[o] : 0.0;
+      ww[k] = ok ? WW[o] : 0.0;
+    }
     gr[k] = 0.0;
   };
   auto store = [&](int k, int dof) {
@@ -2578,15 +2615,30 @@ int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, c
                    const int* efirst, const int* chunks, int nchunk, const double* wt, const double* win,
                    const double* wd, double sL,
                    double sM, double sF, double Cm, double a, double c1, double c2, double* G, double* M, int nel_d,
-                   double* part, int64_t boff, hipStream_t s) {
+                   double* part, int64_t boff, hipStream_t s, int n2, int Q1, const double* e0x2,
+                   const double* e2x2, const int* f2x) {
   if (d < 2 || d > 3 || ps < 1 || ps > 4 || nqt < 1 || nqt > 6) return -1;
+  const bool x2 = e0x2 != nullptr;
+  if (x2 && (d != 3 || !e2x2 || !f2x || Q1 <= 0 || n2 <= 0 || Qin % Q1 != 0)) return -1;
   const dim3 g(static_cast<unsigned>((Qin + 63) / 64), static_cast<unsigned>(ne), static_cast<unsigned>(nchunk));
   const dim3 blk(static_cast<unsigned>(64 * nqt));
   const double rows = static_cast<double>(ne) * nqt;
+  const double in_bytes = x2 ? rows * nd * static_cast<double>(n2) * Q1 * 4.0
+                             : rows * nd * static_cast<double>(Qin) * (d == 3 ? 5.0 : 4.0);
   ProfScope pr(K_POINTWISE, 12, s,
-               (rows * nd * Qin * ((d == 3 ? 5.0 : 4.0) + (G ? 1.0 : 0.0)) + (M ? static_cast<double>(ne) * nel_d * Qin : 0.0) +
+               (in_bytes + rows * nd * Qin * (G ? 1.0 : 0.0) + (M ? static_cast<double>(ne) * nel_d * Qin : 0.0) +
                 static_cast<double>(nel_d) * (ps + 1) * Qin) * sizeof(double));
-#define QF(D_, K_) hipLaunchKernelGGL((k_quad_fused<D_, K_>), g, blk, 0, s, A0, A1, A2, UT, WW, nd, Qin, B0, B2, efirst, chunks, wt, win, wd, sL, sM, sF, Cm, a, c1, c2, G, M, nel_d, part, boff)
+#define QF(D_, K_)                                                                                                \
+  do {                                                                                                            \
+    if (x2)                                                                                                       \
+      hipLaunchKernelGGL((k_quad_fused<D_, K_, true>), g, blk, 0, s, A0, A1, A2, UT, WW, nd, Qin, B0, B2, efirst, \
+                         chunks, wt, win, wd, sL, sM, sF, Cm, a, c1, c2, G, M, nel_d, part, boff, n2, Q1, e0x2,   \
+                         e2x2, f2x);                                                                             \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_quad_fused<D_, K_, false>), g, blk, 0, s, A0, A1, A2, UT, WW, nd, Qin, B0, B2,       \
+                         efirst, chunks, wt, win, wd, sL, sM, sF, Cm, a, c1, c2, G, M, nel_d, part, boff, 0, 1,   \
+                         nullptr, nullptr, nullptr);                                                             \
+  } while (0)
 #define QFK(D_)                         \
   switch (ps) {                         \
     case 1: QF(D_, 2); break;           \

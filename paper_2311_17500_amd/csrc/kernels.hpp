@@ -95,13 +95,18 @@ bool coef_fused(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1
 // [ne][nel_d][Qin] (element maxima of |R| over the axis and time), and block
 // maxima of |u|, |u_t| at part[2(boff + b)], part[2(boff + b) + 1].  Returns
 // the number of blocks written (or -1 if the degrees are not supported:
-// d in {2, 3}, ps <= 4, nqt <= 6).
+// d in {2, 3}, ps <= 4, nqt <= 6).  With e0x2 given (d = 3), A0 = B0 u and
+// A2 = B2 u along x1, UT and WW are expanded along x1 only ([ne*nqt][nd][n2]
+// [Q1], A1 unused) and the kernel forms the x2 expansion: rows f2x[q2] + k
+// (k <= ps, all < n2) with values e0x2 and second derivatives e2x2
+// ([Q2][ps+1]) at x2 Gauss point q2 = c / Q1.
 int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, const double* A2, const double* UT,
                    const double* WW, int nd, int64_t Qin, int ne, const double* B0, const double* B2,
                    const int* efirst, const int* chunks, int nchunk, const double* wt, const double* win,
                    const double* wd, double sL,
                    double sM, double sF, double Cm, double a, double c1, double c2, double* G, double* M, int nel_d,
-                   double* part, int64_t boff, hipStream_t s);
+                   double* part, int64_t boff, hipStream_t s, int n2 = 0, int Q1 = 0, const double* e0x2 = nullptr,
+                   const double* e2x2 = nullptr, const int* f2x = nullptr);
 
 // Dense mode product on MFMA: y[o][i][k] = sum_j A[i][j] x[o][j][k], A given
 // zero-padded as npad x npad (npad = 16 * ceil(n / 16) <= 144), row-major.

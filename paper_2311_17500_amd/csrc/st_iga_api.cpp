@@ -96,6 +96,7 @@ struct st_iga_ctx {
   int qf_ne = 1;
   std::vector<double> cf_B2_h, qf_win_h, qf_wd_h;
   double *cf_B2_d = nullptr, *qf_win = nullptr, *qf_wd = nullptr;
+  bool qf_x2 = false;   // 3D: the fused quadrature kernel forms the x2 expansion itself
   int *cf_first = nullptr, *cf_chunks = nullptr;
   Arena ar;
   std::string err;
@@ -314,6 +315,16 @@ void plan_fused_coef(st_iga_ctx* c) {
   const int64_t per1 = nqt * 6 * nd * Qin + 2LL * D.nel * Qin;
   const int64_t ne = std::min(c->big_len / per0, c->big_len / per1);
   c->qf = nqt >= 1 && nqt <= 6 && ne >= 1;
+  // x2 value and second-derivative tables with the same contiguous in-range
+  // windows of p + 1 B-splines: the quadrature kernel expands along x2 itself
+  c->qf_x2 = false;
+  if (d == 3) {
+    const Gather &g0 = c->Bq[1][0].h, &g2 = c->Bq[1][2].h;
+    bool ok = g0.W == kp && g2.W == kp && g0.n_out == c->Q[1] && g2.n_out == c->Q[1] &&
+              static_cast<int>(g0.c0.size()) == c->Q[1] && g0.c0 == g2.c0;
+    for (int q = 0; ok && q < c->Q[1]; ++q) ok = g0.c0[q] >= 0 && g0.c0[q] + kp <= c->n[1];
+    c->qf_x2 = ok;
+  }
   // spatial Gauss weights factored as (faster axes) x (this axis), each
   // product formed in the same order as the full tensor weights
   c->qf_win_h.assign(Qin, 1.0);
@@ -1515,11 +1526,13 @@ void quad_pass_fused(st_iga_ctx* c, const double* u, const double* w, bool want_
       ax(E2, U0, Xb, o1, 1, n1);
       ax(E0, Ut, Xt, o1, 1, n1);
       ax(E0, W0, Xw, o1, 1, n1);
-      ax(F0, Xa, in[0], o2, Q1, n2);   // B0 B0 u
-      ax(F2, Xa, in[1], o2, Q1, n2);   // x2 second derivative
-      ax(F0, Xb, in[2], o2, Q1, n2);   // x1 second derivative
-      ax(F0, Xt, in[3], o2, Q1, n2);
-      ax(F0, Xw, in[4], o2, Q1, n2);
+      if (!c->qf_x2) {
+        ax(F0, Xa, in[0], o2, Q1, n2);   // B0 B0 u
+        ax(F2, Xa, in[1], o2, Q1, n2);   // x2 second derivative
+        ax(F0, Xb, in[2], o2, Q1, n2);   // x1 second derivative
+        ax(F0, Xt, in[3], o2, Q1, n2);
+        ax(F0, Xw, in[4], o2, Q1, n2);
+      }
       sL = P.sigma[2];
       sM = P.sigma[1];
       sF = P.sigma[0];
@@ -1533,11 +1546,16 @@ void quad_pass_fused(st_iga_ctx* c, const double* u, const double* w, bool want_
       sM = 0.0;
       sF = P.sigma[0];
     }
-    const int64_t nb = quad_fused(d, P.p_s, nq, in[0], in[1], in[2], in[3], in[4], nd, Qin, ne, c->cf_Bl_d,
-                                  c->cf_B2_d, c->cf_first, c->cf_chunks, c->cf_nchunk, c->wq_t + q0, c->qf_win,
-                                  c->qf_wd, sL, sM,
-                                  sF, P.Cm, P.a, P.c1, P.c2, want_res ? Gp : nullptr, want_theta ? Mp : nullptr, neld,
-                                  c->part, boff, s);
+    const bool x2 = d == 3 && c->qf_x2;
+    const DTable<double> &F0d = c->Bq[1][0].d, &F2d = c->Bq[1][2].d;
+    const int64_t nb =
+        x2 ? quad_fused(d, P.p_s, nq, Xa, nullptr, Xb, Xt, Xw, nd, Qin, ne, c->cf_Bl_d, c->cf_B2_d, c->cf_first,
+                        c->cf_chunks, c->cf_nchunk, c->wq_t + q0, c->qf_win, c->qf_wd, sL, sM, sF, P.Cm, P.a, P.c1,
+                        P.c2, want_res ? Gp : nullptr, want_theta ? Mp : nullptr, neld, c->part, boff, s, n2, Q1,
+                        F0d.coef, F2d.coef, F0d.c0)
+           : quad_fused(d, P.p_s, nq, in[0], in[1], in[2], in[3], in[4], nd, Qin, ne, c->cf_Bl_d, c->cf_B2_d,
+                        c->cf_first, c->cf_chunks, c->cf_nchunk, c->wq_t + q0, c->qf_win, c->qf_wd, sL, sM, sF, P.Cm,
+                        P.a, P.c1, P.c2, want_res ? Gp : nullptr, want_theta ? Mp : nullptr, neld, c->part, boff, s);
     if (nb < 0) throw Fail{ST_IGA_EINVAL, "fused quadrature pass: unsupported degrees"};
     boff += nb;
     if (want_theta) {
