@@ -1872,7 +1872,12 @@ __global__ void __launch_bounds__(384) k_quad_fused(
   __shared__ double smax[2][6][64];
   const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
   const int nqt = blockDim.x >> 6;
-  const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+  // column blocks, XCD-aware: gridDim.x is a multiple of 8 and workgroups go
+  // to the 8 XCDs in turn, so XCD k walks the contiguous column blocks
+  // [k gridDim.x / 8, (k + 1) gridDim.x / 8); with X2, neighbouring columns
+  // read the same x1-expanded rows and find them in that XCD's L2
+  const int64_t lx = static_cast<int64_t>(blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  const int64_t c = lx * 64 + lane;
   const bool cv = c < Qin;
   const int64_t cc = cv ? c : 0;
   const int et = blockIdx.y;
@@ -2620,7 +2625,10 @@ int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, c
   if (d < 2 || d > 3 || ps < 1 || ps > 4 || nqt < 1 || nqt > 6) return -1;
   const bool x2 = e0x2 != nullptr;
   if (x2 && (d != 3 || !e2x2 || !f2x || Q1 <= 0 || n2 <= 0 || Qin % Q1 != 0)) return -1;
-  const dim3 g(static_cast<unsigned>((Qin + 63) / 64), static_cast<unsigned>(ne), static_cast<unsigned>(nchunk));
+  // column blocks padded to a multiple of 8 (the padding columns are invalid
+  // and contribute zeros), see the block order in k_quad_fused
+  const dim3 g(static_cast<unsigned>(((Qin + 63) / 64 + 7) / 8 * 8), static_cast<unsigned>(ne),
+               static_cast<unsigned>(nchunk));
   const dim3 blk(static_cast<unsigned>(64 * nqt));
   const double rows = static_cast<double>(ne) * nqt;
   const double in_bytes = x2 ? rows * nd * static_cast<double>(n2) * Q1 * 4.0

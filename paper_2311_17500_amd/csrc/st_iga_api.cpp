@@ -606,7 +606,8 @@ void plan(st_iga_ctx* c) {
   c->nb_part = static_cast<int>((chunk_pts + 255) / 256) * nchunks + 1;
   if (c->qf) {
     const int64_t Qin = (d == 3) ? static_cast<int64_t>(c->Q[0]) * c->Q[1] : c->Q[0];
-    const int64_t nbf = (Qin + 63) / 64 * c->nelt * c->cf_nchunk + 1;
+    // blocks of the fused quadrature kernel: column blocks padded to a multiple of 8
+    const int64_t nbf = ((Qin + 63) / 64 + 7) / 8 * 8 * c->nelt * c->cf_nchunk + 1;
     c->nb_part = static_cast<int>(std::max<int64_t>(c->nb_part, nbf));
   }
   // reduction partials: up to 2 (m + 1) <= 130 sums per block (two-vector multi-dot)
