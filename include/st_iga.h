@@ -82,7 +82,8 @@ typedef struct {
   int32_t su;                /* 1: Spline Upwind term of eq. (3.2) on, 0: plain Galerkin */
   double eps_theta;          /* relative Frobenius tolerance of the theta low rank, eq. (3.8) (paper: 0.1) */
   double eps_react;          /* same tolerance for the reaction coefficient of the Jacobian */
-  int32_t max_rank;          /* cap on each low rank (sizes the workspace); a capped rank misses eps */
+  int32_t max_rank;          /* cap on each low rank (sizes the workspace); a capped rank misses eps
+                                and is counted in st_iga_report.rank_capped */
   int32_t outer;             /* 0: Newton (dI_ion/du), 1: Picard with C_r of eq. (3.6) */
   double alpha;              /* relaxation of the update (paper: 0.5 for Picard) */
   double theta_freeze;       /* theta is recomputed while ||delta||_inf > theta_freeze */
@@ -119,6 +120,9 @@ typedef struct {
   double lin_relres[ST_IGA_MAX_OUTER_LOG];     /* FP64 true relative residual of each linear solve */
   double final_delta_inf;
   double seconds_linearize, seconds_krylov;
+  int32_t rank_capped;                         /* low ranks cut to max_rank (each misses its tolerance) */
+  double lr_relerr_theta[ST_IGA_MAX_OUTER_LOG]; /* achieved ||Theta - U S V^T||_F / ||Theta||_F */
+  double lr_relerr_react[ST_IGA_MAX_OUTER_LOG]; /* same for the reaction coefficient */
 } st_iga_report;
 
 /* Defaults: su=1, eps_theta=0.1, eps_react=1e-2, max_rank=48, outer=0,

@@ -71,16 +71,18 @@ def reaction_coefficient(u, w, P):
 
 
 def truncated_svd(A: np.ndarray, eps: float, max_rank: int = None):
-    """Smallest-rank R with ||A - U S V^T||_F <= eps ||A||_F (eq. (3.8)),
-    optionally capped at max_rank."""
+    """Smallest-rank R with ||A - U S V^T||_F <= eps ||A||_F (eq. (3.8)).
+    The tolerance alone fixes R; a caller that can only hold max_rank terms
+    gets a ValueError when R exceeds it (the tolerance is never missed
+    silently)."""
     U, s, Vt = np.linalg.svd(A, full_matrices=False)
     tot = float(np.sum(s * s))
     if tot == 0.0:
         return 0, U[:, :0], s[:0], Vt[:0].T
     tail = np.concatenate([np.cumsum((s * s)[::-1])[::-1], [0.0]])  # tail[R] = sum_{k>=R} s_k^2
     R = int(np.argmax(tail <= eps * eps * tot))
-    if max_rank is not None:
-        R = min(R, max_rank)
+    if max_rank is not None and R > max_rank:
+        raise ValueError(f"truncated SVD needs rank {R} > cap {max_rank} for eps = {eps}")
     return R, U[:, :R], s[:R], Vt[:R].T
 
 
@@ -356,6 +358,6 @@ class SpaceTime:
         wg = self.greville_values(w_full)
         return ionic_du(ug, wg, self.P) if newton else reaction_coefficient(ug, wg, self.P)
 
-    def lowrank(self, grid: np.ndarray, eps: float, max_rank: int = 48) -> LowRank:
+    def lowrank(self, grid: np.ndarray, eps: float, max_rank: Optional[int] = None) -> LowRank:
         R, U, s, V = truncated_svd(grid, eps, max_rank)
         return LowRank(U, s, V)

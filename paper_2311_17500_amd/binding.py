@@ -55,7 +55,8 @@ class Report(C.Structure):
     _fields_ = [("outer_iters", C.c_int32), ("krylov_total", C.c_int32), ("refinements", C.c_int32),
                 ("krylov", C.c_int32 * LOG), ("rank_theta", C.c_int32 * LOG), ("rank_react", C.c_int32 * LOG),
                 ("delta_inf", C.c_double * LOG), ("lin_relres", C.c_double * LOG), ("final_delta_inf", C.c_double),
-                ("seconds_linearize", C.c_double), ("seconds_krylov", C.c_double)]
+                ("seconds_linearize", C.c_double), ("seconds_krylov", C.c_double), ("rank_capped", C.c_int32),
+                ("lr_relerr_theta", C.c_double * LOG), ("lr_relerr_react", C.c_double * LOG)]
 
 
 class StIgaError(RuntimeError):

@@ -30,18 +30,26 @@ def _run(cmd):
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source (concurrently) and link libstiga.so."""
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    jobs = []
     for src in SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmd = [HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        _run(cmd)
-        objs.append(obj)
+        jobs.append((cmd, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+    failed = []
+    for cmd, obj, proc in jobs:
+        out, errs = proc.communicate()
+        if proc.returncode != 0:
+            sys.stderr.write(out + errs)
+            failed.append(" ".join(cmd))
+    if failed:
+        raise RuntimeError("build failed: " + "; ".join(failed))
     tmp = OUT + ".tmp"
-    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs)
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + [o for _, o, _ in jobs])
     os.replace(tmp, OUT)
     return OUT
 

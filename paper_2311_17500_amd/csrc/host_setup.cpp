@@ -385,140 +385,118 @@ bool tau_at_quad(const Dir1D& T, std::vector<double>& tauq, std::vector<double>&
   return true;
 }
 
-// Symmetric eigenproblem A = Q diag(lam) Q^T by Householder reduction to
-// tridiagonal form followed by the QL iteration with implicit shifts (the
-// classical two-phase method; O(n^3) with small constants, unlike the cyclic
-// Jacobi sweeps).  Output as gen_eig_sym: lam ascending, eigenvectors in the
-// columns of the row-major Q.
+// Symmetric eigenproblem A = Q diag(lam) Q^T (Golub and Van Loan, "Matrix
+// Computations", Sections 8.3.1-8.3.3): an orthogonal similarity to
+// tridiagonal form by Householder reflections, then implicit QR steps with
+// the Wilkinson shift on the tridiagonal matrix, each step chasing the bulge
+// down with Givens rotations; every transformation is accumulated into Q.
+// Off-diagonal entries below eps_mach (|t_ii| + |t_jj|) are set to zero
+// (deflation).  Output as gen_eig_sym: lam ascending, eigenvectors in the
+// columns of the row-major Q.  O(n^3), unlike the cyclic Jacobi sweeps.
 bool sym_eig(const std::vector<double>& A, int n, std::vector<double>& Q, std::vector<double>& lam, std::string& err) {
   for (double v : A)
     if (!std::isfinite(v)) {
       err = "non-finite matrix entry";
       return false;
     }
-  std::vector<double> Z(A), d(n, 0.0), e(n, 0.0);
-  auto z = [&](int i, int j) -> double& { return Z[static_cast<size_t>(i) * n + j]; };
-  // Householder: step i annihilates row i left of the subdiagonal
-  for (int i = n - 1; i >= 1; --i) {
-    const int l = i - 1;
-    double h = 0.0;
-    if (l > 0) {
-      double scale = 0.0;
-      for (int k = 0; k <= l; ++k) scale += std::fabs(z(i, k));
-      if (scale == 0.0) {
-        e[i] = z(i, l);
-      } else {
-        for (int k = 0; k <= l; ++k) {
-          z(i, k) /= scale;
-          h += z(i, k) * z(i, k);
-        }
-        double f = z(i, l);
-        const double g0 = f >= 0.0 ? -std::sqrt(h) : std::sqrt(h);
-        e[i] = scale * g0;
-        h -= f * g0;
-        z(i, l) = f - g0;
-        f = 0.0;
-        for (int j = 0; j <= l; ++j) {
-          z(j, i) = z(i, j) / h;
-          double g = 0.0;
-          for (int k = 0; k <= j; ++k) g += z(j, k) * z(i, k);
-          for (int k = j + 1; k <= l; ++k) g += z(k, j) * z(i, k);
-          e[j] = g / h;
-          f += e[j] * z(i, j);
-        }
-        const double hh = f / (h + h);
-        for (int j = 0; j <= l; ++j) {
-          const double fj = z(i, j);
-          const double gj = e[j] - hh * fj;
-          e[j] = gj;
-          for (int k = 0; k <= j; ++k) z(j, k) -= fj * e[k] + gj * z(i, k);
-        }
-      }
-    } else {
-      e[i] = z(i, l);
+  auto at = [n](std::vector<double>& M, int i, int j) -> double& { return M[static_cast<size_t>(i) * n + j]; };
+  std::vector<double> T(A);                               // working copy, reduced in place
+  std::vector<double> V(static_cast<size_t>(n) * n, 0.0);  // accumulated transformations
+  for (int i = 0; i < n; ++i) at(V, i, i) = 1.0;
+  // ---- phase 1: T <- H T H column by column, H = I - beta v v^T zeroing T[k+2:, k]
+  std::vector<double> v(n), pv(n), wv(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;   // length of the column part x = T[k+1:, k]
+    double xn2 = 0.0;
+    for (int i = 1; i < m; ++i) xn2 += at(T, k + 1 + i, k) * at(T, k + 1 + i, k);
+    if (xn2 == 0.0) continue;   // already tridiagonal in this column
+    const double x0 = at(T, k + 1, k);
+    const double alpha = -std::copysign(std::sqrt(x0 * x0 + xn2), x0);   // H x = alpha e_1
+    // v = x - alpha e_1, beta = 2 / (v^T v)
+    v[0] = x0 - alpha;
+    for (int i = 1; i < m; ++i) v[i] = at(T, k + 1 + i, k);
+    const double vtv = v[0] * v[0] + xn2;
+    const double beta = 2.0 / vtv;
+    // trailing block B = T[k+1:, k+1:]:  p = beta B v,  w = p - (beta p^T v / 2) v,
+    // B <- B - v w^T - w v^T
+    double pv_dot = 0.0;
+    for (int i = 0; i < m; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < m; ++j) acc += at(T, k + 1 + i, k + 1 + j) * v[j];
+      pv[i] = beta * acc;
+      pv_dot += pv[i] * v[i];
     }
-    d[i] = h;
-  }
-  d[0] = 0.0;
-  e[0] = 0.0;
-  // accumulate the transformations
-  for (int i = 0; i < n; ++i) {
-    const int l = i - 1;
-    if (d[i] != 0.0) {
-      for (int j = 0; j <= l; ++j) {
-        double g = 0.0;
-        for (int k = 0; k <= l; ++k) g += z(i, k) * z(k, j);
-        for (int k = 0; k <= l; ++k) z(k, j) -= g * z(k, i);
-      }
+    const double half = 0.5 * beta * pv_dot;
+    for (int i = 0; i < m; ++i) wv[i] = pv[i] - half * v[i];
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) at(T, k + 1 + i, k + 1 + j) -= v[i] * wv[j] + wv[i] * v[j];
+    at(T, k + 1, k) = at(T, k, k + 1) = alpha;
+    for (int i = 1; i < m; ++i) at(T, k + 1 + i, k) = at(T, k, k + 1 + i) = 0.0;
+    // V <- V H (columns k+1..n-1)
+    for (int r = 0; r < n; ++r) {
+      double acc = 0.0;
+      for (int j = 0; j < m; ++j) acc += at(V, r, k + 1 + j) * v[j];
+      acc *= beta;
+      for (int j = 0; j < m; ++j) at(V, r, k + 1 + j) -= acc * v[j];
     }
-    d[i] = z(i, i);
-    z(i, i) = 1.0;
-    for (int j = 0; j <= l; ++j) z(j, i) = z(i, j) = 0.0;
   }
-  // QL with implicit shifts on (d, e); an off-diagonal entry is negligible
-  // relative to its diagonal neighbours or to the matrix norm
-  for (int i = 1; i < n; ++i) e[i - 1] = e[i];
-  if (n > 0) e[n - 1] = 0.0;
-  double anorm = 0.0;
-  for (int i = 0; i < n; ++i) anorm = std::max(anorm, std::fabs(d[i]) + std::fabs(e[i]));
+  std::vector<double> dg(n), od(std::max(n - 1, 1), 0.0);   // diagonal, off-diagonal (od[i] = t_{i,i+1})
+  for (int i = 0; i < n; ++i) dg[i] = at(T, i, i);
+  for (int i = 0; i + 1 < n; ++i) od[i] = at(T, i + 1, i);
+  // ---- phase 2: implicit Wilkinson-shift QR on the unreduced trailing blocks
   const double eps = std::numeric_limits<double>::epsilon();
-  for (int l = 0; l < n; ++l) {
-    int iter = 0, m;
-    do {
-      for (m = l; m < n - 1; ++m) {
-        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-        if (std::fabs(e[m]) <= eps * dd || std::fabs(e[m]) <= eps * eps * anorm) break;
+  auto negligible = [&](int i) { return std::fabs(od[i]) <= eps * (std::fabs(dg[i]) + std::fabs(dg[i + 1])); };
+  int hi = n - 1;
+  long steps = 0;
+  const long max_steps = 40L * std::max(n, 1);
+  while (hi > 0) {
+    if (negligible(hi - 1)) {
+      od[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && !negligible(lo - 1)) --lo;
+    if (++steps > max_steps) {
+      err = "symmetric QR iteration did not converge";
+      return false;
+    }
+    // Wilkinson shift: the eigenvalue of the trailing 2x2 block closer to t_hh
+    const double h = 0.5 * (dg[hi - 1] - dg[hi]);
+    const double e2 = od[hi - 1] * od[hi - 1];
+    const double mu = dg[hi] - e2 / (h + (h >= 0.0 ? 1.0 : -1.0) * std::sqrt(h * h + e2));
+    // rotation k acts on rows/columns (k, k+1) of the block; its first column
+    // is proportional to (t_ll - mu, t_{l+1,l}), the later ones remove the bulge
+    double x = dg[lo] - mu, z = od[lo];
+    for (int k = lo; k < hi; ++k) {
+      const double r = std::hypot(x, z);
+      const double cs = r > 0.0 ? x / r : 1.0;
+      const double sn = r > 0.0 ? -z / r : 0.0;
+      if (k > lo) od[k - 1] = r;
+      const double a0 = dg[k], a1 = dg[k + 1], b0 = od[k];
+      dg[k] = cs * cs * a0 - 2.0 * cs * sn * b0 + sn * sn * a1;
+      dg[k + 1] = sn * sn * a0 + 2.0 * cs * sn * b0 + cs * cs * a1;
+      od[k] = cs * sn * (a0 - a1) + (cs * cs - sn * sn) * b0;
+      if (k + 1 < hi) {
+        z = -sn * od[k + 1];   // bulge at (k, k+2)
+        od[k + 1] *= cs;
+        x = od[k];
       }
-      if (m != l) {
-        if (iter++ == 100) {
-          err = "QL iteration did not converge";
-          return false;
-        }
-        double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-        double r = std::hypot(g, 1.0);
-        g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? std::fabs(r) : -std::fabs(r)));
-        double s = 1.0, c = 1.0, p = 0.0;
-        int i;
-        bool deflated = false;
-        for (i = m - 1; i >= l; --i) {
-          double f = s * e[i];
-          const double b = c * e[i];
-          r = std::hypot(f, g);
-          e[i + 1] = r;
-          if (r == 0.0) {
-            d[i + 1] -= p;
-            e[m] = 0.0;
-            deflated = true;
-            break;
-          }
-          s = f / r;
-          c = g / r;
-          g = d[i + 1] - p;
-          r = (d[i] - g) * s + 2.0 * c * b;
-          p = s * r;
-          d[i + 1] = g + p;
-          g = c * r - b;
-          for (int k = 0; k < n; ++k) {
-            f = z(k, i + 1);
-            z(k, i + 1) = s * z(k, i) + c * f;
-            z(k, i) = c * z(k, i) - s * f;
-          }
-        }
-        if (deflated) continue;
-        d[l] -= p;
-        e[l] = g;
-        e[m] = 0.0;
+      for (int r2 = 0; r2 < n; ++r2) {
+        const double qa = at(V, r2, k), qb = at(V, r2, k + 1);
+        at(V, r2, k) = cs * qa - sn * qb;
+        at(V, r2, k + 1) = sn * qa + cs * qb;
       }
-    } while (m != l);
+    }
   }
-  std::vector<int> idx(n);
-  std::iota(idx.begin(), idx.end(), 0);
-  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return dg[x] < dg[y]; });
   Q.assign(static_cast<size_t>(n) * n, 0.0);
   lam.resize(n);
   for (int j = 0; j < n; ++j) {
-    lam[j] = d[idx[j]];
-    for (int i = 0; i < n; ++i) Q[static_cast<size_t>(i) * n + j] = z(i, idx[j]);
+    lam[j] = dg[order[j]];
+    for (int i = 0; i < n; ++i) Q[static_cast<size_t>(i) * n + j] = at(V, i, order[j]);
   }
   return true;
 }

@@ -123,6 +123,10 @@ struct st_iga_ctx {
   double *wq_s = nullptr, *wq_t = nullptr;
   // low-rank factors
   int maxR = 0, Rth = 0, Rc = 0;
+  double lr_relerr = 0.0;              // achieved relative Frobenius error of the last truncated SVD
+  bool lr_capped = false;              // its rank was cut to max_rank (tolerance missed)
+  double err_th = 0.0, err_c = 0.0;    // the same for the current theta and reaction factors
+  bool cap_th = false, cap_c = false;
   std::vector<double> Uth_h, sth_h, Uc_h, sc_h;  // host copies: U (N_t x R), s
   double *Vth = nullptr, *Vc = nullptr;          // device N_s x maxR
   double *Psi = nullptr, *Tr = nullptr;
@@ -437,6 +441,20 @@ void host_setup(st_iga_ctx* c) {
       s += P.sigma[l] * c->lam_h[l][il];
     }
     c->lam_s_h[j] = s;
+  }
+  // the 1x1 (zero-frequency) time blocks of the arrowhead divide by the
+  // spatial shift a c1 + sum_l sigma_l lambda_l; with a c1 = 0 the constant
+  // Neumann mode makes it (numerically) zero
+  if (2 * c->fd_np < Nt - 1) {
+    double smin = INFINITY, smax = 0.0;
+    for (double v : c->lam_s_h) {
+      smin = std::min(smin, std::fabs(v));
+      smax = std::max(smax, std::fabs(v));
+    }
+    if (!(smin > 1e-12 * std::max(smax, 1.0)))
+      throw Fail{ST_IGA_EINVAL, "fast-diagonalization preconditioner: a zero-frequency time block meets a spatial mode "
+                                "with zero shift (a*c1 = 0 with Neumann boundaries and an odd N_t - 1); use c1 > 0 "
+                                "or an even N_t - 1"};
   }
   // w-update operator: b (W + b de M)^{-1}_{XtXt} M_{Xt,full}
   {
@@ -1758,6 +1776,8 @@ int lowrank(st_iga_ctx* c, const double* C, double eps, std::vector<double>& U, 
   // descending order
   double tot = 0.0;
   for (double& v : lam) { v = std::max(v, 0.0); tot += v; }
+  c->lr_relerr = 0.0;
+  c->lr_capped = false;
   if (tot == 0.0) { U.clear(); sv.clear(); return 0; }
   std::vector<int> idx(m);
   for (int i = 0; i < m; ++i) idx[i] = m - 1 - i;
@@ -1769,7 +1789,14 @@ int lowrank(st_iga_ctx* c, const double* C, double eps, std::vector<double>& U, 
     if (tail <= eps * eps * tot) R = r;
     else break;
   }
-  if (R > c->maxR) R = c->maxR;   // capped: the tolerance is then not met (reported through the rank)
+  const int Rtol = R;
+  if (R > c->maxR) R = c->maxR;   // capped: the tolerance is then not met (flagged in the report)
+  {
+    double t = 0.0;
+    for (int r = R; r < m; ++r) t += lam[idx[r]];
+    c->lr_relerr = std::sqrt(t / tot);
+    c->lr_capped = Rtol > R;
+  }
   U.assign(static_cast<size_t>(m) * R, 0.0);
   sv.assign(R, 0.0);
   std::vector<double> inv(R);
@@ -1877,13 +1904,19 @@ void linearize(st_iga_ctx* c, const double* u, const double* w, bool refresh_the
       c->rfull_w = w;
     }
     c->Rth = lowrank(c, c->grid, c->opt.eps_theta, c->Uth_h, c->sth_h, c->Vth, s);
+    c->err_th = c->lr_relerr;
+    c->cap_th = c->lr_capped;
   } else if (!c->opt.su) {
     c->Rth = 0;
+    c->err_th = 0.0;
+    c->cap_th = false;
   }
   greville_values(c, u, c->grid, s);
   greville_values(c, w, c->grid2, s);
   react_grid(c->grid, c->grid2, c->Cg, c->nunk, c->P.a, c->P.c1, c->P.c2, newton ? 1 : 0, s);
   c->Rc = lowrank(c, c->Cg, c->opt.eps_react, c->Uc_h, c->sc_h, c->Vc, s);
+  c->err_c = c->lr_relerr;
+  c->cap_c = c->lr_capped;
   rebuild_coefficients(c, s);
 }
 
@@ -2191,7 +2224,10 @@ st_iga_status st_iga_solve(st_iga_ctx* c, const st_iga_stimulus* stim, double* u
         R.rank_react[k] = c->Rc;
         R.delta_inf[k] = dinf;
         R.lin_relres[k] = rr;
+        R.lr_relerr_theta[k] = c->err_th;
+        R.lr_relerr_react[k] = c->err_c;
       }
+      R.rank_capped += (c->cap_th ? 1 : 0) + (c->cap_c ? 1 : 0);
       R.krylov_total += it;
       R.outer_iters = k + 1;
       R.final_delta_inf = dinf;

@@ -63,6 +63,7 @@ class Server:
     def _solve(self, slot: int, prob, rec: Record, t0: float):
         torch = self.torch
         stream = self.streams[slot]
+        S = None
         try:
             with torch.cuda.device(self.device):
                 S = binding.Solver(prob, device=self.device, stream=stream, **self.options)
@@ -70,13 +71,19 @@ class Server:
                 rec.outer_iters, rec.krylov = rep.outer_iters, rep.krylov_total
                 if self.keep_results:
                     rec.u = u.cpu().numpy()
-                S.close()
-                del S, u, w
+                del u, w
                 stream.synchronize()
             rec.status = "ok"
-        except binding.StIgaError as e:
-            rec.status = str(e)
-        rec.finished = time.perf_counter() - t0
+        except Exception as e:   # any failure is recorded; the slot is given back by the caller
+            rec.status = f"{type(e).__name__}: {e}"
+        finally:
+            if S is not None:
+                try:
+                    S.close()
+                except Exception as e:
+                    if rec.status == "ok":
+                        rec.status = f"close failed: {e}"
+            rec.finished = time.perf_counter() - t0
 
     def run(self, requests) -> List[Record]:
         """requests: iterable of (arrival_seconds, problem).  Blocks until all finish."""
@@ -92,11 +99,13 @@ class Server:
         t0 = time.perf_counter()
 
         def worker(slot, prob, rec):
-            self._solve(slot, prob, rec, t0)
-            with lock:
-                used[0] -= rec.footprint
-                free_slots.append(slot)
-                lock.notify_all()
+            try:
+                self._solve(slot, prob, rec, t0)
+            finally:
+                with lock:
+                    used[0] -= rec.footprint
+                    free_slots.append(slot)
+                    lock.notify_all()
 
         for (t_arr, prob), rec in zip(reqs, recs):
             now = time.perf_counter() - t0

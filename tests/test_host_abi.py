@@ -219,3 +219,71 @@ def test_invalid_options_rejected(lib):
         assert binding.workspace_bytes(prob, **kw) == 0, kw
     for r in (0, 1, 2):
         assert binding.workspace_bytes(prob, reorth=r) > 0
+
+
+@pytest.mark.parametrize("kind", ["indefinite", "clustered", "tridiag_tiny", "diagonal", "graded"])
+def test_host_symeig_structures(lib, kind):
+    """The same checks on matrices that stress deflation and shifting:
+    indefinite spectra, clustered and repeated eigenvalues, tiny
+    off-diagonals, an already diagonal matrix, and graded magnitudes."""
+    rng = np.random.default_rng(["indefinite", "clustered", "tridiag_tiny", "diagonal", "graded"].index(kind))
+    n = 37
+    if kind == "indefinite":
+        X = rng.standard_normal((n, n))
+        A = X + X.T
+    elif kind == "clustered":
+        Qr, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        lam0 = np.concatenate([np.full(10, 2.0), np.full(10, 2.0 + 1e-12), rng.uniform(-1, 1, n - 20)])
+        A = (Qr * lam0) @ Qr.T
+        A = 0.5 * (A + A.T)
+    elif kind == "tridiag_tiny":
+        A = np.diag(rng.uniform(-1, 1, n)) + np.diag(np.full(n - 1, 1e-17), 1) + np.diag(np.full(n - 1, 1e-17), -1)
+    elif kind == "diagonal":
+        A = np.diag(rng.uniform(-3, 3, n))
+    else:
+        Qr, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        lam0 = 10.0 ** rng.uniform(-12, 3, n)
+        A = (Qr * lam0) @ Qr.T
+        A = 0.5 * (A + A.T)
+    lam, Q = binding.host_symeig(A)
+    scale = np.max(np.abs(np.linalg.eigvalsh(A)))
+    assert np.all(np.diff(lam) >= 0)
+    assert np.max(np.abs(A @ Q - Q * lam)) <= 1e-13 * scale * n
+    assert np.max(np.abs(Q.T @ Q - np.eye(n))) <= 1e-13 * n
+    assert np.max(np.abs(lam - np.linalg.eigvalsh(A))) <= 1e-13 * scale * n
+
+
+def test_host_symeig_rejects_nonfinite(lib):
+    A = np.eye(4)
+    A[1, 2] = A[2, 1] = np.nan
+    with pytest.raises(binding.StIgaError):
+        binding.host_symeig(A)
+
+
+def test_server_failure_releases_slot(monkeypatch):
+    """A request whose solve raises anything (not only a library error) is
+    recorded as failed, gives its slot and memory back, and the loop goes on
+    to the next request."""
+    import contextlib
+    import types
+    from paper_2311_17500_amd import serve
+
+    calls = []
+
+    class Boom:
+        def __init__(self, prob, **kw):
+            calls.append(prob)
+            raise RuntimeError("allocation failed")
+
+    monkeypatch.setattr(binding, "Solver", Boom)
+    monkeypatch.setattr(binding, "workspace_bytes", lambda prob, **o: 1000)
+    fake_torch = types.SimpleNamespace(cuda=types.SimpleNamespace(device=lambda d: contextlib.nullcontext()))
+    srv = object.__new__(serve.Server)
+    srv.torch, srv.device, srv.slots, srv.budget = fake_torch, None, 1, 10 ** 9
+    srv.options, srv.keep_results, srv.streams = {}, False, [None]
+    reqs = [(0.0, W.tiny(2, 2, 4)), (0.0, W.tiny(2, 2, 5))]
+    recs = srv.run(reqs)
+    assert len(calls) == 2
+    assert all(r.status.startswith("RuntimeError") for r in recs)
+    assert all(r.finished >= r.admitted for r in recs)
+    assert serve.summarize(recs)["completed"] == 0
