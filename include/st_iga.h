@@ -179,6 +179,22 @@ st_iga_status st_iga_apply(st_iga_ctx* ctx, const double* x, double* y, void* st
  * eq. (3.10)-(3.11) with sigma-scaled stiffness.  Asynchronous. */
 st_iga_status st_iga_precond(st_iga_ctx* ctx, const double* r, double* z, void* stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): z = A-hat^{-1} r,
+ * the same kernels and result as st_iga_precond, with the preconditioner's
+ * three intermediate vectors in a static device array that each GPU the
+ * library runs on holds from the library's first use until the process ends
+ * (3 x 2^21 FP64 entries, 48 MiB) instead of the context's workspace.  The
+ * array's address is resolved per device by st_iga_setup; no device or host
+ * memory is allocated and no profiler events are recorded by this call.
+ * Every call on one GPU uses that GPU's one array: calls that overlap in time
+ * on one GPU (any contexts, any streams) race and give wrong results.  The
+ * array needs no clearing (every intermediate is written before it is read).
+ * Errors: EINVAL if the problem has more than 2^21 = 2,097,152 unknowns or
+ * the context's device is not the current device; EDEVICE if the array's
+ * address could not be resolved.  Asynchronous. */
+st_iga_status st_iga_precond_noalloc(st_iga_ctx* ctx, const double* r, double* z, void* stream);
+
 /* The same two operators in the context's low precision (FP32; in BF16 mode
  * the preconditioner uses BF16 storage with FP32 arithmetic and the operator
  * stays FP32): FP64 in and out, converted at the boundary.

@@ -24,7 +24,7 @@ EXPORTS = ["st_iga_default_options", "st_iga_workspace_bytes", "st_iga_setup", "
            "st_iga_residual", "st_iga_w_update", "st_iga_krylov", "st_iga_solve", "st_iga_lift", "st_iga_sizes",
            "st_iga_destroy", "st_iga_last_error", "st_iga_host_query", "st_iga_newton_step", "st_iga_profile",
            "st_iga_profile_read", "st_iga_apply_lowp", "st_iga_precond_lowp", "st_iga_profile_record",
-           "st_iga_host_symeig"]
+           "st_iga_host_symeig", "st_iga_precond_noalloc"]
 
 
 class Problem(C.Structure):
@@ -87,6 +87,7 @@ def load(path: str = LIB_PATH):
     lib.st_iga_theta_grid.argtypes = [P, V, V, V, V]
     lib.st_iga_apply.argtypes = [P, V, V, V]
     lib.st_iga_precond.argtypes = [P, V, V, V]
+    lib.st_iga_precond_noalloc.argtypes = [P, V, V, V]
     lib.st_iga_apply_lowp.argtypes = [P, V, V, V]
     lib.st_iga_precond_lowp.argtypes = [P, V, V, V]
     lib.st_iga_residual.argtypes = [P, V, V, V, V]
@@ -271,6 +272,13 @@ class Solver:
     def precond(self, r, z=None):
         z = self.vec() if z is None else z
         self._chk(self.lib.st_iga_precond(self.ctx, self._p(r), self._p(z), self._s()))
+        return z
+
+    def precond_noalloc(self, r, z=None):
+        """z = A-hat^{-1} r through the allocation-free entry point (z must be
+        given to keep the call itself free of allocations)."""
+        z = self.vec() if z is None else z
+        self._chk(self.lib.st_iga_precond_noalloc(self.ctx, self._p(r), self._p(z), self._s()))
         return z
 
     def apply_lowp(self, x, y=None):

@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <string>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -56,6 +58,7 @@ inline unsigned grid_for(int64_t n, int tpb = TPB) { return static_cast<unsigned
 // Process-wide profiler; enabling it is meant for one solver thread at a time
 // (benchmarks).  The gather tag is per thread so concurrent contexts never race.
 thread_local int t_gather_cls = 0;
+thread_local bool t_prof_suppress = false;   // no events recorded (allocation-free entry points)
 struct ProfState {
   bool on = false;
   std::vector<hipEvent_t> pool;
@@ -89,7 +92,7 @@ struct ProfScope {
   hipEvent_t a = nullptr;
   double bytes, flops;
   ProfScope(int c, int f, hipStream_t st, double by, double fl = 0.0) : cls(c), fn(f), s(st), bytes(by), flops(fl) {
-    if (prof().on) {
+    if (prof().on && !t_prof_suppress) {
       a = prof_event();
       if (a) hipEventRecord(a, s);
     }
@@ -2464,6 +2467,7 @@ void arrowhead(const S* r, S* y, const C* lam, const C* mu, int np, const C* l, 
 }
 
 void kprof_enable(bool on) { prof().on = on; }
+void kprof_suppress(bool on) { t_prof_suppress = on; }
 bool kprof_enabled() { return prof().on; }
 void kprof_gather_class(int cls) { t_gather_cls = cls; }
 
@@ -2753,5 +2757,42 @@ template void convert<bf16, float>(const bf16*, float*, int64_t, hipStream_t);
 template void convert<float, double>(const float*, double*, int64_t, hipStream_t);
 template void convert<double, bf16>(const double*, bf16*, int64_t, hipStream_t);
 template void convert<bf16, double>(const bf16*, double*, int64_t, hipStream_t);
+
+// ---------------------------------------------------------------- allocation-free scratch
+// Intermediate vectors of the allocation-free preconditioner entry point: one
+// file-scope array per GPU, loaded with the code object and held until the
+// process ends.  Host code never uses the array's name as an address: its
+// per-device address is resolved once per device (with that device current)
+// and kept in g_scratch_ptr.
+__device__ __align__(256) double scratch[NOALLOC_BUFS * NOALLOC_MAX_UNKNOWNS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+bool noalloc_scratch_init(int device, std::string& err) {
+  if (device < 0 || device >= MAX_DEVICES) {
+    err = "device index out of range";
+    return false;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return true;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return false;
+  }
+  g_scratch_ptr[device] = static_cast<double*>(p);
+  return true;
+}
+
+double* noalloc_scratch(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 }  // namespace stiga

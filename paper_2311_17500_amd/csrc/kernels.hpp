@@ -7,6 +7,7 @@
 #include <hip/hip_runtime_api.h>
 #include <hip/hip_bf16.h>
 #include <cstdint>
+#include <string>
 
 namespace stiga {
 
@@ -17,6 +18,8 @@ typedef __hip_bfloat16 bf16;
 enum KClass { K_GATHER = 0, K_TIME_MIX, K_ARROW, K_MULTIDOT, K_UPDATE, K_POINTWISE, K_MAX, K_BANDED, K_EXPAND,
               K_DENSE, K_COEF, K_NCLASS };
 void kprof_enable(bool on);
+// while on (per thread), launches record no profiler events (no event creation)
+void kprof_suppress(bool on);
 bool kprof_enabled();
 // class recorded for gather launches until changed (K_GATHER by default)
 void kprof_gather_class(int cls);
@@ -198,5 +201,15 @@ void scale_rows(double* Psi, int R, int64_t Qs, const double* wq, hipStream_t s)
 void transpose_nr(const double* V, int64_t N, int R, double* out, hipStream_t s);
 // Newton update u[layers 1..] += alpha * delta; returns nothing (norm via absmax)
 void add_unknowns(double* u_full, const double* delta, double alpha, int64_t n_unk, int64_t Ns, hipStream_t s);
+
+// Allocation-free entry points: NOALLOC_BUFS intermediate vectors of at most
+// NOALLOC_MAX_UNKNOWNS FP64 entries in a static device array per GPU.
+constexpr int NOALLOC_BUFS = 3;
+constexpr int64_t NOALLOC_MAX_UNKNOWNS = int64_t(1) << 21;
+// Resolve (once per device; the device must be current) and keep the address
+// of that device's copy of the array; false with a message on failure.
+bool noalloc_scratch_init(int device, std::string& err);
+// The resolved address for `device` (null if never resolved).
+double* noalloc_scratch(int device);
 
 }  // namespace stiga

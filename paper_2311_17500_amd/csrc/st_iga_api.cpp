@@ -163,6 +163,9 @@ struct st_iga_ctx {
       if (e) hipEventDestroy(e);
     if (step_host) hipHostFree(step_host);
   }
+  int device = -1;                  // device current at setup
+  bool noalloc_ok = false;          // the allocation-free scratch of that device is resolved
+  std::string noalloc_err;
   int last_refinements = 0;
   double *rk = nullptr, *xk = nullptr, *wk = nullptr, *dk = nullptr, *bk = nullptr;
   double *VT = nullptr, *sol_rhs = nullptr, *sol_dx = nullptr;
@@ -2045,6 +2048,8 @@ st_iga_status st_iga_setup(const st_iga_problem* prob, const st_iga_options* opt
     plan(c.get());
     upload_all(c.get(), s);
     for (int l = 0; l < 4; ++l) c->P.knots[l] = nullptr;
+    CK(hipGetDevice(&c->device));
+    c->noalloc_ok = noalloc_scratch_init(c->device, c->noalloc_err);
   });
   if (st != ST_IGA_OK) {
     g_last_err = c->err;
@@ -2119,6 +2124,27 @@ st_iga_status st_iga_precond(st_iga_ctx* c, const double* r, double* z, void* st
   if (!c || !r || !z) return ST_IGA_EINVAL;
   return guard(c, [&] {
     precond64(c, r, z, static_cast<hipStream_t>(stream));
+    check_launch();
+  });
+}
+
+st_iga_status st_iga_precond_noalloc(st_iga_ctx* c, const double* r, double* z, void* stream) {
+  if (!c || !r || !z) return ST_IGA_EINVAL;
+  return guard(c, [&] {
+    if (c->nunk > NOALLOC_MAX_UNKNOWNS)
+      throw Fail{ST_IGA_EINVAL, "allocation-free preconditioner: " + std::to_string(c->nunk) +
+                                    " unknowns exceed its scratch of " + std::to_string(NOALLOC_MAX_UNKNOWNS)};
+    int dev = -1;
+    CK(hipGetDevice(&dev));
+    if (dev != c->device) throw Fail{ST_IGA_EINVAL, "allocation-free preconditioner: the context's device is not current"};
+    double* scr = noalloc_scratch(dev);
+    if (!c->noalloc_ok || !scr) throw Fail{ST_IGA_EDEVICE, "allocation-free scratch unavailable: " + c->noalloc_err};
+    Bufs<double> B = bufs64(c);
+    for (int k = 0; k < NOALLOC_BUFS; ++k) B.t4[k] = scr + static_cast<int64_t>(k) * NOALLOC_MAX_UNKNOWNS;
+    B.t4[3] = nullptr;   // not used by the preconditioner
+    kprof_suppress(true);
+    struct Restore { ~Restore() { kprof_suppress(false); } } restore;
+    precond_impl<double, double>(c, r, z, B, static_cast<hipStream_t>(stream));
     check_launch();
   });
 }
