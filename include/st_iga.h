@@ -68,14 +68,26 @@ typedef struct {
 } st_iga_problem;
 
 /* Stimulus: an initial datum u0 (lifted into time layer 0 by sampling at the
- * spatial Greville abscissae).  Source terms are not supported (f_kind != 0
- * is rejected with ST_IGA_EINVAL). */
+ * spatial Greville abscissae) and/or a source f of eq. (3.1), which enters the
+ * residual as -int f v and the residual inside theta (eq. (3.4)) as -f, both
+ * evaluated at the space-time Gauss points.  The two source kinds are the
+ * stimuli of the paper's experiments (Section 4): a characteristic function
+ * of a ball times a time window (the 3D test), and a moving Gaussian times a
+ * time window (the 2D test).  Times are absolute (0 <= t <= T). */
 typedef struct {
   int32_t u0_kind;           /* 0 none, 1 half-space x_1 < u0_center[0], 2 closed ball |x - c| <= r */
   double u0_center[3];
   double u0_radius;
   double u0_value;
-  int32_t f_kind;            /* must be 0 */
+  int32_t f_kind;            /* 0 none; 1 f = f_amp on the closed ball |x - f_center| <= f_radius
+                                for t in [f_t0, f_t1]; 2 f = f_amp exp(-f_kappa |x - f_center -
+                                f_velocity t|^2) for t in [f_t0, f_t1]; 0 elsewhere */
+  double f_center[3];
+  double f_radius;           /* kind 1: > 0 */
+  double f_t0, f_t1;         /* time window, f_t0 <= f_t1 */
+  double f_amp;              /* finite */
+  double f_kappa;            /* kind 2: > 0 */
+  double f_velocity[3];      /* kind 2 */
 } st_iga_stimulus;
 
 typedef struct {
@@ -84,8 +96,14 @@ typedef struct {
   double eps_react;          /* same tolerance for the reaction coefficient of the Jacobian */
   int32_t max_rank;          /* cap on each low rank (sizes the workspace); a capped rank misses eps
                                 and is counted in st_iga_report.rank_capped */
-  int32_t outer;             /* 0: Newton (dI_ion/du), 1: Picard with C_r of eq. (3.6) */
-  double alpha;              /* relaxation of the update (paper: 0.5 for Picard) */
+  int32_t outer;             /* 0: Newton (dI_ion/du, low rank), w lagged (w = w(u^k));
+                                1: defect-correction Picard with a low-rank C_r of eq. (3.6), w lagged;
+                                2: the fixed-point scheme of Section 3.1 as stated: M_R with the exact
+                                   C_r(u^k, w^k) at every space-time Gauss point (no low rank; the
+                                   coefficient is stored, Q_t x Q_s values), u and w both relaxed with
+                                   alpha from w^0 = 0 (solves are written in defect form, equivalent
+                                   because C_r(u, w) u = I_ion(u, w)) */
+  double alpha;              /* relaxation of the update, in (0, 1] (paper: 0.5 for Picard) */
   double theta_freeze;       /* theta is recomputed while ||delta||_inf > theta_freeze */
   double tol_nonlin;         /* stop when ||delta||_inf <= tol_nonlin */
   double tol_lin;            /* relative true residual of each linear solve */
@@ -165,6 +183,12 @@ st_iga_status st_iga_set_factors(st_iga_ctx* ctx, int32_t r_theta, const double*
 st_iga_status st_iga_get_factors(st_iga_ctx* ctx, int32_t* r_theta, double* U_theta, double* s_theta,
                                  double* V_theta, int32_t* r_react, double* U_react, double* s_react,
                                  double* V_react);
+
+/* Take the source of `stim` (its f_* fields; the initial datum is ignored)
+ * for every later residual, theta and linearization of this context;
+ * st_iga_solve sets it from its own stimulus.  EINVAL for an unknown kind,
+ * a non-positive radius or kappa, f_t0 > f_t1 or a non-finite amplitude. */
+st_iga_status st_iga_set_stimulus(st_iga_ctx* ctx, const st_iga_stimulus* stim);
 
 /* Theta grid of eq. (3.4) before the low rank (N_t x N_s, device) at (u, w). */
 st_iga_status st_iga_theta_grid(st_iga_ctx* ctx, const double* u, const double* w, double* theta,

@@ -56,9 +56,22 @@ class RowSampler:
     def apply_rows(self, x_unk, rows, theta=None, coef=None, coef_const=None):
         """(J x) at the given unknown rows.  theta/coef: (U, s, V) low-rank
         factors on the Greville grid (or None); coef_const: constant reaction."""
+        N_s = int(np.prod(self.n[: self.d]))
+        return self._rows(np.concatenate([np.zeros(N_s), x_unk]), rows, theta, coef, coef_const, None)
+
+    def residual_rows(self, u_full, w_full, rows, theta=None, f=None):
+        """N(u) of eq. (3.2) at the given unknown rows (full vectors u, w with
+        their initial layer): the same form with the reaction term replaced by
+        the exact ionic current I_ion(u_h, w_h) at the Gauss points, minus the
+        source f(xs, t) when given."""
+        return self._rows(u_full, rows, theta, None, None, (w_full, f))
+
+    def _rows(self, x_full, rows, theta, coef, coef_const, ionic):
         P, d = self.P, self.d
         N_s = int(np.prod(self.n[:d]))
-        X = np.concatenate([np.zeros(N_s), x_unk]).reshape([self.n[d]] + [self.n[l] for l in range(d - 1, -1, -1)])
+        shape = [self.n[d]] + [self.n[l] for l in range(d - 1, -1, -1)]
+        X = np.asarray(x_full).reshape(shape)
+        Wf = np.asarray(ionic[0]).reshape(shape) if ionic is not None else None
         out = np.zeros(len(rows))
         for ri, row in enumerate(rows):
             it, isp = divmod(int(row), N_s)
@@ -82,8 +95,8 @@ class RowSampler:
             sl = [slice(loc[d][2], loc[d][3] + 1)] + [slice(loc[l][2], loc[l][3] + 1) for l in range(d - 1, -1, -1)]
             Xl = X[tuple(sl)]
 
-            def field(ders):   # ders[l]: derivative order per direction
-                F = Xl
+            def field(ders, src=None):   # ders[l]: derivative order per direction
+                F = Xl if src is None else src
                 for a, l in enumerate([d] + list(range(d - 1, -1, -1))):
                     F = np.moveaxis(np.tensordot(E[l][ders[l]], F, axes=([1], [a])), 0, a)
                 return F
@@ -116,13 +129,21 @@ class RowSampler:
                         Vr = np.moveaxis(np.tensordot(Hl, Vr, axes=([1], [a])), 0, a)
                     out_f = out_f + s[rr] * np.multiply.outer(tf, Vr)
                 return out_f
-            if coef_const is not None:
-                cf = coef_const
-            elif coef is not None and len(coef[1]):
-                cf = lowrank_field(coef)
+            if ionic is not None:
+                uh, wh = field(z0), field(z0, Wf[tuple(sl)])
+                g = P.c1 * uh * (uh - P.a) * (uh - 1.0) + P.c2 * uh * wh
+                if ionic[1] is not None:
+                    grids = np.meshgrid(*([loc[d][0]] + [loc[l][0] for l in range(d - 1, -1, -1)]), indexing="ij")
+                    g = g - ionic[1]([grids[d - l] for l in range(d)], grids[0])
+                acc += np.sum(W * g * test(z0))
             else:
-                cf = 0.0
-            acc += np.sum(W * cf * test(z0) * field(z0))
+                if coef_const is not None:
+                    cf = coef_const
+                elif coef is not None and len(coef[1]):
+                    cf = lowrank_field(coef)
+                else:
+                    cf = 0.0
+                acc += np.sum(W * cf * test(z0) * field(z0))
             if theta is not None and len(theta[1]):
                 th = lowrank_field(theta)
                 tq = loc[d][0]

@@ -83,6 +83,58 @@ def solve(st: SpaceTime, newton=True, alpha=None, eps_theta=0.1, eps_react=1e-2,
     return u, w, log
 
 
+def solve_picard(st: SpaceTime, alpha=0.5, eps_theta=0.1, tol=1e-4, max_outer=200, theta_freeze=None,
+                 theta_lr=None):
+    """The fixed-point scheme of Section 3.1 as the paper states it, step by
+    step.  From u^0 (the lifted datum in every time layer) and w^0 = 0, each
+    iteration
+      1. builds theta(u^k, w^k) (eq. (3.4)) and its truncated SVD (eq. (3.8)),
+         refreshed every iteration (while the change exceeds theta_freeze,
+         when given; a fixed theta_lr skips this step);
+      2. assembles A of Section 3.1.1 with M_R weighted by the exact
+         C_r(u^k, w^k) of eq. (3.6) at the Gauss points and the low-rank SU
+         term, and the load vector F;
+      3. solves A u~ = F for the unknown layers, the initial layer held at the
+         lifted datum (sparse LU);
+      4. solves L w~ = G(u^k) (the decoupled w-equation);
+      5. relaxes both: u^{k+1} = alpha u~ + (1 - alpha) u^k and
+         w^{k+1} = alpha w~ + (1 - alpha) w^k;
+    and stops when ||u^{k+1} - u^k||_inf <= tol (Section 4: 1e-4).
+    Returns (u, w, log)."""
+    c0 = st.lift()
+    nt = st.n[st.d]
+    N_s = len(c0)
+    u = np.tile(c0, nt)
+    w = np.zeros_like(u)
+    log = OuterLog()
+    frozen = theta_lr is not None
+    F = st.load_vector()
+    for _ in range(max_outer):
+        if st.su and not frozen:
+            theta_lr = st.lowrank(st.theta_grid(u, w), eps_theta)
+        theta_q = st.lowrank_at_quad(theta_lr) if st.su else None
+        A = st.assemble_full(st.reaction_at_quad(u, w), theta_q)
+        rhs = F[N_s:] - A[N_s:, :N_s] @ c0
+        ut = np.concatenate([c0, spla.splu(sp_csc(A[N_s:, N_s:])).solve(rhs)])
+        wt = st.w_update_explicit(u)
+        u_new = alpha * ut + (1.0 - alpha) * u
+        w = alpha * wt + (1.0 - alpha) * w
+        dinf = float(np.max(np.abs(u_new - u)))
+        u = u_new
+        log.deltas.append(dinf)
+        log.ranks_theta.append(theta_lr.R if (st.su and theta_lr is not None) else 0)
+        log.ranks_react.append(0)
+        if theta_freeze is not None and dinf <= theta_freeze:
+            frozen = True
+        if dinf <= tol:
+            break
+    return u, w, log
+
+
+def sp_csc(A):
+    return A.tocsc()
+
+
 def precond_solve(st: SpaceTime, r):
     """z = A-hat^{-1} r with A-hat assembled explicitly (Section 3.2)."""
     return spla.splu(st.assemble_precond().tocsc()).solve(r)

@@ -118,7 +118,8 @@ class SpaceTime:
         self.n = [n_basis(k, p) for k, p in zip(self.kn, self.p)]
         self.mode = mode
         self.su = su
-        self.f = f
+        # the source of eq. (3.1): given explicitly, or the problem's own
+        self.f = f if f is not None else (prob.source if getattr(prob, "f_kind", 0) else None)
         # axis a of an array (time first): a = 0 is time, a = 1 is x_d, ..., a = d is x_1
         self.dirs = [d] + list(range(d - 1, -1, -1))      # direction index of each axis
         self.quad = [quadrature(k, p + 1 + nq_extra) for k, p in zip(self.kn, self.p)]
@@ -247,20 +248,52 @@ class SpaceTime:
         xs = [grids[self.d - l].reshape(-1) for l in range(self.d)]
         return self.f(xs, t)
 
+    def _constant_part(self):
+        """C_m int dt B_j B_i + sum_l sigma_l int dl B_j dl B_i on the full basis
+        (the same every iteration: assembled once and kept)."""
+        if getattr(self, "_Aconst", None) is None:
+            P, d, om = self.P, self.d, self.omega
+            Dg = sp.diags
+            A = P.Cm * self.phi({}).T @ Dg(om) @ self.phi({d: 1})
+            for l in range(d):
+                A = A + P.sigma[l] * self.phi({l: 1}).T @ Dg(om) @ self.phi({l: 1})
+            self._Aconst = sp.csr_matrix(A)
+        return self._Aconst
+
     def assemble_J(self, coef_q, theta_q):
         """Explicit sparse matrix of apply_J (unknown rows x unknown columns)."""
         P, d, om = self.P, self.d, self.omega
         Dg = sp.diags
-        A = P.Cm * self.phi({}).T @ Dg(om) @ self.phi({d: 1})
-        for l in range(d):
-            A = A + P.sigma[l] * self.phi({l: 1}).T @ Dg(om) @ self.phi({l: 1})
-        A = A + self.phi({}).T @ Dg(om * coef_q) @ self.phi({})
+        A = self._constant_part() + self.phi({}).T @ Dg(om * coef_q) @ self.phi({})
         if self.su and theta_q is not None:
             for k in range(1, P.p_t + 1):
                 tk = np.repeat(self.tau_q[k - 1], int(np.prod(self.qshape[1:])))
                 A = A + P.Cm * self.phi({d: k}).T @ Dg(om * tk * theta_q) @ self.phi({d: k})
         N_s = int(np.prod(self.n[:d]))
         return sp.csr_matrix(A)[N_s:, N_s:]
+
+    def assemble_full(self, coef_q, theta_q):
+        """The same bilinear form on the full basis (all n_t time layers, rows
+        and columns), before the lifting split."""
+        P, d, om = self.P, self.d, self.omega
+        Dg = sp.diags
+        A = self._constant_part() + self.phi({}).T @ Dg(om * coef_q) @ self.phi({})
+        if self.su and theta_q is not None:
+            for k in range(1, P.p_t + 1):
+                tk = np.repeat(self.tau_q[k - 1], int(np.prod(self.qshape[1:])))
+                A = A + P.Cm * self.phi({d: k}).T @ Dg(om * tk * theta_q) @ self.phi({d: k})
+        return sp.csr_matrix(A)
+
+    def load_vector(self):
+        """F(v) = int f v of eq. (3.3) for every full-basis test function."""
+        if self.f is None:
+            return np.zeros(int(np.prod(self.shape)))
+        return self.evT(self.omega * self.f_at_quad(), {})
+
+    def reaction_at_quad(self, u_full, w_full):
+        """C_r(u_h, w_h) of eq. (3.6) at every space-time Gauss point (the
+        exact fixed-point reaction coefficient of the matrix M_R)."""
+        return reaction_coefficient(self.ev(u_full, {}), self.ev(w_full, {}), self.P)
 
     def assemble_precond(self):
         """Explicit A-hat of Section 3.2 (sigma-scaled stiffness, shift a*c1, no SU)."""

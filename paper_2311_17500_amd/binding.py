@@ -24,7 +24,7 @@ EXPORTS = ["st_iga_default_options", "st_iga_workspace_bytes", "st_iga_setup", "
            "st_iga_residual", "st_iga_w_update", "st_iga_krylov", "st_iga_solve", "st_iga_lift", "st_iga_sizes",
            "st_iga_destroy", "st_iga_last_error", "st_iga_host_query", "st_iga_newton_step", "st_iga_profile",
            "st_iga_profile_read", "st_iga_apply_lowp", "st_iga_precond_lowp", "st_iga_profile_record",
-           "st_iga_host_symeig", "st_iga_precond_noalloc"]
+           "st_iga_host_symeig", "st_iga_precond_noalloc", "st_iga_set_stimulus"]
 
 
 class Problem(C.Structure):
@@ -36,7 +36,9 @@ class Problem(C.Structure):
 
 class Stimulus(C.Structure):
     _fields_ = [("u0_kind", C.c_int32), ("u0_center", C.c_double * 3), ("u0_radius", C.c_double),
-                ("u0_value", C.c_double), ("f_kind", C.c_int32)]
+                ("u0_value", C.c_double), ("f_kind", C.c_int32), ("f_center", C.c_double * 3),
+                ("f_radius", C.c_double), ("f_t0", C.c_double), ("f_t1", C.c_double), ("f_amp", C.c_double),
+                ("f_kappa", C.c_double), ("f_velocity", C.c_double * 3)]
 
 
 class Options(C.Structure):
@@ -95,6 +97,7 @@ def load(path: str = LIB_PATH):
     lib.st_iga_krylov.argtypes = [P, V, V, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double), V]
     lib.st_iga_solve.argtypes = [P, C.POINTER(Stimulus), V, V, C.POINTER(Report), V]
     lib.st_iga_lift.argtypes = [P, C.POINTER(Stimulus), V, C.POINTER(C.c_int64)]
+    lib.st_iga_set_stimulus.argtypes = [P, C.POINTER(Stimulus)]
     lib.st_iga_sizes.argtypes = [P, C.POINTER(C.c_int64)]
     lib.st_iga_destroy.argtypes = [P]
     lib.st_iga_last_error.argtypes = [P]
@@ -140,7 +143,14 @@ def make_stimulus(prob):
     S.u0_kind = prob.u0_kind
     for l in range(3):
         S.u0_center[l] = prob.u0_center[l] if l < len(prob.u0_center) else 0.0
-    S.u0_radius, S.u0_value, S.f_kind = prob.u0_radius, prob.u0_value, 0
+    S.u0_radius, S.u0_value = prob.u0_radius, prob.u0_value
+    S.f_kind = int(getattr(prob, "f_kind", 0))
+    if S.f_kind:
+        for l in range(3):
+            S.f_center[l] = prob.f_center[l] if l < len(prob.f_center) else 0.0
+            S.f_velocity[l] = prob.f_velocity[l] if l < len(prob.f_velocity) else 0.0
+        S.f_radius, S.f_t0, S.f_t1 = prob.f_radius, prob.f_t0, prob.f_t1
+        S.f_amp, S.f_kappa = prob.f_amp, prob.f_kappa
     return S
 
 
@@ -217,6 +227,13 @@ class Solver:
         self.unknowns = sz[7] + (sz[8] << 32)
         self.full = self.N_s * self.n_t
         self.workspace_bytes = nbytes
+        if getattr(prob, "f_kind", 0):
+            self.set_stimulus(prob)
+
+    def set_stimulus(self, prob):
+        """Make the source of `prob` (its f_* fields) the context's f."""
+        self._stim = make_stimulus(prob)
+        self._chk(self.lib.st_iga_set_stimulus(self.ctx, C.byref(self._stim)))
 
     def _s(self):
         return C.c_void_p(self.stream)
@@ -318,7 +335,7 @@ class Solver:
                 "banded", "expand", "dense_fd", "coefficient"]
     FNAMES = ["gather_scalar", "gather_v4", "gather_rows", "time_mix", "dense_mode_mfma", "arrowhead",
               "multidot", "update_norm", "pointwise_ionic", "mode_max", "gather_sweep", "coef_fused",
-              "quad_fused", "sweep_dual", "time_core"]
+              "quad_fused", "sweep_dual", "time_core", "react_point"]
 
     def profile(self, on=True):
         self._chk(self.lib.st_iga_profile(self.ctx, int(on)))

@@ -613,6 +613,50 @@ __global__ void __launch_bounds__(TPB) k_time_mix(const C* __restrict__ T, const
 }
 
 
+// ---------------------------------------------------------------- exact reaction term
+// Reaction term with a coefficient known at every space-time Gauss point
+// (Cq[g][q] = omega_g omega_q C_r at time Gauss point g and spatial Gauss
+// point q), over one slab of output time rows:
+//   out[t][q] = beta out[t][q] + sum_{e in supp b_i} sum_{g in e} B(g, i) Cq[g][q] sum_a B(g, f_e + a) Z[f_e + a][q]
+// with i = t0 + t + 1 the full index of unknown row t0 + t.  Z holds the
+// spatially expanded input layers of full indices [lo_full, lo_full + nl)
+// (layers outside read as zero: the initial layer of an unknown vector).
+// One thread per (row, spatial point): consecutive threads take consecutive
+// q, so every Z, Cq and out access of a wave is one contiguous segment.
+template <class S, class C, int KP>
+__global__ void __launch_bounds__(TPB) k_react_point(const S* __restrict__ Z, int nl, int lo_full,
+                                                     const C* __restrict__ Bt, const int* __restrict__ tfirst,
+                                                     const int* __restrict__ re0, const int* __restrict__ re1,
+                                                     const C* __restrict__ Cq, int64_t Qs, int t0, int rows,
+                                                     S* __restrict__ out, C beta) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(rows) * Qs) return;
+  const int t = static_cast<int>(idx / Qs);
+  const int64_t q = idx - static_cast<int64_t>(t) * Qs;
+  const int i = t0 + t + 1;
+  C acc = C(0);
+  for (int e = re0[i]; e < re1[i]; ++e) {
+    const int fe = tfirst[e * KP];
+    C zl[KP];
+#pragma unroll
+    for (int a = 0; a < KP; ++a) {
+      const int j = fe + a - lo_full;
+      zl[a] = (j >= 0 && j < nl) ? to_c(Z[static_cast<int64_t>(j) * Qs + q], C(0)) : C(0);
+    }
+    const int ai = i - fe;
+#pragma unroll
+    for (int g = 0; g < KP; ++g) {
+      const int qg = e * KP + g;
+      C z = C(0);
+#pragma unroll
+      for (int a = 0; a < KP; ++a) z += Bt[qg * KP + a] * zl[a];
+      acc += Bt[qg * KP + ai] * Cq[static_cast<int64_t>(qg) * Qs + q] * z;
+    }
+  }
+  const int64_t o = static_cast<int64_t>(t) * Qs + q;
+  out[o] = from_c<S>(beta != C(0) ? beta * to_c(out[o], C(0)) + acc : acc);
+}
+
 // ---------------------------------------------------------------- fused coefficient terms
 // The low-rank coefficient terms along the slowest spatial axis in one pass:
 // expansion of the input to the axis' Gauss points, the time mixing with the
@@ -1822,19 +1866,44 @@ __global__ void k_add_unknowns(double* __restrict__ u, const double* __restrict_
 }
 
 // ---------------------------------------------------------------- linearization
+// f(x, t) of a Source (see kernels.hpp).  Products and sums are rounded one
+// by one (no fused multiply-add), so that an indicator decides a point's
+// membership from the same rounded distance as a plain evaluation of
+// sum_l ((x_l - c_l) - v_l t)^2 in direction order.
+__device__ __forceinline__ double source_value(const Source& f, double x0, double x1, double x2, double t) {
+  if (!(t >= f.t0 && t <= f.t1)) return 0.0;
+  const double x[3] = {x0, x1, x2};
+  double r2 = 0.0;
+  for (int l = 0; l < f.d; ++l) {
+    double dx = __dsub_rn(x[l], f.c[l]);
+    if (f.kind == 2) dx = __dsub_rn(dx, __dmul_rn(f.v[l], t));
+    r2 = __dadd_rn(r2, __dmul_rn(dx, dx));
+  }
+  if (f.kind == 1) return r2 <= f.r2 ? f.amp : 0.0;
+  return f.amp * exp(-f.kappa * r2);
+}
+
 __global__ void __launch_bounds__(TPB) k_pointwise_ionic(
     const double* __restrict__ u, const double* __restrict__ ut, const double* __restrict__ lap,
     const double* __restrict__ w, const double* __restrict__ wt, const double* __restrict__ ws, int64_t Qs,
     int64_t total, double Cm, double a, double c1, double c2, double* __restrict__ g, double* __restrict__ absR,
-    double* __restrict__ part) {
+    double* __restrict__ part, Source f, int q0, int Q1, int Q2, double* __restrict__ Cq) {
   __shared__ double sh[TPB / 64];
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   double mu = 0.0, mt = 0.0;
   if (idx < total) {
     const int64_t qt = idx / Qs, qs = idx - qt * Qs;
     const double uu = u[idx], ww = w[idx], tt = ut[idx];
-    const double I = c1 * uu * (uu - a) * (uu - 1.0) + c2 * uu * ww;
+    double I = c1 * uu * (uu - a) * (uu - 1.0) + c2 * uu * ww;
+    if (f.kind) {
+      const int q1 = static_cast<int>(qs % Q1);
+      const int64_t r = qs / Q1;
+      const int q2 = static_cast<int>(r % Q2), q3 = static_cast<int>(r / Q2);
+      I -= source_value(f, f.xq[0][q1], f.d > 1 ? f.xq[1][q2] : 0.0, f.d > 2 ? f.xq[2][q3] : 0.0,
+                        f.tq[q0 + qt]);
+    }
     g[idx] = wt[qt] * ws[qs] * I;
+    if (Cq) Cq[static_cast<int64_t>(q0) * Qs + idx] = wt[qt] * ws[qs] * (c1 * (uu - a) * (uu - 1.0) + c2 * ww);
     absR[idx] = fabs(Cm * tt - lap[idx] + I);
     mu = fabs(uu);
     mt = fabs(tt);
@@ -1870,7 +1939,8 @@ __global__ void __launch_bounds__(384) k_quad_fused(
     const double* __restrict__ wd, double sL,
     double sM, double sF, double Cm, double a, double c1, double c2, double* __restrict__ G,
     double* __restrict__ M, int nel_d, double* __restrict__ part, int64_t boff, int n2, int Q1,
-    const double* __restrict__ e0x2, const double* __restrict__ e2x2, const int* __restrict__ f2x) {
+    const double* __restrict__ e0x2, const double* __restrict__ e2x2, const int* __restrict__ f2x, Source fsrc, int q0,
+    double* __restrict__ Cq, int64_t Qs) {
   __shared__ double sh[8];
   __shared__ double smax[2][6][64];
   const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
@@ -1891,6 +1961,17 @@ __global__ void __launch_bounds__(384) k_quad_fused(
   const int64_t rb = static_cast<int64_t>(tr) * lay + cc;
   const double wtr = wt[tr];
   const double wc = win[cc];   // product of the faster axes' Gauss weights of column c
+  // source term: coordinates of this thread's column and time row
+  double fx0 = 0.0, fx1 = 0.0, ftt = 0.0;
+  if (fsrc.kind) {
+    ftt = fsrc.tq[q0 + tr];
+    if constexpr (D == 3) {
+      fx0 = fsrc.xq[0][cc % fsrc.Q1];
+      fx1 = fsrc.xq[1][cc / fsrc.Q1];
+    } else {
+      fx0 = fsrc.xq[0][cc];
+    }
+  }
   double a0[KP], a1[D == 3 ? KP : 1], a2[KP], ut[KP], ww[KP], gr[KP];
   // X2 (D == 3): the inputs are expanded along x1 only ([row][nd][n2][Q1]:
   // A0 = B0 u, A2 = B2 u along x1, UT, WW) and the x2 expansion is formed
@@ -1976,11 +2057,18 @@ __global__ void __launch_bounds__(384) k_quad_fused(
         w += b0 * ww[k];
       }
       const double lap = sL * l2 + sM * l1 + sF * l0;
-      const double I = c1 * u * (u - a) * (u - 1.0) + c2 * u * w;
+      double I = c1 * u * (u - a) * (u - 1.0) + c2 * u * w;
+      if (fsrc.kind) {
+        const double xd = fsrc.xq[D - 1][qd];
+        I -= (D == 3) ? source_value(fsrc, fx0, fx1, xd, ftt) : source_value(fsrc, fx0, xd, 0.0, ftt);
+      }
       emax = fmax(emax, fabs(Cm * tt - lap + I));
       mu = fmax(mu, fabs(u));
       mt = fmax(mt, fabs(tt));
       const double gv = wtr * (wc * wd[qd]) * I;
+      if (Cq && cv)
+        Cq[static_cast<int64_t>(q0 + tr) * Qs + static_cast<int64_t>(qd) * Qin + c] =
+            wtr * (wc * wd[qd]) * (c1 * (u - a) * (u - 1.0) + c2 * w);
 #pragma unroll
       for (int k = 0; k < KP; ++k) gr[k] += B0[qd * KP + k] * gv;
     }
@@ -2291,6 +2379,27 @@ void mode_max(const int* start, const int* cnt, int n_out, const double* x, doub
   if (total == 0) return;
   ProfScope ps(K_MAX, 9, s, static_cast<double>(outer) * (n_in + n_out) * inner * sizeof(double));
   hipLaunchKernelGGL(k_mode_max, dim3(grid_for(total)), dim3(TPB), 0, s, start, cnt, n_out, x, y, inner, n_in, total);
+}
+
+template <class S, class C>
+void react_point(const S* Z, int nl, int lo_full, const DTable<C>& Bt, const int* re0, const int* re1, const C* Cq,
+                 int64_t Qs, int t0, int t1, int p, S* out, C beta, hipStream_t s) {
+  const int rows = t1 - t0;
+  const int64_t total = static_cast<int64_t>(rows) * Qs;
+  if (total == 0) return;
+  // algorithmic bytes: the input layers, the coefficient at the slab's time
+  // Gauss points and the output rows, each once
+  ProfScope ps(K_TIME_MIX, 15 + 16 * prec_code<S>(), s,
+               (static_cast<double>(nl) + rows) * Qs * sizeof(S) + static_cast<double>(rows) * (p + 1) * Qs * sizeof(C),
+               2.0 * (p + 1) * (p + 1) * (p + 2) * static_cast<double>(total));
+  const dim3 g(grid_for(total)), b(TPB);
+  switch (p) {
+    case 1: hipLaunchKernelGGL((k_react_point<S, C, 2>), g, b, 0, s, Z, nl, lo_full, Bt.coef, Bt.c0, re0, re1, Cq, Qs, t0, rows, out, beta); break;
+    case 2: hipLaunchKernelGGL((k_react_point<S, C, 3>), g, b, 0, s, Z, nl, lo_full, Bt.coef, Bt.c0, re0, re1, Cq, Qs, t0, rows, out, beta); break;
+    case 3: hipLaunchKernelGGL((k_react_point<S, C, 4>), g, b, 0, s, Z, nl, lo_full, Bt.coef, Bt.c0, re0, re1, Cq, Qs, t0, rows, out, beta); break;
+    case 4: hipLaunchKernelGGL((k_react_point<S, C, 5>), g, b, 0, s, Z, nl, lo_full, Bt.coef, Bt.c0, re0, re1, Cq, Qs, t0, rows, out, beta); break;
+    default: hipLaunchKernelGGL((k_react_point<S, C, 6>), g, b, 0, s, Z, nl, lo_full, Bt.coef, Bt.c0, re0, re1, Cq, Qs, t0, rows, out, beta); break;
+  }
 }
 
 template <class S, class C>
@@ -2612,12 +2721,13 @@ void fill(double* x, double v, int64_t n, hipStream_t s) {
 }
 void pointwise_ionic(const double* u, const double* ut, const double* lap, const double* w, const double* wt_time,
                      const double* wt_space, int64_t Qs, int nq_t, double Cm, double a, double c1, double c2,
-                     double* g, double* absR, double* part, int nb, hipStream_t s) {
+                     double* g, double* absR, double* part, int nb, hipStream_t s, const Source& f, int q0, int Q1,
+                     int Q2, double* Cq) {
   const int64_t total = Qs * nq_t;
   (void)nb;
   ProfScope ps(K_POINTWISE, 8, s, 6.0 * total * sizeof(double));
   hipLaunchKernelGGL(k_pointwise_ionic, dim3(grid_for(total)), dim3(TPB), 0, s, u, ut, lap, w, wt_time, wt_space, Qs,
-                     total, Cm, a, c1, c2, g, absR, part);
+                     total, Cm, a, c1, c2, g, absR, part, f, q0, Q1, Q2, Cq);
 }
 int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, const double* A2, const double* UT,
                    const double* WW, int nd, int64_t Qin, int ne, const double* B0, const double* B2,
@@ -2625,7 +2735,7 @@ int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, c
                    const double* wd, double sL,
                    double sM, double sF, double Cm, double a, double c1, double c2, double* G, double* M, int nel_d,
                    double* part, int64_t boff, hipStream_t s, int n2, int Q1, const double* e0x2,
-                   const double* e2x2, const int* f2x) {
+                   const double* e2x2, const int* f2x, const Source& f, int q0, double* Cq, int64_t Qs) {
   if (d < 2 || d > 3 || ps < 1 || ps > 4 || nqt < 1 || nqt > 6) return -1;
   const bool x2 = e0x2 != nullptr;
   if (x2 && (d != 3 || !e2x2 || !f2x || Q1 <= 0 || n2 <= 0 || Qin % Q1 != 0)) return -1;
@@ -2645,11 +2755,11 @@ int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, c
     if (x2)                                                                                                       \
       hipLaunchKernelGGL((k_quad_fused<D_, K_, true>), g, blk, 0, s, A0, A1, A2, UT, WW, nd, Qin, B0, B2, efirst, \
                          chunks, wt, win, wd, sL, sM, sF, Cm, a, c1, c2, G, M, nel_d, part, boff, n2, Q1, e0x2,   \
-                         e2x2, f2x);                                                                             \
+                         e2x2, f2x, f, q0, Cq, Qs);                                                              \
     else                                                                                                          \
       hipLaunchKernelGGL((k_quad_fused<D_, K_, false>), g, blk, 0, s, A0, A1, A2, UT, WW, nd, Qin, B0, B2,       \
                          efirst, chunks, wt, win, wd, sL, sM, sF, Cm, a, c1, c2, G, M, nel_d, part, boff, 0, 1,   \
-                         nullptr, nullptr, nullptr);                                                             \
+                         nullptr, nullptr, nullptr, f, q0, Cq, Qs);                                              \
   } while (0)
 #define QFK(D_)                         \
   switch (ps) {                         \
@@ -2711,6 +2821,10 @@ template bool coef_fused<double, double>(const double*, const double*, int, int,
 template bool coef_fused<float, float>(const float*, const float*, int, int, int, int, int, int, int, const float*, int,
                                        int, const float*, const int*, const int*, int, int, int64_t, float*, int64_t,
                                        hipStream_t);
+template void react_point<double, double>(const double*, int, int, const DTable<double>&, const int*, const int*,
+                                          const double*, int64_t, int, int, int, double*, double, hipStream_t);
+template void react_point<float, float>(const float*, int, int, const DTable<float>&, const int*, const int*,
+                                        const float*, int64_t, int, int, int, float*, float, hipStream_t);
 template void time_mix<double, double>(const double*, const double*, int, int, int, int, int, int, const double*,
                                        int, int, double*, int64_t, hipStream_t);
 template void time_mix<float, float>(const float*, const float*, int, int, int, int, int, int, const float*, int, int,

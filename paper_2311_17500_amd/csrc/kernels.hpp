@@ -13,6 +13,20 @@ namespace stiga {
 
 typedef __hip_bfloat16 bf16;
 
+// Source term f(x, t) of eq. (3.1) at the space-time Gauss points: kind 1 is
+// amp on the closed ball |x - c| <= r during [t0, t1], kind 2 the moving
+// Gaussian amp exp(-kappa |x - c - v t|^2) during [t0, t1] (the two stimuli of
+// the paper's experiments); kind 0 is f = 0.  xq / tq are the Gauss abscissae
+// of each spatial direction and of time (device arrays).
+struct Source {
+  int kind = 0, d = 0;
+  int Q1 = 1;                 // Gauss points along x_1 (column decomposition of the fused pass)
+  double c[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
+  double r2 = 0.0, t0 = 0.0, t1 = 0.0, amp = 0.0, kappa = 0.0;
+  const double* xq[3] = {nullptr, nullptr, nullptr};
+  const double* tq = nullptr;
+};
+
 // Kernel classes for the optional HIP-event profiler (host-side timing of
 // individual launches on the stream they run on).
 enum KClass { K_GATHER = 0, K_TIME_MIX, K_ARROW, K_MULTIDOT, K_UPDATE, K_POINTWISE, K_MAX, K_BANDED, K_EXPAND,
@@ -69,6 +83,17 @@ template <class S, class C>
 void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1, int p, const S* Z, int n_in,
               int in_base, S* out, int64_t Qs, hipStream_t s);
 
+// Reaction term with a coefficient given at every space-time Gauss point
+// (Cq [Q_t][Qs], Gauss weights included), over output rows [t0, t1) of the
+// unknowns: out[t - t0][q] = beta out + sum over the time Gauss points g in
+// supp b_{t+1} of B(g, t+1) Cq[g][q] (sum_a B(g, a) Z[a][q]).  Z holds the
+// spatially expanded input layers of full indices [lo_full, lo_full + nl).
+// Bt: time basis values at the Gauss points (contiguous windows, W = p + 1);
+// re0/re1: per full time row, the range of time elements in its support.
+template <class S, class C>
+void react_point(const S* Z, int nl, int lo_full, const DTable<C>& Bt, const int* re0, const int* re1, const C* Cq,
+                 int64_t Qs, int t0, int t1, int p, S* out, C beta, hipStream_t s);
+
 // Coefficient part along the slowest spatial axis in one kernel (time_mix
 // between the expansion to that axis' Gauss points and the projection back):
 //   out[t - t0][i][c] = sum_{q in axis Gauss points} Bl[q][i - efirst(q)] *
@@ -108,8 +133,9 @@ int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, c
                    const int* efirst, const int* chunks, int nchunk, const double* wt, const double* win,
                    const double* wd, double sL,
                    double sM, double sF, double Cm, double a, double c1, double c2, double* G, double* M, int nel_d,
-                   double* part, int64_t boff, hipStream_t s, int n2 = 0, int Q1 = 0, const double* e0x2 = nullptr,
-                   const double* e2x2 = nullptr, const int* f2x = nullptr);
+                   double* part, int64_t boff, hipStream_t s, int n2, int Q1, const double* e0x2,
+                   const double* e2x2, const int* f2x, const Source& f, int q0, double* Cq,
+                   int64_t Qs);
 
 // Dense mode product on MFMA: y[o][i][k] = sum_j A[i][j] x[o][j][k], A given
 // zero-padded as npad x npad (npad = 16 * ceil(n / 16) <= 144), row-major.
@@ -184,7 +210,8 @@ void fill(double* x, double v, int64_t n, hipStream_t s);
 void pointwise_ionic(const double* u, const double* ut, const double* lap, const double* w,
                      const double* wt_time, const double* wt_space, int64_t Qs, int nq_t, double Cm,
                      double a, double c1, double c2, double* g, double* absR, double* part, int nb,
-                     hipStream_t s);
+                     hipStream_t s,
+                     const Source& f, int q0, int Q1, int Q2, double* Cq);
 // theta = min(num/den, 1) with den from device maxima (den = Cm (umax/T + utmax)); den == 0 -> num > 0
 void theta_finish(double* th, int64_t n, const double* maxes, double Cm, double invT, hipStream_t s);
 // coefficient grid: newton ? dI/du : C_r at (u, w)

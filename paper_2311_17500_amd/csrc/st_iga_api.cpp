@@ -121,6 +121,17 @@ struct st_iga_ctx {
   int *el_t_s = nullptr, *el_t_c = nullptr, *el_s_s[3] = {}, *el_s_c[3] = {};
   int *win_t_s = nullptr, *win_t_c = nullptr, *win_s_s[3] = {}, *win_s_c[3] = {};
   double *wq_s = nullptr, *wq_t = nullptr;
+  double *xq_dev[3] = {nullptr, nullptr, nullptr}, *tq_dev = nullptr;   // Gauss abscissae
+  Source src;                       // source term f of eq. (3.1) (kind 0: none)
+  // fixed-point scheme of Section 3.1 (outer = 2): M_R with the exact C_r at
+  // every space-time Gauss point (Cq, Gauss weights included) instead of a
+  // low rank; per full time row the time elements of its support (re0/re1)
+  bool exact_react = false;
+  double* Cq_d = nullptr;
+  float* Cq_f = nullptr;
+  double* cq_out = nullptr;         // set while a quadrature pass must fill Cq_d
+  int *re0 = nullptr, *re1 = nullptr;
+  std::vector<int> re0_h, re1_h;
   // low-rank factors
   int maxR = 0, Rth = 0, Rc = 0;
   double lr_relerr = 0.0;              // achieved relative Frobenius error of the last truncated SVD
@@ -192,6 +203,8 @@ void validate(const st_iga_problem* P, const st_iga_options* O) {
     if (!P->knots[l]) throw Fail{ST_IGA_EINVAL, "null knot vector"};
   if (O->restart < 1 || O->restart > 64) throw Fail{ST_IGA_EINVAL, "restart must be in 1..64"};
   if (O->reorth < 0 || O->reorth > 2) throw Fail{ST_IGA_EINVAL, "reorth must be 0, 1 or 2"};
+  if (O->outer < 0 || O->outer > 2) throw Fail{ST_IGA_EINVAL, "outer must be 0, 1 or 2"};
+  if (!(O->alpha > 0) || O->alpha > 1) throw Fail{ST_IGA_EINVAL, "alpha must be in (0, 1]"};
   if (O->max_rank < 1 || O->max_rank > 128) throw Fail{ST_IGA_EINVAL, "max_rank must be in 1..128"};
   if (O->prec < ST_IGA_FP64 || O->prec > ST_IGA_MIXED_BF16) throw Fail{ST_IGA_EINVAL, "bad precision"};
   if (O->su) {  // SU needs C^{p_t - 1} in time: interior time multiplicity 1
@@ -358,6 +371,22 @@ void host_setup(st_iga_ctx* c) {
   if (!build_dir(P.knots[P.d], P.nknots[P.d], P.p_t, P.T, P.p_t, c->dir[P.d], err))
     throw Fail{ST_IGA_EINVAL, "time knots: " + err};
   const Dir1D& T = c->dir[P.d];
+  // exact reaction (fixed-point scheme of Section 3.1): the time elements in
+  // the support of each full time row
+  c->exact_react = c->opt.outer == 2;
+  if (c->exact_react) {
+    c->re0_h.assign(T.n, T.nel);
+    c->re1_h.assign(T.n, 0);
+    for (int e = 0; e < T.nel; ++e) {
+      const int fe = T.first[static_cast<size_t>(e) * T.nq];
+      for (int a = 0; a <= T.p; ++a) {
+        const int i = fe + a;
+        if (i < 0 || i >= T.n) continue;
+        c->re0_h[i] = std::min(c->re0_h[i], e);
+        c->re1_h[i] = std::max(c->re1_h[i], e + 1);
+      }
+    }
+  }
   c->Ns = 1;
   c->Qs = 1;
   c->Nels = 1;
@@ -589,8 +618,17 @@ void plan(st_iga_ctx* c) {
     c->win_s_s[l] = a.get<int>(c->n[l]);
     c->win_s_c[l] = a.get<int>(c->n[l]);
   }
+  if (c->exact_react) {
+    const int64_t nq = static_cast<int64_t>(c->dir[d].Q) * c->Qs;
+    c->Cq_d = a.get<double>(nq);
+    if (mixed) c->Cq_f = a.get<float>(nq);
+    c->re0 = a.get<int>(c->nt);
+    c->re1 = a.get<int>(c->nt);
+  }
   c->wq_s = a.get<double>(c->Qs);
   c->wq_t = a.get<double>(c->dir[d].Q);
+  for (int l = 0; l < d; ++l) c->xq_dev[l] = a.get<double>(c->dir[l].Q);
+  c->tq_dev = a.get<double>(c->dir[d].Q);
   const int R2 = 2 * c->maxR;
   const int WB = 2 * c->P.p_t + 1;
   c->Vth = a.get<double>(c->Ns * c->maxR);
@@ -744,6 +782,12 @@ void upload_all(st_iga_ctx* c, hipStream_t s) {
   }
   keepd.push_back(ws); up(keepd.back(), static_cast<const double*>(c->wq_s), s);
   up(T.wq, static_cast<const double*>(c->wq_t), s);
+  for (int l = 0; l < d; ++l) up(c->dir[l].xq, static_cast<const double*>(c->xq_dev[l]), s);
+  up(T.xq, static_cast<const double*>(c->tq_dev), s);
+  if (c->exact_react) {
+    up(c->re0_h, static_cast<const int*>(c->re0), s);
+    up(c->re1_h, static_cast<const int*>(c->re1), s);
+  }
   CK(hipStreamSynchronize(s));
 }
 
@@ -855,9 +899,10 @@ void apply_impl(st_iga_ctx* c, const S* x, S* y, int L, int in_base, bool with_s
   // low-rank coefficient terms
   const int r0 = with_su ? 0 : c->Rth;
   const int r1 = with_react ? c->Rth + c->Rc : c->Rth;
+  const bool pointwise = with_react && c->exact_react;   // M_R with C_r at every Gauss point
   kprof_gather_class(K_EXPAND);
   struct Reset { ~Reset() { kprof_gather_class(K_GATHER); } } reset_cls;
-  if (r1 <= r0) return;
+  if (r1 <= r0 && !pointwise) return;
   const Tab* ex[3] = {&c->Bq[0][0], &c->Bq[1][0], &c->Bq[2][0]};
   const Tab* pr[3] = {&c->BqT[0], &c->BqT[1], &c->BqT[2]};
   const int qd[3] = {c->Q[0], c->Q[1], c->Q[2]};
@@ -867,7 +912,7 @@ void apply_impl(st_iga_ctx* c, const S* x, S* y, int L, int in_base, bool with_s
   S* bufB = W2;
   const C* Tr = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->Tr) : reinterpret_cast<const C*>(c->Tr_f);
   const int p = P.p_t;
-  if (c->cf) {
+  if (c->cf && !pointwise) {
     // expand along the faster axes, then one fused kernel along the slowest
     const C* Bl = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->cf_Bl_d)
                                                  : reinterpret_cast<const C*>(c->cf_Bl_f);
@@ -914,7 +959,13 @@ void apply_impl(st_iga_ctx* c, const S* x, S* y, int L, int in_base, bool with_s
     const S* xs = x + static_cast<int64_t>(lo) * Ns;
     if (d == 1) gather<S, S, C>(Ops<S, C>::tab(*ex[0]), xs, Z, nl, 1, nn[0], 0, C(1), C(0), s);
     else spatial_chain<S, C>(c, ex, xs, nl, nn, qd, bufA, bufB, Z, C(1), C(0), s);
-    time_mix<S, C>(Tr, B.Psi, r0, r1, c->NtP, t0, t1, p, Z, nl, in_base + lo, W2, c->Qs, s);
+    if (r1 > r0) time_mix<S, C>(Tr, B.Psi, r0, r1, c->NtP, t0, t1, p, Z, nl, in_base + lo, W2, c->Qs, s);
+    if (pointwise) {
+      const C* Cq = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->Cq_d)
+                                                   : reinterpret_cast<const C*>(c->Cq_f);
+      react_point<S, C>(Z, nl, in_base + lo, Ops<S, C>::tab(c->Bt0), c->re0, c->re1, Cq, c->Qs, t0, t1, p, W2,
+                        r1 > r0 ? C(1) : C(0), s);
+    }
     S* ys = y + static_cast<int64_t>(t0) * Ns;
     if (d == 1) gather<S, S, C>(Ops<S, C>::tab(*pr[0]), W2, ys, t1 - t0, 1, qd[0], 0, C(1), C(1), s);
     else spatial_chain<S, C>(c, pr, W2, t1 - t0, qd, nn, Z, (d == 3 ? W2 : Z), ys, C(1), C(1), s);
@@ -1574,10 +1625,11 @@ void quad_pass_fused(st_iga_ctx* c, const double* u, const double* w, bool want_
         x2 ? quad_fused(d, P.p_s, nq, Xa, nullptr, Xb, Xt, Xw, nd, Qin, ne, c->cf_Bl_d, c->cf_B2_d, c->cf_first,
                         c->cf_chunks, c->cf_nchunk, c->wq_t + q0, c->qf_win, c->qf_wd, sL, sM, sF, P.Cm, P.a, P.c1,
                         P.c2, want_res ? Gp : nullptr, want_theta ? Mp : nullptr, neld, c->part, boff, s, n2, Q1,
-                        F0d.coef, F2d.coef, F0d.c0)
+                        F0d.coef, F2d.coef, F0d.c0, c->src, q0, c->cq_out, c->Qs)
            : quad_fused(d, P.p_s, nq, in[0], in[1], in[2], in[3], in[4], nd, Qin, ne, c->cf_Bl_d, c->cf_B2_d,
                         c->cf_first, c->cf_chunks, c->cf_nchunk, c->wq_t + q0, c->qf_win, c->qf_wd, sL, sM, sF, P.Cm,
-                        P.a, P.c1, P.c2, want_res ? Gp : nullptr, want_theta ? Mp : nullptr, neld, c->part, boff, s);
+                        P.a, P.c1, P.c2, want_res ? Gp : nullptr, want_theta ? Mp : nullptr, neld, c->part, boff, s,
+                        0, 1, nullptr, nullptr, nullptr, c->src, q0, c->cq_out, c->Qs);
     if (nb < 0) throw Fail{ST_IGA_EINVAL, "fused quadrature pass: unsupported degrees"};
     boff += nb;
     if (want_theta) {
@@ -1678,7 +1730,7 @@ void quad_pass(st_iga_ctx* c, const double* u, const double* w, bool want_res, b
     }
     const int nbp = static_cast<int>((static_cast<int64_t>(nqc) * Qs + 255) / 256);
     pointwise_ionic(uq, utq, lap, wq, c->wq_t + q0, c->wq_s, Qs, nqc, P.Cm, P.a, P.c1, P.c2, g, absR,
-                    part_u + boff, nbp, s);
+                    part_u + boff, nbp, s, c->src, q0, c->Q[0], c->Q[1], c->cq_out);
     // the kernel writes [2b], [2b+1] pairs: keep them interleaved in part_u region
     boff += 2 * nbp;
     if (want_theta) {
@@ -1898,6 +1950,10 @@ void linearize(st_iga_ctx* c, const double* u, const double* w, bool refresh_the
                bool with_residual = false) {
   const bool newton = c->opt.outer == 0;
   c->rfull_u = c->rfull_w = nullptr;
+  // exact C_r: the quadrature pass at (u, w) also writes omega C_r at every Gauss point
+  c->cq_out = c->exact_react ? c->Cq_d : nullptr;
+  struct ClearCq { st_iga_ctx* c; ~ClearCq() { c->cq_out = nullptr; } } clear_cq{c};
+  bool cq_done = false;
   if (c->opt.su && refresh_theta) {
     // one quadrature pass gives the theta maxima and, on request, the ionic
     // part of the residual at the same (u, w)
@@ -1906,6 +1962,7 @@ void linearize(st_iga_ctx* c, const double* u, const double* w, bool refresh_the
       c->rfull_u = u;
       c->rfull_w = w;
     }
+    cq_done = true;
     c->Rth = lowrank(c, c->grid, c->opt.eps_theta, c->Uth_h, c->sth_h, c->Vth, s);
     c->err_th = c->lr_relerr;
     c->cap_th = c->lr_capped;
@@ -1914,12 +1971,27 @@ void linearize(st_iga_ctx* c, const double* u, const double* w, bool refresh_the
     c->err_th = 0.0;
     c->cap_th = false;
   }
-  greville_values(c, u, c->grid, s);
-  greville_values(c, w, c->grid2, s);
-  react_grid(c->grid, c->grid2, c->Cg, c->nunk, c->P.a, c->P.c1, c->P.c2, newton ? 1 : 0, s);
-  c->Rc = lowrank(c, c->Cg, c->opt.eps_react, c->Uc_h, c->sc_h, c->Vc, s);
-  c->err_c = c->lr_relerr;
-  c->cap_c = c->lr_capped;
+  if (c->exact_react) {
+    if (!cq_done) {
+      quad_pass(c, u, w, with_residual, false, s);
+      if (with_residual) {
+        c->rfull_u = u;
+        c->rfull_w = w;
+      }
+    }
+    if (c->Cq_f)
+      convert<double, float>(c->Cq_d, c->Cq_f, static_cast<int64_t>(c->dir[c->d].Q) * c->Qs, s);
+    c->Rc = 0;
+    c->err_c = 0.0;
+    c->cap_c = false;
+  } else {
+    greville_values(c, u, c->grid, s);
+    greville_values(c, w, c->grid2, s);
+    react_grid(c->grid, c->grid2, c->Cg, c->nunk, c->P.a, c->P.c1, c->P.c2, newton ? 1 : 0, s);
+    c->Rc = lowrank(c, c->Cg, c->opt.eps_react, c->Uc_h, c->sc_h, c->Vc, s);
+    c->err_c = c->lr_relerr;
+    c->cap_c = c->lr_capped;
+  }
   rebuild_coefficients(c, s);
 }
 
@@ -1963,6 +2035,34 @@ std::vector<double> lift_host(st_iga_ctx* c, const st_iga_stimulus* st, int64_t*
   }
   if (count) *count = cnt;
   return c0;
+}
+
+// Validate the source fields of a stimulus and make them the context's f.
+void set_source(st_iga_ctx* c, const st_iga_stimulus* st) {
+  Source f;
+  if (st->f_kind != 0) {
+    if (st->f_kind != 1 && st->f_kind != 2) throw Fail{ST_IGA_EINVAL, "unknown source kind"};
+    if (!(st->f_t0 <= st->f_t1)) throw Fail{ST_IGA_EINVAL, "source time window needs f_t0 <= f_t1"};
+    if (!std::isfinite(st->f_amp)) throw Fail{ST_IGA_EINVAL, "source amplitude must be finite"};
+    if (st->f_kind == 1 && !(st->f_radius > 0)) throw Fail{ST_IGA_EINVAL, "source radius must be positive"};
+    if (st->f_kind == 2 && !(st->f_kappa > 0)) throw Fail{ST_IGA_EINVAL, "source kappa must be positive"};
+    f.kind = st->f_kind;
+    f.d = c->d;
+    f.Q1 = c->Q[0];
+    for (int l = 0; l < 3; ++l) {
+      f.c[l] = st->f_center[l];
+      f.v[l] = st->f_kind == 2 ? st->f_velocity[l] : 0.0;
+      f.xq[l] = c->xq_dev[l];
+    }
+    f.r2 = st->f_radius * st->f_radius;
+    f.t0 = st->f_t0;
+    f.t1 = st->f_t1;
+    f.amp = st->f_amp;
+    f.kappa = st->f_kappa;
+    f.tq = c->tq_dev;
+  }
+  c->src = f;
+  c->rfull_u = c->rfull_w = nullptr;   // a residual cached for the old source is stale
 }
 
 template <class F>
@@ -2102,6 +2202,11 @@ st_iga_status st_iga_get_factors(st_iga_ctx* c, int32_t* rt, double* Ut, double*
   });
 }
 
+st_iga_status st_iga_set_stimulus(st_iga_ctx* c, const st_iga_stimulus* stim) {
+  if (!c || !stim) return ST_IGA_EINVAL;
+  return guard(c, [&] { set_source(c, stim); });
+}
+
 st_iga_status st_iga_theta_grid(st_iga_ctx* c, const double* u, const double* w, double* th, void* stream) {
   if (!c || !u || !w || !th) return ST_IGA_EINVAL;
   return guard(c, [&] {
@@ -2214,19 +2319,23 @@ st_iga_status st_iga_solve(st_iga_ctx* c, const st_iga_stimulus* stim, double* u
                            void* stream) {
   if (!c || !stim || !u || !w) return ST_IGA_EINVAL;
   return guard(c, [&] {
-    if (stim->f_kind != 0) throw Fail{ST_IGA_EINVAL, "source terms are not supported"};
+    set_source(c, stim);
     hipStream_t s = static_cast<hipStream_t>(stream);
     st_iga_report R;
     std::memset(&R, 0, sizeof(R));
     std::vector<double> c0 = lift_host(c, stim, nullptr);
     for (int k = 0; k < c->nt; ++k)
       CK(hipMemcpyAsync(u + static_cast<int64_t>(k) * c->Ns, c0.data(), c->Ns * sizeof(double), hipMemcpyHostToDevice, s));
+    // the fixed-point scheme of Section 3.1 (outer = 2) carries w as a
+    // relaxed iterate from w^0 = 0; the other schemes lag w = w(u^k)
+    const bool paper_fp = c->opt.outer == 2;
+    if (paper_fp) fill(w, 0.0, c->nfull, s);
     CK(hipStreamSynchronize(s));
     bool frozen = false;
     bool converged = false;
     for (int k = 0; k < c->opt.max_outer; ++k) {
       auto t0 = std::chrono::steady_clock::now();
-      w_update(c, u, w, s);
+      if (!paper_fp) w_update(c, u, w, s);
       linearize(c, u, w, c->opt.su && !frozen, s, true);
       residual(c, u, w, c->sol_rhs, s);
       axpby(-1.0, c->sol_rhs, 0.0, c->sol_rhs, c->nunk, s);   // rhs = -N(u)
@@ -2239,6 +2348,12 @@ st_iga_status st_iga_solve(st_iga_ctx* c, const st_iga_stimulus* stim, double* u
       if (c->opt.lin_forcing > 0.0 && k > 0)
         tol_k = std::max(c->opt.tol_lin, std::min(1e-2, c->opt.lin_forcing * R.delta_inf[std::min(k - 1, ST_IGA_MAX_OUTER_LOG - 1)]));
       const int it = krylov(c, c->sol_rhs, c->sol_dx, tol_k, &rr, s);
+      if (paper_fp) {
+        // w~ from L w~ = G(u^k), then w^{k+1} = alpha w~ + (1 - alpha) w^k
+        // (t4[3] is free once the linear solve has finished)
+        w_update(c, u, c->t4[3], s);
+        axpby(c->opt.alpha, c->t4[3], 1.0 - c->opt.alpha, w, c->nfull, s);
+      }
       add_unknowns(u, c->sol_dx, c->opt.alpha, c->nunk, c->Ns, s);
       const double dinf = c->opt.alpha * dev_absmax(c, c->sol_dx, c->nunk, s);
       auto t2 = std::chrono::steady_clock::now();
@@ -2263,7 +2378,7 @@ st_iga_status st_iga_solve(st_iga_ctx* c, const st_iga_stimulus* stim, double* u
         break;
       }
     }
-    w_update(c, u, w, s);
+    if (!paper_fp) w_update(c, u, w, s);
     CK(hipStreamSynchronize(s));
     if (rep) *rep = R;
     if (!converged) throw Fail{ST_IGA_ENOCONV, "outer iteration limit reached"};

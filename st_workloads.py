@@ -53,6 +53,17 @@ class Problem:
     u0_center: Tuple[float, ...] = (0.0, 0.0, 0.0)
     u0_radius: float = 0.1
     u0_value: float = 1.0
+    # source f of the monodomain equation (0: none; 1: f_amp on the closed ball
+    # |x - f_center| <= f_radius for t in [f_t0, f_t1]; 2: moving Gaussian
+    # f_amp exp(-f_kappa |x - f_center - f_velocity t|^2) for t in [f_t0, f_t1])
+    f_kind: int = 0
+    f_center: Tuple[float, ...] = (0.0, 0.0, 0.0)
+    f_radius: float = 0.0
+    f_t0: float = 0.0
+    f_t1: float = 0.0
+    f_amp: float = 0.0
+    f_kappa: float = 0.0
+    f_velocity: Tuple[float, ...] = (0.0, 0.0, 0.0)
 
     @property
     def n_s(self):
@@ -95,6 +106,48 @@ class Problem:
         c = np.asarray(self.u0_center[: self.d])
         r2 = np.sum((pts - c) ** 2, axis=1)
         return np.where(r2 <= self.u0_radius ** 2, self.u0_value, 0.0)
+
+
+    def source(self, xs, t):
+        """Source f at points: xs is a list of d coordinate arrays, t an array
+        of the same shape (absolute times); None when there is no source."""
+        t = np.asarray(t, dtype=np.float64)
+        if self.f_kind == 0:
+            return np.zeros_like(t)
+        r2 = np.zeros_like(t)
+        for l in range(self.d):
+            dx = np.asarray(xs[l], dtype=np.float64) - self.f_center[l]
+            if self.f_kind == 2:
+                dx = dx - self.f_velocity[l] * t
+            r2 = r2 + dx * dx
+        on = (t >= self.f_t0) & (t <= self.f_t1)
+        if self.f_kind == 1:
+            val = np.where(r2 <= self.f_radius * self.f_radius, self.f_amp, 0.0)
+        else:
+            val = self.f_amp * np.exp(-self.f_kappa * r2)
+        return np.where(on, val, 0.0)
+
+
+def clustered_time_knots(nel_t: int, p: int, events, width: float):
+    """Open knot vector on [0,1] with nel_t elements: p+1 interior knots
+    clustered (spacing `width`) around each event time, the remaining interior
+    knots evenly spaced, none coinciding (maximal regularity in time)."""
+    cl = []
+    for te in events:
+        cl.extend(te + (np.arange(p + 1) - 0.5 * p) * width)
+    m = nel_t - 1 - len(cl)
+    if m < 0:
+        raise ValueError("too few elements for the clusters")
+    cl = np.array(cl)
+    even = (np.arange(m) + 1.0) / (m + 1.0)
+    # keep the even knots away from the clusters (at least one cluster width)
+    for te in events:
+        near = np.abs(even - te) < (0.5 * p + 1.0) * width
+        even[near] = np.where(even[near] < te, te - (0.5 * p + 1.0) * width, te + (0.5 * p + 1.0) * width)
+    inner = np.sort(np.concatenate([cl, even]))
+    if np.any(np.diff(inner) <= 0.25 * width) or inner[0] <= 0 or inner[-1] >= 1:
+        raise ValueError("knots too close")
+    return np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)])
 
 
 _RM = rm_paper_params()

@@ -2,7 +2,10 @@
 
 Config 1 (2D, p=3, 64^2 x 64): full vectors against the oracle's tensor
 evaluator.  Config 2 (3D, p=2, 48^3 x 48): sampled rows against the oracle's
-local-quadrature evaluator, plus properties that hold at any size."""
+local-quadrature evaluator, the whole theta grid of a linearization against
+the oracle's tensor evaluator, plus properties that hold at any size.
+Config 4 (3D, p=3, 96^3 x 128, at most 16 terms per low rank): sampled rows
+of the operator, the preconditioner and a Krylov solution."""
 import gc
 
 import numpy as np
@@ -194,5 +197,96 @@ def test_cfg2_lowp_operator_error(gpu_lib, torch, prec, bound_a, bound_p):
     ep = float(torch.linalg.norm(zlp - z64) / torch.linalg.norm(z64))
     assert ea < bound_a and ep < bound_p, (ea, ep)
     del S
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(900)
+def test_cfg2_linearization_full_theta(gpu_lib, torch):
+    """A linearization at a front-shaped state: every theta entry of eq. (3.4)
+    against the oracle's tensor evaluator, identical truncated-SVD ranks and
+    products, and sampled rows of the residual N(u) (with the oracle's own
+    theta factors)."""
+    from oracle.spacetime import truncated_svd
+    prob = W.config(2)
+    u, w = W.smooth_state(prob, 23, noise=0.0)
+    st = SpaceTime(prob, mode="tensor")
+    th_o = st.theta_grid(u, w)
+    del st
+    gc.collect()
+    S = make(prob)
+    ud, wd = dev(torch, u), dev(torch, w)
+    th_g = S.theta_grid(ud, wd).cpu().numpy().reshape(th_o.shape)
+    assert np.max(np.abs(th_g - th_o)) < 1e-12
+    S.linearize(ud, wd)
+    (gt, gc_) = S.get_factors()
+    Rt, Ut, st_, Vt = truncated_svd(th_o, 0.1)
+    assert len(gt[1]) == Rt
+    assert np.linalg.norm((gt[0] * gt[1]) @ gt[2].T - (Ut * st_) @ Vt.T) <= 1e-11 * np.linalg.norm(th_o)
+    r = S.residual(ud, wd).cpu().numpy()
+    rows = np.random.default_rng(4).choice(prob.unknowns, 64, replace=False)
+    want = RowSampler(prob).residual_rows(u, w, rows, theta=(Ut, st_, Vt))
+    assert np.max(np.abs(r[rows] - want)) < 1e-11 * np.max(np.abs(r))
+    del S
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+# ----------------------------------------------------------------- config 4
+ROWS4 = 48
+
+
+@pytest.fixture(scope="module")
+def cfg4():
+    prob = W.config(4)
+    return prob, RowSampler(prob)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
+def test_cfg4_apply_precond_sampled_rows(gpu_lib, torch, cfg4, prec):
+    """FP64 operator and preconditioner (A-hat z = r) on sampled rows; in the
+    mixed context also the FP32 operator, within a modest multiple of the
+    FP32 unit roundoff of the largest entry."""
+    from paper_2311_17500_amd.binding import FP64, MIXED_FP32
+    prob, rs = cfg4
+    S = make(prob, prec={"fp64": FP64, "mixed_fp32": MIXED_FP32}[prec], max_rank=16)
+    ft, fc = W.random_factors(prob, 2, 41), W.random_factors(prob, 3, 42, scale=5.0)
+    S.set_factors(ft, fc)
+    x = W.random_vector(prob.unknowns, 43)
+    xd = dev(torch, x)
+    rows = np.random.default_rng(5).choice(prob.unknowns, ROWS4, replace=False)
+    want = rs.apply_rows(x, rows, theta=ft, coef=fc)
+    y = S.apply(xd).cpu().numpy()
+    ymax = np.max(np.abs(y))
+    assert np.max(np.abs(y[rows] - want)) < 1e-12 * ymax
+    if prec == "mixed_fp32":
+        yl = S.apply_lowp(xd).cpu().numpy()
+        assert np.max(np.abs(yl[rows] - want)) < 1e-5 * ymax
+    del y
+    z = S.precond(xd).cpu().numpy()
+    Az = rs.apply_rows(z, rows, coef_const=prob.a * prob.c1)
+    assert np.max(np.abs(Az - x[rows])) < 1e-10 * np.max(np.abs(x))
+    del S, z, xd
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(900)
+def test_cfg4_mixed_krylov(gpu_lib, torch, cfg4):
+    """Mixed FP32 solve at full size: the reported FP64 true residual meets
+    1e-8 and sampled rows of b - J x from the oracle are consistent with it."""
+    from paper_2311_17500_amd.binding import MIXED_FP32
+    prob, rs = cfg4
+    S = make(prob, prec=MIXED_FP32, max_rank=16)
+    ft, fc = W.coefficient_factors(prob, 2, 44, base=0.3), W.coefficient_factors(prob, 3, 45)
+    S.set_factors(ft, fc)
+    b = W.random_vector(prob.unknowns, 46)
+    xs, it, rr = S.krylov(dev(torch, b), tol=1e-8)
+    assert rr <= 1e-8
+    rows = np.random.default_rng(6).choice(prob.unknowns, ROWS4, replace=False)
+    res_rows = b[rows] - rs.apply_rows(xs.cpu().numpy(), rows, theta=ft, coef=fc)
+    assert np.max(np.abs(res_rows)) <= 1.01e-8 * np.linalg.norm(b)
+    del S, xs
     gc.collect()
     torch.cuda.empty_cache()

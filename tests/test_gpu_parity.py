@@ -15,7 +15,9 @@ SMALL = [("1d_p2", W.tiny(1, 2, 9, nel_t=7)),
          ("2d_p3", W.tiny(2, 3, 5, nel_t=6)),
          ("3d_p2", W.tiny(3, 2, 3, nel_t=5)),
          ("3d_p1", W.tiny(3, 1, 4, nel_t=4)),
-         ("cfg0", W.config(0))]
+         ("cfg0", W.config(0)),
+         ("3d_p3", W.tiny(3, 3, 3, nel_t=4)),
+         ("3d_p3_small", W.tiny(3, 3, 2, nel_t=3))]
 
 
 def rel(a, b):
@@ -43,7 +45,7 @@ def lowrank_product(f):
     return (U * s) @ V.T
 
 
-@pytest.mark.parametrize("name,prob", SMALL, ids=[n for n, _ in SMALL])
+@pytest.mark.parametrize("name,prob", SMALL[:6], ids=[n for n, _ in SMALL[:6]])
 def test_lift_bit_exact(gpu_lib, name, prob):
     S = solver_for(prob)
     st = SpaceTime(prob)
@@ -52,7 +54,7 @@ def test_lift_bit_exact(gpu_lib, name, prob):
     assert np.array_equal(c0, want) and cnt == int(np.sum(want != 0))
 
 
-@pytest.mark.parametrize("name,prob", SMALL, ids=[n for n, _ in SMALL])
+@pytest.mark.parametrize("name,prob", SMALL[:6], ids=[n for n, _ in SMALL[:6]])
 def test_theta_grid(gpu_lib, torch, name, prob):
     S = solver_for(prob)
     st = SpaceTime(prob)
@@ -62,7 +64,7 @@ def test_theta_grid(gpu_lib, torch, name, prob):
     assert np.max(np.abs(got - want)) < 1e-12
 
 
-@pytest.mark.parametrize("name,prob", SMALL, ids=[n for n, _ in SMALL])
+@pytest.mark.parametrize("name,prob", SMALL[:6], ids=[n for n, _ in SMALL[:6]])
 def test_linearize_apply(gpu_lib, torch, name, prob):
     """Linearization (theta, reaction coefficient, low ranks) and y = J x."""
     S = solver_for(prob)
@@ -80,7 +82,7 @@ def test_linearize_apply(gpu_lib, torch, name, prob):
     assert rel(y, st.apply_J(x, lin.coef_q, lin.theta_q)) < 1e-11
 
 
-@pytest.mark.parametrize("name,prob", SMALL, ids=[n for n, _ in SMALL])
+@pytest.mark.parametrize("name,prob", SMALL[:6], ids=[n for n, _ in SMALL[:6]])
 def test_apply_with_given_factors(gpu_lib, torch, name, prob):
     S = solver_for(prob)
     st = SpaceTime(prob)
@@ -94,16 +96,20 @@ def test_apply_with_given_factors(gpu_lib, torch, name, prob):
     assert rel(y, st.apply_J(x, cq, thq)) < 1e-12
 
 
-@pytest.mark.parametrize("name,prob", SMALL, ids=[n for n, _ in SMALL])
+@pytest.mark.parametrize("name,prob", SMALL[:6], ids=[n for n, _ in SMALL[:6]])
 def test_precond(gpu_lib, torch, name, prob):
+    """z = A-hat^{-1} r against the oracle's direct solve.  Both are backward
+    stable, so they differ by a few times cond(A-hat) times the unit roundoff
+    (cond = 2.2e5 for the 3D p = 3 case, <= 1e4 for the others)."""
     S = solver_for(prob)
     st = SpaceTime(prob)
     r = W.random_vector(prob.unknowns, 13)
     z = S.precond(to_dev(torch, r)).cpu().numpy()
-    assert rel(z, solver.precond_solve(st, r)) < 1e-11
+    kappa = np.linalg.cond(st.assemble_precond().toarray()) if prob.unknowns <= 2000 else 1e4
+    assert rel(z, solver.precond_solve(st, r)) < max(1e-11, 20 * kappa * np.finfo(float).eps)
 
 
-@pytest.mark.parametrize("name,prob", SMALL, ids=[n for n, _ in SMALL])
+@pytest.mark.parametrize("name,prob", SMALL[:6], ids=[n for n, _ in SMALL[:6]])
 def test_residual_and_w(gpu_lib, torch, name, prob):
     S = solver_for(prob)
     st = SpaceTime(prob)
@@ -117,7 +123,7 @@ def test_residual_and_w(gpu_lib, torch, name, prob):
     assert rel(r, st.residual(u, w, lin.theta_q)) < 1e-11
 
 
-@pytest.mark.parametrize("name,prob", SMALL, ids=[n for n, _ in SMALL])
+@pytest.mark.parametrize("name,prob", SMALL[:6], ids=[n for n, _ in SMALL[:6]])
 def test_krylov_solve(gpu_lib, torch, name, prob):
     import scipy.sparse.linalg as spla
     S = solver_for(prob)
@@ -127,9 +133,32 @@ def test_krylov_solve(gpu_lib, torch, name, prob):
     lin = solver.linearize(st, u, w)
     b = W.random_vector(prob.unknowns, 14)
     x, it, rr = S.krylov(to_dev(torch, b), tol=1e-12)
-    want = spla.splu(st.assemble_J(lin.coef_q, lin.theta_q).tocsc()).solve(b)
+    J = st.assemble_J(lin.coef_q, lin.theta_q)
+    want = spla.splu(J.tocsc()).solve(b)
     assert rr <= 1e-12 and it > 0
-    assert rel(x.cpu().numpy(), want) < 1e-9
+    # forward error <= cond(J) x relative residual (cond(J) = 4.6e4 for the
+    # 3D p = 3 case, <= 3e3 for the others)
+    kappa = np.linalg.cond(J.toarray()) if prob.unknowns <= 2000 else 1e3
+    assert rel(x.cpu().numpy(), want) < max(1e-9, kappa * 1e-12)
+
+
+def test_nonlinear_steps_3d_p3(gpu_lib, torch):
+    """The outer loop at d = 3, p = 3 (w-update, theta refreshed, both low
+    ranks, residual, Krylov solve, update) for three iterations from the
+    lifted datum, against the oracle's first three iterations (the oracle's
+    explicit 3D p = 3 assembly is too slow for a converged solve here)."""
+    prob = SMALL[6][1]
+    st = SpaceTime(prob)
+    uo, wo, log = solver.solve(st, tol=1e-11, max_outer=3)
+    S = solver_for(prob, tol_lin=1e-12)
+    c0, _ = S.lift()
+    u = to_dev(torch, np.tile(c0, prob.n_t))
+    w = S.vec(S.full)
+    for k in range(3):
+        it, rr, dinf = S.newton_step(u, u, w, refresh_theta=True, tol=1e-12)
+        assert rr <= 1e-12 and dinf == pytest.approx(log.deltas[k], rel=1e-8)
+    assert rel(u.cpu().numpy(), uo) < 1e-10
+    assert rel(S.w_update(u).cpu().numpy(), wo) < 1e-10
 
 
 @pytest.mark.parametrize("name,prob", [SMALL[0], SMALL[1], SMALL[4]], ids=["1d_p2", "2d_p3", "cfg0"])
@@ -314,3 +343,153 @@ def test_full_nonlinear_solve_mixed(gpu_lib, prec):
     assert abs(rep.outer_iters - len(log.deltas)) <= 1
     assert rel(u.cpu().numpy(), uo) < 1e-8
     assert rel(w.cpu().numpy(), wo) < 1e-8
+
+
+def test_zero_datum_gives_zero(gpu_lib):
+    """u0 = 0 and no source: I_ion(0, 0) = 0, so u = w = 0 exactly, theta's
+    denominator is 0 (Theta = 0, rank 0) and one outer iteration suffices."""
+    prob = W.tiny(2, 2, 5, nel_t=4, u0_kind=0)
+    S = solver_for(prob)
+    u, w, rep = S.solve()
+    assert rep.outer_iters == 1 and rep.rank_theta[0] == 0
+    assert not np.any(u.cpu().numpy()) and not np.any(w.cpu().numpy())
+
+
+def test_zero_shift_preconditioner(gpu_lib, torch):
+    """a c1 = 0: with an odd N_t - 1 the zero-frequency time block meets the
+    constant Neumann mode (a zero pivot of the arrowhead), which setup rejects
+    with EINVAL; with an even N_t - 1 every block is invertible and the
+    preconditioner still equals the oracle's direct solve."""
+    from paper_2311_17500_amd.binding import StIgaError, EINVAL
+    odd = W.tiny(1, 2, 9, nel_t=7, c1=0.0)
+    assert (odd.N_t - 1) % 2 == 1
+    with pytest.raises(StIgaError) as e:
+        solver_for(odd)
+    assert e.value.code == EINVAL
+    even = W.tiny(1, 2, 9, nel_t=6, c1=0.0)
+    assert (even.N_t - 1) % 2 == 0
+    S = solver_for(even)
+    st = SpaceTime(even)
+    r = W.random_vector(even.unknowns, 31)
+    z = S.precond(to_dev(torch, r)).cpu().numpy()
+    assert rel(z, solver.precond_solve(st, r)) < 1e-10
+
+
+# Source-term stimuli of the paper's experiments (Section 4): a ball times a
+# time window and a moving Gaussian times a time window, on time knots
+# clustered around the source's on/off times (Section 4.2.1).
+def _src_case(d, p, kind, nel=5, nel_t=12):
+    kw = dict(u0_kind=0, f_kind=kind, f_t0=0.25, f_t1=0.45, f_amp=2.0)
+    if kind == 1:
+        kw.update(f_center=(0.3, 0.4, 0.5), f_radius=0.35)
+    else:
+        kw.update(f_center=(0.1, 0.5, 0.5), f_kappa=20.0, f_velocity=(0.8, 0.0, 0.2))
+    prob = W.tiny(d, p, nel, nel_t=nel_t, **kw)
+    kn = prob.uniform_knots()
+    kn[d] = W.clustered_time_knots(nel_t, p, [0.25, 0.45], 0.01)
+    return prob, kn
+
+
+SRC = [("1d_ball", 1, 2, 1), ("2d_gauss", 2, 3, 2), ("3d_ball", 3, 2, 1), ("3d_gauss_p3", 3, 3, 2)]
+
+
+@pytest.mark.parametrize("name,d,p,kind", SRC, ids=[c[0] for c in SRC])
+def test_source_theta_and_residual(gpu_lib, torch, name, d, p, kind):
+    """Theta (residual -f inside eq. (3.4)) and N(u) (with -int f v) against
+    the oracle on clustered time knots, at a non-trivial state."""
+    prob, kn = _src_case(d, p, kind, nel=4 if d == 3 else 6, nel_t=10)
+    st = SpaceTime(prob, knots=kn)
+    S = solver_for(prob, knots=kn)
+    u, w = W.smooth_state(prob, 12)
+    ud, wd = to_dev(torch, u), to_dev(torch, w)
+    th = S.theta_grid(ud, wd).cpu().numpy()
+    assert np.max(np.abs(th - st.theta_grid(u, w).reshape(-1))) < 1e-12
+    S.linearize(ud, wd)
+    lin = solver.linearize(st, u, w)
+    assert len(S.get_factors()[0][1]) == lin.theta_lr.R
+    r = S.residual(ud, wd).cpu().numpy()
+    assert rel(r, st.residual(u, w, lin.theta_q)) < 1e-11
+
+
+@pytest.mark.parametrize("name,d,p,kind", [("1d_ball", 1, 2, 1), ("2d_gauss_p2", 2, 2, 2)],
+                         ids=["1d_ball", "2d_gauss_p2"])
+def test_source_driven_solve(gpu_lib, name, d, p, kind):
+    """The paper's setting: zero initial datum, the excitation comes from the
+    source.  Whole nonlinear solve on clustered time knots against the
+    oracle's loop."""
+    prob, kn = _src_case(d, p, kind, nel=8 if d == 1 else 4, nel_t=12)
+    S = solver_for(prob, knots=kn, tol_nonlin=1e-11, tol_lin=1e-12)
+    st = SpaceTime(prob, knots=kn)
+    u, w, rep = S.solve()
+    uo, wo, log = solver.solve(st, tol=1e-11)
+    assert np.max(np.abs(uo)) > 0.1          # the source excites the tissue
+    assert rep.outer_iters == len(log.deltas)
+    assert rel(u.cpu().numpy(), uo) < 1e-10
+    assert rel(w.cpu().numpy(), wo) < 1e-10
+
+
+# The fixed-point scheme of Section 3.1 as the paper states it (outer = 2):
+# M_R with the exact C_r(u^k, w^k) at every Gauss point, u and w relaxed.
+@pytest.mark.parametrize("name,prob", [SMALL[0], SMALL[1], SMALL[2]], ids=["1d_p2", "2d_p3", "3d_p2"])
+def test_linearize_exact_reaction(gpu_lib, torch, name, prob):
+    """J with the exact C_r at the Gauss points (no low rank) and the low-rank
+    theta, in FP64 and in the FP32 operator of a mixed context."""
+    from paper_2311_17500_amd.binding import MIXED_FP32
+    st = SpaceTime(prob)
+    u, w = W.smooth_state(prob, 7)
+    th = st.lowrank(st.theta_grid(u, w), 0.1)
+    want_x = W.random_vector(prob.unknowns, 22)
+    want = st.apply_J(want_x, st.reaction_at_quad(u, w), st.lowrank_at_quad(th))
+    S = solver_for(prob, outer=2, alpha=0.5, prec=MIXED_FP32)
+    S.linearize(to_dev(torch, u), to_dev(torch, w))
+    gt, gc = S.get_factors()
+    assert len(gt[1]) == th.R and len(gc[1]) == 0
+    xd = to_dev(torch, want_x)
+    assert rel(S.apply(xd).cpu().numpy(), want) < 1e-11
+    assert rel(S.apply_lowp(xd).cpu().numpy(), want) < 1e-5
+
+
+@pytest.mark.parametrize("name,prob", [SMALL[0], SMALL[4]], ids=["1d_p2", "cfg0"])
+def test_paper_picard_solve(gpu_lib, name, prob):
+    """The whole fixed-point loop with the paper's stopping rule (change of
+    the iterate <= 1e-4, theta refreshed every iteration): same number of
+    iterations and the same final (u, w) as the oracle's literal scheme."""
+    S = solver_for(prob, outer=2, alpha=0.5, tol_nonlin=1e-4, tol_lin=1e-12, max_outer=200)
+    st = SpaceTime(prob)
+    u, w, rep = S.solve()
+    uo, wo, log = solver.solve_picard(st, tol=1e-4, max_outer=200)
+    assert rep.outer_iters == len(log.deltas)
+    assert list(rep.rank_theta[: rep.outer_iters]) == log.ranks_theta[:64]
+    assert rel(u.cpu().numpy(), uo) < 1e-10
+    assert rel(w.cpu().numpy(), wo) < 1e-10
+
+
+def test_paper_picard_tight(gpu_lib):
+    """The same scheme run to 1e-11 with theta frozen below 1e-4 on both sides."""
+    prob = SMALL[1][1]
+    S = solver_for(prob, outer=2, alpha=0.5, tol_nonlin=1e-11, tol_lin=1e-12, max_outer=300)
+    st = SpaceTime(prob)
+    u, w, rep = S.solve()
+    uo, wo, log = solver.solve_picard(st, tol=1e-11, max_outer=300, theta_freeze=1e-4)
+    assert rep.outer_iters == len(log.deltas)
+    assert rel(u.cpu().numpy(), uo) < 1e-10
+    assert rel(w.cpu().numpy(), wo) < 1e-10
+
+
+@pytest.mark.parametrize("outer", [0, 2])
+def test_galerkin_solve(gpu_lib, outer):
+    """Plain Galerkin (su = 0, no stabilization term): Newton with lagged w,
+    and the paper's fixed-point scheme, against the oracle without SU."""
+    prob = SMALL[0][1]
+    st = SpaceTime(prob, su=False)
+    if outer == 0:
+        S = solver_for(prob, su=0, tol_nonlin=1e-11, tol_lin=1e-12)
+        uo, wo, log = solver.solve(st, tol=1e-11)
+    else:
+        S = solver_for(prob, su=0, outer=2, alpha=0.5, tol_nonlin=1e-11, tol_lin=1e-12, max_outer=300)
+        uo, wo, log = solver.solve_picard(st, tol=1e-11, max_outer=300)
+    u, w, rep = S.solve()
+    assert rep.outer_iters == len(log.deltas)
+    assert rep.rank_theta[0] == 0
+    assert rel(u.cpu().numpy(), uo) < 1e-10
+    assert rel(w.cpu().numpy(), wo) < 1e-10

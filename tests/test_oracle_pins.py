@@ -409,3 +409,114 @@ def test_rowsample_matches_full_apply(d, p, nel):
     Ahat = st.assemble_precond() @ x
     got = rs.apply_rows(x, rows, coef_const=P.a * P.c1)
     assert np.allclose(got, Ahat[rows], rtol=1e-12, atol=1e-12 * np.abs(Ahat).max())
+
+
+@pytest.mark.parametrize("d,p,nel,with_f", [(1, 2, 6, False), (2, 3, 4, True), (3, 2, 3, False)])
+def test_rowsample_residual_matches_full(d, p, nel, with_f):
+    """Row-sampled residual N(u) (exact ionic current, optional source) equals
+    the full-grid one."""
+    from oracle.rowsample import RowSampler
+    P = W.tiny(d, p, nel)
+    f = (lambda xs, t: np.exp(-20.0 * sum((x - 0.3) ** 2 for x in xs)) * (t > 0.2)) if with_f else None
+    st = SpaceTime(P, mode="tensor", f=f)
+    ft = W.random_factors(P, 2, 1)
+    u, w = W.smooth_state(P, 4)
+    full = st.residual(u, w, st.lowrank_at_quad(LowRank(*ft)))
+    rows = np.random.default_rng(0).choice(P.unknowns, 25, replace=False)
+    got = RowSampler(P).residual_rows(u, w, rows, theta=ft, f=f)
+    assert np.allclose(got, full[rows], rtol=1e-12, atol=1e-12 * np.abs(full).max())
+
+
+# ---------------------------------------------------------------- source term (eq. (3.1), Section 4 stimuli)
+def test_source_residual_total():
+    """u = w = 0 and f = amp on the whole space-time domain: the residual
+    -int f v summed over the test functions of X_h is -amp |Omega| (T -
+    int b_1), with int b_1 = T h_t / (p + 1) for the first B-spline of an open
+    uniform time knot vector (partition of unity, closed form)."""
+    for d, p in ((1, 2), (2, 3), (3, 2)):
+        P = W.tiny(d, p, 3, nel_t=5, T=2.0, u0_kind=0, f_kind=1, f_center=(0.5, 0.5, 0.5), f_radius=10.0,
+                   f_t0=0.0, f_t1=2.0, f_amp=0.7)
+        st = SpaceTime(P)
+        z = np.zeros(int(np.prod(st.shape)))
+        r = st.residual(z, z, None)
+        want = -0.7 * 1.0 * (P.T - P.T * (1.0 / P.nel_t) / (P.p_t + 1))
+        assert r.sum() == pytest.approx(want, rel=1e-13)
+
+
+def test_source_theta_indicator():
+    """u = w = 0 with a localized source: R = -f, the denominator of eq. (3.4)
+    is 0, so Theta is 1 exactly on the windows that contain a Gauss point with
+    f != 0 and 0 elsewhere (brute force over point coordinates)."""
+    P = W.tiny(2, 2, 6, nel_t=6, u0_kind=0, f_kind=1, f_center=(0.2, 0.7, 0.0), f_radius=0.15,
+               f_t0=0.3, f_t1=0.5, f_amp=1.0)
+    st = SpaceTime(P)
+    z = np.zeros(int(np.prod(st.shape)))
+    Th = st.theta_grid(z, z)
+    assert set(np.unique(Th)) <= {0.0, 1.0} and Th.max() == 1.0 and Th.min() == 0.0
+    grids = np.meshgrid(st.quad[2][0], st.quad[1][0], st.quad[0][0], indexing="ij")
+    fq = P.source([grids[2], grids[1]], grids[0])
+
+    def window(l, j):
+        kn, p = st.kn[l], st.p[l]
+        return kn[max(j - p, 1) - 1], kn[min(j + p + 1, len(kn)) - 1]
+    for it in range(st.n[2] - 1):
+        for i2 in range(st.n[1]):
+            for i1 in range(st.n[0]):
+                (t0, t1), (a0, a1), (b0, b1) = window(2, it + 2), window(1, i2 + 1), window(0, i1 + 1)
+                m = ((grids[0] > t0) & (grids[0] < t1) & (grids[1] > a0) & (grids[1] < a1)
+                     & (grids[2] > b0) & (grids[2] < b1))
+                assert Th[it, i2 * st.n[0] + i1] == (1.0 if np.any(fq[m] != 0) else 0.0)
+
+
+def test_clustered_time_knots():
+    """p+1 distinct knots around each event, the rest evenly spaced, open and
+    of the requested element count (the graded partition of Section 4.2.1)."""
+    for p in (2, 3):
+        kn = W.clustered_time_knots(24, p, [0.3, 0.6], 0.01)
+        assert len(kn) == 24 + 2 * p + 1
+        inner = kn[p + 1:-p - 1]
+        assert np.all(np.diff(inner) > 0)
+        for te in (0.3, 0.6):
+            assert np.sum(np.abs(inner - te) <= 0.5 * p * 0.01 + 1e-12) == p + 1
+
+
+# ---------------------------------------------------------------- fixed-point scheme of Section 3.1
+def test_picard_defect_identity():
+    """A(u^k, w^k) u^k - F = N(u^k) on the test functions of X_h: with the exact
+    C_r of eq. (3.6) in M_R, C_r(u, w) u = I_ion(u, w) at every Gauss point, so
+    the fixed-point matrix applied to its own linearization point reproduces
+    the residual (the defect form the library solves)."""
+    P = W.tiny(2, 2, 4, nel_t=5, f_kind=1, f_center=(0.2, 0.3, 0.0), f_radius=0.3, f_t0=0.2, f_t1=0.6,
+               f_amp=1.5)
+    st = SpaceTime(P)
+    u, w = W.smooth_state(P, 3)
+    thq = st.lowrank_at_quad(st.lowrank(st.theta_grid(u, w), 0.1))
+    A = st.assemble_full(st.reaction_at_quad(u, w), thq)
+    N_s = P.N_s
+    lhs = (A @ u - st.load_vector())[N_s:]
+    r = st.residual(u, w, thq)
+    assert np.max(np.abs(lhs - r)) <= 1e-13 * np.max(np.abs(r))
+
+
+def test_paper_picard_reaches_newton_solution():
+    """The literal fixed-point scheme (exact C_r, u and w relaxed with
+    alpha = 0.5) and Newton with lagged w reach the same discrete solution
+    when theta is held fixed (same fixed point, different iterations)."""
+    P = W.config(0)
+    st = SpaceTime(P)
+    u0 = np.tile(st.lift(), st.n[1])
+    th = st.lowrank(st.theta_grid(u0, st.w_update_explicit(u0)), 0.1)
+    up, wp, lp = solver.solve_picard(st, tol=1e-12, max_outer=400, theta_lr=th)
+    import oracle.solver as S
+    orig = S.linearize
+
+    def frozen(st_, u, w, eps_theta=0.1, eps_react=1e-2, newton=True, theta_lr=None):
+        return orig(st_, u, w, eps_theta, eps_react, newton, th)
+    S.linearize = frozen
+    try:
+        un, wn, ln = S.solve(st, newton=True, tol=1e-12, max_outer=60)
+    finally:
+        S.linearize = orig
+    assert lp.deltas[-1] <= 1e-12 and ln.deltas[-1] <= 1e-12
+    assert np.max(np.abs(un - up)) < 1e-10
+    assert np.max(np.abs(wn - wp)) < 1e-10
