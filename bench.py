@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--prec", default="mixed_fp32", choices=["fp64", "mixed_fp32", "mixed_bf16"])
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the extra workloads (config 2 in BF16, config 4 mixed FP32) of the default line")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-rank", type=int, default=None,
                     help="cap of each low rank (default 48; 16 for config 4 to fit HBM)")
@@ -106,7 +108,7 @@ def time_region(torch, S, u1, u2, w, steps, warmup, tol):
     return ms, wall / steps * 1e3, its, rr, prof
 
 
-def roofline(prof, steps):
+def roofline(prof, steps, cfg=2):
     """Roofline entry of the kernel function with the largest summed duration:
     achieved rate from the algorithmic bytes (and flops, where recorded) of
     its launches over their HIP-event durations; the bound is the resource it
@@ -120,29 +122,39 @@ def roofline(prof, steps):
     f64 = "<f64>" in name
     hbm_frac = dom_by / sec / PEAK_HBM
     comp_frac, comp_peak, comp_bound = 0.0, None, None
+    nonpacked_frac = None
     if dom_fl > 0:
         mfma = name.startswith("dense_mode_mfma") or name.startswith("time_core")
-        comp_peak = PEAK_FP64 if f64 else (PEAK_FP32 if mfma else PEAK_FP32_VALU)
+        # published peaks: FP64 vector and matrix 78.6, FP32 157.3 TFLOP/s
+        comp_peak = PEAK_FP64 if f64 else PEAK_FP32
         comp_bound = "mfma" if mfma else "alu"
         comp_frac = dom_fl / sec / comp_peak
+        if not f64 and not mfma:
+            # FP32 vector code built without packed FP32 retires one FMA per
+            # lane per cycle: 78.6 TFLOP/s is the rate it can reach
+            nonpacked_frac = dom_fl / sec / PEAK_FP32_VALU
     traffic = None
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
         from paper_2311_17500_amd.profiling import kernel_source_hash
-        if t.get("kernel_source_sha256") == kernel_source_hash() and name in t.get("kernels", {}):
-            traffic = t["kernels"][name]["hbm_bytes_per_launch"]
+        kern = t.get("configs", {}).get(str(cfg), {}).get("kernels", {})
+        if t.get("kernel_source_sha256") == kernel_source_hash() and name in kern:
+            traffic = kern[name]["hbm_bytes_per_launch"]
     except (OSError, ValueError):
         pass
-    if comp_bound is not None and comp_frac >= hbm_frac:
+    # the bound is the resource the kernel can saturate first: for FP32
+    # vector code that is the non-packed rate
+    comp_limit_frac = nonpacked_frac if nonpacked_frac is not None else comp_frac
+    if comp_bound is not None and comp_limit_frac >= hbm_frac:
         roof = {"kernel": name, "bound": comp_bound, "achieved": dom_fl / sec / 1e12, "peak": comp_peak / 1e12,
                 "unit": "TFLOP/s", "frac": comp_frac}
     else:
         roof = {"kernel": name, "bound": "hbm", "achieved": dom_by / sec / 1e9, "peak": PEAK_HBM / 1e9,
                 "unit": "GB/s", "frac": hbm_frac}
     roof.update({"traffic": traffic, "hbm_frac": hbm_frac, "compute_frac": comp_frac if comp_bound else None,
-                 "compute_frac_vs_published_peak": (dom_fl / sec / (PEAK_FP64 if f64 else PEAK_FP32)
-                                                    if comp_bound else None),
+                 "compute_frac_vs_nonpacked_fp32": nonpacked_frac,
+                 "nonpacked_fp32_peak_TFLOP_s": PEAK_FP32_VALU / 1e12 if nonpacked_frac is not None else None,
                  "avg_launch_ms": dom_ms / dom_n, "launches": dom_n, "alg_bytes_per_launch": dom_by / dom_n,
                  "alg_flops_per_launch": dom_fl / dom_n,
                  "kernels": {k[3:]: {"ms_per_step": v[0] / steps, "launches_per_step": v[1] / steps,
@@ -185,6 +197,18 @@ def kernel_probe(cfg, reps):
     print(json.dumps({"kernel_probe": True, "config": cfg, "reps": reps, "copy_bytes": 2 * (1 << 30)}), flush=True)
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(cfg):
     """The oracle as it stands on the host cores: one Newton step (explicit
     assembly + sparse LU) of the same physics on a reduced mesh."""
@@ -212,9 +236,87 @@ def cpu_baseline(cfg):
     spla.splu(J.tocsc()).solve(-r)
     dt = time.perf_counter() - t0
     return {"value": prob.dof / dt, "unit": "DOF/s", "cores": int(cores), "kind": "oracle",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
             "sample": (f"one oracle Newton step (explicit sparse assembly by Gauss quadrature + scipy splu) of "
                        f"the same physics at d={prob.d}, p={prob.p_s}, {nel}^{prob.d}x{nel} elements "
                        f"({prob.dof} DOF) in {dt:.2f} s; splu is single-threaded, BLAS pool {cores}")}
+
+
+def bench_config(torch, W, cfg, precs, steps, warmup, tol, max_rank, solve_only_too):
+    """Time one workload in the given precisions at the fixed state u^1 (one
+    FP64 Newton step from the lifted datum).  One large context at a time."""
+    import numpy as np
+    from paper_2311_17500_amd.binding import Solver, FP64, MIXED_FP32, MIXED_BF16
+    prob = W.config(cfg)
+    codes = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}
+    S64 = Solver(prob, prec=FP64, tol_lin=tol, max_rank=max_rank)
+    c0, _ = S64.lift()
+    u0 = torch.tensor(np.tile(c0, prob.n_t), dtype=torch.float64, device="cuda:0")
+    u1, w = S64.vec(S64.full), S64.vec(S64.full)
+    log(f"config {cfg}: {prob.dof} DOF, workspace {S64.workspace_bytes / 1e9:.1f} GB (FP64)")
+    S64.newton_step(u0, u1, w, True, tol)
+    del u0
+    log("state u1 ready")
+    u2 = S64.vec(S64.full)
+    torch.cuda.synchronize()
+
+    def solve_only(S):
+        """The linear solve alone (the Krylov part of the step) on the same system."""
+        S.linearize(u1, w, True)
+        b = -S.residual(u1, w)
+        x = S.vec()
+        for _ in range(warmup):
+            S.krylov(b, tol, x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            _, its, rr = S.krylov(b, tol, x)
+        e1.record()
+        torch.cuda.synchronize()
+        sm = e0.elapsed_time(e1) / steps
+        return {"ms": sm, "dof_per_s": prob.dof / (sm / 1e3), "krylov_iters": its, "relres": rr}
+
+    out = {}
+    for prec in precs:
+        if prec == "fp64":
+            S = S64
+        else:
+            if S64 is not None and S64.ctx:
+                S64.close()
+                S64.ws = None
+                torch.cuda.empty_cache()
+            S = Solver(prob, prec=codes[prec], tol_lin=tol, max_rank=max_rank)
+        ms, wall, its, rr, prof = time_region(torch, S, u1, u2, w, steps, warmup, tol)
+        r = dict(ms=ms, wall=wall, its=its, rr=rr, prof=prof)
+        log(f"config {cfg} {prec} Newton steps timed: {ms:.1f} ms")
+        if solve_only_too:
+            r["solve"] = solve_only(S)
+            log(f"config {cfg} {prec} solve-only timed")
+        out[prec] = r
+        if S is not S64:
+            S.close()
+            S.ws = None
+            torch.cuda.empty_cache()
+    if S64.ctx:
+        S64.close()
+        S64.ws = None
+    torch.cuda.empty_cache()
+    return prob, out
+
+
+def summary(prob, cfg, prec, r, steps):
+    """Compact record of one measured configuration (extra keys of the line)."""
+    roof = roofline(r["prof"], steps, cfg)
+    top = dict(list(roof["kernels"].items())[:6])
+    return {"workload": f"config{cfg}: d={prob.d} p={prob.p_s} {'x'.join(map(str, prob.nel_s))}x{prob.nel_t} "
+                        f"elements, {prob.dof} DOF, {prec}",
+            "dof_per_s": prob.dof / (r["ms"] / 1e3), "ms_per_step": r["ms"], "krylov_iters_per_step": r["its"][0],
+            "final_relres": r["rr"][-1],
+            "dominant_kernel": {k: roof[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac",
+                                                     "hbm_frac", "compute_frac", "compute_frac_vs_nonpacked_fp32",
+                                                     "avg_launch_ms", "traffic")},
+            "top_kernels": top}
 
 
 def main():
@@ -223,10 +325,8 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
               f"(the multi-GPU layout is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     import st_workloads as W
-    from paper_2311_17500_amd.binding import Solver, FP64, MIXED_FP32, MIXED_BF16
     if a.kernel_probe > 0:
         kernel_probe(a.config, a.kernel_probe)
         return
@@ -239,66 +339,14 @@ def main():
                           "serving": s}), flush=True)
         return
 
-    prob = W.config(a.config)
     if a.max_rank is None:
         a.max_rank = 16 if a.config == 4 else 48
-    prec_code = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}[a.prec]
-    prec_bytes = {"fp64": 8, "mixed_fp32": 4, "mixed_bf16": 2}[a.prec]
-
-    # the fixed state u^1: one FP64 Newton step from the lifted datum
-    S64 = Solver(prob, prec=FP64, tol_lin=a.tol, max_rank=a.max_rank)
-    c0, _ = S64.lift()
-    u0 = torch.tensor(np.tile(c0, prob.n_t), dtype=torch.float64, device="cuda:0")
-    u1, w = S64.vec(S64.full), S64.vec(S64.full)
-    log(f"config {a.config}: {prob.dof} DOF, workspace {S64.workspace_bytes / 1e9:.1f} GB (FP64)")
-    S64.newton_step(u0, u1, w, True, a.tol)
-    log("state u1 ready")
-    u2 = S64.vec(S64.full)
-    torch.cuda.synchronize()
-
-    def solve_only(S):
-        """The linear solve alone (the Krylov part of the step) on the same system."""
-        S.linearize(u1, w, True)
-        b = -S.residual(u1, w)
-        x = S.vec()
-        for _ in range(a.warmup):
-            S.krylov(b, a.tol, x)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(a.steps):
-            _, its, rr = S.krylov(b, a.tol, x)
-        e1.record()
-        torch.cuda.synchronize()
-        sm = e0.elapsed_time(e1) / a.steps
-        return {"ms": sm, "dof_per_s": prob.dof / (sm / 1e3), "krylov_iters": its, "relres": rr}
-
-    res = {}
-    solve = {}
-    if a.prec == "fp64" or not a.no_fp64_compare:
-        ms, wall, its, rr, prof = time_region(torch, S64, u1, u2, w, a.steps, a.warmup, a.tol)
-        res["fp64"] = dict(ms=ms, wall=wall, its=its, rr=rr, prof=prof, S=S64)
-        log("fp64 Newton steps timed")
-        solve["fp64"] = solve_only(S64)
-        log("fp64 solve-only timed")
-    if a.prec != "fp64":
-        # one large context at a time: release the FP64 workspace first
-        S64.close()
-        S64.ws = None
-        torch.cuda.empty_cache()
-        Sm = Solver(prob, prec=prec_code, tol_lin=a.tol, max_rank=a.max_rank)
-        ms, wall, its, rr, prof = time_region(torch, Sm, u1, u2, w, a.steps, a.warmup, a.tol)
-        res[a.prec] = dict(ms=ms, wall=wall, its=its, rr=rr, prof=prof, S=Sm)
-        log(f"{a.prec} Newton steps timed")
-        solve[a.prec] = solve_only(Sm)
-        log(f"{a.prec} solve-only timed")
+    precs = [a.prec] if (a.prec == "fp64" or a.no_fp64_compare) else ["fp64", a.prec]
+    prob, res = bench_config(torch, W, a.config, precs, a.steps, a.warmup, a.tol, a.max_rank, True)
     main_r = res[a.prec]
     ms = main_r["ms"]
     value = prob.dof / (ms / 1e3)
-    # dominant kernel function over the timed region, achieved bandwidth from
-    # the algorithmic bytes the library records per launch
-    prof = main_r["prof"]
-    roof = roofline(prof, a.steps)
+    roof = roofline(main_r["prof"], a.steps, a.config)
     out = {
         "metric": "space-time DOF/s to rel. residual 1e-8 (mixed vs FP64); p50/p99 solve latency",
         "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -314,6 +362,7 @@ def main():
         "wall_ms_per_step": main_r["wall"],
         "roofline": roof,
     }
+    solve = {p: r["solve"] for p, r in res.items()}
     if len(solve) == 2:
         solve["speedup_mixed_vs_fp64"] = solve["fp64"]["ms"] / solve[a.prec]["ms"]
     out["linear_solve_only"] = solve
@@ -323,12 +372,15 @@ def main():
         out["fp64_ms_per_step"] = f["ms"]
         out["fp64_krylov_iters_per_step"] = f["its"][0]
         out["speedup_vs_fp64"] = f["ms"] / ms
+    if not a.no_extras and a.config == 2:
+        # the other precision of the same workload and the largest one-GPU workload
+        extras = {}
+        p2, r2 = bench_config(torch, W, 2, ["mixed_bf16"], a.steps, a.warmup, a.tol, 48, False)
+        extras["config2_mixed_bf16"] = summary(p2, 2, "mixed_bf16", r2["mixed_bf16"], a.steps)
+        p4, r4 = bench_config(torch, W, 4, ["mixed_fp32"], 2, 1, a.tol, 16, False)
+        extras["config4_mixed_fp32"] = summary(p4, 4, "mixed_fp32", r4["mixed_fp32"], 2)
+        out["extra_workloads"] = extras
     if a.serve_requests > 0:
-        for r in res.values():         # release the single-solve workspaces first
-            if r["S"].ctx:
-                r["S"].close()
-            r["S"].ws = None
-        torch.cuda.empty_cache()
         log("serving sample")
         out["serving"] = serving(a.serve_requests, a.serve_slots)
     if not a.no_cpu_baseline:

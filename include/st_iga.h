@@ -124,6 +124,13 @@ typedef struct {
   int32_t graphs;            /* 1: with reorth = 1 or 2, replay each Arnoldi step (preconditioner,
                                 operator, Gram-Schmidt) from a HIP graph captured on first use;
                                 0: eager launches */
+  int32_t stall_cycles;      /* ENOCONV after this many consecutive FGMRES restart cycles (or
+                                refinement steps) that reduce the true residual by less than
+                                stall_reduction (relative); 0: never */
+  double stall_reduction;    /* in [0, 1) */
+  int32_t picard_switch;     /* > 0: a Newton solve (outer = 0) whose ||delta||_inf grows in this many
+                                consecutive iterations continues as the outer = 1 Picard iteration
+                                (alpha = 0.5); reported in st_iga_report.switched_at; 0: never */
 } st_iga_options;
 
 #define ST_IGA_MAX_OUTER_LOG 64
@@ -141,12 +148,13 @@ typedef struct {
   int32_t rank_capped;                         /* low ranks cut to max_rank (each misses its tolerance) */
   double lr_relerr_theta[ST_IGA_MAX_OUTER_LOG]; /* achieved ||Theta - U S V^T||_F / ||Theta||_F */
   double lr_relerr_react[ST_IGA_MAX_OUTER_LOG]; /* same for the reaction coefficient */
+  int32_t switched_at;                         /* iterations done before a Newton -> Picard switch; -1: none */
 } st_iga_report;
 
 /* Defaults: su=1, eps_theta=0.1, eps_react=1e-2, max_rank=48, outer=0,
  * alpha=1 (Newton), theta_freeze=1e-4, tol_nonlin=1e-10, tol_lin=1e-10,
  * inner_tol=1e-4, restart=30, max_outer=60, max_krylov=3000, prec=FP64, lin_forcing=0,
- * coef_slab=0, reorth=2, graphs=1. */
+ * coef_slab=0, reorth=2, graphs=1, stall_cycles=10, stall_reduction=1e-3, picard_switch=0. */
 void st_iga_default_options(st_iga_options* opt);
 
 /* Bytes of device workspace st_iga_setup needs for this problem/options

@@ -47,7 +47,8 @@ class Options(C.Structure):
                 ("tol_nonlin", C.c_double), ("tol_lin", C.c_double), ("inner_tol", C.c_double),
                 ("restart", C.c_int32), ("max_outer", C.c_int32), ("max_krylov", C.c_int32), ("prec", C.c_int32),
                 ("lin_forcing", C.c_double), ("coef_slab", C.c_int32), ("reorth", C.c_int32),
-                ("graphs", C.c_int32)]
+                ("graphs", C.c_int32), ("stall_cycles", C.c_int32), ("stall_reduction", C.c_double),
+                ("picard_switch", C.c_int32)]
 
 
 LOG = 64
@@ -58,7 +59,8 @@ class Report(C.Structure):
                 ("krylov", C.c_int32 * LOG), ("rank_theta", C.c_int32 * LOG), ("rank_react", C.c_int32 * LOG),
                 ("delta_inf", C.c_double * LOG), ("lin_relres", C.c_double * LOG), ("final_delta_inf", C.c_double),
                 ("seconds_linearize", C.c_double), ("seconds_krylov", C.c_double), ("rank_capped", C.c_int32),
-                ("lr_relerr_theta", C.c_double * LOG), ("lr_relerr_react", C.c_double * LOG)]
+                ("lr_relerr_theta", C.c_double * LOG), ("lr_relerr_react", C.c_double * LOG),
+                ("switched_at", C.c_int32)]
 
 
 class StIgaError(RuntimeError):

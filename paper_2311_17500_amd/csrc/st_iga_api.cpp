@@ -204,6 +204,9 @@ void validate(const st_iga_problem* P, const st_iga_options* O) {
   if (O->restart < 1 || O->restart > 64) throw Fail{ST_IGA_EINVAL, "restart must be in 1..64"};
   if (O->reorth < 0 || O->reorth > 2) throw Fail{ST_IGA_EINVAL, "reorth must be 0, 1 or 2"};
   if (O->outer < 0 || O->outer > 2) throw Fail{ST_IGA_EINVAL, "outer must be 0, 1 or 2"};
+  if (O->stall_cycles < 0 || !(O->stall_reduction >= 0.0 && O->stall_reduction < 1.0))
+    throw Fail{ST_IGA_EINVAL, "stall_cycles >= 0 and 0 <= stall_reduction < 1 required"};
+  if (O->picard_switch < 0) throw Fail{ST_IGA_EINVAL, "picard_switch must be >= 0"};
   if (!(O->alpha > 0) || O->alpha > 1) throw Fail{ST_IGA_EINVAL, "alpha must be in (0, 1]"};
   if (O->max_rank < 1 || O->max_rank > 128) throw Fail{ST_IGA_EINVAL, "max_rank must be in 1..128"};
   if (O->prec < ST_IGA_FP64 || O->prec > ST_IGA_MIXED_BF16) throw Fail{ST_IGA_EINVAL, "bad precision"};
@@ -1062,6 +1065,27 @@ double dev_absmax(st_iga_ctx* c, const double* x, int64_t n, hipStream_t s) {
   return h;
 }
 
+// Stagnation of a restarted iteration: a cycle (FGMRES restart or refinement
+// step) whose true residual falls by less than the relative amount
+// stall_reduction counts as a stall; stall_cycles stalls in a row end the
+// solve with ENOCONV (stall_cycles = 0: never).
+struct Stall {
+  st_iga_ctx* c;
+  double prev;
+  const char* what;
+  int count = 0;
+  Stall(st_iga_ctx* cc, double start, const char* w) : c(cc), prev(start), what(w) {}
+  void cycle(double rn) {
+    if (c->opt.stall_cycles <= 0) return;
+    if (rn > (1.0 - c->opt.stall_reduction) * prev) {
+      if (++count >= c->opt.stall_cycles) throw Fail{ST_IGA_ENOCONV, what};
+    } else {
+      count = 0;
+    }
+    prev = rn;
+  }
+};
+
 using Op = std::function<void(const double*, double*)>;
 template <class T>
 using OpT = std::function<void(const T*, T*)>;
@@ -1135,6 +1159,7 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
   fill(x, 0.0, n, s);
   int it = 0;
   double rn = bnorm;
+  Stall stall(c, bnorm, "FGMRES stagnated");
   CK(hipMemcpyAsync(c->rk, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   // Hr: Hessenberg matrix as computed (unrotated); R: rotated copy
   std::vector<double> Hr(static_cast<size_t>(m + 1) * m), R(static_cast<size_t>(m + 1) * m), cs(m), sn(m),
@@ -1257,6 +1282,7 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
     *est = rn / bnorm;
     if (rn <= rtol * bnorm) break;
     if (!std::isfinite(rn)) throw Fail{ST_IGA_ENOCONV, "non-finite residual"};
+    stall.cycle(rn);
   }
   return it;
 }
@@ -1271,6 +1297,7 @@ int fgmres(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const double* b, do
   fill(x, 0.0, n, s);
   int it = 0;
   double rn = bnorm;
+  Stall stall(c, bnorm, "FGMRES stagnated");
   CK(hipMemcpyAsync(c->rk, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   std::vector<double> H(static_cast<size_t>(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   double hbuf[258];
@@ -1373,6 +1400,7 @@ int fgmres(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const double* b, do
     *est = rn / bnorm;
     if (rn <= rtol * bnorm) break;
     if (!std::isfinite(rn)) throw Fail{ST_IGA_ENOCONV, "non-finite residual"};
+    stall.cycle(rn);
   }
   return it;
 }
@@ -1498,6 +1526,7 @@ int krylov(st_iga_ctx* c, const double* b, double* x, double tol, double* relres
   CK(hipMemcpyAsync(c->bk, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));   // bk = current residual
   double rn = bnorm;
   int total = 0, refinements = 0;
+  Stall stall(c, bnorm, "iterative refinement stagnated");
   while (rn > tol * bnorm) {
     if (total >= c->opt.max_krylov || refinements >= 60) throw Fail{ST_IGA_ENOCONV, "refinement did not converge"};
     const double itol = std::max(c->opt.inner_tol, 0.5 * tol * bnorm / rn);
@@ -1511,6 +1540,7 @@ int krylov(st_iga_ctx* c, const double* b, double* x, double tol, double* relres
     rn = dev_norm(c, c->bk, n, s);
     ++refinements;
     if (!std::isfinite(rn)) throw Fail{ST_IGA_ENOCONV, "non-finite residual"};
+    if (rn > tol * bnorm) stall.cycle(rn);
   }
   c->last_refinements = refinements;
   *relres = rn / bnorm;
@@ -2102,6 +2132,9 @@ void st_iga_default_options(st_iga_options* o) {
   o->restart = 30;
   o->max_outer = 60;
   o->max_krylov = 3000;
+  o->stall_cycles = 10;
+  o->stall_reduction = 1e-3;
+  o->picard_switch = 0;
   o->prec = ST_IGA_FP64;
   o->lin_forcing = 0.0;
   o->coef_slab = 0;
@@ -2333,6 +2366,23 @@ st_iga_status st_iga_solve(st_iga_ctx* c, const st_iga_stimulus* stim, double* u
     CK(hipStreamSynchronize(s));
     bool frozen = false;
     bool converged = false;
+    // Newton that keeps growing ||delta||_inf for picard_switch iterations in a
+    // row continues as the defect-correction Picard iteration (C_r, alpha =
+    // 0.5) for the rest of this solve
+    const int32_t outer0 = c->opt.outer;
+    const double alpha0 = c->opt.alpha;
+    struct RestoreOpt {
+      st_iga_ctx* c;
+      int32_t o;
+      double a;
+      ~RestoreOpt() {
+        c->opt.outer = o;
+        c->opt.alpha = a;
+      }
+    } restore_opt{c, outer0, alpha0};
+    R.switched_at = -1;
+    int growth = 0;
+    double dprev = -1.0;
     for (int k = 0; k < c->opt.max_outer; ++k) {
       auto t0 = std::chrono::steady_clock::now();
       if (!paper_fp) w_update(c, u, w, s);
@@ -2372,6 +2422,15 @@ st_iga_status st_iga_solve(st_iga_ctx* c, const st_iga_stimulus* stim, double* u
       R.krylov_total += it;
       R.outer_iters = k + 1;
       R.final_delta_inf = dinf;
+      if (outer0 == 0 && c->opt.picard_switch > 0 && R.switched_at < 0) {
+        growth = (dprev >= 0.0 && dinf > dprev) ? growth + 1 : 0;
+        if (growth >= c->opt.picard_switch) {
+          c->opt.outer = 1;
+          c->opt.alpha = 0.5;
+          R.switched_at = k + 1;
+        }
+      }
+      dprev = dinf;
       if (dinf <= c->opt.theta_freeze) frozen = true;
       if (dinf <= c->opt.tol_nonlin) {
         converged = true;

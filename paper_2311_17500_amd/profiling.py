@@ -1,15 +1,17 @@
 """Summaries of rocprofv3 output for the kernels of this library.
 
     python -m paper_2311_17500_amd.profiling stats <kernel_stats.csv> <out.txt> "<command>"
-    python -m paper_2311_17500_amd.profiling traffic <fetch_dir> <write_dir> <out.json> "<command>"
+    python -m paper_2311_17500_amd.profiling traffic <fetch_dir> <write_dir> <out.json> "<command>" [config]
+    python -m paper_2311_17500_amd.profiling resources <remarks.txt> <out.txt> "<command>"
 
 `stats` turns the per-kernel statistics of a `rocprofv3 --kernel-trace
 --stats` run into a short text table (kernel, calls, total and average
 duration).  `traffic` takes two counter runs of `bench.py --kernel-probe`
 (`--pmc FETCH_SIZE` and `--pmc WRITE_SIZE`, KiB per dispatch), calibrates the
 counters on the probe's 1 GiB device copy (1 GiB read, 1 GiB written) and
-writes the HBM bytes per launch of each library kernel, with the hash of the
-kernel sources they were measured on.  Kernel names are reduced to the
+writes the HBM bytes per launch of each library kernel under the workload's
+config number, with the hash of the kernel sources they were measured on
+(entries of other configs measured on the same sources are kept).  Kernel names are reduced to the
 library's short form, e.g. ``k_coef_fused<float, ...>`` -> ``coef_fused<f32>``.
 """
 from __future__ import annotations
@@ -29,7 +31,7 @@ _FN = {"k_sweep": "gather_sweep", "k_sweep_flat": "gather_sweep", "k_sweep_dual"
        "k_dense_rows": "dense_mode_mfma", "k_coef_fused": "coef_fused", "k_coef_fused_pf": "coef_fused",
        "k_quad_fused": "quad_fused", "k_time_core": "time_core", "k_time_mix": "time_mix", "k_arrowhead": "arrowhead",
        "k_multidot": "multidot", "k_multidot_v": "multidot", "k_update_norm": "update_norm",
-       "k_pointwise_ionic": "pointwise_ionic", "k_mode_max": "mode_max"}
+       "k_pointwise_ionic": "pointwise_ionic", "k_mode_max": "mode_max", "k_react_point": "react_point"}
 
 
 def short_name(full: str) -> str:
@@ -96,7 +98,8 @@ def _per_kernel(counter_dir: str, counter: str):
     return per
 
 
-def traffic(fetch_dir: str, write_dir: str, out_json: str, command: str, copy_bytes: int = 1 << 30) -> None:
+def traffic(fetch_dir: str, write_dir: str, out_json: str, command: str, cfg: str = "2",
+            copy_bytes: int = 1 << 30) -> None:
     fetch = _per_kernel(fetch_dir, "FETCH_SIZE")
     write = _per_kernel(write_dir, "WRITE_SIZE")
     # the copy: the non-library kernel (library kernels live in namespace
@@ -120,16 +123,71 @@ def traffic(fetch_dir: str, write_dir: str, out_json: str, command: str, copy_by
         rd = sum(k["reads"]) / len(k["reads"])
         wr = sum(k["writes"]) / len(k["writes"])
         out[s] = {"fetch_bytes_per_launch": rd, "write_bytes_per_launch": wr, "hbm_bytes_per_launch": rd + wr}
-    doc = {"command": command, "copy_kernel": copy[:120], "fetch_scale": f_scale, "write_scale": w_scale,
-           "kernel_source_sha256": kernel_source_hash(), "kernels": out}
+    sha = kernel_source_hash()
+    doc = {"kernel_source_sha256": sha, "configs": {}}
+    try:
+        with open(out_json) as fh:
+            old = json.load(fh)
+        if old.get("kernel_source_sha256") == sha:
+            doc["configs"] = old.get("configs", {})
+    except (OSError, ValueError):
+        pass
+    doc["configs"][str(cfg)] = {"command": command, "copy_kernel": copy[:120], "fetch_scale": f_scale,
+                                "write_scale": w_scale, "kernels": out}
     with open(out_json, "w") as fh:
         json.dump(doc, fh, indent=1, sort_keys=True)
+
+
+def resources(remarks_txt: str, out_txt: str, command: str) -> None:
+    """Per-kernel register, LDS, spill and occupancy figures from the
+    compiler's `-Rpass-analysis=kernel-resource-usage` remarks."""
+    import subprocess
+    fields = ("TotalSGPRs", "VGPRs", "AGPRs", "ScratchSize [bytes/lane]", "Occupancy [waves/SIMD]", "SGPRs Spill",
+              "VGPRs Spill", "LDS Size [bytes/block]")
+    kern, cur = {}, None
+    with open(remarks_txt) as fh:
+        for line in fh:
+            m = re.search(r"remark: Function Name: (\S+)", line)
+            if m:
+                cur = m.group(1)
+                kern[cur] = {}
+                continue
+            m = re.search(r"remark:\s+([A-Za-z ]+(?:\[[^\]]*\])?): (\S+)", line)
+            if cur and m and m.group(1).strip() in fields:
+                kern[cur][m.group(1).strip()] = m.group(2)
+    names = list(kern)
+    try:
+        dem = subprocess.run(["c++filt"], input="\n".join(names), capture_output=True, text=True).stdout.split("\n")
+    except OSError:
+        dem = names
+    rows = []
+    for mangled, full in zip(names, dem):
+        if not full.strip():
+            continue
+        m = re.search(r"(k_\w+)(<[^()]*>)?\(", full)
+        short = (m.group(1) + (m.group(2) or "")) if m else full[:60]
+        short = short.replace("__hip_bfloat16", "bf16").replace("(anonymous namespace)::", "")
+        f = kern[mangled]
+        rows.append((short, f.get("VGPRs", "?"), f.get("AGPRs", "?"), f.get("TotalSGPRs", "?"),
+                     f.get("VGPRs Spill", "?"), f.get("SGPRs Spill", "?"), f.get("ScratchSize [bytes/lane]", "?"),
+                     f.get("LDS Size [bytes/block]", "?"), f.get("Occupancy [waves/SIMD]", "?")))
+    rows.sort()
+    lines = ["# compiler resource usage per kernel instantiation (gfx950)", f"# command: {command}", "",
+             f"{'kernel':78s} {'VGPR':>5s} {'AGPR':>5s} {'SGPR':>5s} {'Vspill':>6s} {'Sspill':>6s} "
+             f"{'scratch':>7s} {'LDS B':>7s} {'waves/SIMD':>10s}"]
+    for r in rows:
+        lines.append(f"{r[0][:78]:78s} {r[1]:>5s} {r[2]:>5s} {r[3]:>5s} {r[4]:>6s} {r[5]:>6s} {r[6]:>7s} "
+                     f"{r[7]:>7s} {r[8]:>10s}")
+    with open(out_txt, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
 
 
 if __name__ == "__main__":
     if len(sys.argv) >= 5 and sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif len(sys.argv) >= 5 and sys.argv[1] == "resources":
+        resources(sys.argv[2], sys.argv[3], sys.argv[4])
     elif len(sys.argv) >= 6 and sys.argv[1] == "traffic":
-        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], *(sys.argv[6:7]))
     else:
         sys.exit(__doc__)
