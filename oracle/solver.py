@@ -52,16 +52,22 @@ def linearize(st: SpaceTime, u_full, w_full, eps_theta=0.1, eps_react=1e-2, newt
 
 
 def solve(st: SpaceTime, newton=True, alpha=None, eps_theta=0.1, eps_react=1e-2, tol=1e-10,
-          theta_freeze=1e-4, max_outer=60, u_init=None):
-    """Full nonlinear solve; returns (u_full, w_full, log)."""
+          theta_freeze=1e-4, max_outer=60, u_init=None, picard_switch=0):
+    """Full nonlinear solve; returns (u_full, w_full, log).  picard_switch > 0:
+    a Newton solve whose ||alpha delta||_inf grows in that many consecutive
+    iterations continues as the Picard iteration (C_r, alpha = 0.5); the
+    iteration count at the switch is log.switched_at (-1: none)."""
     alpha = (1.0 if newton else 0.5) if alpha is None else alpha
+    switch_armed = newton and picard_switch > 0
+    growth, dprev = 0, -1.0
     c0 = st.lift()
     nt = st.n[st.d]
     u = np.tile(c0, nt) if u_init is None else u_init.copy()
     log = OuterLog()
+    log.switched_at = -1
     theta_lr = None
     frozen = False
-    for _ in range(max_outer):
+    for k in range(max_outer):
         w = st.w_update_explicit(u)
         lin = linearize(st, u, w, eps_theta, eps_react, newton, theta_lr if frozen else None)
         theta_lr = lin.theta_lr
@@ -75,6 +81,12 @@ def solve(st: SpaceTime, newton=True, alpha=None, eps_theta=0.1, eps_react=1e-2,
         log.deltas.append(dinf)
         log.ranks_theta.append(theta_lr.R if theta_lr is not None else 0)
         log.ranks_react.append(lin.coef_lr.R)
+        if switch_armed and log.switched_at < 0:
+            growth = growth + 1 if (dprev >= 0.0 and dinf > dprev) else 0
+            if growth >= picard_switch:
+                newton, alpha = False, 0.5
+                log.switched_at = k + 1
+        dprev = dinf
         if dinf <= theta_freeze:
             frozen = True
         if dinf <= tol:

@@ -1291,6 +1291,165 @@ __global__ void __launch_bounds__(64) k_dense_rows(const C* __restrict__ Ap, int
   for (int t = mv * V + lane; t < span; t += 64) ys[t] = Xs[t];
 }
 
+// ---------------------------------------------------------------- dense mode product, BF16 on MFMA
+// The same mode products with BF16 operands and FP32 accumulation on
+// v_mfma_f32_16x16x16bf16_1k (K = 16 per instruction): A lane l holds
+// A[l%16][4(l/16) + 0..3], B lane l holds B[4(l/16) + 0..3][l%16], the result
+// layout is that of the FP32 16x16x4 form (lane l: rows 4(l/16) + v of
+// column l%16).  The matrix is the zero-padded BF16 copy, staged in LDS with
+// rows padded by 16 bytes; rows j >= n of X read as 0.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ fx4 mfma16x16x16bf16(bf16x4 a, bf16x4 b, fx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__host__ __device__ constexpr int lds_stride_b16(int npad) { return npad + 8; }
+
+__device__ __forceinline__ void stage_matrix_b16(const bf16* __restrict__ Ap, unsigned short* As, int npad) {
+  typedef struct { unsigned short v[8]; } __attribute__((aligned(16))) Vec;
+  const Vec* src = reinterpret_cast<const Vec*>(Ap);
+  Vec* dst = reinterpret_cast<Vec*>(As);
+  const int vpr = npad / 8;          // 16-byte vectors per row (row stride npad + 8 = (vpr + 1) vectors)
+  const int nv = npad * vpr;
+#pragma unroll 8
+  for (int t = threadIdx.x; t < nv; t += blockDim.x) dst[t + t / vpr] = src[t];
+  __syncthreads();
+}
+
+__device__ __forceinline__ unsigned short bf16_bits(bf16 v) { return __builtin_bit_cast(unsigned short, v); }
+__device__ __forceinline__ bf16 bf16_from_bits(unsigned short v) { return __builtin_bit_cast(bf16, v); }
+
+// inner % E == 0: a wave owns 16E columns as E tiles, lane l the E adjacent
+// columns c0 + E(l%16) + e (one E x 2-byte load per row)
+template <int NT, int E>
+__global__ void __launch_bounds__(256) k_dense_modeE_b16(const bf16* __restrict__ Ap, int n, int npad,
+                                                         const bf16* __restrict__ x, bf16* __restrict__ y,
+                                                         int64_t inner, int64_t ncols) {
+  extern __shared__ char smem_raw[];
+  unsigned short* As = reinterpret_cast<unsigned short*>(smem_raw);
+  stage_matrix_b16(Ap, As, npad);
+  const int lda = lds_stride_b16(npad);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int64_t ngroups = (ncols + 64 * E - 1) / (64 * E);
+  typedef struct { unsigned short v[E]; } __attribute__((aligned(2 * E))) Row;
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int64_t c = (grp * 4 + wv) * (16 * E) + E * r16;
+    const bool cv = c < ncols;
+    const int64_t o = cv ? c / inner : 0;
+    const int64_t kq = cv ? c - o * inner : 0;
+    const bf16* xb = x + o * static_cast<int64_t>(n) * inner + kq;
+    fx4 acc[NT][E];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc[t][e] = fx4{0, 0, 0, 0};
+    for (int kk = 0; kk < npad; kk += 16) {
+      Row rv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = kk + 4 * q4 + i;
+        if (cv && j < n) {
+          rv[i] = *reinterpret_cast<const Row*>(xb + static_cast<int64_t>(j) * inner);
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e) rv[i].v[e] = 0;
+        }
+      }
+      bf16x4 bop[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        bop[e] = bf16x4{static_cast<short>(rv[0].v[e]), static_cast<short>(rv[1].v[e]),
+                        static_cast<short>(rv[2].v[e]), static_cast<short>(rv[3].v[e])};
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const bf16x4 aop = *reinterpret_cast<const bf16x4*>(As + (t * 16 + r16) * lda + kk + 4 * q4);
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[t][e] = mfma16x16x16bf16(aop, bop[e], acc[t][e]);
+      }
+    }
+    if (cv) {
+      bf16* yb = y + o * static_cast<int64_t>(n) * inner + kq;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = t * 16 + 4 * q4 + v;
+          if (i < n) {
+            Row r;
+#pragma unroll
+            for (int e = 0; e < E; ++e) r.v[e] = bf16_bits(__float2bfloat16(acc[t][e][v]));
+            *reinterpret_cast<Row*>(yb + static_cast<int64_t>(i) * inner) = r;
+          }
+        }
+    }
+  }
+}
+
+// inner == 1 (the fastest axis): a one-wave block stages 16E consecutive rows
+// x[o][0..n) in LDS, multiplies them as E column tiles and writes the results
+// back over the staged rows before the coalesced store
+template <int NT, int E>
+__global__ void __launch_bounds__(64) k_dense_rows_b16(const bf16* __restrict__ Ap, int n, int npad,
+                                                       const bf16* __restrict__ x, bf16* __restrict__ y,
+                                                       int64_t outer) {
+  extern __shared__ char smem_raw[];
+  unsigned short* Xs = reinterpret_cast<unsigned short*>(smem_raw);
+  constexpr int RB = 16 * E;
+  const int64_t o0 = static_cast<int64_t>(blockIdx.x) * RB;
+  const int rows = static_cast<int>(min<int64_t>(RB, outer - o0));
+  const int span = rows * n;
+  const unsigned short* xs = reinterpret_cast<const unsigned short*>(x + o0 * n);
+  const int lane = threadIdx.x;
+  for (int t = lane; t < span; t += 64) Xs[t] = xs[t];
+  __syncthreads();
+  const int r16 = lane & 15, q4 = lane >> 4;
+  fx4 acc[NT][E];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[t][e] = fx4{0, 0, 0, 0};
+  const unsigned short* Au = reinterpret_cast<const unsigned short*>(Ap);
+  for (int kk = 0; kk < npad; kk += 16) {
+    bf16x4 bop[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int rr = 16 * e + r16;
+      short v4[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = kk + 4 * q4 + i;
+        v4[i] = (rr < rows && j < n) ? static_cast<short>(Xs[rr * n + j]) : static_cast<short>(0);
+      }
+      bop[e] = bf16x4{v4[0], v4[1], v4[2], v4[3]};
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const unsigned short* ar = Au + static_cast<int64_t>(t * 16 + r16) * npad + kk + 4 * q4;
+      const bf16x4 aop = *reinterpret_cast<const bf16x4*>(ar);
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc[t][e] = mfma16x16x16bf16(aop, bop[e], acc[t][e]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int rr = 16 * e + r16;
+    if (rr < rows) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = t * 16 + 4 * q4 + v;
+          if (i < n) Xs[rr * n + i] = bf16_bits(__float2bfloat16(acc[t][e][v]));
+        }
+    }
+  }
+  __syncthreads();
+  unsigned short* ys = reinterpret_cast<unsigned short*>(y + o0 * n);
+  for (int t = lane; t < span; t += 64) ys[t] = Xs[t];
+}
+
 // ---------------------------------------------------------------- arrowhead
 template <class S, class C>
 __global__ void __launch_bounds__(TPB) k_arrowhead(const S* __restrict__ r, S* __restrict__ y, const C* __restrict__ lam,
@@ -2566,6 +2725,43 @@ void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, i
     default: break;
   }
 #undef DM_CASE
+}
+
+bool dense_mode_b16(const bf16* Ab, int n, int npad, const bf16* x, bf16* y, int64_t outer, int64_t inner,
+                    hipStream_t s) {
+  const int64_t ncols = outer * inner;
+  if (ncols == 0) return true;
+  const int NT = npad / 16;
+  if (NT < 1 || NT > 9 || npad % 16 != 0) return false;
+  if (inner == 1) {
+    constexpr int E = 4;
+    const size_t xbytes = static_cast<size_t>(16 * E) * n * sizeof(bf16);
+    if (xbytes > 64 * 1024) return false;
+    ProfScope ps(K_DENSE, 4 + 16 * 2, s, 2.0 * ncols * n * sizeof(bf16), 2.0 * ncols * n * n);
+    const unsigned grid = static_cast<unsigned>((outer + 16 * E - 1) / (16 * E));
+#define DRB(nt) case nt: hipLaunchKernelGGL((k_dense_rows_b16<nt, E>), dim3(grid), dim3(64), xbytes, s, Ab, n, npad, x, y, outer); break;
+    switch (NT) { DRB(1) DRB(2) DRB(3) DRB(4) DRB(5) DRB(6) DRB(7) DRB(8) DRB(9) default: break; }
+#undef DRB
+    return true;
+  }
+  auto aligned = [&](int e) {
+    return inner % e == 0 && inner >= 4 * e && reinterpret_cast<uintptr_t>(x) % (e * sizeof(bf16)) == 0 &&
+           reinterpret_cast<uintptr_t>(y) % (e * sizeof(bf16)) == 0;
+  };
+  const int E = aligned(4) ? 4 : (aligned(2) ? 2 : 0);
+  if (E == 0) return false;
+  const size_t abytes = static_cast<size_t>(npad) * lds_stride_b16(npad) * sizeof(bf16);
+  const int64_t groups = (ncols + 64 * E - 1) / (64 * E);
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(groups, 2048));
+  ProfScope ps(K_DENSE, 4 + 16 * 2, s, 2.0 * ncols * n * sizeof(bf16), 2.0 * ncols * n * n);
+#define DEB(nt, e) case nt: hipLaunchKernelGGL((k_dense_modeE_b16<nt, e>), dim3(grid), dim3(256), abytes, s, Ab, n, npad, x, y, inner, ncols); break;
+  if (E == 4) {
+    switch (NT) { DEB(1, 4) DEB(2, 4) DEB(3, 4) DEB(4, 4) DEB(5, 4) DEB(6, 4) DEB(7, 4) DEB(8, 4) DEB(9, 4) default: break; }
+  } else {
+    switch (NT) { DEB(1, 2) DEB(2, 2) DEB(3, 2) DEB(4, 2) DEB(5, 2) DEB(6, 2) DEB(7, 2) DEB(8, 2) DEB(9, 2) default: break; }
+  }
+#undef DEB
+  return true;
 }
 
 template <class S, class C>

@@ -141,6 +141,12 @@ int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, c
 // zero-padded as npad x npad (npad = 16 * ceil(n / 16) <= 144), row-major.
 template <class S, class C>
 void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, int64_t inner, hipStream_t s);
+// The same product with BF16 operands on the BF16 MFMA (FP32 accumulation):
+// Ab is the zero-padded BF16 copy of the matrix.  Returns false (nothing
+// launched) when the layout is not supported (odd inner, npad > 144); the
+// caller then uses dense_mode<bf16, float>.
+bool dense_mode_b16(const bf16* Ab, int n, int npad, const bf16* x, bf16* y, int64_t outer, int64_t inner,
+                    hipStream_t s);
 
 // Arrowhead solve of the fast-diagonalization core, one spatial mode per thread:
 // the first np time-mode pairs are 2x2 blocks (values mu), the remaining

@@ -112,6 +112,7 @@ struct st_iga_ctx {
     std::vector<double> h;
     double* d = nullptr;
     float* f = nullptr;
+    bf16* b = nullptr;     // BF16 copy (BF16 mode: the mode products run on the BF16 MFMA)
     int n = 0, npad = 0;
   } DUsT[3], DUs[3], DUtT, DUt;
   // device data
@@ -603,6 +604,7 @@ void plan(st_iga_ctx* c) {
     if (D->npad == 0) continue;
     D->d = a.get<double>(static_cast<int64_t>(D->npad) * D->npad);
     D->f = a.get<float>(static_cast<int64_t>(D->npad) * D->npad);
+    if (bf) D->b = a.get<bf16>(static_cast<int64_t>(D->npad) * D->npad);
   }
   c->lam_d = a.get<double>(c->Ns);
   c->lam_f = a.get<float>(c->Ns);
@@ -733,6 +735,7 @@ void upload_all(st_iga_ctx* c, hipStream_t s) {
     up(D->h, static_cast<const double*>(D->d), s);
     keepf.emplace_back(D->h.begin(), D->h.end());
     up(keepf.back(), static_cast<const float*>(D->f), s);
+    if (D->b) convert<float, bf16>(D->f, D->b, static_cast<int64_t>(D->npad) * D->npad, s);
   }
   up(c->lam_s_h, static_cast<const double*>(c->lam_d), s);
   keepf.emplace_back(c->lam_s_h.begin(), c->lam_s_h.end());
@@ -998,7 +1001,10 @@ void dense_spatial(st_iga_ctx* c, const st_iga_ctx::Dense* const* M, const S* x,
     for (int k = 0; k < l; ++k) inner *= c->n[k];
     for (int k = l + 1; k < d; ++k) outer *= c->n[k];
     S* out = (l == d - 1) ? dst : bufs[pb];
-    dense_mode<S, C>(dmat<C>(*M[l]), M[l]->n, M[l]->npad, cur, out, outer, inner, s);
+    bool done = false;
+    if constexpr (std::is_same<S, bf16>::value)
+      done = M[l]->b && dense_mode_b16(M[l]->b, M[l]->n, M[l]->npad, cur, out, outer, inner, s);
+    if (!done) dense_mode<S, C>(dmat<C>(*M[l]), M[l]->n, M[l]->npad, cur, out, outer, inner, s);
     cur = out;
     pb ^= 1;
   }

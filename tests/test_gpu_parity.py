@@ -493,3 +493,58 @@ def test_galerkin_solve(gpu_lib, outer):
     assert rep.rank_theta[0] == 0
     assert rel(u.cpu().numpy(), uo) < 1e-10
     assert rel(w.cpu().numpy(), wo) < 1e-10
+
+
+# Failure handling, forced from the host (every kernel still exits normally).
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
+def test_krylov_stagnation_enoconv(gpu_lib, torch, prec):
+    """A restart cycle must cut the true residual by 99.9999 % to count as
+    progress (stall_reduction), one stalled cycle is allowed (stall_cycles):
+    the solve ends with ENOCONV instead of running to max_krylov; the same
+    context then solves normally once the options are back to defaults."""
+    from paper_2311_17500_amd.binding import ENOCONV, FP64, MIXED_FP32, StIgaError
+    prob = SMALL[2][1]
+    code = {"fp64": FP64, "mixed_fp32": MIXED_FP32}[prec]
+    S = solver_for(prob, prec=code, restart=2, stall_cycles=1, stall_reduction=0.999999, graphs=0)
+    u, w = W.smooth_state(prob, 9)
+    S.linearize(to_dev(torch, u), to_dev(torch, w))
+    b = to_dev(torch, W.random_vector(prob.unknowns, 15))
+    with pytest.raises(StIgaError) as e:
+        S.krylov(b, tol=1e-10)
+    assert e.value.code == ENOCONV and "stagnated" in str(e.value)
+    S2 = solver_for(prob, prec=code, restart=2, graphs=0)
+    S2.linearize(to_dev(torch, u), to_dev(torch, w))
+    x, it, rr = S2.krylov(b, tol=1e-8)
+    assert rr <= 1e-8
+
+
+def test_newton_to_picard_switch(gpu_lib):
+    """A source-driven case on which Newton with refreshed theta circles
+    without converging (theta's rank flips): with picard_switch = 2 the solve
+    continues as Picard after the update grows twice in a row and converges;
+    the switch point, iteration count and solution match the oracle's loop
+    with the same rule."""
+    prob, kn = _src_case(2, 2, 2, nel=4, nel_t=9)
+    S = solver_for(prob, knots=kn, tol_nonlin=1e-11, tol_lin=1e-12, max_outer=150, picard_switch=2)
+    st = SpaceTime(prob, knots=kn)
+    u, w, rep = S.solve()
+    uo, wo, log = solver.solve(st, tol=1e-11, max_outer=150, picard_switch=2)
+    assert log.switched_at > 0 and rep.switched_at == log.switched_at
+    assert rep.outer_iters == len(log.deltas)
+    assert rel(u.cpu().numpy(), uo) < 1e-10
+    assert rel(w.cpu().numpy(), wo) < 1e-10
+
+
+@pytest.mark.parametrize("name,prob", SMALL[:6], ids=[n for n, _ in SMALL[:6]])
+def test_precond_bf16_mfma(gpu_lib, torch, name, prob):
+    """BF16 mode: the eigenvector mode products run on the BF16 MFMA with
+    FP32 accumulation (BF16 vectors and matrices).  Against the oracle's
+    direct solve the error is a small multiple of the BF16 unit roundoff
+    (3.9e-3) times the conditioning of the eigenvector bases."""
+    from paper_2311_17500_amd.binding import MIXED_BF16
+    S = solver_for(prob, prec=MIXED_BF16)
+    st = SpaceTime(prob)
+    r = W.random_vector(prob.unknowns, 33)
+    z = S.precond_lowp(to_dev(torch, r)).cpu().numpy()
+    want = solver.precond_solve(st, r)
+    assert rel(z, want) < 5e-2
