@@ -53,9 +53,9 @@ typedef enum {
   ST_IGA_MIXED_BF16 = 2   /* FP32 apply, preconditioner with BF16 storage and FP32 arithmetic, same FP64 loop */
 } st_iga_precision;
 
-/* Problem statement, paper Section 3, eq. (3.1), and Section 2 (knots).
- * Domain (0,1)^d x (0,T) with the identity geometry map; homogeneous Neumann
- * boundary conditions; D = diag(sigma). */
+/* Problem statement, paper Section 3, eq. (3.1), and Section 2 (knots, map).
+ * Parametric domain (0,1)^d x (0,T) with a separable geometry map (identity
+ * by default); homogeneous Neumann boundary conditions; D = diag(sigma). */
 typedef struct {
   int32_t d;                 /* spatial dimension, 1..3 */
   int32_t p_s, p_t;          /* spline degrees in space / time, >= 1 */
@@ -65,6 +65,18 @@ typedef struct {
   double Cm;                 /* membrane capacitance > 0 */
   double sigma[3];           /* diffusivities > 0 */
   double a, b, c1, c2, de;   /* Rogers-McCulloch parameters of eq. (3.1), > 0 (c1, c2 >= 0) */
+  /* Separable geometry map x_l = F_l(eta_l) of each spatial direction (the
+   * spatial part of G = (F, T tau), Section 2, with a diagonal Jacobian):
+   * 0 identity (domain (0,1)); 1 affine F = a + (b - a) eta; 2 exponential
+   * grading F = a + (b - a) (exp(k eta) - 1) / (exp(k) - 1), with
+   * (a, b, k) = map_param[l], a < b, 1e-8 < |k| < 50.  Integrals carry
+   * |det DF| = prod_l F_l', gradients 1/F_l', theta's residual the physical
+   * Laplacian, and the initial datum, theta's interpolation and the source
+   * use physical coordinates (mapped Greville and Gauss points).  The
+   * fast-diagonalization preconditioner uses the mapped 1D pencils, which
+   * keeps it exact for the constant-coefficient part on such geometries. */
+  int32_t map_kind[3];
+  double map_param[3][3];
 } st_iga_problem;
 
 /* Stimulus: an initial datum u0 (lifted into time layer 0 by sampling at the

@@ -24,6 +24,8 @@ from .splines import bspline_all, breakpoints, greville, gauss_rule
 
 class RowSampler:
     def __init__(self, prob, knots=None):
+        if any(getattr(prob, "map_kind", (0, 0, 0))[:prob.d]):
+            raise NotImplementedError("row sampling is for the identity geometry")
         d = prob.d
         kn = knots if knots is not None else prob.uniform_knots()
         self.P = prob

@@ -70,6 +70,24 @@ def reaction_coefficient(u, w, P):
     return P.c1 * (u - P.a) * (u - 1.0) + P.c2 * w
 
 
+def geometry_map(prob, l):
+    """Spatial map x = F(eta) of direction l (Section 2: the spatial part of
+    G = (F, T tau), here separable) as a function returning (F, F', F'')
+    at parametric points, or None for the identity.  Kinds: 1 affine
+    a + (b - a) eta; 2 exponential grading a + (b - a) (e^{k eta} - 1) / (e^k - 1)."""
+    kind = getattr(prob, "map_kind", (0, 0, 0))[l]
+    if kind == 0:
+        return None
+    a, b, k = prob.map_param[l]
+    if kind == 1:
+        return lambda e: (a + (b - a) * e, np.full_like(e, b - a), np.zeros_like(e))
+
+    def graded(e):
+        d1 = (b - a) * k * np.exp(k * e) / np.expm1(k)
+        return a + (b - a) * np.expm1(k * e) / np.expm1(k), d1, k * d1
+    return graded
+
+
 def truncated_svd(A: np.ndarray, eps: float, max_rank: int = None):
     """Smallest-rank R with ||A - U S V^T||_F <= eps ||A||_F (eq. (3.8)).
     The tolerance alone fixes R; a caller that can only hold max_rank terms
@@ -126,6 +144,23 @@ class SpaceTime:
         maxder = [2] * d + [prob.p_t]
         self.E = [[bspline_all(self.kn[l], self.p[l], self.quad[l][0], k) for k in range(maxder[l] + 1)]
                   for l in range(d + 1)]
+        # separable geometry: physical Gauss points and weights (w F'), and
+        # physical derivatives d/dx = (1/F') d/deta,
+        # d2/dx2 = (1/F'^2) d2/deta2 - (F''/F'^3) d/deta
+        self.maps = [geometry_map(prob, l) for l in range(d)]
+        self.grev_phys = []
+        for l in range(d):
+            mp = self.maps[l]
+            eta, w, el = self.quad[l]
+            g = greville(self.kn[l], self.p[l])
+            if mp is None:
+                self.grev_phys.append(g)
+                continue
+            F, F1, F2 = mp(eta)
+            E0, E1, E2 = self.E[l]
+            self.E[l] = [E0, E1 / F1[:, None], E2 / (F1 ** 2)[:, None] - (F2 / F1 ** 3)[:, None] * E1]
+            self.quad[l] = (F, w * F1, el)
+            self.grev_phys.append(mp(g)[0])
         self.omega = self._outer([self.quad[l][1] for l in range(d + 1)])
         self.taus = tau_splines(self.kn[d], prob.p_t, prob.p_t + 1 + nq_extra)
         tq = self.quad[d][0]
@@ -133,7 +168,8 @@ class SpaceTime:
         self.grev_s = [greville(self.kn[l], self.p[l]) for l in range(d)]
         self.grev_t = greville(self.kn[d], self.p[d])[1:]          # X_t Greville points
         self.Ht = hat_matrix(self.grev_t, tq)
-        self.Hs = [hat_matrix(self.grev_s[l], self.quad[l][0]) for l in range(d)]
+        # theta's interpolation at the Greville abscissae mapped to the physical domain
+        self.Hs = [hat_matrix(self.grev_phys[l], self.quad[l][0]) for l in range(d)]
         self.shape = tuple([self.n[d]] + [self.n[l] for l in range(d - 1, -1, -1)])
         self.qshape = tuple([len(self.quad[d][0])] + [len(self.quad[l][0]) for l in range(d - 1, -1, -1)])
         self._phi = {}
@@ -207,8 +243,8 @@ class SpaceTime:
 
     # --------------------------------------------------------- initial datum
     def lift(self) -> np.ndarray:
-        """Coefficients of the lifted initial datum: u0 at the spatial Greville grid."""
-        grids = np.meshgrid(*[self.grev_s[l] for l in range(self.d - 1, -1, -1)], indexing="ij")
+        """Coefficients of the lifted initial datum: u0 at the (mapped) spatial Greville grid."""
+        grids = np.meshgrid(*[self.grev_phys[l] for l in range(self.d - 1, -1, -1)], indexing="ij")
         pts = np.stack([grids[self.d - 1 - l].reshape(-1) for l in range(self.d)], axis=1)
         return self.P.u0(pts)
 

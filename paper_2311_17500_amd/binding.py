@@ -31,7 +31,8 @@ class Problem(C.Structure):
     _fields_ = [("d", C.c_int32), ("p_s", C.c_int32), ("p_t", C.c_int32), ("nknots", C.c_int32 * 4),
                 ("knots", C.POINTER(C.c_double) * 4), ("T", C.c_double), ("Cm", C.c_double),
                 ("sigma", C.c_double * 3), ("a", C.c_double), ("b", C.c_double), ("c1", C.c_double),
-                ("c2", C.c_double), ("de", C.c_double)]
+                ("c2", C.c_double), ("de", C.c_double), ("map_kind", C.c_int32 * 3),
+                ("map_param", (C.c_double * 3) * 3)]
 
 
 class Stimulus(C.Structure):
@@ -137,6 +138,12 @@ def make_problem(prob, knots=None):
     for l, s in enumerate(prob.sigma):
         P.sigma[l] = s
     P.a, P.b, P.c1, P.c2, P.de = prob.a, prob.b, prob.c1, prob.c2, prob.de
+    mk = getattr(prob, "map_kind", (0, 0, 0))
+    mp = getattr(prob, "map_param", ((0.0, 1.0, 0.0),) * 3)
+    for l in range(3):
+        P.map_kind[l] = int(mk[l]) if l < len(mk) else 0
+        for j in range(3):
+            P.map_param[l][j] = float(mp[l][j]) if l < len(mp) else (0.0, 1.0, 0.0)[j]
     return P, arrs
 
 

@@ -270,6 +270,50 @@ bool build_dir(const double* knots01, int nk, int p, double scale, int nder, Dir
     for (int k = i + 1; k <= i + p; ++k) s += D.knots[k];
     D.grev[i] = s / p;
   }
+  D.grev_x = D.grev;
+  return true;
+}
+
+bool apply_map(Dir1D& D, int kind, const double* prm, std::string& err) {
+  if (kind == 0) return true;
+  if (kind != 1 && kind != 2) { err = "unknown geometry map"; return false; }
+  const double a = prm[0], b = prm[1], k = prm[2];
+  if (!(b > a) || !std::isfinite(a) || !std::isfinite(b)) { err = "geometry map needs a < b"; return false; }
+  if (kind == 2 && (!(std::fabs(k) > 1e-8) || !(std::fabs(k) < 50.0))) {
+    err = "graded geometry map needs 1e-8 < |k| < 50";
+    return false;
+  }
+  // F, F', F'' at a parametric point
+  auto map = [&](double e, double& F, double& F1, double& F2) {
+    if (kind == 1) {
+      F = a + (b - a) * e;
+      F1 = b - a;
+      F2 = 0.0;
+    } else {
+      const double den = std::expm1(k);
+      F = a + (b - a) * std::expm1(k * e) / den;
+      F1 = (b - a) * k * std::exp(k * e) / den;
+      F2 = k * F1;
+    }
+  };
+  const int p1 = D.p + 1;
+  for (int q = 0; q < D.Q; ++q) {
+    double F, F1, F2;
+    map(D.xq[q], F, F1, F2);
+    D.xq[q] = F;
+    D.wq[q] *= F1;
+    for (int r = 0; r < p1; ++r) {
+      const size_t i = static_cast<size_t>(q) * p1 + r;
+      const double d1 = D.B[1][i];
+      if (D.nder >= 2) D.B[2][i] = D.B[2][i] / (F1 * F1) - F2 * d1 / (F1 * F1 * F1);
+      D.B[1][i] = d1 / F1;
+    }
+  }
+  for (int i = 0; i < D.n; ++i) {
+    double F, F1, F2;
+    map(D.grev[i], F, F1, F2);
+    D.grev_x[i] = F;
+  }
   return true;
 }
 

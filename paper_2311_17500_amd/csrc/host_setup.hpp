@@ -25,8 +25,19 @@ struct Dir1D {
   std::vector<double> xq, wq;  // Gauss points / weights, element-major
   std::vector<int> first;      // index of the first non-zero basis function at each point
   std::vector<std::vector<double>> B;  // B[k][q*(p+1)+j] = k-th derivative of basis first[q]+j at xq[q]
-  std::vector<double> grev;    // Greville abscissae
+  std::vector<double> grev;    // Greville abscissae (parametric)
+  std::vector<double> grev_x;  // the same mapped to the physical axis (equal to grev for the identity map)
 };
+
+// Separable geometry map x = F(eta) of one spatial direction (the spatial
+// part of the map G = (F, T tau) of Section 2 with a diagonal Jacobian):
+// kind 0 identity, 1 affine F = a + (b - a) eta, 2 exponential grading
+// F = a + (b - a) (exp(k eta) - 1) / (exp(k) - 1).  Rewrites the direction's
+// Gauss data to physical quantities: points F(eta_q), weights w_q F'(eta_q),
+// first derivatives b'/F', second derivatives b''/F'^2 - F'' b'/F'^3, and
+// the mapped Greville abscissae; knots, spans and element windows stay
+// parametric.  False with a message for invalid parameters.
+bool apply_map(Dir1D& D, int kind, const double* param, std::string& err);
 
 // Sparse row table for y[i] = sum_w coef[i*W+w] * x[col[i*W+w]].
 struct Gather {

@@ -370,8 +370,10 @@ void host_setup(st_iga_ctx* c) {
   c->d = P.d;
   c->dir.assign(P.d + 1, Dir1D());
   std::string err;
-  for (int l = 0; l < P.d; ++l)
+  for (int l = 0; l < P.d; ++l) {
     if (!build_dir(P.knots[l], P.nknots[l], P.p_s, 1.0, 2, c->dir[l], err)) throw Fail{ST_IGA_EINVAL, "space knots: " + err};
+    if (!apply_map(c->dir[l], P.map_kind[l], P.map_param[l], err)) throw Fail{ST_IGA_EINVAL, err};
+  }
   if (!build_dir(P.knots[P.d], P.nknots[P.d], P.p_t, P.T, P.p_t, c->dir[P.d], err))
     throw Fail{ST_IGA_EINVAL, "time knots: " + err};
   const Dir1D& T = c->dir[P.d];
@@ -431,7 +433,7 @@ void host_setup(st_iga_ctx* c) {
     c->Ks[l].h = banded_table(K, D.n, 0, D.n, D.p);
     for (int k = 0; k <= 2; ++k) c->Bq[l][k].h = eval_table(D, k);
     c->BqT[l].h = eval_table_T(D, 0, nullptr);
-    c->Hs[l].h = hat_table(D.grev, D.xq);
+    c->Hs[l].h = hat_table(D.grev_x, D.xq);   // interpolation at the mapped Greville abscissae
     c->Gs[l].h = sparse_rows(collocation(D, D.grev, 0), D.n, D.n);
     if (!gen_eig_sym(K, M, D.n, c->Us_h[l], c->lam_h[l], err)) throw Fail{ST_IGA_EINVAL, err};
     c->Us[l].h = dense_table(c->Us_h[l], D.n, D.n, false);
@@ -2054,7 +2056,7 @@ std::vector<double> lift_host(st_iga_ctx* c, const st_iga_stimulus* st, int64_t*
     double x[3] = {0, 0, 0};
     int64_t r = j;
     for (int l = 0; l < c->d; ++l) {
-      x[l] = c->dir[l].grev[r % c->n[l]];
+      x[l] = c->dir[l].grev_x[r % c->n[l]];
       r /= c->n[l];
     }
     bool in = false;
@@ -2539,7 +2541,7 @@ st_iga_status st_iga_host_query(const st_iga_problem* prob, int32_t what, int32_
     const Dir1D& D = c.dir[dir];
     std::vector<double> v;
     switch (what) {
-      case 0: v = D.grev; break;
+      case 0: v = D.grev_x; break;
       case 1: v = gram1d(D, 0, 0, nullptr); break;
       case 2: v = gram1d(D, 1, 1, nullptr); break;
       case 3: v = gram1d(D, 0, 1, nullptr); break;

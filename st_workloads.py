@@ -64,6 +64,11 @@ class Problem:
     f_amp: float = 0.0
     f_kappa: float = 0.0
     f_velocity: Tuple[float, ...] = (0.0, 0.0, 0.0)
+    # separable geometry map of each spatial direction, x_l = F_l(eta_l):
+    # 0 identity, 1 affine a + (b - a) eta, 2 exponential grading
+    # a + (b - a) (exp(k eta) - 1) / (exp(k) - 1); map_param[l] = (a, b, k)
+    map_kind: Tuple[int, ...] = (0, 0, 0)
+    map_param: Tuple[Tuple[float, float, float], ...] = ((0.0, 1.0, 0.0),) * 3
 
     @property
     def n_s(self):

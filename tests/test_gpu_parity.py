@@ -548,3 +548,50 @@ def test_precond_bf16_mfma(gpu_lib, torch, name, prob):
     z = S.precond_lowp(to_dev(torch, r)).cpu().numpy()
     want = solver.precond_solve(st, r)
     assert rel(z, want) < 5e-2
+
+
+# Separable geometry maps x_l = F_l(eta_l) (Section 2; the spatial part of G).
+GEO = [("1d_graded", W.tiny(1, 2, 9, nel_t=7, map_kind=(2, 0, 0), map_param=((0.0, 2.0, 2.0),) * 3,
+                            u0_center=(0.3, 0.0, 0.0))),
+       ("2d_graded", W.tiny(2, 3, 5, nel_t=6, map_kind=(2, 2, 0),
+                            map_param=((0.0, 1.5, 2.5), (-0.5, 0.5, -1.5), (0, 1, 0)), u0_center=(0.0, 0.5, 0.0))),
+       ("3d_mixed", W.tiny(3, 2, 3, nel_t=5, map_kind=(1, 2, 2),
+                           map_param=((0.0, 1.2, 0.0), (0.0, 1.0, 1.5), (0.0, 0.8, -2.0)), u0_radius=0.5))]
+
+
+@pytest.mark.parametrize("name,prob", GEO, ids=[n for n, _ in GEO])
+def test_geometry_linearization_and_operators(gpu_lib, torch, name, prob):
+    """On a mapped box: the lifted datum at the mapped Greville points (bit
+    exact), theta (physical Laplacian, interpolation at mapped Greville
+    points), the linearized operator, the FD preconditioner built from the
+    mapped 1D pencils against the oracle's direct solve, and the residual."""
+    st = SpaceTime(prob)
+    S = solver_for(prob)
+    c0, cnt = S.lift()
+    assert np.array_equal(c0, st.lift()) and cnt > 0
+    u, w = W.smooth_state(prob, 14)
+    ud, wd = to_dev(torch, u), to_dev(torch, w)
+    th = S.theta_grid(ud, wd).cpu().numpy()
+    assert np.max(np.abs(th - st.theta_grid(u, w).reshape(-1))) < 1e-12
+    S.linearize(ud, wd)
+    lin = solver.linearize(st, u, w)
+    gt, gc = S.get_factors()
+    assert len(gt[1]) == lin.theta_lr.R and len(gc[1]) == lin.coef_lr.R
+    x = W.random_vector(prob.unknowns, 34)
+    assert rel(S.apply(to_dev(torch, x)).cpu().numpy(), st.apply_J(x, lin.coef_q, lin.theta_q)) < 1e-11
+    kappa = np.linalg.cond(st.assemble_precond().toarray())
+    z = S.precond(to_dev(torch, x)).cpu().numpy()
+    assert rel(z, solver.precond_solve(st, x)) < max(1e-11, 20 * kappa * np.finfo(float).eps)
+    r = S.residual(ud, wd).cpu().numpy()
+    assert rel(r, st.residual(u, w, lin.theta_q)) < 1e-11
+
+
+@pytest.mark.parametrize("name,prob", GEO[:2], ids=[n for n, _ in GEO[:2]])
+def test_geometry_full_solve(gpu_lib, name, prob):
+    S = solver_for(prob, tol_nonlin=1e-11, tol_lin=1e-12)
+    st = SpaceTime(prob)
+    u, w, rep = S.solve()
+    uo, wo, log = solver.solve(st, tol=1e-11)
+    assert rep.outer_iters == len(log.deltas)
+    assert rel(u.cpu().numpy(), uo) < 1e-10
+    assert rel(w.cpu().numpy(), wo) < 1e-10

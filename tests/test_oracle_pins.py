@@ -520,3 +520,88 @@ def test_paper_picard_reaches_newton_solution():
     assert lp.deltas[-1] <= 1e-12 and ln.deltas[-1] <= 1e-12
     assert np.max(np.abs(un - up)) < 1e-10
     assert np.max(np.abs(wn - wp)) < 1e-10
+
+
+# ---------------------------------------------------------------- separable geometry (Section 2, map G = (F, T tau))
+MAPS = [(1, (0.2, 1.7, 0.0)), (2, (-0.5, 1.0, 2.5)), (2, (0.0, 2.0, -1.7))]
+
+
+@pytest.mark.parametrize("kind,param", MAPS)
+def test_geometry_derivatives_by_differences(kind, param):
+    """Physical first and second derivatives of a spline at the mapped Gauss
+    points against central differences in x through the inverse map
+    (bisection), for random coefficients."""
+    P = W.tiny(1, 3, 5, map_kind=(kind, 0, 0), map_param=(param,) * 3)
+    st = SpaceTime(P)
+    a, b, k = param
+    rng = np.random.default_rng(kind)
+    c = rng.standard_normal(st.n[0])
+    kn = st.kn[0]
+
+    def F(e):
+        return a + (b - a) * e if kind == 1 else a + (b - a) * np.expm1(k * e) / np.expm1(k)
+
+    def Finv(x):
+        lo, hi = np.zeros_like(x), np.ones_like(x)
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            go = F(mid) < x
+            lo, hi = np.where(go, mid, lo), np.where(go, hi, mid)
+        return 0.5 * (lo + hi)
+
+    def g(x):
+        return bspline_all(kn, 3, Finv(x)) @ c
+    xq = st.quad[0][0]
+    h1, h2 = 1e-6 * (b - a), 1e-4 * (b - a)
+    d1 = (g(xq + h1) - g(xq - h1)) / (2 * h1)
+    d2 = (g(xq + h2) - 2 * g(xq) + g(xq - h2)) / h2 ** 2
+    assert np.max(np.abs(st.E[0][1] @ c - d1)) < 1e-6 * max(1.0, np.max(np.abs(d1)))
+    assert np.max(np.abs(st.E[0][2] @ c - d2)) < 1e-3 * max(1.0, np.max(np.abs(d2)))
+    # mapped Gauss points and Greville abscissae
+    assert np.allclose(xq, F(quadrature(kn, 4)[0]), rtol=0, atol=1e-14)
+    assert np.allclose(st.grev_phys[0], F(greville(kn, 3)), rtol=0, atol=1e-14)
+
+
+def test_geometry_measure():
+    """Space-time mass = |Omega| T with |Omega| the physical measure of the
+    mapped box (exact for the affine direction; for the graded one the Gauss
+    rule integrates F' = c e^{k eta} with an error that vanishes as the rule
+    grows); K 1 = 0 in every direction."""
+    mp = ((0.2, 1.7, 0.0), (-0.5, 1.0, 2.5), (0, 1, 0))
+    for extra, tol in ((0, 1e-6), (4, 1e-13)):
+        P = W.tiny(2, 2, 4, nel_t=3, T=1.5, map_kind=(1, 2, 0), map_param=mp)
+        st = SpaceTime(P, nq_extra=extra)
+        one = np.ones(int(np.prod(st.shape)))
+        assert np.sum(st.evT(st.omega * st.ev(one, {}), {})) == pytest.approx(1.5 * 1.5 * 1.5, rel=tol)
+    for l in range(2):
+        assert np.max(np.abs(st.ev(one, {l: 1}))) < 1e-12
+        assert np.max(np.abs(st.ev(one, {l: 2}))) < 1e-10
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_geometry_manufactured_rate(p):
+    """Linear heat equation on a graded interval x = F(eta) in [0.2, 1.7]
+    (exponential grading, k = 2.5) with sigma = 0.05 and the manufactured
+    u = cos(pi (x - a)/(b - a)) sin(pi t) (Neumann at both ends, zero at
+    t = 0): the physical L2 error of the Galerkin solution decays at order
+    p + 1 under uniform parametric refinement."""
+    import sympy as sy
+    a, b, k = 0.2, 1.7, 2.5
+    X, Tt = sy.symbols("x t")
+    ue = sy.cos(sy.pi * (X - a) / (b - a)) * sy.sin(sy.pi * Tt)
+    D = 0.05
+    fe = sy.lambdify((X, Tt), sy.diff(ue, Tt) - D * sy.diff(ue, X, 2), "numpy")
+    ul = sy.lambdify((X, Tt), ue, "numpy")
+    errs = []
+    for nel in (4, 8, 16):
+        P = W.tiny(1, p, nel, u0_kind=0, c1=0.0, c2=0.0, sigma=(D,), map_kind=(2, 0, 0),
+                   map_param=((a, b, k),) * 3)
+        f = lambda xs, t: fe(xs[0], t)
+        st = SpaceTime(P, su=False, f=f, nq_extra=2)
+        u, w, log = solver.solve(st, tol=1e-12, max_outer=30)
+        uh = (st.E[1][0] @ u.reshape(st.n[1], st.n[0]) @ st.E[0][0].T)
+        ex = ul(st.quad[0][0][None, :], st.quad[1][0][:, None])
+        wt = np.outer(st.quad[1][1], st.quad[0][1])
+        errs.append(np.sqrt(np.sum(wt * (uh - ex) ** 2) / np.sum(wt * ex ** 2)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates[-1] > p + 1 - 0.35, (errs, rates)
