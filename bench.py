@@ -48,9 +48,12 @@ def parse():
     ap.add_argument("--max-rank", type=int, default=None,
                     help="cap of each low rank (default 48; 16 for config 4 to fit HBM)")
     ap.add_argument("--serve", action="store_true", help="run only the serving stream (512 requests)")
-    ap.add_argument("--serve-requests", type=int, default=128,
+    ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving stream sampled in the default run (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--compare-su", action="store_true",
+                    help="fixed-point scheme of Section 3.1 (exact C_r, alpha = 0.5, stop at 1e-4) with and "
+                         "without the SU term on config 1: iteration counts and times")
     ap.add_argument("--kernel-probe", type=int, default=0, metavar="REPS",
                     help="run only the hardware-counter probe (1 GiB copy, then REPS operator applications)")
     return ap.parse_args()
@@ -64,9 +67,14 @@ def serving(n_requests, slots):
     from paper_2311_17500_amd.serve import Server, summarize
     reqs = W.serve_stream(512, 0)[:n_requests]
     srv = Server(slots=slots, prec=MIXED_FP32, tol_lin=1e-8, tol_nonlin=1e-8, lin_forcing=0.1)
-    out = summarize(srv.run(reqs))
+    recs = srv.run(reqs)
+    out = summarize(recs)
+    window = max(t for t, _ in reqs) - min(t for t, _ in reqs)
     out.update({"slots": slots, "arrival_rate_per_s": 20.0, "stream": f"first {n_requests} of 512 (seed 0)",
-                "hbm_budget_bytes": srv.budget})
+                "hbm_budget_bytes": srv.budget, "arrival_window_s": window,
+                "sustained_req_per_s": out["completed"] / out["makespan_s"] if out["makespan_s"] > 0 else None,
+                "unknowns_per_s": sum(p.unknowns for _, p in reqs) / out["makespan_s"] if out["makespan_s"] > 0
+                else None})
     return out
 
 
@@ -319,6 +327,65 @@ def summary(prob, cfg, prec, r, steps):
             "top_kernels": top}
 
 
+def compare_su(torch, W):
+    """Galerkin vs SU with the paper's fixed-point scheme (Section 3.1 with
+    the stopping rule of Section 4) on config 1 and on a source-driven
+    variant of it (zero datum, a disc stimulus during [0.1, 0.2], time knots
+    clustered at the source's on/off times): fixed-point iterations, Krylov
+    iterations per fixed-point iteration, wall time."""
+    from paper_2311_17500_amd.binding import Solver, FP64, StIgaError
+    base = W.config(1)
+    src = dict(base.__dict__)
+    src.update(u0_kind=0, f_kind=1, f_center=(0.0, 0.0, 0.0), f_radius=0.1, f_t0=0.1, f_t1=0.2, f_amp=5.0)
+    # the paper's 2D test (Section 4.2) with its Rogers-McCulloch set, C_m = 1,
+    # D = 1e-4, T = 300, p = 3 and its meshes (2^-6 x 2^-3 x 2^-5) and moving
+    # Gaussian source during [90, 100], on the rectangle [0, 1.5] x [0, 0.125]
+    # (affine map) standing in for the elliptic ring, whose parametrization
+    # the paper does not give
+    L1, L2, Tp = 1.5, 0.125, 300.0
+    paper = W.Problem(d=2, p_s=3, p_t=3, nel_s=(64, 8), nel_t=32, sigma=(1e-4, 1e-4), T=Tp, Cm=1.0,
+                      a=0.13, b=0.013, c1=0.26, c2=0.1, de=1.0, u0_kind=0,
+                      f_kind=2, f_center=(0.0, L2 / 2, 0.0), f_velocity=(8.0 / 15.0 * L1 / Tp, 0.0, 0.0),
+                      f_kappa=500.0, f_amp=0.25, f_t0=90.0, f_t1=100.0,
+                      map_kind=(1, 1, 0), map_param=((0.0, L1, 0.0), (0.0, L2, 0.0), (0.0, 1.0, 0.0)))
+    cases = [("config1", base, None),
+             ("config1_source_clustered_time", W.Problem(**src),
+              W.clustered_time_knots(base.nel_t, base.p_t, [0.1, 0.2], 0.004)),
+             ("paper2d_uniform_time", paper, None),
+             ("paper2d_clustered_time", paper, W.clustered_time_knots(32, 3, [90.0 / Tp, 100.0 / Tp], 0.003))]
+    out = {}
+    for name, prob, tk in cases:
+        knots = None
+        if tk is not None:
+            knots = prob.uniform_knots()
+            knots[prob.d] = tk
+        for su in (1, 0):
+            S = Solver(prob, knots=knots, prec=FP64, su=su, outer=2, alpha=0.5, tol_nonlin=1e-4, tol_lin=1e-8,
+                       max_outer=300)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            status = "ok"
+            try:
+                u, w, rep = S.solve()
+            except StIgaError as e:
+                status = str(e)
+                rep = None
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rec = {"status": status, "seconds": dt}
+            if rep is not None:
+                n = rep.outer_iters
+                rec.update({"fixed_point_iters": n, "krylov_total": rep.krylov_total,
+                            "krylov_per_fixed_point": rep.krylov_total / max(n, 1),
+                            "theta_rank_last": rep.rank_theta[min(n, 64) - 1] if su else 0,
+                            "u_max": float(u.abs().max()), "u_min": float(u.min())})
+            out[f"{name}_{'su' if su else 'galerkin'}"] = rec
+            log(f"{name} su={su}: {rec}")
+            S.close()
+            torch.cuda.empty_cache()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -329,6 +396,9 @@ def main():
     import st_workloads as W
     if a.kernel_probe > 0:
         kernel_probe(a.config, a.kernel_probe)
+        return
+    if a.compare_su:
+        print(json.dumps({"compare_su": compare_su(torch, W)}), flush=True)
         return
     if a.serve:
         s = serving(512, a.serve_slots)

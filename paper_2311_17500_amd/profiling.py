@@ -3,6 +3,7 @@
     python -m paper_2311_17500_amd.profiling stats <kernel_stats.csv> <out.txt> "<command>"
     python -m paper_2311_17500_amd.profiling traffic <fetch_dir> <write_dir> <out.json> "<command>" [config]
     python -m paper_2311_17500_amd.profiling resources <remarks.txt> <out.txt> "<command>"
+    python -m paper_2311_17500_amd.profiling activity <dir1,dir2,...> <out.txt> "<command>"
 
 `stats` turns the per-kernel statistics of a `rocprofv3 --kernel-trace
 --stats` run into a short text table (kernel, calls, total and average
@@ -138,6 +139,57 @@ def traffic(fetch_dir: str, write_dir: str, out_json: str, command: str, cfg: st
         json.dump(doc, fh, indent=1, sort_keys=True)
 
 
+def activity(dirs: str, out_txt: str, command: str, cus: int = 256, simds: int = 1024) -> None:
+    """Per-kernel hardware activity from one or more `rocprofv3 --pmc` runs
+    (comma-separated output directories, at most 8 SQ counters and one GRBM
+    counter each): counter values averaged over each kernel's dispatches and
+    the usual derived ratios (VALU busy = 4 SQ_ACTIVE_INST_VALU / SIMDs /
+    GRBM_GUI_ACTIVE, MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (CUs 4
+    GRBM_GUI_ACTIVE), LDS bank-conflict share = SQ_LDS_BANK_CONFLICT /
+    SQ_LDS_IDX_ACTIVE, instructions per wave)."""
+    vals = defaultdict(lambda: defaultdict(list))
+    for d in dirs.split(","):
+        for r in _rows(_find(d, "counter_collection.csv")):
+            name = r.get("Kernel_Name") or r.get("KernelName") or ""
+            if "stiga" not in name:
+                continue
+            vals[short_name(name)][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    avg = {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in vals.items()}
+
+    def ratio(a, b, scale=1.0):
+        return scale * a / b if (a is not None and b) else None
+    lines = ["# hardware activity per kernel (rocprofv3 --pmc, values averaged over the kernel's dispatches)",
+             f"# command: {command}",
+             "# VALU%: 4 SQ_ACTIVE_INST_VALU / SIMDs / GRBM_GUI_ACTIVE;  MFMA%: SQ_VALU_MFMA_BUSY_CYCLES / "
+             "(CUs 4 GRBM_GUI_ACTIVE);", "# LDS conf%: SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE;  "
+             "VALU/w, MFMA/w, VMEM/w, LDS/w: instructions per wave;  wait%: SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES", "",
+             f"{'kernel':28s} {'waves':>8s} {'VALU%':>6s} {'MFMA%':>6s} {'LDSconf%':>8s} {'VALU/w':>8s} "
+             f"{'MFMA/w':>7s} {'VMEM/w':>7s} {'LDS/w':>7s} {'wait%':>6s}"]
+    for k in sorted(avg, key=lambda n: -avg[n].get("GRBM_GUI_ACTIVE", 0.0)):
+        a = avg[k]
+        g = a.get("GRBM_GUI_ACTIVE")
+        wv = a.get("SQ_WAVES")
+        vmem = (a.get("SQ_INSTS_VMEM_RD", 0.0) + a.get("SQ_INSTS_VMEM_WR", 0.0)) if "SQ_INSTS_VMEM_RD" in a else None
+        cells = [ratio(a.get("SQ_ACTIVE_INST_VALU"), g, 4.0 * 100.0 / simds) if "SQ_ACTIVE_INST_VALU" in a else None,
+                 ratio(a.get("SQ_VALU_MFMA_BUSY_CYCLES"), g, 100.0 / (4 * cus)) if "SQ_VALU_MFMA_BUSY_CYCLES" in a else None,
+                 ratio(a.get("SQ_LDS_BANK_CONFLICT"), a.get("SQ_LDS_IDX_ACTIVE"), 100.0) if "SQ_LDS_BANK_CONFLICT" in a else None,
+                 ratio(a.get("SQ_INSTS_VALU"), wv) if "SQ_INSTS_VALU" in a else None,
+                 ratio(a.get("SQ_INSTS_MFMA"), wv) if "SQ_INSTS_MFMA" in a else None,
+                 ratio(vmem, wv),
+                 ratio(a.get("SQ_INSTS_LDS"), wv) if "SQ_INSTS_LDS" in a else None,
+                 ratio(a.get("SQ_WAIT_INST_ANY"), a.get("SQ_WAVE_CYCLES"), 100.0) if "SQ_WAIT_INST_ANY" in a else None]
+        fmt = lambda v, w, p: (f"{v:{w}.{p}f}" if v is not None else f"{'-':>{w}s}")
+        lines.append(f"{k[:28]:28s} {(wv or 0):8.0f} {fmt(cells[0], 6, 1)} {fmt(cells[1], 6, 1)} {fmt(cells[2], 8, 1)} "
+                     f"{fmt(cells[3], 8, 0)} {fmt(cells[4], 7, 0)} {fmt(cells[5], 7, 0)} {fmt(cells[6], 7, 0)} "
+                     f"{fmt(cells[7], 6, 1)}")
+    lines.append("")
+    lines.append("# raw averages")
+    for k in sorted(avg):
+        lines.append(f"{k}: " + ", ".join(f"{c}={v:.4g}" for c, v in sorted(avg[k].items())))
+    with open(out_txt, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def resources(remarks_txt: str, out_txt: str, command: str) -> None:
     """Per-kernel register, LDS, spill and occupancy figures from the
     compiler's `-Rpass-analysis=kernel-resource-usage` remarks."""
@@ -185,6 +237,8 @@ def resources(remarks_txt: str, out_txt: str, command: str) -> None:
 if __name__ == "__main__":
     if len(sys.argv) >= 5 and sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif len(sys.argv) >= 5 and sys.argv[1] == "activity":
+        activity(sys.argv[2], sys.argv[3], sys.argv[4])
     elif len(sys.argv) >= 5 and sys.argv[1] == "resources":
         resources(sys.argv[2], sys.argv[3], sys.argv[4])
     elif len(sys.argv) >= 6 and sys.argv[1] == "traffic":

@@ -58,7 +58,14 @@ class Server:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
 
     def footprint(self, prob) -> int:
-        return binding.workspace_bytes(prob, **self.options) + 2 * prob.dof * 8 + (1 << 20)
+        """HBM bytes a request holds while admitted (workspace + u, w), cached
+        per mesh shape (the workspace does not depend on sigma or the stimulus)."""
+        key = (prob.d, prob.p_s, prob.p_t, tuple(prob.nel_s), prob.nel_t)
+        if not hasattr(self, "_fp_cache"):
+            self._fp_cache = {}
+        if key not in self._fp_cache:
+            self._fp_cache[key] = binding.workspace_bytes(prob, **self.options) + 2 * prob.dof * 8 + (1 << 20)
+        return self._fp_cache[key]
 
     def _solve(self, slot: int, prob, rec: Record, t0: float):
         torch = self.torch
