@@ -139,14 +139,15 @@ def traffic(fetch_dir: str, write_dir: str, out_json: str, command: str, cfg: st
         json.dump(doc, fh, indent=1, sort_keys=True)
 
 
-def activity(dirs: str, out_txt: str, command: str, cus: int = 256, simds: int = 1024) -> None:
+def activity(dirs: str, out_txt: str, command: str, cus: int = 256, simds: int = 1024, xcds: int = 8) -> None:
     """Per-kernel hardware activity from one or more `rocprofv3 --pmc` runs
     (comma-separated output directories, at most 8 SQ counters and one GRBM
     counter each): counter values averaged over each kernel's dispatches and
     the usual derived ratios (VALU busy = 4 SQ_ACTIVE_INST_VALU / SIMDs /
-    GRBM_GUI_ACTIVE, MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (CUs 4
-    GRBM_GUI_ACTIVE), LDS bank-conflict share = SQ_LDS_BANK_CONFLICT /
-    SQ_LDS_IDX_ACTIVE, instructions per wave)."""
+    G, MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (CUs 4 G), with G the active
+    cycles of one XCD: GRBM_GUI_ACTIVE, which sums the XCDs' GRBMs, divided by
+    the XCD count; LDS bank-conflict share = SQ_LDS_BANK_CONFLICT /
+    SQ_LDS_IDX_ACTIVE; instructions per wave)."""
     vals = defaultdict(lambda: defaultdict(list))
     for d in dirs.split(","):
         for r in _rows(_find(d, "counter_collection.csv")):
@@ -160,14 +161,15 @@ def activity(dirs: str, out_txt: str, command: str, cus: int = 256, simds: int =
         return scale * a / b if (a is not None and b) else None
     lines = ["# hardware activity per kernel (rocprofv3 --pmc, values averaged over the kernel's dispatches)",
              f"# command: {command}",
-             "# VALU%: 4 SQ_ACTIVE_INST_VALU / SIMDs / GRBM_GUI_ACTIVE;  MFMA%: SQ_VALU_MFMA_BUSY_CYCLES / "
-             "(CUs 4 GRBM_GUI_ACTIVE);", "# LDS conf%: SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE;  "
+             "# G = GRBM_GUI_ACTIVE / 8 (the counter sums the 8 XCDs' GRBMs): one XCD's active cycles",
+             "# VALU%: 4 SQ_ACTIVE_INST_VALU / SIMDs / G;  MFMA%: SQ_VALU_MFMA_BUSY_CYCLES / (CUs 4 G);", "# LDS conf%: SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE;  "
              "VALU/w, MFMA/w, VMEM/w, LDS/w: instructions per wave;  wait%: SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES", "",
              f"{'kernel':28s} {'waves':>8s} {'VALU%':>6s} {'MFMA%':>6s} {'LDSconf%':>8s} {'VALU/w':>8s} "
              f"{'MFMA/w':>7s} {'VMEM/w':>7s} {'LDS/w':>7s} {'wait%':>6s}"]
     for k in sorted(avg, key=lambda n: -avg[n].get("GRBM_GUI_ACTIVE", 0.0)):
         a = avg[k]
         g = a.get("GRBM_GUI_ACTIVE")
+        g = g / xcds if g else g
         wv = a.get("SQ_WAVES")
         vmem = (a.get("SQ_INSTS_VMEM_RD", 0.0) + a.get("SQ_INSTS_VMEM_WR", 0.0)) if "SQ_INSTS_VMEM_RD" in a else None
         cells = [ratio(a.get("SQ_ACTIVE_INST_VALU"), g, 4.0 * 100.0 / simds) if "SQ_ACTIVE_INST_VALU" in a else None,
