@@ -105,7 +105,9 @@ def solve_picard(st: SpaceTime, alpha=0.5, eps_theta=0.1, tol=1e-4, max_outer=20
          when given; a fixed theta_lr skips this step);
       2. assembles A of Section 3.1.1 with M_R weighted by the exact
          C_r(u^k, w^k) of eq. (3.6) at the Gauss points and the low-rank SU
-         term, and the load vector F;
+         term (or, with SUPG, the SUPG and shock-capturing terms of Section
+         4.2.2 with C_r and the residual ratio at (u^k, w^k) taken exactly at
+         the Gauss points), and the load vector F;
       3. solves A u~ = F for the unknown layers, the initial layer held at the
          lifted datum (sparse LU);
       4. solves L w~ = G(u^k) (the decoupled w-equation);
@@ -125,7 +127,9 @@ def solve_picard(st: SpaceTime, alpha=0.5, eps_theta=0.1, tol=1e-4, max_outer=20
         if st.su and not frozen:
             theta_lr = st.lowrank(st.theta_grid(u, w), eps_theta)
         theta_q = st.lowrank_at_quad(theta_lr) if st.su else None
-        A = st.assemble_full(st.reaction_at_quad(u, w), theta_q)
+        # SUPG + shock capturing (Section 4.2.2): the coefficients at (u^k, w^k)
+        sc_q = st.sc_coefficient(u, w) if (st.supg and st.sc_c > 0.0) else None
+        A = st.assemble_full(st.reaction_at_quad(u, w), theta_q, sc_q)
         rhs = F[N_s:] - A[N_s:, :N_s] @ c0
         ut = np.concatenate([c0, spla.splu(sp_csc(A[N_s:, N_s:])).solve(rhs)])
         wt = st.w_update_explicit(u)

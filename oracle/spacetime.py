@@ -41,6 +41,13 @@ Readings taken here (the paper is silent or ambiguous):
   ||delta||_inf > theta_freeze and then kept fixed.
 * The FD preconditioner of Section 3.2 uses sigma-scaled stiffness matrices
   (the paper's parametric version has unit diffusion).
+* SUPG + shock capturing (Section 4.2.2): h in h/(2p+1) and c h^2/4 is the
+  length of the time element (the streamline direction of the space-time
+  operator is time), in physical time units; the diffusion part of the SUPG
+  term is the strong form -sum_l sigma_l u_ll at the Gauss points, as the
+  residual is written; C_r and the residual ratio of S_SC are taken exactly at
+  the Gauss points (the paper low-ranks both to make assembly cheaper); the
+  ratio is not capped and is zero when its denominator vanishes (u = 0).
 """
 from __future__ import annotations
 
@@ -126,7 +133,8 @@ class SpaceTime:
     """Discrete space-time problem of one workload (see module doc)."""
 
     def __init__(self, prob, knots: Optional[List[np.ndarray]] = None, mode: str = "explicit",
-                 nq_extra: int = 0, su: bool = True, f: Optional[Callable] = None):
+                 nq_extra: int = 0, su: bool = True, f: Optional[Callable] = None, supg: bool = False,
+                 sc_c: float = 0.0):
         self.P = prob
         d = prob.d
         self.d = d
@@ -135,7 +143,12 @@ class SpaceTime:
         self.p = [prob.p_s] * d + [prob.p_t]
         self.n = [n_basis(k, p) for k, p in zip(self.kn, self.p)]
         self.mode = mode
+        if su and supg:
+            raise ValueError("the Spline Upwind and the SUPG + shock-capturing terms are alternatives")
         self.su = su
+        # SUPG + shock capturing (Section 4.2.2), for splines of any regularity in time
+        self.supg = supg
+        self.sc_c = float(sc_c)
         # the source of eq. (3.1): given explicitly, or the problem's own
         self.f = f if f is not None else (prob.source if getattr(prob, "f_kind", 0) else None)
         # axis a of an array (time first): a = 0 is time, a = 1 is x_d, ..., a = d is x_1
@@ -162,9 +175,15 @@ class SpaceTime:
             self.quad[l] = (F, w * F1, el)
             self.grev_phys.append(mp(g)[0])
         self.omega = self._outer([self.quad[l][1] for l in range(d + 1)])
-        self.taus = tau_splines(self.kn[d], prob.p_t, prob.p_t + 1 + nq_extra)
         tq = self.quad[d][0]
-        self.tau_q = [eval_spline(kk, q, c, tq) for kk, q, c in self.taus]
+        # the tau_k splines of the SU term need C^{p-1} time splines: built for SU only
+        self.taus = tau_splines(self.kn[d], prob.p_t, prob.p_t + 1 + nq_extra) if su else None
+        self.tau_q = [eval_spline(kk, q, c, tq) for kk, q, c in self.taus] if su else None
+        # SUPG parameter h/(2 p_t + 1) and shock-capturing scale c h^2/4 at the
+        # time Gauss points, h the length of the time element holding the point
+        ht = np.diff(breakpoints(self.kn[d]))[self.quad[d][2]]
+        self.supg_tau_t = ht / (2 * prob.p_t + 1)
+        self.sc_scale_t = self.sc_c * ht * ht / 4.0
         self.grev_s = [greville(self.kn[l], self.p[l]) for l in range(d)]
         self.grev_t = greville(self.kn[d], self.p[d])[1:]          # X_t Greville points
         self.Ht = hat_matrix(self.grev_t, tq)
@@ -308,9 +327,14 @@ class SpaceTime:
         N_s = int(np.prod(self.n[:d]))
         return sp.csr_matrix(A)[N_s:, N_s:]
 
-    def assemble_full(self, coef_q, theta_q):
+    def assemble_full(self, coef_q, theta_q, sc_q=None):
         """The same bilinear form on the full basis (all n_t time layers, rows
-        and columns), before the lifting split."""
+        and columns), before the lifting split.  With SUPG (Section 4.2.2) the
+        stabilization is S_SUPG + S_SC instead of the SU term:
+          S_SUPG(u, v) = int tau (C_m u_t - sum_l sigma_l u_ll + coef u) v_t,
+          S_SC(u, v)   = int sc_q u_t v_t,
+        tau = h/(2p+1) per time element and sc_q the shock-capturing
+        coefficient at the Gauss points (``sc_coefficient``; None: no term)."""
         P, d, om = self.P, self.d, self.omega
         Dg = sp.diags
         A = self._constant_part() + self.phi({}).T @ Dg(om * coef_q) @ self.phi({})
@@ -318,13 +342,27 @@ class SpaceTime:
             for k in range(1, P.p_t + 1):
                 tk = np.repeat(self.tau_q[k - 1], int(np.prod(self.qshape[1:])))
                 A = A + P.Cm * self.phi({d: k}).T @ Dg(om * tk * theta_q) @ self.phi({d: k})
+        if self.supg:
+            tau = np.repeat(self.supg_tau_t, int(np.prod(self.qshape[1:])))
+            Pt = self.phi({d: 1})
+            Lu = P.Cm * Pt + Dg(coef_q) @ self.phi({})
+            for l in range(d):
+                Lu = Lu - P.sigma[l] * self.phi({l: 2})
+            A = A + Pt.T @ Dg(om * tau) @ Lu
+            if sc_q is not None:
+                A = A + Pt.T @ Dg(om * sc_q) @ Pt
         return sp.csr_matrix(A)
 
     def load_vector(self):
-        """F(v) = int f v of eq. (3.3) for every full-basis test function."""
+        """F(v) = int f v of eq. (3.3) for every full-basis test function; with
+        SUPG the residual's source also meets the test function tau v_t."""
         if self.f is None:
             return np.zeros(int(np.prod(self.shape)))
-        return self.evT(self.omega * self.f_at_quad(), {})
+        fq = self.omega * self.f_at_quad()
+        F = self.evT(fq, {})
+        if self.supg:
+            F = F + self.evT(np.repeat(self.supg_tau_t, int(np.prod(self.qshape[1:]))) * fq, {self.d: 1})
+        return F
 
     def reaction_at_quad(self, u_full, w_full):
         """C_r(u_h, w_h) of eq. (3.6) at every space-time Gauss point (the
@@ -384,8 +422,10 @@ class SpaceTime:
             out.append((min(es), max(es) + 1))
         return out
 
-    def theta_grid(self, u_full, w_full):
-        """Theta of eq. (3.4) on the (X_t time) x (space) Greville grid: N_t x N_s."""
+    def residual_at_quad(self, u_full, w_full):
+        """The residual R = C_m u_t - sum_l sigma_l u_ll + I_ion(u, w) - f at every
+        Gauss point and the denominator C_m (||u||_inf / T + ||u_t||_inf) of
+        eq. (3.4) (maxima over the Gauss points)."""
         P, d = self.P, self.d
         uq = self.ev(u_full, {})
         wq = self.ev(w_full, {})
@@ -396,6 +436,21 @@ class SpaceTime:
         if self.f is not None:
             R -= self.f_at_quad()
         den = P.Cm * (np.max(np.abs(uq)) / P.T + np.max(np.abs(utq)))
+        return R, den
+
+    def sc_coefficient(self, u_full, w_full):
+        """Shock-capturing coefficient c h^2/4 |R| / (C_m (T^-1 ||u||_inf +
+        ||u_t||_inf)) of Section 4.2.2 at every Gauss point; zero everywhere
+        when the denominator vanishes (u = 0)."""
+        R, den = self.residual_at_quad(u_full, w_full)
+        if not den > 0:
+            return np.zeros_like(R)
+        return np.repeat(self.sc_scale_t, int(np.prod(self.qshape[1:]))) * np.abs(R) / den
+
+    def theta_grid(self, u_full, w_full):
+        """Theta of eq. (3.4) on the (X_t time) x (space) Greville grid: N_t x N_s."""
+        P, d = self.P, self.d
+        R, den = self.residual_at_quad(u_full, w_full)
         # element-wise maxima of |R|
         nq = [self.p[self.dirs[a]] + 1 for a in range(d + 1)]
         nel = [self.qshape[a] // nq[a] for a in range(d + 1)]

@@ -261,3 +261,10 @@ def coefficient_factors(prob: Problem, R: int, seed: int = 0, base: float = 1.5,
     V = np.concatenate([np.ones((prob.N_s, 1)), V], axis=1)
     s = np.concatenate([[base], s])
     return U[:, :R], s[:R], V[:, :R]
+
+
+def c0_time_knots(nel_t: int, p: int):
+    """Open knot vector on [0,1] with nel_t uniform elements and every interior
+    knot repeated p times: C^0 splines in time (n_t = p nel_t + 1)."""
+    inner = np.repeat(np.arange(1, nel_t) / nel_t, p)
+    return np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)])
