@@ -103,7 +103,15 @@ typedef struct {
 } st_iga_stimulus;
 
 typedef struct {
-  int32_t su;                /* 1: Spline Upwind term of eq. (3.2) on, 0: plain Galerkin */
+  int32_t su;                /* stabilization: 1 the Spline Upwind term of eq. (3.2), 0 none (plain
+                                Galerkin), 2 SUPG + shock capturing of Section 4.2.2 (the comparison
+                                method for splines of any regularity in time, C^0 included; needs
+                                outer = 2): the test function v + tau v_t on the residual
+                                C_m u_t - sum_l sigma_l u_ll + C_r u - f (strong form), tau = h/(2p_t+1),
+                                plus int sc_c h^2/4 |R(u^k, w^k)| / (C_m (||u^k||_inf/T +
+                                ||u^k_t||_inf)) u_t v_t (zero when that denominator is 0), h the
+                                length of the time element; C_r and |R| are exact at every Gauss point
+                                (the paper low-ranks both) */
   double eps_theta;          /* relative Frobenius tolerance of the theta low rank, eq. (3.8) (paper: 0.1) */
   double eps_react;          /* same tolerance for the reaction coefficient of the Jacobian */
   int32_t max_rank;          /* cap on each low rank (sizes the workspace); a capped rank misses eps
@@ -143,6 +151,8 @@ typedef struct {
   int32_t picard_switch;     /* > 0: a Newton solve (outer = 0) whose ||delta||_inf grows in this many
                                 consecutive iterations continues as the outer = 1 Picard iteration
                                 (alpha = 0.5); reported in st_iga_report.switched_at; 0: never */
+  double sc_c;               /* shock-capturing constant c >= 0 of the su = 2 stabilization (the paper
+                                leaves it as a tuning parameter); 0 turns the term off */
 } st_iga_options;
 
 #define ST_IGA_MAX_OUTER_LOG 64
@@ -166,7 +176,7 @@ typedef struct {
 /* Defaults: su=1, eps_theta=0.1, eps_react=1e-2, max_rank=48, outer=0,
  * alpha=1 (Newton), theta_freeze=1e-4, tol_nonlin=1e-10, tol_lin=1e-10,
  * inner_tol=1e-4, restart=30, max_outer=60, max_krylov=3000, prec=FP64, lin_forcing=0,
- * coef_slab=0, reorth=2, graphs=1, stall_cycles=10, stall_reduction=1e-3, picard_switch=0. */
+ * coef_slab=0, reorth=2, graphs=1, stall_cycles=10, stall_reduction=1e-3, picard_switch=0, sc_c=1. */
 void st_iga_default_options(st_iga_options* opt);
 
 /* Bytes of device workspace st_iga_setup needs for this problem/options

@@ -793,6 +793,19 @@ Gather eval_table_T(const Dir1D& D, int der, const std::vector<double>* ws) {
   return G;
 }
 
+Gather streamline_table_T(const Dir1D& D, const std::vector<double>& tau) {
+  Gather G = eval_table_T(D, 0, nullptr);
+  // same rows and columns as the value projection; coefficients b + tau b'
+  std::vector<int> fill(D.n, 0);
+  for (int q = 0; q < D.Q; ++q)
+    for (int j = 0; j <= D.p; ++j) {
+      const int i = D.first[q] + j;
+      const size_t k = static_cast<size_t>(i) * G.W + fill[i]++;
+      G.coef[k] = D.B[0][static_cast<size_t>(q) * (D.p + 1) + j] + tau[q] * D.B[1][static_cast<size_t>(q) * (D.p + 1) + j];
+    }
+  return G;
+}
+
 Gather dense_table(const std::vector<double>& A, int nrow, int ncol, bool transpose) {
   Gather G;
   const int no = transpose ? ncol : nrow, ni = transpose ? nrow : ncol;

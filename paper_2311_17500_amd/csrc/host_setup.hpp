@@ -85,6 +85,9 @@ bool time_fd(const std::vector<double>& Wt, const std::vector<double>& Mt, int N
 Gather banded_table(const std::vector<double>& A, int n, int row0, int nrow, int bw);
 Gather eval_table(const Dir1D& D, int der);             // Q x n (expansion to Gauss points)
 Gather eval_table_T(const Dir1D& D, int der, const std::vector<double>* wscale);  // n x Q (projection)
+// Projection onto the streamline test functions b_i + tau b_i' (tau per Gauss
+// point), same layout as eval_table_T(D, 0, nullptr).
+Gather streamline_table_T(const Dir1D& D, const std::vector<double>& tau);
 Gather dense_table(const std::vector<double>& A, int nrow, int ncol, bool transpose);
 
 // Hat-function interpolation weights from nodes to points (constant extension outside).

@@ -614,21 +614,27 @@ __global__ void __launch_bounds__(TPB) k_time_mix(const C* __restrict__ T, const
 
 
 // ---------------------------------------------------------------- exact reaction term
-// Reaction term with a coefficient known at every space-time Gauss point
-// (Cq[g][q] = omega_g omega_q C_r at time Gauss point g and spatial Gauss
-// point q), over one slab of output time rows:
-//   out[t][q] = beta out[t][q] + sum_{e in supp b_i} sum_{g in e} B(g, i) Cq[g][q] sum_a B(g, f_e + a) Z[f_e + a][q]
-// with i = t0 + t + 1 the full index of unknown row t0 + t.  Z holds the
-// spatially expanded input layers of full indices [lo_full, lo_full + nl)
-// (layers outside read as zero: the initial layer of an unknown vector).
-// One thread per (row, spatial point): consecutive threads take consecutive
-// q, so every Z, Cq and out access of a wave is one contiguous segment.
+// Reaction (and shock-capturing) terms with coefficients known at every
+// space-time Gauss point (Cq[g][q] = omega_g omega_q C_r at time Gauss point g
+// and spatial Gauss point q; Rq the same for the shock-capturing coefficient),
+// over one slab of output time rows:
+//   out[t][q] = beta out[t][q]
+//     + sum_{e in supp b_i} sum_{g in e} Bv(g, i) Cq[g][q] sum_a B(g, f_e + a) Z[f_e + a][q]
+//     + sum_{e in supp b_i} sum_{g in e} B'(g, i) Rq[g][q] sum_a B'(g, f_e + a) Z[f_e + a][q]
+// with i = t0 + t + 1 the full index of unknown row t0 + t, Bv the test
+// values (b_i, or b_i + tau b_i' with SUPG) and B' the time derivatives.
+// Either term is skipped when its coefficient is null.  Z holds the spatially
+// expanded input layers of full indices [lo_full, lo_full + nl) (layers
+// outside read as zero: the initial layer of an unknown vector).  One thread
+// per (row, spatial point): consecutive threads take consecutive q, so every
+// Z, Cq, Rq and out access of a wave is one contiguous segment.
 template <class S, class C, int KP>
 __global__ void __launch_bounds__(TPB) k_react_point(const S* __restrict__ Z, int nl, int lo_full,
-                                                     const C* __restrict__ Bt, const int* __restrict__ tfirst,
+                                                     const C* __restrict__ Bt, const C* __restrict__ Bv,
+                                                     const C* __restrict__ Bd, const int* __restrict__ tfirst,
                                                      const int* __restrict__ re0, const int* __restrict__ re1,
-                                                     const C* __restrict__ Cq, int64_t Qs, int t0, int rows,
-                                                     S* __restrict__ out, C beta) {
+                                                     const C* __restrict__ Cq, const C* __restrict__ Rq, int64_t Qs,
+                                                     int t0, int rows, S* __restrict__ out, C beta) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= static_cast<int64_t>(rows) * Qs) return;
   const int t = static_cast<int>(idx / Qs);
@@ -647,10 +653,18 @@ __global__ void __launch_bounds__(TPB) k_react_point(const S* __restrict__ Z, in
 #pragma unroll
     for (int g = 0; g < KP; ++g) {
       const int qg = e * KP + g;
-      C z = C(0);
+      if (Cq) {
+        C z = C(0);
 #pragma unroll
-      for (int a = 0; a < KP; ++a) z += Bt[qg * KP + a] * zl[a];
-      acc += Bt[qg * KP + ai] * Cq[static_cast<int64_t>(qg) * Qs + q] * z;
+        for (int a = 0; a < KP; ++a) z += Bt[qg * KP + a] * zl[a];
+        acc += Bv[qg * KP + ai] * Cq[static_cast<int64_t>(qg) * Qs + q] * z;
+      }
+      if (Rq) {
+        C z = C(0);
+#pragma unroll
+        for (int a = 0; a < KP; ++a) z += Bd[qg * KP + a] * zl[a];
+        acc += Bd[qg * KP + ai] * Rq[static_cast<int64_t>(qg) * Qs + q] * z;
+      }
     }
   }
   const int64_t o = static_cast<int64_t>(t) * Qs + q;
@@ -1985,6 +1999,16 @@ __global__ void k_scale_by_dev(T* __restrict__ x, int64_t n, const double* __res
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) x[i] = static_cast<T>(static_cast<double>(x[i]) * (1.0 / sqrt(nrm2[0])));
 }
+// Shock-capturing coefficient from omega |R| at the Gauss points of one
+// linearization: R[g][q] *= fac[g] / den with den = Cm (max|u| / T + max|u_t|)
+// from the device maxima (maxes[0], maxes[1]); zero when den is 0.
+__global__ void k_sc_scale(double* __restrict__ R, const double* __restrict__ fac, const double* __restrict__ maxes,
+                           double Cm, double invT, int64_t Qs, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double den = Cm * (maxes[0] * invT + maxes[1]);
+  R[i] = den > 0.0 ? R[i] * fac[i / Qs] / den : 0.0;
+}
 // y = a * x (FP64 in, basis type out)
 template <class T>
 __global__ void k_scale_to(const double* __restrict__ x, double a, T* __restrict__ y, int64_t n) {
@@ -2046,7 +2070,7 @@ __global__ void __launch_bounds__(TPB) k_pointwise_ionic(
     const double* __restrict__ u, const double* __restrict__ ut, const double* __restrict__ lap,
     const double* __restrict__ w, const double* __restrict__ wt, const double* __restrict__ ws, int64_t Qs,
     int64_t total, double Cm, double a, double c1, double c2, double* __restrict__ g, double* __restrict__ absR,
-    double* __restrict__ part, Source f, int q0, int Q1, int Q2, double* __restrict__ Cq) {
+    double* __restrict__ part, Source f, int q0, int Q1, int Q2, double* __restrict__ Cq, double* __restrict__ Rq) {
   __shared__ double sh[TPB / 64];
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   double mu = 0.0, mt = 0.0;
@@ -2064,6 +2088,7 @@ __global__ void __launch_bounds__(TPB) k_pointwise_ionic(
     g[idx] = wt[qt] * ws[qs] * I;
     if (Cq) Cq[static_cast<int64_t>(q0) * Qs + idx] = wt[qt] * ws[qs] * (c1 * (uu - a) * (uu - 1.0) + c2 * ww);
     absR[idx] = fabs(Cm * tt - lap[idx] + I);
+    if (Rq) Rq[static_cast<int64_t>(q0) * Qs + idx] = wt[qt] * ws[qs] * absR[idx];
     mu = fabs(uu);
     mt = fabs(tt);
   }
@@ -2099,7 +2124,7 @@ __global__ void __launch_bounds__(384) k_quad_fused(
     double sM, double sF, double Cm, double a, double c1, double c2, double* __restrict__ G,
     double* __restrict__ M, int nel_d, double* __restrict__ part, int64_t boff, int n2, int Q1,
     const double* __restrict__ e0x2, const double* __restrict__ e2x2, const int* __restrict__ f2x, Source fsrc, int q0,
-    double* __restrict__ Cq, int64_t Qs) {
+    double* __restrict__ Cq, double* __restrict__ Rq, int64_t Qs) {
   __shared__ double sh[8];
   __shared__ double smax[2][6][64];
   const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
@@ -2221,7 +2246,10 @@ __global__ void __launch_bounds__(384) k_quad_fused(
         const double xd = fsrc.xq[D - 1][qd];
         I -= (D == 3) ? source_value(fsrc, fx0, fx1, xd, ftt) : source_value(fsrc, fx0, xd, 0.0, ftt);
       }
-      emax = fmax(emax, fabs(Cm * tt - lap + I));
+      const double aR = fabs(Cm * tt - lap + I);
+      emax = fmax(emax, aR);
+      if (Rq && cv)
+        Rq[static_cast<int64_t>(q0 + tr) * Qs + static_cast<int64_t>(qd) * Qin + c] = wtr * (wc * wd[qd]) * aR;
       mu = fmax(mu, fabs(u));
       mt = fmax(mt, fabs(tt));
       const double gv = wtr * (wc * wd[qd]) * I;
@@ -2541,24 +2569,31 @@ void mode_max(const int* start, const int* cnt, int n_out, const double* x, doub
 }
 
 template <class S, class C>
-void react_point(const S* Z, int nl, int lo_full, const DTable<C>& Bt, const int* re0, const int* re1, const C* Cq,
-                 int64_t Qs, int t0, int t1, int p, S* out, C beta, hipStream_t s) {
+void react_point(const S* Z, int nl, int lo_full, const DTable<C>& Bt, const C* Bv, const C* Bd, const int* re0,
+                 const int* re1, const C* Cq, const C* Rq, int64_t Qs, int t0, int t1, int p, S* out, C beta,
+                 hipStream_t s) {
   const int rows = t1 - t0;
   const int64_t total = static_cast<int64_t>(rows) * Qs;
-  if (total == 0) return;
-  // algorithmic bytes: the input layers, the coefficient at the slab's time
+  if (total == 0 || (!Cq && !Rq)) return;
+  if (!Bv) Bv = Bt.coef;
+  const int nterm = (Cq ? 1 : 0) + (Rq ? 1 : 0);
+  // algorithmic bytes: the input layers, the coefficients at the slab's time
   // Gauss points and the output rows, each once
   ProfScope ps(K_TIME_MIX, 15 + 16 * prec_code<S>(), s,
-               (static_cast<double>(nl) + rows) * Qs * sizeof(S) + static_cast<double>(rows) * (p + 1) * Qs * sizeof(C),
-               2.0 * (p + 1) * (p + 1) * (p + 2) * static_cast<double>(total));
+               (static_cast<double>(nl) + rows) * Qs * sizeof(S) +
+                   nterm * static_cast<double>(rows) * (p + 1) * Qs * sizeof(C),
+               nterm * 2.0 * (p + 1) * (p + 1) * (p + 2) * static_cast<double>(total));
   const dim3 g(grid_for(total)), b(TPB);
+#define RP(KP_) hipLaunchKernelGGL((k_react_point<S, C, KP_>), g, b, 0, s, Z, nl, lo_full, Bt.coef, Bv, Bd, Bt.c0, \
+                                   re0, re1, Cq, Rq, Qs, t0, rows, out, beta)
   switch (p) {
-    case 1: hipLaunchKernelGGL((k_react_point<S, C, 2>), g, b, 0, s, Z, nl, lo_full, Bt.coef, Bt.c0, re0, re1, Cq, Qs, t0, rows, out, beta); break;
-    case 2: hipLaunchKernelGGL((k_react_point<S, C, 3>), g, b, 0, s, Z, nl, lo_full, Bt.coef, Bt.c0, re0, re1, Cq, Qs, t0, rows, out, beta); break;
-    case 3: hipLaunchKernelGGL((k_react_point<S, C, 4>), g, b, 0, s, Z, nl, lo_full, Bt.coef, Bt.c0, re0, re1, Cq, Qs, t0, rows, out, beta); break;
-    case 4: hipLaunchKernelGGL((k_react_point<S, C, 5>), g, b, 0, s, Z, nl, lo_full, Bt.coef, Bt.c0, re0, re1, Cq, Qs, t0, rows, out, beta); break;
-    default: hipLaunchKernelGGL((k_react_point<S, C, 6>), g, b, 0, s, Z, nl, lo_full, Bt.coef, Bt.c0, re0, re1, Cq, Qs, t0, rows, out, beta); break;
+    case 1: RP(2); break;
+    case 2: RP(3); break;
+    case 3: RP(4); break;
+    case 4: RP(5); break;
+    default: RP(6); break;
   }
+#undef RP
 }
 
 template <class S, class C>
@@ -2888,29 +2923,33 @@ void finalize_max2(const double* part, int64_t nb, double* out, hipStream_t s) {
 }
 template <class T>
 void scale_by_dev(T* x, int64_t n, const double* nrm2, hipStream_t s) {
-  hipLaunchKernelGGL((k_scale_by_dev<T>), dim3(grid_for(n)), dim3(TPB), 0, s, x, n, nrm2);
+  if (n > 0) hipLaunchKernelGGL((k_scale_by_dev<T>), dim3(grid_for(n)), dim3(TPB), 0, s, x, n, nrm2);
+}
+void sc_scale(double* R, const double* fac, const double* maxes, double Cm, double invT, int64_t Qs, int64_t n,
+              hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_sc_scale, dim3(grid_for(n)), dim3(TPB), 0, s, R, fac, maxes, Cm, invT, Qs, n);
 }
 template <class T>
 void scale_to(const double* x, double a, T* y, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL((k_scale_to<T>), dim3(grid_for(n)), dim3(TPB), 0, s, x, a, y, n);
+  if (n > 0) hipLaunchKernelGGL((k_scale_to<T>), dim3(grid_for(n)), dim3(TPB), 0, s, x, a, y, n);
 }
 template <class T>
 void sub_from(const double* b, const T* y, double* r, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL((k_sub_from<T>), dim3(grid_for(n)), dim3(TPB), 0, s, b, y, r, n);
+  if (n > 0) hipLaunchKernelGGL((k_sub_from<T>), dim3(grid_for(n)), dim3(TPB), 0, s, b, y, r, n);
 }
 void axpy(double a, const double* x, double* y, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(TPB), 0, s, a, x, 1.0, y, n);
+  if (n > 0) hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(TPB), 0, s, a, x, 1.0, y, n);
 }
 void axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(TPB), 0, s, a, x, b, y, n);
+  if (n > 0) hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(TPB), 0, s, a, x, b, y, n);
 }
 template <class T>
 void combine(const T* Z, int64_t ldz, int k, const double* c, double* x, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL((k_combine<T>), dim3(grid_for(n)), dim3(TPB), 0, s, Z, ldz, k, c, x, n);
+  if (n > 0) hipLaunchKernelGGL((k_combine<T>), dim3(grid_for(n)), dim3(TPB), 0, s, Z, ldz, k, c, x, n);
 }
 template <class A, class B>
 void convert(const A* x, B* y, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL((k_convert<A, B>), dim3(grid_for(n)), dim3(TPB), 0, s, x, y, n);
+  if (n > 0) hipLaunchKernelGGL((k_convert<A, B>), dim3(grid_for(n)), dim3(TPB), 0, s, x, y, n);
 }
 void fill(double* x, double v, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(TPB), 0, s, x, v, n);
@@ -2918,12 +2957,12 @@ void fill(double* x, double v, int64_t n, hipStream_t s) {
 void pointwise_ionic(const double* u, const double* ut, const double* lap, const double* w, const double* wt_time,
                      const double* wt_space, int64_t Qs, int nq_t, double Cm, double a, double c1, double c2,
                      double* g, double* absR, double* part, int nb, hipStream_t s, const Source& f, int q0, int Q1,
-                     int Q2, double* Cq) {
+                     int Q2, double* Cq, double* Rq) {
   const int64_t total = Qs * nq_t;
   (void)nb;
   ProfScope ps(K_POINTWISE, 8, s, 6.0 * total * sizeof(double));
   hipLaunchKernelGGL(k_pointwise_ionic, dim3(grid_for(total)), dim3(TPB), 0, s, u, ut, lap, w, wt_time, wt_space, Qs,
-                     total, Cm, a, c1, c2, g, absR, part, f, q0, Q1, Q2, Cq);
+                     total, Cm, a, c1, c2, g, absR, part, f, q0, Q1, Q2, Cq, Rq);
 }
 int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, const double* A2, const double* UT,
                    const double* WW, int nd, int64_t Qin, int ne, const double* B0, const double* B2,
@@ -2931,7 +2970,8 @@ int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, c
                    const double* wd, double sL,
                    double sM, double sF, double Cm, double a, double c1, double c2, double* G, double* M, int nel_d,
                    double* part, int64_t boff, hipStream_t s, int n2, int Q1, const double* e0x2,
-                   const double* e2x2, const int* f2x, const Source& f, int q0, double* Cq, int64_t Qs) {
+                   const double* e2x2, const int* f2x, const Source& f, int q0, double* Cq, double* Rq,
+                   int64_t Qs) {
   if (d < 2 || d > 3 || ps < 1 || ps > 4 || nqt < 1 || nqt > 6) return -1;
   const bool x2 = e0x2 != nullptr;
   if (x2 && (d != 3 || !e2x2 || !f2x || Q1 <= 0 || n2 <= 0 || Qin % Q1 != 0)) return -1;
@@ -2951,11 +2991,11 @@ int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, c
     if (x2)                                                                                                       \
       hipLaunchKernelGGL((k_quad_fused<D_, K_, true>), g, blk, 0, s, A0, A1, A2, UT, WW, nd, Qin, B0, B2, efirst, \
                          chunks, wt, win, wd, sL, sM, sF, Cm, a, c1, c2, G, M, nel_d, part, boff, n2, Q1, e0x2,   \
-                         e2x2, f2x, f, q0, Cq, Qs);                                                              \
+                         e2x2, f2x, f, q0, Cq, Rq, Qs);                                                          \
     else                                                                                                          \
       hipLaunchKernelGGL((k_quad_fused<D_, K_, false>), g, blk, 0, s, A0, A1, A2, UT, WW, nd, Qin, B0, B2,       \
                          efirst, chunks, wt, win, wd, sL, sM, sF, Cm, a, c1, c2, G, M, nel_d, part, boff, 0, 1,   \
-                         nullptr, nullptr, nullptr, f, q0, Cq, Qs);                                              \
+                         nullptr, nullptr, nullptr, f, q0, Cq, Rq, Qs);                                          \
   } while (0)
 #define QFK(D_)                         \
   switch (ps) {                         \
@@ -2974,11 +3014,11 @@ int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, c
   return static_cast<int64_t>(g.x) * g.y * g.z;
 }
 void theta_finish(double* th, int64_t n, const double* maxes, double Cm, double invT, hipStream_t s) {
-  hipLaunchKernelGGL(k_theta_finish, dim3(grid_for(n)), dim3(TPB), 0, s, th, n, maxes, Cm, invT);
+  if (n > 0) hipLaunchKernelGGL(k_theta_finish, dim3(grid_for(n)), dim3(TPB), 0, s, th, n, maxes, Cm, invT);
 }
 void react_grid(const double* u, const double* w, double* c, int64_t n, double a, double c1, double c2, int newton,
                 hipStream_t s) {
-  hipLaunchKernelGGL(k_react_grid, dim3(grid_for(n)), dim3(TPB), 0, s, u, w, c, n, a, c1, c2, newton);
+  if (n > 0) hipLaunchKernelGGL(k_react_grid, dim3(grid_for(n)), dim3(TPB), 0, s, u, w, c, n, a, c1, c2, newton);
 }
 void gram_partial(const double* C, int m, int64_t n, double* part, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_gram, dim3(nb), dim3(TPB), static_cast<size_t>(m) * GRAM_CH * sizeof(double), s, C, m, n, part);
@@ -3017,10 +3057,12 @@ template bool coef_fused<double, double>(const double*, const double*, int, int,
 template bool coef_fused<float, float>(const float*, const float*, int, int, int, int, int, int, int, const float*, int,
                                        int, const float*, const int*, const int*, int, int, int64_t, float*, int64_t,
                                        hipStream_t);
-template void react_point<double, double>(const double*, int, int, const DTable<double>&, const int*, const int*,
-                                          const double*, int64_t, int, int, int, double*, double, hipStream_t);
-template void react_point<float, float>(const float*, int, int, const DTable<float>&, const int*, const int*,
-                                        const float*, int64_t, int, int, int, float*, float, hipStream_t);
+template void react_point<double, double>(const double*, int, int, const DTable<double>&, const double*,
+                                          const double*, const int*, const int*, const double*, const double*, int64_t,
+                                          int, int, int, double*, double, hipStream_t);
+template void react_point<float, float>(const float*, int, int, const DTable<float>&, const float*, const float*,
+                                        const int*, const int*, const float*, const float*, int64_t, int, int, int,
+                                        float*, float, hipStream_t);
 template void time_mix<double, double>(const double*, const double*, int, int, int, int, int, int, const double*,
                                        int, int, double*, int64_t, hipStream_t);
 template void time_mix<float, float>(const float*, const float*, int, int, int, int, int, int, const float*, int, int,

@@ -86,13 +86,18 @@ void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1, 
 // Reaction term with a coefficient given at every space-time Gauss point
 // (Cq [Q_t][Qs], Gauss weights included), over output rows [t0, t1) of the
 // unknowns: out[t - t0][q] = beta out + sum over the time Gauss points g in
-// supp b_{t+1} of B(g, t+1) Cq[g][q] (sum_a B(g, a) Z[a][q]).  Z holds the
-// spatially expanded input layers of full indices [lo_full, lo_full + nl).
-// Bt: time basis values at the Gauss points (contiguous windows, W = p + 1);
-// re0/re1: per full time row, the range of time elements in its support.
+// supp b_{t+1} of Bv(g, t+1) Cq[g][q] (sum_a B(g, a) Z[a][q])
+//            + B'(g, t+1) Rq[g][q] (sum_a B'(g, a) Z[a][q]).
+// Z holds the spatially expanded input layers of full indices [lo_full,
+// lo_full + nl).  Bt: time basis values at the Gauss points (contiguous
+// windows, W = p + 1); Bv: test values in the same layout (null: Bt); Bd:
+// time derivatives in the same layout (read only with Rq); Cq or Rq null:
+// that term is skipped; re0/re1: per full time row, the range of time
+// elements in its support.
 template <class S, class C>
-void react_point(const S* Z, int nl, int lo_full, const DTable<C>& Bt, const int* re0, const int* re1, const C* Cq,
-                 int64_t Qs, int t0, int t1, int p, S* out, C beta, hipStream_t s);
+void react_point(const S* Z, int nl, int lo_full, const DTable<C>& Bt, const C* Bv, const C* Bd, const int* re0,
+                 const int* re1, const C* Cq, const C* Rq, int64_t Qs, int t0, int t1, int p, S* out, C beta,
+                 hipStream_t s);
 
 // Coefficient part along the slowest spatial axis in one kernel (time_mix
 // between the expansion to that axis' Gauss points and the projection back):
@@ -120,7 +125,9 @@ bool coef_fused(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1
 // rows; win: products of the faster axes' Gauss weights [Qin]; wd: Gauss
 // weights of the axis [Q].  Outputs (each optional): G [ne*nqt][nd][Qin]
 // (weighted ionic current projected onto the axis' B-splines), M
-// [ne][nel_d][Qin] (element maxima of |R| over the axis and time), and block
+// [ne][nel_d][Qin] (element maxima of |R| over the axis and time), Cq and
+// Rq (omega C_r and omega |R| at every space-time Gauss point, layout
+// [q0 + row][Qs]), and block
 // maxima of |u|, |u_t| at part[2(boff + b)], part[2(boff + b) + 1].  Returns
 // the number of blocks written (or -1 if the degrees are not supported:
 // d in {2, 3}, ps <= 4, nqt <= 6).  With e0x2 given (d = 3), A0 = B0 u and
@@ -134,7 +141,7 @@ int64_t quad_fused(int d, int ps, int nqt, const double* A0, const double* A1, c
                    const double* wd, double sL,
                    double sM, double sF, double Cm, double a, double c1, double c2, double* G, double* M, int nel_d,
                    double* part, int64_t boff, hipStream_t s, int n2, int Q1, const double* e0x2,
-                   const double* e2x2, const int* f2x, const Source& f, int q0, double* Cq,
+                   const double* e2x2, const int* f2x, const Source& f, int q0, double* Cq, double* Rq,
                    int64_t Qs);
 
 // Dense mode product on MFMA: y[o][i][k] = sum_j A[i][j] x[o][j][k], A given
@@ -217,7 +224,11 @@ void pointwise_ionic(const double* u, const double* ut, const double* lap, const
                      const double* wt_time, const double* wt_space, int64_t Qs, int nq_t, double Cm,
                      double a, double c1, double c2, double* g, double* absR, double* part, int nb,
                      hipStream_t s,
-                     const Source& f, int q0, int Q1, int Q2, double* Cq);
+                     const Source& f, int q0, int Q1, int Q2, double* Cq, double* Rq);
+// R[g][q] *= fac[g] / (Cm (maxes[0] invT + maxes[1])), 0 where that is 0
+// (n = Q_t Qs values, Gauss-point layout [g][q]).
+void sc_scale(double* R, const double* fac, const double* maxes, double Cm, double invT, int64_t Qs, int64_t n,
+              hipStream_t s);
 // theta = min(num/den, 1) with den from device maxima (den = Cm (umax/T + utmax)); den == 0 -> num > 0
 void theta_finish(double* th, int64_t n, const double* maxes, double Cm, double invT, hipStream_t s);
 // coefficient grid: newton ? dI/du : C_r at (u, w)

@@ -133,6 +133,21 @@ struct st_iga_ctx {
   double* cq_out = nullptr;         // set while a quadrature pass must fill Cq_d
   int *re0 = nullptr, *re1 = nullptr;
   std::vector<int> re0_h, re1_h;
+  // SUPG + shock capturing (su = 2): test functions v + tau v_t, tau =
+  // h/(2 p_t + 1) per time element.  Ls[l]: 1D matrices int B_j'' B_i of the
+  // strong-form diffusion; Wtau_x: time table sum_e tau_e int b_j b_i'; BtTs
+  // and Bts: projection onto / values of b_i + tau b_i' at the time Gauss
+  // points; scfac: sc_c h^2/4 per time Gauss point; Rq: the shock-capturing
+  // coefficient at every Gauss point (Gauss weights included)
+  bool supg = false, sc_on = false;
+  bool dualL[3] = {false, false, false};
+  Tab Ls[3], Wtau_x, BtTs;
+  std::vector<double> Bts_h, scfac_h;
+  double *Bts_d = nullptr, *scfac_d = nullptr;
+  float* Bts_f = nullptr;
+  double* Rq_d = nullptr;
+  float* Rq_f = nullptr;
+  double* rq_out = nullptr;         // set while a quadrature pass must fill Rq_d
   // low-rank factors
   int maxR = 0, Rth = 0, Rc = 0;
   double lr_relerr = 0.0;              // achieved relative Frobenius error of the last truncated SVD
@@ -211,7 +226,11 @@ void validate(const st_iga_problem* P, const st_iga_options* O) {
   if (!(O->alpha > 0) || O->alpha > 1) throw Fail{ST_IGA_EINVAL, "alpha must be in (0, 1]"};
   if (O->max_rank < 1 || O->max_rank > 128) throw Fail{ST_IGA_EINVAL, "max_rank must be in 1..128"};
   if (O->prec < ST_IGA_FP64 || O->prec > ST_IGA_MIXED_BF16) throw Fail{ST_IGA_EINVAL, "bad precision"};
-  if (O->su) {  // SU needs C^{p_t - 1} in time: interior time multiplicity 1
+  if (O->su < 0 || O->su > 2) throw Fail{ST_IGA_EINVAL, "su must be 0, 1 or 2"};
+  if (O->su == 2 && O->outer != 2)
+    throw Fail{ST_IGA_EINVAL, "SUPG + shock capturing (su = 2) runs in the fixed-point scheme (outer = 2)"};
+  if (!(O->sc_c >= 0.0) || !std::isfinite(O->sc_c)) throw Fail{ST_IGA_EINVAL, "sc_c must be finite and >= 0"};
+  if (O->su == 1) {  // SU needs C^{p_t - 1} in time: interior time multiplicity 1
     const double* k = P->knots[P->d];
     const int nk = P->nknots[P->d];
     for (int i = P->p_t + 1; i + 1 <= nk - P->p_t - 2; ++i)   // interior knots only
@@ -423,7 +442,36 @@ void host_setup(st_iga_ctx* c) {
   c->Bt1.h = eval_table(T, 1);
   c->BtT.h = eval_table_T(T, 0, nullptr);
   std::vector<double> tau_coefs;
-  if (!tau_at_quad(T, c->tauq, tau_coefs, err)) throw Fail{ST_IGA_EINVAL, err};
+  // the tau_k of the SU term need C^{p_t - 1} time splines: SU only
+  if (c->opt.su == 1) {
+    if (!tau_at_quad(T, c->tauq, tau_coefs, err)) throw Fail{ST_IGA_EINVAL, err};
+  } else {
+    c->tauq.assign(static_cast<size_t>(pt) * T.Q, 0.0);
+  }
+  c->supg = c->opt.su == 2;
+  c->sc_on = c->supg && c->opt.sc_c > 0.0;
+  if (c->supg) {
+    // Section 4.2.2: tau = h/(2p+1) and c h^2/4 with h the time element length
+    std::vector<double> tq(T.Q);
+    c->scfac_h.assign(T.Q, 0.0);
+    c->Bts_h.assign(static_cast<size_t>(T.Q) * (pt + 1), 0.0);
+    for (int q = 0; q < T.Q; ++q) {
+      const int e = q / T.nq;
+      const double h = T.brk[e + 1] - T.brk[e];
+      tq[q] = h / (2.0 * pt + 1.0);
+      c->scfac_h[q] = c->opt.sc_c * h * h / 4.0;
+      for (int a = 0; a <= pt; ++a)
+        c->Bts_h[static_cast<size_t>(q) * (pt + 1) + a] =
+            T.B[0][static_cast<size_t>(q) * (pt + 1) + a] + tq[q] * T.B[1][static_cast<size_t>(q) * (pt + 1) + a];
+    }
+    // C_m (W_t + K_t^tau) on the mass part, W_tau on the strong-form diffusion
+    std::vector<double> Wsum = c->Wt_full;
+    const std::vector<double> Kt = gram1d(T, 1, 1, &tq);
+    for (size_t k = 0; k < Wsum.size(); ++k) Wsum[k] += Kt[k];
+    c->Wt_x.h = banded_table(Wsum, nt, 1, Nt, pt);
+    c->Wtau_x.h = banded_table(gram1d(T, 1, 0, &tq), nt, 1, Nt, pt);
+    c->BtTs.h = streamline_table_T(T, tq);
+  }
   c->Us_h.assign(P.d, {});
   c->lam_h.assign(P.d, {});
   for (int l = 0; l < P.d; ++l) {
@@ -431,6 +479,7 @@ void host_setup(st_iga_ctx* c) {
     std::vector<double> M = gram1d(D, 0, 0, nullptr), K = gram1d(D, 1, 1, nullptr);
     c->Ms[l].h = banded_table(M, D.n, 0, D.n, D.p);
     c->Ks[l].h = banded_table(K, D.n, 0, D.n, D.p);
+    if (c->supg) c->Ls[l].h = banded_table(gram1d(D, 0, 2, nullptr), D.n, 0, D.n, D.p);
     for (int k = 0; k <= 2; ++k) c->Bq[l][k].h = eval_table(D, k);
     c->BqT[l].h = eval_table_T(D, 0, nullptr);
     c->Hs[l].h = hat_table(D.grev_x, D.xq);   // interpolation at the mapped Greville abscissae
@@ -543,6 +592,14 @@ void host_setup(st_iga_ctx* c) {
   };
   for (int l = 0; l < P.d; ++l) c->dual[l] = same_windows(c->Ms[l].h, c->Ks[l].h);
   c->dual[P.d] = same_windows(c->Mt_x.h, c->Wt_x.h);
+  if (c->supg) {
+    for (int l = 0; l < P.d; ++l) {
+      make_contiguous(c->Ls[l].h, c->dir[l].n);
+      c->dualL[l] = same_windows(c->Ms[l].h, c->Ls[l].h);
+    }
+    make_contiguous(c->Wtau_x.h, c->nt);
+    make_contiguous(c->BtTs.h, T.Q);
+  }
   make_contiguous(c->Bt0.h, c->nt);
   make_contiguous(c->Bt1.h, c->nt);
   make_contiguous(c->BtT.h, T.Q);
@@ -631,6 +688,18 @@ void plan(st_iga_ctx* c) {
     if (mixed) c->Cq_f = a.get<float>(nq);
     c->re0 = a.get<int>(c->nt);
     c->re1 = a.get<int>(c->nt);
+    if (c->sc_on) {
+      c->Rq_d = a.get<double>(nq);
+      if (mixed) c->Rq_f = a.get<float>(nq);
+    }
+  }
+  if (c->supg) {
+    for (int l = 0; l < d; ++l) T(c->Ls[l]);
+    T(c->Wtau_x);
+    T(c->BtTs);
+    c->Bts_d = a.get<double>(static_cast<int64_t>(c->Bts_h.size()));
+    if (mixed) c->Bts_f = a.get<float>(static_cast<int64_t>(c->Bts_h.size()));
+    c->scfac_d = a.get<double>(static_cast<int64_t>(c->scfac_h.size()));
   }
   c->wq_s = a.get<double>(c->Qs);
   c->wq_t = a.get<double>(c->dir[d].Q);
@@ -796,6 +865,17 @@ void upload_all(st_iga_ctx* c, hipStream_t s) {
     up(c->re0_h, static_cast<const int*>(c->re0), s);
     up(c->re1_h, static_cast<const int*>(c->re1), s);
   }
+  if (c->supg) {
+    for (int l = 0; l < d; ++l) upload_tab(c->Ls[l], s, keepf);
+    upload_tab(c->Wtau_x, s, keepf);
+    upload_tab(c->BtTs, s, keepf);
+    up(c->Bts_h, static_cast<const double*>(c->Bts_d), s);
+    if (c->Bts_f) {
+      keepf.emplace_back(c->Bts_h.begin(), c->Bts_h.end());
+      up(keepf.back(), static_cast<const float*>(c->Bts_f), s);
+    }
+    up(c->scfac_h, static_cast<const double*>(c->scfac_d), s);
+  }
   CK(hipStreamSynchronize(s));
 }
 
@@ -904,10 +984,43 @@ void apply_impl(st_iga_ctx* c, const S* x, S* y, int L, int in_base, bool with_s
     gather<S, S, C>(Ops<S, C>::tab(c->Wt_x), SM, y, 1, Ns, L, in_base, C(P.Cm), C(0), s);
     gather<S, S, C>(Ops<S, C>::tab(c->Mt_x), SK, y, 1, Ns, L, in_base, C(1), C(1), s);
   }
+  if (c->supg) {
+    // strong-form diffusion of the SUPG term (Section 4.2.2):
+    // y -= W_tau (x) sum_l sigma_l (M_d .. L_l .. M_1) x, L_l = int B_j'' B_i
+    auto axisL = [&](int l, const S* xa, const S* xb, S* oa, S* ob, int64_t outer, int64_t inner, C sb) {
+      if (c->dualL[l] && gather_dual<S, C>(Ops<S, C>::tab(c->Ms[l]), Ops<S, C>::tab(c->Ls[l]), xa, xb, oa, ob, outer,
+                                           inner, nn[l], 0, C(P.sigma[l]), sb, s))
+        return;
+      if (oa) gather<S, S, C>(Ops<S, C>::tab(c->Ms[l]), xa, oa, outer, inner, nn[l], 0, C(1), C(0), s);
+      gather<S, S, C>(Ops<S, C>::tab(c->Ls[l]), xa, ob, outer, inner, nn[l], 0, C(P.sigma[l]), C(0), s);
+      gather<S, S, C>(Ops<S, C>::tab(c->Ms[l]), xb, ob, outer, inner, nn[l], 0, sb, C(1), s);
+    };
+    S* SG;
+    kprof_gather_class(K_BANDED);
+    if (d == 1) {
+      gather<S, S, C>(Ops<S, C>::tab(c->Ls[0]), x, a, L, 1, nn[0], 0, C(P.sigma[0]), C(0), s);
+      SG = a;
+    } else if (d == 2) {
+      gather<S, S, C>(Ops<S, C>::tab(c->Ms[0]), x, a, L * nn[1], 1, nn[0], 0, C(1), C(0), s);
+      gather<S, S, C>(Ops<S, C>::tab(c->Ls[0]), x, b, L * nn[1], 1, nn[0], 0, C(1), C(0), s);
+      axisL(1, a, b, nullptr, e, L, nn[0], C(P.sigma[0]));   // sigma2 L2 M1 x + sigma1 M2 L1 x
+      SG = e;
+    } else {
+      gather<S, S, C>(Ops<S, C>::tab(c->Ms[0]), x, a, L * nn[1] * nn[2], 1, nn[0], 0, C(1), C(0), s);
+      gather<S, S, C>(Ops<S, C>::tab(c->Ls[0]), x, b, L * nn[1] * nn[2], 1, nn[0], 0, C(1), C(0), s);
+      axisL(1, a, b, e, f, L * nn[2], nn[0], C(P.sigma[0]));
+      axisL(2, e, f, nullptr, a, L, static_cast<int64_t>(nn[0]) * nn[1], C(1));
+      SG = a;
+    }
+    gather<S, S, C>(Ops<S, C>::tab(c->Wtau_x), SG, y, 1, Ns, L, in_base, C(-1), C(1), s);
+  }
   // low-rank coefficient terms
   const int r0 = with_su ? 0 : c->Rth;
   const int r1 = with_react ? c->Rth + c->Rc : c->Rth;
-  const bool pointwise = with_react && c->exact_react;   // M_R with C_r at every Gauss point
+  // M_R with C_r at every Gauss point, and the shock-capturing term
+  const bool pw_react = with_react && c->exact_react;
+  const bool pw_sc = with_su && c->sc_on;
+  const bool pointwise = pw_react || pw_sc;
   kprof_gather_class(K_EXPAND);
   struct Reset { ~Reset() { kprof_gather_class(K_GATHER); } } reset_cls;
   if (r1 <= r0 && !pointwise) return;
@@ -969,10 +1082,15 @@ void apply_impl(st_iga_ctx* c, const S* x, S* y, int L, int in_base, bool with_s
     else spatial_chain<S, C>(c, ex, xs, nl, nn, qd, bufA, bufB, Z, C(1), C(0), s);
     if (r1 > r0) time_mix<S, C>(Tr, B.Psi, r0, r1, c->NtP, t0, t1, p, Z, nl, in_base + lo, W2, c->Qs, s);
     if (pointwise) {
-      const C* Cq = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->Cq_d)
-                                                   : reinterpret_cast<const C*>(c->Cq_f);
-      react_point<S, C>(Z, nl, in_base + lo, Ops<S, C>::tab(c->Bt0), c->re0, c->re1, Cq, c->Qs, t0, t1, p, W2,
-                        r1 > r0 ? C(1) : C(0), s);
+      const bool dbl = std::is_same<C, double>::value;
+      const C* Cq = !pw_react ? nullptr
+                              : dbl ? reinterpret_cast<const C*>(c->Cq_d) : reinterpret_cast<const C*>(c->Cq_f);
+      const C* Rq = !pw_sc ? nullptr
+                           : dbl ? reinterpret_cast<const C*>(c->Rq_d) : reinterpret_cast<const C*>(c->Rq_f);
+      const C* Bv = !c->supg ? nullptr
+                             : dbl ? reinterpret_cast<const C*>(c->Bts_d) : reinterpret_cast<const C*>(c->Bts_f);
+      react_point<S, C>(Z, nl, in_base + lo, Ops<S, C>::tab(c->Bt0), Bv, Ops<S, C>::tab(c->Bt1).coef, c->re0, c->re1,
+                        Cq, Rq, c->Qs, t0, t1, p, W2, r1 > r0 ? C(1) : C(0), s);
     }
     S* ys = y + static_cast<int64_t>(t0) * Ns;
     if (d == 1) gather<S, S, C>(Ops<S, C>::tab(*pr[0]), W2, ys, t1 - t0, 1, qd[0], 0, C(1), C(1), s);
@@ -1663,11 +1781,11 @@ void quad_pass_fused(st_iga_ctx* c, const double* u, const double* w, bool want_
         x2 ? quad_fused(d, P.p_s, nq, Xa, nullptr, Xb, Xt, Xw, nd, Qin, ne, c->cf_Bl_d, c->cf_B2_d, c->cf_first,
                         c->cf_chunks, c->cf_nchunk, c->wq_t + q0, c->qf_win, c->qf_wd, sL, sM, sF, P.Cm, P.a, P.c1,
                         P.c2, want_res ? Gp : nullptr, want_theta ? Mp : nullptr, neld, c->part, boff, s, n2, Q1,
-                        F0d.coef, F2d.coef, F0d.c0, c->src, q0, c->cq_out, c->Qs)
+                        F0d.coef, F2d.coef, F0d.c0, c->src, q0, c->cq_out, c->rq_out, c->Qs)
            : quad_fused(d, P.p_s, nq, in[0], in[1], in[2], in[3], in[4], nd, Qin, ne, c->cf_Bl_d, c->cf_B2_d,
                         c->cf_first, c->cf_chunks, c->cf_nchunk, c->wq_t + q0, c->qf_win, c->qf_wd, sL, sM, sF, P.Cm,
                         P.a, P.c1, P.c2, want_res ? Gp : nullptr, want_theta ? Mp : nullptr, neld, c->part, boff, s,
-                        0, 1, nullptr, nullptr, nullptr, c->src, q0, c->cq_out, c->Qs);
+                        0, 1, nullptr, nullptr, nullptr, c->src, q0, c->cq_out, c->rq_out, c->Qs);
     if (nb < 0) throw Fail{ST_IGA_EINVAL, "fused quadrature pass: unsupported degrees"};
     boff += nb;
     if (want_theta) {
@@ -1686,7 +1804,7 @@ void quad_pass_fused(st_iga_ctx* c, const double* u, const double* w, bool want_
       } else {
         ax(c->BqT[0], Gp, U0, static_cast<int64_t>(nqc) * n2, 1, Q1);
       }
-      gather<double, double, double>(c->BtT.d, U0, c->rfull, 1, Ns, nqc, q0, 1.0, 1.0, s);
+      gather<double, double, double>((c->supg ? c->BtTs : c->BtT).d, U0, c->rfull, 1, Ns, nqc, q0, 1.0, 1.0, s);
     }
   }
   finish_uv_maxima(c, boff, s);
@@ -1768,7 +1886,7 @@ void quad_pass(st_iga_ctx* c, const double* u, const double* w, bool want_res, b
     }
     const int nbp = static_cast<int>((static_cast<int64_t>(nqc) * Qs + 255) / 256);
     pointwise_ionic(uq, utq, lap, wq, c->wq_t + q0, c->wq_s, Qs, nqc, P.Cm, P.a, P.c1, P.c2, g, absR,
-                    part_u + boff, nbp, s, c->src, q0, c->Q[0], c->Q[1], c->cq_out);
+                    part_u + boff, nbp, s, c->src, q0, c->Q[0], c->Q[1], c->cq_out, c->rq_out);
     // the kernel writes [2b], [2b+1] pairs: keep them interleaved in part_u region
     boff += 2 * nbp;
     if (want_theta) {
@@ -1795,7 +1913,7 @@ void quad_pass(st_iga_ctx* c, const double* u, const double* w, bool want_res, b
     if (want_res) {
       // project g over space into U0 region (reuse), then over time into rfull
       project_space(c, g, nqc, tA, tB, U0, 0.0, s);
-      DTable<double> tt = c->BtT.d;
+      DTable<double> tt = (c->supg ? c->BtTs : c->BtT).d;   // test functions b_i (+ tau b_i' with SUPG)
       gather<double, double, double>(tt, U0, c->rfull, 1, Ns, nqc, q0, 1.0, 1.0, s);
     }
   }
@@ -1990,9 +2108,13 @@ void linearize(st_iga_ctx* c, const double* u, const double* w, bool refresh_the
   c->rfull_u = c->rfull_w = nullptr;
   // exact C_r: the quadrature pass at (u, w) also writes omega C_r at every Gauss point
   c->cq_out = c->exact_react ? c->Cq_d : nullptr;
-  struct ClearCq { st_iga_ctx* c; ~ClearCq() { c->cq_out = nullptr; } } clear_cq{c};
+  c->rq_out = c->sc_on ? c->Rq_d : nullptr;   // omega |R| for the shock-capturing coefficient
+  struct ClearCq {
+    st_iga_ctx* c;
+    ~ClearCq() { c->cq_out = c->rq_out = nullptr; }
+  } clear_cq{c};
   bool cq_done = false;
-  if (c->opt.su && refresh_theta) {
+  if (c->opt.su == 1 && refresh_theta) {
     // one quadrature pass gives the theta maxima and, on request, the ionic
     // part of the residual at the same (u, w)
     theta_grid(c, u, w, c->grid, s, with_residual);
@@ -2004,7 +2126,7 @@ void linearize(st_iga_ctx* c, const double* u, const double* w, bool refresh_the
     c->Rth = lowrank(c, c->grid, c->opt.eps_theta, c->Uth_h, c->sth_h, c->Vth, s);
     c->err_th = c->lr_relerr;
     c->cap_th = c->lr_capped;
-  } else if (!c->opt.su) {
+  } else if (c->opt.su != 1) {
     c->Rth = 0;
     c->err_th = 0.0;
     c->cap_th = false;
@@ -2017,8 +2139,13 @@ void linearize(st_iga_ctx* c, const double* u, const double* w, bool refresh_the
         c->rfull_w = w;
       }
     }
-    if (c->Cq_f)
-      convert<double, float>(c->Cq_d, c->Cq_f, static_cast<int64_t>(c->dir[c->d].Q) * c->Qs, s);
+    const int64_t nq = static_cast<int64_t>(c->dir[c->d].Q) * c->Qs;
+    if (c->Cq_f) convert<double, float>(c->Cq_d, c->Cq_f, nq, s);
+    if (c->sc_on) {
+      // sc_c h^2/4 |R| / (C_m (||u||/T + ||u_t||)) with the maxima of this pass
+      sc_scale(c->Rq_d, c->scfac_d, c->dsc + 300, c->P.Cm, 1.0 / c->P.T, c->Qs, nq, s);
+      if (c->Rq_f) convert<double, float>(c->Rq_d, c->Rq_f, nq, s);
+    }
     c->Rc = 0;
     c->err_c = 0.0;
     c->cap_c = false;
@@ -2143,6 +2270,7 @@ void st_iga_default_options(st_iga_options* o) {
   o->stall_cycles = 10;
   o->stall_reduction = 1e-3;
   o->picard_switch = 0;
+  o->sc_c = 1.0;
   o->prec = ST_IGA_FP64;
   o->lin_forcing = 0.0;
   o->coef_slab = 0;
@@ -2203,7 +2331,7 @@ st_iga_status st_iga_setup(const st_iga_problem* prob, const st_iga_options* opt
 st_iga_status st_iga_linearize(st_iga_ctx* c, const double* u, const double* w, int32_t refresh_theta, void* stream) {
   if (!c || !u || !w) return ST_IGA_EINVAL;
   return guard(c, [&] {
-    if (!c->linearized && c->opt.su && !refresh_theta) throw Fail{ST_IGA_ESTATE, "theta has never been computed"};
+    if (!c->linearized && c->opt.su == 1 && !refresh_theta) throw Fail{ST_IGA_ESTATE, "theta has never been computed"};
     linearize(c, u, w, refresh_theta != 0, static_cast<hipStream_t>(stream));
     c->rfull_u = c->rfull_w = nullptr;
   });
@@ -2394,7 +2522,7 @@ st_iga_status st_iga_solve(st_iga_ctx* c, const st_iga_stimulus* stim, double* u
     for (int k = 0; k < c->opt.max_outer; ++k) {
       auto t0 = std::chrono::steady_clock::now();
       if (!paper_fp) w_update(c, u, w, s);
-      linearize(c, u, w, c->opt.su && !frozen, s, true);
+      linearize(c, u, w, c->opt.su == 1 && !frozen, s, true);
       residual(c, u, w, c->sol_rhs, s);
       axpby(-1.0, c->sol_rhs, 0.0, c->sol_rhs, c->nunk, s);   // rhs = -N(u)
       CK(hipStreamSynchronize(s));
@@ -2459,7 +2587,7 @@ st_iga_status st_iga_newton_step(st_iga_ctx* c, const double* u_in, double* u_ou
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (u_out != u_in) CK(hipMemcpyAsync(u_out, u_in, c->nfull * sizeof(double), hipMemcpyDeviceToDevice, s));
     w_update(c, u_out, w, s);
-    if (!c->linearized && c->opt.su && !refresh_theta) throw Fail{ST_IGA_ESTATE, "theta has never been computed"};
+    if (!c->linearized && c->opt.su == 1 && !refresh_theta) throw Fail{ST_IGA_ESTATE, "theta has never been computed"};
     linearize(c, u_out, w, refresh_theta != 0, s, true);
     residual(c, u_out, w, c->sol_rhs, s);
     axpby(-1.0, c->sol_rhs, 0.0, c->sol_rhs, c->nunk, s);

@@ -495,6 +495,21 @@ def test_galerkin_solve(gpu_lib, outer):
     assert rel(w.cpu().numpy(), wo) < 1e-10
 
 
+def test_galerkin_mixed_no_low_rank(gpu_lib, torch):
+    """A mixed-precision context with no low-rank terms at all (Galerkin, exact
+    C_r): the empty factor tables are skipped, the FP32 operator matches."""
+    from paper_2311_17500_amd.binding import MIXED_FP32
+    prob = SMALL[1][1]
+    st = SpaceTime(prob, su=False)
+    u, w = W.smooth_state(prob, 8)
+    S = solver_for(prob, su=0, outer=2, alpha=0.5, prec=MIXED_FP32)
+    S.linearize(to_dev(torch, u), to_dev(torch, w))
+    x = W.random_vector(prob.unknowns, 23)
+    want = st.apply_J(x, st.reaction_at_quad(u, w), None)
+    assert rel(S.apply(to_dev(torch, x)).cpu().numpy(), want) < 1e-11
+    assert rel(S.apply_lowp(to_dev(torch, x)).cpu().numpy(), want) < 1e-5
+
+
 # Failure handling, forced from the host (every kernel still exits normally).
 @pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
 def test_krylov_stagnation_enoconv(gpu_lib, torch, prec):

@@ -1,0 +1,140 @@
+"""GPU parity of the SUPG + shock-capturing stabilization (Section 4.2.2, the
+paper's comparison method for C^0 splines in time) against the oracle,
+through the C ABI: the linearized operator, the residual and whole
+fixed-point solves.  FP64 tolerances as in the other parity tests."""
+import numpy as np
+import pytest
+
+import st_workloads as W
+from oracle import solver
+from oracle.spacetime import SpaceTime
+
+pytestmark = pytest.mark.gpu
+
+SC_C = 0.7
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def to_dev(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+def _case(d, p, nel, nel_t, c0=True, source=False):
+    kw = {}
+    if source:
+        kw = dict(u0_kind=0, f_kind=2, f_t0=0.2, f_t1=0.5, f_amp=2.0, f_center=(0.1, 0.5, 0.5), f_kappa=20.0,
+                  f_velocity=(0.8, 0.0, 0.2))
+    prob = W.tiny(d, p, nel, nel_t=nel_t, **kw)
+    kn = prob.uniform_knots()
+    if c0:
+        kn[d] = W.c0_time_knots(nel_t, p)
+    return prob, kn
+
+
+CASES = [("1d_p3_c0", 1, 3, 8, 4, True, False),
+         ("2d_p2_c0", 2, 2, 5, 4, True, False),
+         ("2d_p3_c0_src", 2, 3, 4, 3, True, True),
+         ("2d_p2_smooth", 2, 2, 5, 6, False, False),
+         ("3d_p2_c0", 3, 2, 3, 3, True, False),
+         ("3d_p3_c0_src", 3, 3, 2, 2, True, True)]
+
+
+def _state(st, seed):
+    """A seeded (u, w) pair on the full basis of st (any time knots)."""
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(st.shape))
+    return rng.uniform(-0.2, 1.1, n), rng.uniform(0.0, 0.3, n)
+
+
+def _unknowns(st):
+    return int(np.prod(st.shape)) - int(np.prod(st.n[:st.d]))
+
+
+def _solver(prob, kn, **kw):
+    from paper_2311_17500_amd.binding import Solver
+    return Solver(prob, knots=kn, su=2, outer=2, alpha=0.5, sc_c=SC_C, **kw)
+
+
+@pytest.mark.parametrize("name,d,p,nel,nel_t,c0,src", CASES, ids=[c[0] for c in CASES])
+def test_supg_operator_and_residual(gpu_lib, torch, name, d, p, nel, nel_t, c0, src):
+    """J x with the SUPG test functions, the strong-form diffusion, the exact
+    C_r and the shock-capturing coefficient at a non-trivial state; the
+    residual A(u, w) u - F; the FP32 operator of a mixed context."""
+    from paper_2311_17500_amd.binding import MIXED_FP32
+    prob, kn = _case(d, p, nel, nel_t, c0, src)
+    st = SpaceTime(prob, knots=kn, su=False, supg=True, sc_c=SC_C)
+    u, w = _state(st, 31)
+    sc = st.sc_coefficient(u, w)
+    assert np.max(sc) > 0.0
+    A = st.assemble_full(st.reaction_at_quad(u, w), None, sc)
+    N_s = int(np.prod(st.n[:d]))
+    x = W.random_vector(_unknowns(st), 32)
+    want = A[N_s:, N_s:] @ x
+    want_r = st.rows(A @ u - st.load_vector())
+    S = _solver(prob, kn, prec=MIXED_FP32)
+    ud, wd = to_dev(torch, u), to_dev(torch, w)
+    S.linearize(ud, wd)
+    gt, gc = S.get_factors()
+    assert len(gt[1]) == 0 and len(gc[1]) == 0
+    xd = to_dev(torch, x)
+    assert rel(S.apply(xd).cpu().numpy(), want) < 1e-11
+    assert rel(S.apply_lowp(xd).cpu().numpy(), want) < 1e-5
+    assert rel(S.residual(ud, wd).cpu().numpy(), want_r) < 1e-11
+
+
+def test_supg_shock_capturing_off(gpu_lib, torch):
+    """sc_c = 0: the shock-capturing term vanishes, SUPG alone remains."""
+    from paper_2311_17500_amd.binding import Solver
+    prob, kn = _case(2, 2, 5, 4)
+    st = SpaceTime(prob, knots=kn, su=False, supg=True, sc_c=0.0)
+    u, w = _state(st, 33)
+    A = st.assemble_full(st.reaction_at_quad(u, w), None, None)
+    N_s = int(np.prod(st.n[:2]))
+    x = W.random_vector(_unknowns(st), 34)
+    S = Solver(prob, knots=kn, su=2, outer=2, alpha=0.5, sc_c=0.0)
+    S.linearize(to_dev(torch, u), to_dev(torch, w))
+    assert rel(S.apply(to_dev(torch, x)).cpu().numpy(), A[N_s:, N_s:] @ x) < 1e-11
+
+
+SOLVES = [("1d_p3_c0", 1, 3, 8, 4, True, False), ("2d_p2_c0_src", 2, 2, 4, 6, True, True)]
+
+
+@pytest.mark.parametrize("name,d,p,nel,nel_t,c0,src", SOLVES, ids=[c[0] for c in SOLVES])
+def test_supg_fixed_point_solve(gpu_lib, name, d, p, nel, nel_t, c0, src):
+    """The Section 3.1 iteration with SUPG + SC (coefficients refreshed every
+    iteration), run to 1e-11: same iteration count and (u, w) as the oracle's
+    literal scheme; the paper's stop at 1e-4 gives the same count too."""
+    prob, kn = _case(d, p, nel, nel_t, c0, src)
+    st = SpaceTime(prob, knots=kn, su=False, supg=True, sc_c=SC_C)
+    S = _solver(prob, kn, tol_nonlin=1e-11, tol_lin=1e-12, max_outer=400)
+    u, w, rep = S.solve()
+    uo, wo, log = solver.solve_picard(st, tol=1e-11, max_outer=400)
+    if src:
+        assert np.max(np.abs(uo)) > 0.1
+    assert rep.outer_iters == len(log.deltas)
+    assert rel(u.cpu().numpy(), uo) < 1e-10
+    assert rel(w.cpu().numpy(), wo) < 1e-10
+    S4 = _solver(prob, kn, tol_nonlin=1e-4, tol_lin=1e-12, max_outer=400)
+    u4, w4, rep4 = S4.solve()
+    uo4, wo4, log4 = solver.solve_picard(st, tol=1e-4, max_outer=400)
+    assert rep4.outer_iters == len(log4.deltas)
+    assert rel(u4.cpu().numpy(), uo4) < 1e-10
+
+
+def test_supg_mixed_solve_matches_fp64(gpu_lib):
+    """FP32 operator + FP64 refinement reaches the FP64 solution."""
+    from paper_2311_17500_amd.binding import MIXED_FP32
+    prob, kn = _case(2, 3, 5, 4, True, True)
+    u64, w64, r64 = _solver(prob, kn, tol_nonlin=1e-11, tol_lin=1e-12, max_outer=400).solve()
+    u32, w32, r32 = _solver(prob, kn, tol_nonlin=1e-11, tol_lin=1e-12, max_outer=400, prec=MIXED_FP32).solve()
+    assert rel(u32.cpu().numpy(), u64.cpu().numpy()) < 1e-8

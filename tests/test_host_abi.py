@@ -219,6 +219,23 @@ def test_invalid_options_rejected(lib):
         assert binding.workspace_bytes(prob, **kw) == 0, kw
     for r in (0, 1, 2):
         assert binding.workspace_bytes(prob, reorth=r) > 0
+    # stabilization modes: SUPG + shock capturing runs in the fixed-point scheme
+    for kw in ({"su": 3}, {"su": -1}, {"su": 2, "outer": 0}, {"su": 2, "outer": 1},
+               {"su": 2, "outer": 2, "sc_c": -1.0}, {"su": 2, "outer": 2, "sc_c": float("nan")}):
+        assert binding.workspace_bytes(prob, **kw) == 0, kw
+    assert binding.workspace_bytes(prob, su=2, outer=2, sc_c=0.0) > 0
+
+
+def test_time_regularity_per_stabilization(lib):
+    """C^0 time splines: SU (which needs C^{p_t - 1}) is rejected, Galerkin and
+    SUPG + shock capturing are accepted; SUPG sizes its extra tables."""
+    prob = W.tiny(2, 3, 4, nel_t=5)
+    kn = prob.uniform_knots()
+    kn[2] = W.c0_time_knots(5, 3)
+    assert binding.workspace_bytes(prob, kn, su=1) == 0
+    assert binding.workspace_bytes(prob, kn, su=0) > 0
+    sup = binding.workspace_bytes(prob, kn, su=2, outer=2)
+    assert sup > binding.workspace_bytes(prob, kn, su=0, outer=2)
 
 
 @pytest.mark.parametrize("kind", ["indefinite", "clustered", "tridiag_tiny", "diagonal", "graded"])
