@@ -331,8 +331,11 @@ def compare_su(torch, W):
     """Galerkin vs SU with the paper's fixed-point scheme (Section 3.1 with
     the stopping rule of Section 4) on config 1 and on a source-driven
     variant of it (zero datum, a disc stimulus during [0.1, 0.2], time knots
-    clustered at the source's on/off times): fixed-point iterations, Krylov
-    iterations per fixed-point iteration, wall time."""
+    clustered at the source's on/off times), on the paper's 2D setting, and
+    SUPG with and without shock capturing (c = 0.1, h in physical time) on
+    C^0 time splines in that setting:
+    fixed-point iterations, Krylov iterations per fixed-point iteration,
+    extremes of u, wall time."""
     from paper_2311_17500_amd.binding import Solver, FP64, StIgaError
     base = W.config(1)
     src = dict(base.__dict__)
@@ -348,20 +351,26 @@ def compare_su(torch, W):
                       f_kind=2, f_center=(0.0, L2 / 2, 0.0), f_velocity=(8.0 / 15.0 * L1 / Tp, 0.0, 0.0),
                       f_kappa=500.0, f_amp=0.25, f_t0=90.0, f_t1=100.0,
                       map_kind=(1, 1, 0), map_param=((0.0, L1, 0.0), (0.0, L2, 0.0), (0.0, 1.0, 0.0)))
-    cases = [("config1", base, None),
+    # the paper's C^0 comparison (Section 4.2.2): the same 2D setting with C^0
+    # cubic splines in time on 12 elements (N_t = 36), SUPG + shock capturing
+    paper_c0 = W.Problem(**{**paper.__dict__, "nel_t": 12})
+    std = (("su", 1, 0.0), ("galerkin", 0, 0.0))
+    cases = [("config1", base, None, std),
              ("config1_source_clustered_time", W.Problem(**src),
-              W.clustered_time_knots(base.nel_t, base.p_t, [0.1, 0.2], 0.004)),
-             ("paper2d_uniform_time", paper, None),
-             ("paper2d_clustered_time", paper, W.clustered_time_knots(32, 3, [90.0 / Tp, 100.0 / Tp], 0.003))]
+              W.clustered_time_knots(base.nel_t, base.p_t, [0.1, 0.2], 0.004), std),
+             ("paper2d_uniform_time", paper, None, std),
+             ("paper2d_clustered_time", paper, W.clustered_time_knots(32, 3, [90.0 / Tp, 100.0 / Tp], 0.003), std),
+             ("paper2d_c0_time", paper_c0, W.c0_time_knots(12, 3),
+              (("supg_sc", 2, 0.1), ("supg", 2, 0.0), ("galerkin", 0, 0.0)))]
     out = {}
-    for name, prob, tk in cases:
+    for name, prob, tk, modes in cases:
         knots = None
         if tk is not None:
             knots = prob.uniform_knots()
             knots[prob.d] = tk
-        for su in (1, 0):
+        for mode, su, sc_c in modes:
             S = Solver(prob, knots=knots, prec=FP64, su=su, outer=2, alpha=0.5, tol_nonlin=1e-4, tol_lin=1e-8,
-                       max_outer=300)
+                       max_outer=300, sc_c=sc_c)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             status = "ok"
@@ -377,9 +386,9 @@ def compare_su(torch, W):
                 n = rep.outer_iters
                 rec.update({"fixed_point_iters": n, "krylov_total": rep.krylov_total,
                             "krylov_per_fixed_point": rep.krylov_total / max(n, 1),
-                            "theta_rank_last": rep.rank_theta[min(n, 64) - 1] if su else 0,
+                            "theta_rank_last": rep.rank_theta[min(n, 64) - 1] if su == 1 else 0,
                             "u_max": float(u.abs().max()), "u_min": float(u.min())})
-            out[f"{name}_{'su' if su else 'galerkin'}"] = rec
+            out[f"{name}_{mode}"] = rec
             log(f"{name} su={su}: {rec}")
             S.close()
             torch.cuda.empty_cache()

@@ -152,7 +152,8 @@ typedef struct {
                                 consecutive iterations continues as the outer = 1 Picard iteration
                                 (alpha = 0.5); reported in st_iga_report.switched_at; 0: never */
   double sc_c;               /* shock-capturing constant c >= 0 of the su = 2 stabilization (the paper
-                                leaves it as a tuning parameter); 0 turns the term off */
+                                leaves it as a tuning parameter; h is in the time units of T, so the
+                                term scales with the square of the element length); 0 turns it off */
 } st_iga_options;
 
 #define ST_IGA_MAX_OUTER_LOG 64
@@ -176,7 +177,7 @@ typedef struct {
 /* Defaults: su=1, eps_theta=0.1, eps_react=1e-2, max_rank=48, outer=0,
  * alpha=1 (Newton), theta_freeze=1e-4, tol_nonlin=1e-10, tol_lin=1e-10,
  * inner_tol=1e-4, restart=30, max_outer=60, max_krylov=3000, prec=FP64, lin_forcing=0,
- * coef_slab=0, reorth=2, graphs=1, stall_cycles=10, stall_reduction=1e-3, picard_switch=0, sc_c=1. */
+ * coef_slab=0, reorth=2, graphs=1, stall_cycles=10, stall_reduction=1e-3, picard_switch=0, sc_c=0.1. */
 void st_iga_default_options(st_iga_options* opt);
 
 /* Bytes of device workspace st_iga_setup needs for this problem/options

@@ -379,6 +379,42 @@ class SpaceTime:
         N_s = int(np.prod(self.n[:d]))
         return sp.csr_matrix(A)[N_s:, N_s:]
 
+    def precond_means(self, u_full, w_full):
+        """Time profiles of the preconditioner of the SUPG system (not from the
+        paper, which solves directly): at each time Gauss point the spatial
+        mean (Gauss-weighted) of C_r(u, w), clipped at 0, and of the
+        shock-capturing coefficient (zero when sc_c = 0)."""
+        Qt = self.qshape[0]
+        ws = np.array([1.0])
+        for a in range(1, self.d + 1):
+            ws = np.multiply.outer(ws, self.quad[self.dirs[a]][1])
+        ws = ws.reshape(-1)
+        cr = np.maximum(self.reaction_at_quad(u_full, w_full).reshape(Qt, -1) @ ws / ws.sum(), 0.0)
+        if self.sc_c > 0.0:
+            sc = self.sc_coefficient(u_full, w_full).reshape(Qt, -1) @ ws / ws.sum()
+        else:
+            sc = np.zeros(Qt)
+        return cr, sc
+
+    def assemble_precond_supg(self, cr_t, sc_t):
+        """Preconditioner of the SUPG system on X_h x X_h: the bilinear form
+          int C_m u_t (v + tau v_t) + sum_l sigma_l int u_l (v + tau v_t)_l
+          + int cr(t) u (v + tau v_t) + int sc(t) u_t v_t
+        with coefficients depending on time only (so that it is a Kronecker
+        sum A_t (x) M_s + B_t (x) K_s); cr_t, sc_t at the time Gauss points."""
+        P, d, om = self.P, self.d, self.omega
+        Dg = sp.diags
+        Qs = int(np.prod(self.qshape[1:]))
+        tau, cr, sc = (np.repeat(v, Qs) for v in (self.supg_tau_t, cr_t, sc_t))
+        P0, Pt = self.phi({}), self.phi({d: 1})
+        A = P0.T @ Dg(om) @ (P.Cm * Pt) + Pt.T @ Dg(om * tau) @ (P.Cm * Pt)
+        A = A + P0.T @ Dg(om * cr) @ P0 + Pt.T @ Dg(om * tau * cr) @ P0 + Pt.T @ Dg(om * sc) @ Pt
+        for l in range(d):
+            Pl = self.phi({l: 1})
+            A = A + P.sigma[l] * (Pl.T @ Dg(om) @ Pl + self.phi({l: 1, d: 1}).T @ Dg(om * tau) @ Pl)
+        N_s = int(np.prod(self.n[:d]))
+        return sp.csr_matrix(A)[N_s:, N_s:]
+
     # --------------------------------------------------------- w update
     def w_update_explicit(self, u_full):
         """Solve L w = g of Section 3.1.1 as one explicit sparse system.

@@ -671,6 +671,90 @@ __global__ void __launch_bounds__(TPB) k_react_point(const S* __restrict__ Z, in
   out[o] = from_c<S>(beta != C(0) ? beta * to_c(out[o], C(0)) + acc : acc);
 }
 
+// ---------------------------------------------------------------- banded time solves
+// Time direction of the preconditioner of the SUPG system: for every spatial
+// mode j the banded N_t x N_t matrix T_j = A + (lam_j - shift) B (band
+// half-width P, rows and columns of X_t; A and B stored as [t][2P + 1], column
+// t - P + k) is factorized T_j = L_j U_j without pivoting (the symmetric part
+// of T_j is positive definite: the time derivative with its initial condition,
+// the SUPG time stiffness and non-negative reaction and diffusion terms), one
+// thread per mode.  F[(t (2P + 1) + k) Ns + j]: k < P the multipliers
+// l_{t, t-P+k}, k = P the reciprocal pivot, k > P the entries u_{t, t+k-P}.
+template <int P>
+__global__ void __launch_bounds__(TPB) k_band_factor(const double* __restrict__ A, const double* __restrict__ B,
+                                                     int Nt, const double* __restrict__ lam, double shift, int64_t Ns,
+                                                     double* __restrict__ F) {
+  constexpr int KW = 2 * P + 1;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= Ns) return;
+  const double lj = lam[j] - shift;
+  double up[P][P + 1];   // U rows t - P .. t - 1 (diagonal first)
+#pragma unroll
+  for (int r = 0; r < P; ++r)
+#pragma unroll
+    for (int m = 0; m <= P; ++m) up[r][m] = 0.0;
+  for (int t = 0; t < Nt; ++t) {
+    double a[KW];
+#pragma unroll
+    for (int k = 0; k < KW; ++k) a[k] = A[t * KW + k] + lj * B[t * KW + k];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      double l = 0.0;
+      if (t - P + k >= 0) {
+        l = a[k] / up[k][0];
+#pragma unroll
+        for (int m = 1; m <= P; ++m) a[k + m] -= l * up[k][m];
+      }
+      F[(static_cast<int64_t>(t) * KW + k) * Ns + j] = l;
+    }
+    F[(static_cast<int64_t>(t) * KW + P) * Ns + j] = 1.0 / a[P];
+#pragma unroll
+    for (int m = 1; m <= P; ++m) F[(static_cast<int64_t>(t) * KW + P + m) * Ns + j] = a[P + m];
+#pragma unroll
+    for (int r = 0; r < P - 1; ++r)
+#pragma unroll
+      for (int m = 0; m <= P; ++m) up[r][m] = up[r + 1][m];
+#pragma unroll
+    for (int m = 0; m <= P; ++m) up[P - 1][m] = a[P + m];
+  }
+}
+
+// x_j = T_j^{-1} r_j with the factors of k_band_factor (layout [t][Ns] for r
+// and x, which must not alias): forward substitution into x, then backward
+// substitution in place, one thread per mode (each access of a wave is one
+// contiguous segment).
+template <class S, class C, int P>
+__global__ void __launch_bounds__(TPB) k_band_solve(const C* __restrict__ F, int Nt, int64_t Ns,
+                                                    const S* __restrict__ r, S* __restrict__ x) {
+  constexpr int KW = 2 * P + 1;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= Ns) return;
+  C ring[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) ring[k] = C(0);
+  for (int t = 0; t < Nt; ++t) {       // L y = r, ring = y_{t-P .. t-1}
+    C y = to_c(r[static_cast<int64_t>(t) * Ns + j], C(0));
+#pragma unroll
+    for (int k = 0; k < P; ++k) y -= F[(static_cast<int64_t>(t) * KW + k) * Ns + j] * ring[k];
+#pragma unroll
+    for (int k = 0; k < P - 1; ++k) ring[k] = ring[k + 1];
+    ring[P - 1] = y;
+    x[static_cast<int64_t>(t) * Ns + j] = from_c<S>(y);
+  }
+#pragma unroll
+  for (int k = 0; k < P; ++k) ring[k] = C(0);
+  for (int t = Nt - 1; t >= 0; --t) {  // U x = y, ring = x_{t+1 .. t+P}
+    C v = to_c(x[static_cast<int64_t>(t) * Ns + j], C(0));
+#pragma unroll
+    for (int m = 1; m <= P; ++m) v -= F[(static_cast<int64_t>(t) * KW + P + m) * Ns + j] * ring[m - 1];
+    v *= F[(static_cast<int64_t>(t) * KW + P) * Ns + j];
+#pragma unroll
+    for (int m = P - 1; m > 0; --m) ring[m] = ring[m - 1];
+    ring[0] = v;
+    x[static_cast<int64_t>(t) * Ns + j] = from_c<S>(v);
+  }
+}
+
 // ---------------------------------------------------------------- fused coefficient terms
 // The low-rank coefficient terms along the slowest spatial axis in one pass:
 // expansion of the input to the axis' Gauss points, the time mixing with the
@@ -1679,6 +1763,17 @@ __device__ double block_max(double v, double* sh) {
   return r;
 }
 
+// out[g] = sum_q X[g][q] over the Qs values of row g (one block per row).
+__global__ void __launch_bounds__(TPB) k_row_sums(const double* __restrict__ X, int64_t Qs, double* __restrict__ out) {
+  __shared__ double sh[TPB / 64];
+  const double* row = X + static_cast<int64_t>(blockIdx.x) * Qs;
+  double v = 0.0;
+  for (int64_t q = threadIdx.x; q < Qs; q += blockDim.x) v += row[q];
+  const double tot = block_sum(v, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = tot;
+}
+
+
 template <class T>
 __global__ void __launch_bounds__(TPB) k_multidot(const T* __restrict__ V, int64_t ldv, int k,
                                                   const T* __restrict__ w, int64_t n, double* __restrict__ part) {
@@ -2596,6 +2691,44 @@ void react_point(const S* Z, int nl, int lo_full, const DTable<C>& Bt, const C* 
 #undef RP
 }
 
+bool band_factor(const double* A, const double* B, int Nt, const double* lam, double shift, int64_t Ns, int p,
+                 double* F, hipStream_t s) {
+  if (Ns == 0) return true;
+  const dim3 g(grid_for(Ns)), b(TPB);
+  switch (p) {
+    case 1: hipLaunchKernelGGL(k_band_factor<1>, g, b, 0, s, A, B, Nt, lam, shift, Ns, F); break;
+    case 2: hipLaunchKernelGGL(k_band_factor<2>, g, b, 0, s, A, B, Nt, lam, shift, Ns, F); break;
+    case 3: hipLaunchKernelGGL(k_band_factor<3>, g, b, 0, s, A, B, Nt, lam, shift, Ns, F); break;
+    case 4: hipLaunchKernelGGL(k_band_factor<4>, g, b, 0, s, A, B, Nt, lam, shift, Ns, F); break;
+    case 5: hipLaunchKernelGGL(k_band_factor<5>, g, b, 0, s, A, B, Nt, lam, shift, Ns, F); break;
+    default: return false;
+  }
+  return true;
+}
+
+template <class S, class C>
+bool band_solve(const C* F, int Nt, int64_t Ns, int p, const S* r, S* x, hipStream_t s) {
+  if (Ns == 0) return true;
+  // algorithmic bytes: r read, x written, x read back and written, the factors read
+  ProfScope ps(K_ARROW, 5 + 16 * prec_code<S>(), s,
+               static_cast<double>(Nt) * Ns * (4.0 * sizeof(S) + (2.0 * p + 1.0) * sizeof(C)),
+               static_cast<double>(Nt) * Ns * (4.0 * p + 1.0));
+  const dim3 g(grid_for(Ns)), b(TPB);
+  switch (p) {
+    case 1: hipLaunchKernelGGL((k_band_solve<S, C, 1>), g, b, 0, s, F, Nt, Ns, r, x); break;
+    case 2: hipLaunchKernelGGL((k_band_solve<S, C, 2>), g, b, 0, s, F, Nt, Ns, r, x); break;
+    case 3: hipLaunchKernelGGL((k_band_solve<S, C, 3>), g, b, 0, s, F, Nt, Ns, r, x); break;
+    case 4: hipLaunchKernelGGL((k_band_solve<S, C, 4>), g, b, 0, s, F, Nt, Ns, r, x); break;
+    case 5: hipLaunchKernelGGL((k_band_solve<S, C, 5>), g, b, 0, s, F, Nt, Ns, r, x); break;
+    default: return false;
+  }
+  return true;
+}
+
+void row_sums(const double* X, int rows, int64_t Qs, double* out, hipStream_t s) {
+  if (rows > 0) hipLaunchKernelGGL(k_row_sums, dim3(rows), dim3(TPB), 0, s, X, Qs, out);
+}
+
 template <class S, class C>
 void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1, int p, const S* Z, int n_in,
               int in_base, S* out, int64_t Qs, hipStream_t s) {
@@ -3063,6 +3196,9 @@ template void react_point<double, double>(const double*, int, int, const DTable<
 template void react_point<float, float>(const float*, int, int, const DTable<float>&, const float*, const float*,
                                         const int*, const int*, const float*, const float*, int64_t, int, int, int,
                                         float*, float, hipStream_t);
+template bool band_solve<double, double>(const double*, int, int64_t, int, const double*, double*, hipStream_t);
+template bool band_solve<float, float>(const float*, int, int64_t, int, const float*, float*, hipStream_t);
+template bool band_solve<bf16, float>(const float*, int, int64_t, int, const bf16*, bf16*, hipStream_t);
 template void time_mix<double, double>(const double*, const double*, int, int, int, int, int, int, const double*,
                                        int, int, double*, int64_t, hipStream_t);
 template void time_mix<float, float>(const float*, const float*, int, int, int, int, int, int, const float*, int, int,

@@ -99,6 +99,18 @@ void react_point(const S* Z, int nl, int lo_full, const DTable<C>& Bt, const C* 
                  const int* re1, const C* Cq, const C* Rq, int64_t Qs, int t0, int t1, int p, S* out, C beta,
                  hipStream_t s);
 
+// Banded time solves of the SUPG preconditioner: per spatial mode j the
+// matrix T_j = A + (lam[j] - shift) B (bands [t][2p+1] of X_t, column t-p+k)
+// factorized without pivoting into F ([t][2p+1][Ns]: multipliers, reciprocal
+// pivot, upper entries); band_solve applies T_j^{-1} to r ([t][Ns]) into x
+// (no aliasing).  False (nothing launched) for p outside 1..5.
+bool band_factor(const double* A, const double* B, int Nt, const double* lam, double shift, int64_t Ns, int p,
+                 double* F, hipStream_t s);
+template <class S, class C>
+bool band_solve(const C* F, int Nt, int64_t Ns, int p, const S* r, S* x, hipStream_t s);
+// out[g] = sum of the Qs values of row g of X ([rows][Qs]).
+void row_sums(const double* X, int rows, int64_t Qs, double* out, hipStream_t s);
+
 // Coefficient part along the slowest spatial axis in one kernel (time_mix
 // between the expansion to that axis' Gauss points and the projection back):
 //   out[t - t0][i][c] = sum_{q in axis Gauss points} Bl[q][i - efirst(q)] *

@@ -148,6 +148,14 @@ struct st_iga_ctx {
   double* Rq_d = nullptr;
   float* Rq_f = nullptr;
   double* rq_out = nullptr;         // set while a quadrature pass must fill Rq_d
+  // preconditioner of the SUPG system: fast diagonalization in space, and
+  // per spatial mode an exact banded solve in time with T_j = A + lam_j B,
+  // B = M_t + W_tau, A = C_m (W_t + K_t^tau) plus the reaction and
+  // shock-capturing terms with their spatial means at each time Gauss point
+  // (refactorized at every linearization)
+  std::vector<double> supgA0_full, band_B_h, tq_h, wsum_h;
+  double *bandA_d = nullptr, *bandB_d = nullptr, *bandF_d = nullptr, *rowsum_d = nullptr;
+  float* bandF_f = nullptr;
   // low-rank factors
   int maxR = 0, Rth = 0, Rc = 0;
   double lr_relerr = 0.0;              // achieved relative Frobenius error of the last truncated SVD
@@ -384,6 +392,19 @@ void plan_fused_coef(st_iga_ctx* c) {
   c->qf_ne = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(c->nelt, ne)));
 }
 
+// Band [t][2p+1] (column t - p + k, zero outside) of the X_t block
+// (full rows and columns 1..nt-1) of a full nt x nt matrix.
+std::vector<double> band_rows(const std::vector<double>& A, int nt, int p) {
+  const int Nt = nt - 1, KW = 2 * p + 1;
+  std::vector<double> b(static_cast<size_t>(Nt) * KW, 0.0);
+  for (int t = 0; t < Nt; ++t)
+    for (int k = 0; k < KW; ++k) {
+      const int col = t - p + k;
+      if (col >= 0 && col < Nt) b[static_cast<size_t>(t) * KW + k] = A[static_cast<size_t>(t + 1) * nt + col + 1];
+    }
+  return b;
+}
+
 void host_setup(st_iga_ctx* c) {
   const st_iga_problem& P = c->P;
   c->d = P.d;
@@ -469,8 +490,15 @@ void host_setup(st_iga_ctx* c) {
     const std::vector<double> Kt = gram1d(T, 1, 1, &tq);
     for (size_t k = 0; k < Wsum.size(); ++k) Wsum[k] += Kt[k];
     c->Wt_x.h = banded_table(Wsum, nt, 1, Nt, pt);
-    c->Wtau_x.h = banded_table(gram1d(T, 1, 0, &tq), nt, 1, Nt, pt);
+    const std::vector<double> Wtau = gram1d(T, 1, 0, &tq);
+    c->Wtau_x.h = banded_table(Wtau, nt, 1, Nt, pt);
     c->BtTs.h = streamline_table_T(T, tq);
+    c->tq_h = tq;
+    c->supgA0_full = Wsum;
+    for (double& v : c->supgA0_full) v *= P.Cm;
+    std::vector<double> Bf = c->Mt_full;
+    for (size_t k = 0; k < Bf.size(); ++k) Bf[k] += Wtau[k];
+    c->band_B_h = band_rows(Bf, nt, pt);
   }
   c->Us_h.assign(P.d, {});
   c->lam_h.assign(P.d, {});
@@ -532,7 +560,7 @@ void host_setup(st_iga_ctx* c) {
   // the 1x1 (zero-frequency) time blocks of the arrowhead divide by the
   // spatial shift a c1 + sum_l sigma_l lambda_l; with a c1 = 0 the constant
   // Neumann mode makes it (numerically) zero
-  if (2 * c->fd_np < Nt - 1) {
+  if (!c->supg && 2 * c->fd_np < Nt - 1) {   // (the SUPG preconditioner solves in time exactly)
     double smin = INFINITY, smax = 0.0;
     for (double v : c->lam_s_h) {
       smin = std::min(smin, std::fabs(v));
@@ -700,6 +728,12 @@ void plan(st_iga_ctx* c) {
     c->Bts_d = a.get<double>(static_cast<int64_t>(c->Bts_h.size()));
     if (mixed) c->Bts_f = a.get<float>(static_cast<int64_t>(c->Bts_h.size()));
     c->scfac_d = a.get<double>(static_cast<int64_t>(c->scfac_h.size()));
+    const int64_t kw = 2 * c->P.p_t + 1;
+    c->bandA_d = a.get<double>(c->Nt * kw);
+    c->bandB_d = a.get<double>(c->Nt * kw);
+    c->bandF_d = a.get<double>(c->Ns * c->Nt * kw);
+    if (mixed) c->bandF_f = a.get<float>(c->Ns * c->Nt * kw);
+    c->rowsum_d = a.get<double>(2LL * c->dir[d].Q);
   }
   c->wq_s = a.get<double>(c->Qs);
   c->wq_t = a.get<double>(c->dir[d].Q);
@@ -875,8 +909,37 @@ void upload_all(st_iga_ctx* c, hipStream_t s) {
       up(keepf.back(), static_cast<const float*>(c->Bts_f), s);
     }
     up(c->scfac_h, static_cast<const double*>(c->scfac_d), s);
+    up(c->band_B_h, static_cast<const double*>(c->bandB_d), s);
   }
   CK(hipStreamSynchronize(s));
+}
+
+// Factorize the per-mode time matrices of the SUPG preconditioner with the
+// spatial means cr[g] of C_r (clipped at 0) and sc[g] of the shock-capturing
+// coefficient at the time Gauss points: A = C_m (W_t + K_t^tau) +
+// int cr b_j (b_i + tau b_i') + int sc b_j' b_i', T_j = A + lam_j B with lam_j
+// the spatial eigenvalue sums without the reaction shift.
+void supg_time_factor(st_iga_ctx* c, const std::vector<double>& cr, const std::vector<double>& sc, hipStream_t s) {
+  const Dir1D& T = c->dir[c->d];
+  const int pt = c->P.p_t, nt = c->nt;
+  std::vector<double> crt(T.Q), sct(T.Q), crtau(T.Q);
+  for (int q = 0; q < T.Q; ++q) {
+    crt[q] = std::max(cr[q], 0.0);
+    crtau[q] = crt[q] * c->tq_h[q];
+    sct[q] = std::max(sc[q], 0.0);
+  }
+  std::vector<double> A = c->supgA0_full;
+  const std::vector<double> R0 = gram1d(T, 0, 0, &crt), R1 = gram1d(T, 1, 0, &crtau), Sc = gram1d(T, 1, 1, &sct);
+  for (size_t k = 0; k < A.size(); ++k) A[k] += R0[k] + R1[k] + Sc[k];
+  const std::vector<double> band = band_rows(A, nt, pt);
+  CK(hipMemcpyAsync(c->bandA_d, band.data(), band.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  if (!band_factor(c->bandA_d, c->bandB_d, c->Nt, c->lam_d, c->P.a * c->P.c1, c->Ns, pt, c->bandF_d, s))
+    throw Fail{ST_IGA_EINVAL, "SUPG preconditioner: time degree above 5"};
+  const int64_t nf = c->Ns * c->Nt * (2 * pt + 1);
+  if (c->bandF_f) convert<double, float>(c->bandF_d, c->bandF_f, nf, s);
+  // the host vectors above are released on return: wait for the upload
+  CK(hipStreamSynchronize(s));
+  check_launch();
 }
 
 // ------------------------------------------------------------------ operators
@@ -1142,6 +1205,14 @@ void precond_impl(st_iga_ctx* c, const S* r, S* z, Bufs<S>& B, hipStream_t s) {
   const C* lam = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->lam_d) : reinterpret_cast<const C*>(c->lam_f);
   const C* mu = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->mu_d) : reinterpret_cast<const C*>(c->mu_f);
   const C* l = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->l_d) : reinterpret_cast<const C*>(c->l_f);
+  if (c->supg) {
+    // SUPG: exact banded solve per spatial mode in time
+    const C* F = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->bandF_d)
+                                                : reinterpret_cast<const C*>(c->bandF_f);
+    if (!band_solve<S, C>(F, Nt, Ns, c->P.p_t, a, b, s)) throw Fail{ST_IGA_EINVAL, "time degree above 5"};
+    dense_spatial<S, C>(c, U, b, Nt, a, e, z, s);
+    return;
+  }
   bool fused = false;
   if constexpr (std::is_same<C, float>::value) {
     // FP32: time transforms and arrowhead in one pass, b = U_t core^{-1} U_t^T a
@@ -2146,6 +2217,29 @@ void linearize(st_iga_ctx* c, const double* u, const double* w, bool refresh_the
       sc_scale(c->Rq_d, c->scfac_d, c->dsc + 300, c->P.Cm, 1.0 / c->P.T, c->Qs, nq, s);
       if (c->Rq_f) convert<double, float>(c->Rq_d, c->Rq_f, nq, s);
     }
+    if (c->supg) {
+      // spatial means of C_r and of the shock-capturing coefficient at each
+      // time Gauss point (Cq and Rq carry the Gauss weights)
+      const Dir1D& T = c->dir[c->d];
+      row_sums(c->Cq_d, T.Q, c->Qs, c->rowsum_d, s);
+      if (c->sc_on) row_sums(c->Rq_d, T.Q, c->Qs, c->rowsum_d + T.Q, s);
+      std::vector<double> sums(2 * static_cast<size_t>(T.Q), 0.0);
+      CK(hipMemcpyAsync(sums.data(), c->rowsum_d, (c->sc_on ? 2 : 1) * T.Q * sizeof(double), hipMemcpyDeviceToHost,
+                        s));
+      CK(hipStreamSynchronize(s));
+      double vol = 1.0;
+      for (int l = 0; l < c->d; ++l) {
+        double sw = 0.0;
+        for (double w : c->dir[l].wq) sw += w;
+        vol *= sw;
+      }
+      std::vector<double> cr(T.Q), sc(T.Q);
+      for (int q = 0; q < T.Q; ++q) {
+        cr[q] = sums[q] / (T.wq[q] * vol);
+        sc[q] = sums[T.Q + q] / (T.wq[q] * vol);
+      }
+      supg_time_factor(c, cr, sc, s);
+    }
     c->Rc = 0;
     c->err_c = 0.0;
     c->cap_c = false;
@@ -2270,7 +2364,7 @@ void st_iga_default_options(st_iga_options* o) {
   o->stall_cycles = 10;
   o->stall_reduction = 1e-3;
   o->picard_switch = 0;
-  o->sc_c = 1.0;
+  o->sc_c = 0.1;
   o->prec = ST_IGA_FP64;
   o->lin_forcing = 0.0;
   o->coef_slab = 0;
@@ -2316,6 +2410,12 @@ st_iga_status st_iga_setup(const st_iga_problem* prob, const st_iga_options* opt
     c->ar.dry = false;
     plan(c.get());
     upload_all(c.get(), s);
+    if (c->supg) {
+      // before the first linearization: the shift a c1 of the fast
+      // diagonalization as reaction, no shock capturing
+      const int Q = c->dir[c->d].Q;
+      supg_time_factor(c.get(), std::vector<double>(Q, c->P.a * c->P.c1), std::vector<double>(Q, 0.0), s);
+    }
     for (int l = 0; l < 4; ++l) c->P.knots[l] = nullptr;
     CK(hipGetDevice(&c->device));
     c->noalloc_ok = noalloc_scratch_init(c->device, c->noalloc_err);

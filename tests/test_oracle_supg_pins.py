@@ -218,3 +218,51 @@ def test_supg_picard_fixed_point():
     N = st.rows(A @ u - st.load_vector())
     assert np.max(np.abs(N)) <= 1e-7
     assert np.all(np.isfinite(u)) and u[:N_s].max() == pytest.approx(1.0)
+
+
+def test_supg_preconditioner_reduces_to_fast_diagonalization_operator():
+    """With tau = 0, cr = a c1 and sc = 0 the preconditioner's bilinear form is
+    the operator A-hat of Section 3.2 (assembled independently)."""
+    P, kn = _case(2, "c0")
+    st = SpaceTime(P, knots=kn, su=False, supg=True, sc_c=1.0)
+    st.supg_tau_t = np.zeros_like(st.supg_tau_t)
+    Qt = st.qshape[0]
+    A = st.assemble_precond_supg(np.full(Qt, P.a * P.c1), np.zeros(Qt))
+    B = st.assemble_precond()
+    assert abs(A - B).max() <= 1e-13 * abs(B).max()
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_supg_preconditioner_is_kronecker(d):
+    """The preconditioner is A_t (x) M_s + B_t (x) K_s with 1D matrices from
+    SciPy's basis: B_t = M_t + W_tau, A_t = C_m (W_t + K_tau) + cr-terms + sc-term."""
+    P, kn = _case(d, "graded")
+    st = SpaceTime(P, knots=kn, su=False, supg=True, sc_c=1.0)
+    Qt = st.qshape[0]
+    rng = np.random.default_rng(5)
+    cr_t, sc_t = rng.uniform(0.0, 0.5, Qt), rng.uniform(0.0, 2.0, Qt)
+    A = st.assemble_precond_supg(cr_t, sc_t).toarray()
+    # 1D matrices on a fine rule with SciPy's B-splines; the time coefficients
+    # are given at the oracle's Gauss points, so integrate them on that rule
+    Tk = P.T * np.asarray(kn[d])
+    tq, tw, tel = st.quad[d]
+    h = np.diff(np.unique(Tk))[tel]
+    tau = h / (2 * P.p_t + 1)
+    b0, b1 = _basis(Tk, P.p_t, tq, 0), _basis(Tk, P.p_t, tq, 1)
+    g = lambda wt, X, Y: X.T @ (wt[:, None] * Y)
+    At = P.Cm * (g(tw, b0, b1) + g(tw * tau, b1, b1)) + g(tw * cr_t, b0, b0) + g(tw * tau * cr_t, b1, b0) \
+        + g(tw * sc_t, b1, b1)
+    Bt = g(tw, b0, b0) + g(tw * tau, b1, b0)
+    Ms, Ks = [], []
+    for l in range(d):
+        x, w, _ = _fine_rule(kn[l], P.p_s + 2)
+        B0, B1 = _basis(kn[l], P.p_s, x, 0), _basis(kn[l], P.p_s, x, 1)
+        Ms.append(g(w, B0, B0))
+        Ks.append(g(w, B1, B1))
+    if d == 1:
+        M, K = Ms[0], P.sigma[0] * Ks[0]
+    else:
+        M = np.kron(Ms[1], Ms[0])
+        K = P.sigma[0] * np.kron(Ms[1], Ks[0]) + P.sigma[1] * np.kron(Ks[1], Ms[0])
+    want = np.kron(At[1:, 1:], M) + np.kron(Bt[1:, 1:], K)
+    assert np.max(np.abs(A - want)) <= 1e-12 * np.max(np.abs(want))
