@@ -297,7 +297,7 @@ st_iga_status st_iga_newton_step(st_iga_ctx* ctx, const double* u_in, double* u_
  * update+norm, 5 pointwise ionic quadrature, 6 element/window maxima,
  * 7 banded mode products (constant part of the operator), 8 spline
  * expansion/projection at Gauss points, 9 dense eigenvector mode products of
- * the preconditioner, 10 fused coefficient terms.  Classes 100 + f + 16 q
+ * the preconditioner, 10 fused coefficient terms.  Classes 100 + f + 32 q
  * select one kernel function f
  * (0 scalar gather, 1 4-wide gather, 2 LDS row gather, 3 time mixing,
  * 4 MFMA dense mode product, 5 arrowhead, 6 multi-dot, 7 update+norm,
@@ -310,7 +310,7 @@ st_iga_status st_iga_newton_step(st_iga_ctx* ctx, const double* u_in, double* u_
  * time mixing, the fused coefficient kernel and the dense mode products, 0
  * elsewhere) since the last reset, and synchronizes the recorded events.  Any
  * output pointer may be NULL.  profile_record returns launch i (in launch
- * order since the last reset): function id f + 16 q, duration (ms),
+ * order since the last reset): function id f + 32 q, duration (ms),
  * algorithmic bytes and flops; EINVAL past the last launch. */
 st_iga_status st_iga_profile(st_iga_ctx* ctx, int32_t enable);
 st_iga_status st_iga_profile_read(st_iga_ctx* ctx, int32_t kernel_class, double* ms, int64_t* launches,

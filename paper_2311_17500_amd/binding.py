@@ -344,7 +344,7 @@ class Solver:
                 "banded", "expand", "dense_fd", "coefficient"]
     FNAMES = ["gather_scalar", "gather_v4", "gather_rows", "time_mix", "dense_mode_mfma", "arrowhead",
               "multidot", "update_norm", "pointwise_ionic", "mode_max", "gather_sweep", "coef_fused",
-              "quad_fused", "sweep_dual", "time_core", "react_point"]
+              "quad_fused", "sweep_dual", "time_core", "react_point", "band_solve"]
 
     def profile(self, on=True):
         self._chk(self.lib.st_iga_profile(self.ctx, int(on)))
@@ -354,7 +354,7 @@ class Solver:
         out, i = [], 0
         fn, ms, by, fl = C.c_int32(0), C.c_double(0), C.c_double(0), C.c_double(0)
         while self.lib.st_iga_profile_record(self.ctx, i, C.byref(fn), C.byref(ms), C.byref(by), C.byref(fl)) == OK:
-            name = self.FNAMES[fn.value % 16] + "<" + ["f64", "f32", "bf16"][fn.value // 16] + ">"
+            name = self.FNAMES[fn.value % 32] + "<" + ["f64", "f32", "bf16"][fn.value // 32] + ">"
             out.append((name, ms.value, by.value, fl.value))
             i += 1
         return out
@@ -370,7 +370,7 @@ class Solver:
         for q, pn in enumerate(["f64", "f32", "bf16"]):
             for f, fname in enumerate(self.FNAMES):
                 ms, n, by, fl = C.c_double(0), C.c_int64(0), C.c_double(0), C.c_double(0)
-                self._chk(self.lib.st_iga_profile_read(self.ctx, 100 + f + 16 * q, C.byref(ms), C.byref(n),
+                self._chk(self.lib.st_iga_profile_read(self.ctx, 100 + f + 32 * q, C.byref(ms), C.byref(n),
                                                        C.byref(by), C.byref(fl), 0))
                 if n.value:
                     out[f"fn:{fname}<{pn}>"] = (ms.value, n.value, by.value, fl.value)

@@ -175,47 +175,6 @@ void upper_solve_T(const std::vector<double>& L, int n, std::vector<double>& A, 
     }
 }
 
-// Cyclic Jacobi eigensolver for a symmetric n x n matrix (row-major, destroyed).
-// V[i*n+j] = component i of eigenvector j.
-void jacobi_eig(std::vector<double>& A, int n, std::vector<double>& V, std::vector<double>& lam) {
-  V.assign(static_cast<size_t>(n) * n, 0.0);
-  for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
-  double fro = 0.0;
-  for (double v : A) fro += v * v;
-  fro = std::sqrt(fro);
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = i + 1; j < n; ++j) off += A[i * n + j] * A[i * n + j];
-    if (std::sqrt(off) <= 1e-17 * fro || fro == 0.0) break;
-    for (int p = 0; p < n; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = A[p * n + q];
-        if (std::fabs(apq) <= 1e-300) continue;
-        const double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < n; ++k) {  // columns p, q
-          const double akp = A[k * n + p], akq = A[k * n + q];
-          A[k * n + p] = c * akp - s * akq;
-          A[k * n + q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < n; ++k) {  // rows p, q
-          const double apk = A[p * n + k], aqk = A[q * n + k];
-          A[p * n + k] = c * apk - s * aqk;
-          A[q * n + k] = s * apk + c * aqk;
-        }
-        for (int k = 0; k < n; ++k) {
-          const double vkp = V[k * n + p], vkq = V[k * n + q];
-          V[k * n + p] = c * vkp - s * vkq;
-          V[k * n + q] = s * vkp + c * vkq;
-        }
-      }
-  }
-  lam.resize(n);
-  for (int i = 0; i < n; ++i) lam[i] = A[i * n + i];
-}
-
 }  // namespace
 
 bool build_dir(const double* knots01, int nk, int p, double scale, int nder, Dir1D& D, std::string& err) {
@@ -561,7 +520,7 @@ bool gen_eig_sym(const std::vector<double>& K, const std::vector<double>& M, int
       Ct[static_cast<size_t>(i) * n + j] = Ct[static_cast<size_t>(j) * n + i] = v;
     }
   std::vector<double> Q, l;
-  jacobi_eig(Ct, n, Q, l);
+  if (!sym_eig(Ct, n, Q, l, err)) return false;
   std::vector<int> idx(n);
   std::iota(idx.begin(), idx.end(), 0);
   std::sort(idx.begin(), idx.end(), [&](int a, int b) { return l[a] < l[b]; });
@@ -616,7 +575,7 @@ bool time_fd(const std::vector<double>& Wt, const std::vector<double>& Mt, int N
       S[static_cast<size_t>(i) * n + j] = s;
     }
   std::vector<double> V, mu2;
-  jacobi_eig(S, n, V, mu2);
+  if (!sym_eig(S, n, V, mu2, err)) return false;
   std::vector<int> idx(n);
   std::iota(idx.begin(), idx.end(), 0);
   std::sort(idx.begin(), idx.end(), [&](int a, int b) { return mu2[a] > mu2[b]; });

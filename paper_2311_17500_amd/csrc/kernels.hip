@@ -65,7 +65,7 @@ struct ProfState {
   size_t used = 0;
   struct Rec {
     int cls;   // purpose class
-    int fn;    // kernel function id + 16 * precision (0 f64, 1 f32, 2 bf16)
+    int fn;    // kernel function id + 32 * precision (0 f64, 1 f32, 2 bf16)
     hipEvent_t a, b;
     double bytes, flops;
   };
@@ -2494,7 +2494,7 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
     const int rc = static_cast<int>((t.n_out + nchunks - 1) / nchunks);
     nchunks = (t.n_out + rc - 1) / rc;
     const int64_t waves = groups * nchunks;
-    ProfScope ps(t_gather_cls, 10 + 16 * prec_code<Ti>(), s, gbytes);
+    ProfScope ps(t_gather_cls, 10 + 32 * prec_code<Ti>(), s, gbytes);
     const unsigned blocks = static_cast<unsigned>((waves * 64 + TPB - 1) / TPB);
 #define SF(w)                                                                                                        \
   hipLaunchKernelGGL((k_sweep_flat<Ti, C, w, 4>), dim3(blocks), dim3(TPB), 0, s, t.c0, t.coef, t.n_out, x,              \
@@ -2522,7 +2522,7 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
     nchunks = (t.n_out + rc - 1) / rc;
     const int64_t total_t = outer * nchunks * slots;
     if (total_t < (static_cast<int64_t>(1) << 32)) {
-      ProfScope ps(t_gather_cls, 10 + 16 * prec_code<Ti>(), s, gbytes);
+      ProfScope ps(t_gather_cls, 10 + 32 * prec_code<Ti>(), s, gbytes);
       const unsigned blocks = static_cast<unsigned>((total_t + TPB - 1) / TPB);
 #define SW(w, v)                                                                                                    \
   hipLaunchKernelGGL((k_sweep<Ti, C, w, v>), dim3(blocks), dim3(TPB), 0, s, t.c0, t.coef, t.n_out, x,                \
@@ -2551,7 +2551,7 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
     const int64_t kchunks = rpb > 1 ? 1 : (slots + TPB - 1) / TPB;
     const int64_t blocks = rpb > 1 ? (nrows + rpb - 1) / rpb : kchunks * nrows;
     if (blocks < (static_cast<int64_t>(1) << 31) && nrows < (static_cast<int64_t>(1) << 32)) {
-      ProfScope ps(t_gather_cls, 1 + 16 * prec_code<Ti>(), s, gbytes);
+      ProfScope ps(t_gather_cls, 1 + 32 * prec_code<Ti>(), s, gbytes);
 #define GV(wc, v)                                                                                              \
   hipLaunchKernelGGL((k_gather_v4<Ti, C, wc, v>), dim3(static_cast<unsigned>(blocks)), dim3(TPB), 0, s, t.col, t.coef, \
                      t.W, t.n_out, x, reinterpret_cast<Ti*>(y), static_cast<uint32_t>(inner), n_in, in_base, alpha,  \
@@ -2583,7 +2583,7 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
     const size_t sh = tab + static_cast<size_t>(RB) * n_in * sizeof(Ti);
     const int64_t groups = (outer + RB - 1) / RB;
     if (sh <= 64 * 1024) {
-      ProfScope ps(t_gather_cls, 2 + 16 * prec_code<Ti>(), s, gbytes);
+      ProfScope ps(t_gather_cls, 2 + 32 * prec_code<Ti>(), s, gbytes);
       const int64_t blocks = std::min<int64_t>(groups, 2048);
 #define GR(wt) hipLaunchKernelGGL((k_gather_rows<Ti, C, wt>), dim3(static_cast<unsigned>(blocks)), dim3(TPB), sh, s, t.col, t.coef, t.W, t.n_out, x, reinterpret_cast<Ti*>(y), n_in, in_base, alpha, beta, outer, RB)
       switch (t.W) {
@@ -2599,7 +2599,7 @@ void gather(const DTable<C>& t, const Ti* x, To* y, int64_t outer, int64_t inner
       return;
     }
   }
-  ProfScope ps(t_gather_cls, 0 + 16 * prec_code<Ti>(), s, gbytes);
+  ProfScope ps(t_gather_cls, 0 + 32 * prec_code<Ti>(), s, gbytes);
   if (total < (static_cast<int64_t>(1) << 32))
     hipLaunchKernelGGL((k_gather<Ti, To, C, uint32_t>), dim3(grid_for(total)), dim3(TPB), 0, s, t.col, t.coef, t.W,
                        t.n_out, x, y, static_cast<uint32_t>(inner), n_in, in_base, alpha, beta,
@@ -2625,7 +2625,7 @@ bool gather_dual(const DTable<C>& P, const DTable<C>& Q, const S* x, const S* z,
   nchunks = (P.n_out + rc - 1) / rc;
   const int64_t waves = groups * nchunks;
   const double by = (2.0 * outer * n_in * inner + (out1 ? 2.0 : 1.0) * outer * P.n_out * inner) * sizeof(S);
-  ProfScope ps(t_gather_cls, 13 + 16 * prec_code<S>(), s, by);
+  ProfScope ps(t_gather_cls, 13 + 32 * prec_code<S>(), s, by);
   const unsigned blocks = static_cast<unsigned>((waves * 64 + TPB - 1) / TPB);
 #define SD(w)                                                                                                      \
   hipLaunchKernelGGL((k_sweep_dual<S, C, w, E>), dim3(blocks), dim3(TPB), 0, s, P.c0, P.coef, Q.coef, P.n_out, x, z, \
@@ -2674,7 +2674,7 @@ void react_point(const S* Z, int nl, int lo_full, const DTable<C>& Bt, const C* 
   const int nterm = (Cq ? 1 : 0) + (Rq ? 1 : 0);
   // algorithmic bytes: the input layers, the coefficients at the slab's time
   // Gauss points and the output rows, each once
-  ProfScope ps(K_TIME_MIX, 15 + 16 * prec_code<S>(), s,
+  ProfScope ps(K_TIME_MIX, 15 + 32 * prec_code<S>(), s,
                (static_cast<double>(nl) + rows) * Qs * sizeof(S) +
                    nterm * static_cast<double>(rows) * (p + 1) * Qs * sizeof(C),
                nterm * 2.0 * (p + 1) * (p + 1) * (p + 2) * static_cast<double>(total));
@@ -2710,7 +2710,7 @@ template <class S, class C>
 bool band_solve(const C* F, int Nt, int64_t Ns, int p, const S* r, S* x, hipStream_t s) {
   if (Ns == 0) return true;
   // algorithmic bytes: r read, x written, x read back and written, the factors read
-  ProfScope ps(K_ARROW, 5 + 16 * prec_code<S>(), s,
+  ProfScope ps(K_ARROW, 16 + 32 * prec_code<S>(), s,
                static_cast<double>(Nt) * Ns * (4.0 * sizeof(S) + (2.0 * p + 1.0) * sizeof(C)),
                static_cast<double>(Nt) * Ns * (4.0 * p + 1.0));
   const dim3 g(grid_for(Ns)), b(TPB);
@@ -2737,7 +2737,7 @@ void time_mix(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1, 
   while (tpb > 64 && static_cast<size_t>(R) * tpb * sizeof(C) > 64 * 1024) tpb /= 2;
   const size_t sh = static_cast<size_t>(R > 0 ? R : 1) * tpb * sizeof(C);
   const dim3 g(grid_for(Qs, tpb)), b(tpb);
-  ProfScope ps(K_TIME_MIX, 3 + 16 * prec_code<S>(), s, (static_cast<double>(n_in) + R + (t1 - t0)) * Qs * sizeof(S),
+  ProfScope ps(K_TIME_MIX, 3 + 32 * prec_code<S>(), s, (static_cast<double>(n_in) + R + (t1 - t0)) * Qs * sizeof(S),
                2.0 * R * (2 * p + 2) * static_cast<double>(t1 - t0) * Qs);
   switch (p) {
     case 1: hipLaunchKernelGGL((k_time_mix<S, C, 1>), g, b, sh, s, T, Psi, r0, R, Nt, t0, t1, Z, n_in, in_base, out, Qs); break;
@@ -2769,7 +2769,7 @@ bool coef_fused(const C* T, const S* Psi, int r0, int r1, int Nt, int t0, int t1
   const double lim = 4294967295.0;
   const bool i32 = static_cast<double>(n_in) * nd * Qin < lim && static_cast<double>(t1 - t0 + TS) * nd * Qin < lim &&
                    static_cast<double>(r1) * Qs < lim;
-  ProfScope pr(K_COEF, 11 + 16 * prec_code<S>(), s,
+  ProfScope pr(K_COEF, 11 + 32 * prec_code<S>(), s,
                (static_cast<double>(n_in) * nd * Qin + rows * nd * Qin + static_cast<double>(R) * Qs) * sizeof(S), fl);
 #define CF(P_, K_)                                                                                                \
   do {                                                                                                            \
@@ -2812,7 +2812,7 @@ void dense_mode(const C* Ap, int n, int npad, const S* x, S* y, int64_t outer, i
   const size_t abytes = static_cast<size_t>(npad) * lds_stride<C>(npad) * sizeof(C);
   // the matrix goes to LDS up to 96 KB (gfx950 allows 160 KB per workgroup)
   const bool lds = abytes <= 96 * 1024;
-  ProfScope ps(K_DENSE, 4 + 16 * prec_code<S>(), s, 2.0 * ncols * n * sizeof(S), 2.0 * ncols * n * n);
+  ProfScope ps(K_DENSE, 4 + 32 * prec_code<S>(), s, 2.0 * ncols * n * sizeof(S), 2.0 * ncols * n * n);
   if (inner == 1 && NT <= 9) {
     // one wave per block; 4 column tiles (64 rows) unless the accumulators
     // (FP64 beyond 4 row tiles) or the staged rows would not fit
@@ -2905,7 +2905,7 @@ bool dense_mode_b16(const bf16* Ab, int n, int npad, const bf16* x, bf16* y, int
     constexpr int E = 4;
     const size_t xbytes = static_cast<size_t>(16 * E) * n * sizeof(bf16);
     if (xbytes > 64 * 1024) return false;
-    ProfScope ps(K_DENSE, 4 + 16 * 2, s, 2.0 * ncols * n * sizeof(bf16), 2.0 * ncols * n * n);
+    ProfScope ps(K_DENSE, 4 + 32 * 2, s, 2.0 * ncols * n * sizeof(bf16), 2.0 * ncols * n * n);
     const unsigned grid = static_cast<unsigned>((outer + 16 * E - 1) / (16 * E));
 #define DRB(nt) case nt: hipLaunchKernelGGL((k_dense_rows_b16<nt, E>), dim3(grid), dim3(64), xbytes, s, Ab, n, npad, x, y, outer); break;
     switch (NT) { DRB(1) DRB(2) DRB(3) DRB(4) DRB(5) DRB(6) DRB(7) DRB(8) DRB(9) default: break; }
@@ -2921,7 +2921,7 @@ bool dense_mode_b16(const bf16* Ab, int n, int npad, const bf16* x, bf16* y, int
   const size_t abytes = static_cast<size_t>(npad) * lds_stride_b16(npad) * sizeof(bf16);
   const int64_t groups = (ncols + 64 * E - 1) / (64 * E);
   const unsigned grid = static_cast<unsigned>(std::min<int64_t>(groups, 2048));
-  ProfScope ps(K_DENSE, 4 + 16 * 2, s, 2.0 * ncols * n * sizeof(bf16), 2.0 * ncols * n * n);
+  ProfScope ps(K_DENSE, 4 + 32 * 2, s, 2.0 * ncols * n * sizeof(bf16), 2.0 * ncols * n * n);
 #define DEB(nt, e) case nt: hipLaunchKernelGGL((k_dense_modeE_b16<nt, e>), dim3(grid), dim3(256), abytes, s, Ab, n, npad, x, y, inner, ncols); break;
   if (E == 4) {
     switch (NT) { DEB(1, 4) DEB(2, 4) DEB(3, 4) DEB(4, 4) DEB(5, 4) DEB(6, 4) DEB(7, 4) DEB(8, 4) DEB(9, 4) default: break; }
@@ -2935,7 +2935,7 @@ bool dense_mode_b16(const bf16* Ab, int n, int npad, const bf16* x, bf16* y, int
 template <class S, class C>
 void arrowhead(const S* r, S* y, const C* lam, const C* mu, int np, const C* l, C sigma, C Cm, int Nt,
                int64_t Ns, hipStream_t s) {
-  ProfScope ps(K_ARROW, 5 + 16 * prec_code<S>(), s, 2.0 * Nt * Ns * sizeof(S));
+  ProfScope ps(K_ARROW, 5 + 32 * prec_code<S>(), s, 2.0 * Nt * Ns * sizeof(S));
   hipLaunchKernelGGL((k_arrowhead<S, C>), dim3(grid_for(Ns)), dim3(TPB), 0, s, r, y, lam, mu, l, sigma, Cm, Nt, np, Ns);
 }
 
@@ -2992,7 +2992,7 @@ bool time_core(const float* UtT, const float* Ut, int Nt, int npad, const S* x, 
   // two blocks of TC_WAVES waves per CU (LDS bound) on 256 CUs
   const int64_t ntiles = (Ns + 15) / 16;
   const unsigned grid = static_cast<unsigned>(std::min<int64_t>((ntiles + TC_WAVES - 1) / TC_WAVES, 512));
-  ProfScope ps(K_DENSE, 14 + 16 * prec_code<S>(), s, 2.0 * Nt * Ns * sizeof(S) + Ns * sizeof(float),
+  ProfScope ps(K_DENSE, 14 + 32 * prec_code<S>(), s, 2.0 * Nt * Ns * sizeof(S) + Ns * sizeof(float),
                4.0 * Nt * Nt * Ns + 12.0 * Nt * Ns);
 #define TCK(nt) hipLaunchKernelGGL((k_time_core<S, nt>), dim3(grid), dim3(64 * TC_WAVES), lds, s, UtT, Ut, Nt, npad, x, z, Ns, lam, mu, np, l, sigma, Cm)
   switch (npad / 16) {
@@ -3009,7 +3009,7 @@ int reduce_blocks(int64_t n) { return static_cast<int>((n + RED_CHUNK - 1) / RED
 
 template <class T>
 void multidot_partial(const T* V, int64_t ldv, int k, const T* w, int64_t n, double* part, int nb, hipStream_t s) {
-  ProfScope ps(K_MULTIDOT, 6 + 16 * prec_code<T>(), s, (k + 1.0) * n * sizeof(T));
+  ProfScope ps(K_MULTIDOT, 6 + 32 * prec_code<T>(), s, (k + 1.0) * n * sizeof(T));
   constexpr int VEC = 16 / sizeof(T);
   if (ldv % VEC == 0 && reinterpret_cast<uintptr_t>(V) % 16 == 0 && reinterpret_cast<uintptr_t>(w) % 16 == 0)
     hipLaunchKernelGGL((k_multidot_v<T, VEC>), dim3(nb), dim3(TPB), 0, s, V, ldv, k, w, n, part);
@@ -3019,7 +3019,7 @@ void multidot_partial(const T* V, int64_t ldv, int k, const T* w, int64_t n, dou
 template <class T>
 void multidot2_partial(const T* V, int64_t ldv, int k, const T* a, const T* b, int64_t n, double* part, int nb,
                        hipStream_t s) {
-  ProfScope ps(K_MULTIDOT, 6 + 16 * prec_code<T>(), s, (k + 2.0) * n * sizeof(T));
+  ProfScope ps(K_MULTIDOT, 6 + 32 * prec_code<T>(), s, (k + 2.0) * n * sizeof(T));
   constexpr int VEC = 16 / sizeof(T);
   if (ldv % VEC == 0 && reinterpret_cast<uintptr_t>(V) % 16 == 0 && reinterpret_cast<uintptr_t>(a) % 16 == 0 &&
       reinterpret_cast<uintptr_t>(b) % 16 == 0)
@@ -3030,7 +3030,7 @@ void multidot2_partial(const T* V, int64_t ldv, int k, const T* a, const T* b, i
 template <class T>
 void dcgs_update_partial(T* V, int64_t ldv, int j, const double* dots, int64_t n, double* part, int nb, double* sc,
                          hipStream_t s) {
-  ProfScope ps(K_UPDATE, 7 + 16 * prec_code<T>(), s, (j + 4.0) * n * sizeof(T));
+  ProfScope ps(K_UPDATE, 7 + 32 * prec_code<T>(), s, (j + 4.0) * n * sizeof(T));
   hipLaunchKernelGGL((k_dcgs_update<T>), dim3(nb), dim3(TPB), 0, s, V, ldv, j, dots, n, part, sc);
 }
 void finalize_sum(const double* part, int nb, int k, double* out, hipStream_t s) {
@@ -3039,7 +3039,7 @@ void finalize_sum(const double* part, int nb, int k, double* out, hipStream_t s)
 template <class T>
 void update_norm_partial(const T* V, int64_t ldv, int k, const double* h, T* w, int64_t n, double* part, int nb,
                          hipStream_t s) {
-  ProfScope ps(K_UPDATE, 7 + 16 * prec_code<T>(), s, (k + 2.0) * n * sizeof(T));
+  ProfScope ps(K_UPDATE, 7 + 32 * prec_code<T>(), s, (k + 2.0) * n * sizeof(T));
   hipLaunchKernelGGL((k_update_norm<T>), dim3(nb), dim3(TPB), 0, s, V, ldv, k, h, w, n, part);
 }
 void absmax_partial(const double* x, int64_t n, double* part, int nb, hipStream_t s) {

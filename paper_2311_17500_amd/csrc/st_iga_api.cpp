@@ -2709,7 +2709,7 @@ st_iga_status st_iga_profile(st_iga_ctx* c, int32_t enable) {
 
 st_iga_status st_iga_profile_read(st_iga_ctx* c, int32_t cls, double* ms, int64_t* launches, double* bytes,
                                   double* flops, int32_t reset) {
-  if (!c || cls < 0 || (cls >= K_NCLASS && (cls < 100 || cls >= 148))) return ST_IGA_EINVAL;
+  if (!c || cls < 0 || (cls >= K_NCLASS && (cls < 100 || cls >= 196))) return ST_IGA_EINVAL;
   return guard(c, [&] { kprof_read(cls, ms, launches, bytes, flops, reset); });
 }
 

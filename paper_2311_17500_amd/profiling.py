@@ -32,7 +32,8 @@ _FN = {"k_sweep": "gather_sweep", "k_sweep_flat": "gather_sweep", "k_sweep_dual"
        "k_dense_rows": "dense_mode_mfma", "k_coef_fused": "coef_fused", "k_coef_fused_pf": "coef_fused",
        "k_quad_fused": "quad_fused", "k_time_core": "time_core", "k_time_mix": "time_mix", "k_arrowhead": "arrowhead",
        "k_multidot": "multidot", "k_multidot_v": "multidot", "k_update_norm": "update_norm",
-       "k_pointwise_ionic": "pointwise_ionic", "k_mode_max": "mode_max", "k_react_point": "react_point"}
+       "k_pointwise_ionic": "pointwise_ionic", "k_mode_max": "mode_max", "k_react_point": "react_point",
+       "k_band_solve": "band_solve", "k_band_factor": "band_factor"}
 
 
 def short_name(full: str) -> str:
