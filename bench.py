@@ -313,6 +313,25 @@ def bench_config(torch, W, cfg, precs, steps, warmup, tol, max_rank, solve_only_
     return prob, out
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Context for the HBM fractions: read + write bytes per second of a
+    plain device-to-device copy of 1 GiB on this GPU (torch's copy kernel)."""
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def summary(prob, cfg, prec, r, steps):
     """Compact record of one measured configuration (extra keys of the line)."""
     roof = roofline(r["prof"], steps, cfg)
@@ -426,6 +445,7 @@ def main():
     ms = main_r["ms"]
     value = prob.dof / (ms / 1e3)
     roof = roofline(main_r["prof"], a.steps, a.config)
+    roof["device_copy_GB_per_s"] = copy_bandwidth(torch)
     out = {
         "metric": "space-time DOF/s to rel. residual 1e-8 (mixed vs FP64); p50/p99 solve latency",
         "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
