@@ -2,8 +2,9 @@
 
     python -m paper_2311_17500_amd.profiling stats <kernel_stats.csv> <out.txt> "<command>"
     python -m paper_2311_17500_amd.profiling traffic <fetch_dir> <write_dir> <out.json> "<command>" [config]
-    python -m paper_2311_17500_amd.profiling resources <remarks.txt> <out.txt> "<command>"
+    python -m paper_2311_17500_amd.profiling resources <remarks.txt> <out.txt> "<command>" [<kernel_stats.csv>]
     python -m paper_2311_17500_amd.profiling activity <dir1,dir2,...> <out.txt> "<command>"
+    python -m paper_2311_17500_amd.profiling traffic-text <traffic.json> <config> <out.txt> ["<notes>"]
 
 `stats` turns the per-kernel statistics of a `rocprofv3 --kernel-trace
 --stats` run into a short text table (kernel, calls, total and average
@@ -193,9 +194,10 @@ def activity(dirs: str, out_txt: str, command: str, cus: int = 256, simds: int =
         fh.write("\n".join(lines) + "\n")
 
 
-def resources(remarks_txt: str, out_txt: str, command: str) -> None:
+def resources(remarks_txt: str, out_txt: str, command: str, launched_csv: str = "") -> None:
     """Per-kernel register, LDS, spill and occupancy figures from the
-    compiler's `-Rpass-analysis=kernel-resource-usage` remarks."""
+    compiler's `-Rpass-analysis=kernel-resource-usage` remarks; with a
+    rocprofv3 kernel_stats.csv, only the instantiations that run launched."""
     import subprocess
     fields = ("TotalSGPRs", "VGPRs", "AGPRs", "ScratchSize [bytes/lane]", "Occupancy [waves/SIMD]", "SGPRs Spill",
               "VGPRs Spill", "LDS Size [bytes/block]")
@@ -226,13 +228,44 @@ def resources(remarks_txt: str, out_txt: str, command: str) -> None:
         rows.append((short, f.get("VGPRs", "?"), f.get("AGPRs", "?"), f.get("TotalSGPRs", "?"),
                      f.get("VGPRs Spill", "?"), f.get("SGPRs Spill", "?"), f.get("ScratchSize [bytes/lane]", "?"),
                      f.get("LDS Size [bytes/block]", "?"), f.get("Occupancy [waves/SIMD]", "?")))
+    if launched_csv:
+        launched = set()
+        for r in _rows(launched_csv):
+            m = re.search(r"(k_\w+)(<[^()]*>)?\(", r["Name"])
+            if m:
+                launched.add((m.group(1) + (m.group(2) or "")).replace("__hip_bfloat16", "bf16"))
+        rows = [r for r in rows if r[0] in launched]
     rows.sort()
-    lines = ["# compiler resource usage per kernel instantiation (gfx950)", f"# command: {command}", "",
+    lines = ["# compiler resource usage per kernel instantiation (gfx950)"
+             + (" launched by the benchmark run" if launched_csv else ""), f"# command: {command}", "",
              f"{'kernel':78s} {'VGPR':>5s} {'AGPR':>5s} {'SGPR':>5s} {'Vspill':>6s} {'Sspill':>6s} "
              f"{'scratch':>7s} {'LDS B':>7s} {'waves/SIMD':>10s}"]
     for r in rows:
         lines.append(f"{r[0][:78]:78s} {r[1]:>5s} {r[2]:>5s} {r[3]:>5s} {r[4]:>6s} {r[5]:>6s} {r[6]:>7s} "
                      f"{r[7]:>7s} {r[8]:>10s}")
+    with open(out_txt, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def traffic_text(in_json: str, cfg: str, out_txt: str, notes: str = "") -> None:
+    """Text table of one workload's entry in the traffic record (read, write
+    and total HBM MB per launch), sorted by total, with optional note lines."""
+    with open(in_json) as fh:
+        doc = json.load(fh)
+    c = doc["configs"][cfg]
+    lines = [f"# HBM traffic per launch from rocprofv3 counters (config {cfg} workload)",
+             f"# command: {c['command']}",
+             f"# calibration: the probe's 1 GiB device copy ({c['copy_kernel']}): its known bytes are FETCH_SIZE x "
+             f"{c['fetch_scale']:.4f}",
+             f"#              and WRITE_SIZE x {c['write_scale']:.4f}; both factors applied below",
+             f"# kernel sources sha256 {doc['kernel_source_sha256']}",
+             "", f"{'kernel':28s} {'read MB':>8s} {'write MB':>10s} {'total MB':>10s}"]
+    rows = sorted(c["kernels"].items(), key=lambda kv: -kv[1]["hbm_bytes_per_launch"])
+    for name, k in rows:
+        lines.append(f"{name:28s} {k['fetch_bytes_per_launch'] / 1e6:8.1f} {k['write_bytes_per_launch'] / 1e6:10.1f} "
+                     f"{k['hbm_bytes_per_launch'] / 1e6:10.1f}")
+    if notes:
+        lines += [""] + ["# " + ln for ln in notes.split("\n")]
     with open(out_txt, "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
@@ -243,7 +276,9 @@ if __name__ == "__main__":
     elif len(sys.argv) >= 5 and sys.argv[1] == "activity":
         activity(sys.argv[2], sys.argv[3], sys.argv[4])
     elif len(sys.argv) >= 5 and sys.argv[1] == "resources":
-        resources(sys.argv[2], sys.argv[3], sys.argv[4])
+        resources(sys.argv[2], sys.argv[3], sys.argv[4], *(sys.argv[5:6]))
+    elif len(sys.argv) >= 5 and sys.argv[1] == "traffic-text":
+        traffic_text(sys.argv[2], sys.argv[3], sys.argv[4], *(sys.argv[5:6]))
     elif len(sys.argv) >= 6 and sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], *(sys.argv[6:7]))
     else:
