@@ -10,7 +10,9 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -392,6 +394,105 @@ void plan_fused_coef(st_iga_ctx* c) {
   c->qf_ne = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(c->nelt, ne)));
 }
 
+// Process-wide cache of the 1D eigen setups and of the SU coefficients tau_k.
+// The pencils (K_l, M_l) and (W_t, M_t) and the tau_k depend only on knots,
+// degree, map and T, not on sigma or the ionic parameters, so requests of the
+// same shape (a serving stream repeats a few dozen shapes) share them.  Keyed by the exact matrix entries; at most
+// kEigCacheMax entries of each kind (oldest evicted); thread-safe.
+constexpr size_t kEigCacheMax = 32;
+struct EigCache {
+  std::mutex mu;
+  std::map<std::vector<double>, std::pair<std::vector<double>, std::vector<double>>> space;   // -> (U, lambda)
+  std::map<std::vector<double>, TimeFD> time;
+  std::map<std::vector<double>, std::vector<double>> tau;   // time knots (+ degree) -> tau_k at the Gauss points
+  std::vector<std::vector<double>> space_order, time_order, tau_order;
+};
+EigCache& eig_cache() {
+  static EigCache c;
+  return c;
+}
+std::vector<double> pencil_key(const std::vector<double>& A, const std::vector<double>& B, int n) {
+  std::vector<double> k;
+  k.reserve(A.size() + B.size() + 1);
+  k.push_back(static_cast<double>(n));
+  k.insert(k.end(), A.begin(), A.end());
+  k.insert(k.end(), B.begin(), B.end());
+  return k;
+}
+bool gen_eig_sym_cached(const std::vector<double>& K, const std::vector<double>& M, int n, std::vector<double>& U,
+                        std::vector<double>& lam, std::string& err) {
+  EigCache& c = eig_cache();
+  const std::vector<double> key = pencil_key(K, M, n);
+  {
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.space.find(key);
+    if (it != c.space.end()) {
+      U = it->second.first;
+      lam = it->second.second;
+      return true;
+    }
+  }
+  if (!gen_eig_sym(K, M, n, U, lam, err)) return false;
+  std::lock_guard<std::mutex> g(c.mu);
+  if (c.space.emplace(key, std::make_pair(U, lam)).second) {
+    c.space_order.push_back(key);
+    if (c.space_order.size() > kEigCacheMax) {
+      c.space.erase(c.space_order.front());
+      c.space_order.erase(c.space_order.begin());
+    }
+  }
+  return true;
+}
+bool time_fd_cached(const std::vector<double>& Wt, const std::vector<double>& Mt, int N, TimeFD& F,
+                    std::string& err) {
+  EigCache& c = eig_cache();
+  const std::vector<double> key = pencil_key(Wt, Mt, N);
+  {
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.time.find(key);
+    if (it != c.time.end()) {
+      F = it->second;
+      return true;
+    }
+  }
+  if (!time_fd(Wt, Mt, N, F, err)) return false;
+  std::lock_guard<std::mutex> g(c.mu);
+  if (c.time.emplace(key, F).second) {
+    c.time_order.push_back(key);
+    if (c.time_order.size() > kEigCacheMax) {
+      c.time.erase(c.time_order.front());
+      c.time_order.erase(c.time_order.begin());
+    }
+  }
+  return true;
+}
+
+bool tau_at_quad_cached(const Dir1D& T, std::vector<double>& tauq, std::string& err) {
+  EigCache& c = eig_cache();
+  std::vector<double> key(T.knots);
+  key.push_back(static_cast<double>(T.p));
+  key.push_back(static_cast<double>(T.nq));
+  {
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.tau.find(key);
+    if (it != c.tau.end()) {
+      tauq = it->second;
+      return true;
+    }
+  }
+  std::vector<double> coefs;
+  if (!tau_at_quad(T, tauq, coefs, err)) return false;
+  std::lock_guard<std::mutex> g(c.mu);
+  if (c.tau.emplace(key, tauq).second) {
+    c.tau_order.push_back(key);
+    if (c.tau_order.size() > kEigCacheMax) {
+      c.tau.erase(c.tau_order.front());
+      c.tau_order.erase(c.tau_order.begin());
+    }
+  }
+  return true;
+}
+
 // Band [t][2p+1] (column t - p + k, zero outside) of the X_t block
 // (full rows and columns 1..nt-1) of a full nt x nt matrix.
 std::vector<double> band_rows(const std::vector<double>& A, int nt, int p) {
@@ -462,10 +563,9 @@ void host_setup(st_iga_ctx* c) {
   c->Bt0.h = eval_table(T, 0);
   c->Bt1.h = eval_table(T, 1);
   c->BtT.h = eval_table_T(T, 0, nullptr);
-  std::vector<double> tau_coefs;
   // the tau_k of the SU term need C^{p_t - 1} time splines: SU only
   if (c->opt.su == 1) {
-    if (!tau_at_quad(T, c->tauq, tau_coefs, err)) throw Fail{ST_IGA_EINVAL, err};
+    if (!tau_at_quad_cached(T, c->tauq, err)) throw Fail{ST_IGA_EINVAL, err};
   } else {
     c->tauq.assign(static_cast<size_t>(pt) * T.Q, 0.0);
   }
@@ -512,7 +612,7 @@ void host_setup(st_iga_ctx* c) {
     c->BqT[l].h = eval_table_T(D, 0, nullptr);
     c->Hs[l].h = hat_table(D.grev_x, D.xq);   // interpolation at the mapped Greville abscissae
     c->Gs[l].h = sparse_rows(collocation(D, D.grev, 0), D.n, D.n);
-    if (!gen_eig_sym(K, M, D.n, c->Us_h[l], c->lam_h[l], err)) throw Fail{ST_IGA_EINVAL, err};
+    if (!gen_eig_sym_cached(K, M, D.n, c->Us_h[l], c->lam_h[l], err)) throw Fail{ST_IGA_EINVAL, err};
     c->Us[l].h = dense_table(c->Us_h[l], D.n, D.n, false);
     c->UsT[l].h = dense_table(c->Us_h[l], D.n, D.n, true);
   }
@@ -521,7 +621,7 @@ void host_setup(st_iga_ctx* c) {
   c->Gt.h = sparse_rows(collocation(T, gt, 0), Nt, nt);
   // FD time data on the X_t block
   std::vector<double> Wx = sub_rows(c->Wt_full, nt, 1, nt, 1, nt), Mx = sub_rows(c->Mt_full, nt, 1, nt, 1, nt);
-  if (!time_fd(Wx, Mx, Nt, c->fd, err)) throw Fail{ST_IGA_EINVAL, err};
+  if (!time_fd_cached(Wx, Mx, Nt, c->fd, err)) throw Fail{ST_IGA_EINVAL, err};
   // the 2x2 blocks lead, 1x1 blocks follow (checked: the kernel relies on it)
   c->fd_np = 0;
   while (2 * c->fd_np + 1 < Nt - 1 && c->fd.kind[2 * c->fd_np] == 0 && c->fd.kind[2 * c->fd_np + 1] == 1) ++c->fd_np;

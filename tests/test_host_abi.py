@@ -304,3 +304,40 @@ def test_server_failure_releases_slot(monkeypatch):
     assert all(r.status.startswith("RuntimeError") for r in recs)
     assert all(r.finished >= r.admitted for r in recs)
     assert serve.summarize(recs)["completed"] == 0
+
+
+def test_eigen_setup_cache_is_transparent(lib):
+    """The process-wide cache of the 1D eigen setups returns exactly what a
+    fresh computation gives: a shape seen for the first time, the same shape
+    again (a cache hit, with another sigma), and again after more distinct
+    shapes than the cache holds (evicted, recomputed)."""
+    def knots(seed):
+        rng = np.random.default_rng(seed)
+        inner = np.sort(rng.uniform(0.05, 0.95, 6))
+        return np.concatenate([np.zeros(3), inner, np.ones(3)])
+
+    def prob_for(seed, sigma):
+        P = W.tiny(2, 2, 7, nel_t=7)
+        P.sigma = sigma
+        kn = P.uniform_knots()
+        kn[0] = knots(seed)
+        kn[2] = knots(seed + 1000)
+        return P, kn
+
+    def setup(P, kn):
+        return [binding.host_query(P, w, 0, kn) for w in (5, 6)] + [binding.host_query(P, 7, 2, kn),
+                                                                   binding.host_query(P, 4, 2, kn)]
+
+    P, kn = prob_for(12345, (1e-3, 2.5e-4))
+    first = setup(P, kn)
+    P2, kn2 = prob_for(12345, (3e-3, 1e-4))
+    again = setup(P2, kn2)
+    for a, b in zip(first, again):
+        assert np.array_equal(a, b)
+    for s in range(40):                       # more distinct shapes than the cache keeps
+        Pi, kni = prob_for(20000 + s, (1e-3, 2.5e-4))
+        binding.host_query(Pi, 5, 0, kni)
+        binding.host_query(Pi, 7, 2, kni)
+    later = setup(P, kn)
+    for a, b in zip(first, later):
+        assert np.array_equal(a, b)
