@@ -1510,9 +1510,11 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
         finalize_sum(c->part, nb, 2 * (j + 1), D, ss);
         dcgs_update_partial<T>(V, ld, j, D, n, c->part, nb, D + 128, ss);
         finalize_sum(c->part, nb, 1, D + 256, ss);
+        // the step's scalars to pinned host memory, inside the replayed graph
+        // (one runtime call less per Krylov iteration)
+        CK(hipMemcpyAsync(c->step_host + (j & 1) * HS, D, 257 * sizeof(double), hipMemcpyDeviceToHost, ss));
       };
       run_step(c, gv, j, m, body, s);
-      CK(hipMemcpyAsync(c->step_host + (j & 1) * HS, D, 257 * sizeof(double), hipMemcpyDeviceToHost, s));
       CK(hipEventRecord(c->step_ev[j & 1], s));
     };
     int queued = -1;          // last step already on the stream
