@@ -29,11 +29,13 @@ def torch():
     return t
 
 
-def _case(d, p, nel, nel_t, c0=True, source=False):
+def _case(d, p, nel, nel_t, c0=True, source=False, mapped=False):
     kw = {}
     if source:
         kw = dict(u0_kind=0, f_kind=2, f_t0=0.2, f_t1=0.5, f_amp=2.0, f_center=(0.1, 0.5, 0.5), f_kappa=20.0,
                   f_velocity=(0.8, 0.0, 0.2))
+    if mapped:   # affine stretch along x1, exponential grading along x2
+        kw.update(map_kind=(1, 2, 0), map_param=((0.0, 1.5, 0.0), (0.0, 0.5, 2.0), (0.0, 1.0, 0.0)))
     prob = W.tiny(d, p, nel, nel_t=nel_t, **kw)
     kn = prob.uniform_knots()
     if c0:
@@ -42,6 +44,7 @@ def _case(d, p, nel, nel_t, c0=True, source=False):
 
 
 CASES = [("1d_p3_c0", 1, 3, 8, 4, True, False),
+         ("2d_p3_c0_src_mapped", 2, 3, 4, 3, True, "mapped"),
          ("2d_p2_c0", 2, 2, 5, 4, True, False),
          ("2d_p3_c0_src", 2, 3, 4, 3, True, True),
          ("2d_p2_smooth", 2, 2, 5, 6, False, False),
@@ -71,7 +74,7 @@ def test_supg_operator_and_residual(gpu_lib, torch, name, d, p, nel, nel_t, c0, 
     C_r and the shock-capturing coefficient at a non-trivial state; the
     residual A(u, w) u - F; the FP32 operator of a mixed context."""
     from paper_2311_17500_amd.binding import MIXED_FP32
-    prob, kn = _case(d, p, nel, nel_t, c0, src)
+    prob, kn = _case(d, p, nel, nel_t, c0, bool(src), mapped=src == "mapped")
     st = SpaceTime(prob, knots=kn, su=False, supg=True, sc_c=SC_C)
     u, w = _state(st, 31)
     sc = st.sc_coefficient(u, w)
@@ -92,7 +95,7 @@ def test_supg_operator_and_residual(gpu_lib, torch, name, d, p, nel, nel_t, c0, 
     assert rel(S.residual(ud, wd).cpu().numpy(), want_r) < 1e-11
 
 
-PREC = [CASES[0], CASES[2], CASES[4]]
+PREC = [CASES[0], CASES[1], CASES[3], CASES[5]]
 
 
 @pytest.mark.parametrize("name,d,p,nel,nel_t,c0,src", PREC, ids=[c[0] for c in PREC])
@@ -104,7 +107,7 @@ def test_supg_preconditioner(gpu_lib, torch, name, d, p, nel, nel_t, c0, src):
     preconditioner; FP32 and allocation-free variants."""
     import scipy.sparse.linalg as spla
     from paper_2311_17500_amd.binding import MIXED_FP32
-    prob, kn = _case(d, p, nel, nel_t, c0, src)
+    prob, kn = _case(d, p, nel, nel_t, c0, bool(src), mapped=src == "mapped")
     st = SpaceTime(prob, knots=kn, su=False, supg=True, sc_c=SC_C)
     Qt = st.qshape[0]
     S = _solver(prob, kn, prec=MIXED_FP32)
