@@ -81,7 +81,7 @@ typedef struct {
 
 /* Stimulus: an initial datum u0 (lifted into time layer 0 by sampling at the
  * spatial Greville abscissae) and/or a source f of eq. (3.1), which enters the
- * residual as -int f v and the residual inside theta (eq. (3.4)) as -f, both
+ * residual as -int f v and the residual inside theta (eq. (3.6)) as -f, both
  * evaluated at the space-time Gauss points.  The two source kinds are the
  * stimuli of the paper's experiments (Section 4): a characteristic function
  * of a ball times a time window (the 3D test), and a moving Gaussian times a
@@ -103,7 +103,7 @@ typedef struct {
 } st_iga_stimulus;
 
 typedef struct {
-  int32_t su;                /* stabilization: 1 the Spline Upwind term of eq. (3.2), 0 none (plain
+  int32_t su;                /* stabilization: 1 the Spline Upwind term of eq. (3.4), 0 none (plain
                                 Galerkin), 2 SUPG + shock capturing of Section 4.2.2 (the comparison
                                 method for splines of any regularity in time, C^0 included; needs
                                 outer = 2): the test function v + tau v_t on the residual
@@ -112,12 +112,12 @@ typedef struct {
                                 ||u^k_t||_inf)) u_t v_t (zero when that denominator is 0), h the
                                 length of the time element; C_r and |R| are exact at every Gauss point
                                 (the paper low-ranks both) */
-  double eps_theta;          /* relative Frobenius tolerance of the theta low rank, eq. (3.8) (paper: 0.1) */
+  double eps_theta;          /* relative Frobenius tolerance of the theta low rank, eq. (3.9) (paper: 0.1) */
   double eps_react;          /* same tolerance for the reaction coefficient of the Jacobian */
   int32_t max_rank;          /* cap on each low rank (sizes the workspace); a capped rank misses eps
                                 and is counted in st_iga_report.rank_capped */
   int32_t outer;             /* 0: Newton (dI_ion/du, low rank), w lagged (w = w(u^k));
-                                1: defect-correction Picard with a low-rank C_r of eq. (3.6), w lagged;
+                                1: defect-correction Picard with a low-rank C_r of eq. (3.8), w lagged;
                                 2: the fixed-point scheme of Section 3.1 as stated: M_R with the exact
                                    C_r(u^k, w^k) at every space-time Gauss point (no low rank; the
                                    coefficient is stored, Q_t x Q_s values), u and w both relaxed with
@@ -184,7 +184,7 @@ void st_iga_default_options(st_iga_options* opt);
  * (256-byte aligned sub-buffers included).  Returns 0 on invalid input. */
 size_t st_iga_workspace_bytes(const st_iga_problem* prob, const st_iga_options* opt);
 
-/* Build the 1D operators (Section 3.1.1), tau_k (eq. (3.3)) and the
+/* Build the 1D operators (Section 3.1.1), tau_k (eq. (3.5)) and the
  * fast-diagonalization factors (Section 3.2) on the host in FP64 and upload
  * them into `workspace` (device, >= st_iga_workspace_bytes, 256-byte aligned).
  * Errors: EINVAL for invalid problems (knots not open/non-decreasing on
@@ -194,8 +194,8 @@ size_t st_iga_workspace_bytes(const st_iga_problem* prob, const st_iga_options* 
 st_iga_status st_iga_setup(const st_iga_problem* prob, const st_iga_options* opt, void* workspace,
                            size_t workspace_bytes, void* stream, st_iga_ctx** out);
 
-/* Linearize at (u, w) (full device vectors): theta of eq. (3.4) on the
- * Greville grid (when su = 1 and refresh_theta != 0), its low rank (eq. (3.8)),
+/* Linearize at (u, w) (full device vectors): theta of eq. (3.6) on the
+ * Greville grid (when su = 1 and refresh_theta != 0), its low rank (eq. (3.9)),
  * the reaction coefficient (Newton: dI_ion/du; Picard: C_r) on the Greville
  * grid and its low rank; the result defines J_k for apply/krylov.  Synchronizes. */
 st_iga_status st_iga_linearize(st_iga_ctx* ctx, const double* u, const double* w, int32_t refresh_theta,
@@ -221,7 +221,7 @@ st_iga_status st_iga_get_factors(st_iga_ctx* ctx, int32_t* r_theta, double* U_th
  * a non-positive radius or kappa, f_t0 > f_t1 or a non-finite amplitude. */
 st_iga_status st_iga_set_stimulus(st_iga_ctx* ctx, const st_iga_stimulus* stim);
 
-/* Theta grid of eq. (3.4) before the low rank (N_t x N_s, device) at (u, w). */
+/* Theta grid of eq. (3.6) before the low rank (N_t x N_s, device) at (u, w). */
 st_iga_status st_iga_theta_grid(st_iga_ctx* ctx, const double* u, const double* w, double* theta,
                                 void* stream);
 
@@ -231,7 +231,7 @@ st_iga_status st_iga_theta_grid(st_iga_ctx* ctx, const double* u, const double* 
 st_iga_status st_iga_apply(st_iga_ctx* ctx, const double* x, double* y, void* stream);
 
 /* z = A-hat^{-1} r (device): the fast-diagonalization preconditioner of
- * eq. (3.10)-(3.11) with sigma-scaled stiffness.  Asynchronous. */
+ * eq. (3.15)-(3.16) with sigma-scaled stiffness.  Asynchronous. */
 st_iga_status st_iga_precond(st_iga_ctx* ctx, const double* r, double* z, void* stream);
 
 /* For callers that cannot allocate memory (code under HIP graph capture,
@@ -258,7 +258,7 @@ st_iga_status st_iga_precond_noalloc(st_iga_ctx* ctx, const double* r, double* z
 st_iga_status st_iga_apply_lowp(st_iga_ctx* ctx, const double* x, double* y, void* stream);
 st_iga_status st_iga_precond_lowp(st_iga_ctx* ctx, const double* r, double* z, void* stream);
 
-/* Residual N(u) (unknown-sized output) of eq. (3.2) at full vectors (u, w) with
+/* Residual N(u) (unknown-sized output) of eq. (3.4) at full vectors (u, w) with
  * the current low-rank theta and the exact ionic current at the Gauss points. */
 st_iga_status st_iga_residual(st_iga_ctx* ctx, const double* u, const double* w, double* r,
                               void* stream);
@@ -344,7 +344,7 @@ st_iga_status st_iga_host_query(const st_iga_problem* prob, int32_t what, int32_
                                 int64_t cap, int64_t* len);
 
 /* Host-only check of the symmetric eigensolver used for the truncated SVDs of
- * eq. (3.8) (through the N_t x N_t Gram matrix): A (n x n, row-major,
+ * eq. (3.9) (through the N_t x N_t Gram matrix): A (n x n, row-major,
  * symmetric, HOST) = Q diag(lam) Q^T with lam ascending and the eigenvectors
  * in the columns of the row-major Q (n*n, HOST).  ENOCONV if the QL
  * iteration fails. */

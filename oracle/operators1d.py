@@ -8,7 +8,7 @@ evaluated with (p+1)-point Gauss quadrature per element (reading: the paper
 does not name its rule; p+1 points integrate these polynomial products of
 degree <= 2p exactly).
 
-The tau_k of the SU term (eq. (3.3)) are splines of degree p_t - k with
+The tau_k of the SU term (eq. (3.5)) are splines of degree p_t - k with
 maximal regularity on the time breakpoints.  Reading of the index set: the
 equations are imposed for every pair (i, i + l) of the *full* time basis with
 1 <= l <= min(p_t, n_t - i); this makes the linear system square (its
@@ -54,7 +54,7 @@ def reduced_knots(knots, q: int) -> np.ndarray:
 
 
 def tau_splines(knots_t, p_t: int, nq=None):
-    """Solve eq. (3.3) for tau_1..tau_{p_t}.
+    """Solve eq. (3.5) for tau_1..tau_{p_t}.
 
     Returns a list of (knots_k, degree_k, coefficients_k).  The square system
     has one row per full-basis pair (i, i+l) and one column per basis function

@@ -62,7 +62,7 @@ class RowSampler:
         return self._rows(np.concatenate([np.zeros(N_s), x_unk]), rows, theta, coef, coef_const, None)
 
     def residual_rows(self, u_full, w_full, rows, theta=None, f=None):
-        """N(u) of eq. (3.2) at the given unknown rows (full vectors u, w with
+        """N(u) of eq. (3.4) at the given unknown rows (full vectors u, w with
         their initial layer): the same form with the reaction term replaced by
         the exact ionic current I_ion(u_h, w_h) at the Gauss points, minus the
         source f(xs, t) when given."""

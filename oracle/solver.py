@@ -4,10 +4,10 @@ Test infrastructure (see package doc).
 One outer iteration at the iterate (u^k, w^k) (readings listed in
 ``spacetime``):
   1. w^k from the L-system of Section 3.1.1 (explicit sparse solve);
-  2. theta of eq. (3.4) on the Greville grid, truncated SVD with eps_theta,
+  2. theta of eq. (3.6) on the Greville grid, truncated SVD with eps_theta,
      interpolated to the Gauss points (refreshed until ||delta||_inf <=
      theta_freeze, frozen afterwards);
-  3. reaction coefficient (dI/du for Newton, C_r of eq. (3.6) for Picard) on
+  3. reaction coefficient (dI/du for Newton, C_r of eq. (3.8) for Picard) on
      the Greville grid, truncated SVD with eps_react, interpolated;
   4. J = explicit sparse matrix of the linearised form, r = N(u^k);
   5. delta = -J^{-1} r by a sparse LU (scipy splu);
@@ -100,11 +100,11 @@ def solve_picard(st: SpaceTime, alpha=0.5, eps_theta=0.1, tol=1e-4, max_outer=20
     """The fixed-point scheme of Section 3.1 as the paper states it, step by
     step.  From u^0 (the lifted datum in every time layer) and w^0 = 0, each
     iteration
-      1. builds theta(u^k, w^k) (eq. (3.4)) and its truncated SVD (eq. (3.8)),
+      1. builds theta(u^k, w^k) (eq. (3.6)) and its truncated SVD (eq. (3.9)),
          refreshed every iteration (while the change exceeds theta_freeze,
          when given; a fixed theta_lr skips this step);
       2. assembles A of Section 3.1.1 with M_R weighted by the exact
-         C_r(u^k, w^k) of eq. (3.6) at the Gauss points and the low-rank SU
+         C_r(u^k, w^k) of eq. (3.8) at the Gauss points and the low-rank SU
          term (or, with SUPG, the SUPG and shock-capturing terms of Section
          4.2.2 with C_r and the residual ratio at (u^k, w^k) taken exactly at
          the Gauss points), and the load vector F;

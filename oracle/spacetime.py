@@ -20,22 +20,22 @@ Readings taken here (the paper is silent or ambiguous):
 * Initial datum (eq. (3.1) has u = 0 at t = 0 plus a source; the workloads
   use an indicator initial datum and no source): the datum is lifted into time
   layer 0 with coefficients u0(gamma_i) sampled at the spatial Greville points.
-* theta (eq. (3.4)): the L-infinity norms are maxima of |.| over the Gauss
+* theta (eq. (3.6)): the L-infinity norms are maxima of |.| over the Gauss
   points of the elements inside the window; the window of the full-basis
   function j (0-based) in a direction is (xi_{j-p}, xi_{j+p+1}) in the paper's
-  1-based knot indexing (eq. (2.2)) with indices clamped to the knot vector;
+  1-based knot indexing (eq. (2.3)) with indices clamped to the knot vector;
   time functions of X_t are full indices 1..n_t-1.  If the denominator is 0,
   Theta = 1 where the numerator is positive, else 0.
 * theta is min(..., 1) on the Greville grid, then low-ranked; the low-rank
   interpolant is not clipped again.  Interpolation in time uses the Greville
   points of X_t; below the first of them it is extended by a constant.
-* The low rank (eq. (3.8)) is the truncated SVD with the smallest R such that
+* The low rank (eq. (3.9)) is the truncated SVD with the smallest R such that
   the Frobenius tail is <= eps times the norm (a deterministic stand-in for a
   randomized sketch: the same tolerance, a unique answer).
 * Outer loop: defect correction u <- u + alpha*delta with
   (A_lin + M[c~]) delta = -N(u), N the full residual with the exact ionic
   current at the Gauss points.  Newton: c = dI_ion/du, alpha = 1.  Picard
-  (Section 3.1): c = C_r of eq. (3.6), alpha = 0.5.  c is sampled on the
+  (Section 3.1): c = C_r of eq. (3.8), alpha = 0.5.  c is sampled on the
   Greville grid and low-ranked like theta.  w is lagged: w^k solves the
   L-system of Section 3.1.1 with u^k.  theta is refreshed while
   ||delta||_inf > theta_freeze and then kept fixed.
@@ -73,7 +73,7 @@ def ionic_du(u, w, P):
 
 
 def reaction_coefficient(u, w, P):
-    """C_r = c1 (u-a)(u-1) + c2 w (eq. (3.6)), the fixed-point reaction coefficient."""
+    """C_r = c1 (u-a)(u-1) + c2 w (eq. (3.8)), the fixed-point reaction coefficient."""
     return P.c1 * (u - P.a) * (u - 1.0) + P.c2 * w
 
 
@@ -96,7 +96,7 @@ def geometry_map(prob, l):
 
 
 def truncated_svd(A: np.ndarray, eps: float, max_rank: int = None):
-    """Smallest-rank R with ||A - U S V^T||_F <= eps ||A||_F (eq. (3.8)).
+    """Smallest-rank R with ||A - U S V^T||_F <= eps ||A||_F (eq. (3.9)).
     The tolerance alone fixes R; a caller that can only hold max_rank terms
     gets a ValueError when R exceeds it (the tolerance is never missed
     silently)."""
@@ -365,7 +365,7 @@ class SpaceTime:
         return F
 
     def reaction_at_quad(self, u_full, w_full):
-        """C_r(u_h, w_h) of eq. (3.6) at every space-time Gauss point (the
+        """C_r(u_h, w_h) of eq. (3.8) at every space-time Gauss point (the
         exact fixed-point reaction coefficient of the matrix M_R)."""
         return reaction_coefficient(self.ev(u_full, {}), self.ev(w_full, {}), self.P)
 
@@ -444,7 +444,7 @@ class SpaceTime:
         w = np.linalg.solve(Lt, G @ U)
         return self.full(w.reshape(-1))
 
-    # --------------------------------------------------------- theta (eq. 3.4)
+    # --------------------------------------------------------- theta (eq. 3.6)
     def element_windows(self, l: int, first: int):
         """For each full basis index j >= first in direction l, the element range
         [e0, e1) inside (xi_{j-p}, xi_{j+p+1}) (1-based paper indices, clamped)."""
@@ -461,7 +461,7 @@ class SpaceTime:
     def residual_at_quad(self, u_full, w_full):
         """The residual R = C_m u_t - sum_l sigma_l u_ll + I_ion(u, w) - f at every
         Gauss point and the denominator C_m (||u||_inf / T + ||u_t||_inf) of
-        eq. (3.4) (maxima over the Gauss points)."""
+        eq. (3.6) (maxima over the Gauss points)."""
         P, d = self.P, self.d
         uq = self.ev(u_full, {})
         wq = self.ev(w_full, {})
@@ -484,7 +484,7 @@ class SpaceTime:
         return np.repeat(self.sc_scale_t, int(np.prod(self.qshape[1:]))) * np.abs(R) / den
 
     def theta_grid(self, u_full, w_full):
-        """Theta of eq. (3.4) on the (X_t time) x (space) Greville grid: N_t x N_s."""
+        """Theta of eq. (3.6) on the (X_t time) x (space) Greville grid: N_t x N_s."""
         P, d = self.P, self.d
         R, den = self.residual_at_quad(u_full, w_full)
         # element-wise maxima of |R|

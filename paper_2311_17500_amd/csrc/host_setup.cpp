@@ -1,5 +1,5 @@
 // Host-side FP64 setup: univariate B-splines (Section 2), Galerkin matrices
-// (Section 3.1.1), SU coefficients tau_k (eq. (3.3)), fast-diagonalization
+// (Section 3.1.1), SU coefficients tau_k (eq. (3.5)), fast-diagonalization
 // factors (Section 3.2) and the gather tables of the GPU mode products.
 #include "host_setup.hpp"
 

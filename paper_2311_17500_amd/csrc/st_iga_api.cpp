@@ -2095,7 +2095,7 @@ void quad_pass(st_iga_ctx* c, const double* u, const double* w, bool want_res, b
   finish_uv_maxima(c, boff / 2, s);
 }
 
-// Theta grid (N_t x N_s) of eq. (3.4) into dst.
+// Theta grid (N_t x N_s) of eq. (3.6) into dst.
 void theta_grid(st_iga_ctx* c, const double* u, const double* w, double* dst, hipStream_t s, bool with_res = false) {
   const int d = c->d;
   quad_pass(c, u, w, with_res, true, s);

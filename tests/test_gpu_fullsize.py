@@ -203,7 +203,7 @@ def test_cfg2_lowp_operator_error(gpu_lib, torch, prec, bound_a, bound_p):
 
 @pytest.mark.timeout(900)
 def test_cfg2_linearization_full_theta(gpu_lib, torch):
-    """A linearization at a front-shaped state: every theta entry of eq. (3.4)
+    """A linearization at a front-shaped state: every theta entry of eq. (3.6)
     against the oracle's tensor evaluator, identical truncated-SVD ranks and
     products, and sampled rows of the residual N(u) (with the oracle's own
     theta factors)."""

@@ -298,7 +298,7 @@ def test_krylov_graph_replay(gpu_lib, torch, prec, reorth):
 
 @pytest.mark.parametrize("name,prob", [SMALL[1], SMALL[2]], ids=["2d_p3", "3d_p2"])
 def test_linearize_picard(gpu_lib, torch, name, prob):
-    """Picard linearization (reaction coefficient C_r of eq. (3.6)): ranks,
+    """Picard linearization (reaction coefficient C_r of eq. (3.8)): ranks,
     low-rank products and the operator against the oracle."""
     S = solver_for(prob, outer=1, alpha=0.5)
     st = SpaceTime(prob)
@@ -395,7 +395,7 @@ SRC = [("1d_ball", 1, 2, 1), ("2d_gauss", 2, 3, 2), ("3d_ball", 3, 2, 1), ("3d_g
 
 @pytest.mark.parametrize("name,d,p,kind", SRC, ids=[c[0] for c in SRC])
 def test_source_theta_and_residual(gpu_lib, torch, name, d, p, kind):
-    """Theta (residual -f inside eq. (3.4)) and N(u) (with -int f v) against
+    """Theta (residual -f inside eq. (3.6)) and N(u) (with -int f v) against
     the oracle on clustered time knots, at a non-trivial state."""
     prob, kn = _src_case(d, p, kind, nel=4 if d == 3 else 6, nel_t=10)
     st = SpaceTime(prob, knots=kn)

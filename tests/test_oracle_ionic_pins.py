@@ -5,10 +5,10 @@ or by calculus, not by retyping the oracle's formulas:
 * the Rogers-McCulloch current of eq. (3.1) vanishes at its three resting
   roots u = 0, a, 1 when w = 0, and is linear in w with slope c2 u;
 * dI_ion/du against a central difference of I_ion;
-* C_r of eq. (3.6) splits the current, C_r(u, w) u = I_ion(u, w) (the
+* C_r of eq. (3.8) splits the current, C_r(u, w) u = I_ion(u, w) (the
   fixed-point scheme of Section 3.1 moves exactly this factor to the
   unknown);
-* the residual inside Theta of eq. (3.4) against SymPy's
+* the residual inside Theta of eq. (3.6) against SymPy's
   C_m u_t - sum_l sigma_l u_ll + I_ion(u, w) - f, for splines that reproduce
   polynomials exactly (coefficients from SciPy's independent B-spline
   interpolation at the Greville points);
@@ -89,8 +89,8 @@ def _poly_state(st, expr_u, expr_w, syms):
 
 @pytest.mark.parametrize("d,p,with_f", [(1, 2, False), (2, 2, True), (2, 3, False), (3, 2, True)])
 def test_theta_numerator_against_sympy(d, p, with_f):
-    """Theta of eq. (3.4) from the residual evaluated symbolically at the Gauss points."""
-    # a short final time keeps the denominator of eq. (3.4) (which holds
+    """Theta of eq. (3.6) from the residual evaluated symbolically at the Gauss points."""
+    # a short final time keeps the denominator of eq. (3.6) (which holds
     # ||u||/T) large, so that Theta stays below its cap of 1 and the numerator
     # is visible
     T = 0.02
@@ -129,7 +129,7 @@ def test_theta_numerator_against_sympy(d, p, with_f):
     den = P.Cm * (np.abs(Uq).max() / P.T + np.abs(Utq).max())
     Th = st.theta_grid(uf, wf)
 
-    def window(l, j):          # support extension of eq. (2.2), 1-based j, clamped
+    def window(l, j):          # support extension of eq. (2.3), 1-based j, clamped
         kn, pp = st.kn[l], st.p[l]
         return kn[max(j - pp, 1) - 1], kn[min(j + pp + 1, len(kn)) - 1]
 

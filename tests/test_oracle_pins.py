@@ -101,7 +101,7 @@ def test_interior_stencils_closed_form(p):
         assert np.allclose(K[i, sl] * h, [-1, 2, -1])
 
 
-# ---------------------------------------------------------------- tau (eq. 3.3)
+# ---------------------------------------------------------------- tau (eq. 3.5)
 def test_tau_p1_is_half_h():
     """p_t = 1: tau_1 = h/2 (closed form; with T-scaled time h is physical)."""
     for T in (1.0, 300.0):
@@ -187,7 +187,7 @@ def test_explicit_apply_matches_assembly():
     assert np.allclose(st.assemble_J(cq, tq) @ x, st.apply_J(x, cq, tq), rtol=1e-13, atol=1e-13)
 
 
-# ---------------------------------------------------------------- low rank (eq. 3.8)
+# ---------------------------------------------------------------- low rank (eq. 3.9)
 def test_truncated_svd_eckart_young():
     """||A - A_R||_F <= eps ||A||_F and R is the smallest rank achieving it."""
     rng = np.random.default_rng(5)
@@ -215,10 +215,10 @@ def test_hat_interpolation():
     assert np.allclose((H @ f)[~inside], f[0])
 
 
-# ---------------------------------------------------------------- theta (eq. 3.4)
+# ---------------------------------------------------------------- theta (eq. 3.6)
 def test_theta_bruteforce_windows():
     """Theta entries recomputed by brute force: residual at the Gauss points whose
-    coordinates lie inside the support extension (eq. (2.2)), max, normalised."""
+    coordinates lie inside the support extension (eq. (2.3)), max, normalised."""
     P = W.tiny(2, 2, 4)
     st = SpaceTime(P)
     u, w = W.smooth_state(P, 7)
@@ -444,7 +444,7 @@ def test_source_residual_total():
 
 
 def test_source_theta_indicator():
-    """u = w = 0 with a localized source: R = -f, the denominator of eq. (3.4)
+    """u = w = 0 with a localized source: R = -f, the denominator of eq. (3.6)
     is 0, so Theta is 1 exactly on the windows that contain a Gauss point with
     f != 0 and 0 elsewhere (brute force over point coordinates)."""
     P = W.tiny(2, 2, 6, nel_t=6, u0_kind=0, f_kind=1, f_center=(0.2, 0.7, 0.0), f_radius=0.15,
@@ -483,7 +483,7 @@ def test_clustered_time_knots():
 # ---------------------------------------------------------------- fixed-point scheme of Section 3.1
 def test_picard_defect_identity():
     """A(u^k, w^k) u^k - F = N(u^k) on the test functions of X_h: with the exact
-    C_r of eq. (3.6) in M_R, C_r(u, w) u = I_ion(u, w) at every Gauss point, so
+    C_r of eq. (3.8) in M_R, C_r(u, w) u = I_ion(u, w) at every Gauss point, so
     the fixed-point matrix applied to its own linearization point reproduces
     the residual (the defect form the library solves)."""
     P = W.tiny(2, 2, 4, nel_t=5, f_kind=1, f_center=(0.2, 0.3, 0.0), f_radius=0.3, f_t0=0.2, f_t1=0.6,
