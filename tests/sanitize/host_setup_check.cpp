@@ -83,13 +83,27 @@ int main() {
           (void)DT;
           (void)E2;
         }
-        // time direction: tau and the fast-diagonalization data (maximal regularity only)
-        if (kind == 2) continue;
+        // time direction: the fast-diagonalization data, the SUPG streamline
+        // projection (any knots, repeated ones included) and tau (maximal
+        // regularity only)
         Dir1D T;
         std::string err;
         if (!build_dir(kn.data(), static_cast<int>(kn.size()), p, 2.0, p, T, err)) continue;
-        std::vector<double> tauq, coefs;
-        check(tau_at_quad(T, tauq, coefs, err), "tau_at_quad", p, nel);
+        if (kind != 2) {
+          std::vector<double> tauq, coefs;
+          check(tau_at_quad(T, tauq, coefs, err), "tau_at_quad", p, nel);
+        }
+        {
+          std::vector<double> tq(T.Q);
+          for (int q = 0; q < T.Q; ++q) tq[q] = (T.brk[q / T.nq + 1] - T.brk[q / T.nq]) / (2.0 * p + 1.0);
+          Gather SP = streamline_table_T(T, tq);
+          make_contiguous(SP, T.Q);
+          std::vector<double> Kt = gram1d(T, 1, 1, &tq), Wt = gram1d(T, 1, 0, &tq);
+          double sk = 0.0;
+          for (double v : Kt) sk += v;
+          check(std::fabs(sk) < 1e-9 * (1.0 + nel), "tau-weighted time stiffness kernel", p, nel);
+          (void)Wt;
+        }
         const int nt = T.n, Nt = nt - 1;
         if (Nt < 2) continue;
         std::vector<double> Wf = gram1d(T, 0, 1, nullptr), Mf = gram1d(T, 0, 0, nullptr);
