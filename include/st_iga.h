@@ -154,6 +154,17 @@ typedef struct {
   double sc_c;               /* shock-capturing constant c >= 0 of the su = 2 stabilization (the paper
                                 leaves it as a tuning parameter; h is in the time units of T, so the
                                 term scales with the square of the element length); 0 turns it off */
+  int32_t precond;           /* 0: the fast-diagonalization preconditioner of Section 3.2, eqs.
+                                (3.15)-(3.16) (arrowhead time core); 1: the same spatial fast
+                                diagonalization with an exact banded LU per spatial mode in time, whose
+                                time matrices also carry the time profiles (spatial means at each time
+                                Gauss point) of theta's SU term and of the reaction coefficient (floored
+                                at a*c1; needs a*c1 > 0 unless su = 2: the per-mode factorization has no
+                                pivoting) of the current linearization (refactorized at each
+                                linearization); it pays
+                                when the front fills a large part of the domain and not when it is
+                                localized (the spatial mean of theta is then near zero).  su = 2
+                                always uses 1. */
 } st_iga_options;
 
 #define ST_IGA_MAX_OUTER_LOG 64
@@ -177,7 +188,7 @@ typedef struct {
 /* Defaults: su=1, eps_theta=0.1, eps_react=1e-2, max_rank=48, outer=0,
  * alpha=1 (Newton), theta_freeze=1e-4, tol_nonlin=1e-10, tol_lin=1e-10,
  * inner_tol=1e-4, restart=30, max_outer=60, max_krylov=3000, prec=FP64, lin_forcing=0,
- * coef_slab=0, reorth=2, graphs=1, stall_cycles=10, stall_reduction=1e-3, picard_switch=0, sc_c=0.1. */
+ * coef_slab=0, reorth=2, graphs=1, stall_cycles=10, stall_reduction=1e-3, picard_switch=0, sc_c=0.1, precond=0. */
 void st_iga_default_options(st_iga_options* opt);
 
 /* Bytes of device workspace st_iga_setup needs for this problem/options

@@ -379,6 +379,45 @@ class SpaceTime:
         N_s = int(np.prod(self.n[:d]))
         return sp.csr_matrix(A)[N_s:, N_s:]
 
+    def precond_time_profiles(self, coef_q, theta_q):
+        """Time profiles of the banded preconditioner (not from the paper): at
+        each time Gauss point the spatial mean (Gauss-weighted) of the reaction
+        coefficient coef_q, floored at the shift a c1 of the fast
+        diagonalization, and of theta_q, floored at 0 (zero without SU)."""
+        Qt = self.qshape[0]
+        ws = np.array([1.0])
+        for a in range(1, self.d + 1):
+            ws = np.multiply.outer(ws, self.quad[self.dirs[a]][1])
+        ws = ws.reshape(-1)
+        c = np.maximum(np.asarray(coef_q).reshape(Qt, -1) @ ws / ws.sum(), self.P.a * self.P.c1)
+        th = (np.asarray(theta_q).reshape(Qt, -1) @ ws / ws.sum()) if (self.su and theta_q is not None) else np.zeros(Qt)
+        return c, np.maximum(th, 0.0)
+
+    def assemble_precond_profiles(self, c_t, th_t):
+        """Banded preconditioner of the Galerkin / SU system on X_h x X_h: the
+        bilinear form
+          int C_m u_t v + sum_l sigma_l int u_l v_l + int c(t) u v
+          + C_m sum_k int tau_k th(t) d^k_t u d^k_t v
+        with coefficients depending on time only (a Kronecker sum
+        A_t (x) M_s + M_t (x) K_s); c_t, th_t at the time Gauss points, the
+        weights tau_k th floored at 0."""
+        P, d, om = self.P, self.d, self.omega
+        Dg = sp.diags
+        Qs = int(np.prod(self.qshape[1:]))
+        cq, thq = np.repeat(c_t, Qs), np.repeat(th_t, Qs)
+        P0 = self.phi({})
+        A = P.Cm * P0.T @ Dg(om) @ self.phi({d: 1}) + P0.T @ Dg(om * cq) @ P0
+        for l in range(d):
+            Pl = self.phi({l: 1})
+            A = A + P.sigma[l] * Pl.T @ Dg(om) @ Pl
+        if self.su and np.any(th_t):
+            for k in range(1, P.p_t + 1):
+                tk = np.repeat(self.tau_q[k - 1], Qs)
+                Pk = self.phi({d: k})
+                A = A + Pk.T @ Dg(om * np.maximum(P.Cm * tk * thq, 0.0)) @ Pk
+        N_s = int(np.prod(self.n[:d]))
+        return sp.csr_matrix(A)[N_s:, N_s:]
+
     def precond_means(self, u_full, w_full):
         """Time profiles of the preconditioner of the SUPG system (not from the
         paper, which solves directly): at each time Gauss point the spatial

@@ -49,7 +49,7 @@ class Options(C.Structure):
                 ("restart", C.c_int32), ("max_outer", C.c_int32), ("max_krylov", C.c_int32), ("prec", C.c_int32),
                 ("lin_forcing", C.c_double), ("coef_slab", C.c_int32), ("reorth", C.c_int32),
                 ("graphs", C.c_int32), ("stall_cycles", C.c_int32), ("stall_reduction", C.c_double),
-                ("picard_switch", C.c_int32), ("sc_c", C.c_double)]
+                ("picard_switch", C.c_int32), ("sc_c", C.c_double), ("precond", C.c_int32)]
 
 
 LOG = 64

@@ -155,7 +155,12 @@ struct st_iga_ctx {
   // B = M_t + W_tau, A = C_m (W_t + K_t^tau) plus the reaction and
   // shock-capturing terms with their spatial means at each time Gauss point
   // (refactorized at every linearization)
-  std::vector<double> supgA0_full, band_B_h, tq_h, wsum_h;
+  bool banded = false;              // time part of the preconditioner: banded LU per spatial mode
+  std::vector<double> timeA0_full, band_B_h, tq_h, wsum_h;
+  // time profiles of the preconditioner at the time Gauss points: spatial
+  // means of the reaction coefficient, of the shock-capturing coefficient and
+  // of theta (empty: zero)
+  std::vector<double> prof_cr, prof_sc, prof_th;
   double *bandA_d = nullptr, *bandB_d = nullptr, *bandF_d = nullptr, *rowsum_d = nullptr;
   float* bandF_f = nullptr;
   // low-rank factors
@@ -240,6 +245,10 @@ void validate(const st_iga_problem* P, const st_iga_options* O) {
   if (O->su == 2 && O->outer != 2)
     throw Fail{ST_IGA_EINVAL, "SUPG + shock capturing (su = 2) runs in the fixed-point scheme (outer = 2)"};
   if (!(O->sc_c >= 0.0) || !std::isfinite(O->sc_c)) throw Fail{ST_IGA_EINVAL, "sc_c must be finite and >= 0"};
+  if (O->precond < 0 || O->precond > 1) throw Fail{ST_IGA_EINVAL, "precond must be 0 or 1"};
+  if (O->precond == 1 && O->su != 2 && !(P->a * P->c1 > 0.0))
+    throw Fail{ST_IGA_EINVAL, "the banded time solve (precond = 1) needs a reaction shift a*c1 > 0 "
+                              "(its factorization has no pivoting)"};
   if (O->su == 1) {  // SU needs C^{p_t - 1} in time: interior time multiplicity 1
     const double* k = P->knots[P->d];
     const int nk = P->nknots[P->d];
@@ -594,11 +603,18 @@ void host_setup(st_iga_ctx* c) {
     c->Wtau_x.h = banded_table(Wtau, nt, 1, Nt, pt);
     c->BtTs.h = streamline_table_T(T, tq);
     c->tq_h = tq;
-    c->supgA0_full = Wsum;
-    for (double& v : c->supgA0_full) v *= P.Cm;
+    c->timeA0_full = Wsum;
+    for (double& v : c->timeA0_full) v *= P.Cm;
     std::vector<double> Bf = c->Mt_full;
     for (size_t k = 0; k < Bf.size(); ++k) Bf[k] += Wtau[k];
     c->band_B_h = band_rows(Bf, nt, pt);
+  }
+  c->banded = c->supg || c->opt.precond == 1;
+  if (c->banded && !c->supg) {
+    // A = C_m W_t (+ the profile terms at each linearization), B = M_t
+    c->timeA0_full = c->Wt_full;
+    for (double& v : c->timeA0_full) v *= P.Cm;
+    c->band_B_h = band_rows(c->Mt_full, nt, pt);
   }
   c->Us_h.assign(P.d, {});
   c->lam_h.assign(P.d, {});
@@ -660,7 +676,7 @@ void host_setup(st_iga_ctx* c) {
   // the 1x1 (zero-frequency) time blocks of the arrowhead divide by the
   // spatial shift a c1 + sum_l sigma_l lambda_l; with a c1 = 0 the constant
   // Neumann mode makes it (numerically) zero
-  if (!c->supg && 2 * c->fd_np < Nt - 1) {   // (the SUPG preconditioner solves in time exactly)
+  if (!c->banded && 2 * c->fd_np < Nt - 1) {   // (the banded time solve needs no such split)
     double smin = INFINITY, smax = 0.0;
     for (double v : c->lam_s_h) {
       smin = std::min(smin, std::fabs(v));
@@ -828,12 +844,14 @@ void plan(st_iga_ctx* c) {
     c->Bts_d = a.get<double>(static_cast<int64_t>(c->Bts_h.size()));
     if (mixed) c->Bts_f = a.get<float>(static_cast<int64_t>(c->Bts_h.size()));
     c->scfac_d = a.get<double>(static_cast<int64_t>(c->scfac_h.size()));
+  }
+  if (c->banded) {
     const int64_t kw = 2 * c->P.p_t + 1;
     c->bandA_d = a.get<double>(c->Nt * kw);
     c->bandB_d = a.get<double>(c->Nt * kw);
     c->bandF_d = a.get<double>(c->Ns * c->Nt * kw);
     if (mixed) c->bandF_f = a.get<float>(c->Ns * c->Nt * kw);
-    c->rowsum_d = a.get<double>(2LL * c->dir[d].Q);
+    c->rowsum_d = a.get<double>(std::max<int64_t>(2LL * c->dir[d].Q, 2LL * c->maxR));
   }
   c->wq_s = a.get<double>(c->Qs);
   c->wq_t = a.get<double>(c->dir[d].Q);
@@ -1009,37 +1027,70 @@ void upload_all(st_iga_ctx* c, hipStream_t s) {
       up(keepf.back(), static_cast<const float*>(c->Bts_f), s);
     }
     up(c->scfac_h, static_cast<const double*>(c->scfac_d), s);
-    up(c->band_B_h, static_cast<const double*>(c->bandB_d), s);
   }
+  if (c->banded) up(c->band_B_h, static_cast<const double*>(c->bandB_d), s);
   CK(hipStreamSynchronize(s));
 }
 
-// Factorize the per-mode time matrices of the SUPG preconditioner with the
-// spatial means cr[g] of C_r (clipped at 0) and sc[g] of the shock-capturing
-// coefficient at the time Gauss points: A = C_m (W_t + K_t^tau) +
-// int cr b_j (b_i + tau b_i') + int sc b_j' b_i', T_j = A + lam_j B with lam_j
-// the spatial eigenvalue sums without the reaction shift.
-void supg_time_factor(st_iga_ctx* c, const std::vector<double>& cr, const std::vector<double>& sc, hipStream_t s) {
+// Factorize the per-mode time matrices T_j = A + lam_j B of the banded
+// preconditioner, lam_j the spatial eigenvalue sums without the reaction
+// shift, B = M_t (+ W_tau with SUPG) and
+//   A = C_m W_t + int max(cr, a c1) b_j b_i + sum_k int max(C_m tau_k th, 0) b_j^(k) b_i^(k)   (Galerkin / SU)
+//   A = C_m (W_t + K_t^tau) + int cr b_j (b_i + tau b_i') + int sc b_j' b_i'  (SUPG + SC)
+// with the time profiles cr (reaction coefficient, clipped at 0), th (theta)
+// and sc (shock capturing) at the time Gauss points (empty: zero).
+void time_factor(st_iga_ctx* c, hipStream_t s) {
   const Dir1D& T = c->dir[c->d];
   const int pt = c->P.p_t, nt = c->nt;
-  std::vector<double> crt(T.Q), sct(T.Q), crtau(T.Q);
-  for (int q = 0; q < T.Q; ++q) {
-    crt[q] = std::max(cr[q], 0.0);
-    crtau[q] = crt[q] * c->tq_h[q];
-    sct[q] = std::max(sc[q], 0.0);
+  auto prof = [&](const std::vector<double>& v, int q) { return v.empty() ? 0.0 : std::max(v[q], 0.0); };
+  // the factorization has no pivoting: its symmetric part must stay positive
+  // definite.  SUPG's tau K_t term ensures that; otherwise the reaction
+  // profile is floored at the shift a c1 of the fast diagonalization (> 0,
+  // checked at setup) and the theta terms at 0
+  const double floor_cr = c->supg ? 0.0 : c->P.a * c->P.c1;
+  std::vector<double> crt(T.Q);
+  for (int q = 0; q < T.Q; ++q) crt[q] = std::max(prof(c->prof_cr, q), floor_cr);
+  std::vector<double> A = c->timeA0_full;
+  auto add = [&](const std::vector<double>& G) {
+    for (size_t k = 0; k < A.size(); ++k) A[k] += G[k];
+  };
+  add(gram1d(T, 0, 0, &crt));
+  if (c->supg) {
+    std::vector<double> crtau(T.Q), sct(T.Q);
+    for (int q = 0; q < T.Q; ++q) {
+      crtau[q] = crt[q] * c->tq_h[q];
+      sct[q] = prof(c->prof_sc, q);
+    }
+    add(gram1d(T, 1, 0, &crtau));
+    add(gram1d(T, 1, 1, &sct));
+  } else if (c->opt.su == 1 && !c->prof_th.empty()) {
+    for (int k = 1; k <= pt; ++k) {
+      std::vector<double> wk(T.Q);
+      for (int q = 0; q < T.Q; ++q)
+        wk[q] = std::max(c->P.Cm * c->tauq[static_cast<size_t>(k - 1) * T.Q + q] * prof(c->prof_th, q), 0.0);
+      add(gram1d(T, k, k, &wk));
+    }
   }
-  std::vector<double> A = c->supgA0_full;
-  const std::vector<double> R0 = gram1d(T, 0, 0, &crt), R1 = gram1d(T, 1, 0, &crtau), Sc = gram1d(T, 1, 1, &sct);
-  for (size_t k = 0; k < A.size(); ++k) A[k] += R0[k] + R1[k] + Sc[k];
   const std::vector<double> band = band_rows(A, nt, pt);
   CK(hipMemcpyAsync(c->bandA_d, band.data(), band.size() * sizeof(double), hipMemcpyHostToDevice, s));
   if (!band_factor(c->bandA_d, c->bandB_d, c->Nt, c->lam_d, c->P.a * c->P.c1, c->Ns, pt, c->bandF_d, s))
-    throw Fail{ST_IGA_EINVAL, "SUPG preconditioner: time degree above 5"};
+    throw Fail{ST_IGA_EINVAL, "banded preconditioner: time degree above 5"};
   const int64_t nf = c->Ns * c->Nt * (2 * pt + 1);
   if (c->bandF_f) convert<double, float>(c->bandF_d, c->bandF_f, nf, s);
   // the host vectors above are released on return: wait for the upload
   CK(hipStreamSynchronize(s));
   check_launch();
+}
+
+// Total Gauss weight of the spatial domain (its measure).
+double space_volume(const st_iga_ctx* c) {
+  double vol = 1.0;
+  for (int l = 0; l < c->d; ++l) {
+    double sw = 0.0;
+    for (double w : c->dir[l].wq) sw += w;
+    vol *= sw;
+  }
+  return vol;
 }
 
 // ------------------------------------------------------------------ operators
@@ -1305,8 +1356,8 @@ void precond_impl(st_iga_ctx* c, const S* r, S* z, Bufs<S>& B, hipStream_t s) {
   const C* lam = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->lam_d) : reinterpret_cast<const C*>(c->lam_f);
   const C* mu = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->mu_d) : reinterpret_cast<const C*>(c->mu_f);
   const C* l = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->l_d) : reinterpret_cast<const C*>(c->l_f);
-  if (c->supg) {
-    // SUPG: exact banded solve per spatial mode in time
+  if (c->banded) {
+    // exact banded solve per spatial mode in time
     const C* F = std::is_same<C, double>::value ? reinterpret_cast<const C*>(c->bandF_d)
                                                 : reinterpret_cast<const C*>(c->bandF_f);
     if (!band_solve<S, C>(F, Nt, Ns, c->P.p_t, a, b, s)) throw Fail{ST_IGA_EINVAL, "time degree above 5"};
@@ -2226,6 +2277,21 @@ void rebuild_coefficients(st_iga_ctx* c, hipStream_t s) {
   }
   scale_rows(c->Psi, Rt, c->Qs, c->wq_s, s);
   if (c->Psi_f) convert<double, float>(c->Psi, c->Psi_f, static_cast<int64_t>(Rt) * c->Qs, s);
+  // banded preconditioner: spatial means of the low-rank spatial factors
+  // (Psi carries the Gauss weights), for the time profiles of theta and of
+  // the reaction coefficient
+  std::vector<double> psibar(static_cast<size_t>(std::max(Rt, 1)), 0.0);
+  if (c->banded && Rt > 0) {
+    row_sums(c->Psi, Rt, c->Qs, c->rowsum_d, s);
+    CK(hipMemcpyAsync(psibar.data(), c->rowsum_d, Rt * sizeof(double), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    const double vol = space_volume(c);
+    for (double& v : psibar) v /= vol;
+  }
+  if (c->banded) {
+    if (c->opt.su == 1) c->prof_th.assign(T.Q, 0.0);
+    if (!c->exact_react) c->prof_cr.assign(T.Q, 0.0);
+  }
   // time tables
   std::vector<double> nodes(T.grev.begin() + 1, T.grev.end());
   std::vector<int> left;
@@ -2238,12 +2304,14 @@ void rebuild_coefficients(st_iga_ctx* c, hipStream_t s) {
     const std::vector<double>& U = set == 0 ? c->Uth_h : c->Uc_h;
     const std::vector<double>& sv = set == 0 ? c->sth_h : c->sc_h;
     const int roff = set == 0 ? 0 : c->Rth;
+    std::vector<double>* prof = !c->banded ? nullptr : set == 0 ? &c->prof_th : (c->exact_react ? nullptr : &c->prof_cr);
     for (int r = 0; r < R; ++r) {
       double* Trr = &Tr[static_cast<size_t>(roff + r) * NtP * WB];
       for (int q = 0; q < T.Q; ++q) {
         const int g0 = left[q];
         const int g1 = std::min(g0 + 1, Nt - 1);
         const double phi = wl[q] * U[static_cast<size_t>(g0) * R + r] + (1.0 - wl[q]) * U[static_cast<size_t>(g1) * R + r];
+        if (prof && !prof->empty()) (*prof)[q] += sv[r] * phi * psibar[roff + r];
         const int f = T.first[q];
         for (int a = 0; a <= pt; ++a) {
           const int i = f + a;             // full row index
@@ -2272,6 +2340,7 @@ void rebuild_coefficients(st_iga_ctx* c, hipStream_t s) {
   CK(hipMemcpyAsync(c->Tr_f, Trf.data(), Trf.size() * sizeof(float), hipMemcpyHostToDevice, s));
   CK(hipStreamSynchronize(s));
   check_launch();
+  if (c->banded) time_factor(c, s);
   c->linearized = true;
 }
 
@@ -2319,7 +2388,7 @@ void linearize(st_iga_ctx* c, const double* u, const double* w, bool refresh_the
       sc_scale(c->Rq_d, c->scfac_d, c->dsc + 300, c->P.Cm, 1.0 / c->P.T, c->Qs, nq, s);
       if (c->Rq_f) convert<double, float>(c->Rq_d, c->Rq_f, nq, s);
     }
-    if (c->supg) {
+    if (c->banded) {
       // spatial means of C_r and of the shock-capturing coefficient at each
       // time Gauss point (Cq and Rq carry the Gauss weights)
       const Dir1D& T = c->dir[c->d];
@@ -2329,18 +2398,13 @@ void linearize(st_iga_ctx* c, const double* u, const double* w, bool refresh_the
       CK(hipMemcpyAsync(sums.data(), c->rowsum_d, (c->sc_on ? 2 : 1) * T.Q * sizeof(double), hipMemcpyDeviceToHost,
                         s));
       CK(hipStreamSynchronize(s));
-      double vol = 1.0;
-      for (int l = 0; l < c->d; ++l) {
-        double sw = 0.0;
-        for (double w : c->dir[l].wq) sw += w;
-        vol *= sw;
-      }
-      std::vector<double> cr(T.Q), sc(T.Q);
+      const double vol = space_volume(c);
+      c->prof_cr.assign(T.Q, 0.0);
+      c->prof_sc.assign(T.Q, 0.0);
       for (int q = 0; q < T.Q; ++q) {
-        cr[q] = sums[q] / (T.wq[q] * vol);
-        sc[q] = sums[T.Q + q] / (T.wq[q] * vol);
+        c->prof_cr[q] = sums[q] / (T.wq[q] * vol);
+        c->prof_sc[q] = sums[T.Q + q] / (T.wq[q] * vol);
       }
-      supg_time_factor(c, cr, sc, s);
     }
     c->Rc = 0;
     c->err_c = 0.0;
@@ -2467,6 +2531,7 @@ void st_iga_default_options(st_iga_options* o) {
   o->stall_reduction = 1e-3;
   o->picard_switch = 0;
   o->sc_c = 0.1;
+  o->precond = 0;
   o->prec = ST_IGA_FP64;
   o->lin_forcing = 0.0;
   o->coef_slab = 0;
@@ -2512,11 +2577,13 @@ st_iga_status st_iga_setup(const st_iga_problem* prob, const st_iga_options* opt
     c->ar.dry = false;
     plan(c.get());
     upload_all(c.get(), s);
-    if (c->supg) {
+    if (c->banded) {
       // before the first linearization: the shift a c1 of the fast
-      // diagonalization as reaction, no shock capturing
-      const int Q = c->dir[c->d].Q;
-      supg_time_factor(c.get(), std::vector<double>(Q, c->P.a * c->P.c1), std::vector<double>(Q, 0.0), s);
+      // diagonalization as reaction, no theta and no shock capturing
+      c->prof_cr.assign(c->dir[c->d].Q, c->P.a * c->P.c1);
+      c->prof_sc.clear();
+      c->prof_th.clear();
+      time_factor(c.get(), s);
     }
     for (int l = 0; l < 4; ++l) c->P.knots[l] = nullptr;
     CK(hipGetDevice(&c->device));

@@ -68,7 +68,7 @@ def test_cfg1_theta_grid(gpu_lib, torch, cfg1):
 
 def test_cfg1_apply_precond_krylov(gpu_lib, torch, cfg1):
     prob, st = cfg1
-    S = make(prob)
+    S = make(prob, precond=0)   # the fast diagonalization of Section 3.2 (A-hat below)
     ft, fc = W.random_factors(prob, 3, 4), W.random_factors(prob, 4, 5, scale=5.0)
     S.set_factors(ft, fc)
     thq = st.lowrank_at_quad(LowRank(*ft))
@@ -250,7 +250,7 @@ def test_cfg4_apply_precond_sampled_rows(gpu_lib, torch, cfg4, prec):
     FP32 unit roundoff of the largest entry."""
     from paper_2311_17500_amd.binding import FP64, MIXED_FP32
     prob, rs = cfg4
-    S = make(prob, prec={"fp64": FP64, "mixed_fp32": MIXED_FP32}[prec], max_rank=16)
+    S = make(prob, prec={"fp64": FP64, "mixed_fp32": MIXED_FP32}[prec], max_rank=16, precond=0)
     ft, fc = W.random_factors(prob, 2, 41), W.random_factors(prob, 3, 42, scale=5.0)
     S.set_factors(ft, fc)
     x = W.random_vector(prob.unknowns, 43)

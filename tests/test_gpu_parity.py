@@ -96,12 +96,16 @@ def test_apply_with_given_factors(gpu_lib, torch, name, prob):
     assert rel(y, st.apply_J(x, cq, thq)) < 1e-12
 
 
+@pytest.mark.parametrize("precond", [0, 1], ids=["fd_sec32", "banded"])
 @pytest.mark.parametrize("name,prob", SMALL[:6], ids=[n for n, _ in SMALL[:6]])
-def test_precond(gpu_lib, torch, name, prob):
-    """z = A-hat^{-1} r against the oracle's direct solve.  Both are backward
-    stable, so they differ by a few times cond(A-hat) times the unit roundoff
-    (cond = 2.2e5 for the 3D p = 3 case, <= 1e4 for the others)."""
-    S = solver_for(prob)
+def test_precond(gpu_lib, torch, name, prob, precond):
+    """z = A-hat^{-1} r against the oracle's direct solve, for the fast
+    diagonalization of Section 3.2 and for the banded time solve (before any
+    linearization its time profiles are the shift a c1 and no theta, so it
+    inverts the same A-hat).  Both are backward stable, so they differ by a
+    few times cond(A-hat) times the unit roundoff (cond = 2.2e5 for the 3D
+    p = 3 case, <= 1e4 for the others)."""
+    S = solver_for(prob, precond=precond)
     st = SpaceTime(prob)
     r = W.random_vector(prob.unknowns, 13)
     z = S.precond(to_dev(torch, r)).cpu().numpy()
@@ -364,15 +368,19 @@ def test_zero_shift_preconditioner(gpu_lib, torch):
     odd = W.tiny(1, 2, 9, nel_t=7, c1=0.0)
     assert (odd.N_t - 1) % 2 == 1
     with pytest.raises(StIgaError) as e:
-        solver_for(odd)
+        solver_for(odd, precond=0)
     assert e.value.code == EINVAL
     even = W.tiny(1, 2, 9, nel_t=6, c1=0.0)
     assert (even.N_t - 1) % 2 == 0
-    S = solver_for(even)
+    S = solver_for(even, precond=0)
     st = SpaceTime(even)
     r = W.random_vector(even.unknowns, 31)
     z = S.precond(to_dev(torch, r)).cpu().numpy()
     assert rel(z, solver.precond_solve(st, r)) < 1e-10
+    # the banded time solve factorizes without pivoting and needs a c1 > 0
+    with pytest.raises(StIgaError) as e:
+        solver_for(even, precond=1)
+    assert e.value.code == EINVAL
 
 
 # Source-term stimuli of the paper's experiments (Section 4): a ball times a
@@ -495,6 +503,35 @@ def test_galerkin_solve(gpu_lib, outer):
     assert rel(w.cpu().numpy(), wo) < 1e-10
 
 
+@pytest.mark.parametrize("outer", [0, 2])
+@pytest.mark.parametrize("name,prob", [SMALL[0], SMALL[1], SMALL[2], SMALL[5]], ids=["1d_p2", "2d_p3", "3d_p2", "3d_p3"])
+def test_banded_precond_after_linearization(gpu_lib, torch, name, prob, outer):
+    """The banded preconditioner after a linearization: time profiles of
+    theta and of the reaction coefficient (low rank for Newton, exact C_r for
+    the Section 3.1 scheme) in the time matrices, against a sparse LU of the
+    oracle's assembly of the same form; FP32 in a mixed context."""
+    import scipy.sparse.linalg as spla
+    from paper_2311_17500_amd.binding import MIXED_FP32
+    st = SpaceTime(prob)
+    u, w = W.smooth_state(prob, 44)
+    if outer == 0:
+        lin = solver.linearize(st, u, w)
+        coef_q, theta_q = lin.coef_q, lin.theta_q
+    else:
+        coef_q = st.reaction_at_quad(u, w)
+        theta_q = st.lowrank_at_quad(st.lowrank(st.theta_grid(u, w), 0.1))
+    c_t, th_t = st.precond_time_profiles(coef_q, theta_q)
+    assert np.max(th_t) > 0.0
+    want_A = st.assemble_precond_profiles(c_t, th_t)
+    S = solver_for(prob, prec=MIXED_FP32, outer=outer, alpha=1.0 if outer == 0 else 0.5, precond=1)
+    S.linearize(to_dev(torch, u), to_dev(torch, w))
+    r = W.random_vector(prob.unknowns, 45)
+    want = spla.splu(want_A.tocsc()).solve(r)
+    rd = to_dev(torch, r)
+    assert rel(S.precond(rd).cpu().numpy(), want) < 1e-10
+    assert rel(S.precond_lowp(rd).cpu().numpy(), want) < 1e-4
+
+
 def test_galerkin_mixed_no_low_rank(gpu_lib, torch):
     """A mixed-precision context with no low-rank terms at all (Galerkin, exact
     C_r): the empty factor tables are skipped, the FP32 operator matches."""
@@ -550,14 +587,15 @@ def test_newton_to_picard_switch(gpu_lib):
     assert rel(w.cpu().numpy(), wo) < 1e-10
 
 
+@pytest.mark.parametrize("precond", [0, 1], ids=["fd_sec32", "banded"])
 @pytest.mark.parametrize("name,prob", SMALL[:6], ids=[n for n, _ in SMALL[:6]])
-def test_precond_bf16_mfma(gpu_lib, torch, name, prob):
+def test_precond_bf16_mfma(gpu_lib, torch, name, prob, precond):
     """BF16 mode: the eigenvector mode products run on the BF16 MFMA with
     FP32 accumulation (BF16 vectors and matrices).  Against the oracle's
     direct solve the error is a small multiple of the BF16 unit roundoff
     (3.9e-3) times the conditioning of the eigenvector bases."""
     from paper_2311_17500_amd.binding import MIXED_BF16
-    S = solver_for(prob, prec=MIXED_BF16)
+    S = solver_for(prob, prec=MIXED_BF16, precond=precond)
     st = SpaceTime(prob)
     r = W.random_vector(prob.unknowns, 33)
     z = S.precond_lowp(to_dev(torch, r)).cpu().numpy()
@@ -581,7 +619,7 @@ def test_geometry_linearization_and_operators(gpu_lib, torch, name, prob):
     points), the linearized operator, the FD preconditioner built from the
     mapped 1D pencils against the oracle's direct solve, and the residual."""
     st = SpaceTime(prob)
-    S = solver_for(prob)
+    S = solver_for(prob, precond=0)
     c0, cnt = S.lift()
     assert np.array_equal(c0, st.lift()) and cnt > 0
     u, w = W.smooth_state(prob, 14)

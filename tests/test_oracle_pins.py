@@ -605,3 +605,60 @@ def test_geometry_manufactured_rate(p):
         errs.append(np.sqrt(np.sum(wt * (uh - ex) ** 2) / np.sum(wt * ex ** 2)))
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert rates[-1] > p + 1 - 0.35, (errs, rates)
+
+
+# ------------------------------------------------ banded preconditioner (not from the paper)
+def test_banded_precond_reduces_to_fast_diagonalization_operator():
+    """With c = a c1 and no theta the banded preconditioner's form is A-hat of
+    Section 3.2 (assembled independently by assemble_precond)."""
+    P = W.tiny(2, 2, 5, nel_t=5)
+    st = SpaceTime(P)
+    Qt = st.qshape[0]
+    A = st.assemble_precond_profiles(np.full(Qt, P.a * P.c1), np.zeros(Qt))
+    B = st.assemble_precond()
+    assert abs(A - B).max() <= 1e-13 * abs(B).max()
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_banded_precond_is_kronecker(d):
+    """A_t (x) M_s + M_t (x) K_s with the time matrix built from SciPy's
+    B-spline basis and the oracle's tau_k at the time Gauss points:
+    A_t = C_m W_t + int c b b + C_m sum_k int tau_k th b^(k) b^(k)."""
+    from scipy.interpolate import BSpline
+    P = W.tiny(d, 3, 4, nel_t=5)
+    kn = P.uniform_knots()
+    st = SpaceTime(P, knots=kn)
+    Qt = st.qshape[0]
+    rng = np.random.default_rng(d + 7)
+    c_t, th_t = rng.uniform(0.0, 2.0, Qt), rng.uniform(0.0, 0.8, Qt)
+    A = st.assemble_precond_profiles(c_t, th_t).toarray()
+
+    def basis(kv, p, x, der):
+        n = len(kv) - p - 1
+        B = BSpline(kv, np.eye(n), p, extrapolate=False)
+        return np.nan_to_num((B.derivative(der) if der else B)(x))
+
+    Tk = P.T * np.asarray(kn[d])
+    tq, tw, _ = st.quad[d]
+    g = lambda wt, X, Y: X.T @ (wt[:, None] * Y)
+    b = [basis(Tk, P.p_t, tq, k) for k in range(P.p_t + 1)]
+    At = P.Cm * g(tw, b[0], b[1]) + g(tw * c_t, b[0], b[0])
+    for k in range(1, P.p_t + 1):
+        At = At + g(tw * np.maximum(P.Cm * st.tau_q[k - 1] * th_t, 0.0), b[k], b[k])
+    Mt = g(tw, b[0], b[0])
+    Ms, Ks = [], []
+    for l in range(d):
+        z = np.unique(kn[l])
+        gg, ww = np.polynomial.legendre.leggauss(P.p_s + 2)
+        x = np.concatenate([0.5 * (a0 + a1) + 0.5 * (a1 - a0) * gg for a0, a1 in zip(z[:-1], z[1:])])
+        w = np.concatenate([0.5 * (a1 - a0) * ww for a0, a1 in zip(z[:-1], z[1:])])
+        B0, B1 = basis(kn[l], P.p_s, x, 0), basis(kn[l], P.p_s, x, 1)
+        Ms.append(g(w, B0, B0))
+        Ks.append(g(w, B1, B1))
+    if d == 1:
+        M, K = Ms[0], P.sigma[0] * Ks[0]
+    else:
+        M = np.kron(Ms[1], Ms[0])
+        K = P.sigma[0] * np.kron(Ms[1], Ks[0]) + P.sigma[1] * np.kron(Ks[1], Ms[0])
+    want = np.kron(At[1:, 1:], M) + np.kron(Mt[1:, 1:], K)
+    assert np.max(np.abs(A - want)) <= 1e-12 * np.max(np.abs(want))

@@ -24,8 +24,8 @@ def test_precond_noalloc_matches_precond(gpu_lib):
     big = W.tiny(2, 3, 12, nel_t=10)     # 15^2 x 12 = 2700 unknowns
     small = W.tiny(1, 2, 9, nel_t=6)     # 11 x 7 = 77 unknowns
     assert big.unknowns > small.unknowns
-    for seed, prob in ((41, big), (42, small)):
-        S = Solver(prob)
+    for seed, prob, precond in ((41, big, 1), (42, small, 1), (43, big, 0), (44, small, 0)):
+        S = Solver(prob, precond=precond)
         r = _dev(torch, W.random_vector(prob.unknowns, seed))
         z_ref = S.precond(r)
         z = S.vec()
