@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the extra workloads (config 2 in BF16, config 4 mixed FP32) of the default line")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--precond", type=int, default=0, choices=[0, 1],
+                    help="0: fast diagonalization (Sec. 3.2); 1: banded time solve per spatial mode")
     ap.add_argument("--max-rank", type=int, default=None,
                     help="cap of each low rank (default 48; 16 for config 4 to fit HBM)")
     ap.add_argument("--serve", action="store_true", help="run only the serving stream (512 requests)")
@@ -253,14 +255,14 @@ def cpu_baseline(cfg):
                        f"({prob.dof} DOF) in {dt:.2f} s; splu is single-threaded, BLAS pool {cores}")}
 
 
-def bench_config(torch, W, cfg, precs, steps, warmup, tol, max_rank, solve_only_too):
+def bench_config(torch, W, cfg, precs, steps, warmup, tol, max_rank, solve_only_too, precond=0):
     """Time one workload in the given precisions at the fixed state u^1 (one
     FP64 Newton step from the lifted datum).  One large context at a time."""
     import numpy as np
     from paper_2311_17500_amd.binding import Solver, FP64, MIXED_FP32, MIXED_BF16
     prob = W.config(cfg)
     codes = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}
-    S64 = Solver(prob, prec=FP64, tol_lin=tol, max_rank=max_rank)
+    S64 = Solver(prob, prec=FP64, tol_lin=tol, max_rank=max_rank, precond=precond)
     c0, _ = S64.lift()
     u0 = torch.tensor(np.tile(c0, prob.n_t), dtype=torch.float64, device="cuda:0")
     u1, w = S64.vec(S64.full), S64.vec(S64.full)
@@ -297,7 +299,7 @@ def bench_config(torch, W, cfg, precs, steps, warmup, tol, max_rank, solve_only_
                 S64.close()
                 S64.ws = None
                 torch.cuda.empty_cache()
-            S = Solver(prob, prec=codes[prec], tol_lin=tol, max_rank=max_rank)
+            S = Solver(prob, prec=codes[prec], tol_lin=tol, max_rank=max_rank, precond=precond)
         ms, wall, its, rr, prof = time_region(torch, S, u1, u2, w, steps, warmup, tol)
         r = dict(ms=ms, wall=wall, its=its, rr=rr, prof=prof)
         log(f"config {cfg} {prec} Newton steps timed: {ms:.1f} ms")
@@ -443,7 +445,7 @@ def main():
     if a.max_rank is None:
         a.max_rank = 16 if a.config == 4 else 48
     precs = [a.prec] if (a.prec == "fp64" or a.no_fp64_compare) else ["fp64", a.prec]
-    prob, res = bench_config(torch, W, a.config, precs, a.steps, a.warmup, a.tol, a.max_rank, True)
+    prob, res = bench_config(torch, W, a.config, precs, a.steps, a.warmup, a.tol, a.max_rank, True, a.precond)
     main_r = res[a.prec]
     ms = main_r["ms"]
     value = prob.dof / (ms / 1e3)
@@ -459,7 +461,8 @@ def main():
                                f"{'x'.join(map(str, prob.nel_s))}x{prob.nel_t} elements, "
                                f"{prob.dof} DOF ({prob.unknowns} unknowns), {a.prec}",
                    "dof": prob.dof, "unknowns": prob.unknowns, "precision": a.prec,
-                   "tol": a.tol, "step": "one Newton iteration (linearize + residual + FGMRES/FD to 1e-8)"},
+                   "tol": a.tol, "precond": ["fast diagonalization", "banded time"][a.precond],
+                   "step": "one Newton iteration (linearize + residual + FGMRES/FD to 1e-8)"},
         "krylov_iters_per_step": main_r["its"][0], "final_relres": main_r["rr"][-1],
         "wall_ms_per_step": main_r["wall"],
         "roofline": roof,
