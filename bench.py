@@ -70,7 +70,7 @@ def serving(n_requests, slots):
     from paper_2311_17500_amd.serve import Server, summarize
     reqs = W.serve_stream(512, 0)[:n_requests]
     # banded time preconditioner: on these 2D requests (up to 131 time
-    # layers) it cuts the Krylov iterations by 1.1x to 2.9x
+    # layers) it cuts the Krylov iterations by 1.1x to 3.8x
     srv = Server(slots=slots, prec=MIXED_FP32, tol_lin=1e-8, tol_nonlin=1e-8, lin_forcing=0.1, precond=1)
     recs = srv.run(reqs)
     out = summarize(recs)
