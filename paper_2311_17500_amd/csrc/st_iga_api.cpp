@@ -117,6 +117,10 @@ struct st_iga_ctx {
     bf16* b = nullptr;     // BF16 copy (BF16 mode: the mode products run on the BF16 MFMA)
     int n = 0, npad = 0;
   } DUsT[3], DUs[3], DUtT, DUt;
+  // the w-update as one dense product along time (FP64 MFMA): the n_t x n_t
+  // matrix whose first row (the initial layer, w = 0) is zero; set when
+  // n_t <= 144, else the update runs as a table gather
+  Dense DEw;
   // device data
   double *lam_d = nullptr, *mu_d = nullptr, *l_d = nullptr;
   float *lam_f = nullptr, *mu_f = nullptr, *l_f = nullptr;
@@ -717,6 +721,14 @@ void host_setup(st_iga_ctx* c) {
     for (int r = 0; r < Nt; ++r)
       for (int k = 0; k < nt; ++k) R[static_cast<size_t>(r) * nt + k] /= L[static_cast<size_t>(r) * Nt + r];
     c->Ew.h = dense_table(R, Nt, nt, false);
+    if (nt <= 144) {
+      st_iga_ctx::Dense& D = c->DEw;
+      D.n = nt;
+      D.npad = 16 * ((nt + 15) / 16);
+      D.h.assign(static_cast<size_t>(D.npad) * D.npad, 0.0);
+      for (int r = 0; r < Nt; ++r)
+        for (int k = 0; k < nt; ++k) D.h[static_cast<size_t>(r + 1) * D.npad + k] = R[static_cast<size_t>(r) * nt + k];
+    }
   }
   // chunking of the quadrature pass: arrays per time Gauss point row
   // contiguous windows for the sweep kernels
@@ -802,6 +814,7 @@ void plan(st_iga_ctx* c) {
     c->qf_wd = a.get<double>(static_cast<int64_t>(c->qf_wd_h.size()));
   }
   T(c->Mt_x); T(c->Wt_x); T(c->Bt0); T(c->Bt1); T(c->BtT); T(c->Gt); T(c->Ut); T(c->UtT); T(c->Ew);
+  if (c->DEw.npad) c->DEw.d = a.get<double>(static_cast<int64_t>(c->DEw.npad) * c->DEw.npad);
   for (st_iga_ctx::Dense* D : {&c->DUt, &c->DUtT, &c->DUs[0], &c->DUs[1], &c->DUs[2], &c->DUsT[0], &c->DUsT[1],
                                &c->DUsT[2]}) {
     if (D->npad == 0) continue;
@@ -952,6 +965,7 @@ void upload_all(st_iga_ctx* c, hipStream_t s) {
     up(c->qf_win_h, static_cast<const double*>(c->qf_win), s);
     up(c->qf_wd_h, static_cast<const double*>(c->qf_wd), s);
   }
+  if (c->DEw.npad) up(c->DEw.h, static_cast<const double*>(c->DEw.d), s);
   for (st_iga_ctx::Dense* D : {&c->DUt, &c->DUtT, &c->DUs[0], &c->DUs[1], &c->DUs[2], &c->DUsT[0], &c->DUsT[1],
                                &c->DUsT[2]}) {
     if (D->npad == 0) continue;
@@ -2431,8 +2445,13 @@ void residual(st_iga_ctx* c, const double* u, const double* w, double* r, hipStr
 }
 
 void w_update(st_iga_ctx* c, const double* u, double* w, hipStream_t s) {
-  fill(w, 0.0, c->Ns, s);
-  gather<double, double, double>(c->Ew.d, u, w + c->Ns, 1, c->Ns, c->nt, 0, 1.0, 0.0, s);
+  if (c->DEw.d) {
+    // one pass over u and w (the gather re-reads every input layer per output layer)
+    dense_mode<double, double>(c->DEw.d, c->nt, c->DEw.npad, u, w, 1, c->Ns, s);
+  } else {
+    fill(w, 0.0, c->Ns, s);
+    gather<double, double, double>(c->Ew.d, u, w + c->Ns, 1, c->Ns, c->nt, 0, 1.0, 0.0, s);
+  }
   check_launch();
 }
 
