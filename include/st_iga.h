@@ -274,11 +274,13 @@ st_iga_status st_iga_precond_lowp(st_iga_ctx* ctx, const double* r, double* z, v
 st_iga_status st_iga_residual(st_iga_ctx* ctx, const double* u, const double* w, double* r,
                               void* stream);
 
-/* w-update of Section 3.2: solves L w = g(u) (full vectors; w layer 0 = 0). */
+/* w-update of Section 3.2: solves L w = g(u) (full vectors; w layer 0 = 0;
+ * u and w must not overlap). */
 st_iga_status st_iga_w_update(st_iga_ctx* ctx, const double* u, double* w, void* stream);
 
 /* Solve J_k x = b (device, unknown-sized) with right-preconditioned FGMRES
- * (FP64 Arnoldi with re-orthogonalization and Givens rotations); in mixed
+ * (FP64 Arnoldi with re-orthogonalization; the Givens rotations and the
+ * least-squares solve run on the device in FP64); in mixed
  * precision, inner FGMRES solves with low-precision apply/precond inside an
  * FP64 iterative refinement on the true residual.  x is overwritten (zero
  * initial guess).  Stops at ||b - J x|| <= tol ||b|| (FP64 true residual).

@@ -1763,6 +1763,130 @@ __device__ double block_max(double v, double* sh) {
   return r;
 }
 
+// ---------------------------------------------------------------- FGMRES Givens rotations
+// The small serial part of an Arnoldi step, fused with the reduction that
+// finishes |w'|^2 (one block): the Hessenberg column updates of the delayed
+// Gram-Schmidt scheme and the Givens rotations that turn the Hessenberg
+// matrix into R and the start residual into g, so that |g[k+1]| is the
+// residual estimate after k + 1 steps.  The block stages the rotations, the
+// step's dots and the stored raw column j - 1 in LDS; one lane then runs the
+// rotation chain (the running entry of the column in a register) and writes
+// back.  Plain FP64 arithmetic without contraction into fused multiply-adds.
+__global__ void __launch_bounds__(TPB) k_norm_givens(const double* __restrict__ part, int nb, double* __restrict__ D,
+                                                     double* __restrict__ G, GivensLayout L, int m, int j) {
+#pragma clang fp contract(off)
+  __shared__ double sh[TPB / 64];
+  __shared__ double lcs[64], lsn[64], dd[128], colA[66], colB[66], misc[2];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += TPB) acc += part[b];
+  const double w2 = block_sum(acc, sh);   // as k_finalize_sum with k = 1
+  const int t = threadIdx.x;
+  if (t < m) {
+    lcs[t] = G[L.cs + t];
+    lsn[t] = G[L.sn + t];
+  }
+  if (t < 2 * j + 1) dd[t] = D[t];
+  if (t < j) colA[t] = G[L.Hr + t * m + j - 1];
+  if (t == 0) {
+    misc[0] = G[L.gpre + (j > 0 ? j - 1 : 0)];
+    misc[1] = G[L.ap];
+  }
+  __syncthreads();
+  if (t != 0) return;
+  D[256] = w2;
+  double* out = G + L.out + (j & 1) * 8;
+  const double alpha = D[128], h = D[129];
+  // the stored next vector is the projected w divided by alpha
+  const double beta = alpha * sqrt(fmax(w2, 0.0));
+  out[0] = alpha;
+  out[1] = h;
+  out[2] = beta;
+  out[3] = 0.0;
+  out[4] = 0.0;
+  out[5] = 0.0;
+  if (!isfinite(alpha) || !isfinite(h) || !isfinite(beta)) {
+    out[5] = 1.0;
+    return;
+  }
+  // Givens rotation of column k (raw entries col[0..k+1]) by the rotations of
+  // the columns before it and its own new rotation; returns g[k] and sets
+  // g[k+1] (gnext) from the provisional entry gp = g[k] before rotation
+  auto rotate = [&](double* col, int k, double gp, double& gk, double& gnext) {
+    double carry = col[0];
+    for (int i = 0; i < k; ++i) {
+      const double t1 = carry, t2 = col[i + 1];
+      col[i] = lcs[i] * t1 + lsn[i] * t2;
+      carry = -lsn[i] * t1 + lcs[i] * t2;
+    }
+    const double hkk = carry, hn = col[k + 1];
+    const double den = hypot(hkk, hn);
+    const double c = den == 0.0 ? 1.0 : hkk / den;
+    const double sv = den == 0.0 ? 0.0 : hn / den;
+    col[k] = den;
+    lcs[k] = c;
+    lsn[k] = sv;
+    G[L.cs + k] = c;
+    G[L.sn + k] = sv;
+    gnext = -sv * gp;
+    gk = c * gp;
+  };
+  double gpj;   // provisional g[j] entry before the rotation of column j
+  if (j == 0) {
+    // u = r / |r| in the basis precision: |r| alpha is the exact start norm
+    if (alpha == 0.0) {
+      out[5] = 2.0;
+      return;
+    }
+    gpj = misc[0] * alpha;
+    G[L.gpre] = gpj;
+  } else {
+    // u = (A z_{j-1} - sum_{i<j} h_{i,j-1} v_i) / alpha_{j-1} = sum_{i<j} s_i v_i + alpha v_j
+    const double ap = misc[1];
+    for (int i = 0; i < j; ++i) colA[i] += ap * dd[i];
+    colA[j] = ap * alpha;
+    double gk, gn;
+    rotate(colA, j - 1, misc[0], gk, gn);
+    for (int i = 0; i < j; ++i) G[L.R + i * m + j - 1] = colA[i];
+    G[L.g + j - 1] = gk;
+    G[L.g + j] = gn;
+    G[L.gpre + j] = gn;
+    out[3] = gn;
+    gpj = gn;
+  }
+  // provisional column j (subdiagonal beta until step j + 1 completes it)
+  for (int i = 0; i < j; ++i) colB[i] = dd[j + 1 + i];
+  colB[j] = h;
+  colB[j + 1] = beta;
+  for (int i = 0; i <= j + 1; ++i) G[L.Hr + i * m + j] = colB[i];
+  double gk, gn;
+  rotate(colB, j, gpj, gk, gn);
+  double* sr = G + L.snapR + (j & 1) * (m + 1);
+  for (int i = 0; i <= j; ++i) {
+    G[L.R + i * m + j] = colB[i];
+    sr[i] = colB[i];
+  }
+  G[L.g + j] = gk;
+  G[L.g + j + 1] = gn;
+  G[L.gpre + j + 1] = gn;
+  G[L.snapg + (j & 1)] = gk;
+  out[4] = gn;
+  G[L.ap] = alpha;
+}
+
+__global__ void k_givens_solve(const double* __restrict__ G, GivensLayout L, int m, int jn, int snap_j,
+                               double* __restrict__ y) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0) return;
+  const double *R = G + L.R, *g = G + L.g;
+  const double* sr = G + L.snapR + (snap_j >= 0 ? (snap_j & 1) * (m + 1) : 0);
+  auto r = [&](int i, int k) { return k == snap_j ? sr[i] : R[i * m + k]; };
+  for (int i = jn - 1; i >= 0; --i) {
+    double t = i == snap_j ? G[L.snapg + (snap_j & 1)] : g[i];
+    for (int k = i + 1; k < jn; ++k) t -= r(i, k) * y[k];
+    y[i] = t / r(i, i);
+  }
+}
+
 // out[g] = sum_q X[g][q] over the Qs values of row g (one block per row).
 __global__ void __launch_bounds__(TPB) k_row_sums(const double* __restrict__ X, int64_t Qs, double* __restrict__ out) {
   __shared__ double sh[TPB / 64];
@@ -3035,6 +3159,13 @@ void dcgs_update_partial(T* V, int64_t ldv, int j, const double* dots, int64_t n
 }
 void finalize_sum(const double* part, int nb, int k, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize_sum, dim3(k), dim3(TPB), 0, s, part, nb, k, out);
+}
+void norm_givens(const double* part, int nb, double* D, double* G, const GivensLayout& L, int m, int j,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_givens, dim3(1), dim3(TPB), 0, s, part, nb, D, G, L, m, j);
+}
+void givens_solve(const double* G, const GivensLayout& L, int m, int jn, int snap_j, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_givens_solve, dim3(1), dim3(64), 0, s, G, L, m, jn, snap_j, y);
 }
 template <class T>
 void update_norm_partial(const T* V, int64_t ldv, int k, const double* h, T* w, int64_t n, double* part, int nb,

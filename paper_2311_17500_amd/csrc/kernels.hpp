@@ -202,6 +202,44 @@ template <class T>
 void dcgs_update_partial(T* V, int64_t ldv, int j, const double* dots, int64_t n, double* part, int nb, double* sc,
                          hipStream_t s);
 void finalize_sum(const double* part, int nb, int k, double* out, hipStream_t s);
+
+// Givens state of one FGMRES(m) cycle on the device (FP64, offsets in doubles):
+// the raw and the rotated Hessenberg matrices Hr and R ((m+1) x m, row-major),
+// the rotations cs, sn (m), the rotated right-hand side g and its provisional
+// entries gpre (m+1), the previous step's alpha, per step parity a copy of
+// the provisional column of R and of g at its diagonal, and per step parity
+// the values the host reads: alpha, h, beta, g[j] after column j-1 is
+// completed, g[j+1] after the provisional rotation of column j, and a flag
+// (1: non-finite coefficients, 2: zero start vector).
+struct GivensLayout {
+  int64_t Hr, R, cs, sn, g, gpre, ap, snapR, snapg, out, total;
+};
+inline GivensLayout givens_layout(int m) {
+  GivensLayout L;
+  const int64_t hm = static_cast<int64_t>(m + 1) * m;
+  L.Hr = 0;
+  L.R = L.Hr + hm;
+  L.cs = L.R + hm;
+  L.sn = L.cs + m;
+  L.g = L.sn + m;
+  L.gpre = L.g + m + 1;
+  L.ap = L.gpre + m + 1;
+  L.snapR = L.ap + 1;
+  L.snapg = L.snapR + 2 * (m + 1);
+  L.out = L.snapg + 2;
+  L.total = L.out + 2 * 8;
+  return L;
+}
+// Arnoldi step j of the FGMRES cycle with the delayed second Gram-Schmidt
+// pass: D[256] = |w'|^2 = sum of the nb partials, then from the step's
+// scalars D (dots of u at [0, j), of w at [j+1, 2j+1), alpha at 128, h at
+// 129) completes Hessenberg column j - 1, sets the provisional column j and
+// applies the Givens rotations (one block; m <= 64).
+void norm_givens(const double* part, int nb, double* D, double* G, const GivensLayout& L, int m, int j,
+                 hipStream_t s);
+// y[0..jn) = R^{-1} g by back substitution; column snap_j (if >= 0) and g at
+// its diagonal come from that step's copies (a later step may have run).
+void givens_solve(const double* G, const GivensLayout& L, int m, int jn, int snap_j, double* y, hipStream_t s);
 // w -= sum_j h[j] V_j ; part[b] = partial ||w||^2 (h read from device)
 template <class T>
 void update_norm_partial(const T* V, int64_t ldv, int k, const double* h, T* w, int64_t n, double* part, int nb,

@@ -108,7 +108,7 @@ struct st_iga_ctx {
   TimeFD fd;
   // tables
   Tab Ms[3], Ks[3], Bq[3][3], BqT[3], Hs[3], Gs[3], Us[3], UsT[3];
-  Tab Mt_x, Wt_x, Bt0, Bt1, BtT, Gt, Ut, UtT, Ew;
+  Tab Mt_x, Wt_x, Bt0, Bt1, BtT, Gt, Ut, UtT;
   // zero-padded dense FD matrices for the MFMA mode products (A[i][j] applied as sum_j A[i][j] x_j)
   struct Dense {
     std::vector<double> h;
@@ -118,8 +118,7 @@ struct st_iga_ctx {
     int n = 0, npad = 0;
   } DUsT[3], DUs[3], DUtT, DUt;
   // the w-update as one dense product along time (FP64 MFMA): the n_t x n_t
-  // matrix whose first row (the initial layer, w = 0) is zero; set when
-  // n_t <= 144, else the update runs as a table gather
+  // matrix whose first row (the initial layer, w = 0) is zero
   Dense DEw;
   // device data
   double *lam_d = nullptr, *mu_d = nullptr, *l_d = nullptr;
@@ -218,6 +217,7 @@ struct st_iga_ctx {
   const double *rfull_u = nullptr, *rfull_w = nullptr;   // (u, w) whose ionic residual part is in rfull
   double *grid = nullptr, *grid2 = nullptr, *E = nullptr, *rfull = nullptr, *Cg = nullptr;
   double *part = nullptr, *dsc = nullptr, *gram = nullptr, *tmpR = nullptr;
+  double* givens = nullptr;   // Givens state of the FGMRES cycle with the delayed second pass
   int nb_red = 0, nb_part = 0, gram_nb = 0;
 };
 
@@ -720,15 +720,13 @@ void host_setup(st_iga_ctx* c) {
     }
     for (int r = 0; r < Nt; ++r)
       for (int k = 0; k < nt; ++k) R[static_cast<size_t>(r) * nt + k] /= L[static_cast<size_t>(r) * Nt + r];
-    c->Ew.h = dense_table(R, Nt, nt, false);
-    if (nt <= 144) {
-      st_iga_ctx::Dense& D = c->DEw;
-      D.n = nt;
-      D.npad = 16 * ((nt + 15) / 16);
-      D.h.assign(static_cast<size_t>(D.npad) * D.npad, 0.0);
-      for (int r = 0; r < Nt; ++r)
-        for (int k = 0; k < nt; ++k) D.h[static_cast<size_t>(r + 1) * D.npad + k] = R[static_cast<size_t>(r) * nt + k];
-    }
+    // n_t <= 143 (checked above): at most nine 16-row tiles
+    st_iga_ctx::Dense& D = c->DEw;
+    D.n = nt;
+    D.npad = 16 * ((nt + 15) / 16);
+    D.h.assign(static_cast<size_t>(D.npad) * D.npad, 0.0);
+    for (int r = 0; r < Nt; ++r)
+      for (int k = 0; k < nt; ++k) D.h[static_cast<size_t>(r + 1) * D.npad + k] = R[static_cast<size_t>(r) * nt + k];
   }
   // chunking of the quadrature pass: arrays per time Gauss point row
   // contiguous windows for the sweep kernels
@@ -813,8 +811,8 @@ void plan(st_iga_ctx* c) {
     c->qf_win = a.get<double>(static_cast<int64_t>(c->qf_win_h.size()));
     c->qf_wd = a.get<double>(static_cast<int64_t>(c->qf_wd_h.size()));
   }
-  T(c->Mt_x); T(c->Wt_x); T(c->Bt0); T(c->Bt1); T(c->BtT); T(c->Gt); T(c->Ut); T(c->UtT); T(c->Ew);
-  if (c->DEw.npad) c->DEw.d = a.get<double>(static_cast<int64_t>(c->DEw.npad) * c->DEw.npad);
+  T(c->Mt_x); T(c->Wt_x); T(c->Bt0); T(c->Bt1); T(c->BtT); T(c->Gt); T(c->Ut); T(c->UtT);
+  c->DEw.d = a.get<double>(static_cast<int64_t>(c->DEw.npad) * c->DEw.npad);
   for (st_iga_ctx::Dense* D : {&c->DUt, &c->DUtT, &c->DUs[0], &c->DUs[1], &c->DUs[2], &c->DUsT[0], &c->DUsT[1],
                                &c->DUsT[2]}) {
     if (D->npad == 0) continue;
@@ -913,6 +911,7 @@ void plan(st_iga_ctx* c) {
   // reduction partials: up to 2 (m + 1) <= 130 sums per block (two-vector multi-dot)
   c->part = a.get<double>(std::max<int64_t>(static_cast<int64_t>(c->nb_red) * 130, 2 * static_cast<int64_t>(c->nb_part)));
   c->dsc = a.get<double>(1024);
+  c->givens = a.get<double>(givens_layout(c->opt.restart).total);
   c->gram_nb = static_cast<int>(std::min<int64_t>(512, (c->Ns + 31) / 32));
   c->gram = a.get<double>(static_cast<int64_t>(c->gram_nb) * c->Nt * c->Nt);
   c->tmpR = a.get<double>(static_cast<int64_t>(c->Nt) * c->maxR + 2 * c->maxR);
@@ -954,7 +953,7 @@ void upload_all(st_iga_ctx* c, hipStream_t s) {
                    &c->Bq[l][1], &c->Bq[l][2]})
       upload_tab(*t, s, keepf);
   }
-  for (Tab* t : {&c->Mt_x, &c->Wt_x, &c->Bt0, &c->Bt1, &c->BtT, &c->Gt, &c->Ut, &c->UtT, &c->Ew}) upload_tab(*t, s, keepf);
+  for (Tab* t : {&c->Mt_x, &c->Wt_x, &c->Bt0, &c->Bt1, &c->BtT, &c->Gt, &c->Ut, &c->UtT}) upload_tab(*t, s, keepf);
   if (c->cf) {
     up(c->cf_Bl_h, static_cast<const double*>(c->cf_Bl_d), s);
     keepf.emplace_back(c->cf_Bl_h.begin(), c->cf_Bl_h.end());
@@ -965,7 +964,7 @@ void upload_all(st_iga_ctx* c, hipStream_t s) {
     up(c->qf_win_h, static_cast<const double*>(c->qf_win), s);
     up(c->qf_wd_h, static_cast<const double*>(c->qf_wd), s);
   }
-  if (c->DEw.npad) up(c->DEw.h, static_cast<const double*>(c->DEw.d), s);
+  up(c->DEw.h, static_cast<const double*>(c->DEw.d), s);
   for (st_iga_ctx::Dense* D : {&c->DUt, &c->DUtT, &c->DUs[0], &c->DUs[1], &c->DUs[2], &c->DUsT[0], &c->DUsT[1],
                                &c->DUsT[2]}) {
     if (D->npad == 0) continue;
@@ -1523,10 +1522,12 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
   double rn = bnorm;
   Stall stall(c, bnorm, "FGMRES stagnated");
   CK(hipMemcpyAsync(c->rk, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  // Hr: Hessenberg matrix as computed (unrotated); R: rotated copy
-  std::vector<double> Hr(static_cast<size_t>(m + 1) * m), R(static_cast<size_t>(m + 1) * m), cs(m), sn(m),
-      g(m + 1), gpre(m + 1), y(m);
-  constexpr int HS = 264;   // per step: dots [0, 128), {alpha, h} at 128, |w'|^2 at 256
+  // the Hessenberg matrix, its Givens rotations and the back substitution
+  // live on the device (norm_givens, givens_solve); per step the host
+  // reads 8 values to decide whether the cycle goes on
+  const GivensLayout GL = givens_layout(m);
+  double* G = c->givens;
+  constexpr int HS = 264;   // pinned slot per step parity
   if (!c->step_host) CK(hipHostMalloc(reinterpret_cast<void**>(&c->step_host), 2 * HS * sizeof(double), 0));
   for (auto& ev : c->step_ev)
     if (!ev) CK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -1535,31 +1536,14 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
   // buffer, so step j + 1 can run while the host reads step j
   auto region = [&](int j) { return c->dsc + (j & 1) * 640; };
   const bool overlap = c->opt.graphs != 0 && !kprof_enabled();
-  // Givens rotation of column k from its raw entries and the rotations of the
-  // columns before it; g[k], g[k + 1] from gpre[k]
-  auto rotate = [&](int k) {
-    for (int i = 0; i <= k + 1; ++i) R[static_cast<size_t>(i) * m + k] = Hr[static_cast<size_t>(i) * m + k];
-    for (int i = 0; i < k; ++i) {
-      const double t1 = R[static_cast<size_t>(i) * m + k], t2 = R[static_cast<size_t>(i + 1) * m + k];
-      R[static_cast<size_t>(i) * m + k] = cs[i] * t1 + sn[i] * t2;
-      R[static_cast<size_t>(i + 1) * m + k] = -sn[i] * t1 + cs[i] * t2;
-    }
-    const double hkk = R[static_cast<size_t>(k) * m + k], hn = R[static_cast<size_t>(k + 1) * m + k];
-    const double den = std::hypot(hkk, hn);
-    cs[k] = den == 0.0 ? 1.0 : hkk / den;
-    sn[k] = den == 0.0 ? 0.0 : hn / den;
-    R[static_cast<size_t>(k) * m + k] = den;
-    g[k + 1] = -sn[k] * gpre[k];
-    g[k] = cs[k] * gpre[k];
-    gpre[k + 1] = g[k + 1];
-  };
   while (it < maxit) {
     scale_to<T>(c->rk, 1.0 / rn, V, n, s);
-    std::fill(Hr.begin(), Hr.end(), 0.0);
-    std::fill(g.begin(), g.end(), 0.0);
-    gpre[0] = rn;
+    // Hr = 0, g = 0, gpre = (rn, 0, ...)
+    fill(G + GL.Hr, 0.0, GL.R - GL.Hr, s);
+    fill(G + GL.g, 0.0, GL.ap - GL.g, s);
+    fill(G + GL.gpre, rn, 1, s);
     int ncol = 0;
-    double alpha_prev = 1.0;
+    bool final_col_provisional = true;   // false: the cycle stopped right after completing a column
     // step j on the stream, followed by the copy of its scalars and its event
     auto launch = [&](int j) {
       T* Vj = V + static_cast<int64_t>(j) * ld;
@@ -1574,23 +1558,26 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
         multidot2_partial<T>(V, ld, j + 1, Vj, w, n, c->part, nb, ss);
         finalize_sum(c->part, nb, 2 * (j + 1), D, ss);
         dcgs_update_partial<T>(V, ld, j, D, n, c->part, nb, D + 128, ss);
-        finalize_sum(c->part, nb, 1, D + 256, ss);
-        // the step's scalars to pinned host memory, inside the replayed graph
-        // (one runtime call less per Krylov iteration)
-        CK(hipMemcpyAsync(c->step_host + (j & 1) * HS, D, 257 * sizeof(double), hipMemcpyDeviceToHost, ss));
+        norm_givens(c->part, nb, D, G, GL, m, j, ss);
+        // the step's decision values to pinned host memory, inside the
+        // replayed graph (one runtime call less per Krylov iteration)
+        CK(hipMemcpyAsync(c->step_host + (j & 1) * HS, G + GL.out + (j & 1) * 8, 8 * sizeof(double),
+                          hipMemcpyDeviceToHost, ss));
       };
       run_step(c, gv, j, m, body, s);
       CK(hipEventRecord(c->step_ev[j & 1], s));
     };
     int queued = -1;          // last step already on the stream
     double res_prev = -1.0;   // residual estimate one step earlier
+    double res_next = rn;     // |g[j]| as left by step j - 1 (the provisional rotation)
     for (int j = 0; j < m && it < maxit; ++j) {
       if (queued < j) launch(j);
       queued = j;
       // step j + 1 needs only device data: queue it before reading step j
       // while the residual estimate is far from the tolerance (a step that
-      // turns out unneeded writes only basis columns the solution ignores)
-      const double res = std::fabs(j == 0 ? gpre[0] : g[j]);
+      // turns out unneeded writes only basis columns, the provisional column
+      // of R and g entries that the back substitution does not read)
+      const double res = std::fabs(res_next);
       const double q = res_prev > 0.0 ? std::min(1.0, res / res_prev) : 0.0;
       if (overlap && j + 1 < m && it + 1 < maxit && res * (j == 0 ? 1.0 / 64 : q) > 4.0 * rtol * bnorm) {
         launch(j + 1);
@@ -1601,39 +1588,24 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
       check_launch();
       const double* hb = c->step_host + (j & 1) * HS;
       ++it;
-      const double alpha = hb[128], h = hb[129];
-      // the stored next vector is the projected w divided by alpha
-      const double beta = alpha * std::sqrt(std::max(hb[256], 0.0));
-      if (!std::isfinite(alpha) || !std::isfinite(h) || !std::isfinite(beta))
-        throw Fail{ST_IGA_ENOCONV, "non-finite Arnoldi coefficients"};
-      if (j == 0) {
-        // u = r / |r| in the basis precision: |r| alpha is the exact start norm
-        if (alpha == 0.0) throw Fail{ST_IGA_ENOCONV, "zero Krylov start vector"};
-        gpre[0] = rn * alpha;
-      } else {
-        // u = (A z_{j-1} - sum_{i<j} h_{i,j-1} v_i) / alpha_{j-1}
-        //   = sum_{i<j} s_i v_i + alpha v_j
-        for (int i = 0; i < j; ++i) Hr[static_cast<size_t>(i) * m + j - 1] += alpha_prev * hb[i];
-        Hr[static_cast<size_t>(j) * m + j - 1] = alpha_prev * alpha;
-        rotate(j - 1);
+      // hb: alpha, h, beta, g[j] after completing column j - 1, g[j + 1]
+      // after the provisional rotation of column j, flag
+      if (hb[5] == 1.0) throw Fail{ST_IGA_ENOCONV, "non-finite Arnoldi coefficients"};
+      if (hb[5] == 2.0) throw Fail{ST_IGA_ENOCONV, "zero Krylov start vector"};
+      const double alpha = hb[0], beta = hb[2];
+      if (j > 0) {
         ncol = j;
-        if (alpha == 0.0 || std::fabs(g[j]) <= rtol * bnorm) break;   // breakdown, or converged
+        if (alpha == 0.0 || std::fabs(hb[3]) <= rtol * bnorm) {   // breakdown, or converged
+          final_col_provisional = false;
+          break;
+        }
       }
-      for (int i = 0; i < j; ++i) Hr[static_cast<size_t>(i) * m + j] = hb[j + 1 + i];
-      Hr[static_cast<size_t>(j) * m + j] = h;
-      Hr[static_cast<size_t>(j + 1) * m + j] = beta;
-      rotate(j);   // provisional subdiagonal until step j + 1
       ncol = j + 1;
-      alpha_prev = alpha;
-      if (std::fabs(g[j + 1]) <= rtol * bnorm || beta == 0.0) break;
+      res_next = hb[4];
+      if (std::fabs(hb[4]) <= rtol * bnorm || beta == 0.0) break;
     }
     const int jn = ncol;
-    for (int i = jn - 1; i >= 0; --i) {
-      double t = g[i];
-      for (int k = i + 1; k < jn; ++k) t -= R[static_cast<size_t>(i) * m + k] * y[k];
-      y[i] = t / R[static_cast<size_t>(i) * m + i];
-    }
-    CK(hipMemcpyAsync(c->dsc + 512, y.data(), jn * sizeof(double), hipMemcpyHostToDevice, s));
+    givens_solve(G, GL, m, jn, final_col_provisional ? jn - 1 : -1, c->dsc + 512, s);
     combine<T>(Z, ld, jn, c->dsc + 512, x, n, s);
     if (std::is_same<T, double>::value) {
       A(reinterpret_cast<const T*>(x), yt);
@@ -2445,13 +2417,8 @@ void residual(st_iga_ctx* c, const double* u, const double* w, double* r, hipStr
 }
 
 void w_update(st_iga_ctx* c, const double* u, double* w, hipStream_t s) {
-  if (c->DEw.d) {
-    // one pass over u and w (the gather re-reads every input layer per output layer)
-    dense_mode<double, double>(c->DEw.d, c->nt, c->DEw.npad, u, w, 1, c->Ns, s);
-  } else {
-    fill(w, 0.0, c->Ns, s);
-    gather<double, double, double>(c->Ew.d, u, w + c->Ns, 1, c->Ns, c->nt, 0, 1.0, 0.0, s);
-  }
+  // one pass over u and w: layer 0 of w is the zero row of the matrix
+  dense_mode<double, double>(c->DEw.d, c->nt, c->DEw.npad, u, w, 1, c->Ns, s);
   check_launch();
 }
 
@@ -2747,7 +2714,11 @@ st_iga_status st_iga_residual(st_iga_ctx* c, const double* u, const double* w, d
 
 st_iga_status st_iga_w_update(st_iga_ctx* c, const double* u, double* w, void* stream) {
   if (!c || !u || !w) return ST_IGA_EINVAL;
-  return guard(c, [&] { w_update(c, u, w, static_cast<hipStream_t>(stream)); });
+  return guard(c, [&] {
+    const int64_t full = static_cast<int64_t>(c->nt) * c->Ns;
+    if (u < w + full && w < u + full) throw Fail{ST_IGA_EINVAL, "u and w overlap"};
+    w_update(c, u, w, static_cast<hipStream_t>(stream));
+  });
 }
 
 st_iga_status st_iga_krylov(st_iga_ctx* c, const double* b, double* x, double tol, int32_t* iters, double* relres,

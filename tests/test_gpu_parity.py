@@ -113,6 +113,24 @@ def test_precond(gpu_lib, torch, name, prob, precond):
     assert rel(z, solver.precond_solve(st, r)) < max(1e-11, 20 * kappa * np.finfo(float).eps)
 
 
+@pytest.mark.parametrize("nel_t", [140, 141])
+def test_w_update_time_extent(gpu_lib, torch, nel_t):
+    """The w-update (one dense product along time on MFMA) at the largest
+    time extents setup accepts: 142 and 143 time B-splines (p = 2), nine
+    16-row tiles with a ragged last one, against the oracle.  Overlapping u
+    and w are refused."""
+    from paper_2311_17500_amd.binding import StIgaError
+    prob = W.tiny(1, 2, 4, nel_t=nel_t)
+    S = solver_for(prob)
+    st = SpaceTime(prob)
+    u, _ = W.smooth_state(prob, 7)
+    assert st.n[-1] == nel_t + 2
+    ud = to_dev(torch, u)
+    assert rel(S.w_update(ud).cpu().numpy(), st.w_update_explicit(u)) < 1e-12
+    with pytest.raises(StIgaError, match="EINVAL"):
+        S._chk(S.lib.st_iga_w_update(S.ctx, S._p(ud), S._p(ud), S._s()))
+
+
 @pytest.mark.parametrize("name,prob", SMALL[:6], ids=[n for n, _ in SMALL[:6]])
 def test_residual_and_w(gpu_lib, torch, name, prob):
     S = solver_for(prob)
