@@ -2715,8 +2715,9 @@ st_iga_status st_iga_residual(st_iga_ctx* c, const double* u, const double* w, d
 st_iga_status st_iga_w_update(st_iga_ctx* c, const double* u, double* w, void* stream) {
   if (!c || !u || !w) return ST_IGA_EINVAL;
   return guard(c, [&] {
-    const int64_t full = static_cast<int64_t>(c->nt) * c->Ns;
-    if (u < w + full && w < u + full) throw Fail{ST_IGA_EINVAL, "u and w overlap"};
+    const uintptr_t bytes = static_cast<uintptr_t>(c->nt) * c->Ns * sizeof(double);
+    const uintptr_t ua = reinterpret_cast<uintptr_t>(u), wa = reinterpret_cast<uintptr_t>(w);
+    if (ua < wa + bytes && wa < ua + bytes) throw Fail{ST_IGA_EINVAL, "u and w overlap"};
     w_update(c, u, w, static_cast<hipStream_t>(stream));
   });
 }
