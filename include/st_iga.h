@@ -142,8 +142,12 @@ typedef struct {
                                 only when the first removes more than 1 - 1/sqrt(2) of the norm.
                                 Other values: ST_IGA_EINVAL */
   int32_t graphs;            /* 1: with reorth = 1 or 2, replay each Arnoldi step (preconditioner,
-                                operator, Gram-Schmidt) from a HIP graph captured on first use;
-                                0: eager launches */
+                                operator, Gram-Schmidt) from a HIP graph captured on first use,
+                                queueing the next step before the host reads the current one while
+                                the residual estimate is far from the tolerance;
+                                2: as 1, but with reorth = 2 the next step is always queued ahead
+                                (extra work at the end of each cycle; for tests of that path);
+                                0: eager launches; EINVAL otherwise */
   int32_t stall_cycles;      /* ENOCONV after this many consecutive FGMRES restart cycles (or
                                 refinement steps) that reduce the true residual by less than
                                 stall_reduction (relative); 0: never */

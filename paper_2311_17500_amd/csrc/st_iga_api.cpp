@@ -237,6 +237,7 @@ void validate(const st_iga_problem* P, const st_iga_options* O) {
   for (int l = 0; l <= P->d; ++l)
     if (!P->knots[l]) throw Fail{ST_IGA_EINVAL, "null knot vector"};
   if (O->restart < 1 || O->restart > 64) throw Fail{ST_IGA_EINVAL, "restart must be in 1..64"};
+  if (O->graphs < 0 || O->graphs > 2) throw Fail{ST_IGA_EINVAL, "graphs must be 0, 1 or 2"};
   if (O->reorth < 0 || O->reorth > 2) throw Fail{ST_IGA_EINVAL, "reorth must be 0, 1 or 2"};
   if (O->outer < 0 || O->outer > 2) throw Fail{ST_IGA_EINVAL, "outer must be 0, 1 or 2"};
   if (O->stall_cycles < 0 || !(O->stall_reduction >= 0.0 && O->stall_reduction < 1.0))
@@ -1579,7 +1580,8 @@ int fgmres_delayed(st_iga_ctx* c, const OpT<T>& A, const OpT<T>& Pc, const doubl
       // of R and g entries that the back substitution does not read)
       const double res = std::fabs(res_next);
       const double q = res_prev > 0.0 ? std::min(1.0, res / res_prev) : 0.0;
-      if (overlap && j + 1 < m && it + 1 < maxit && res * (j == 0 ? 1.0 / 64 : q) > 4.0 * rtol * bnorm) {
+      if (overlap && j + 1 < m && it + 1 < maxit &&
+          (c->opt.graphs == 2 || res * (j == 0 ? 1.0 / 64 : q) > 4.0 * rtol * bnorm)) {
         launch(j + 1);
         queued = j + 1;
       }

@@ -318,6 +318,33 @@ def test_krylov_graph_replay(gpu_lib, torch, prec, reorth):
             torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("restart", [3, 30])
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
+def test_krylov_next_step_always_queued(gpu_lib, torch, prec, restart):
+    """With the next Arnoldi step always queued before the host reads the
+    current one (graphs = 2), every stop of a cycle happens with one more
+    step already run on the device, which overwrites the provisional column
+    of R and g that the back substitution needs; its per-step copies must
+    give bit-identical solves to eager launches, over short (3) and long
+    restart cycles."""
+    from paper_2311_17500_amd.binding import FP64, MIXED_FP32
+    code = {"fp64": FP64, "mixed_fp32": MIXED_FP32}[prec]
+    prob = SMALL[2][1]
+    Sq = solver_for(prob, prec=code, graphs=2, restart=restart)
+    Se = solver_for(prob, prec=code, graphs=0, restart=restart)
+    tol = 1e-11 if prec == "fp64" else 1e-8
+    u, w = W.smooth_state(prob, 12)
+    ud, wd = to_dev(torch, u), to_dev(torch, w)
+    Sq.linearize(ud, wd)
+    Se.linearize(ud, wd)
+    b = to_dev(torch, W.random_vector(prob.unknowns, 32))
+    xe, ite, rre = Se.krylov(b, tol=tol)
+    xq, itq, rrq = Sq.krylov(b, tol=tol)
+    assert rre <= tol
+    assert itq == ite and rrq == rre
+    assert np.array_equal(xq.cpu().numpy(), xe.cpu().numpy())
+
+
 @pytest.mark.parametrize("name,prob", [SMALL[1], SMALL[2]], ids=["2d_p3", "3d_p2"])
 def test_linearize_picard(gpu_lib, torch, name, prob):
     """Picard linearization (reaction coefficient C_r of eq. (3.8)): ranks,

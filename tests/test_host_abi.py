@@ -215,10 +215,11 @@ def test_invalid_options_rejected(lib):
     same validation rejects them in setup with EINVAL)."""
     prob = W.tiny(2, 2, 4)
     assert binding.workspace_bytes(prob) > 0
-    for kw in ({"reorth": 3}, {"reorth": -1}, {"restart": 0}, {"restart": 65}):
+    for kw in ({"reorth": 3}, {"reorth": -1}, {"restart": 0}, {"restart": 65}, {"graphs": 3}, {"graphs": -1}):
         assert binding.workspace_bytes(prob, **kw) == 0, kw
     for r in (0, 1, 2):
         assert binding.workspace_bytes(prob, reorth=r) > 0
+        assert binding.workspace_bytes(prob, graphs=r) > 0
     # stabilization modes: SUPG + shock capturing runs in the fixed-point scheme
     for kw in ({"su": 3}, {"su": -1}, {"su": 2, "outer": 0}, {"su": 2, "outer": 1},
                {"su": 2, "outer": 2, "sc_c": -1.0}, {"su": 2, "outer": 2, "sc_c": float("nan")}):
