@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--serve", action="store_true", help="run only the serving stream (512 requests)")
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving stream sampled in the default run (0: skip)")
-    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-slots", type=int, default=6)
     ap.add_argument("--compare-su", action="store_true",
                     help="fixed-point scheme of Section 3.1 (exact C_r, alpha = 0.5, stop at 1e-4) with and "
                          "without the SU term on config 1: iteration counts and times")
