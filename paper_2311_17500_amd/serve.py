@@ -44,7 +44,7 @@ class Record:
 
 
 class Server:
-    def __init__(self, device="cuda:0", slots: int = 16, hbm_budget: Optional[int] = None,
+    def __init__(self, device="cuda:0", slots: int = 6, hbm_budget: Optional[int] = None,
                  keep_results: bool = False, **options):
         import torch
         self.torch = torch
