@@ -113,6 +113,34 @@ def test_precond(gpu_lib, torch, name, prob, precond):
     assert rel(z, solver.precond_solve(st, r)) < max(1e-11, 20 * kappa * np.finfo(float).eps)
 
 
+@pytest.mark.parametrize("nel_s", [(142, 4), (4, 142)], ids=["x1_144", "x2_144"])
+def test_largest_spatial_extent(gpu_lib, torch, nel_s):
+    """144 B-splines along one spatial axis, the most setup accepts (p = 2):
+    the FD mode products then span nine 16-row tiles, along x1 (row-staged
+    kernel) or along x2 (column-tile kernel).  Operator with given low-rank
+    factors and both preconditioners against the oracle, in FP64 and FP32
+    (cond(A-hat) = 814 and 267)."""
+    from paper_2311_17500_amd.binding import MIXED_FP32
+    prob = W.tiny(2, 2, 4, nel_t=3, nel_s=nel_s)
+    st = SpaceTime(prob)
+    assert max(st.n[:2]) == 144
+    ft = W.random_factors(prob, 3, 1)
+    fc = W.random_factors(prob, 4, 2, scale=5.0)
+    x = W.random_vector(prob.unknowns, 12)
+    want_y = st.apply_J(x, st.lowrank_at_quad(LowRank(*fc)), st.lowrank_at_quad(LowRank(*ft)))
+    want_z = solver.precond_solve(st, x)
+    xd = to_dev(torch, x)
+    for precond in (0, 1):
+        S = solver_for(prob, prec=MIXED_FP32, precond=precond)
+        # before any coefficients are set both preconditioners invert A-hat
+        assert rel(S.precond(xd).cpu().numpy(), want_z) < 1e-11
+        assert rel(S.precond_lowp(xd).cpu().numpy(), want_z) < 1e-4
+        S.set_factors(ft, fc)
+        assert rel(S.apply(xd).cpu().numpy(), want_y) < 1e-12
+        assert rel(S.apply_lowp(xd).cpu().numpy(), want_y) < 1e-5
+        S.close()
+
+
 @pytest.mark.parametrize("nel_t", [140, 141])
 def test_w_update_time_extent(gpu_lib, torch, nel_t):
     """The w-update (one dense product along time on MFMA) at the largest
