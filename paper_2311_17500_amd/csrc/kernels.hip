@@ -732,6 +732,9 @@ __global__ void __launch_bounds__(TPB) k_band_solve(const C* __restrict__ F, int
   C ring[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) ring[k] = C(0);
+  // unrolled: the loads of eight rows (independent of the recurrence) are in
+  // flight together; with few spatial modes the walk is latency-bound
+#pragma unroll 8
   for (int t = 0; t < Nt; ++t) {       // L y = r, ring = y_{t-P .. t-1}
     C y = to_c(r[static_cast<int64_t>(t) * Ns + j], C(0));
 #pragma unroll
@@ -743,6 +746,7 @@ __global__ void __launch_bounds__(TPB) k_band_solve(const C* __restrict__ F, int
   }
 #pragma unroll
   for (int k = 0; k < P; ++k) ring[k] = C(0);
+#pragma unroll 8
   for (int t = Nt - 1; t >= 0; --t) {  // U x = y, ring = x_{t+1 .. t+P}
     C v = to_c(x[static_cast<int64_t>(t) * Ns + j], C(0));
 #pragma unroll
